@@ -1,0 +1,300 @@
+"""Pins of the CPU reference against facts fixed by the paper or by mathematics.
+
+Each test checks the reference against something other than itself: a
+closed form, an invariant, a special case with a textbook answer, or brute
+force.  A plausible slip in the reference (a dropped term, a wrong sign or
+index, a transposed operand) fails at least one of them.
+"""
+import numpy as np
+import pytest
+
+from oracle import hmatrix as hm
+from oracle import reference as ref
+from synth import CAP_SMALL, CapSpec, cap_mesh
+
+
+def sphere_facets(N, r=2.0, seed=0):
+    """Centroids on a sphere with inward radial normals and random areas."""
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal((N, 3))
+    p /= np.linalg.norm(p, axis=1, keepdims=True)
+    x = r * p
+    n = -p
+    A = rng.uniform(0.5, 1.5, N) * 1e-2
+    return ref.Facets.from_arrays(x, n, A)
+
+
+# ---------------------------------------------------------------- P1, eq. FF-def
+def test_sphere_kernel_is_constant():
+    """On a sphere with inward normals the kernel of eq. FF-def is A_j / (4 pi r^2) exactly."""
+    r = 2.0
+    fac = sphere_facets(300, r=r)
+    F = ref.view_factor_matrix(fac)
+    expect = np.tile(fac.A / (4 * np.pi * r * r), (fac.N, 1))
+    np.fill_diagonal(expect, 0.0)
+    assert np.max(np.abs(F - expect) / expect.max()) < 1e-12
+
+
+# ---------------------------------------------------------------- P2, Jacobi
+@pytest.mark.parametrize("rho", [0.3, 1.0])
+def test_jacobi_sherman_morrison(rho):
+    """F = c(1 A^T - diag A) gives (I - rho F)B = E in closed form (Sherman-Morrison)."""
+    r = 2.0
+    fac = sphere_facets(400, r=r, seed=1)
+    F = ref.view_factor_matrix(fac)
+    c = 1.0 / (4 * np.pi * r * r)
+    E = np.random.default_rng(2).uniform(0.0, 10.0, (fac.N, 3))
+    D = 1.0 + rho * c * fac.A
+    s = (fac.A @ (E / D[:, None])) / (1.0 - rho * c * np.sum(fac.A / D))
+    B_exact = (E + rho * c * s[None, :]) / D[:, None]
+    B, iters = ref.jacobi(lambda X: F @ X, rho, E, tol=1e-15)
+    assert np.max(np.abs(B - B_exact)) / np.max(np.abs(B_exact)) < 1e-13
+    assert np.all(iters > 0)
+
+
+# ---------------------------------------------------------------- P3, section 7.1
+def test_closed_form_constants_agree():
+    """The two printed forms of the shadowed-crater temperature are the same number,
+    and f equals sin^2(beta/2), the view factor of a spherical cap seen from itself."""
+    alpha, emiss, S, e = 0.3, 0.99, 1365.0, 15.0
+    f = ref.crater_f(5.0)  # D/d = 5
+    T1 = ref.crater_shadow_temperature(S, e, alpha, emiss, f)
+    T2 = ref.crater_temperature(S, np.sin(np.deg2rad(e)), 0.0, True, alpha, emiss, f)
+    assert abs(T1 - T2) < 1e-10 * T1
+    rc, d = 1000.0, 400.0
+    r = (rc * rc + d * d) / (2 * d)
+    beta = np.arcsin(rc / r)           # half-angle of the cap seen from the sphere centre
+    assert abs(f - np.sin(beta / 2) ** 2) < 1e-14 * 10 and abs(f - 1 / 7.25) < 1e-15
+
+
+def _cap_temperature(spec):
+    v, f = cap_mesh(spec)
+    fac = ref.Facets(v, f)
+    F = ref.view_factor_matrix(fac)
+    e = 15.0
+    s = np.array([[np.cos(np.deg2rad(e)), 0.0, np.sin(np.deg2rad(e))]])
+    Q = ref.insolation(fac, s, S=1365.0)
+    out = ref.equilibrium_temperature(lambda X: F @ X, Q, 0.3, 0.99)
+    shadow = Q[:, 0] == 0.0
+    fcr = ref.crater_f(5.0)
+    Tc = ref.crater_temperature(1365.0, np.sin(np.deg2rad(e)), fac.n @ s[0], shadow,
+                                0.3, 0.99, fcr)
+    rel = np.abs(out["T"][:, 0] - Tc) / Tc
+    return rel, shadow
+
+
+def test_cap_matches_closed_form():
+    """Discrete equilibrium T on the ~1,600-facet bowl vs the closed form of section 7.1."""
+    rel, shadow = _cap_temperature(CAP_SMALL)
+    assert 0.4 < shadow.mean() < 0.8
+    assert rel[shadow].mean() < 5e-3 and rel[shadow].max() < 3e-2
+    assert rel[~shadow].mean() < 2e-3
+
+
+@pytest.mark.slow
+def test_cap_converges_to_closed_form():
+    """Halving the mesh spacing shrinks the shadowed-region error (first-order scheme)."""
+    rel1, sh1 = _cap_temperature(CAP_SMALL)
+    rel2, sh2 = _cap_temperature(CapSpec(h=CAP_SMALL.h / 2))
+    assert rel2[sh2].mean() < 0.7 * rel1[sh1].mean()
+
+
+# ---------------------------------------------------------------- P4, P5
+def test_reciprocity_and_row_sums():
+    v, f = cap_mesh(CAP_SMALL)
+    fac = ref.Facets(v, f)
+    F = ref.view_factor_matrix(fac)
+    M = fac.A[:, None] * F
+    assert np.max(np.abs(M - M.T)) <= 1e-14 * M.max()
+    rs = F.sum(axis=1)
+    assert rs.max() < 1.0
+    fcr = ref.crater_f(5.0)
+    assert abs(rs.mean() - fcr) < 0.01 * fcr
+    assert np.all(np.diag(F) == 0.0)
+
+
+# ---------------------------------------------------------------- P6, section 3.2
+def _tri(a, b, c):
+    return np.array([a, b, c], dtype=np.float64).reshape(9)
+
+
+def test_visibility_blocker():
+    """Two facing facets; a triangle across the segment hides them, one beside does not."""
+    x = np.array([[0, 0, 0], [0, 0, 2.0], [0, 0, 1.0], [5, 5, 1.0]], dtype=np.float64)
+    n = np.array([[0, 0, 1], [0, 0, -1], [1, 0, 0], [1, 0, 0]], dtype=np.float64)
+    A = np.ones(4)
+    tris = np.stack([
+        _tri([-.1, -.1, 0], [.1, -.1, 0], [0, .1, 0]),
+        _tri([-.1, -.1, 2], [0, .1, 2], [.1, -.1, 2]),
+        _tri([-1, -1, 1], [1, -1, 1], [0, 1, 1]),        # blocker across the segment
+        _tri([4, 4, 1], [6, 4, 1], [5, 6, 1]),           # far away
+    ])
+    fac = ref.Facets.from_arrays(x, n, A, tris)
+    vis = ref.pair_visibility(fac, "raycast")
+    assert vis[0, 1] == 0 and vis[1, 0] == 0
+    tris2 = tris.copy()
+    tris2[2] = _tri([3, 3, 1], [4, 3, 1], [3, 4, 1])   # move the blocker aside
+    fac2 = ref.Facets.from_arrays(x, n, A, tris2)
+    assert ref.pair_visibility(fac2, "raycast")[0, 1] == 1
+    # a hit exactly on the blocker's edge still blocks (edges are inclusive)
+    tris3 = tris.copy()
+    tris3[2] = _tri([0, 0, 1], [1, 0, 1], [0, 1, 1])   # vertex on the segment
+    fac3 = ref.Facets.from_arrays(x, n, A, tris3)
+    assert ref.pair_visibility(fac3, "raycast")[0, 1] == 0
+    # back-face culling: facet 3 faces +x, away from facet 0's column
+    assert vis[0, 3] == 0 or np.dot(n[3], x[0] - x[3]) > 0
+
+
+def test_convex_bowl_all_facing_pairs_visible():
+    """Inside a convex bowl no segment between facets leaves the bowl: brute-force
+    ray casting and the back-face test agree on every pair."""
+    v, f = cap_mesh(CapSpec(h=120.0, seed=3))
+    fac = ref.Facets(v, f)
+    assert np.array_equal(ref.pair_visibility(fac, "raycast"), ref.pair_visibility(fac, "backface"))
+
+
+def test_bowl_shadow_matches_sphere():
+    """Sun shadowing on the meshed bowl agrees with the exact sphere away from the
+    shadow line: a ray from a point on the bowl leaves through the opening iff its
+    second intersection with the sphere lies above the rim plane."""
+    spec = CAP_SMALL
+    v, f = cap_mesh(spec)
+    fac = ref.Facets(v, f)
+    r, d = spec.sphere_radius, spec.depth
+    c = np.array([0.0, 0.0, r - d])
+    e = np.deg2rad(15.0)
+    s = np.array([np.cos(e), 0.0, np.sin(e)])
+    lit = ref.sun_visibility(fac, s[None, :])[:, 0].astype(bool)
+    p = fac.x - c
+    b = p @ s
+    disc = b * b - (np.sum(p * p, axis=1) - r * r)
+    t2 = -b + np.sqrt(np.maximum(disc, 0.0))
+    zexit = fac.x[:, 2] + t2 * s[2]
+    margin = 0.4 * spec.h * s[2]
+    facing = fac.n @ s > 0.05          # facets turned away are dark by the cosine factor
+    sure_lit = facing & (zexit > margin)
+    sure_dark = facing & (zexit < -margin)
+    assert sure_lit.sum() > 100 and sure_dark.sum() > 100
+    assert np.all(lit[sure_lit]) and not np.any(lit[sure_dark])
+
+
+# ---------------------------------------------------------------- P7
+def test_jacobi_matches_lapack():
+    v, f = cap_mesh(CAP_SMALL)
+    fac = ref.Facets(v, f)
+    F = ref.view_factor_matrix(fac)
+    E = np.random.default_rng(3).uniform(0, 100, (fac.N, 2))
+    for rho in (0.3, 1.0):
+        B, _ = ref.jacobi(lambda X: F @ X, rho, E, tol=1e-14)
+        B2 = ref.solve_direct(F, rho, E)
+        assert np.linalg.norm(B - B2) / np.linalg.norm(B2) < 1e-12
+
+
+# ---------------------------------------------------------------- P9
+def test_flat_plane_has_no_exchange():
+    g = np.linspace(0, 1, 9)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    verts = np.column_stack([X.ravel(), Y.ravel(), np.zeros(X.size)])
+    m = g.size
+    faces = []
+    for i in range(m - 1):
+        for j in range(m - 1):
+            a, b, c, d = i * m + j, (i + 1) * m + j, (i + 1) * m + j + 1, i * m + j + 1
+            faces += [[a, b, c], [a, c, d]]
+    fac = ref.Facets(verts, np.array(faces, dtype=np.int32))
+    F = ref.view_factor_matrix(fac, ref.pair_visibility(fac, "raycast"))
+    assert np.all(F == 0.0)
+    E = np.ones((fac.N, 1))
+    B, iters = ref.jacobi(lambda X: F @ X, 0.5, E)
+    assert np.array_equal(B, E) and iters[0] == 1
+
+
+def test_matvec_free_matches_dense():
+    v, f = cap_mesh(CapSpec(h=100.0, seed=5))
+    fac = ref.Facets(v, f)
+    F = ref.view_factor_matrix(fac)
+    X = np.random.default_rng(0).random((fac.N, 3))
+    np.testing.assert_allclose(ref.matvec_free(fac, X), F @ X, rtol=1e-13, atol=0)
+    rows = np.array([0, 5, fac.N - 1])
+    np.testing.assert_array_equal(ref.view_factor_rows(fac, rows), F[rows])
+
+
+# ---------------------------------------------------------------- H-matrix reference
+def test_quadtree_partition():
+    v, f = cap_mesh(CAP_SMALL)
+    fac = ref.Facets(v, f)
+    root = hm.quadtree(fac.x[:, :2], leaf_size=64)
+    perm = hm.tree_permutation(root)
+    assert np.array_equal(np.sort(perm), np.arange(fac.N))
+    for lf in hm.leaves(root):
+        assert 1 <= lf.size <= 64
+
+    def check(node):
+        if node.is_leaf:
+            return
+        p = fac.x[node.idx, :2]
+        xmid = 0.5 * (p[:, 0].min() + p[:, 0].max())
+        ymid = 0.5 * (p[:, 1].min() + p[:, 1].max())
+        for c in node.children:
+            q = fac.x[c.idx, :2]
+            assert np.all(q[:, 0] < xmid) or np.all(q[:, 0] >= xmid)
+            assert np.all(q[:, 1] < ymid) or np.all(q[:, 1] >= ymid)
+            check(c)
+    check(root)
+
+
+def test_rank_rule_on_known_spectrum():
+    rng = np.random.default_rng(0)
+    m, n = 120, 90
+    U, _ = np.linalg.qr(rng.standard_normal((m, 40)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, 40)))
+    sv = np.array([1.0, 0.5, 0.1, 0.01, 0.001] + [1e-6] * 35)
+    A = (U * sv) @ V.T
+    q, *_ = hm.estimate_rank(A, 0.05, 8)
+    assert q == 3                      # sigma_4 / sigma_1 = 0.01 is the first below 0.05
+    q, *_ = hm.estimate_rank(A, 2e-3, 8)
+    assert q == 4
+    q, *_ = hm.estimate_rank(A, 1e-7, 8)
+    assert q == 40                     # beyond the rank sigma is 0
+    # a rank that does not pay for itself in bytes fails
+    full = rng.standard_normal((40, 40))
+    assert hm.estimate_rank(full, 1e-12, 8) is None
+
+
+def test_hmatrix_exact_sphere_blocks_rank_one():
+    """Off-diagonal blocks of the sphere kernel are exactly rank one."""
+    fac = sphere_facets(600, seed=4)
+    F = ref.view_factor_matrix(fac)
+    # project the sphere to 2D by longitude/latitude for the quadtree
+    xy = np.column_stack([np.arctan2(fac.x[:, 1], fac.x[:, 0]), fac.x[:, 2]])
+    H = hm.assemble(F, xy, eps=1e-8, leaf_size=32)
+    for b in hm.leaf_blocks(H):
+        if b.kind == "svd" and not np.intersect1d(b.rows, b.cols).size:
+            assert b.data[0].shape[1] == 1
+    X = np.random.default_rng(1).random((fac.N, 2))
+    Y = hm.multiply(H, X)
+    assert np.linalg.norm(Y - F @ X) / np.linalg.norm(F @ X) < 1e-7
+
+
+def test_hmatrix_tiles_matrix_and_error_tracks_eps():
+    v, f = cap_mesh(CAP_SMALL)
+    fac = ref.Facets(v, f)
+    F = ref.view_factor_matrix(fac)
+    xy = fac.x[:, :2]
+    X = np.random.default_rng(2).random((fac.N, 4))
+    Y0 = F @ X
+    prev = None
+    for eps in (1e-2, 1e-3, 1e-4, 1e-6):
+        H = hm.assemble(F, xy, eps=eps)
+        blocks = hm.leaf_blocks(H)
+        cover = np.zeros((fac.N, fac.N), dtype=np.int32)
+        for b in blocks:
+            cover[np.ix_(b.rows, b.cols)] += 1
+        assert np.all(cover == 1)
+        err = np.linalg.norm(hm.multiply(H, X) - Y0) / np.linalg.norm(Y0)
+        assert err <= eps
+        if prev is not None:
+            assert H.nbytes() >= prev
+        prev = H.nbytes()
+    H = hm.assemble(F, xy, eps=1e-15)
+    np.testing.assert_allclose(hm.multiply(H, X), Y0, rtol=1e-10)
