@@ -1,0 +1,169 @@
+/*
+ * rad.h — C-ABI of librad: hierarchical low-rank view-factor matrices and
+ * radiosity solves on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Potter, Bertone, Schorghofer, Mazarico, "Fast hierarchical low-rank
+ * view factor matrices for thermal irradiance on planetary surfaces"
+ * (arXiv 2209.07632).  Equation and algorithm names below are the paper's.
+ *
+ * Conventions (all entry points)
+ *  - Status codes only; no C++ exception crosses this boundary.  On any status
+ *    other than RAD_OK, rad_last_error() returns a thread-local message.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory of the device the matrix was built on.  The caller owns every
+ *    pointer it passes; the library never frees caller memory.
+ *  - Vectors and blocks of right-hand sides are column-major N x R with a
+ *    leading dimension >= N, facets in the caller's original face order
+ *    unless RAD_ORDER_TREE is passed.
+ *  - hip_stream may be NULL (the null stream).  Work is enqueued on it;
+ *    matvec returns without waiting, solve synchronises on it because its
+ *    stopping test reads residuals back to the host.
+ *  - A rad_hmat is immutable after build; concurrent matvecs on different
+ *    streams need separate workspaces and are not supported: calls on one
+ *    matrix must be serialised by the caller.
+ */
+#ifndef RAD_H
+#define RAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rad_hmat rad_hmat;
+
+typedef enum {
+    RAD_OK = 0,
+    RAD_EINVAL = 1,  /* bad argument: null pointer, size, ld < N, non-finite input, bad mesh */
+    RAD_ENOMEM = 2,  /* device or host allocation failed                                       */
+    RAD_EDEVICE = 3, /* a HIP call failed                                                      */
+    RAD_ENOCONV = 4, /* iterative solve hit max_iter before rtol (results and info still filled) */
+    RAD_EUNSUP = 5   /* valid request this build does not implement                            */
+} rad_status;
+
+typedef enum { RAD_F64 = 0, RAD_F32 = 1, RAD_F16 = 2, RAD_BF16 = 3 } rad_dtype;
+
+/* Visibility V_ij of eq. FF-def (section 3.2). */
+typedef enum {
+    RAD_VIS_BACKFACE = 0, /* n_i.d_ij > 0 and n_j.d_ji > 0 only (no occlusion test) */
+    RAD_VIS_RAYCAST = 1   /* back-face test, then the centroid segment must miss every other triangle */
+} rad_visibility;
+
+/* Storage of leaf blocks next to the diagonal (Algorithm 4, step 2). */
+typedef enum {
+    RAD_NEAR_AUTO = 0,  /* fewer bytes of dense or CSR, as the paper states */
+    RAD_NEAR_DENSE = 1, /* always dense                                      */
+    RAD_NEAR_CSR = 2    /* always CSR                                        */
+} rad_nearfield;
+
+typedef enum { RAD_ORDER_ORIGINAL = 0, RAD_ORDER_TREE = 1 } rad_order;
+
+typedef struct {
+    double tol;           /* compression tolerance eps of Algorithm 3 (> 0)           */
+    int32_t leaf_size;    /* quadtree leaf capacity, Algorithm 2 (default 64, <= 64)  */
+    int32_t max_depth;    /* quadtree depth limit (0: none)                           */
+    int32_t nearfield;    /* rad_nearfield                                            */
+    int32_t visibility;   /* rad_visibility                                           */
+    int32_t storage;      /* RAD_F64 or RAD_F32: precision of stored blocks and of matvec/solve */
+    int32_t oversample;   /* extra sketch columns in the randomized rank search (default 8) */
+    int32_t power_iters;  /* subspace iterations of the rank search (default 1)       */
+    int32_t max_rhs;      /* workspace is sized for up to this many right-hand sides (default 1) */
+    int32_t device;       /* HIP device ordinal (default 0)                           */
+    uint64_t seed;        /* seed of the sketch's random signs                        */
+    int32_t verbose;      /* 1: print build statistics to stderr                      */
+} rad_build_opts;
+
+/* Fills *opts with the defaults listed above (tol 1e-3). */
+void rad_build_opts_default(rad_build_opts *opts);
+
+/*
+ * Builds the compressed view-factor matrix F-hat (Algorithms 2-4) from a
+ * triangle mesh: host arrays verts (nv x 3, row-major, FP64) and faces
+ * (nf x 3, row-major, 0-based int32).  Facet i is face i; its centroid,
+ * unit normal (right-hand rule) and area follow section 3.  F_ij is eq. FF-def
+ * (it includes the column area A_j), F_ii = 0.  The matrix lives on
+ * opts->device until rad_hmat_free.
+ * Errors: RAD_EINVAL for null pointers, nf < 1, indices outside [0, nv),
+ * non-finite coordinates, zero-area faces or bad options; RAD_ENOMEM;
+ * RAD_EDEVICE.  *out is NULL on error.
+ */
+rad_status rad_hmat_build(const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
+                          const rad_build_opts *opts, rad_hmat **out);
+
+/*
+ * Y = F-hat X (Algorithm 5) for R right-hand sides.  X and Y are device
+ * arrays, column-major with leading dimensions ldx, ldy >= N, of the
+ * matrix's compute dtype (rad_hmat_dtype).  X and Y must not overlap.
+ * order: rad_order of the rows of X and Y.  1 <= R <= max_rhs.
+ * Errors: RAD_EINVAL (null, R out of range, ld < N, dtype mismatch), RAD_EDEVICE.
+ */
+rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const void *X, int64_t ldx,
+                           void *Y, int64_t ldy, int32_t order, void *hip_stream);
+
+typedef struct {
+    double rtol;      /* stop column c when ||B^{k+1}-B^k||_2 <= rtol ||E_c||_2 (default 1e-3) */
+    int32_t max_iter; /* default 100                                                     */
+    int32_t order;    /* rad_order of E and B                                            */
+    int32_t check_every; /* read residuals back every this many iterations (default 1) */
+} rad_solve_opts;
+
+void rad_solve_opts_default(rad_solve_opts *opts);
+
+typedef struct {
+    int32_t *iters;      /* host, length R (or NULL): iterations at which column met rtol (-1: never) */
+    double *rel_change;  /* host, length R (or NULL): last ||B^{k+1}-B^k|| / ||E||                   */
+    int32_t total_iters; /* iterations run                                                          */
+} rad_solve_info;
+
+/*
+ * Solves (I - diag(rho) F-hat) B = E, the radiosity system eq.
+ * radiosity-system, for R right-hand sides by Jacobi relaxation
+ * B^{k+1} = E + rho (F-hat B^k), B^0 = E (sections 3 and 5.1).
+ * rho: device array of N reflectances in the order of E, or NULL to use
+ * rho_scalar for every facet.  E and B are device arrays (compute dtype,
+ * column-major, ld >= N) and may not overlap.
+ * Errors: RAD_EINVAL, RAD_ENOCONV (B holds the last iterate, info filled),
+ * RAD_EDEVICE.
+ */
+rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int64_t R, int32_t dtype,
+                     const void *E, int64_t lde, void *B, int64_t ldb, const rad_solve_opts *opts,
+                     rad_solve_info *info, void *hip_stream);
+
+typedef struct {
+    int64_t n;                 /* facets                                              */
+    int64_t n_leaves;          /* quadtree leaves                                     */
+    int32_t depth;             /* quadtree depth                                      */
+    int32_t dtype;             /* compute/storage dtype                               */
+    int64_t n_dense, n_csr, n_lowrank, n_zero; /* final blocks by kind                */
+    int64_t bytes_dense, bytes_csr, bytes_lowrank; /* stored value+index bytes by kind */
+    int64_t bytes_total;       /* all device bytes of the operator incl. task lists   */
+    int64_t nnz_near;          /* stored near-field entries (dense + CSR)             */
+    int64_t sum_rank;          /* sum of ranks of low-rank blocks                     */
+    int64_t lowrank_elems;     /* sum over low-rank blocks of (m+n) k                 */
+    int32_t max_rank;
+    double build_seconds;
+    double flops_per_rhs;      /* 2 (sum (m+n)k + nnz_near): matvec flops per column   */
+} rad_hmat_stats;
+
+rad_status rad_hmat_info(const rad_hmat *H, rad_hmat_stats *stats);
+
+/* Number of facets N and compute dtype of H (-1 when H is NULL). */
+int64_t rad_hmat_n(const rad_hmat *H);
+int32_t rad_hmat_dtype(const rad_hmat *H);
+
+/* perm (host, length N): perm[t] = original index of the facet in tree position t. */
+rad_status rad_hmat_perm(const rad_hmat *H, int32_t *perm);
+
+/* Releases H and its device memory.  NULL is allowed. */
+void rad_hmat_free(rad_hmat *H);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *rad_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAD_H */

@@ -1,0 +1,243 @@
+// C-ABI of librad: argument checks, error translation, workspace, solve loop.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "rad_internal.h"
+
+namespace rad {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+static int dsize(int32_t dt) { return dt == RAD_F64 ? 8 : dt == RAD_F32 ? 4 : 2; }
+
+static void alloc_workspace(rad_hmat *H) {
+    size_t s = (size_t)dsize(H->dtype);
+    size_t nr = (size_t)H->N * (size_t)H->max_rhs;
+    H->w_x.alloc(nr * s);
+    H->w_y.alloc(nr * s);
+    H->w_b.alloc(nr * s);
+    H->w_e.alloc(nr * s);
+    H->w_t.alloc((size_t)std::max(H->t_ld, 4) * (size_t)H->max_rhs * s);
+    H->w_rho.alloc((size_t)H->N * s);
+    H->w_red.alloc(reduction_doubles(H->max_rhs) * sizeof(double));
+    H->w_norms.alloc((size_t)3 * H->max_rhs);
+}
+
+template <class F>
+static rad_status guard(F &&f) {
+    try {
+        f();
+        return RAD_OK;
+    } catch (const Error &e) {
+        set_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return RAD_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return RAD_EDEVICE;
+    }
+}
+
+static void check_hmat(const rad_hmat *H) { RAD_REQUIRE(H != nullptr, "null matrix handle"); }
+
+}  // namespace rad
+
+using namespace rad;
+
+extern "C" {
+
+void rad_build_opts_default(rad_build_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-3;
+    o->leaf_size = 64;
+    o->max_depth = 0;
+    o->nearfield = RAD_NEAR_AUTO;
+    o->visibility = RAD_VIS_BACKFACE;
+    o->storage = RAD_F64;
+    o->oversample = 8;
+    o->power_iters = 1;
+    o->max_rhs = 1;
+    o->device = 0;
+    o->seed = 0x5eed;
+    o->verbose = 0;
+}
+
+void rad_solve_opts_default(rad_solve_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->rtol = 1e-3;
+    o->max_iter = 100;
+    o->order = RAD_ORDER_ORIGINAL;
+    o->check_every = 1;
+}
+
+const char *rad_last_error(void) { return g_last_error.c_str(); }
+
+rad_status rad_hmat_build(const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
+                          const rad_build_opts *opts, rad_hmat **out) {
+    if (out) *out = nullptr;
+    rad_hmat *H = nullptr;
+    rad_status st = guard([&] {
+        RAD_REQUIRE(out != nullptr, "null output pointer");
+        rad_build_opts o;
+        if (opts)
+            o = *opts;
+        else
+            rad_build_opts_default(&o);
+        H = new rad_hmat();
+        build_hmat(H, verts, nv, faces, nf, o);
+        alloc_workspace(H);
+    });
+    if (st != RAD_OK) {
+        delete H;
+        return st;
+    }
+    *out = H;
+    return RAD_OK;
+}
+
+void rad_hmat_free(rad_hmat *H) {
+    if (!H) return;
+    (void)hipSetDevice(H->device);
+    delete H;
+}
+
+int64_t rad_hmat_n(const rad_hmat *H) { return H ? H->N : -1; }
+int32_t rad_hmat_dtype(const rad_hmat *H) { return H ? H->dtype : -1; }
+
+rad_status rad_hmat_info(const rad_hmat *H, rad_hmat_stats *s) {
+    return guard([&] {
+        check_hmat(H);
+        RAD_REQUIRE(s != nullptr, "null stats pointer");
+        *s = H->stats;
+    });
+}
+
+rad_status rad_hmat_perm(const rad_hmat *H, int32_t *perm) {
+    return guard([&] {
+        check_hmat(H);
+        RAD_REQUIRE(perm != nullptr, "null perm pointer");
+        std::copy(H->perm.begin(), H->perm.end(), perm);
+    });
+}
+
+rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const void *X, int64_t ldx, void *Y,
+                           int64_t ldy, int32_t order, void *hip_stream) {
+    return guard([&] {
+        check_hmat(H);
+        RAD_REQUIRE(X && Y, "null X or Y");
+        RAD_REQUIRE(dtype == H->dtype, "dtype does not match the matrix");
+        RAD_REQUIRE(R >= 1 && R <= H->max_rhs, "R must be in [1, max_rhs]");
+        RAD_REQUIRE(ldx >= H->N && ldy >= H->N, "leading dimension smaller than N");
+        RAD_REQUIRE(order == RAD_ORDER_ORIGINAL || order == RAD_ORDER_TREE, "bad order");
+        RAD_HIP(hipSetDevice(H->device));
+        hipStream_t s = (hipStream_t)hip_stream;
+        if (order == RAD_ORDER_TREE) {
+            mv_apply(H, X, ldx, Y, ldy, R, s);
+        } else {
+            mv_gather(H, X, ldx, H->w_x.p, H->N, R, s);
+            mv_apply(H, H->w_x.p, H->N, H->w_y.p, H->N, R, s);
+            mv_scatter(H, H->w_y.p, H->N, Y, ldy, R, s);
+        }
+    });
+}
+
+rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int64_t R, int32_t dtype, const void *E,
+                     int64_t lde, void *B, int64_t ldb, const rad_solve_opts *opts, rad_solve_info *info,
+                     void *hip_stream) {
+    rad_status conv = RAD_OK;
+    rad_status st = guard([&] {
+        check_hmat(H);
+        RAD_REQUIRE(E && B, "null E or B");
+        RAD_REQUIRE(dtype == H->dtype, "dtype does not match the matrix");
+        RAD_REQUIRE(R >= 1 && R <= H->max_rhs, "R must be in [1, max_rhs]");
+        RAD_REQUIRE(lde >= H->N && ldb >= H->N, "leading dimension smaller than N");
+        RAD_REQUIRE(std::isfinite(rho_scalar), "rho_scalar must be finite");
+        rad_solve_opts o;
+        if (opts)
+            o = *opts;
+        else
+            rad_solve_opts_default(&o);
+        RAD_REQUIRE(o.rtol > 0 && o.max_iter >= 1 && o.check_every >= 1, "bad solve options");
+        RAD_HIP(hipSetDevice(H->device));
+        hipStream_t s = (hipStream_t)hip_stream;
+        const int64_t N = H->N;
+        const size_t es = (size_t)dsize(H->dtype);
+        void *Et = H->w_e.p;
+        void *Bk = H->w_x.p;
+        void *FB = H->w_y.p;
+        void *Bn = H->w_b.p;
+        const void *rho_t = nullptr;
+        if (o.order == RAD_ORDER_TREE) {
+            RAD_HIP(hipMemcpy2DAsync(Et, N * es, E, lde * es, N * es, R, hipMemcpyDeviceToDevice, s));
+            if (rho) {
+                RAD_HIP(hipMemcpyAsync(H->w_rho.p, rho, N * es, hipMemcpyDeviceToDevice, s));
+                rho_t = H->w_rho.p;
+            }
+        } else {
+            mv_gather(H, E, lde, Et, N, R, s);
+            if (rho) {
+                mv_gather(H, rho, N, H->w_rho.p, N, 1, s);
+                rho_t = H->w_rho.p;
+            }
+        }
+        RAD_HIP(hipMemcpyAsync(Bk, Et, (size_t)N * R * es, hipMemcpyDeviceToDevice, s));
+        double *enorm_d = H->w_norms.p;
+        double *dnorm_d = H->w_norms.p + H->max_rhs;
+        col_norms2(H, Et, N, R, enorm_d, s);
+        std::vector<double> enorm(R), dn(R);
+        RAD_HIP(hipMemcpyAsync(enorm.data(), enorm_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
+        RAD_HIP(hipStreamSynchronize(s));
+        for (auto &v : enorm) {
+            RAD_REQUIRE(std::isfinite(v), "E contains non-finite values");
+            v = std::sqrt(v);
+        }
+        std::vector<int32_t> iters(R, -1);
+        std::vector<double> rel(R, 0.0);
+        int k = 0;
+        bool done = false;
+        while (k < o.max_iter && !done) {
+            ++k;
+            mv_apply(H, Bk, N, FB, N, R, s);
+            solve_update(H, Et, rho_t, rho_scalar, FB, Bk, Bn, N, R, dnorm_d, s);
+            std::swap(Bk, Bn);
+            if (k % o.check_every == 0 || k == o.max_iter) {
+                RAD_HIP(hipMemcpyAsync(dn.data(), dnorm_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
+                RAD_HIP(hipStreamSynchronize(s));
+                done = true;
+                for (int64_t c = 0; c < R; ++c) {
+                    double d = std::sqrt(dn[c]);
+                    rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
+                    RAD_REQUIRE(std::isfinite(rel[c]), "solve produced non-finite values");
+                    if (iters[c] < 0 && rel[c] <= o.rtol) iters[c] = k;
+                    if (iters[c] < 0) done = false;
+                }
+            }
+        }
+        if (o.order == RAD_ORDER_TREE)
+            RAD_HIP(hipMemcpy2DAsync(B, ldb * es, Bk, N * es, N * es, R, hipMemcpyDeviceToDevice, s));
+        else
+            mv_scatter(H, Bk, N, B, ldb, R, s);
+        RAD_HIP(hipStreamSynchronize(s));
+        if (info) {
+            if (info->iters) std::copy(iters.begin(), iters.end(), info->iters);
+            if (info->rel_change) std::copy(rel.begin(), rel.end(), info->rel_change);
+            info->total_iters = k;
+        }
+        if (!done) {
+            conv = RAD_ENOCONV;
+            set_error("Jacobi reached max_iter before rtol");
+        }
+    });
+    return st != RAD_OK ? st : conv;
+}
+
+}  // extern "C"

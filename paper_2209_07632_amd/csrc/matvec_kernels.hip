@@ -1,0 +1,227 @@
+// H-matvec Y = F-hat X (Algorithm 5) and the Jacobi update of the radiosity
+// solve, on the device layout written by the builder.
+//
+// Two phases per product, both owner-computes (no atomics, deterministic):
+//   phase 1: for every column node J with low-rank blocks, T_J = V_J^T X_J
+//            (V_J = the V factors of all those blocks stacked side by side);
+//   phase 2: for every quadtree leaf L (rows I_L):
+//            Y_L = sum_dense A_LJ X_J + sum_csr A_LJ X_J + sum_lowrank U'_L T_b.
+#include <hip/hip_runtime.h>
+
+#include "rad_internal.h"
+
+namespace rad {
+
+namespace {
+
+template <class T>
+__device__ __forceinline__ T wsum(T v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <class T>
+__global__ void k_gather(const int32_t *perm, const T *src, int64_t lds, T *dst, int64_t ldd, int64_t N, int64_t R) {
+    int64_t tot = N * R;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = e / N, t = e - r * N;
+        dst[t + r * ldd] = src[(int64_t)perm[t] + r * lds];
+    }
+}
+
+template <class T>
+__global__ void k_scatter(const int32_t *perm, const T *src, int64_t lds, T *dst, int64_t ldd, int64_t N, int64_t R) {
+    int64_t tot = N * R;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = e / N, t = e - r * N;
+        dst[(int64_t)perm[t] + r * ldd] = src[t + r * lds];
+    }
+}
+
+// phase 1: one wave per stacked V column, lanes stride the rows of X_J
+template <class T>
+__global__ void __launch_bounds__(256) k_proj(const ProjGroup *groups, const T *vals, const T *X, int64_t ldx,
+                                               T *Tb, int32_t t_ld) {
+    const ProjGroup g = groups[blockIdx.x];
+    const int64_t r = blockIdx.z;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const T *x = X + g.j0 + r * ldx;
+    for (int kk = blockIdx.y * 4 + w; kk < g.ktot; kk += gridDim.y * 4) {
+        const T *v = vals + g.v_off + (int64_t)kk * g.ld;
+        T acc = 0;
+        for (int j = lane; j < g.n; j += 64) acc += v[j] * x[j];
+        acc = wsum(acc);
+        if (lane == 0) Tb[g.t_off + kk + r * t_ld] = acc;
+    }
+}
+
+// phase 2: one workgroup per (leaf, right-hand side); wave w takes tasks w, w+4, ...
+// Leaves larger than 64 rows (depth limit, coincident centroids) are walked in
+// chunks of 64 rows.
+template <class T>
+__global__ void __launch_bounds__(256) k_leaf(const LeafInfo *leaves, const LeafTask *tasks, const T *vals,
+                                               const int32_t *csr_ptr, const int32_t *csr_idx, int64_t csr_val_start,
+                                               const T *X, int64_t ldx, const T *Tb, int32_t t_ld, T *Y, int64_t ldy) {
+    const LeafInfo L = leaves[blockIdx.x];
+    const int64_t r = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const T *x = X + r * ldx;
+    const T *tb = Tb + r * t_ld;
+    __shared__ T red[4][64];
+    for (int rb = 0; rb < L.size; rb += 64) {
+        const int row = rb + lane;
+        T acc = 0;
+        if (row < L.size) {
+            for (int ti = L.task_begin + w; ti < L.task_end; ti += 4) {
+                const LeafTask tk = tasks[ti];
+                if (tk.type == TASK_DENSE) {
+                    const T *a = vals + tk.a_off + row;
+                    const T *xc = x + tk.col0;
+                    for (int c = 0; c < tk.ncol; ++c) acc += a[(int64_t)c * tk.ld] * xc[c];
+                } else if (tk.type == TASK_LOWRANK) {
+                    const T *a = vals + tk.a_off + row;
+                    const T *tc = tb + tk.col0;
+                    for (int k = 0; k < tk.ncol; ++k) acc += a[(int64_t)k * tk.ld] * tc[k];
+                } else {
+                    const int32_t *ptr = csr_ptr + tk.aux_off;
+                    const T *v = vals + tk.a_off;
+                    const int32_t *ci = csr_idx + (tk.a_off - csr_val_start);
+                    const T *xc = x + tk.col0;
+                    for (int e = ptr[row]; e < ptr[row + 1]; ++e) acc += v[e] * xc[ci[e]];
+                }
+            }
+        }
+        red[w][lane] = acc;
+        __syncthreads();
+        if (w == 0 && row < L.size) {
+            T s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+            Y[L.start + row + r * ldy] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// B_new = E + rho * FB; partial[col][block] = sum (B_new - B_old)^2
+template <class T>
+__global__ void __launch_bounds__(256) k_jacobi_update(const T *E, const T *rho, T rho_s, const T *FB, const T *Bold,
+                                                        T *Bnew, int64_t N, int64_t ld, double *partial) {
+    const int64_t r = blockIdx.y;
+    double s = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
+        T rh = rho ? rho[t] : rho_s;
+        int64_t e = t + r * ld;
+        T b = E[e] + rh * FB[e];
+        double d = (double)b - (double)Bold[e];
+        s += d * d;
+        Bnew[e] = b;
+    }
+    s = wsum(s);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x + r * gridDim.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_colnorm2(const T *E, int64_t N, int64_t ld, double *partial) {
+    const int64_t r = blockIdx.y;
+    double s = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
+        double v = (double)E[t + r * ld];
+        s += v * v;
+    }
+    s = wsum(s);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x + r * gridDim.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// deterministic per-column sum of the partials
+__global__ void k_reduce_cols(const double *partial, int nparts, int64_t R, double *out) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += partial[i + r * nparts];
+    out[r] = s;
+}
+
+template <class T>
+void apply_t(const rad_hmat *H, const T *X, int64_t ldx, T *Y, int64_t ldy, int64_t R, T *Tb, hipStream_t s) {
+    if (H->n_groups > 0) {
+        int maxk = 0;
+        for (const ProjGroup &g : H->h_groups) maxk = std::max(maxk, g.ktot);
+        dim3 grid(H->n_groups, std::max(1, std::min(64, (maxk + 3) / 4)), (unsigned)R);
+        hipLaunchKernelGGL(k_proj<T>, grid, dim3(256), 0, s, H->d_groups.p, (const T *)H->d_vals.p, X, ldx, Tb,
+                           H->t_ld);
+        RAD_HIP(hipGetLastError());
+    }
+    dim3 grid2(H->n_leaves, (unsigned)R);
+    hipLaunchKernelGGL(k_leaf<T>, grid2, dim3(256), 0, s, H->d_leaves.p, H->d_tasks.p, (const T *)H->d_vals.p,
+                       H->d_csr_ptr.p, H->d_csr_idx.p, H->csr_val_start, X, ldx, (const T *)Tb, H->t_ld, Y, ldy);
+    RAD_HIP(hipGetLastError());
+}
+
+constexpr int kRedParts = 128;
+
+}  // namespace
+
+void mv_gather(const rad_hmat *H, const void *src, int64_t lds, void *dst, int64_t ldd, int64_t R, hipStream_t s) {
+    int64_t tot = H->N * R;
+    unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 8192);
+    if (H->dtype == RAD_F64)
+        hipLaunchKernelGGL(k_gather<double>, dim3(blocks), dim3(256), 0, s, H->d_perm.p, (const double *)src, lds,
+                           (double *)dst, ldd, H->N, R);
+    else
+        hipLaunchKernelGGL(k_gather<float>, dim3(blocks), dim3(256), 0, s, H->d_perm.p, (const float *)src, lds,
+                           (float *)dst, ldd, H->N, R);
+    RAD_HIP(hipGetLastError());
+}
+
+void mv_scatter(const rad_hmat *H, const void *src, int64_t lds, void *dst, int64_t ldd, int64_t R, hipStream_t s) {
+    int64_t tot = H->N * R;
+    unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 8192);
+    if (H->dtype == RAD_F64)
+        hipLaunchKernelGGL(k_scatter<double>, dim3(blocks), dim3(256), 0, s, H->d_perm.p, (const double *)src, lds,
+                           (double *)dst, ldd, H->N, R);
+    else
+        hipLaunchKernelGGL(k_scatter<float>, dim3(blocks), dim3(256), 0, s, H->d_perm.p, (const float *)src, lds,
+                           (float *)dst, ldd, H->N, R);
+    RAD_HIP(hipGetLastError());
+}
+
+void mv_apply(const rad_hmat *H, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R, hipStream_t s) {
+    if (H->dtype == RAD_F64)
+        apply_t<double>(H, (const double *)X, ldx, (double *)Y, ldy, R, (double *)H->w_t.p, s);
+    else
+        apply_t<float>(H, (const float *)X, ldx, (float *)Y, ldy, R, (float *)H->w_t.p, s);
+}
+
+void col_norms2(const rad_hmat *H, const void *E, int64_t ld, int64_t R, double *out, hipStream_t s) {
+    dim3 grid(kRedParts, (unsigned)R);
+    double *part = (double *)H->w_red.p;
+    if (H->dtype == RAD_F64)
+        hipLaunchKernelGGL(k_colnorm2<double>, grid, dim3(256), 0, s, (const double *)E, H->N, ld, part);
+    else
+        hipLaunchKernelGGL(k_colnorm2<float>, grid, dim3(256), 0, s, (const float *)E, H->N, ld, part);
+    hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, part, kRedParts, R, out);
+    RAD_HIP(hipGetLastError());
+}
+
+void solve_update(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *FB,
+                  const void *Bold, void *Bnew, int64_t ld, int64_t R, double *norms, hipStream_t s) {
+    dim3 grid(kRedParts, (unsigned)R);
+    double *part = (double *)H->w_red.p;
+    if (H->dtype == RAD_F64)
+        hipLaunchKernelGGL(k_jacobi_update<double>, grid, dim3(256), 0, s, (const double *)E, (const double *)rho,
+                           rho_scalar, (const double *)FB, (const double *)Bold, (double *)Bnew, H->N, ld, part);
+    else
+        hipLaunchKernelGGL(k_jacobi_update<float>, grid, dim3(256), 0, s, (const float *)E, (const float *)rho,
+                           (float)rho_scalar, (const float *)FB, (const float *)Bold, (float *)Bnew, H->N, ld, part);
+    hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, part, kRedParts, R, norms);
+    RAD_HIP(hipGetLastError());
+}
+
+size_t reduction_doubles(int64_t R) { return (size_t)kRedParts * (size_t)R; }
+
+}  // namespace rad

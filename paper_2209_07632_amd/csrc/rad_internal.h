@@ -1,0 +1,225 @@
+// Internal declarations of librad (not part of the public C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "rad.h"
+
+namespace rad {
+
+struct Error : std::runtime_error {
+    rad_status code;
+    Error(rad_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define RAD_HIP(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            throw ::rad::Error(RAD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define RAD_REQUIRE(cond, msg)                                 \
+    do {                                                       \
+        if (!(cond))                                           \
+            throw ::rad::Error(RAD_EINVAL, std::string(msg));  \
+    } while (0)
+
+// Owning device allocation.
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) return;
+        hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error(RAD_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        }
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void upload(const std::vector<T> &h) {
+        alloc(h.size());
+        if (!h.empty()) RAD_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+    std::vector<T> download(size_t count) const {
+        std::vector<T> h(count);
+        if (count) RAD_HIP(hipMemcpy(h.data(), p, count * sizeof(T), hipMemcpyDeviceToHost));
+        return h;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// ----------------------------------------------------------------------------
+// Quadtree (Algorithm 2) and block pairs (Algorithm 4)
+// ----------------------------------------------------------------------------
+struct TreeNode {
+    int32_t start;        // first facet (tree order)
+    int32_t size;         // number of facets
+    int32_t depth;
+    int32_t first_child;  // index of first child node, children contiguous; -1 for a leaf
+    int32_t nchild;
+    int32_t leaf_index;   // position among leaves (DFS order), -1 for internal nodes
+    int32_t leaf_first;   // first leaf under this node
+    int32_t leaf_count;   // leaves under this node
+};
+
+enum BlockKind : int8_t { BK_ZERO = 0, BK_DENSE = 1, BK_CSR = 2, BK_LOWRANK = 3, BK_HIER = 4 };
+
+struct BlockPair {
+    int32_t I, J;          // tree node indices
+    int32_t level;         // 0 = pairs of the root's children
+    int32_t first_child;   // -1 for a leaf pair
+    int32_t nchild;
+    int64_t nnz;           // non-zero entries of F_IJ
+    int64_t best_bytes;    // bytes of the chosen representation
+    int8_t kind;           // chosen BlockKind
+    int32_t rank;          // accepted SVD rank (0: none)
+    int64_t svd_bytes;     // bytes of the accepted SVD (-1: none)
+    int64_t cand_off;      // offset of the candidate factors in its level pool (doubles)
+    int32_t cand_level;
+};
+
+// Sketch task for the randomized rank search: one block of F.
+struct SketchBlock {
+    int32_t i0, m;         // rows [i0, i0+m) in tree order
+    int32_t j0, n;         // cols [j0, j0+n)
+    int32_t ell;           // sketch width
+    int32_t pad_;
+    int64_t y_off;         // m x ell (col-major, ld = m) in the Y workspace
+    int64_t z_off;         // n x ell (col-major, ld = n) in the Z workspace
+    uint64_t seed;
+};
+
+// Phase-2 task of one row leaf.
+enum TaskType : int32_t { TASK_DENSE = 0, TASK_CSR = 1, TASK_LOWRANK = 2 };
+struct LeafTask {
+    int32_t type;
+    int32_t ncol;          // dense/CSR: columns n of the block; low-rank: rank k
+    int32_t ld;            // leading dimension of the slice (dense, low-rank)
+    int32_t col0;          // first column (tree order) of the block (dense/CSR) or T row offset (low-rank)
+    int64_t a_off;         // value offset of the slice (dense/low-rank) or of the CSR values base
+    int64_t aux_off;       // CSR: offset of this slice's row pointers (int32, m_L+1 entries)
+};
+
+// Phase-1 group: all low-rank blocks sharing column node J.
+struct ProjGroup {
+    int32_t j0, n;         // X rows
+    int32_t ktot;          // stacked rank
+    int32_t ld;            // leading dimension of stacked V (>= n, multiple of 4)
+    int64_t v_off;         // value offset of V_J (n x ktot, col-major)
+    int32_t t_off;         // row offset of T_J in T
+    int32_t pad_;
+};
+
+struct LeafInfo {
+    int32_t start, size;   // rows (tree order)
+    int32_t task_begin, task_end;
+};
+
+}  // namespace rad
+
+// Opaque matrix handle (device-resident operator + host metadata).
+struct rad_hmat {
+    int device = 0;
+    int64_t N = 0;
+    int32_t dtype = RAD_F64;   // storage and compute dtype
+    int32_t max_rhs = 1;
+    int32_t leaf_size = 64;
+    std::vector<int32_t> perm;        // tree position -> original facet
+    std::vector<rad::TreeNode> nodes;
+    rad_hmat_stats stats{};
+
+    // device operator
+    rad::DevBuf<int32_t> d_perm;       // tree -> original
+    rad::DevBuf<unsigned char> d_vals; // value pool (dtype)
+    rad::DevBuf<int32_t> d_csr_idx;    // CSR column indices (local to the block)
+    rad::DevBuf<int32_t> d_csr_ptr;    // CSR row pointers per leaf slice
+    rad::DevBuf<rad::LeafTask> d_tasks;
+    rad::DevBuf<rad::LeafInfo> d_leaves;
+    rad::DevBuf<rad::ProjGroup> d_groups;
+    int32_t n_leaves = 0, n_groups = 0, t_rows = 0, t_ld = 0;
+    int32_t max_leaf_rows = 0;
+    int64_t csr_val_start = 0;
+    std::vector<rad::LeafInfo> h_leaves;
+    std::vector<rad::LeafTask> h_tasks;
+    std::vector<rad::ProjGroup> h_groups;
+
+    // workspace (sized for max_rhs)
+    rad::DevBuf<unsigned char> w_x, w_y, w_t, w_b, w_e, w_rho, w_red;
+    rad::DevBuf<double> w_norms;
+};
+
+namespace rad {
+
+// thread-local error text
+void set_error(const std::string &msg);
+
+// builder entry (build.cpp)
+void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
+                const rad_build_opts &o);
+
+// device geometry used by the build kernels (tree order, FP64)
+struct DevGeom {
+    const double *x;   // N x 3
+    const double *n;   // N x 3
+    const double *a;   // N
+    const uint32_t *vis;  // optional visibility bitmap (N x N bits, row-major), nullptr = back-face only
+    int64_t vis_words_per_row;
+};
+
+// build kernels (build_kernels.hip)
+void launch_leaf_nnz(const DevGeom &g, const int32_t *pairs /*4 per pair: i0,m,j0,n*/, int64_t npairs,
+                     int64_t *nnz_out, hipStream_t s);
+void launch_fill_rademacher(double *Z, const SketchBlock *blocks, int32_t nblocks, hipStream_t s);
+void launch_sketch_apply(const DevGeom &g, const SketchBlock *blocks, int32_t nblocks, int transpose,
+                         const double *in, double *out, int32_t max_rows, int32_t max_ell, hipStream_t s);
+void launch_cgs2(double *Ybase, const SketchBlock *blocks, int32_t nblocks, int use_z, double *Rout,
+                 const int64_t *roff, hipStream_t s);
+void launch_small_gemm(const double *Qbase, const SketchBlock *blocks, const int64_t *small_off,
+                       const double *small, const int32_t *qk, const int64_t *out_off, double *out,
+                       int32_t nblocks, int use_z, int32_t max_rows, hipStream_t s);
+void launch_dense_fill(const DevGeom &g, const int32_t *tiles /*6 per: i0,m,j0,n,ld,pad*/,
+                       const int64_t *offs, int64_t ntiles, void *vals, int32_t dtype, hipStream_t s);
+void launch_csr_count(const DevGeom &g, const int32_t *tiles, int64_t ntiles, int32_t *row_counts,
+                      const int64_t *row_offs, hipStream_t s);
+void launch_csr_fill(const DevGeom &g, const int32_t *tiles, int64_t ntiles, const int32_t *rowptr,
+                     const int64_t *row_offs, const int64_t *val_base, void *vals, int32_t *cols,
+                     int32_t dtype, hipStream_t s);
+void launch_copy_cast(const double *src, int64_t rows, int64_t cols, int64_t lds, void *dst,
+                      int64_t ldd, int32_t dtype, hipStream_t s);
+void launch_visibility_bitmap(const DevGeom &g, int64_t N, const double *tri, const int32_t *perm,
+                              uint32_t *bits, hipStream_t s);
+
+// matvec / solve kernels (matvec_kernels.hip)
+void mv_gather(const rad_hmat *H, const void *src, int64_t lds, void *dst, int64_t ldd, int64_t R, hipStream_t s);
+void mv_scatter(const rad_hmat *H, const void *src, int64_t lds, void *dst, int64_t ldd, int64_t R, hipStream_t s);
+void mv_apply(const rad_hmat *H, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R, hipStream_t s);
+void col_norms2(const rad_hmat *H, const void *E, int64_t ld, int64_t R, double *out, hipStream_t s);
+void solve_update(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *FB,
+                  const void *Bold, void *Bnew, int64_t ld, int64_t R, double *norms, hipStream_t s);
+size_t reduction_doubles(int64_t R);
+
+}  // namespace rad

@@ -1,0 +1,240 @@
+"""ctypes binding of librad (the C-ABI in include/rad.h).
+
+Argument marshalling only: every step of the computation runs in librad's
+HIP kernels.  Device tensors are torch CUDA tensors; the binding passes their
+data pointers and the current torch stream.  There is no fallback: if
+librad.so is missing or the device is not available, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librad.so")
+
+RAD_OK, RAD_EINVAL, RAD_ENOMEM, RAD_EDEVICE, RAD_ENOCONV, RAD_EUNSUP = range(6)
+RAD_F64, RAD_F32, RAD_F16, RAD_BF16 = range(4)
+NEARFIELD = {"auto": 0, "dense": 1, "csr": 2}
+VISIBILITY = {"backface": 0, "raycast": 1}
+ORDER = {"original": 0, "tree": 1}
+DTYPES = {"f64": RAD_F64, "f32": RAD_F32}
+
+
+class RadError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"librad status {status}: {msg}")
+        self.status = status
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("leaf_size", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("nearfield", ctypes.c_int32), ("visibility", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("oversample", ctypes.c_int32), ("power_iters", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("seed", ctypes.c_uint64), ("verbose", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("check_every", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.POINTER(ctypes.c_int32)), ("rel_change", ctypes.POINTER(ctypes.c_double)),
+                ("total_iters", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_leaves", ctypes.c_int64), ("depth", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("n_dense", ctypes.c_int64), ("n_csr", ctypes.c_int64),
+                ("n_lowrank", ctypes.c_int64), ("n_zero", ctypes.c_int64), ("bytes_dense", ctypes.c_int64),
+                ("bytes_csr", ctypes.c_int64), ("bytes_lowrank", ctypes.c_int64), ("bytes_total", ctypes.c_int64),
+                ("nnz_near", ctypes.c_int64), ("sum_rank", ctypes.c_int64), ("lowrank_elems", ctypes.c_int64),
+                ("max_rank", ctypes.c_int32), ("build_seconds", ctypes.c_double), ("flops_per_rhs", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_matvec", "rad_solve_opts_default", "rad_solve",
+           "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free", "rad_last_error"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librad.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2209_07632_amd.build_lib.build()")
+    L = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    L.rad_build_opts_default.argtypes = [ctypes.POINTER(BuildOpts)]
+    L.rad_build_opts_default.restype = None
+    L.rad_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
+    L.rad_solve_opts_default.restype = None
+    L.rad_hmat_build.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, ctypes.POINTER(BuildOpts),
+                                 ctypes.POINTER(vp)]
+    L.rad_hmat_build.restype = ctypes.c_int
+    L.rad_hmat_matvec.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int64, vp, ctypes.c_int64,
+                                  ctypes.c_int32, vp]
+    L.rad_hmat_matvec.restype = ctypes.c_int
+    L.rad_solve.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int64, vp,
+                            ctypes.c_int64, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
+    L.rad_solve.restype = ctypes.c_int
+    L.rad_hmat_info.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.rad_hmat_info.restype = ctypes.c_int
+    L.rad_hmat_n.argtypes = [vp]
+    L.rad_hmat_n.restype = ctypes.c_int64
+    L.rad_hmat_dtype.argtypes = [vp]
+    L.rad_hmat_dtype.restype = ctypes.c_int32
+    L.rad_hmat_perm.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.rad_hmat_perm.restype = ctypes.c_int
+    L.rad_hmat_free.argtypes = [vp]
+    L.rad_hmat_free.restype = None
+    L.rad_last_error.argtypes = []
+    L.rad_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != RAD_OK:
+        raise RadError(status, load().rad_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _colmajor(t, N):
+    """View a (N,) or (N,R) device tensor as column-major with leading dimension >= N."""
+    if t.dim() == 1:
+        t = t.reshape(N, 1)
+    if t.stride(0) != 1 or (t.shape[1] > 1 and t.stride(1) < N):
+        t = t.t().contiguous().t()
+    ld = t.stride(1) if t.shape[1] > 1 else N
+    return t, ld
+
+
+class HMatrix:
+    """Compressed view-factor matrix F-hat resident on one GPU."""
+
+    def __init__(self, verts, faces, tol=1e-3, leaf_size=64, max_depth=0, nearfield="auto",
+                 visibility="backface", storage="f64", oversample=8, power_iters=1, max_rhs=1, device=0,
+                 seed=0x5EED, verbose=False):
+        L = load()
+        o = BuildOpts()
+        L.rad_build_opts_default(ctypes.byref(o))
+        o.tol = float(tol)
+        o.leaf_size = int(leaf_size)
+        o.max_depth = int(max_depth)
+        o.nearfield = NEARFIELD[nearfield]
+        o.visibility = VISIBILITY[visibility]
+        o.storage = DTYPES[storage]
+        o.oversample = int(oversample)
+        o.power_iters = int(power_iters)
+        o.max_rhs = int(max_rhs)
+        o.device = int(device)
+        o.seed = int(seed)
+        o.verbose = int(bool(verbose))
+        v = np.ascontiguousarray(verts, dtype=np.float64)
+        f = np.ascontiguousarray(faces, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(L.rad_hmat_build(v.ctypes.data, v.shape[0], f.ctypes.data, f.shape[0], ctypes.byref(o),
+                                ctypes.byref(h)))
+        self._h = h
+        self.N = int(L.rad_hmat_n(h))
+        self.rad_dtype = int(L.rad_hmat_dtype(h))
+        self.max_rhs = int(max_rhs)
+        self.device = int(device)
+
+    @property
+    def torch_dtype(self):
+        torch = _torch()
+        return torch.float64 if self.rad_dtype == RAD_F64 else torch.float32
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(load().rad_hmat_info(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def perm(self) -> np.ndarray:
+        p = np.empty(self.N, dtype=np.int32)
+        _check(load().rad_hmat_perm(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return p
+
+    def matvec(self, X, out=None, order="original"):
+        """Y = F-hat X for a device tensor X of shape (N,) or (N, R)."""
+        torch = _torch()
+        squeeze = X.dim() == 1
+        Xc, ldx = _colmajor(X, self.N)
+        R = Xc.shape[1]
+        if out is None:
+            out = torch.empty((R, self.N), dtype=X.dtype, device=X.device).t()
+        Yc, ldy = _colmajor(out, self.N)
+        _check(load().rad_hmat_matvec(self._h, R, self.rad_dtype, ctypes.c_void_p(Xc.data_ptr()), ldx,
+                                      ctypes.c_void_p(Yc.data_ptr()), ldy, ORDER[order], _stream_handle()))
+        if Yc.data_ptr() != out.data_ptr():
+            out.copy_(Yc)
+        return out.reshape(-1) if squeeze else out
+
+    def solve(self, E, rho=0.3, rtol=1e-3, max_iter=100, order="original", check_every=1, out=None,
+              raise_on_noconv=True):
+        """Jacobi solve of (I - diag(rho) F-hat) B = E; returns (B, info dict)."""
+        torch = _torch()
+        L = load()
+        squeeze = E.dim() == 1
+        Ec, lde = _colmajor(E, self.N)
+        R = Ec.shape[1]
+        if out is None:
+            out = torch.empty((R, self.N), dtype=E.dtype, device=E.device).t()
+        Bc, ldb = _colmajor(out, self.N)
+        rho_ptr = ctypes.c_void_p(0)
+        rho_s = 0.0
+        if isinstance(rho, (float, int)):
+            rho_s = float(rho)
+        else:
+            rho_t = rho.contiguous()
+            rho_ptr = ctypes.c_void_p(rho_t.data_ptr())
+        o = SolveOpts()
+        L.rad_solve_opts_default(ctypes.byref(o))
+        o.rtol = float(rtol)
+        o.max_iter = int(max_iter)
+        o.order = ORDER[order]
+        o.check_every = int(check_every)
+        iters = np.zeros(R, dtype=np.int32)
+        rel = np.zeros(R, dtype=np.float64)
+        info = SolveInfo(iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         rel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0)
+        st = L.rad_solve(self._h, rho_ptr, rho_s, R, self.rad_dtype, ctypes.c_void_p(Ec.data_ptr()), lde,
+                         ctypes.c_void_p(Bc.data_ptr()), ldb, ctypes.byref(o), ctypes.byref(info),
+                         _stream_handle())
+        if st != RAD_OK and not (st == RAD_ENOCONV and not raise_on_noconv):
+            _check(st)
+        if Bc.data_ptr() != out.data_ptr():
+            out.copy_(Bc)
+        res = {"iters": iters, "rel_change": rel, "total_iters": int(info.total_iters),
+               "converged": st == RAD_OK}
+        return (out.reshape(-1) if squeeze else out), res
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rad_hmat_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
