@@ -1,0 +1,162 @@
+"""Benchmark: sun-RHS radiosity solves/s on one MI355X.
+
+Workload (default): spherical-cap crater, depth/diameter 0.2, rim radius
+1 km, ~40,000 facets (seeded jittered grid, lower convex hull); compressed
+view-factor matrix at tol 1e-3 with near-field leaves stored as CSR; 1,024
+sun directions (elevation U[5, 30] deg, azimuth U[0, 360) deg, seed 1);
+E = albedo * Q_dir with albedo 0.3 (insolation with shadows computed on the
+GPU, outside the timed region).  One step = the Jacobi solve of
+(I - 0.3 F-hat) B = E for all 1,024 right-hand sides to a per-column
+relative change of 1e-3.
+
+Prints one JSON line.  See the design doc for the roofline accounting.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(verts, faces, suns, albedo, B_gpu_cols, cols, S):
+    """Time the FP64 CPU reference on a bounded sample: the listed sun columns,
+    full mesh, insolation + matrix-free Jacobi to 1e-10."""
+    from oracle import reference as ref
+    t0 = time.perf_counter()
+    fac = ref.Facets(verts, faces)
+    Q = ref.insolation(fac, suns[cols], S=S)
+    E = albedo * Q
+    B, iters = ref.jacobi(lambda X: ref.matvec_free(fac, X), albedo, E, tol=1e-10)
+    dt = time.perf_counter() - t0
+    errs = [float(np.linalg.norm(B_gpu_cols[:, k] - B[:, k]) / np.linalg.norm(B[:, k]))
+            for k in range(len(cols))]
+    return {"value": len(cols) / dt, "unit": "solves/s", "cores": ref.num_threads(), "kind": "oracle",
+            "sample": f"{len(cols)} sun columns of the full workload (insolation + FP64 matrix-free "
+                      f"Jacobi to 1e-10), {dt:.1f} s"}, max(errs), iters.tolist()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--tol", type=float, default=1e-3)
+    ap.add_argument("--rhs", type=int, default=1024)
+    ap.add_argument("--rtol", type=float, default=1e-3)
+    ap.add_argument("--nearfield", default="csr")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cols", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2209_07632_amd import HMatrix
+    from synth import CAP_LARGE, cap_mesh, sun_directions
+
+    dev = "cuda:0"
+    S, albedo = 1365.0, 0.3
+    verts, faces = cap_mesh(CAP_LARGE)
+    N = faces.shape[0]
+    R = args.rhs
+    suns = sun_directions(R, (5.0, 30.0), seed=1)
+    log(f"mesh N={N}; building F-hat tol={args.tol} {args.dtype} nearfield={args.nearfield}")
+    t0 = time.perf_counter()
+    H = HMatrix(verts, faces, tol=args.tol, storage=args.dtype, nearfield=args.nearfield, max_rhs=R,
+                verbose=True)
+    build_s = time.perf_counter() - t0
+    st = H.stats()
+    log(f"built in {build_s:.2f} s: {st}")
+    t0 = time.perf_counter()
+    Q = H.insolation(suns, flux=S)
+    torch.cuda.synchronize()
+    log(f"insolation {time.perf_counter() - t0:.2f} s")
+    E = (albedo * Q).contiguous() if Q.is_contiguous() else albedo * Q
+    E = (albedo * Q)
+    B = torch.empty_like(E)
+
+    def step():
+        _, info = H.solve(E, rho=albedo, rtol=args.rtol, out=B)
+        return info
+
+    for _ in range(args.warmup):
+        info = step()
+    torch.cuda.synchronize()
+    log(f"warmup done, iters {int(info['total_iters'])}")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    solves_per_s = R * args.steps / dt
+    iters = int(info["total_iters"])
+    log(f"{ms_per_step:.3f} ms/step, {solves_per_s:.1f} solves/s, {iters} iterations")
+
+    # H-matvec timing (tree order, all R columns) with events on the launch stream
+    X = torch.rand((R, N), dtype=E.dtype, device=dev).t()
+    Y = torch.empty_like(X)
+    for _ in range(3):
+        H.matvec(X, out=Y, order="tree")
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nrep = 20
+    ev0.record(stream)
+    for _ in range(nrep):
+        H.matvec(X, out=Y, order="tree")
+    ev1.record(stream)
+    ev1.synchronize()
+    mv_ms = ev0.elapsed_time(ev1) / nrep
+    s_bytes = 8 if args.dtype == "f64" else 4
+    alg_bytes = st["bytes_dense"] + st["bytes_csr"] + st["bytes_lowrank"] + 2 * N * R * s_bytes
+    alg_flops = st["flops_per_rhs"] * R
+    gbs = alg_bytes / (mv_ms * 1e-3) / 1e9
+    tflops = alg_flops / (mv_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.dtype]
+    log(f"matvec {mv_ms:.3f} ms: {gbs:.1f} GB/s, {tflops:.2f} TFLOP/s")
+
+    result = {
+        "metric": "sun-RHS radiosity solves/s + H-matvec HBM GB/s at 1e-3 rel err vs plain FP64",
+        "value": solves_per_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": f"spherical-cap crater N={N}, {R} sun RHS, tol {args.tol}, "
+                               f"near-field {args.nearfield}, Jacobi rtol {args.rtol}, albedo {albedo}",
+                   "N": N, "rhs": R, "tol": args.tol, "nearfield": args.nearfield},
+        "iterations": iters,
+        "build_seconds": build_s,
+        "hmat_bytes": st["bytes_total"],
+        "hmatvec_ms": mv_ms, "hmatvec_gbs": gbs, "hmatvec_tflops": tflops,
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
+                     "frac": tflops / peak, "traffic": None, "kernel": "H-matvec (phase 1 + phase 2)"},
+    }
+    if not args.no_cpu_baseline:
+        cols = list(range(args.cpu_cols))
+        Bc = B.double().cpu().numpy()[:, cols]
+        log("CPU reference on sampled columns ...")
+        cb, err, it = cpu_baseline(verts, faces, suns, albedo, Bc, cols, S)
+        result["cpu_baseline"] = cb
+        result["max_rel_err_vs_fp64"] = err
+        log(f"cpu baseline {cb}; GPU vs FP64 reference max rel err {err:.3e}")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -131,6 +131,21 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                      const void *E, int64_t lde, void *B, int64_t ldb, const rad_solve_opts *opts,
                      rad_solve_info *info, void *hip_stream);
 
+/*
+ * Direct insolation for R point-sun directions (eq. insolation, section 2;
+ * used for the right-hand sides of section 5.1):
+ *   Q[i, k] = flux * max(0, n_i . s_k) * V_sun(i, k),
+ * where V_sun(i, k) = 1 when the ray x_i + t s_k, t > 1e-9, hits no mesh
+ * triangle other than facet i.  suns: host array, R x 3 row-major unit vectors
+ * (direction towards the sun).  flux = S / d^2 in W/m^2 (d in AU).
+ * Q: device, column-major N x R (ldq >= N), compute dtype of H.
+ * Runs asynchronously on hip_stream except for the upload of suns.
+ * Errors: RAD_EINVAL (null, R < 1, non-finite or zero-length direction,
+ * ld < N, dtype mismatch), RAD_ENOMEM, RAD_EDEVICE.
+ */
+rad_status rad_insolation(const rad_hmat *H, int64_t R, const double *suns, double flux, int32_t dtype,
+                          void *Q, int64_t ldq, int32_t order, void *hip_stream);
+
 typedef struct {
     int64_t n;                 /* facets                                              */
     int64_t n_leaves;          /* quadtree leaves                                     */

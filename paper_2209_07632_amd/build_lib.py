@@ -13,7 +13,11 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librad.so")
 
-SOURCES = ["api.cpp", "build.cpp", "build_kernels.hip", "matvec_kernels.hip"]
+SOURCES = ["api.cpp", "build.cpp", "build_kernels.hip", "matvec_kernels.hip", "matmat_kernels.hip", "raycast.hip"]
+
+# geometry, entries and ray tests are evaluated without contraction so that
+# their zero/non-zero and hit/miss decisions equal plain FP64 arithmetic
+NO_CONTRACT = {"build.cpp", "build_kernels.hip", "raycast.hip"}
 
 # packed FP32 instructions are disabled for every HIP translation unit
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I" + INCLUDE, "-I" + CSRC,
@@ -31,6 +35,8 @@ def hipcc() -> str:
 def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
     cmd = [hipcc(), *COMMON, "-fopenmp", "-c", os.path.join(CSRC, src), "-o", obj]
+    if src in NO_CONTRACT:
+        cmd.insert(1, "-ffp-contract=off")
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     subprocess.run(cmd, check=True)

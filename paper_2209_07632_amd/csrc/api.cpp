@@ -17,15 +17,18 @@ static int dsize(int32_t dt) { return dt == RAD_F64 ? 8 : dt == RAD_F32 ? 4 : 2;
 
 static void alloc_workspace(rad_hmat *H) {
     size_t s = (size_t)dsize(H->dtype);
-    size_t nr = (size_t)H->N * (size_t)H->max_rhs;
+    size_t ldr = (size_t)mm_ldr(H->max_rhs);
+    size_t nr = (size_t)H->N * ldr;
     H->w_x.alloc(nr * s);
     H->w_y.alloc(nr * s);
     H->w_b.alloc(nr * s);
     H->w_e.alloc(nr * s);
-    H->w_t.alloc((size_t)std::max(H->t_ld, 4) * (size_t)H->max_rhs * s);
+    H->w_t.alloc((size_t)std::max(H->t_ld, 4) * ldr * s);
     H->w_rho.alloc((size_t)H->N * s);
-    H->w_red.alloc(reduction_doubles(H->max_rhs) * sizeof(double));
+    H->w_red.alloc(std::max(reduction_doubles(H->max_rhs), mm_reduction_doubles(H->max_rhs)) * sizeof(double));
     H->w_norms.alloc((size_t)3 * H->max_rhs);
+    if (H->max_rhs >= kMfmaMinRhs && H->n_parts > 0)
+        H->w_part.alloc((size_t)H->n_parts * mm_part_rows() * ldr * s);
 }
 
 template <class F>
@@ -140,7 +143,13 @@ rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const vo
         RAD_REQUIRE(order == RAD_ORDER_ORIGINAL || order == RAD_ORDER_TREE, "bad order");
         RAD_HIP(hipSetDevice(H->device));
         hipStream_t s = (hipStream_t)hip_stream;
-        if (order == RAD_ORDER_TREE) {
+        if (R >= kMfmaMinRhs) {
+            int64_t ldr = mm_ldr(R);
+            bool perm = order == RAD_ORDER_ORIGINAL;
+            mm_to_rmajor(H, X, ldx, perm, H->w_x.p, ldr, R, s);
+            mm_apply(H, H->w_x.p, H->w_y.p, ldr, R, s);
+            mm_from_rmajor(H, H->w_y.p, ldr, perm, Y, ldy, R, s);
+        } else if (order == RAD_ORDER_TREE) {
             mv_apply(H, X, ldx, Y, ldy, R, s);
         } else {
             mv_gather(H, X, ldx, H->w_x.p, H->N, R, s);
@@ -176,7 +185,18 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         void *FB = H->w_y.p;
         void *Bn = H->w_b.p;
         const void *rho_t = nullptr;
-        if (o.order == RAD_ORDER_TREE) {
+        const bool mm = R >= kMfmaMinRhs;
+        const int64_t ldr = mm ? mm_ldr(R) : N;
+        if (mm) {
+            mm_to_rmajor(H, E, lde, o.order == RAD_ORDER_ORIGINAL, Et, ldr, R, s);
+            if (rho) {
+                if (o.order == RAD_ORDER_TREE)
+                    RAD_HIP(hipMemcpyAsync(H->w_rho.p, rho, N * es, hipMemcpyDeviceToDevice, s));
+                else
+                    mv_gather(H, rho, N, H->w_rho.p, N, 1, s);
+                rho_t = H->w_rho.p;
+            }
+        } else if (o.order == RAD_ORDER_TREE) {
             RAD_HIP(hipMemcpy2DAsync(Et, N * es, E, lde * es, N * es, R, hipMemcpyDeviceToDevice, s));
             if (rho) {
                 RAD_HIP(hipMemcpyAsync(H->w_rho.p, rho, N * es, hipMemcpyDeviceToDevice, s));
@@ -189,10 +209,13 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 rho_t = H->w_rho.p;
             }
         }
-        RAD_HIP(hipMemcpyAsync(Bk, Et, (size_t)N * R * es, hipMemcpyDeviceToDevice, s));
+        RAD_HIP(hipMemcpyAsync(Bk, Et, (size_t)N * (mm ? ldr : R) * es, hipMemcpyDeviceToDevice, s));
         double *enorm_d = H->w_norms.p;
         double *dnorm_d = H->w_norms.p + H->max_rhs;
-        col_norms2(H, Et, N, R, enorm_d, s);
+        if (mm)
+            mm_col_norms2(H, Et, ldr, R, enorm_d, s);
+        else
+            col_norms2(H, Et, N, R, enorm_d, s);
         std::vector<double> enorm(R), dn(R);
         RAD_HIP(hipMemcpyAsync(enorm.data(), enorm_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
         RAD_HIP(hipStreamSynchronize(s));
@@ -206,8 +229,13 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         bool done = false;
         while (k < o.max_iter && !done) {
             ++k;
-            mv_apply(H, Bk, N, FB, N, R, s);
-            solve_update(H, Et, rho_t, rho_scalar, FB, Bk, Bn, N, R, dnorm_d, s);
+            if (mm) {
+                mm_apply(H, Bk, FB, ldr, R, s);
+                mm_solve_update(H, Et, rho_t, rho_scalar, FB, Bk, Bn, ldr, R, dnorm_d, s);
+            } else {
+                mv_apply(H, Bk, N, FB, N, R, s);
+                solve_update(H, Et, rho_t, rho_scalar, FB, Bk, Bn, N, R, dnorm_d, s);
+            }
             std::swap(Bk, Bn);
             if (k % o.check_every == 0 || k == o.max_iter) {
                 RAD_HIP(hipMemcpyAsync(dn.data(), dnorm_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -222,7 +250,9 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 }
             }
         }
-        if (o.order == RAD_ORDER_TREE)
+        if (mm)
+            mm_from_rmajor(H, Bk, ldr, o.order == RAD_ORDER_ORIGINAL, B, ldb, R, s);
+        else if (o.order == RAD_ORDER_TREE)
             RAD_HIP(hipMemcpy2DAsync(B, ldb * es, Bk, N * es, N * es, R, hipMemcpyDeviceToDevice, s));
         else
             mv_scatter(H, Bk, N, B, ldb, R, s);
@@ -238,6 +268,29 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         }
     });
     return st != RAD_OK ? st : conv;
+}
+
+rad_status rad_insolation(const rad_hmat *H, int64_t R, const double *suns, double flux, int32_t dtype, void *Q,
+                          int64_t ldq, int32_t order, void *hip_stream) {
+    return guard([&] {
+        check_hmat(H);
+        RAD_REQUIRE(suns && Q, "null suns or Q");
+        RAD_REQUIRE(R >= 1, "R must be >= 1");
+        RAD_REQUIRE(dtype == H->dtype, "dtype does not match the matrix");
+        RAD_REQUIRE(ldq >= H->N, "leading dimension smaller than N");
+        RAD_REQUIRE(std::isfinite(flux), "flux must be finite");
+        RAD_REQUIRE(order == RAD_ORDER_ORIGINAL || order == RAD_ORDER_TREE, "bad order");
+        for (int64_t r = 0; r < R; ++r) {
+            double n2 = suns[3 * r] * suns[3 * r] + suns[3 * r + 1] * suns[3 * r + 1] + suns[3 * r + 2] * suns[3 * r + 2];
+            RAD_REQUIRE(std::isfinite(n2) && n2 > 0.0, "sun direction must be finite and non-zero");
+        }
+        RAD_HIP(hipSetDevice(H->device));
+        hipStream_t s = (hipStream_t)hip_stream;
+        DevBuf<double> d_s((size_t)3 * R);
+        RAD_HIP(hipMemcpy(d_s.p, suns, sizeof(double) * 3 * R, hipMemcpyHostToDevice));
+        launch_insolation(H, d_s.p, R, flux, H->dtype, Q, ldq, order == RAD_ORDER_ORIGINAL, s);
+        RAD_HIP(hipStreamSynchronize(s));
+    });
 }
 
 }  // extern "C"

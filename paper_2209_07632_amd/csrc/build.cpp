@@ -194,7 +194,6 @@ struct Builder {
     rad_build_opts o;
     int s;  // bytes per stored value
     std::vector<double> xt, nt, at;  // tree-ordered geometry
-    DevBuf<double> d_x, d_n, d_a, d_tri;
     DevBuf<uint32_t> d_vis;
     DevGeom geom{};
     std::vector<BlockPair> bp;
@@ -768,6 +767,29 @@ struct Builder {
         H->d_tasks.upload(tasks);
         H->d_groups.upload(groups);
         H->n_groups = (int32_t)groups.size();
+        // split-K work lists of the multi-RHS projections
+        {
+            const int32_t kSplit = 512;
+            std::vector<P1Work> work;
+            std::vector<P1Red> red;
+            int32_t part = 0;
+            for (int32_t gi = 0; gi < (int32_t)groups.size(); ++gi) {
+                const ProjGroup &g = groups[gi];
+                for (int32_t k0 = 0; k0 < g.ktot; k0 += 64) {
+                    P1Red rd{g.t_off + k0, std::min(64, g.ktot - k0), part, 0};
+                    for (int32_t jb = 0; jb < g.n; jb += kSplit) {
+                        work.push_back(P1Work{gi, k0, jb, std::min(g.n, jb + kSplit), part++, 0});
+                        rd.part_count++;
+                    }
+                    red.push_back(rd);
+                }
+            }
+            H->d_p1work.upload(work);
+            H->d_p1red.upload(red);
+            H->n_p1work = (int32_t)work.size();
+            H->n_p1red = (int32_t)red.size();
+            H->n_parts = part;
+        }
         H->t_rows = t_fill;
         H->t_ld = std::max<int32_t>(round4(t_fill), 4);
         H->max_leaf_rows = max_rows;
@@ -841,27 +863,29 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
         }
         B.at[t] = A[i];
     }
-    B.d_x.upload(B.xt);
-    B.d_n.upload(B.nt);
-    B.d_a.upload(B.at);
+    H->d_x.upload(B.xt);
+    H->d_n.upload(B.nt);
+    H->d_a.upload(B.at);
     H->d_perm.upload(H->perm);
-    B.geom.x = B.d_x.p;
-    B.geom.n = B.d_n.p;
-    B.geom.a = B.d_a.p;
+    B.geom.x = H->d_x.p;
+    B.geom.n = H->d_n.p;
+    B.geom.a = H->d_a.p;
     B.geom.vis = nullptr;
-    if (o.visibility == RAD_VIS_RAYCAST) {
+    {
         std::vector<double> tri(9 * nf);
         for (int64_t t = 0; t < nf; ++t) {
             int32_t f = H->perm[t];
             for (int v = 0; v < 3; ++v)
                 for (int k = 0; k < 3; ++k) tri[9 * t + 3 * v + k] = verts[3 * (int64_t)faces[3 * f + v] + k];
         }
-        B.d_tri.upload(tri);
+        build_grid(H, tri);
+    }
+    if (o.visibility == RAD_VIS_RAYCAST) {
         int64_t wpr = (nf + 31) / 32;
         B.d_vis.alloc((size_t)wpr * nf);
         B.geom.vis = B.d_vis.p;
         B.geom.vis_words_per_row = wpr;
-        launch_visibility_bitmap(B.geom, nf, B.d_tri.p, H->d_perm.p, B.d_vis.p, B.st);
+        launch_vis_grid(H, B.d_vis.p, wpr, B.st);
         RAD_HIP(hipStreamSynchronize(B.st));
     }
 

@@ -305,56 +305,6 @@ __global__ void k_copy_cast(const double *src, int64_t rows, int64_t cols, int64
     }
 }
 
-// Moeller-Trumbore segment test, t in (1e-9, 1-1e-9), inclusive edges.
-__device__ bool seg_hits(const double *o, const double *d, const double *tri) {
-    double e1[3] = {tri[3] - tri[0], tri[4] - tri[1], tri[5] - tri[2]};
-    double e2[3] = {tri[6] - tri[0], tri[7] - tri[1], tri[8] - tri[2]};
-    double pv[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
-    double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
-    if (det == 0.0) return false;
-    double inv = 1.0 / det;
-    double tv[3] = {o[0] - tri[0], o[1] - tri[1], o[2] - tri[2]};
-    double u = (tv[0] * pv[0] + tv[1] * pv[1] + tv[2] * pv[2]) * inv;
-    if (u < 0.0 || u > 1.0) return false;
-    double qv[3] = {tv[1] * e1[2] - tv[2] * e1[1], tv[2] * e1[0] - tv[0] * e1[2], tv[0] * e1[1] - tv[1] * e1[0]};
-    double v = (d[0] * qv[0] + d[1] * qv[1] + d[2] * qv[2]) * inv;
-    if (v < 0.0 || u + v > 1.0) return false;
-    double tt = (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) * inv;
-    return tt > 1e-9 && tt < 1.0 - 1e-9;
-}
-
-// Brute-force ray-cast visibility bitmap: each thread owns one 32-bit word
-// (row i, columns 32w..32w+31).  The segment is always cast from the facet
-// with the smaller original index, so the bitmap is symmetric.
-__global__ void k_vis_bitmap(DevGeom g, int64_t N, const double *tri, const int32_t *perm, uint32_t *bits) {
-    int64_t wpr = g.vis_words_per_row;
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= N * wpr) return;
-    int64_t i = id / wpr, w = id - i * wpr;
-    uint32_t word = 0;
-    for (int b = 0; b < 32; ++b) {
-        int64_t j = w * 32 + b;
-        if (j >= N || j == i) continue;
-        const double *xi = g.x + 3 * i, *xj = g.x + 3 * j;
-        const double *ni = g.n + 3 * i, *nj = g.n + 3 * j;
-        double r0 = __dsub_rn(xj[0], xi[0]), r1 = __dsub_rn(xj[1], xi[1]), r2 = __dsub_rn(xj[2], xi[2]);
-        double ci = dot3_exact(ni[0], ni[1], ni[2], r0, r1, r2);
-        double cj = -dot3_exact(nj[0], nj[1], nj[2], r0, r1, r2);
-        if (!(ci > 0.0) || !(cj > 0.0)) continue;
-        int64_t a = i, c = j;
-        if (perm[j] < perm[i]) { a = j; c = i; }
-        const double *xa = g.x + 3 * a, *xc = g.x + 3 * c;
-        double d[3] = {xc[0] - xa[0], xc[1] - xa[1], xc[2] - xa[2]};
-        bool blocked = false;
-        for (int64_t k = 0; k < N && !blocked; ++k) {
-            if (k == a || k == c) continue;
-            blocked = seg_hits(xa, d, tri + 9 * k);
-        }
-        if (!blocked) word |= 1u << b;
-    }
-    bits[id] = word;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -438,14 +388,6 @@ void launch_copy_cast(const double *src, int64_t rows, int64_t cols, int64_t lds
         hipLaunchKernelGGL(k_copy_cast<double>, dim3(blocks), dim3(256), 0, s, src, rows, cols, lds, (double *)dst, ldd);
     else
         hipLaunchKernelGGL(k_copy_cast<float>, dim3(blocks), dim3(256), 0, s, src, rows, cols, lds, (float *)dst, ldd);
-    RAD_HIP(hipGetLastError());
-}
-
-void launch_visibility_bitmap(const DevGeom &g, int64_t N, const double *tri, const int32_t *perm, uint32_t *bits,
-                              hipStream_t s) {
-    int64_t tot = N * g.vis_words_per_row;
-    if (tot <= 0) return;
-    hipLaunchKernelGGL(k_vis_bitmap, dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, s, g, N, tri, perm, bits);
     RAD_HIP(hipGetLastError());
 }
 

@@ -134,6 +134,18 @@ struct ProjGroup {
     int32_t pad_;
 };
 
+// Phase-1 split-K work item of the multi-RHS path: rows [krow0, krow0+64) of
+// stacked V_J^T times facets [jb, je) of the column node, into partial tile `part`.
+struct P1Work {
+    int32_t group, krow0, jb, je;
+    int32_t part, pad_;
+};
+
+// Sum of the partial tiles of one 64-row slab of T.
+struct P1Red {
+    int32_t t_row0, nrows, part_begin, part_count;
+};
+
 struct LeafInfo {
     int32_t start, size;   // rows (tree order)
     int32_t task_begin, task_end;
@@ -166,9 +178,18 @@ struct rad_hmat {
     std::vector<rad::LeafInfo> h_leaves;
     std::vector<rad::LeafTask> h_tasks;
     std::vector<rad::ProjGroup> h_groups;
+    rad::DevBuf<rad::P1Work> d_p1work;
+    rad::DevBuf<rad::P1Red> d_p1red;
+    int32_t n_p1work = 0, n_p1red = 0, n_parts = 0;
+
+    // geometry and ray-casting grid (tree order, FP64)
+    rad::DevBuf<double> d_x, d_n, d_a, d_tri, d_cell_zmax;
+    rad::DevBuf<int32_t> d_cell_start, d_cell_tris;
+    double grid_x0 = 0, grid_y0 = 0, grid_h = 1, grid_ztop = 0;
+    int32_t grid_gx = 1, grid_gy = 1;
 
     // workspace (sized for max_rhs)
-    rad::DevBuf<unsigned char> w_x, w_y, w_t, w_b, w_e, w_rho, w_red;
+    rad::DevBuf<unsigned char> w_x, w_y, w_t, w_b, w_e, w_rho, w_red, w_part;
     rad::DevBuf<double> w_norms;
 };
 
@@ -210,8 +231,11 @@ void launch_csr_fill(const DevGeom &g, const int32_t *tiles, int64_t ntiles, con
                      int32_t dtype, hipStream_t s);
 void launch_copy_cast(const double *src, int64_t rows, int64_t cols, int64_t lds, void *dst,
                       int64_t ldd, int32_t dtype, hipStream_t s);
-void launch_visibility_bitmap(const DevGeom &g, int64_t N, const double *tri, const int32_t *perm,
-                              uint32_t *bits, hipStream_t s);
+// ray casting (raycast.hip)
+void build_grid(rad_hmat *H, const std::vector<double> &tri);
+void launch_vis_grid(const rad_hmat *H, uint32_t *bits, int64_t wpr, hipStream_t s);
+void launch_insolation(const rad_hmat *H, const double *suns_dev, int64_t R, double flux, int32_t dtype, void *Q,
+                       int64_t ldq, bool original_order, hipStream_t s);
 
 // matvec / solve kernels (matvec_kernels.hip)
 void mv_gather(const rad_hmat *H, const void *src, int64_t lds, void *dst, int64_t ldd, int64_t R, hipStream_t s);
@@ -221,5 +245,19 @@ void col_norms2(const rad_hmat *H, const void *E, int64_t ld, int64_t R, double 
 void solve_update(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *FB,
                   const void *Bold, void *Bnew, int64_t ld, int64_t R, double *norms, hipStream_t s);
 size_t reduction_doubles(int64_t R);
+
+// multi-RHS path (matmat_kernels.hip), R-major tree-ordered buffers
+constexpr int64_t kMfmaMinRhs = 16;
+int64_t mm_ldr(int64_t R);
+int mm_part_rows();
+size_t mm_reduction_doubles(int64_t R);
+void mm_to_rmajor(const rad_hmat *H, const void *src, int64_t lds, bool permute, void *dst, int64_t ldr, int64_t R,
+                  hipStream_t s);
+void mm_from_rmajor(const rad_hmat *H, const void *src, int64_t ldr, bool permute, void *dst, int64_t ldd, int64_t R,
+                    hipStream_t s);
+void mm_apply(const rad_hmat *H, const void *X, void *Y, int64_t ldr, int64_t R, hipStream_t s);
+void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, double *out, hipStream_t s);
+void mm_solve_update(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *FB,
+                     const void *Bold, void *Bnew, int64_t ldr, int64_t R, double *norms, hipStream_t s);
 
 }  // namespace rad

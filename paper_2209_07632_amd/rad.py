@@ -59,7 +59,8 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_matvec", "rad_solve_opts_default", "rad_solve",
-           "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free", "rad_last_error"]
+           "rad_insolation", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free",
+           "rad_last_error"]
 
 _lib = None
 
@@ -86,6 +87,9 @@ def load(path: str = LIB_PATH):
     L.rad_solve.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int64, vp,
                             ctypes.c_int64, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     L.rad_solve.restype = ctypes.c_int
+    L.rad_insolation.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_double, ctypes.c_int32, vp, ctypes.c_int64,
+                                 ctypes.c_int32, vp]
+    L.rad_insolation.restype = ctypes.c_int
     L.rad_hmat_info.argtypes = [vp, ctypes.POINTER(Stats)]
     L.rad_hmat_info.restype = ctypes.c_int
     L.rad_hmat_n.argtypes = [vp]
@@ -227,6 +231,20 @@ class HMatrix:
         res = {"iters": iters, "rel_change": rel, "total_iters": int(info.total_iters),
                "converged": st == RAD_OK}
         return (out.reshape(-1) if squeeze else out), res
+
+    def insolation(self, suns, flux=1365.0, order="original", out=None):
+        """Q_dir (N, R) on the device for sun unit vectors suns (R, 3)."""
+        torch = _torch()
+        s = np.ascontiguousarray(np.atleast_2d(suns), dtype=np.float64)
+        R = s.shape[0]
+        if out is None:
+            out = torch.empty((R, self.N), dtype=self.torch_dtype, device=f"cuda:{self.device}").t()
+        Qc, ldq = _colmajor(out, self.N)
+        _check(load().rad_insolation(self._h, R, s.ctypes.data, float(flux), self.rad_dtype,
+                                     ctypes.c_void_p(Qc.data_ptr()), ldq, ORDER[order], _stream_handle()))
+        if Qc.data_ptr() != out.data_ptr():
+            out.copy_(Qc)
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

@@ -131,3 +131,118 @@ def test_single_leaf_and_deep_leaves():
     H = _hm(verts, faces, tol=1e-8, max_depth=1)  # leaves far above 64 rows
     X = np.random.default_rng(7).random(fac.N)
     assert _rel(H.matvec(torch.from_numpy(X).to(DEV)).cpu().numpy(), F @ X) < 1e-7
+
+
+def test_insolation_matches_reference(cap):
+    verts, faces, fac, F = cap
+    suns = sun_directions(16, seed=2)
+    Q0 = ref.insolation(fac, suns)
+    H = _hm(verts, faces, tol=1e-3)
+    Q = H.insolation(suns, flux=1365.0).cpu().numpy()
+    assert np.array_equal(Q > 0, Q0 > 0)          # shadow decisions are bit-exact
+    np.testing.assert_allclose(Q, Q0, rtol=1e-13, atol=1e-10)
+    Qt = H.insolation(suns, flux=1365.0, order="tree").cpu().numpy()
+    np.testing.assert_array_equal(Qt, Q[H.perm()])
+
+
+def test_insolation_terrain_low_sun():
+    from synth import DemSpec, dem_mesh, sun_grid_azimuth
+    verts, faces = dem_mesh(DemSpec(n=24, seed=3))
+    fac = ref.Facets(verts, faces)
+    suns = sun_grid_azimuth(1.5, 24, 15.0)
+    Q0 = ref.insolation(fac, suns)
+    H = _hm(verts, faces, tol=1e-3)
+    Q = H.insolation(suns).cpu().numpy()
+    assert 0.05 < (Q0 == 0).mean() < 0.95
+    assert np.array_equal(Q > 0, Q0 > 0)
+    np.testing.assert_allclose(Q, Q0, rtol=1e-13, atol=1e-10)
+
+
+@pytest.mark.parametrize("n", [12, 16])
+def test_raycast_visibility_terrain(n):
+    """V_ij by ray casting (section 3.2) on occluding terrain: with a tight
+    tolerance the GPU product equals the reference F built with brute force."""
+    from synth import DemSpec, dem_mesh
+    verts, faces = dem_mesh(DemSpec(n=n, seed=3))
+    fac = ref.Facets(verts, faces)
+    vis = ref.pair_visibility(fac, "raycast")
+    F = ref.view_factor_matrix(fac, vis)
+    assert (vis != ref.pair_visibility(fac, "backface")).sum() > 1000
+    H = _hm(verts, faces, tol=1e-12, visibility="raycast", leaf_size=16)
+    X = np.random.default_rng(8).random(fac.N)
+    Y = H.matvec(torch.from_numpy(X).to(DEV)).cpu().numpy()
+    assert _rel(Y, F @ X) < 1e-10
+
+
+# ------------------------------------------------------------ multi-RHS (MFMA) path
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("R", [16, 37, 130])
+def test_matmat_mfma(cap, storage, R):
+    verts, faces, fac, F = cap
+    H = _hm(verts, faces, tol=1e-4, storage=storage, max_rhs=R)
+    X = np.random.default_rng(10 + R).random((fac.N, R))
+    dt = torch.float64 if storage == "f64" else torch.float32
+    Y = H.matvec(torch.from_numpy(X).to(DEV, dt)).double().cpu().numpy()
+    assert _rel(Y, F @ X) <= 1e-4 + 1e-6
+    cols = [0, R // 2, R - 1]
+    for c in cols:                                   # every column is right, not only the norm
+        assert _rel(Y[:, c], F @ X[:, c]) <= 1e-4 + 1e-6
+
+
+@pytest.mark.parametrize("nearfield", ["dense", "csr"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_matmat_nearfield(cap, nearfield, storage):
+    verts, faces, fac, F = cap
+    H = _hm(verts, faces, tol=1e-6, storage=storage, nearfield=nearfield, max_rhs=40)
+    st = H.stats()
+    assert (st["n_csr"] if nearfield == "csr" else st["n_dense"]) > 0
+    X = np.random.default_rng(11).random((fac.N, 40))
+    dt = torch.float64 if storage == "f64" else torch.float32
+    Y = H.matvec(torch.from_numpy(X).to(DEV, dt)).double().cpu().numpy()
+    assert _rel(Y, F @ X) <= 1e-6 + 1e-6
+
+
+def test_matmat_big_leaves_and_terrain():
+    verts, faces = cap_mesh(CapSpec(h=100.0, seed=9))
+    fac = ref.Facets(verts, faces)
+    F = ref.view_factor_matrix(fac)
+    H = _hm(verts, faces, tol=1e-8, max_depth=1, max_rhs=20)
+    X = np.random.default_rng(12).random((fac.N, 20))
+    assert _rel(H.matvec(torch.from_numpy(X).to(DEV)).cpu().numpy(), F @ X) < 1e-7
+    from synth import DemSpec, dem_mesh
+    verts, faces = dem_mesh(DemSpec(n=16, seed=3))
+    fac = ref.Facets(verts, faces)
+    F = ref.view_factor_matrix(fac, ref.pair_visibility(fac, "raycast"))
+    for nf in ("auto", "csr"):
+        H = _hm(verts, faces, tol=1e-12, visibility="raycast", leaf_size=16, nearfield=nf, max_rhs=24)
+        X = np.random.default_rng(13).random((fac.N, 24))
+        assert _rel(H.matvec(torch.from_numpy(X).to(DEV)).cpu().numpy(), F @ X) < 1e-10
+
+
+def test_matmat_agrees_with_single_rhs(cap):
+    verts, faces, fac, F = cap
+    H = _hm(verts, faces, tol=1e-3, storage="f64", max_rhs=16)
+    X = np.random.default_rng(14).random((fac.N, 16))
+    Xd = torch.from_numpy(X).to(DEV)
+    Ym = H.matvec(Xd).cpu().numpy()
+    Y1 = np.stack([H.matvec(Xd[:, c].contiguous()).cpu().numpy() for c in range(16)], axis=1)
+    np.testing.assert_allclose(Ym, Y1, rtol=1e-12, atol=1e-15 * np.abs(Y1).max())
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_solve_many_rhs(cap, storage):
+    verts, faces, fac, F = cap
+    suns = sun_directions(64, seed=3)
+    E = 0.3 * ref.insolation(fac, suns)
+    B0 = ref.solve_direct(F, 0.3, E)
+    H = _hm(verts, faces, tol=1e-3, storage=storage, max_rhs=64)
+    dt = torch.float64 if storage == "f64" else torch.float32
+    B, info = H.solve(torch.from_numpy(E).to(DEV, dt), rho=0.3, rtol=1e-3)
+    Bn = B.double().cpu().numpy()
+    errs = [_rel(Bn[:, c], B0[:, c]) for c in range(64)]
+    assert max(errs) <= 1e-3
+    assert info["converged"] and info["total_iters"] <= 5
+    # IR band (rho = 1) on the same matrix
+    B, info = H.solve(torch.from_numpy(E).to(DEV, dt), rho=1.0, rtol=1e-6, max_iter=200)
+    B1 = ref.solve_direct(F, 1.0, E)
+    assert _rel(B.double().cpu().numpy(), B1) <= 1e-3
