@@ -25,7 +25,7 @@ static void alloc_workspace(rad_hmat *H) {
     H->w_e.alloc(nr * s);
     H->w_t.alloc((size_t)std::max(H->t_ld, 4) * ldr * s);
     H->w_rho.alloc((size_t)H->N * s);
-    H->w_red.alloc(std::max(reduction_doubles(H->max_rhs), mm_reduction_doubles(H->max_rhs)) * sizeof(double));
+    H->w_red.alloc(std::max(reduction_doubles(H->max_rhs), mm_reduction_doubles_for(H, H->max_rhs)) * sizeof(double));
     H->w_norms.alloc((size_t)3 * H->max_rhs);
     if (H->max_rhs >= kMfmaMinRhs && H->n_parts > 0)
         H->w_part.alloc((size_t)H->n_parts * mm_part_rows() * ldr * s);
@@ -230,8 +230,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         while (k < o.max_iter && !done) {
             ++k;
             if (mm) {
-                mm_apply(H, Bk, FB, ldr, R, s);
-                mm_solve_update(H, Et, rho_t, rho_scalar, FB, Bk, Bn, ldr, R, dnorm_d, s);
+                mm_jacobi_step(H, Et, rho_t, rho_scalar, Bk, Bn, ldr, R, dnorm_d, s);
             } else {
                 mv_apply(H, Bk, N, FB, N, R, s);
                 solve_update(H, Et, rho_t, rho_scalar, FB, Bk, Bn, N, R, dnorm_d, s);

@@ -544,6 +544,7 @@ struct Builder {
     // device layout
     // ---------------------------------------------------------------------
     void layout() {
+        // final (non-hierarchical, non-zero) blocks of the chosen partition
         std::vector<int64_t> finals;
         std::vector<int64_t> stack;
         for (size_t p = 0; p < bp.size() && bp[p].level == 0; ++p) stack.push_back((int64_t)p);
@@ -564,31 +565,22 @@ struct Builder {
         for (const TreeNode &t : H->nodes)
             if (t.nchild == 0) leaves[t.leaf_index] = &t;
 
-        // per leaf task lists
-        std::vector<std::vector<LeafTask>> lt(H->n_leaves);
-        int64_t vfill = 0;  // value pool fill (elements)
-        std::vector<int32_t> dense_tiles;  // i0,m,j0,n,ld,pad
-        std::vector<int64_t> dense_offs;
-        std::vector<int32_t> csr_tiles;
-        std::vector<int64_t> csr_row_offs;  // where each slice's rowptr starts in the ptr pool
-        int64_t ptr_fill = 0;
-        std::vector<std::pair<int32_t, int32_t>> csr_task_pos;
         struct Copy {
-            int64_t src_off;  // in candidate pool (doubles)
+            int64_t src_off;  // candidate pool (doubles)
             int32_t level;
-            int32_t rows, cols;
-            int32_t lds;
+            int32_t rows, cols, lds;
             int64_t dst_off;
             int32_t ldd;
         };
         std::vector<Copy> copies;
+        int64_t vfill = 0;
 
-        // low-rank blocks grouped by column node
+        // phase 1 groups: V factors of the low-rank blocks, stacked per column node
         std::vector<std::vector<int64_t>> by_col(H->nodes.size());
         for (int64_t p : finals)
             if (bp[p].kind == BK_LOWRANK) by_col[bp[p].J].push_back(p);
         std::vector<ProjGroup> groups;
-        std::vector<std::pair<int64_t, int32_t>> t_rows;  // (p, T row offset)
+        std::vector<std::pair<int64_t, int32_t>> t_rows;  // (block, first row in T)
         int32_t t_fill = 0;
         for (size_t J = 0; J < by_col.size(); ++J) {
             if (by_col[J].empty()) continue;
@@ -616,73 +608,61 @@ struct Builder {
             groups.push_back(g);
             H->stats.n_lowrank += (int64_t)by_col[J].size();
         }
-        std::vector<std::pair<int64_t, int32_t>> sorted_t(t_rows);
-        std::sort(sorted_t.begin(), sorted_t.end());
+        std::sort(t_rows.begin(), t_rows.end());
         auto t_find = [&](int64_t p) {
-            auto it = std::lower_bound(sorted_t.begin(), sorted_t.end(), std::make_pair(p, INT32_MIN));
+            auto it = std::lower_bound(t_rows.begin(), t_rows.end(), std::make_pair(p, INT32_MIN));
             return it->second;
         };
 
+        // block storage: dense and U' column-major with ld = rows of the block;
+        // CSR per block (row pointers relative to the block's first value)
+        struct Placed {
+            int64_t p;
+            int64_t a_off;    // dense/U' values, or CSR value base (set after counting)
+            int64_t ptr_off;  // CSR row pointers
+        };
+        std::vector<Placed> placed;
+        std::vector<int32_t> dense_tiles, csr_tiles;
+        std::vector<int64_t> dense_offs, csr_row_offs;
+        int64_t ptr_fill = 0;
         for (int64_t p : finals) {
             const BlockPair &b = bp[p];
             const TreeNode &rn = H->nodes[b.I], &cn = H->nodes[b.J];
-            for (int32_t lf = rn.leaf_first; lf < rn.leaf_first + rn.leaf_count; ++lf) {
-                const TreeNode &L = *leaves[lf];
-                int32_t r0 = L.start - rn.start;
-                int32_t ldL = round4(L.size);
-                LeafTask t{};
-                if (b.kind == BK_DENSE) {
-                    t.type = TASK_DENSE;
-                    t.ncol = cn.size;
-                    t.ld = ldL;
-                    t.col0 = cn.start;
-                    t.a_off = vfill;
-                    dense_tiles.insert(dense_tiles.end(), {L.start, L.size, cn.start, cn.size, ldL, 0});
-                    dense_offs.push_back(vfill);
-                    vfill += (int64_t)ldL * cn.size;
-                } else if (b.kind == BK_CSR) {
-                    t.type = TASK_CSR;
-                    t.ncol = cn.size;
-                    t.ld = L.size;
-                    t.col0 = cn.start;
-                    t.aux_off = ptr_fill;
-                    csr_tiles.insert(csr_tiles.end(), {L.start, L.size, cn.start, cn.size, 0, 0});
-                    csr_row_offs.push_back(ptr_fill);
-                    ptr_fill += L.size + 1;
-                    csr_task_pos.push_back({lf, (int32_t)lt[lf].size()});
-                } else {  // low rank: slice of U'
-                    t.type = TASK_LOWRANK;
-                    t.ncol = b.rank;
-                    t.ld = ldL;
-                    t.col0 = t_find(p);
-                    t.a_off = vfill;
-                    copies.push_back(Copy{b.cand_off + r0, b.cand_level, L.size, b.rank, rn.size, vfill, ldL});
-                    vfill += (int64_t)ldL * b.rank;
-                }
-                lt[lf].push_back(t);
-            }
+            Placed pl{p, 0, 0};
             if (b.kind == BK_DENSE) {
+                pl.a_off = vfill;
+                dense_tiles.insert(dense_tiles.end(), {rn.start, rn.size, cn.start, cn.size, rn.size, 0});
+                dense_offs.push_back(vfill);
+                vfill += (int64_t)rn.size * cn.size;
                 H->stats.n_dense++;
                 H->stats.bytes_dense += dense_bytes(rn.size, cn.size);
                 H->stats.nnz_near += (int64_t)rn.size * cn.size;
             } else if (b.kind == BK_CSR) {
+                pl.ptr_off = ptr_fill;
+                csr_tiles.insert(csr_tiles.end(), {rn.start, rn.size, cn.start, cn.size, 0, 0});
+                csr_row_offs.push_back(ptr_fill);
+                ptr_fill += rn.size + 1;
                 H->stats.n_csr++;
                 H->stats.bytes_csr += csr_bytes(rn.size, b.nnz);
                 H->stats.nnz_near += b.nnz;
             } else {
+                pl.a_off = vfill;
+                copies.push_back(Copy{b.cand_off, b.cand_level, rn.size, b.rank, rn.size, vfill, rn.size});
+                vfill += (int64_t)rn.size * b.rank;
                 H->stats.bytes_lowrank += svd_bytes(rn.size, cn.size, b.rank);
                 H->stats.sum_rank += b.rank;
                 H->stats.lowrank_elems += (int64_t)(rn.size + cn.size) * b.rank;
                 H->stats.max_rank = std::max(H->stats.max_rank, b.rank);
             }
+            placed.push_back(pl);
         }
 
-        // CSR: count, scan, fill
+        // CSR: count per row on the GPU, scan on the host
         int64_t ntile_csr = (int64_t)csr_tiles.size() / 6;
         std::vector<int32_t> h_ptr;
         int64_t csr_nnz_total = 0;
         std::vector<int64_t> csr_val_base(ntile_csr);
-        DevBuf<int32_t> d_ctiles, d_ptr;
+        DevBuf<int32_t> d_ctiles;
         DevBuf<int64_t> d_crow;
         if (ntile_csr > 0) {
             d_ctiles.upload(csr_tiles);
@@ -706,15 +686,55 @@ struct Builder {
                 csr_nnz_total += acc;
             }
         }
-        // CSR values go after the dense/low-rank values in the pool
-        int64_t csr_val_start = vfill;
+        const int64_t csr_val_start = vfill;
         vfill += csr_nnz_total;
-        for (int64_t t = 0; t < ntile_csr; ++t) {
-            auto pos = csr_task_pos[t];
-            lt[pos.first][pos.second].a_off = csr_val_start + csr_val_base[t];
+        {
+            int64_t ci = 0;
+            for (Placed &pl : placed)
+                if (bp[pl.p].kind == BK_CSR) pl.a_off = csr_val_start + csr_val_base[ci++];
         }
 
-        // flatten tasks: dense, CSR, low-rank per leaf
+        // task lists: per leaf (single-RHS kernels) and per 64-row tile (MFMA kernels)
+        std::vector<std::vector<LeafTask>> lt(H->n_leaves);
+        const int32_t n_tiles = (int32_t)((H->N + 63) / 64);
+        std::vector<std::vector<TileTask>> tt(n_tiles);
+        for (const Placed &pl : placed) {
+            const BlockPair &b = bp[pl.p];
+            const TreeNode &rn = H->nodes[b.I], &cn = H->nodes[b.J];
+            int32_t type = b.kind == BK_DENSE ? TASK_DENSE : b.kind == BK_CSR ? TASK_CSR : TASK_LOWRANK;
+            int32_t ncol = b.kind == BK_LOWRANK ? b.rank : cn.size;
+            int32_t col0 = b.kind == BK_LOWRANK ? t_find(pl.p) : cn.start;
+            for (int32_t lf = rn.leaf_first; lf < rn.leaf_first + rn.leaf_count; ++lf) {
+                const TreeNode &L = *leaves[lf];
+                int32_t r0 = L.start - rn.start;
+                LeafTask t{};
+                t.type = type;
+                t.ncol = ncol;
+                t.ld = rn.size;
+                t.col0 = col0;
+                if (type == TASK_CSR) {
+                    t.a_off = pl.a_off;
+                    t.aux_off = pl.ptr_off + r0;
+                } else {
+                    t.a_off = pl.a_off + r0;
+                }
+                lt[lf].push_back(t);
+            }
+            for (int32_t tile = rn.start / 64; tile * 64 < rn.start + rn.size; ++tile) {
+                int32_t tile0 = tile * 64;
+                TileTask t{};
+                t.type = type;
+                t.ncol = ncol;
+                t.ld = rn.size;
+                t.col0 = col0;
+                t.a_off = pl.a_off;
+                t.aux_off = pl.ptr_off;
+                t.row_off = tile0 - rn.start;
+                t.r_lo = std::max(0, rn.start - tile0);
+                t.r_hi = std::min(64, rn.start + rn.size - tile0);
+                tt[tile].push_back(t);
+            }
+        }
         std::vector<LeafInfo> linfo(H->n_leaves);
         std::vector<LeafTask> tasks;
         int32_t max_rows = 0;
@@ -728,6 +748,15 @@ struct Builder {
             linfo[lf].task_end = (int32_t)tasks.size();
             max_rows = std::max(max_rows, leaves[lf]->size);
         }
+        std::vector<int32_t> tile_ptr(n_tiles + 1, 0);
+        std::vector<TileTask> ttasks;
+        for (int32_t tl = 0; tl < n_tiles; ++tl) {
+            auto &v = tt[tl];
+            std::stable_sort(v.begin(), v.end(), [](const TileTask &a, const TileTask &b) { return a.type < b.type; });
+            tile_ptr[tl] = (int32_t)ttasks.size();
+            ttasks.insert(ttasks.end(), v.begin(), v.end());
+        }
+        tile_ptr[n_tiles] = (int32_t)ttasks.size();
 
         // allocate the value pool and fill it
         H->d_vals.alloc((size_t)std::max<int64_t>(vfill, 1) * s);
@@ -745,12 +774,13 @@ struct Builder {
             H->d_csr_ptr.upload(h_ptr);
             H->d_csr_idx.alloc((size_t)std::max<int64_t>(csr_nnz_total, 1));
             std::vector<int64_t> vb(ntile_csr);
-            for (int64_t t = 0; t < ntile_csr; ++t) vb[t] = csr_val_start + csr_val_base[t];
+            for (int64_t t = 0; t < ntile_csr; ++t) vb[t] = csr_val_base[t];
             DevBuf<int64_t> d_vb;
             d_vb.upload(vb);
-            // column indices are stored at (value index - csr_val_start)
-            launch_csr_fill(geom, d_ctiles.p, ntile_csr, H->d_csr_ptr.p, d_crow.p, d_vb.p, H->d_vals.p,
-                            H->d_csr_idx.p - csr_val_start, H->dtype, st);
+            // values at csr_val_start + base; column indices at base
+            char *vals_csr = (char *)H->d_vals.p + (size_t)csr_val_start * s;
+            launch_csr_fill(geom, d_ctiles.p, ntile_csr, H->d_csr_ptr.p, d_crow.p, d_vb.p, vals_csr,
+                            H->d_csr_idx.p, H->dtype, st);
             RAD_HIP(hipStreamSynchronize(st));
         }
         for (const Copy &c : copies) {
@@ -766,6 +796,9 @@ struct Builder {
         H->d_leaves.upload(linfo);
         H->d_tasks.upload(tasks);
         H->d_groups.upload(groups);
+        H->d_tile_ptr.upload(tile_ptr);
+        H->d_tile_tasks.upload(ttasks);
+        H->n_tiles = n_tiles;
         H->n_groups = (int32_t)groups.size();
         // split-K work lists of the multi-RHS projections
         {
@@ -797,7 +830,7 @@ struct Builder {
         H->stats.bytes_total = (int64_t)H->d_vals.bytes() + (int64_t)H->d_csr_idx.bytes() +
                                (int64_t)H->d_csr_ptr.bytes() + (int64_t)H->d_tasks.bytes() +
                                (int64_t)H->d_leaves.bytes() + (int64_t)H->d_groups.bytes() +
-                               (int64_t)H->d_perm.bytes();
+                               (int64_t)H->d_tile_tasks.bytes() + (int64_t)H->d_perm.bytes();
         H->stats.flops_per_rhs = 2.0 * ((double)H->stats.lowrank_elems + (double)H->stats.nnz_near);
     }
 };

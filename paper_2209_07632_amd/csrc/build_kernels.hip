@@ -161,8 +161,11 @@ __global__ void __launch_bounds__(256) k_sketch_apply(DevGeom g, const SketchBlo
 
 // ---------------------------------------------------------------------------
 // Classical Gram-Schmidt, applied twice per column (CGS2), FP64, one
-// workgroup per block.  Columns whose norm collapses below 1e-13 of their
-// starting norm are set to zero (dependent).  Optionally records R.
+// workgroup per block.  The projections d = Q[:, :c]^T v are formed 32
+// columns at a time with per-thread partial sums over the thread's rows;
+// the update v -= Q d runs with one thread per row.  Columns whose norm
+// collapses below 1e-13 of their starting norm are set to zero (dependent).
+// Optionally records R.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_cgs2(double *base, const SketchBlock *blocks, int use_z, double *Rout,
                                                const int64_t *roff) {
@@ -171,7 +174,8 @@ __global__ void __launch_bounds__(256) k_cgs2(double *base, const SketchBlock *b
     const int ell = b.ell;
     double *Q = base + (use_z ? b.z_off : b.y_off);
     double *R = Rout ? Rout + roff[blockIdx.x] : nullptr;
-    __shared__ double sd[512];
+    __shared__ double sd[4][64];
+    __shared__ double sdot[64];
     __shared__ double sred[4];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 
@@ -181,34 +185,41 @@ __global__ void __launch_bounds__(256) k_cgs2(double *base, const SketchBlock *b
     }
     for (int c = 0; c < ell; ++c) {
         double *v = Q + (int64_t)c * rows;
-        // starting norm
         double s = 0.0;
         for (int r = t; r < rows; r += 256) s += v[r] * v[r];
         s = wave_sum(s);
         if (lane == 0) sred[w] = s;
         __syncthreads();
-        double norm0 = sqrt(sred[0] + sred[1] + sred[2] + sred[3]);
+        const double norm0 = sqrt(sred[0] + sred[1] + sred[2] + sred[3]);
         __syncthreads();
         for (int pass = 0; pass < 2 && c > 0; ++pass) {
-            for (int j0 = 0; j0 < c; j0 += 512) {
-                int jn = min(512, c - j0);
-                for (int e = t; e < jn; e += 256) sd[e] = 0.0;
-                __syncthreads();
-                for (int jj = 0; jj < jn; ++jj) {
-                    const double *qj = Q + (int64_t)(j0 + jj) * rows;
-                    double p = 0.0;
-                    for (int r = t; r < rows; r += 256) p += qj[r] * v[r];
-                    p = wave_sum(p);
-                    if (lane == 0) atomicAdd(&sd[jj], p);
+            for (int j0 = 0; j0 < c; j0 += 32) {
+                const int jn = min(32, c - j0);
+                // d_j = Q[:, j0+j]^T v: every thread keeps 32 partial sums over
+                // its rows (coalesced loads), then the block reduces them.
+                double pj[32];
+#pragma unroll
+                for (int jj = 0; jj < 32; ++jj) pj[jj] = 0.0;
+                for (int r = t; r < rows; r += 256) {
+                    const double vr = v[r];
+#pragma unroll
+                    for (int jj = 0; jj < 32; ++jj)
+                        if (jj < jn) pj[jj] += Q[(int64_t)(j0 + jj) * rows + r] * vr;
                 }
+#pragma unroll
+                for (int jj = 0; jj < 32; ++jj) {
+                    double q = wave_sum(pj[jj]);
+                    if (lane == 0) sd[w][jj] = q;
+                }
+                __syncthreads();
+                if (t < 32) sdot[t] = (t < jn) ? sd[0][t] + sd[1][t] + sd[2][t] + sd[3][t] : 0.0;
                 __syncthreads();
                 for (int r = t; r < rows; r += 256) {
                     double acc = v[r];
-                    for (int jj = 0; jj < jn; ++jj) acc -= Q[(int64_t)(j0 + jj) * rows + r] * sd[jj];
+                    for (int jj = 0; jj < jn; ++jj) acc -= Q[(int64_t)(j0 + jj) * rows + r] * sdot[jj];
                     v[r] = acc;
                 }
-                if (R)
-                    for (int e = t; e < jn; e += 256) R[(j0 + e) + (int64_t)c * ell] += sd[e];
+                if (R && t < jn) R[(j0 + t) + (int64_t)c * ell] += sdot[t];
                 __syncthreads();
             }
         }
@@ -217,10 +228,10 @@ __global__ void __launch_bounds__(256) k_cgs2(double *base, const SketchBlock *b
         s = wave_sum(s);
         if (lane == 0) sred[w] = s;
         __syncthreads();
-        double nrm = sqrt(sred[0] + sred[1] + sred[2] + sred[3]);
+        const double nrm = sqrt(sred[0] + sred[1] + sred[2] + sred[3]);
         __syncthreads();
-        bool dep = !(nrm > 1e-13 * norm0) || !(nrm > 0.0);
-        double inv = dep ? 0.0 : 1.0 / nrm;
+        const bool dep = !(nrm > 1e-13 * norm0) || !(nrm > 0.0);
+        const double inv = dep ? 0.0 : 1.0 / nrm;
         for (int r = t; r < rows; r += 256) v[r] = dep ? 0.0 : v[r] * inv;
         if (R && t == 0) R[c + (int64_t)c * ell] = dep ? 0.0 : nrm;
         __syncthreads();

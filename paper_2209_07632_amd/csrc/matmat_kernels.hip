@@ -80,15 +80,35 @@ struct Tile {
     }
 };
 
-// B chunk: rows [brow, brow + kcount) of an R-major matrix, columns [r0, r0+TN)
+// B chunk: rows [brow, brow + kcount) of an R-major matrix, columns [r0, r0+TN).
+// ldr and r0 are multiples of 4, so groups of four columns are loaded as one
+// 16-byte (FP32) or two 16-byte (FP64) vectors.
 template <class T>
 __device__ __forceinline__ void load_b_rmajor(T (*sB)[TN + PADB], const T *src, int64_t brow, int kcount,
                                               int64_t ldr, int r0, int R, int t) {
-    for (int e = t; e < KC * TN; e += 256) {
-        int k = e / TN, c = e - k * TN;
-        T v = 0;
-        if (k < kcount && r0 + c < R) v = src[(brow + k) * ldr + r0 + c];
-        sB[k][c] = v;
+    for (int e = t; e < KC * TN / 4; e += 256) {
+        int k = e / (TN / 4), c = (e - k * (TN / 4)) * 4;
+        T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+        if (k < kcount) {
+            const T *p = src + (brow + k) * ldr + r0 + c;
+            if (r0 + c + 3 < R) {
+                if constexpr (sizeof(T) == 4) {
+                    float4 q = *(const float4 *)p;
+                    v0 = q.x; v1 = q.y; v2 = q.z; v3 = q.w;
+                } else {
+                    double2 q0 = *(const double2 *)p, q1 = *(const double2 *)(p + 2);
+                    v0 = q0.x; v1 = q0.y; v2 = q1.x; v3 = q1.y;
+                }
+            } else {
+                if (r0 + c < R) v0 = p[0];
+                if (r0 + c + 1 < R) v1 = p[1];
+                if (r0 + c + 2 < R) v2 = p[2];
+            }
+        }
+        sB[k][c] = v0;
+        sB[k][c + 1] = v1;
+        sB[k][c + 2] = v2;
+        sB[k][c + 3] = v3;
     }
 }
 
@@ -104,6 +124,80 @@ __device__ __forceinline__ void load_a_colmajor(T (*sA)[TM + PADA], const T *src
     }
 }
 
+// One reduction chunk of a GEMM, staged through registers so that the global
+// loads of chunk c+1 are in flight while chunk c runs on the matrix cores.
+// A[r][k]: kind 0 = column-major block rows (row_off + r, r in [r_lo, r_hi)),
+//          kind 1 = transposed V (A[r][k] = V[k + r * ld], r < r_hi).
+template <class T>
+struct Stage {
+    T a[KC * TM / 256];
+    T b[KC * TN / 256];
+    __device__ __forceinline__ void fetch(int kind, const T *A, int64_t ld, int row_off, int r_lo, int r_hi, int kb,
+                                          int kcount, const T *B, int64_t brow, int64_t ldr, int r0, int R, int t) {
+#pragma unroll
+        for (int q = 0; q < KC * TM / 256; ++q) {
+            int e = t + q * 256;
+            T v = 0;
+            if (kind == 0) {
+                int k = e / TM, r = e - k * TM;
+                if (k < kcount && r >= r_lo && r < r_hi) v = A[(int64_t)(row_off + r) + (int64_t)(kb + k) * ld];
+            } else {
+                int r = e / KC, k = e - r * KC;
+                if (k < kcount && r < r_hi) v = A[(int64_t)(kb + k) + (int64_t)r * ld];
+            }
+            a[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < KC * TN / 1024; ++q) {
+            int e = t + q * 256;
+            int k = e / (TN / 4), c = (e - k * (TN / 4)) * 4;
+            T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+            if (k < kcount) {
+                const T *p = B + (brow + k) * ldr + r0 + c;
+                if (r0 + c + 3 < R) {
+                    if constexpr (sizeof(T) == 4) {
+                        float4 qv = *(const float4 *)p;
+                        v0 = qv.x; v1 = qv.y; v2 = qv.z; v3 = qv.w;
+                    } else {
+                        double2 q0 = *(const double2 *)p, q1 = *(const double2 *)(p + 2);
+                        v0 = q0.x; v1 = q0.y; v2 = q1.x; v3 = q1.y;
+                    }
+                } else {
+                    if (r0 + c < R) v0 = p[0];
+                    if (r0 + c + 1 < R) v1 = p[1];
+                    if (r0 + c + 2 < R) v2 = p[2];
+                }
+            }
+            b[4 * q] = v0;
+            b[4 * q + 1] = v1;
+            b[4 * q + 2] = v2;
+            b[4 * q + 3] = v3;
+        }
+    }
+    __device__ __forceinline__ void commit(int kind, T (*sA)[TM + PADA], T (*sB)[TN + PADB], int t) {
+#pragma unroll
+        for (int q = 0; q < KC * TM / 256; ++q) {
+            int e = t + q * 256;
+            if (kind == 0) {
+                int k = e / TM, r = e - k * TM;
+                sA[k][r] = a[q];
+            } else {
+                int r = e / KC, k = e - r * KC;
+                sA[k][r] = a[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KC * TN / 1024; ++q) {
+            int e = t + q * 256;
+            int k = e / (TN / 4), c = (e - k * (TN / 4)) * 4;
+            sB[k][c] = b[4 * q];
+            sB[k][c + 1] = b[4 * q + 1];
+            sB[k][c + 2] = b[4 * q + 2];
+            sB[k][c + 3] = b[4 * q + 3];
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // phase 1: partial projections
 // ---------------------------------------------------------------------------
@@ -114,25 +208,22 @@ __global__ void __launch_bounds__(256) k_proj_mm(const ProjGroup *groups, const 
     const ProjGroup g = groups[wk.group];
     const int r0 = blockIdx.y * TN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    __shared__ T sA[KC][TM + PADA];
-    __shared__ T sB[KC][TN + PADB];
+    __shared__ T sA[2][KC][TM + PADA];
+    __shared__ T sB[2][KC][TN + PADB];
     Tile<T> tile;
     tile.zero();
     const int rows = min(TM, g.ktot - wk.krow0);
     const T *V = vals + g.v_off + (int64_t)wk.krow0 * g.ld;
+    Stage<T> st;
+    int buf = 0;
+    st.fetch(1, V, g.ld, 0, 0, rows, wk.jb, min(KC, wk.je - wk.jb), X, (int64_t)g.j0 + wk.jb, ldr, r0, R, t);
     for (int kb = wk.jb; kb < wk.je; kb += KC) {
-        const int kcount = min(KC, wk.je - kb);
-        // A[row][k] = V[(kb + k) + row * ld]: threads walk k fastest (contiguous in V)
-        for (int e = t; e < KC * TM; e += 256) {
-            int r = e / KC, k = e - r * KC;
-            T v = 0;
-            if (k < kcount && r < rows) v = V[(int64_t)(kb + k) + (int64_t)r * g.ld];
-            sA[k][r] = v;
-        }
-        load_b_rmajor(sB, X, (int64_t)g.j0 + kb, kcount, ldr, r0, R, t);
+        st.commit(1, sA[buf], sB[buf], t);
         __syncthreads();
-        tile.mma(sA, sB, lane, w);
-        __syncthreads();
+        const int nk = kb + KC;
+        if (nk < wk.je) st.fetch(1, V, g.ld, 0, 0, rows, nk, min(KC, wk.je - nk), X, (int64_t)g.j0 + nk, ldr, r0, R, t);
+        tile.mma(sA[buf], sB[buf], lane, w);
+        buf ^= 1;
     }
     T *out = part + (int64_t)wk.part * TM * ldr;
     const int lr = lane & 15, lk = lane >> 4;
@@ -148,138 +239,198 @@ __global__ void __launch_bounds__(256) k_proj_mm(const ProjGroup *groups, const 
             }
 }
 
-// T rows = sum of the partial tiles of every split (fixed order)
+// T rows = sum of the partial tiles of every split (fixed order); one thread
+// per (row of T, column)
 template <class T>
 __global__ void __launch_bounds__(256) k_proj_reduce(const P1Red *red, const T *part, int64_t ldr, int R, T *Tb) {
-    const P1Red rd = red[blockIdx.x];
+    const P1Red rd = red[blockIdx.x / TM];
+    const int row = blockIdx.x % TM;
     const int c = blockIdx.y * 256 + threadIdx.x;
-    if (c >= R) return;
-    for (int row = 0; row < rd.nrows; ++row) {
-        T s = 0;
-        for (int p = 0; p < rd.part_count; ++p) s += part[((int64_t)(rd.part_begin + p) * TM + row) * ldr + c];
-        Tb[(int64_t)(rd.t_row0 + row) * ldr + c] = s;
-    }
+    if (c >= R || row >= rd.nrows) return;
+    T s = 0;
+    for (int p = 0; p < rd.part_count; ++p) s += part[((int64_t)(rd.part_begin + p) * TM + row) * ldr + c];
+    Tb[(int64_t)(rd.t_row0 + row) * ldr + c] = s;
 }
 
 // ---------------------------------------------------------------------------
-// phase 2: per leaf
+// phase 2: one workgroup per (64-row tile, 128-column tile).  With E given,
+// the epilogue performs the Jacobi update B_new = E + rho * (F B_old) and
+// writes the per-column partial sums of (B_new - B_old)^2 for this tile.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(256) k_leaf_mm(const LeafInfo *leaves, const LeafTask *tasks, const T *vals,
+__global__ void __launch_bounds__(256) k_tile_mm(const int32_t *tile_ptr, const TileTask *tasks, const T *vals,
                                                   const int32_t *csr_ptr, const int32_t *csr_idx,
                                                   int64_t csr_val_start, const T *X, const T *Tb, int64_t ldr, int R,
-                                                  T *Y) {
-    const LeafInfo L = leaves[blockIdx.x];
+                                                  int64_t N, T *Y, const T *E, const T *rho, T rho_s,
+                                                  double *partial) {
+    const int tile = blockIdx.x;
+    const int64_t tile0 = (int64_t)tile * TM;
     const int r0 = blockIdx.y * TN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    __shared__ T sA[KC][TM + PADA];
-    __shared__ T sB[KC][TN + PADB];
-    for (int rb = 0; rb < L.size; rb += TM) {
-        const int rows = min(TM, L.size - rb);
-        Tile<T> tile;
-        tile.zero();
-        for (int ti = L.task_begin; ti < L.task_end; ++ti) {
-            const LeafTask tk = tasks[ti];
-            if (tk.type == TASK_CSR) {
-                const int32_t *ptr = csr_ptr + tk.aux_off;
-                const T *v = vals + tk.a_off;
-                const int32_t *ci = csr_idx + (tk.a_off - csr_val_start);
-                int cur = 0, end = 0;
-                if (t < rows) {
-                    cur = ptr[rb + t];
-                    end = ptr[rb + t + 1];
-                }
-                for (int kb = 0; kb < tk.ncol; kb += KC) {
-                    const int kcount = min(KC, tk.ncol - kb);
-                    for (int e = t; e < KC * TM; e += 256) sA[e / TM][e % TM] = 0;
-                    __syncthreads();
-                    if (t < rows) {
-                        while (cur < end && ci[cur] < kb + KC) {
-                            sA[ci[cur] - kb][t] = v[cur];
-                            ++cur;
-                        }
-                    }
-                    load_b_rmajor(sB, X, (int64_t)tk.col0 + kb, kcount, ldr, r0, R, t);
-                    __syncthreads();
-                    tile.mma(sA, sB, lane, w);
-                    __syncthreads();
-                }
-            } else {
-                const T *A = vals + tk.a_off + rb;
-                const T *Bsrc = tk.type == TASK_DENSE ? X : Tb;
-                for (int kb = 0; kb < tk.ncol; kb += KC) {
-                    const int kcount = min(KC, tk.ncol - kb);
-                    load_a_colmajor(sA, A, tk.ld, rows, kb, kcount, t);
-                    load_b_rmajor(sB, Bsrc, (int64_t)tk.col0 + kb, kcount, ldr, r0, R, t);
-                    __syncthreads();
-                    tile.mma(sA, sB, lane, w);
-                    __syncthreads();
-                }
-            }
+    __shared__ T sA[2][KC][TM + PADA];
+    __shared__ T sB[2][KC][TN + PADB];
+    Tile<T> acc;
+    acc.zero();
+    const int tb = tile_ptr[tile], te = tile_ptr[tile + 1];
+    // CSR tasks: rows expanded into dense chunks in LDS
+    for (int ti = tb; ti < te; ++ti) {
+        const TileTask tk = tasks[ti];
+        if (tk.type != TASK_CSR) continue;
+        const T *v = vals + tk.a_off;
+        const int32_t *ci = csr_idx + (tk.a_off - csr_val_start);
+        int cur = 0, end = 0;
+        if (t >= tk.r_lo && t < tk.r_hi) {
+            cur = csr_ptr[tk.aux_off + tk.row_off + t];
+            end = csr_ptr[tk.aux_off + tk.row_off + t + 1];
         }
-        const int lr = lane & 15, lk = lane >> 4;
+        for (int kb = 0; kb < tk.ncol; kb += KC) {
+            const int kcount = min(KC, tk.ncol - kb);
+            for (int e = t; e < KC * TM; e += 256) sA[0][e / TM][e % TM] = 0;
+            __syncthreads();
+            while (cur < end && ci[cur] < kb + KC) {
+                sA[0][ci[cur] - kb][t] = v[cur];
+                ++cur;
+            }
+            load_b_rmajor(sB[0], X, (int64_t)tk.col0 + kb, kcount, ldr, r0, R, t);
+            __syncthreads();
+            acc.mma(sA[0], sB[0], lane, w);
+            __syncthreads();
+        }
+    }
+    // dense and low-rank tasks: flattened chunk sequence, software pipelined
+    int ti = tb, kb = 0;
+    auto skip_csr = [&]() {
+        while (ti < te && tasks[ti].type == TASK_CSR) ++ti;
+    };
+    skip_csr();
+    if (ti < te) {
+        Stage<T> st;
+        TileTask tk = tasks[ti];
+        st.fetch(0, vals + tk.a_off, tk.ld, tk.row_off, tk.r_lo, tk.r_hi, 0, min(KC, tk.ncol),
+                 tk.type == TASK_DENSE ? X : Tb, tk.col0, ldr, r0, R, t);
+        int buf = 0;
+        while (true) {
+            st.commit(0, sA[buf], sB[buf], t);
+            __syncthreads();
+            // advance to the next chunk and prefetch it
+            kb += KC;
+            if (kb >= tk.ncol) {
+                ++ti;
+                kb = 0;
+                skip_csr();
+            }
+            const bool more = ti < te;
+            if (more) {
+                tk = tasks[ti];
+                st.fetch(0, vals + tk.a_off, tk.ld, tk.row_off, tk.r_lo, tk.r_hi, kb, min(KC, tk.ncol - kb),
+                         tk.type == TASK_DENSE ? X : Tb, (int64_t)tk.col0 + kb, ldr, r0, R, t);
+            }
+            acc.mma(sA[buf], sB[buf], lane, w);
+            buf ^= 1;
+            if (!more) break;
+        }
+    }
+    const int lr = lane & 15, lk = lane >> 4;
+    const int rows = (int)min((int64_t)TM, N - tile0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = r0 + w * 32 + j * 16 + lr;
+        double d2 = 0.0;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    int row = i * 16 + Mfma<T>::row(lk, v);
-                    int col = r0 + w * 32 + j * 16 + lr;
-                    if (row < rows && col < R) Y[(int64_t)(L.start + rb + row) * ldr + col] = tile.acc[i][j][v];
+            for (int v = 0; v < 4; ++v) {
+                const int row = i * 16 + Mfma<T>::row(lk, v);
+                if (row < rows && col < R) {
+                    const int64_t e = (tile0 + row) * ldr + col;
+                    T y = acc.acc[i][j][v];
+                    if (E) {
+                        T rh = rho ? rho[tile0 + row] : rho_s;
+                        T bn = E[e] + rh * y;
+                        double d = (double)bn - (double)X[e];
+                        d2 += d * d;
+                        y = bn;
+                    }
+                    Y[e] = y;
                 }
+            }
+        if (E) {
+            d2 += __shfl_xor(d2, 16, 64);
+            d2 += __shfl_xor(d2, 32, 64);
+            if (lk == 0 && col < R) partial[(int64_t)tile * R + col] = d2;
+        }
     }
 }
 
-// col-major (original or tree order) <-> R-major tree order
+// col-major (original or tree order) <-> R-major tree order, 64 x 64 tiles
+// through LDS so that both the column-major and the R-major side are walked
+// along their contiguous dimension.
 template <class T>
-__global__ void k_to_rmajor(const int32_t *perm, const T *src, int64_t lds, T *dst, int64_t ldr, int64_t N, int R) {
-    int64_t tot = N * (int64_t)R;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-        int64_t t = e / R;
-        int r = (int)(e - t * R);
-        int64_t row = perm ? (int64_t)perm[t] : t;
-        dst[t * ldr + r] = src[row + (int64_t)r * lds];
+__global__ void __launch_bounds__(256) k_to_rmajor(const int32_t *perm, const T *src, int64_t lds, T *dst,
+                                                    int64_t ldr, int64_t N, int R) {
+    __shared__ T sm[64][65];
+    const int64_t t0 = (int64_t)blockIdx.x * 64;
+    const int r0 = blockIdx.y * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        int tt = e & 63, rr = e >> 6;
+        int64_t t = t0 + tt;
+        T v = 0;
+        if (t < N && r0 + rr < R) v = src[(perm ? (int64_t)perm[t] : t) + (int64_t)(r0 + rr) * lds];
+        sm[rr][tt] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        int rr = e & 63, tt = e >> 6;
+        int64_t t = t0 + tt;
+        if (t < N && r0 + rr < R) dst[t * ldr + r0 + rr] = sm[rr][tt];
     }
 }
 
 template <class T>
-__global__ void k_from_rmajor(const int32_t *perm, const T *src, int64_t ldr, T *dst, int64_t ldd, int64_t N, int R) {
-    int64_t tot = N * (int64_t)R;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-        int64_t t = e / R;
-        int r = (int)(e - t * R);
-        int64_t row = perm ? (int64_t)perm[t] : t;
-        dst[row + (int64_t)r * ldd] = src[t * ldr + r];
+__global__ void __launch_bounds__(256) k_from_rmajor(const int32_t *perm, const T *src, int64_t ldr, T *dst,
+                                                      int64_t ldd, int64_t N, int R) {
+    __shared__ T sm[64][65];
+    const int64_t t0 = (int64_t)blockIdx.x * 64;
+    const int r0 = blockIdx.y * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        int rr = e & 63, tt = e >> 6;
+        int64_t t = t0 + tt;
+        T v = 0;
+        if (t < N && r0 + rr < R) v = src[t * ldr + r0 + rr];
+        sm[rr][tt] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        int tt = e & 63, rr = e >> 6;
+        int64_t t = t0 + tt;
+        if (t < N && r0 + rr < R) dst[(perm ? (int64_t)perm[t] : t) + (int64_t)(r0 + rr) * ldd] = sm[rr][tt];
     }
 }
 
-// Jacobi update in R-major layout; partial[block][r] = sum over the block's facets of (Bnew - Bold)^2
-template <class T>
-__global__ void __launch_bounds__(256) k_jacobi_rm(const T *E, const T *rho, T rho_s, const T *FB, const T *Bold,
-                                                    T *Bnew, int64_t N, int64_t ldr, int R, double *partial) {
-    const int r = blockIdx.y * 256 + threadIdx.x;
-    if (r >= R) return;
-    const int64_t per = (N + gridDim.x - 1) / gridDim.x;
-    const int64_t t0 = blockIdx.x * per, t1 = min(N, t0 + per);
+// out[r] = sum_i partial[i * R + r]: 16 columns x 16 part groups per
+// workgroup, fixed summation order (deterministic)
+__global__ void __launch_bounds__(256) k_reduce_rm(const double *partial, int nparts, int R, double *out) {
+    const int cl = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int r = blockIdx.x * 16 + cl;
     double s = 0.0;
-    for (int64_t t = t0; t < t1; ++t) {
-        int64_t e = t * ldr + r;
-        T rh = rho ? rho[t] : rho_s;
-        T b = E[e] + rh * FB[e];
-        double d = (double)b - (double)Bold[e];
-        s += d * d;
-        Bnew[e] = b;
+    if (r < R)
+        for (int i = g; i < nparts; i += 16) s += partial[(int64_t)i * R + r];
+    __shared__ double red[16][17];
+    red[g][cl] = s;
+    __syncthreads();
+    if (g == 0 && r < R) {
+        double tot = 0.0;
+        for (int k = 0; k < 16; ++k) tot += red[k][cl];
+        out[r] = tot;
     }
-    partial[(int64_t)blockIdx.x * R + r] = s;
 }
 
+// partial[tile * R + r] = sum over the tile's 64 facets of E^2 (R-major)
 template <class T>
-__global__ void __launch_bounds__(256) k_colnorm_rm(const T *E, int64_t N, int64_t ldr, int R, double *partial) {
+__global__ void __launch_bounds__(256) k_colnorm_tiles(const T *E, int64_t N, int64_t ldr, int R, double *partial) {
     const int r = blockIdx.y * 256 + threadIdx.x;
     if (r >= R) return;
-    const int64_t per = (N + gridDim.x - 1) / gridDim.x;
-    const int64_t t0 = blockIdx.x * per, t1 = min(N, t0 + per);
+    const int64_t t0 = (int64_t)blockIdx.x * 64, t1 = min(N, t0 + 64);
     double s = 0.0;
     for (int64_t t = t0; t < t1; ++t) {
         double v = (double)E[t * ldr + r];
@@ -288,30 +439,29 @@ __global__ void __launch_bounds__(256) k_colnorm_rm(const T *E, int64_t N, int64
     partial[(int64_t)blockIdx.x * R + r] = s;
 }
 
-__global__ void k_reduce_rm(const double *partial, int nparts, int R, double *out) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    double s = 0.0;
-    for (int i = 0; i < nparts; ++i) s += partial[(int64_t)i * R + r];
-    out[r] = s;
-}
-
 constexpr int kRmParts = 64;
 
 template <class T>
-void apply_mm_t(const rad_hmat *H, const T *X, T *Y, int64_t ldr, int R, hipStream_t s) {
+void proj_mm_t(const rad_hmat *H, const T *X, int64_t ldr, int R, hipStream_t s) {
     unsigned rtiles = (unsigned)((R + TN - 1) / TN);
     if (H->n_p1work > 0) {
         hipLaunchKernelGGL(k_proj_mm<T>, dim3(H->n_p1work, rtiles), dim3(256), 0, s, H->d_groups.p, H->d_p1work.p,
                            (const T *)H->d_vals.p, X, ldr, R, (T *)H->w_part.p);
         RAD_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_proj_reduce<T>, dim3(H->n_p1red, (R + 255) / 256), dim3(256), 0, s, H->d_p1red.p,
+        hipLaunchKernelGGL(k_proj_reduce<T>, dim3(H->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s, H->d_p1red.p,
                            (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p);
         RAD_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_leaf_mm<T>, dim3(H->n_leaves, rtiles), dim3(256), 0, s, H->d_leaves.p, H->d_tasks.p,
+}
+
+template <class T>
+void apply_mm_t(const rad_hmat *H, const T *X, T *Y, int64_t ldr, int R, const T *E, const T *rho, T rho_s,
+                double *partial, hipStream_t s) {
+    proj_mm_t<T>(H, X, ldr, R, s);
+    unsigned rtiles = (unsigned)((R + TN - 1) / TN);
+    hipLaunchKernelGGL(k_tile_mm<T>, dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tile_ptr.p, H->d_tile_tasks.p,
                        (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p, H->csr_val_start, X,
-                       (const T *)H->w_t.p, ldr, R, Y);
+                       (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial);
     RAD_HIP(hipGetLastError());
 }
 
@@ -319,67 +469,66 @@ void apply_mm_t(const rad_hmat *H, const T *X, T *Y, int64_t ldr, int R, hipStre
 
 int64_t mm_ldr(int64_t R) { return (R + 3) & ~(int64_t)3; }
 int mm_part_rows() { return TM; }
-size_t mm_reduction_doubles(int64_t R) { return (size_t)kRmParts * (size_t)R; }
 
 void mm_to_rmajor(const rad_hmat *H, const void *src, int64_t lds, bool permute, void *dst, int64_t ldr, int64_t R,
                   hipStream_t s) {
-    int64_t tot = H->N * R;
-    unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 16384);
+    dim3 grid((unsigned)((H->N + 63) / 64), (unsigned)((R + 63) / 64));
     const int32_t *perm = permute ? H->d_perm.p : nullptr;
     if (H->dtype == RAD_F64)
-        hipLaunchKernelGGL(k_to_rmajor<double>, dim3(blocks), dim3(256), 0, s, perm, (const double *)src, lds,
-                           (double *)dst, ldr, H->N, (int)R);
+        hipLaunchKernelGGL(k_to_rmajor<double>, grid, dim3(256), 0, s, perm, (const double *)src, lds, (double *)dst,
+                           ldr, H->N, (int)R);
     else
-        hipLaunchKernelGGL(k_to_rmajor<float>, dim3(blocks), dim3(256), 0, s, perm, (const float *)src, lds,
-                           (float *)dst, ldr, H->N, (int)R);
+        hipLaunchKernelGGL(k_to_rmajor<float>, grid, dim3(256), 0, s, perm, (const float *)src, lds, (float *)dst, ldr,
+                           H->N, (int)R);
     RAD_HIP(hipGetLastError());
 }
 
 void mm_from_rmajor(const rad_hmat *H, const void *src, int64_t ldr, bool permute, void *dst, int64_t ldd, int64_t R,
                     hipStream_t s) {
-    int64_t tot = H->N * R;
-    unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 16384);
+    dim3 grid((unsigned)((H->N + 63) / 64), (unsigned)((R + 63) / 64));
     const int32_t *perm = permute ? H->d_perm.p : nullptr;
     if (H->dtype == RAD_F64)
-        hipLaunchKernelGGL(k_from_rmajor<double>, dim3(blocks), dim3(256), 0, s, perm, (const double *)src, ldr,
-                           (double *)dst, ldd, H->N, (int)R);
+        hipLaunchKernelGGL(k_from_rmajor<double>, grid, dim3(256), 0, s, perm, (const double *)src, ldr, (double *)dst,
+                           ldd, H->N, (int)R);
     else
-        hipLaunchKernelGGL(k_from_rmajor<float>, dim3(blocks), dim3(256), 0, s, perm, (const float *)src, ldr,
-                           (float *)dst, ldd, H->N, (int)R);
+        hipLaunchKernelGGL(k_from_rmajor<float>, grid, dim3(256), 0, s, perm, (const float *)src, ldr, (float *)dst,
+                           ldd, H->N, (int)R);
     RAD_HIP(hipGetLastError());
 }
 
 void mm_apply(const rad_hmat *H, const void *X, void *Y, int64_t ldr, int64_t R, hipStream_t s) {
     if (H->dtype == RAD_F64)
-        apply_mm_t<double>(H, (const double *)X, (double *)Y, ldr, (int)R, s);
+        apply_mm_t<double>(H, (const double *)X, (double *)Y, ldr, (int)R, nullptr, nullptr, 0.0, nullptr, s);
     else
-        apply_mm_t<float>(H, (const float *)X, (float *)Y, ldr, (int)R, s);
+        apply_mm_t<float>(H, (const float *)X, (float *)Y, ldr, (int)R, nullptr, nullptr, 0.0f, nullptr, s);
 }
 
-void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, double *out, hipStream_t s) {
-    dim3 grid(kRmParts, (unsigned)((R + 255) / 256));
+// one Jacobi iteration: B_new = E + rho * (F-hat B_old), norms[r] = ||B_new - B_old||^2
+void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
+                    int64_t ldr, int64_t R, double *norms, hipStream_t s) {
     double *part = (double *)H->w_red.p;
     if (H->dtype == RAD_F64)
-        hipLaunchKernelGGL(k_colnorm_rm<double>, grid, dim3(256), 0, s, (const double *)E, H->N, ldr, (int)R, part);
+        apply_mm_t<double>(H, (const double *)Bold, (double *)Bnew, ldr, (int)R, (const double *)E,
+                           (const double *)rho, rho_scalar, part, s);
     else
-        hipLaunchKernelGGL(k_colnorm_rm<float>, grid, dim3(256), 0, s, (const float *)E, H->N, ldr, (int)R, part);
-    hipLaunchKernelGGL(k_reduce_rm, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, part, kRmParts, (int)R, out);
+        apply_mm_t<float>(H, (const float *)Bold, (float *)Bnew, ldr, (int)R, (const float *)E, (const float *)rho,
+                          (float)rho_scalar, part, s);
+    hipLaunchKernelGGL(k_reduce_rm, dim3((unsigned)((R + 15) / 16)), dim3(256), 0, s, part, H->n_tiles, (int)R, norms);
     RAD_HIP(hipGetLastError());
 }
 
-void mm_solve_update(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *FB,
-                     const void *Bold, void *Bnew, int64_t ldr, int64_t R, double *norms, hipStream_t s) {
-    dim3 grid(kRmParts, (unsigned)((R + 255) / 256));
+size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R) {
+    return (size_t)std::max<int64_t>(H->n_tiles, kRmParts) * (size_t)R;
+}
+
+void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, double *out, hipStream_t s) {
+    dim3 grid((unsigned)H->n_tiles, (unsigned)((R + 255) / 256));
     double *part = (double *)H->w_red.p;
     if (H->dtype == RAD_F64)
-        hipLaunchKernelGGL(k_jacobi_rm<double>, grid, dim3(256), 0, s, (const double *)E, (const double *)rho,
-                           rho_scalar, (const double *)FB, (const double *)Bold, (double *)Bnew, H->N, ldr, (int)R,
-                           part);
+        hipLaunchKernelGGL(k_colnorm_tiles<double>, grid, dim3(256), 0, s, (const double *)E, H->N, ldr, (int)R, part);
     else
-        hipLaunchKernelGGL(k_jacobi_rm<float>, grid, dim3(256), 0, s, (const float *)E, (const float *)rho,
-                           (float)rho_scalar, (const float *)FB, (const float *)Bold, (float *)Bnew, H->N, ldr,
-                           (int)R, part);
-    hipLaunchKernelGGL(k_reduce_rm, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, part, kRmParts, (int)R, norms);
+        hipLaunchKernelGGL(k_colnorm_tiles<float>, grid, dim3(256), 0, s, (const float *)E, H->N, ldr, (int)R, part);
+    hipLaunchKernelGGL(k_reduce_rm, dim3((unsigned)((R + 15) / 16)), dim3(256), 0, s, part, H->n_tiles, (int)R, out);
     RAD_HIP(hipGetLastError());
 }
 

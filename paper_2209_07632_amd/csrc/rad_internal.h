@@ -124,6 +124,21 @@ struct LeafTask {
     int64_t aux_off;       // CSR: offset of this slice's row pointers (int32, m_L+1 entries)
 };
 
+// Task of one 64-row tile of the multi-RHS kernels: rows [r_lo, r_hi) of the
+// tile are block rows row_off + r of a block stored column-major (ld = block
+// rows) at a_off; CSR blocks keep row pointers at aux_off (relative to a_off).
+struct TileTask {
+    int32_t type;
+    int32_t ncol;
+    int32_t ld;
+    int32_t col0;
+    int64_t a_off;
+    int64_t aux_off;
+    int32_t row_off;
+    int32_t r_lo, r_hi;
+    int32_t pad_;
+};
+
 // Phase-1 group: all low-rank blocks sharing column node J.
 struct ProjGroup {
     int32_t j0, n;         // X rows
@@ -178,6 +193,9 @@ struct rad_hmat {
     std::vector<rad::LeafInfo> h_leaves;
     std::vector<rad::LeafTask> h_tasks;
     std::vector<rad::ProjGroup> h_groups;
+    rad::DevBuf<rad::TileTask> d_tile_tasks;
+    rad::DevBuf<int32_t> d_tile_ptr;
+    int32_t n_tiles = 0;
     rad::DevBuf<rad::P1Work> d_p1work;
     rad::DevBuf<rad::P1Red> d_p1red;
     int32_t n_p1work = 0, n_p1red = 0, n_parts = 0;
@@ -250,14 +268,14 @@ size_t reduction_doubles(int64_t R);
 constexpr int64_t kMfmaMinRhs = 16;
 int64_t mm_ldr(int64_t R);
 int mm_part_rows();
-size_t mm_reduction_doubles(int64_t R);
 void mm_to_rmajor(const rad_hmat *H, const void *src, int64_t lds, bool permute, void *dst, int64_t ldr, int64_t R,
                   hipStream_t s);
 void mm_from_rmajor(const rad_hmat *H, const void *src, int64_t ldr, bool permute, void *dst, int64_t ldd, int64_t R,
                     hipStream_t s);
 void mm_apply(const rad_hmat *H, const void *X, void *Y, int64_t ldr, int64_t R, hipStream_t s);
 void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, double *out, hipStream_t s);
-void mm_solve_update(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *FB,
-                     const void *Bold, void *Bnew, int64_t ldr, int64_t R, double *norms, hipStream_t s);
+void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
+                    int64_t ldr, int64_t R, double *norms, hipStream_t s);
+size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R);
 
 }  // namespace rad
