@@ -160,9 +160,22 @@ typedef struct {
     int32_t max_rank;
     double build_seconds;
     double flops_per_rhs;      /* 2 (sum (m+n)k + nnz_near): matvec flops per column   */
+    int64_t lowrank_row_elems; /* sum over low-rank blocks of m k (U' factors)        */
+    int64_t lowrank_col_elems; /* sum over low-rank blocks of n k (V factors)         */
 } rad_hmat_stats;
 
 rad_status rad_hmat_info(const rad_hmat *H, rad_hmat_stats *stats);
+
+/*
+ * Diagnostic timing of the multi-RHS kernels of one Jacobi iteration on the
+ * caller's stream, measured with HIP events over nrep back-to-back launches of
+ * each kernel on the library's own workspace (contents irrelevant):
+ *   ms[0] = projections T = V^T X (split-K GEMM),
+ *   ms[1] = sum of the split-K partial tiles,
+ *   ms[2] = expansion and near field with the fused Jacobi update.
+ * Averages per launch in milliseconds.  Requires 16 <= R <= max_rhs.
+ */
+rad_status rad_hmat_time_phases(const rad_hmat *H, int64_t R, int32_t nrep, void *hip_stream, double *ms);
 
 /* Number of facets N and compute dtype of H (-1 when H is NULL). */
 int64_t rad_hmat_n(const rad_hmat *H);

@@ -561,10 +561,6 @@ struct Builder {
         }
         std::sort(finals.begin(), finals.end());
 
-        std::vector<const TreeNode *> leaves(H->n_leaves);
-        for (const TreeNode &t : H->nodes)
-            if (t.nchild == 0) leaves[t.leaf_index] = &t;
-
         struct Copy {
             int64_t src_off;  // candidate pool (doubles)
             int32_t level;
@@ -614,47 +610,72 @@ struct Builder {
             return it->second;
         };
 
-        // block storage: dense and U' column-major with ld = rows of the block;
-        // CSR per block (row pointers relative to the block's first value)
-        struct Placed {
+        // Row tiles of 64 facets (tree order).  Dense and low-rank blocks are
+        // stored per tile as one packed panel: 64 x K_tile, column-major
+        // (ld 64), holding the dense rows and U' rows of every block that
+        // touches the tile, with brow[] naming the operand row of each panel
+        // column (X row >= 0, T row -1-t < 0).  CSR blocks keep their own
+        // per-block storage and per-tile task entries.
+        const int32_t n_tiles = (int32_t)((H->N + 63) / 64);
+        struct PT {
+            int32_t type;
             int64_t p;
-            int64_t a_off;    // dense/U' values, or CSR value base (set after counting)
-            int64_t ptr_off;  // CSR row pointers
+            int32_t ncol, r_lo, r_hi, row_off, src_row0;
         };
-        std::vector<Placed> placed;
-        std::vector<int32_t> dense_tiles, csr_tiles;
-        std::vector<int64_t> dense_offs, csr_row_offs;
+        std::vector<std::vector<PT>> tp(n_tiles);
+        std::vector<std::vector<TileTask>> tcsr(n_tiles);
+        std::vector<int32_t> csr_tiles;
+        std::vector<int64_t> csr_row_offs;
+        std::vector<std::pair<int64_t, int64_t>> csr_ptr_of;  // (p, ptr_off)
         int64_t ptr_fill = 0;
         for (int64_t p : finals) {
             const BlockPair &b = bp[p];
             const TreeNode &rn = H->nodes[b.I], &cn = H->nodes[b.J];
-            Placed pl{p, 0, 0};
+            int64_t ptr_off = 0;
             if (b.kind == BK_DENSE) {
-                pl.a_off = vfill;
-                dense_tiles.insert(dense_tiles.end(), {rn.start, rn.size, cn.start, cn.size, rn.size, 0});
-                dense_offs.push_back(vfill);
-                vfill += (int64_t)rn.size * cn.size;
                 H->stats.n_dense++;
                 H->stats.bytes_dense += dense_bytes(rn.size, cn.size);
                 H->stats.nnz_near += (int64_t)rn.size * cn.size;
             } else if (b.kind == BK_CSR) {
-                pl.ptr_off = ptr_fill;
+                ptr_off = ptr_fill;
                 csr_tiles.insert(csr_tiles.end(), {rn.start, rn.size, cn.start, cn.size, 0, 0});
                 csr_row_offs.push_back(ptr_fill);
+                csr_ptr_of.push_back({p, ptr_fill});
                 ptr_fill += rn.size + 1;
                 H->stats.n_csr++;
                 H->stats.bytes_csr += csr_bytes(rn.size, b.nnz);
                 H->stats.nnz_near += b.nnz;
             } else {
-                pl.a_off = vfill;
-                copies.push_back(Copy{b.cand_off, b.cand_level, rn.size, b.rank, rn.size, vfill, rn.size});
-                vfill += (int64_t)rn.size * b.rank;
                 H->stats.bytes_lowrank += svd_bytes(rn.size, cn.size, b.rank);
                 H->stats.sum_rank += b.rank;
                 H->stats.lowrank_elems += (int64_t)(rn.size + cn.size) * b.rank;
+                H->stats.lowrank_row_elems += (int64_t)rn.size * b.rank;
+                H->stats.lowrank_col_elems += (int64_t)cn.size * b.rank;
                 H->stats.max_rank = std::max(H->stats.max_rank, b.rank);
             }
-            placed.push_back(pl);
+            for (int32_t tile = rn.start / 64; (int64_t)tile * 64 < (int64_t)rn.start + rn.size; ++tile) {
+                int32_t tile0 = tile * 64;
+                int32_t r_lo = std::max(0, rn.start - tile0);
+                int32_t r_hi = std::min(64, rn.start + rn.size - tile0);
+                int32_t row_off = tile0 - rn.start;
+                if (b.kind == BK_CSR) {
+                    TileTask t{};
+                    t.type = TASK_CSR;
+                    t.ncol = cn.size;
+                    t.col0 = cn.start;
+                    t.aux_off = ptr_off;
+                    t.a_off = p;  // replaced by the value base once CSR sizes are known
+                    t.row_off = row_off;
+                    t.r_lo = r_lo;
+                    t.r_hi = r_hi;
+                    tcsr[tile].push_back(t);
+                } else {
+                    int32_t type = b.kind == BK_DENSE ? TASK_DENSE : TASK_LOWRANK;
+                    int32_t ncol = b.kind == BK_DENSE ? cn.size : b.rank;
+                    int32_t src = b.kind == BK_DENSE ? cn.start : t_find(p);
+                    tp[tile].push_back(PT{type, p, ncol, r_lo, r_hi, row_off, src});
+                }
+            }
         }
 
         // CSR: count per row on the GPU, scan on the host
@@ -686,117 +707,109 @@ struct Builder {
                 csr_nnz_total += acc;
             }
         }
+
+        // panels (16-byte vector loads need panel_off aligned to 64 elements)
+        vfill = (vfill + 63) / 64 * 64;
+        std::vector<TileInfo> tinfo(n_tiles);
+        std::vector<int32_t> brow;
+        std::vector<int32_t> dense_desc;  // i0, m, j0, n, ld, pad
+        std::vector<int64_t> dense_offs;
+        std::vector<CopyDesc> lr_copies;
+        std::vector<TileTask> ttasks;
+        std::sort(csr_ptr_of.begin(), csr_ptr_of.end());
+        for (int32_t tl = 0; tl < n_tiles; ++tl) {
+            auto &v = tp[tl];
+            std::stable_sort(v.begin(), v.end(), [](const PT &a, const PT &b) { return a.type < b.type; });
+            int64_t K = 0;
+            for (const PT &pt : v) K += pt.ncol;
+            int64_t kpad = (K + 31) / 32 * 32;
+            TileInfo ti{};
+            ti.panel_off = vfill;
+            ti.kpad = (int32_t)kpad;
+            ti.brow_off = (int64_t)brow.size();
+            int64_t col = 0;
+            for (const PT &pt : v) {
+                const BlockPair &b = bp[pt.p];
+                int64_t dst = vfill + col * 64 + pt.r_lo;
+                if (pt.type == TASK_DENSE) {
+                    dense_desc.insert(dense_desc.end(), {tl * 64 + pt.r_lo, pt.r_hi - pt.r_lo, pt.src_row0, pt.ncol, 64, 0});
+                    dense_offs.push_back(dst);
+                    for (int32_t k = 0; k < pt.ncol; ++k) brow.push_back(pt.src_row0 + k);
+                } else {
+                    const TreeNode &rn = H->nodes[b.I];
+                    CopyDesc c{};
+                    c.src = pools[b.cand_level].p + b.cand_off + (pt.row_off + pt.r_lo);
+                    c.rows = pt.r_hi - pt.r_lo;
+                    c.cols = pt.ncol;
+                    c.lds = rn.size;
+                    c.dst_off = dst;
+                    c.ldd = 64;
+                    lr_copies.push_back(c);
+                    for (int32_t k = 0; k < pt.ncol; ++k) brow.push_back(-(pt.src_row0 + k) - 1);
+                }
+                col += pt.ncol;
+            }
+            for (int64_t k = K; k < kpad; ++k) brow.push_back(0);
+            vfill += 64 * kpad;
+            ti.csr_begin = (int32_t)ttasks.size();
+            for (TileTask t : tcsr[tl]) {
+                auto it = std::lower_bound(csr_ptr_of.begin(), csr_ptr_of.end(), std::make_pair(t.a_off, (int64_t)INT64_MIN));
+                int64_t ci = it - csr_ptr_of.begin();
+                t.a_off = csr_val_base[ci];  // relative; made absolute below
+                ttasks.push_back(t);
+            }
+            ti.csr_end = (int32_t)ttasks.size();
+            tinfo[tl] = ti;
+        }
         const int64_t csr_val_start = vfill;
         vfill += csr_nnz_total;
-        {
-            int64_t ci = 0;
-            for (Placed &pl : placed)
-                if (bp[pl.p].kind == BK_CSR) pl.a_off = csr_val_start + csr_val_base[ci++];
-        }
-
-        // task lists: per leaf (single-RHS kernels) and per 64-row tile (MFMA kernels)
-        std::vector<std::vector<LeafTask>> lt(H->n_leaves);
-        const int32_t n_tiles = (int32_t)((H->N + 63) / 64);
-        std::vector<std::vector<TileTask>> tt(n_tiles);
-        for (const Placed &pl : placed) {
-            const BlockPair &b = bp[pl.p];
-            const TreeNode &rn = H->nodes[b.I], &cn = H->nodes[b.J];
-            int32_t type = b.kind == BK_DENSE ? TASK_DENSE : b.kind == BK_CSR ? TASK_CSR : TASK_LOWRANK;
-            int32_t ncol = b.kind == BK_LOWRANK ? b.rank : cn.size;
-            int32_t col0 = b.kind == BK_LOWRANK ? t_find(pl.p) : cn.start;
-            for (int32_t lf = rn.leaf_first; lf < rn.leaf_first + rn.leaf_count; ++lf) {
-                const TreeNode &L = *leaves[lf];
-                int32_t r0 = L.start - rn.start;
-                LeafTask t{};
-                t.type = type;
-                t.ncol = ncol;
-                t.ld = rn.size;
-                t.col0 = col0;
-                if (type == TASK_CSR) {
-                    t.a_off = pl.a_off;
-                    t.aux_off = pl.ptr_off + r0;
-                } else {
-                    t.a_off = pl.a_off + r0;
-                }
-                lt[lf].push_back(t);
-            }
-            for (int32_t tile = rn.start / 64; tile * 64 < rn.start + rn.size; ++tile) {
-                int32_t tile0 = tile * 64;
-                TileTask t{};
-                t.type = type;
-                t.ncol = ncol;
-                t.ld = rn.size;
-                t.col0 = col0;
-                t.a_off = pl.a_off;
-                t.aux_off = pl.ptr_off;
-                t.row_off = tile0 - rn.start;
-                t.r_lo = std::max(0, rn.start - tile0);
-                t.r_hi = std::min(64, rn.start + rn.size - tile0);
-                tt[tile].push_back(t);
-            }
-        }
-        std::vector<LeafInfo> linfo(H->n_leaves);
-        std::vector<LeafTask> tasks;
-        int32_t max_rows = 0;
-        for (int32_t lf = 0; lf < H->n_leaves; ++lf) {
-            auto &v = lt[lf];
-            std::stable_sort(v.begin(), v.end(), [](const LeafTask &a, const LeafTask &b) { return a.type < b.type; });
-            linfo[lf].start = leaves[lf]->start;
-            linfo[lf].size = leaves[lf]->size;
-            linfo[lf].task_begin = (int32_t)tasks.size();
-            tasks.insert(tasks.end(), v.begin(), v.end());
-            linfo[lf].task_end = (int32_t)tasks.size();
-            max_rows = std::max(max_rows, leaves[lf]->size);
-        }
-        std::vector<int32_t> tile_ptr(n_tiles + 1, 0);
-        std::vector<TileTask> ttasks;
-        for (int32_t tl = 0; tl < n_tiles; ++tl) {
-            auto &v = tt[tl];
-            std::stable_sort(v.begin(), v.end(), [](const TileTask &a, const TileTask &b) { return a.type < b.type; });
-            tile_ptr[tl] = (int32_t)ttasks.size();
-            ttasks.insert(ttasks.end(), v.begin(), v.end());
-        }
-        tile_ptr[n_tiles] = (int32_t)ttasks.size();
+        for (TileTask &t : ttasks) t.a_off += csr_val_start;
 
         // allocate the value pool and fill it
         H->d_vals.alloc((size_t)std::max<int64_t>(vfill, 1) * s);
         RAD_HIP(hipMemsetAsync(H->d_vals.p, 0, (size_t)std::max<int64_t>(vfill, 1) * s, st));
-        int64_t ntile_dense = (int64_t)dense_tiles.size() / 6;
-        if (ntile_dense > 0) {
+        int64_t n_dense_desc = (int64_t)dense_desc.size() / 6;
+        if (n_dense_desc > 0) {
             DevBuf<int32_t> d_t;
-            d_t.upload(dense_tiles);
+            d_t.upload(dense_desc);
             DevBuf<int64_t> d_o;
             d_o.upload(dense_offs);
-            launch_dense_fill(geom, d_t.p, d_o.p, ntile_dense, H->d_vals.p, H->dtype, st);
+            launch_dense_fill(geom, d_t.p, d_o.p, n_dense_desc, H->d_vals.p, H->dtype, st);
             RAD_HIP(hipStreamSynchronize(st));
         }
         if (ntile_csr > 0) {
             H->d_csr_ptr.upload(h_ptr);
             H->d_csr_idx.alloc((size_t)std::max<int64_t>(csr_nnz_total, 1));
-            std::vector<int64_t> vb(ntile_csr);
-            for (int64_t t = 0; t < ntile_csr; ++t) vb[t] = csr_val_base[t];
             DevBuf<int64_t> d_vb;
-            d_vb.upload(vb);
+            d_vb.upload(csr_val_base);
             // values at csr_val_start + base; column indices at base
             char *vals_csr = (char *)H->d_vals.p + (size_t)csr_val_start * s;
             launch_csr_fill(geom, d_ctiles.p, ntile_csr, H->d_csr_ptr.p, d_crow.p, d_vb.p, vals_csr,
                             H->d_csr_idx.p, H->dtype, st);
             RAD_HIP(hipStreamSynchronize(st));
         }
-        for (const Copy &c : copies) {
-            char *dst = (char *)H->d_vals.p + (size_t)c.dst_off * s;
-            launch_copy_cast(pools[c.level].p + c.src_off, c.rows, c.cols, c.lds, dst, c.ldd, H->dtype, st);
+        for (const Copy &c : copies) {  // stacked V factors
+            CopyDesc d{};
+            d.src = pools[c.level].p + c.src_off;
+            d.rows = c.rows;
+            d.cols = c.cols;
+            d.lds = c.lds;
+            d.dst_off = c.dst_off;
+            d.ldd = c.ldd;
+            lr_copies.push_back(d);
         }
-        RAD_HIP(hipStreamSynchronize(st));
+        if (!lr_copies.empty()) {
+            DevBuf<CopyDesc> d_c;
+            d_c.upload(lr_copies);
+            launch_copy_batched(d_c.p, (int64_t)lr_copies.size(), H->d_vals.p, H->dtype, st);
+            RAD_HIP(hipStreamSynchronize(st));
+        }
         H->csr_val_start = csr_val_start;
 
-        H->h_leaves = linfo;
-        H->h_tasks = tasks;
         H->h_groups = groups;
-        H->d_leaves.upload(linfo);
-        H->d_tasks.upload(tasks);
         H->d_groups.upload(groups);
-        H->d_tile_ptr.upload(tile_ptr);
+        H->d_tiles.upload(tinfo);
+        H->d_brow.upload(brow);
         H->d_tile_tasks.upload(ttasks);
         H->n_tiles = n_tiles;
         H->n_groups = (int32_t)groups.size();
@@ -825,11 +838,10 @@ struct Builder {
         }
         H->t_rows = t_fill;
         H->t_ld = std::max<int32_t>(round4(t_fill), 4);
-        H->max_leaf_rows = max_rows;
 
         H->stats.bytes_total = (int64_t)H->d_vals.bytes() + (int64_t)H->d_csr_idx.bytes() +
-                               (int64_t)H->d_csr_ptr.bytes() + (int64_t)H->d_tasks.bytes() +
-                               (int64_t)H->d_leaves.bytes() + (int64_t)H->d_groups.bytes() +
+                               (int64_t)H->d_csr_ptr.bytes() + (int64_t)H->d_tiles.bytes() +
+                               (int64_t)H->d_brow.bytes() + (int64_t)H->d_groups.bytes() +
                                (int64_t)H->d_tile_tasks.bytes() + (int64_t)H->d_perm.bytes();
         H->stats.flops_per_rhs = 2.0 * ((double)H->stats.lowrank_elems + (double)H->stats.nnz_near);
     }

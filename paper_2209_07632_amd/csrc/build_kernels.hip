@@ -5,6 +5,8 @@
 // (eq. FF-def) from the tree-ordered geometry, with V_ij the back-face test
 // of section 3.2 and, when a visibility bitmap is present, its ray-cast bit.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <hip/hip_fp16.h>
 
 #include "rad_internal.h"
@@ -307,12 +309,15 @@ __global__ void k_csr_fill(DevGeom g, const int32_t *tiles, const int32_t *rowpt
     }
 }
 
+// one workgroup per copy descriptor: FP64 source block -> value pool (cast)
 template <class T>
-__global__ void k_copy_cast(const double *src, int64_t rows, int64_t cols, int64_t lds, T *dst, int64_t ldd) {
-    int64_t tot = rows * cols;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-        int64_t c = e / rows, r = e - c * rows;
-        dst[r + c * ldd] = cast_to<T>(src[r + c * lds]);
+__global__ void k_copy_batched(const CopyDesc *d, T *vals) {
+    const CopyDesc c = d[blockIdx.x];
+    T *dst = vals + c.dst_off;
+    const int64_t tot = (int64_t)c.rows * c.cols;
+    for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+        int64_t col = e / c.rows, r = e - col * c.rows;
+        dst[r + col * c.ldd] = cast_to<T>(c.src[r + col * c.lds]);
     }
 }
 
@@ -390,16 +395,15 @@ void launch_csr_fill(const DevGeom &g, const int32_t *tiles, int64_t ntiles, con
     RAD_HIP(hipGetLastError());
 }
 
-void launch_copy_cast(const double *src, int64_t rows, int64_t cols, int64_t lds, void *dst, int64_t ldd,
-                      int32_t dtype, hipStream_t s) {
-    int64_t tot = rows * cols;
-    if (tot <= 0) return;
-    unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 4096);
-    if (dtype == RAD_F64)
-        hipLaunchKernelGGL(k_copy_cast<double>, dim3(blocks), dim3(256), 0, s, src, rows, cols, lds, (double *)dst, ldd);
-    else
-        hipLaunchKernelGGL(k_copy_cast<float>, dim3(blocks), dim3(256), 0, s, src, rows, cols, lds, (float *)dst, ldd);
-    RAD_HIP(hipGetLastError());
+void launch_copy_batched(const CopyDesc *d, int64_t n, void *vals, int32_t dtype, hipStream_t s) {
+    for (int64_t b0 = 0; b0 < n; b0 += (int64_t)1 << 30) {
+        unsigned nb = (unsigned)std::min<int64_t>(n - b0, (int64_t)1 << 30);
+        if (dtype == RAD_F64)
+            hipLaunchKernelGGL(k_copy_batched<double>, dim3(nb), dim3(256), 0, s, d + b0, (double *)vals);
+        else
+            hipLaunchKernelGGL(k_copy_batched<float>, dim3(nb), dim3(256), 0, s, d + b0, (float *)vals);
+        RAD_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace rad

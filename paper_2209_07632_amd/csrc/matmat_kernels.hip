@@ -21,7 +21,7 @@ namespace {
 
 constexpr int TM = 64;    // output rows per workgroup
 constexpr int TN = 128;   // output columns (right-hand sides) per workgroup
-constexpr int KC = 32;    // reduction chunk
+constexpr int KC = 16;    // reduction chunk
 constexpr int PADA = 4, PADB = 4;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -198,6 +198,73 @@ struct Stage {
     }
 };
 
+// Chunk of a packed panel (64 x KC contiguous, ld 64) and of the operand rows
+// it multiplies (gathered through brow: X row if >= 0, T row -1-v if < 0).
+template <class T>
+struct PanelStage {
+    T a[KC * TM / 256];
+    T b[KC * TN / 256];
+    __device__ __forceinline__ void fetch(const T *pan, const int32_t *brc, const T *X, const T *Tb, int64_t ldr, int r0,
+                                          int R, int t) {
+#pragma unroll
+        for (int q = 0; q < KC * TM / 1024; ++q) {
+            const T *p = pan + 4 * (t + q * 256);
+            if constexpr (sizeof(T) == 4) {
+                float4 v = *(const float4 *)p;
+                a[4 * q] = v.x; a[4 * q + 1] = v.y; a[4 * q + 2] = v.z; a[4 * q + 3] = v.w;
+            } else {
+                double2 v0 = *(const double2 *)p, v1 = *(const double2 *)(p + 2);
+                a[4 * q] = v0.x; a[4 * q + 1] = v0.y; a[4 * q + 2] = v1.x; a[4 * q + 3] = v1.y;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KC * TN / 1024; ++q) {
+            int e = t + q * 256;
+            int k = e / (TN / 4), c = (e - k * (TN / 4)) * 4;
+            int32_t v = brc[k];
+            const T *p = (v >= 0 ? X + (int64_t)v * ldr : Tb + (int64_t)(-1 - v) * ldr) + r0 + c;
+            T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+            if (r0 + c + 3 < R) {
+                if constexpr (sizeof(T) == 4) {
+                    float4 qv = *(const float4 *)p;
+                    v0 = qv.x; v1 = qv.y; v2 = qv.z; v3 = qv.w;
+                } else {
+                    double2 q0 = *(const double2 *)p, q1 = *(const double2 *)(p + 2);
+                    v0 = q0.x; v1 = q0.y; v2 = q1.x; v3 = q1.y;
+                }
+            } else {
+                if (r0 + c < R) v0 = p[0];
+                if (r0 + c + 1 < R) v1 = p[1];
+                if (r0 + c + 2 < R) v2 = p[2];
+            }
+            b[4 * q] = v0;
+            b[4 * q + 1] = v1;
+            b[4 * q + 2] = v2;
+            b[4 * q + 3] = v3;
+        }
+    }
+    __device__ __forceinline__ void commit(T (*sA)[TM + PADA], T (*sB)[TN + PADB], int t) {
+#pragma unroll
+        for (int q = 0; q < KC * TM / 1024; ++q) {
+            int e = 4 * (t + q * 256);
+            int k = e / TM, r = e - k * TM;
+            sA[k][r] = a[4 * q];
+            sA[k][r + 1] = a[4 * q + 1];
+            sA[k][r + 2] = a[4 * q + 2];
+            sA[k][r + 3] = a[4 * q + 3];
+        }
+#pragma unroll
+        for (int q = 0; q < KC * TN / 1024; ++q) {
+            int e = t + q * 256;
+            int k = e / (TN / 4), c = (e - k * (TN / 4)) * 4;
+            sB[k][c] = b[4 * q];
+            sB[k][c + 1] = b[4 * q + 1];
+            sB[k][c + 2] = b[4 * q + 2];
+            sB[k][c + 3] = b[4 * q + 3];
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // phase 1: partial projections
 // ---------------------------------------------------------------------------
@@ -258,24 +325,28 @@ __global__ void __launch_bounds__(256) k_proj_reduce(const P1Red *red, const T *
 // writes the per-column partial sums of (B_new - B_old)^2 for this tile.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(256) k_tile_mm(const int32_t *tile_ptr, const TileTask *tasks, const T *vals,
-                                                  const int32_t *csr_ptr, const int32_t *csr_idx,
+__global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
+                                                  const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
                                                   int64_t csr_val_start, const T *X, const T *Tb, int64_t ldr, int R,
                                                   int64_t N, T *Y, const T *E, const T *rho, T rho_s,
                                                   double *partial) {
     const int tile = blockIdx.x;
+    const TileInfo ti = tiles[tile];
     const int64_t tile0 = (int64_t)tile * TM;
     const int r0 = blockIdx.y * TN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    __shared__ T sA[2][KC][TM + PADA];
-    __shared__ T sB[2][KC][TN + PADB];
+    // pipeline buffers during the reduction, the 64 x 128 result tile after it
+    constexpr int kPipe = 2 * KC * (TM + PADA) + 2 * KC * (TN + PADB);
+    constexpr int kOut = TM * (TN + PADB);
+    __shared__ T smem[kPipe > kOut ? kPipe : kOut];
+    static_assert(8 * TN * sizeof(double) <= sizeof(T) * (kPipe > kOut ? kPipe : kOut), "partial sums fit");
+    T (*sA)[KC][TM + PADA] = (T (*)[KC][TM + PADA])smem;
+    T (*sB)[KC][TN + PADB] = (T (*)[KC][TN + PADB])(smem + 2 * KC * (TM + PADA));
     Tile<T> acc;
     acc.zero();
-    const int tb = tile_ptr[tile], te = tile_ptr[tile + 1];
     // CSR tasks: rows expanded into dense chunks in LDS
-    for (int ti = tb; ti < te; ++ti) {
-        const TileTask tk = tasks[ti];
-        if (tk.type != TASK_CSR) continue;
+    for (int c = ti.csr_begin; c < ti.csr_end; ++c) {
+        const TileTask tk = ctasks[c];
         const T *v = vals + tk.a_off;
         const int32_t *ci = csr_idx + (tk.a_off - csr_val_start);
         int cur = 0, end = 0;
@@ -297,67 +368,114 @@ __global__ void __launch_bounds__(256) k_tile_mm(const int32_t *tile_ptr, const 
             __syncthreads();
         }
     }
-    // dense and low-rank tasks: flattened chunk sequence, software pipelined
-    int ti = tb, kb = 0;
-    auto skip_csr = [&]() {
-        while (ti < te && tasks[ti].type == TASK_CSR) ++ti;
-    };
-    skip_csr();
-    if (ti < te) {
-        Stage<T> st;
-        TileTask tk = tasks[ti];
-        st.fetch(0, vals + tk.a_off, tk.ld, tk.row_off, tk.r_lo, tk.r_hi, 0, min(KC, tk.ncol),
-                 tk.type == TASK_DENSE ? X : Tb, tk.col0, ldr, r0, R, t);
+    // packed panel: software-pipelined chunks
+    if (ti.kpad > 0) {
+        const T *pan = vals + ti.panel_off;
+        const int32_t *br = brow + ti.brow_off;
+        PanelStage<T> st;
+        st.fetch(pan, br, X, Tb, ldr, r0, R, t);
         int buf = 0;
-        while (true) {
-            st.commit(0, sA[buf], sB[buf], t);
+        for (int kb = 0; kb < ti.kpad; kb += KC) {
+            st.commit(sA[buf], sB[buf], t);
             __syncthreads();
-            // advance to the next chunk and prefetch it
-            kb += KC;
-            if (kb >= tk.ncol) {
-                ++ti;
-                kb = 0;
-                skip_csr();
-            }
-            const bool more = ti < te;
-            if (more) {
-                tk = tasks[ti];
-                st.fetch(0, vals + tk.a_off, tk.ld, tk.row_off, tk.r_lo, tk.r_hi, kb, min(KC, tk.ncol - kb),
-                         tk.type == TASK_DENSE ? X : Tb, (int64_t)tk.col0 + kb, ldr, r0, R, t);
-            }
+            if (kb + KC < ti.kpad) st.fetch(pan + (int64_t)(kb + KC) * TM, br + kb + KC, X, Tb, ldr, r0, R, t);
             acc.mma(sA[buf], sB[buf], lane, w);
             buf ^= 1;
-            if (!more) break;
         }
     }
-    const int lr = lane & 15, lk = lane >> 4;
-    const int rows = (int)min((int64_t)TM, N - tile0);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int col = r0 + w * 32 + j * 16 + lr;
-        double d2 = 0.0;
+    // epilogue through LDS: the 64 x 128 result tile is written to LDS, then
+    // every thread streams 16-byte groups of whole rows (coalesced E, B_old,
+    // B_new accesses).  Per-column partial sums are reduced in a fixed order.
+    __syncthreads();
+    T (*sC)[TN + PADB] = (T (*)[TN + PADB])smem;
+    {
+        const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = i * 16 + Mfma<T>::row(lk, v);
-                if (row < rows && col < R) {
-                    const int64_t e = (tile0 + row) * ldr + col;
-                    T y = acc.acc[i][j][v];
-                    if (E) {
-                        T rh = rho ? rho[tile0 + row] : rho_s;
-                        T bn = E[e] + rh * y;
-                        double d = (double)bn - (double)X[e];
-                        d2 += d * d;
-                        y = bn;
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sC[i * 16 + Mfma<T>::row(lk, v)][w * 32 + j * 16 + lr] = acc.acc[i][j][v];
+    }
+    __syncthreads();
+    const int rows = (int)min((int64_t)TM, N - tile0);
+    const int c4 = (t & 31) * 4;          // this thread's four columns
+    const int rsub = t >> 5;              // rows rsub, rsub + 8, ...
+    const int col = r0 + c4;
+    double d2[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool full = col + 3 < R;
+    // rows rsub + 8q in two halves of four: all loads of a half first, then
+    // the arithmetic and the stores
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        T ev[4][4], bo[4][4];
+        if (E) {
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int row = rsub + 8 * (4 * half + qq);
+                const int64_t e = (tile0 + row) * ldr + col;
+                if (row < rows && full) {
+                    if constexpr (sizeof(T) == 4) {
+                        float4 a = *(const float4 *)(E + e), o = *(const float4 *)(X + e);
+                        ev[qq][0] = a.x; ev[qq][1] = a.y; ev[qq][2] = a.z; ev[qq][3] = a.w;
+                        bo[qq][0] = o.x; bo[qq][1] = o.y; bo[qq][2] = o.z; bo[qq][3] = o.w;
+                    } else {
+                        double2 a0 = *(const double2 *)(E + e), a1 = *(const double2 *)(E + e + 2);
+                        double2 o0 = *(const double2 *)(X + e), o1 = *(const double2 *)(X + e + 2);
+                        ev[qq][0] = a0.x; ev[qq][1] = a0.y; ev[qq][2] = a1.x; ev[qq][3] = a1.y;
+                        bo[qq][0] = o0.x; bo[qq][1] = o0.y; bo[qq][2] = o1.x; bo[qq][3] = o1.y;
                     }
-                    Y[e] = y;
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        bool ok = row < rows && col + u < R;
+                        ev[qq][u] = ok ? E[e + u] : (T)0;
+                        bo[qq][u] = ok ? X[e + u] : (T)0;
+                    }
                 }
             }
-        if (E) {
-            d2 += __shfl_xor(d2, 16, 64);
-            d2 += __shfl_xor(d2, 32, 64);
-            if (lk == 0 && col < R) partial[(int64_t)tile * R + col] = d2;
+        }
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int row = rsub + 8 * (4 * half + qq);
+            if (row < rows) {
+                const int64_t e = (tile0 + row) * ldr + col;
+                T y[4] = {sC[row][c4], sC[row][c4 + 1], sC[row][c4 + 2], sC[row][c4 + 3]};
+                if (E) {
+                    T rh = rho ? rho[tile0 + row] : rho_s;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        T bn = ev[qq][u] + rh * y[u];
+                        double d = (double)bn - (double)bo[qq][u];
+                        if (col + u < R) d2[u] += d * d;
+                        y[u] = bn;
+                    }
+                }
+                if (full) {
+                    if constexpr (sizeof(T) == 4) {
+                        *(float4 *)(Y + e) = make_float4(y[0], y[1], y[2], y[3]);
+                    } else {
+                        *(double2 *)(Y + e) = make_double2(y[0], y[1]);
+                        *(double2 *)(Y + e + 2) = make_double2(y[2], y[3]);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (col + u < R) Y[e + u] = y[u];
+                }
+            }
+        }
+    }
+    if (E) {
+        __syncthreads();
+        double *red = (double *)smem;   // 8 x 128 partial sums (fits in the LDS tile)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) red[rsub * TN + c4 + u] = d2[u];
+        __syncthreads();
+        if (t < TN) {
+            double sum = 0.0;
+            for (int q = 0; q < 8; ++q) sum += red[q * TN + t];
+            if (r0 + t < R) partial[(int64_t)tile * R + r0 + t] = sum;
         }
     }
 }
@@ -459,8 +577,8 @@ void apply_mm_t(const rad_hmat *H, const T *X, T *Y, int64_t ldr, int R, const T
                 double *partial, hipStream_t s) {
     proj_mm_t<T>(H, X, ldr, R, s);
     unsigned rtiles = (unsigned)((R + TN - 1) / TN);
-    hipLaunchKernelGGL(k_tile_mm<T>, dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tile_ptr.p, H->d_tile_tasks.p,
-                       (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p, H->csr_val_start, X,
+    hipLaunchKernelGGL(k_tile_mm<T>, dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
+                       H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p, H->csr_val_start, X,
                        (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial);
     RAD_HIP(hipGetLastError());
 }
@@ -515,6 +633,59 @@ void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rh
                           (float)rho_scalar, part, s);
     hipLaunchKernelGGL(k_reduce_rm, dim3((unsigned)((R + 15) / 16)), dim3(256), 0, s, part, H->n_tiles, (int)R, norms);
     RAD_HIP(hipGetLastError());
+}
+
+template <class T>
+void time_phases_t(const rad_hmat *H, int R, int nrep, hipStream_t s, double *ms) {
+    const int64_t ldr = mm_ldr(R);
+    const T *X = (const T *)H->w_x.p;
+    T *Y = (T *)H->w_b.p;
+    const T *E = (const T *)H->w_e.p;
+    double *part = (double *)H->w_red.p;
+    unsigned rtiles = (unsigned)((R + TN - 1) / TN);
+    hipEvent_t e0, e1;
+    RAD_HIP(hipEventCreate(&e0));
+    RAD_HIP(hipEventCreate(&e1));
+    float t = 0;
+    ms[0] = ms[1] = ms[2] = 0.0;
+    if (H->n_p1work > 0) {
+        RAD_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < nrep; ++i)
+            hipLaunchKernelGGL(k_proj_mm<T>, dim3(H->n_p1work, rtiles), dim3(256), 0, s, H->d_groups.p,
+                               H->d_p1work.p, (const T *)H->d_vals.p, X, ldr, R, (T *)H->w_part.p);
+        RAD_HIP(hipEventRecord(e1, s));
+        RAD_HIP(hipEventSynchronize(e1));
+        RAD_HIP(hipEventElapsedTime(&t, e0, e1));
+        ms[0] = t / nrep;
+        RAD_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < nrep; ++i)
+            hipLaunchKernelGGL(k_proj_reduce<T>, dim3(H->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s,
+                               H->d_p1red.p, (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p);
+        RAD_HIP(hipEventRecord(e1, s));
+        RAD_HIP(hipEventSynchronize(e1));
+        RAD_HIP(hipEventElapsedTime(&t, e0, e1));
+        ms[1] = t / nrep;
+    }
+    RAD_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < nrep; ++i)
+        hipLaunchKernelGGL(k_tile_mm<T>, dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
+                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
+                           H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, (const T *)nullptr, (T)0.3,
+                           part);
+    RAD_HIP(hipEventRecord(e1, s));
+    RAD_HIP(hipEventSynchronize(e1));
+    RAD_HIP(hipEventElapsedTime(&t, e0, e1));
+    ms[2] = t / nrep;
+    RAD_HIP(hipGetLastError());
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+void mm_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, double *ms) {
+    if (H->dtype == RAD_F64)
+        time_phases_t<double>(H, (int)R, nrep, s, ms);
+    else
+        time_phases_t<float>(H, (int)R, nrep, s, ms);
 }
 
 size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R) {

@@ -55,50 +55,53 @@ __global__ void __launch_bounds__(256) k_proj(const ProjGroup *groups, const T *
     }
 }
 
-// phase 2: one workgroup per (leaf, right-hand side); wave w takes tasks w, w+4, ...
-// Leaves larger than 64 rows (depth limit, coincident centroids) are walked in
-// chunks of 64 rows.
+// phase 2: one workgroup per (64-row tile, right-hand side).  Lane = row of
+// the tile; wave w takes panel columns w, w+4, ... (each a contiguous 64-row
+// column of the packed panel) and CSR tasks w, w+4, ...; the four partial
+// results meet in LDS.
 template <class T>
-__global__ void __launch_bounds__(256) k_leaf(const LeafInfo *leaves, const LeafTask *tasks, const T *vals,
-                                               const int32_t *csr_ptr, const int32_t *csr_idx, int64_t csr_val_start,
-                                               const T *X, int64_t ldx, const T *Tb, int32_t t_ld, T *Y, int64_t ldy) {
-    const LeafInfo L = leaves[blockIdx.x];
+__global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
+                                                    const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
+                                                    int64_t csr_val_start, const T *X, int64_t ldx, const T *Tb,
+                                                    int32_t t_ld, int64_t N, T *Y, int64_t ldy) {
+    const int tile = blockIdx.x;
+    const TileInfo ti = tiles[tile];
     const int64_t r = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const T *x = X + r * ldx;
     const T *tb = Tb + r * t_ld;
-    __shared__ T red[4][64];
-    for (int rb = 0; rb < L.size; rb += 64) {
-        const int row = rb + lane;
-        T acc = 0;
-        if (row < L.size) {
-            for (int ti = L.task_begin + w; ti < L.task_end; ti += 4) {
-                const LeafTask tk = tasks[ti];
-                if (tk.type == TASK_DENSE) {
-                    const T *a = vals + tk.a_off + row;
-                    const T *xc = x + tk.col0;
-                    for (int c = 0; c < tk.ncol; ++c) acc += a[(int64_t)c * tk.ld] * xc[c];
-                } else if (tk.type == TASK_LOWRANK) {
-                    const T *a = vals + tk.a_off + row;
-                    const T *tc = tb + tk.col0;
-                    for (int k = 0; k < tk.ncol; ++k) acc += a[(int64_t)k * tk.ld] * tc[k];
-                } else {
-                    const int32_t *ptr = csr_ptr + tk.aux_off;
-                    const T *v = vals + tk.a_off;
-                    const int32_t *ci = csr_idx + (tk.a_off - csr_val_start);
-                    const T *xc = x + tk.col0;
-                    for (int e = ptr[row]; e < ptr[row + 1]; ++e) acc += v[e] * xc[ci[e]];
-                }
-            }
-        }
-        red[w][lane] = acc;
-        __syncthreads();
-        if (w == 0 && row < L.size) {
-            T s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-            Y[L.start + row + r * ldy] = s;
-        }
-        __syncthreads();
+    const T *panel = vals + ti.panel_off + lane;
+    const int32_t *br = brow + ti.brow_off;
+    T acc = 0;
+    int k = w;
+    for (; k + 12 < ti.kpad; k += 16) {
+        T a0 = panel[(int64_t)k * 64], a1 = panel[(int64_t)(k + 4) * 64];
+        T a2 = panel[(int64_t)(k + 8) * 64], a3 = panel[(int64_t)(k + 12) * 64];
+        int32_t b0 = br[k], b1 = br[k + 4], b2 = br[k + 8], b3 = br[k + 12];
+        acc += a0 * (b0 >= 0 ? x[b0] : tb[-1 - b0]);
+        acc += a1 * (b1 >= 0 ? x[b1] : tb[-1 - b1]);
+        acc += a2 * (b2 >= 0 ? x[b2] : tb[-1 - b2]);
+        acc += a3 * (b3 >= 0 ? x[b3] : tb[-1 - b3]);
     }
+    for (; k < ti.kpad; k += 4) {
+        int32_t b0 = br[k];
+        acc += panel[(int64_t)k * 64] * (b0 >= 0 ? x[b0] : tb[-1 - b0]);
+    }
+    for (int c = ti.csr_begin + w; c < ti.csr_end; c += 4) {
+        const TileTask tk = ctasks[c];
+        if (lane >= tk.r_lo && lane < tk.r_hi) {
+            const int32_t *ptr = csr_ptr + tk.aux_off + tk.row_off + lane;
+            const T *v = vals + tk.a_off;
+            const int32_t *ci = csr_idx + (tk.a_off - csr_val_start);
+            const T *xc = x + tk.col0;
+            for (int e = ptr[0]; e < ptr[1]; ++e) acc += v[e] * xc[ci[e]];
+        }
+    }
+    __shared__ T red[4][64];
+    red[w][lane] = acc;
+    __syncthreads();
+    const int64_t row = (int64_t)tile * 64 + lane;
+    if (w == 0 && row < N) Y[row + r * ldy] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
 }
 
 // B_new = E + rho * FB; partial[col][block] = sum (B_new - B_old)^2
@@ -156,9 +159,10 @@ void apply_t(const rad_hmat *H, const T *X, int64_t ldx, T *Y, int64_t ldy, int6
                            H->t_ld);
         RAD_HIP(hipGetLastError());
     }
-    dim3 grid2(H->n_leaves, (unsigned)R);
-    hipLaunchKernelGGL(k_leaf<T>, grid2, dim3(256), 0, s, H->d_leaves.p, H->d_tasks.p, (const T *)H->d_vals.p,
-                       H->d_csr_ptr.p, H->d_csr_idx.p, H->csr_val_start, X, ldx, (const T *)Tb, H->t_ld, Y, ldy);
+    dim3 grid2(H->n_tiles, (unsigned)R);
+    hipLaunchKernelGGL(k_tile_gemv<T>, grid2, dim3(256), 0, s, H->d_tiles.p, H->d_brow.p, H->d_tile_tasks.p,
+                       (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p, H->csr_val_start, X, ldx,
+                       (const T *)Tb, H->t_ld, H->N, Y, ldy);
     RAD_HIP(hipGetLastError());
 }
 

@@ -113,20 +113,31 @@ struct SketchBlock {
     uint64_t seed;
 };
 
-// Phase-2 task of one row leaf.
 enum TaskType : int32_t { TASK_DENSE = 0, TASK_CSR = 1, TASK_LOWRANK = 2 };
-struct LeafTask {
-    int32_t type;
-    int32_t ncol;          // dense/CSR: columns n of the block; low-rank: rank k
-    int32_t ld;            // leading dimension of the slice (dense, low-rank)
-    int32_t col0;          // first column (tree order) of the block (dense/CSR) or T row offset (low-rank)
-    int64_t a_off;         // value offset of the slice (dense/low-rank) or of the CSR values base
-    int64_t aux_off;       // CSR: offset of this slice's row pointers (int32, m_L+1 entries)
+
+// One 64-row tile of the tree order: its packed panel of dense and U' rows
+// (64 x kpad, column-major, ld 64, kpad a multiple of 32) with the operand
+// row of each panel column in brow[brow_off + k] (X row if >= 0, T row
+// -1 - v if < 0), and its CSR tasks [csr_begin, csr_end).
+struct TileInfo {
+    int64_t panel_off;
+    int64_t brow_off;
+    int32_t kpad;
+    int32_t csr_begin, csr_end;
+    int32_t pad_;
 };
 
-// Task of one 64-row tile of the multi-RHS kernels: rows [r_lo, r_hi) of the
-// tile are block rows row_off + r of a block stored column-major (ld = block
-// rows) at a_off; CSR blocks keep row pointers at aux_off (relative to a_off).
+// Batched copy-with-cast of a column-major FP64 block into the value pool.
+struct CopyDesc {
+    const double *src;
+    int64_t dst_off;
+    int32_t rows, cols;
+    int32_t lds, ldd;
+};
+
+// CSR task of one 64-row tile: rows [r_lo, r_hi) of the tile are block rows
+// row_off + r; row pointers at aux_off are relative to the value base a_off;
+// column indices (local to the block) at a_off - csr_val_start.
 struct TileTask {
     int32_t type;
     int32_t ncol;
@@ -161,11 +172,6 @@ struct P1Red {
     int32_t t_row0, nrows, part_begin, part_count;
 };
 
-struct LeafInfo {
-    int32_t start, size;   // rows (tree order)
-    int32_t task_begin, task_end;
-};
-
 }  // namespace rad
 
 // Opaque matrix handle (device-resident operator + host metadata).
@@ -184,17 +190,13 @@ struct rad_hmat {
     rad::DevBuf<unsigned char> d_vals; // value pool (dtype)
     rad::DevBuf<int32_t> d_csr_idx;    // CSR column indices (local to the block)
     rad::DevBuf<int32_t> d_csr_ptr;    // CSR row pointers per leaf slice
-    rad::DevBuf<rad::LeafTask> d_tasks;
-    rad::DevBuf<rad::LeafInfo> d_leaves;
     rad::DevBuf<rad::ProjGroup> d_groups;
     int32_t n_leaves = 0, n_groups = 0, t_rows = 0, t_ld = 0;
-    int32_t max_leaf_rows = 0;
     int64_t csr_val_start = 0;
-    std::vector<rad::LeafInfo> h_leaves;
-    std::vector<rad::LeafTask> h_tasks;
     std::vector<rad::ProjGroup> h_groups;
     rad::DevBuf<rad::TileTask> d_tile_tasks;
-    rad::DevBuf<int32_t> d_tile_ptr;
+    rad::DevBuf<rad::TileInfo> d_tiles;
+    rad::DevBuf<int32_t> d_brow;
     int32_t n_tiles = 0;
     rad::DevBuf<rad::P1Work> d_p1work;
     rad::DevBuf<rad::P1Red> d_p1red;
@@ -247,8 +249,7 @@ void launch_csr_count(const DevGeom &g, const int32_t *tiles, int64_t ntiles, in
 void launch_csr_fill(const DevGeom &g, const int32_t *tiles, int64_t ntiles, const int32_t *rowptr,
                      const int64_t *row_offs, const int64_t *val_base, void *vals, int32_t *cols,
                      int32_t dtype, hipStream_t s);
-void launch_copy_cast(const double *src, int64_t rows, int64_t cols, int64_t lds, void *dst,
-                      int64_t ldd, int32_t dtype, hipStream_t s);
+void launch_copy_batched(const CopyDesc *d, int64_t n, void *vals, int32_t dtype, hipStream_t s);
 // ray casting (raycast.hip)
 void build_grid(rad_hmat *H, const std::vector<double> &tri);
 void launch_vis_grid(const rad_hmat *H, uint32_t *bits, int64_t wpr, hipStream_t s);
@@ -277,5 +278,6 @@ void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, dou
 void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
                     int64_t ldr, int64_t R, double *norms, hipStream_t s);
 size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R);
+void mm_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, double *ms);
 
 }  // namespace rad

@@ -52,14 +52,15 @@ class Stats(ctypes.Structure):
                 ("n_lowrank", ctypes.c_int64), ("n_zero", ctypes.c_int64), ("bytes_dense", ctypes.c_int64),
                 ("bytes_csr", ctypes.c_int64), ("bytes_lowrank", ctypes.c_int64), ("bytes_total", ctypes.c_int64),
                 ("nnz_near", ctypes.c_int64), ("sum_rank", ctypes.c_int64), ("lowrank_elems", ctypes.c_int64),
-                ("max_rank", ctypes.c_int32), ("build_seconds", ctypes.c_double), ("flops_per_rhs", ctypes.c_double)]
+                ("max_rank", ctypes.c_int32), ("build_seconds", ctypes.c_double), ("flops_per_rhs", ctypes.c_double),
+                ("lowrank_row_elems", ctypes.c_int64), ("lowrank_col_elems", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_matvec", "rad_solve_opts_default", "rad_solve",
-           "rad_insolation", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free",
+           "rad_insolation", "rad_hmat_time_phases", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free",
            "rad_last_error"]
 
 _lib = None
@@ -90,6 +91,8 @@ def load(path: str = LIB_PATH):
     L.rad_insolation.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_double, ctypes.c_int32, vp, ctypes.c_int64,
                                  ctypes.c_int32, vp]
     L.rad_insolation.restype = ctypes.c_int
+    L.rad_hmat_time_phases.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
+    L.rad_hmat_time_phases.restype = ctypes.c_int
     L.rad_hmat_info.argtypes = [vp, ctypes.POINTER(Stats)]
     L.rad_hmat_info.restype = ctypes.c_int
     L.rad_hmat_n.argtypes = [vp]
@@ -245,6 +248,12 @@ class HMatrix:
         if Qc.data_ptr() != out.data_ptr():
             out.copy_(Qc)
         return out
+
+    def time_phases(self, R, nrep=20):
+        """Average ms per launch of (projections, split-K sum, expansion + Jacobi update)."""
+        ms = (ctypes.c_double * 3)()
+        _check(load().rad_hmat_time_phases(self._h, int(R), int(nrep), _stream_handle(), ms))
+        return list(ms)
 
     def close(self):
         if getattr(self, "_h", None):
