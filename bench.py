@@ -84,15 +84,18 @@ def main():
     build_s = time.perf_counter() - t0
     st = H.stats()
     log(f"built in {build_s:.2f} s: {st}")
+    # right-hand sides written directly in the library's internal layout
+    # (tree order, right-hand-side-minor), where the solve also leaves B
     t0 = time.perf_counter()
-    Q = H.insolation(suns, flux=S)
+    Q = H.insolation(suns, flux=S, order="tree_rmajor")
     torch.cuda.synchronize()
     log(f"insolation {time.perf_counter() - t0:.2f} s")
     E = albedo * Q
-    B = torch.empty_like(E)
+    B = torch.zeros_like(E)
+    perm = H.perm()
 
     def step():
-        _, info = H.solve(E, rho=albedo, rtol=args.rtol, out=B)
+        _, info = H.solve(E, rho=albedo, rtol=args.rtol, out=B, order="tree_rmajor", R=R)
         return info
 
     for _ in range(args.warmup):
@@ -110,16 +113,16 @@ def main():
     log(f"{ms_per_step:.3f} ms/step, {solves_per_s:.1f} solves/s, {iters} iterations")
 
     # H-matvec timing (tree order, all R columns) with events on the launch stream
-    X = torch.rand((R, N), dtype=E.dtype, device=dev).t()
-    Y = torch.empty_like(X)
+    X = torch.rand(E.shape, dtype=E.dtype, device=dev)
+    Y = torch.zeros_like(X)
     for _ in range(3):
-        H.matvec(X, out=Y, order="tree")
+        H.matvec(X, out=Y, order="tree_rmajor", R=R)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     nrep = 20
     ev0.record(stream)
     for _ in range(nrep):
-        H.matvec(X, out=Y, order="tree")
+        H.matvec(X, out=Y, order="tree_rmajor", R=R)
     ev1.record(stream)
     ev1.synchronize()
     mv_ms = ev0.elapsed_time(ev1) / nrep
@@ -161,7 +164,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         cols = list(range(args.cpu_cols))
-        Bc = B.double().cpu().numpy()[:, cols]
+        Bt = B.double().cpu().numpy()[:, :R]
+        Bo = np.empty_like(Bt)
+        Bo[perm] = Bt
+        Bc = Bo[:, cols]
         log("CPU reference on sampled columns ...")
         cb, err, it = cpu_baseline(verts, faces, suns, albedo, Bc, cols, S)
         result["cpu_baseline"] = cb

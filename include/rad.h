@@ -58,7 +58,16 @@ typedef enum {
     RAD_NEAR_CSR = 2    /* always CSR                                        */
 } rad_nearfield;
 
-typedef enum { RAD_ORDER_ORIGINAL = 0, RAD_ORDER_TREE = 1 } rad_order;
+/*
+ * Layout of vectors and blocks of right-hand sides:
+ *  RAD_ORDER_ORIGINAL: column-major N x R, rows in the caller's face order;
+ *  RAD_ORDER_TREE: column-major N x R, rows in tree order (rad_hmat_perm);
+ *  RAD_ORDER_TREE_RMAJOR: the library's internal layout, rows in tree order
+ *      with the R values of a facet contiguous: element (t, r) at t * ld + r,
+ *      where ld must equal R rounded up to a multiple of 4 and the pointer must
+ *      be 16-byte aligned.  No layout conversion is done on this path.
+ */
+typedef enum { RAD_ORDER_ORIGINAL = 0, RAD_ORDER_TREE = 1, RAD_ORDER_TREE_RMAJOR = 2 } rad_order;
 
 typedef struct {
     double tol;           /* compression tolerance eps of Algorithm 3 (> 0)           */
@@ -94,9 +103,9 @@ rad_status rad_hmat_build(const double *verts, int64_t nv, const int32_t *faces,
 
 /*
  * Y = F-hat X (Algorithm 5) for R right-hand sides.  X and Y are device
- * arrays, column-major with leading dimensions ldx, ldy >= N, of the
- * matrix's compute dtype (rad_hmat_dtype).  X and Y must not overlap.
- * order: rad_order of the rows of X and Y.  1 <= R <= max_rhs.
+ * arrays of the matrix's compute dtype (rad_hmat_dtype) in the layout named
+ * by order (rad_order; leading dimensions ldx, ldy as that layout requires).
+ * X and Y must not overlap.  1 <= R <= max_rhs.
  * Errors: RAD_EINVAL (null, R out of range, ld < N, dtype mismatch), RAD_EDEVICE.
  */
 rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const void *X, int64_t ldx,
@@ -107,6 +116,7 @@ typedef struct {
     int32_t max_iter; /* default 100                                                     */
     int32_t order;    /* rad_order of E and B                                            */
     int32_t check_every; /* read residuals back every this many iterations (default 1) */
+    int32_t use_graph;   /* 1: replay each iteration as a cached HIP graph (default 1) */
 } rad_solve_opts;
 
 void rad_solve_opts_default(rad_solve_opts *opts);
@@ -121,9 +131,11 @@ typedef struct {
  * Solves (I - diag(rho) F-hat) B = E, the radiosity system eq.
  * radiosity-system, for R right-hand sides by Jacobi relaxation
  * B^{k+1} = E + rho (F-hat B^k), B^0 = E (sections 3 and 5.1).
- * rho: device array of N reflectances in the order of E, or NULL to use
- * rho_scalar for every facet.  E and B are device arrays (compute dtype,
- * column-major, ld >= N) and may not overlap.
+ * rho: device array of N reflectances (original order for RAD_ORDER_ORIGINAL,
+ * tree order otherwise), or NULL to use rho_scalar for every facet.  E and B
+ * are device arrays of the compute dtype in the layout opts->order names; they
+ * may not overlap.  With RAD_ORDER_TREE_RMAJOR, lde and ldb must both equal
+ * R rounded up to a multiple of 4.
  * Errors: RAD_EINVAL, RAD_ENOCONV (B holds the last iterate, info filled),
  * RAD_EDEVICE.
  */
@@ -138,7 +150,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
  * where V_sun(i, k) = 1 when the ray x_i + t s_k, t > 1e-9, hits no mesh
  * triangle other than facet i.  suns: host array, R x 3 row-major unit vectors
  * (direction towards the sun).  flux = S / d^2 in W/m^2 (d in AU).
- * Q: device, column-major N x R (ldq >= N), compute dtype of H.
+ * Q: device, layout named by order (rad_order), compute dtype of H.
  * Runs asynchronously on hip_stream except for the upload of suns.
  * Errors: RAD_EINVAL (null, R < 1, non-finite or zero-length direction,
  * ld < N, dtype mismatch), RAD_ENOMEM, RAD_EDEVICE.

@@ -29,6 +29,66 @@ static void alloc_workspace(rad_hmat *H) {
     H->w_norms.alloc((size_t)3 * H->max_rhs);
     if (H->max_rhs >= kMfmaMinRhs && H->n_parts > 0)
         H->w_part.alloc((size_t)H->n_parts * mm_part_rows() * ldr * s);
+    RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * (size_t)H->max_rhs, hipHostMallocDefault));
+    RAD_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
+}
+
+// One Jacobi iteration, enqueued on stream s: B_new = E + rho (F-hat B_old),
+// the squared column changes in w_norms[max_rhs...], copied to pinned memory.
+struct IterArgs {
+    bool mm;
+    int64_t R, ld;
+    const void *E, *rho, *Bold;
+    void *Bnew;
+    double rho_s;
+};
+
+static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t s) {
+    double *dn = H->w_norms.p + H->max_rhs;
+    if (a.mm) {
+        mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s);
+    } else {
+        mv_apply(H, a.Bold, a.ld, H->w_y.p, a.ld, a.R, s);
+        solve_update(H, a.E, a.rho, a.rho_s, H->w_y.p, a.Bold, a.Bnew, a.ld, a.R, dn, s);
+    }
+    RAD_HIP(hipMemcpyAsync(H->h_norms, dn, sizeof(double) * a.R, hipMemcpyDeviceToHost, s));
+}
+
+// Cached graph of one iteration (captured on the library's own stream,
+// launched on the caller's); the cache is keyed by every captured argument.
+static hipGraphExec_t iteration_graph(rad_hmat *H, const IterArgs &a) {
+    for (auto &g : H->graphs)
+        if (g.path == (int)a.mm && g.R == a.R && g.Bold == a.Bold && g.Bnew == a.Bnew && g.E == a.E &&
+            g.rho == a.rho && g.rho_s == a.rho_s)
+            return g.ex;
+    if (H->graphs.size() >= 24) {
+        for (auto &g : H->graphs) {
+            (void)hipGraphExecDestroy(g.ex);
+            (void)hipGraphDestroy(g.g);
+        }
+        H->graphs.clear();
+    }
+    rad_hmat::GraphEntry e{};
+    e.path = (int)a.mm;
+    e.R = a.R;
+    e.Bold = a.Bold;
+    e.Bnew = a.Bnew;
+    e.E = a.E;
+    e.rho = a.rho;
+    e.rho_s = a.rho_s;
+    RAD_HIP(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue_iteration(H, a, H->cap_stream);
+    } catch (...) {
+        hipGraph_t tmp = nullptr;
+        (void)hipStreamEndCapture(H->cap_stream, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        throw;
+    }
+    RAD_HIP(hipStreamEndCapture(H->cap_stream, &e.g));
+    RAD_HIP(hipGraphInstantiate(&e.ex, e.g, nullptr, nullptr, 0));
+    H->graphs.push_back(e);
+    return e.ex;
 }
 
 template <class F>
@@ -51,6 +111,15 @@ static rad_status guard(F &&f) {
 static void check_hmat(const rad_hmat *H) { RAD_REQUIRE(H != nullptr, "null matrix handle"); }
 
 }  // namespace rad
+
+rad_hmat::~rad_hmat() {
+    for (auto &g : graphs) {
+        (void)hipGraphExecDestroy(g.ex);
+        (void)hipGraphDestroy(g.g);
+    }
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (h_norms) (void)hipHostFree(h_norms);
+}
 
 using namespace rad;
 
@@ -80,6 +149,7 @@ void rad_solve_opts_default(rad_solve_opts *o) {
     o->max_iter = 100;
     o->order = RAD_ORDER_ORIGINAL;
     o->check_every = 1;
+    o->use_graph = 1;
 }
 
 const char *rad_last_error(void) { return g_last_error.c_str(); }
@@ -132,6 +202,14 @@ rad_status rad_hmat_perm(const rad_hmat *H, int32_t *perm) {
     });
 }
 
+static void check_layout(const rad_hmat *H, int32_t order, int64_t R, int64_t ld, const char *name) {
+    RAD_REQUIRE(order == RAD_ORDER_ORIGINAL || order == RAD_ORDER_TREE || order == RAD_ORDER_TREE_RMAJOR, "bad order");
+    if (order == RAD_ORDER_TREE_RMAJOR)
+        RAD_REQUIRE(ld == mm_ldr(R), std::string(name) + ": R-major leading dimension must be R rounded up to 4");
+    else
+        RAD_REQUIRE(ld >= H->N, std::string(name) + ": leading dimension smaller than N");
+}
+
 rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const void *X, int64_t ldx, void *Y,
                            int64_t ldy, int32_t order, void *hip_stream) {
     return guard([&] {
@@ -139,22 +217,31 @@ rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const vo
         RAD_REQUIRE(X && Y, "null X or Y");
         RAD_REQUIRE(dtype == H->dtype, "dtype does not match the matrix");
         RAD_REQUIRE(R >= 1 && R <= H->max_rhs, "R must be in [1, max_rhs]");
-        RAD_REQUIRE(ldx >= H->N && ldy >= H->N, "leading dimension smaller than N");
-        RAD_REQUIRE(order == RAD_ORDER_ORIGINAL || order == RAD_ORDER_TREE, "bad order");
+        check_layout(H, order, R, ldx, "X");
+        check_layout(H, order, R, ldy, "Y");
         RAD_HIP(hipSetDevice(H->device));
         hipStream_t s = (hipStream_t)hip_stream;
+        const int64_t N = H->N;
         if (R >= kMfmaMinRhs) {
             int64_t ldr = mm_ldr(R);
-            bool perm = order == RAD_ORDER_ORIGINAL;
-            mm_to_rmajor(H, X, ldx, perm, H->w_x.p, ldr, R, s);
-            mm_apply(H, H->w_x.p, H->w_y.p, ldr, R, s);
-            mm_from_rmajor(H, H->w_y.p, ldr, perm, Y, ldy, R, s);
+            if (order == RAD_ORDER_TREE_RMAJOR) {
+                mm_apply(H, X, Y, ldr, R, s);
+            } else {
+                bool perm = order == RAD_ORDER_ORIGINAL;
+                mm_to_rmajor(H, X, ldx, perm, H->w_x.p, ldr, R, s);
+                mm_apply(H, H->w_x.p, H->w_y.p, ldr, R, s);
+                mm_from_rmajor(H, H->w_y.p, ldr, perm, Y, ldy, R, s);
+            }
         } else if (order == RAD_ORDER_TREE) {
             mv_apply(H, X, ldx, Y, ldy, R, s);
+        } else if (order == RAD_ORDER_TREE_RMAJOR) {
+            mm_from_rmajor(H, X, ldx, false, H->w_x.p, N, R, s);
+            mv_apply(H, H->w_x.p, N, H->w_y.p, N, R, s);
+            mm_to_rmajor(H, H->w_y.p, N, false, Y, ldy, R, s);
         } else {
-            mv_gather(H, X, ldx, H->w_x.p, H->N, R, s);
-            mv_apply(H, H->w_x.p, H->N, H->w_y.p, H->N, R, s);
-            mv_scatter(H, H->w_y.p, H->N, Y, ldy, R, s);
+            mv_gather(H, X, ldx, H->w_x.p, N, R, s);
+            mv_apply(H, H->w_x.p, N, H->w_y.p, N, R, s);
+            mv_scatter(H, H->w_y.p, N, Y, ldy, R, s);
         }
     });
 }
@@ -168,7 +255,6 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         RAD_REQUIRE(E && B, "null E or B");
         RAD_REQUIRE(dtype == H->dtype, "dtype does not match the matrix");
         RAD_REQUIRE(R >= 1 && R <= H->max_rhs, "R must be in [1, max_rhs]");
-        RAD_REQUIRE(lde >= H->N && ldb >= H->N, "leading dimension smaller than N");
         RAD_REQUIRE(std::isfinite(rho_scalar), "rho_scalar must be finite");
         rad_solve_opts o;
         if (opts)
@@ -176,46 +262,48 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         else
             rad_solve_opts_default(&o);
         RAD_REQUIRE(o.rtol > 0 && o.max_iter >= 1 && o.check_every >= 1, "bad solve options");
+        check_layout(H, o.order, R, lde, "E");
+        check_layout(H, o.order, R, ldb, "B");
         RAD_HIP(hipSetDevice(H->device));
+        rad_hmat *Hm = const_cast<rad_hmat *>(H);  // graph cache only
         hipStream_t s = (hipStream_t)hip_stream;
         const int64_t N = H->N;
         const size_t es = (size_t)dsize(H->dtype);
-        void *Et = H->w_e.p;
-        void *Bk = H->w_x.p;
-        void *FB = H->w_y.p;
-        void *Bn = H->w_b.p;
-        const void *rho_t = nullptr;
         const bool mm = R >= kMfmaMinRhs;
-        const int64_t ldr = mm ? mm_ldr(R) : N;
-        if (mm) {
-            mm_to_rmajor(H, E, lde, o.order == RAD_ORDER_ORIGINAL, Et, ldr, R, s);
-            if (rho) {
-                if (o.order == RAD_ORDER_TREE)
-                    RAD_HIP(hipMemcpyAsync(H->w_rho.p, rho, N * es, hipMemcpyDeviceToDevice, s));
-                else
-                    mv_gather(H, rho, N, H->w_rho.p, N, 1, s);
-                rho_t = H->w_rho.p;
-            }
-        } else if (o.order == RAD_ORDER_TREE) {
-            RAD_HIP(hipMemcpy2DAsync(Et, N * es, E, lde * es, N * es, R, hipMemcpyDeviceToDevice, s));
-            if (rho) {
-                RAD_HIP(hipMemcpyAsync(H->w_rho.p, rho, N * es, hipMemcpyDeviceToDevice, s));
-                rho_t = H->w_rho.p;
-            }
+        const bool rmaj = o.order == RAD_ORDER_TREE_RMAJOR;
+        const int64_t ld = mm ? mm_ldr(R) : N;
+        // E in the working layout, ping-pong buffers P[0], P[1]
+        const void *Ein;
+        void *P[2];
+        if (mm && rmaj) {
+            Ein = E;
+            P[0] = B;
         } else {
-            mv_gather(H, E, lde, Et, N, R, s);
-            if (rho) {
-                mv_gather(H, rho, N, H->w_rho.p, N, 1, s);
-                rho_t = H->w_rho.p;
-            }
+            if (mm)
+                mm_to_rmajor(H, E, lde, o.order == RAD_ORDER_ORIGINAL, H->w_e.p, ld, R, s);
+            else if (rmaj)
+                mm_from_rmajor(H, E, lde, false, H->w_e.p, N, R, s);
+            else if (o.order == RAD_ORDER_TREE)
+                RAD_HIP(hipMemcpy2DAsync(H->w_e.p, N * es, E, lde * es, N * es, R, hipMemcpyDeviceToDevice, s));
+            else
+                mv_gather(H, E, lde, H->w_e.p, N, R, s);
+            Ein = H->w_e.p;
+            P[0] = H->w_x.p;
         }
-        RAD_HIP(hipMemcpyAsync(Bk, Et, (size_t)N * (mm ? ldr : R) * es, hipMemcpyDeviceToDevice, s));
+        P[1] = H->w_b.p;
+        const void *rho_t = nullptr;
+        if (rho) {
+            if (o.order == RAD_ORDER_ORIGINAL)
+                mv_gather(H, rho, N, H->w_rho.p, N, 1, s);
+            else
+                RAD_HIP(hipMemcpyAsync(H->w_rho.p, rho, N * es, hipMemcpyDeviceToDevice, s));
+            rho_t = H->w_rho.p;
+        }
         double *enorm_d = H->w_norms.p;
-        double *dnorm_d = H->w_norms.p + H->max_rhs;
         if (mm)
-            mm_col_norms2(H, Et, ldr, R, enorm_d, s);
+            mm_col_norms2(H, Ein, ld, R, enorm_d, s);
         else
-            col_norms2(H, Et, N, R, enorm_d, s);
+            col_norms2(H, Ein, N, R, enorm_d, s);
         std::vector<double> enorm(R), dn(R);
         RAD_HIP(hipMemcpyAsync(enorm.data(), enorm_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
         RAD_HIP(hipStreamSynchronize(s));
@@ -229,16 +317,14 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         bool done = false;
         while (k < o.max_iter && !done) {
             ++k;
-            if (mm) {
-                mm_jacobi_step(H, Et, rho_t, rho_scalar, Bk, Bn, ldr, R, dnorm_d, s);
-            } else {
-                mv_apply(H, Bk, N, FB, N, R, s);
-                solve_update(H, Et, rho_t, rho_scalar, FB, Bk, Bn, N, R, dnorm_d, s);
-            }
-            std::swap(Bk, Bn);
+            IterArgs a{mm, R, ld, Ein, rho_t, k == 1 ? Ein : P[k % 2], P[(k - 1) % 2], rho_scalar};
+            if (o.use_graph)
+                RAD_HIP(hipGraphLaunch(iteration_graph(Hm, a), s));
+            else
+                enqueue_iteration(H, a, s);
             if (k % o.check_every == 0 || k == o.max_iter) {
-                RAD_HIP(hipMemcpyAsync(dn.data(), dnorm_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
                 RAD_HIP(hipStreamSynchronize(s));
+                std::copy(H->h_norms, H->h_norms + R, dn.begin());
                 done = true;
                 for (int64_t c = 0; c < R; ++c) {
                     double d = std::sqrt(dn[c]);
@@ -249,12 +335,18 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 }
             }
         }
-        if (mm)
-            mm_from_rmajor(H, Bk, ldr, o.order == RAD_ORDER_ORIGINAL, B, ldb, R, s);
-        else if (o.order == RAD_ORDER_TREE)
+        void *Bk = P[(k - 1) % 2];
+        if (mm && rmaj) {
+            if (Bk != B) RAD_HIP(hipMemcpyAsync(B, Bk, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
+        } else if (mm) {
+            mm_from_rmajor(H, Bk, ld, o.order == RAD_ORDER_ORIGINAL, B, ldb, R, s);
+        } else if (rmaj) {
+            mm_to_rmajor(H, Bk, N, false, B, ldb, R, s);
+        } else if (o.order == RAD_ORDER_TREE) {
             RAD_HIP(hipMemcpy2DAsync(B, ldb * es, Bk, N * es, N * es, R, hipMemcpyDeviceToDevice, s));
-        else
+        } else {
             mv_scatter(H, Bk, N, B, ldb, R, s);
+        }
         RAD_HIP(hipStreamSynchronize(s));
         if (info) {
             if (info->iters) std::copy(iters.begin(), iters.end(), info->iters);
@@ -276,9 +368,8 @@ rad_status rad_insolation(const rad_hmat *H, int64_t R, const double *suns, doub
         RAD_REQUIRE(suns && Q, "null suns or Q");
         RAD_REQUIRE(R >= 1, "R must be >= 1");
         RAD_REQUIRE(dtype == H->dtype, "dtype does not match the matrix");
-        RAD_REQUIRE(ldq >= H->N, "leading dimension smaller than N");
         RAD_REQUIRE(std::isfinite(flux), "flux must be finite");
-        RAD_REQUIRE(order == RAD_ORDER_ORIGINAL || order == RAD_ORDER_TREE, "bad order");
+        check_layout(H, order, R, ldq, "Q");
         for (int64_t r = 0; r < R; ++r) {
             double n2 = suns[3 * r] * suns[3 * r] + suns[3 * r + 1] * suns[3 * r + 1] + suns[3 * r + 2] * suns[3 * r + 2];
             RAD_REQUIRE(std::isfinite(n2) && n2 > 0.0, "sun direction must be finite and non-zero");
@@ -287,7 +378,7 @@ rad_status rad_insolation(const rad_hmat *H, int64_t R, const double *suns, doub
         hipStream_t s = (hipStream_t)hip_stream;
         DevBuf<double> d_s((size_t)3 * R);
         RAD_HIP(hipMemcpy(d_s.p, suns, sizeof(double) * 3 * R, hipMemcpyHostToDevice));
-        launch_insolation(H, d_s.p, R, flux, H->dtype, Q, ldq, order == RAD_ORDER_ORIGINAL, s);
+        launch_insolation(H, d_s.p, R, flux, H->dtype, Q, ldq, order, s);
         RAD_HIP(hipStreamSynchronize(s));
     });
 }

@@ -208,6 +208,21 @@ struct rad_hmat {
     double grid_x0 = 0, grid_y0 = 0, grid_h = 1, grid_ztop = 0;
     int32_t grid_gx = 1, grid_gy = 1;
 
+    // cached HIP graphs of one solve iteration (see api.cpp)
+    struct GraphEntry {
+        int path;
+        int64_t R;
+        const void *Bold, *E, *rho;
+        void *Bnew;
+        double rho_s;
+        hipGraph_t g;
+        hipGraphExec_t ex;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;
+    double *h_norms = nullptr;   // pinned host copy of the per-column norms
+    ~rad_hmat();
+
     // workspace (sized for max_rhs)
     rad::DevBuf<unsigned char> w_x, w_y, w_t, w_b, w_e, w_rho, w_red, w_part;
     rad::DevBuf<double> w_norms;
@@ -254,7 +269,7 @@ void launch_copy_batched(const CopyDesc *d, int64_t n, void *vals, int32_t dtype
 void build_grid(rad_hmat *H, const std::vector<double> &tri);
 void launch_vis_grid(const rad_hmat *H, uint32_t *bits, int64_t wpr, hipStream_t s);
 void launch_insolation(const rad_hmat *H, const double *suns_dev, int64_t R, double flux, int32_t dtype, void *Q,
-                       int64_t ldq, bool original_order, hipStream_t s);
+                       int64_t ldq, int32_t order, hipStream_t s);
 
 // matvec / solve kernels (matvec_kernels.hip)
 void mv_gather(const rad_hmat *H, const void *src, int64_t lds, void *dst, int64_t ldd, int64_t R, hipStream_t s);

@@ -120,7 +120,7 @@ __device__ bool occluded(const GridView &G, const double *o, const double *d, do
 
 template <class T>
 __global__ void k_insolation(GridView G, const double *x, const double *n, const double *suns, int64_t N,
-                             double flux, const int32_t *perm, T *Q, int64_t ldq) {
+                             double flux, const int32_t *perm, int rmajor, T *Q, int64_t ldq) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t r = blockIdx.y;
     if (t >= N) return;
@@ -129,8 +129,12 @@ __global__ void k_insolation(GridView G, const double *x, const double *n, const
     double c = dot3(nt, s);
     double q = 0.0;
     if (c > 0.0 && !occluded(G, x + 3 * t, s, 1e-9, __builtin_huge_val(), t, t)) q = flux * c;
-    int64_t row = perm ? (int64_t)perm[t] : t;
-    Q[row + r * ldq] = (T)q;
+    if (rmajor) {
+        Q[t * ldq + r] = (T)q;
+    } else {
+        int64_t row = perm ? (int64_t)perm[t] : t;
+        Q[row + r * ldq] = (T)q;
+    }
 }
 
 // V_ij bitmap (row i, 32 columns per word); the segment is cast from the facet
@@ -254,17 +258,19 @@ void launch_vis_grid(const rad_hmat *H, uint32_t *bits, int64_t wpr, hipStream_t
 }
 
 void launch_insolation(const rad_hmat *H, const double *suns_dev, int64_t R, double flux, int32_t dtype, void *Q,
-                       int64_t ldq, bool original_order, hipStream_t s) {
+                       int64_t ldq, int32_t order, hipStream_t s) {
+    const int rmajor = order == RAD_ORDER_TREE_RMAJOR;
+    const int32_t *perm = order == RAD_ORDER_ORIGINAL ? H->d_perm.p : nullptr;
     for (int64_t r0 = 0; r0 < R; r0 += 32768) {
         int64_t rn = std::min<int64_t>(32768, R - r0);
         dim3 grid((unsigned)((H->N + 127) / 128), (unsigned)rn);
-        const int32_t *perm = original_order ? H->d_perm.p : nullptr;
+        int64_t shift = rmajor ? r0 : r0 * ldq;
         if (dtype == RAD_F64)
             hipLaunchKernelGGL(k_insolation<double>, grid, dim3(128), 0, s, view_of(H), H->d_x.p, H->d_n.p,
-                               suns_dev + 3 * r0, H->N, flux, perm, (double *)Q + r0 * ldq, ldq);
+                               suns_dev + 3 * r0, H->N, flux, perm, rmajor, (double *)Q + shift, ldq);
         else
             hipLaunchKernelGGL(k_insolation<float>, grid, dim3(128), 0, s, view_of(H), H->d_x.p, H->d_n.p,
-                               suns_dev + 3 * r0, H->N, flux, perm, (float *)Q + r0 * ldq, ldq);
+                               suns_dev + 3 * r0, H->N, flux, perm, rmajor, (float *)Q + shift, ldq);
         RAD_HIP(hipGetLastError());
     }
 }

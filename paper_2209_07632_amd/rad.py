@@ -19,7 +19,7 @@ RAD_OK, RAD_EINVAL, RAD_ENOMEM, RAD_EDEVICE, RAD_ENOCONV, RAD_EUNSUP = range(6)
 RAD_F64, RAD_F32, RAD_F16, RAD_BF16 = range(4)
 NEARFIELD = {"auto": 0, "dense": 1, "csr": 2}
 VISIBILITY = {"backface": 0, "raycast": 1}
-ORDER = {"original": 0, "tree": 1}
+ORDER = {"original": 0, "tree": 1, "tree_rmajor": 2}
 DTYPES = {"f64": RAD_F64, "f32": RAD_F32}
 
 
@@ -38,7 +38,7 @@ class BuildOpts(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("check_every", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -124,6 +124,19 @@ def _stream_handle():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def ldr_of(R: int) -> int:
+    """Leading dimension of the internal R-major layout for R right-hand sides."""
+    return (int(R) + 3) // 4 * 4
+
+
+def _rmajor(t, N, R):
+    """Check a (N, ldr_of(R)) row-major device tensor for RAD_ORDER_TREE_RMAJOR."""
+    ldr = ldr_of(R)
+    if t.dim() != 2 or t.shape[0] != N or t.shape[1] != ldr or not t.is_contiguous():
+        raise ValueError(f"tree_rmajor tensors must be contiguous with shape ({N}, {ldr})")
+    return t, ldr
+
+
 def _colmajor(t, N):
     """View a (N,) or (N,R) device tensor as column-major with leading dimension >= N."""
     if t.dim() == 1:
@@ -181,9 +194,19 @@ class HMatrix:
         _check(load().rad_hmat_perm(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return p
 
-    def matvec(self, X, out=None, order="original"):
-        """Y = F-hat X for a device tensor X of shape (N,) or (N, R)."""
+    def matvec(self, X, out=None, order="original", R=None):
+        """Y = F-hat X.  Column-major orders take X of shape (N,) or (N, R);
+        order="tree_rmajor" takes the internal layout, shape (N, ldr_of(R))."""
         torch = _torch()
+        if order == "tree_rmajor":
+            R = int(R if R is not None else X.shape[1])
+            Xc, ldx = _rmajor(X, self.N, R)
+            if out is None:
+                out = torch.zeros_like(X)
+            Yc, ldy = _rmajor(out, self.N, R)
+            _check(load().rad_hmat_matvec(self._h, R, self.rad_dtype, ctypes.c_void_p(Xc.data_ptr()), ldx,
+                                          ctypes.c_void_p(Yc.data_ptr()), ldy, ORDER[order], _stream_handle()))
+            return out
         squeeze = X.dim() == 1
         Xc, ldx = _colmajor(X, self.N)
         R = Xc.shape[1]
@@ -197,16 +220,24 @@ class HMatrix:
         return out.reshape(-1) if squeeze else out
 
     def solve(self, E, rho=0.3, rtol=1e-3, max_iter=100, order="original", check_every=1, out=None,
-              raise_on_noconv=True):
+              raise_on_noconv=True, use_graph=True, R=None):
         """Jacobi solve of (I - diag(rho) F-hat) B = E; returns (B, info dict)."""
         torch = _torch()
         L = load()
-        squeeze = E.dim() == 1
-        Ec, lde = _colmajor(E, self.N)
-        R = Ec.shape[1]
-        if out is None:
-            out = torch.empty((R, self.N), dtype=E.dtype, device=E.device).t()
-        Bc, ldb = _colmajor(out, self.N)
+        squeeze = False
+        if order == "tree_rmajor":
+            R = int(R if R is not None else E.shape[1])
+            Ec, lde = _rmajor(E, self.N, R)
+            if out is None:
+                out = torch.zeros_like(E)
+            Bc, ldb = _rmajor(out, self.N, R)
+        else:
+            squeeze = E.dim() == 1
+            Ec, lde = _colmajor(E, self.N)
+            R = Ec.shape[1]
+            if out is None:
+                out = torch.empty((R, self.N), dtype=E.dtype, device=E.device).t()
+            Bc, ldb = _colmajor(out, self.N)
         rho_ptr = ctypes.c_void_p(0)
         rho_s = 0.0
         if isinstance(rho, (float, int)):
@@ -220,6 +251,7 @@ class HMatrix:
         o.max_iter = int(max_iter)
         o.order = ORDER[order]
         o.check_every = int(check_every)
+        o.use_graph = int(bool(use_graph))
         iters = np.zeros(R, dtype=np.int32)
         rel = np.zeros(R, dtype=np.float64)
         info = SolveInfo(iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -236,13 +268,20 @@ class HMatrix:
         return (out.reshape(-1) if squeeze else out), res
 
     def insolation(self, suns, flux=1365.0, order="original", out=None):
-        """Q_dir (N, R) on the device for sun unit vectors suns (R, 3)."""
+        """Q_dir on the device for sun unit vectors suns (R, 3): shape (N, R)
+        column-major, or (N, ldr_of(R)) for order="tree_rmajor"."""
         torch = _torch()
         s = np.ascontiguousarray(np.atleast_2d(suns), dtype=np.float64)
         R = s.shape[0]
-        if out is None:
-            out = torch.empty((R, self.N), dtype=self.torch_dtype, device=f"cuda:{self.device}").t()
-        Qc, ldq = _colmajor(out, self.N)
+        dev = f"cuda:{self.device}"
+        if order == "tree_rmajor":
+            if out is None:
+                out = torch.zeros((self.N, ldr_of(R)), dtype=self.torch_dtype, device=dev)
+            Qc, ldq = _rmajor(out, self.N, R)
+        else:
+            if out is None:
+                out = torch.empty((R, self.N), dtype=self.torch_dtype, device=dev).t()
+            Qc, ldq = _colmajor(out, self.N)
         _check(load().rad_insolation(self._h, R, s.ctypes.data, float(flux), self.rad_dtype,
                                      ctypes.c_void_p(Qc.data_ptr()), ldq, ORDER[order], _stream_handle()))
         if Qc.data_ptr() != out.data_ptr():

@@ -246,3 +246,44 @@ def test_solve_many_rhs(cap, storage):
     B, info = H.solve(torch.from_numpy(E).to(DEV, dt), rho=1.0, rtol=1e-6, max_iter=200)
     B1 = ref.solve_direct(F, 1.0, E)
     assert _rel(B.double().cpu().numpy(), B1) <= 1e-3
+
+
+# ------------------------------------------------------------ layouts and graphs
+@pytest.mark.parametrize("R", [3, 20])
+def test_rmajor_layout_matches_colmajor(cap, R):
+    from paper_2209_07632_amd.rad import ldr_of
+    verts, faces, fac, F = cap
+    H = _hm(verts, faces, tol=1e-4, storage="f64", max_rhs=R)
+    perm = H.perm()
+    X = np.random.default_rng(20 + R).random((fac.N, R))
+    Y = H.matvec(torch.from_numpy(X).to(DEV)).cpu().numpy()
+    Xr = np.zeros((fac.N, ldr_of(R)))
+    Xr[:, :R] = X[perm]
+    Yr = H.matvec(torch.from_numpy(Xr).to(DEV), order="tree_rmajor", R=R).cpu().numpy()
+    np.testing.assert_allclose(Yr[:, :R], Y[perm], rtol=1e-12, atol=1e-15)
+    suns = sun_directions(R, seed=7)
+    Qr = H.insolation(suns, order="tree_rmajor").cpu().numpy()
+    Q = H.insolation(suns).cpu().numpy()
+    np.testing.assert_array_equal(Qr[:, :R], Q[perm])
+    E = torch.from_numpy(0.3 * Q).to(DEV)
+    B, _ = H.solve(E, rho=0.3, rtol=1e-8)
+    Br, _ = H.solve(torch.from_numpy(0.3 * Qr).to(DEV), rho=0.3, rtol=1e-8, order="tree_rmajor", R=R)
+    np.testing.assert_allclose(Br.cpu().numpy()[:, :R], B.cpu().numpy()[perm], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("R", [1, 24])
+def test_graph_replays_match_eager(cap, R):
+    """Every replay of the cached iteration graphs equals the eager result, with
+    eager work and synchronisation between the replays."""
+    verts, faces, fac, F = cap
+    H = _hm(verts, faces, tol=1e-4, storage="f32", max_rhs=R)
+    rng = np.random.default_rng(30 + R)
+    Es = [torch.from_numpy(rng.uniform(0, 100, (fac.N, R))).to(DEV, torch.float32) for _ in range(3)]
+    ref_B = [H.solve(E, rho=0.3, rtol=1e-6, use_graph=False)[0].cpu().numpy() for E in Es]
+    for rep in range(3):
+        for E, B0 in zip(Es, ref_B):
+            B, info = H.solve(E, rho=0.3, rtol=1e-6, use_graph=True)
+            np.testing.assert_array_equal(B.cpu().numpy(), B0)
+            # eager work on the same stream between replays
+            H.matvec(E[:, 0].contiguous())
+            torch.cuda.synchronize()
