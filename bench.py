@@ -33,6 +33,22 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def measured_traffic(dtype, R):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    runs, or None when the kernel source changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != rec["source_sha1"]:
+        return None
+    if rec["dtype"] != dtype or rec["rhs"] != R:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(verts, faces, suns, albedo, B_gpu_cols, cols, S):
     """Time the FP64 CPU reference on a bounded sample: the listed sun columns,
     full mesh, insolation + matrix-free Jacobi to 1e-10."""
@@ -62,6 +78,7 @@ def main():
     ap.add_argument("--nearfield", default="csr")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=2)
+    ap.add_argument("--calib-copy", action="store_true", help="add a 1 GiB copy for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it"}))
@@ -137,11 +154,39 @@ def main():
     # dominant kernel of a solve iteration, timed alone with HIP events on the
     # stream it is launched on: expansion + near field + fused Jacobi update
     ph = H.time_phases(R, nrep=20)
+    # algorithmic work of one launch of the expansion kernel (R columns):
+    # flops 2 R (sum_LR m k + nnz_near); bytes: E, B_old read and B_new written
+    # (3 N R s), the U' rows and near-field values once, T read once (sum_rank x R)
     p2_flops = 2.0 * R * (st["lowrank_row_elems"] + st["nnz_near"])
+    p2_bytes = (3.0 * N * R * s_bytes + st["lowrank_row_elems"] * s_bytes + st["bytes_dense"] + st["bytes_csr"]
+                + st["sum_rank"] * R * s_bytes)
     p1_flops = 2.0 * R * st["lowrank_col_elems"]
     p2_tf = p2_flops / (ph[2] * 1e-3) / 1e12
+    p2_gbs = p2_bytes / (ph[2] * 1e-3) / 1e9
     p1_tf = p1_flops / (ph[0] * 1e-3) / 1e12 if ph[0] > 0 else 0.0
-    log(f"phases ms {ph}: expansion {p2_tf:.2f} TFLOP/s, projections {p1_tf:.2f} TFLOP/s")
+    intensity = p2_flops / p2_bytes
+    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if intensity < ridge:
+        roof = {"bound": "hbm", "achieved": p2_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": p2_gbs / HBM_PEAK_GBS}
+    else:
+        roof = {"bound": "mfma", "achieved": p2_tf, "peak": peak, "unit": "TFLOP/s", "frac": p2_tf / peak}
+    roof.update({"traffic": measured_traffic(args.dtype, R),
+                 "kernel": f"k_tile_mm<{'double' if args.dtype == 'f64' else 'float'}, true> "
+                           "(expansion + near field + fused Jacobi update)",
+                 "ms_per_launch": ph[2], "flops_per_launch": p2_flops, "bytes_per_launch": p2_bytes,
+                 "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+                 "tflops": p2_tf, "gbs": p2_gbs})
+    log(f"phases ms {ph}: expansion {p2_tf:.2f} TFLOP/s {p2_gbs:.0f} GB/s (I={intensity:.1f}), "
+        f"projections {p1_tf:.2f} TFLOP/s")
+    if args.calib_copy:
+        # plain copy of known size for scaling hardware byte counters
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 1 GiB read + 1 GiB written")
 
     result = {
         "metric": "sun-RHS radiosity solves/s + H-matvec HBM GB/s at 1e-3 rel err vs plain FP64",
@@ -155,10 +200,7 @@ def main():
         "build_seconds": build_s,
         "hmat_bytes": st["bytes_total"],
         "hmatvec_ms": mv_ms, "hmatvec_gbs": gbs, "hmatvec_tflops": tflops,
-        "roofline": {"bound": "mfma", "achieved": p2_tf, "peak": peak, "unit": "TFLOP/s",
-                     "frac": p2_tf / peak, "traffic": None,
-                     "kernel": f"k_tile_mm<{'double' if args.dtype == 'f64' else 'float'}> (expansion + fused Jacobi update)",
-                     "ms_per_launch": ph[2], "flops_per_launch": p2_flops},
+        "roofline": roof,
         "phase_ms": {"projections": ph[0], "split_k_sum": ph[1], "expansion_jacobi": ph[2]},
         "projections_tflops": p1_tf,
     }

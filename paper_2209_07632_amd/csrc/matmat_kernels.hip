@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(256) k_proj_reduce(const P1Red *red, const T *
 // the epilogue performs the Jacobi update B_new = E + rho * (F B_old) and
 // writes the per-column partial sums of (B_new - B_old)^2 for this tile.
 // ---------------------------------------------------------------------------
-template <class T>
+template <class T, bool kFused>
 __global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
                                                   const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
                                                   int64_t csr_val_start, const T *X, const T *Tb, int64_t ldr, int R,
@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const in
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         T ev[4][4], bo[4][4];
-        if (E) {
+        if constexpr (kFused) {
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) {
                 const int row = rsub + 8 * (4 * half + qq);
@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const in
             if (row < rows) {
                 const int64_t e = (tile0 + row) * ldr + col;
                 T y[4] = {sC[row][c4], sC[row][c4 + 1], sC[row][c4 + 2], sC[row][c4 + 3]};
-                if (E) {
+                if constexpr (kFused) {
                     T rh = rho ? rho[tile0 + row] : rho_s;
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const in
             }
         }
     }
-    if (E) {
+    if constexpr (kFused) {
         __syncthreads();
         double *red = (double *)smem;   // 8 x 128 partial sums (fits in the LDS tile)
 #pragma unroll
@@ -577,9 +577,14 @@ void apply_mm_t(const rad_hmat *H, const T *X, T *Y, int64_t ldr, int R, const T
                 double *partial, hipStream_t s) {
     proj_mm_t<T>(H, X, ldr, R, s);
     unsigned rtiles = (unsigned)((R + TN - 1) / TN);
-    hipLaunchKernelGGL(k_tile_mm<T>, dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
-                       H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p, H->csr_val_start, X,
-                       (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial);
+    if (E)
+        hipLaunchKernelGGL((k_tile_mm<T, true>), dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
+                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
+                           H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial);
+    else
+        hipLaunchKernelGGL((k_tile_mm<T, false>), dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p,
+                           H->d_brow.p, H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
+                           H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial);
     RAD_HIP(hipGetLastError());
 }
 
@@ -668,7 +673,7 @@ void time_phases_t(const rad_hmat *H, int R, int nrep, hipStream_t s, double *ms
     }
     RAD_HIP(hipEventRecord(e0, s));
     for (int i = 0; i < nrep; ++i)
-        hipLaunchKernelGGL(k_tile_mm<T>, dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
+        hipLaunchKernelGGL((k_tile_mm<T, true>), dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
                            H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
                            H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, (const T *)nullptr, (T)0.3,
                            part);
