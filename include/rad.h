@@ -71,7 +71,7 @@ typedef enum { RAD_ORDER_ORIGINAL = 0, RAD_ORDER_TREE = 1, RAD_ORDER_TREE_RMAJOR
 
 typedef struct {
     double tol;           /* compression tolerance eps of Algorithm 3 (> 0)           */
-    int32_t leaf_size;    /* quadtree leaf capacity, Algorithm 2 (default 64, <= 64)  */
+    int32_t leaf_size;    /* quadtree leaf capacity, Algorithm 2 (default 64, <= 4096) */
     int32_t max_depth;    /* quadtree depth limit (0: none)                           */
     int32_t nearfield;    /* rad_nearfield                                            */
     int32_t visibility;   /* rad_visibility                                           */
@@ -81,7 +81,8 @@ typedef struct {
     int32_t max_rhs;      /* workspace is sized for up to this many right-hand sides (default 1) */
     int32_t device;       /* HIP device ordinal (default 0)                           */
     uint64_t seed;        /* seed of the sketch's random signs                        */
-    int32_t verbose;      /* 1: print build statistics to stderr                      */
+    int32_t verbose;      /* 1: print build progress and statistics to stderr         */
+    int32_t max_rank;     /* 0: no limit; else Algorithm 3 gives up above this rank   */
 } rad_build_opts;
 
 /* Fills *opts with the defaults listed above (tol 1e-3). */
@@ -157,6 +158,24 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
  */
 rad_status rad_insolation(const rad_hmat *H, int64_t R, const double *suns, double flux, int32_t dtype,
                           void *Q, int64_t ldq, int32_t order, void *hip_stream);
+
+/*
+ * Equilibrium surface temperature for R sun positions (section 5.1 with
+ * eqs. 3d-equilbr, Qvis and QIR; subsurface flux H = 0), all on the device:
+ *   short wave: (I - albedo F-hat) B_s = albedo Q_dir,   Q_refl = F-hat B_s,
+ *               Q_vis = Q_dir + Q_refl;
+ *   long wave:  (I - F-hat) B_IR = (1 - albedo) Q_vis,   Q_IR = F-hat B_IR;
+ *   T = ( max(0, (1 - albedo) Q_vis + emissivity Q_IR) / (emissivity sigma) )^(1/4),
+ * sigma = 5.670374419e-8.  Qdir, T, Qvis, Qir: device arrays of the compute
+ * dtype in the layout opts->order names, all with leading dimension ld (N for
+ * the column-major layouts, R rounded up to 4 for RAD_ORDER_TREE_RMAJOR); Qvis
+ * and Qir may be NULL.  albedo in [0, 1), emissivity in (0, 1].  The two
+ * solves use opts (rtol, max_iter, graphs); info_sw / info_ir may be NULL.
+ * Errors: as rad_solve, plus RAD_EINVAL for albedo/emissivity out of range.
+ */
+rad_status rad_equilibrium(const rad_hmat *H, int64_t R, int32_t dtype, const void *Qdir, int64_t ld, double albedo,
+                           double emissivity, void *T, void *Qvis, void *Qir, const rad_solve_opts *opts,
+                           rad_solve_info *info_sw, rad_solve_info *info_ir, void *hip_stream);
 
 typedef struct {
     int64_t n;                 /* facets                                              */

@@ -29,6 +29,8 @@ static void alloc_workspace(rad_hmat *H) {
     H->w_norms.alloc((size_t)3 * H->max_rhs);
     if (H->max_rhs >= kMfmaMinRhs && H->n_parts > 0)
         H->w_part.alloc((size_t)H->n_parts * mm_part_rows() * ldr * s);
+    H->w_q1.alloc(nr * s);
+    H->w_q2.alloc(nr * s);
     RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * (size_t)H->max_rhs, hipHostMallocDefault));
     RAD_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
 }
@@ -357,6 +359,61 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             conv = RAD_ENOCONV;
             set_error("Jacobi reached max_iter before rtol");
         }
+    });
+    return st != RAD_OK ? st : conv;
+}
+
+rad_status rad_equilibrium(const rad_hmat *H, int64_t R, int32_t dtype, const void *Qdir, int64_t ld, double albedo,
+                           double emissivity, void *T, void *Qvis, void *Qir, const rad_solve_opts *opts,
+                           rad_solve_info *info_sw, rad_solve_info *info_ir, void *hip_stream) {
+    rad_status conv = RAD_OK;
+    rad_status st = guard([&] {
+        check_hmat(H);
+        RAD_REQUIRE(Qdir && T, "null Qdir or T");
+        RAD_REQUIRE(dtype == H->dtype, "dtype does not match the matrix");
+        RAD_REQUIRE(R >= 1 && R <= H->max_rhs, "R must be in [1, max_rhs]");
+        RAD_REQUIRE(albedo >= 0.0 && albedo < 1.0, "albedo must be in [0, 1)");
+        RAD_REQUIRE(emissivity > 0.0 && emissivity <= 1.0, "emissivity must be in (0, 1]");
+        rad_solve_opts o;
+        if (opts)
+            o = *opts;
+        else
+            rad_solve_opts_default(&o);
+        check_layout(H, o.order, R, ld, "Qdir");
+        const bool rmaj = o.order == RAD_ORDER_TREE_RMAJOR;
+        RAD_REQUIRE(rmaj || ld == H->N, "column-major layouts need ld == N here");
+        RAD_HIP(hipSetDevice(H->device));
+        hipStream_t s = (hipStream_t)hip_stream;
+        void *q1 = H->w_q1.p, *q2 = H->w_q2.p;
+        auto ew = [&](int32_t op, double a, double b, double c, const void *x, const void *y, void *z) {
+            launch_elementwise(H, op, a, b, c, x, y, z, R, ld, rmaj, s);
+        };
+        auto band = [&](double rho, const void *E, rad_solve_info *info) {
+            rad_status r = rad_solve(H, nullptr, rho, R, dtype, E, ld, T, ld, &o, info, hip_stream);
+            if (r == RAD_ENOCONV)
+                conv = RAD_ENOCONV;
+            else if (r != RAD_OK)
+                throw Error(r, rad_last_error());
+        };
+        auto product = [&](const void *X, void *Y) {
+            rad_status r = rad_hmat_matvec(H, R, dtype, X, ld, Y, ld, o.order, hip_stream);
+            if (r != RAD_OK) throw Error(r, rad_last_error());
+        };
+        // short wave: T holds B_s, q1 ends as Q_vis
+        ew(EW_SCALE, albedo, 0, 0, Qdir, nullptr, q1);
+        band(albedo, q1, info_sw);
+        product(T, q1);
+        ew(EW_ADD, 0, 0, 0, Qdir, q1, q1);
+        // long wave: T holds B_IR, q2 ends as Q_IR
+        ew(EW_SCALE, 1.0 - albedo, 0, 0, q1, nullptr, q2);
+        band(1.0, q2, info_ir);
+        product(T, q2);
+        ew(EW_TEMP, 1.0 - albedo, emissivity, emissivity * 5.670374419e-8, q1, q2, T);
+        const size_t bytes = (size_t)H->N * (size_t)(rmaj ? ld : R) * dsize(H->dtype);
+        if (Qvis) RAD_HIP(hipMemcpyAsync(Qvis, q1, bytes, hipMemcpyDeviceToDevice, s));
+        if (Qir) RAD_HIP(hipMemcpyAsync(Qir, q2, bytes, hipMemcpyDeviceToDevice, s));
+        RAD_HIP(hipStreamSynchronize(s));
+        if (conv != RAD_OK) set_error("a band's Jacobi solve reached max_iter before rtol");
     });
     return st != RAD_OK ? st : conv;
 }

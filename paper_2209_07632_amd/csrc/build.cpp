@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <numeric>
 
 #include "rad_internal.h"
@@ -189,7 +190,27 @@ void jacobi_svd(int l, std::vector<double> &A, std::vector<double> &V, std::vect
     sv.swap(s2);
 }
 
+// verbose progress: one flushed line per stage with the elapsed time
+struct StageLog {
+    bool on = false;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    void operator()(const char *what, const std::string &extra = std::string()) const {
+        if (!on) return;
+        double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        std::fprintf(stderr, "[rad build %7.2fs] %s %s\n", dt, what, extra.c_str());
+        std::fflush(stderr);
+    }
+};
+
+// Row count from which CGS2 runs on many workgroups per block (the
+// environment variable RAD_CGS2_TALL_ROWS overrides it, for tests).
+int32_t cgs2_tall_rows() {
+    const char *e = std::getenv("RAD_CGS2_TALL_ROWS");
+    return e ? std::max(1, std::atoi(e)) : 4096;
+}
+
 struct Builder {
+    StageLog log;
     rad_hmat *H;
     rad_build_opts o;
     int s;  // bytes per stored value
@@ -278,7 +299,17 @@ struct Builder {
             int64_t m = a.size, n = b.size;
             int64_t cb = csr_bytes(m, bp[p].nnz);
             int64_t per = (m + n + 1) * (int64_t)s;
-            int64_t qlim = (cb + per - 1) / per - 1;  // largest q with svd bytes < CSR bytes
+            // Algorithm 3 accepts q only if its bytes are below the CSR bytes.
+            int64_t qlim = (cb + per - 1) / per - 1;
+            // Algorithm 4 then keeps the SVD only if it also beats the other
+            // forms: below dense/CSR (when allowed) and not above the children,
+            // which are already decided.  Ranks beyond that cannot change the
+            // result, so the doubling stops there.
+            int64_t hb = 0;
+            for (int k = 0; k < bp[p].nchild; ++k) hb += bp[bp[p].first_child + k].best_bytes;
+            qlim = std::min<int64_t>(qlim, hb / per);
+            if (o.nearfield != RAD_NEAR_CSR) qlim = std::min<int64_t>(qlim, (dense_bytes(m, n) - 1) / per);
+            if (o.max_rank > 0) qlim = std::min<int64_t>(qlim, o.max_rank);
             qlim = std::min<int64_t>(qlim, std::min(m, n));
             if (qlim < 1) continue;
             active.push_back(State{p, 8, (int32_t)qlim});
@@ -336,6 +367,9 @@ struct Builder {
                               },
                               chunk);
             }
+            log("  rank round", "L=" + std::to_string(level) + " round=" + std::to_string(round) +
+                                    " blocks=" + std::to_string(active.size()) + " unresolved=" +
+                                    std::to_string(next.size()));
             active.swap(next);
         }
     }
@@ -353,22 +387,36 @@ struct Builder {
             rfill += (int64_t)sb[c].ell * sb[c].ell;
         }
         DevBuf<double> Rbuf(rfill);
+        DevBuf<int64_t> d_roff;
+        d_roff.upload(roff);
+        // tall blocks are orthonormalised by many workgroups per block
+        const bool tall = max_rows >= cgs2_tall_rows();
+        DevBuf<double> part, normpart;
+        if (tall) {
+            int64_t nch = (max_rows + 2047) / 2048;
+            part.alloc((size_t)nb * nch * (max_ell + 1));
+            normpart.alloc((size_t)nb * nch);
+        }
+        auto orth = [&](double *base, int use_z, double *R) {
+            if (tall)
+                launch_cgs2_tall(base, d_sb.p, (int32_t)nb, use_z, R, d_roff.p, max_rows, max_ell, part.p, normpart.p,
+                                 nullptr, st);
+            else
+                launch_cgs2(base, d_sb.p, (int32_t)nb, use_z, R, d_roff.p, st);
+        };
         // Y = F Omega (Omega: random signs written into Z), then subspace iterations.
         launch_fill_rademacher(Z.p, d_sb.p, (int32_t)nb, st);
         launch_sketch_apply(geom, d_sb.p, (int32_t)nb, 0, Z.p, Y.p, max_rows, max_ell, st);
-        launch_cgs2(Y.p, d_sb.p, (int32_t)nb, 0, nullptr, nullptr, st);
+        orth(Y.p, 0, nullptr);
         for (int it = 0; it < o.power_iters; ++it) {
             launch_sketch_apply(geom, d_sb.p, (int32_t)nb, 1, Y.p, Z.p, max_rows, max_ell, st);
-            launch_cgs2(Z.p, d_sb.p, (int32_t)nb, 1, nullptr, nullptr, st);
+            orth(Z.p, 1, nullptr);
             launch_sketch_apply(geom, d_sb.p, (int32_t)nb, 0, Z.p, Y.p, max_rows, max_ell, st);
-            launch_cgs2(Y.p, d_sb.p, (int32_t)nb, 0, nullptr, nullptr, st);
+            orth(Y.p, 0, nullptr);
         }
         // Z = F^T Q = Q2 R
         launch_sketch_apply(geom, d_sb.p, (int32_t)nb, 1, Y.p, Z.p, max_rows, max_ell, st);
-        // R buffer: per block ell x ell at roff
-        DevBuf<int64_t> d_roff;
-        d_roff.upload(roff);
-        launch_cgs2(Z.p, d_sb.p, (int32_t)nb, 1, Rbuf.p, d_roff.p, st);
+        orth(Z.p, 1, Rbuf.p);
         RAD_HIP(hipStreamSynchronize(st));
         std::vector<double> Rh = Rbuf.download(rfill);
 
@@ -537,6 +585,8 @@ struct Builder {
                 if (bp[p].first_child >= 0 && bp[p].nnz > 0) internal.push_back(p);
             if (!internal.empty()) rank_search(L, internal);
             for (int64_t p : by_level[L]) decide(p);
+            log("level decided", "L=" + std::to_string(L) + " pairs=" + std::to_string(by_level[L].size()) +
+                                     " internal=" + std::to_string(internal.size()));
         }
     }
 
@@ -856,7 +906,7 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
     RAD_REQUIRE(nv >= 3 && nf >= 1, "mesh needs nv >= 3 and nf >= 1");
     RAD_REQUIRE(nf < (int64_t)1 << 31, "too many faces");
     RAD_REQUIRE(o.tol > 0.0 && std::isfinite(o.tol), "tol must be positive");
-    RAD_REQUIRE(o.leaf_size >= 1 && o.leaf_size <= 64, "leaf_size must be in [1, 64]");
+    RAD_REQUIRE(o.leaf_size >= 1 && o.leaf_size <= 4096, "leaf_size must be in [1, 4096]");
     RAD_REQUIRE(o.storage == RAD_F64 || o.storage == RAD_F32, "storage must be RAD_F64 or RAD_F32");
     RAD_REQUIRE(o.nearfield >= RAD_NEAR_AUTO && o.nearfield <= RAD_NEAR_CSR, "bad nearfield option");
     RAD_REQUIRE(o.visibility == RAD_VIS_BACKFACE || o.visibility == RAD_VIS_RAYCAST, "bad visibility option");
@@ -865,6 +915,7 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
     RAD_REQUIRE(o.max_rhs >= 1, "max_rhs must be >= 1");
 
     Builder B;
+    B.log.on = o.verbose != 0;
     B.H = H;
     B.o = o;
     B.s = dtype_size(o.storage);
@@ -887,6 +938,7 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
     std::vector<int32_t> all(nf);
     std::iota(all.begin(), all.end(), 0);
     qb.split(0, std::move(all), 0);
+    B.log("quadtree", "leaves=" + std::to_string(qb.nleaves));
     H->nodes = std::move(qb.nodes);
     H->perm = std::move(qb.perm);
     H->n_leaves = qb.nleaves;
@@ -925,6 +977,7 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
         }
         build_grid(H, tri);
     }
+    B.log("grid");
     if (o.visibility == RAD_VIS_RAYCAST) {
         int64_t wpr = (nf + 31) / 32;
         B.d_vis.alloc((size_t)wpr * nf);
@@ -932,12 +985,17 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
         B.geom.vis_words_per_row = wpr;
         launch_vis_grid(H, B.d_vis.p, wpr, B.st);
         RAD_HIP(hipStreamSynchronize(B.st));
+        B.log("visibility bitmap");
     }
 
     B.enumerate_pairs();
+    B.log("block pairs", std::to_string(B.bp.size()));
     B.count_nnz();
+    B.log("leaf non-zeros");
     B.run_dp();
+    B.log("rank search and choice");
     B.layout();
+    B.log("layout");
 
     auto t1 = std::chrono::steady_clock::now();
     H->stats.build_seconds = std::chrono::duration<double>(t1 - t0).count();

@@ -240,6 +240,127 @@ __global__ void __launch_bounds__(256) k_cgs2(double *base, const SketchBlock *b
     }
 }
 
+__global__ void k_zero_r(const SketchBlock *blocks, double *Rout, const int64_t *roff) {
+    const SketchBlock b = blocks[blockIdx.x];
+    double *R = Rout + roff[blockIdx.x];
+    for (int e = threadIdx.x; e < b.ell * b.ell; e += blockDim.x) R[e] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// CGS2 for tall blocks, spread over many workgroups: for each column c the
+// rows are split in chunks of kCgsRows; every chunk writes partial dot
+// products (or norms), and the next launch sums them in a fixed order.
+// One column needs five launches: dots, update, dots, update, normalize.
+// ---------------------------------------------------------------------------
+constexpr int kCgsRows = 2048;
+
+// part[(b * nch + ch) * stride + j] = sum over the chunk of Q[:, j] v (j < c);
+// with first != 0 also writes the chunk's sum of v^2 at index stride - 1.
+__global__ void __launch_bounds__(256) k_cgs2_dots(double *base, const SketchBlock *blocks, int use_z, int c,
+                                                    int nch, int stride, double *part, int first) {
+    const SketchBlock b = blocks[blockIdx.y];
+    const int rows = use_z ? b.n : b.m;
+    const int ch = blockIdx.x;
+    if (c >= b.ell || ch * kCgsRows >= rows) return;
+    const double *Q = base + (use_z ? b.z_off : b.y_off);
+    const double *v = Q + (int64_t)c * rows;
+    const int r0 = ch * kCgsRows, r1 = min(rows, r0 + kCgsRows);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    __shared__ double sd[4][33];
+    double *out = part + ((int64_t)blockIdx.y * nch + ch) * stride;
+    for (int j0 = 0; j0 < c; j0 += 32) {
+        const int jn = min(32, c - j0);
+        double pj[32];
+#pragma unroll
+        for (int jj = 0; jj < 32; ++jj) pj[jj] = 0.0;
+        for (int r = r0 + t; r < r1; r += 256) {
+            const double vr = v[r];
+#pragma unroll
+            for (int jj = 0; jj < 32; ++jj)
+                if (jj < jn) pj[jj] += Q[(int64_t)(j0 + jj) * rows + r] * vr;
+        }
+#pragma unroll
+        for (int jj = 0; jj < 32; ++jj) {
+            double q = wave_sum(pj[jj]);
+            if (lane == 0) sd[w][jj] = q;
+        }
+        __syncthreads();
+        if (t < jn) out[j0 + t] = sd[0][t] + sd[1][t] + sd[2][t] + sd[3][t];
+        __syncthreads();
+    }
+    if (first) {
+        double s = 0.0;
+        for (int r = r0 + t; r < r1; r += 256) s += v[r] * v[r];
+        s = wave_sum(s);
+        if (lane == 0) sd[w][32] = s;
+        __syncthreads();
+        if (t == 0) out[stride - 1] = sd[0][32] + sd[1][32] + sd[2][32] + sd[3][32];
+    }
+}
+
+// v -= Q[:, :c] d with d = sum of the chunk partials; chunk 0 adds d to R.
+// Writes the chunk's sum of the updated v^2 at normpart[b * nch + ch].
+__global__ void __launch_bounds__(256) k_cgs2_update(double *base, const SketchBlock *blocks, int use_z, int c,
+                                                      int nch, int stride, const double *part, double *Rout,
+                                                      const int64_t *roff, double *normpart) {
+    const SketchBlock b = blocks[blockIdx.y];
+    const int rows = use_z ? b.n : b.m;
+    const int ch = blockIdx.x;
+    if (c >= b.ell || ch * kCgsRows >= rows) return;
+    double *Q = base + (use_z ? b.z_off : b.y_off);
+    double *v = Q + (int64_t)c * rows;
+    const int r0 = ch * kCgsRows, r1 = min(rows, r0 + kCgsRows);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int nchb = (rows + kCgsRows - 1) / kCgsRows;
+    __shared__ double sdot[512];
+    __shared__ double sred[4];
+    double s = 0.0;
+    for (int j0 = 0; j0 < c; j0 += 512) {
+        const int jn = min(512, c - j0);
+        for (int jj = t; jj < jn; jj += 256) {
+            double d = 0.0;
+            for (int k = 0; k < nchb; ++k) d += part[((int64_t)blockIdx.y * nch + k) * stride + j0 + jj];
+            sdot[jj] = d;
+            if (Rout && ch == 0) Rout[roff[blockIdx.y] + (j0 + jj) + (int64_t)c * b.ell] += d;
+        }
+        __syncthreads();
+        for (int r = r0 + t; r < r1; r += 256) {
+            double acc = v[r];
+            for (int jj = 0; jj < jn; ++jj) acc -= Q[(int64_t)(j0 + jj) * rows + r] * sdot[jj];
+            v[r] = acc;
+        }
+        __syncthreads();
+    }
+    for (int r = r0 + t; r < r1; r += 256) s += v[r] * v[r];
+    s = wave_sum(s);
+    if (lane == 0) sred[w] = s;
+    __syncthreads();
+    if (t == 0) normpart[(int64_t)blockIdx.y * nch + ch] = sred[0] + sred[1] + sred[2] + sred[3];
+}
+
+// normalize column c (or zero it when it collapsed below 1e-13 of its start)
+__global__ void __launch_bounds__(256) k_cgs2_norm(double *base, const SketchBlock *blocks, int use_z, int c, int nch,
+                                                    int stride, const double *part, const double *normpart,
+                                                    double *Rout, const int64_t *roff) {
+    const SketchBlock b = blocks[blockIdx.y];
+    const int rows = use_z ? b.n : b.m;
+    const int ch = blockIdx.x;
+    if (c >= b.ell || ch * kCgsRows >= rows) return;
+    double *v = base + (use_z ? b.z_off : b.y_off) + (int64_t)c * rows;
+    const int nchb = (rows + kCgsRows - 1) / kCgsRows;
+    double n0 = 0.0, n1 = 0.0;
+    for (int k = 0; k < nchb; ++k) {
+        n0 += part[((int64_t)blockIdx.y * nch + k) * stride + stride - 1];
+        n1 += normpart[(int64_t)blockIdx.y * nch + k];
+    }
+    const double norm0 = sqrt(n0), nrm = sqrt(n1);
+    const bool dep = !(nrm > 1e-13 * norm0) || !(nrm > 0.0);
+    const double inv = dep ? 0.0 : 1.0 / nrm;
+    const int r0 = ch * kCgsRows, r1 = min(rows, r0 + kCgsRows);
+    for (int r = r0 + threadIdx.x; r < r1; r += 256) v[r] = dep ? 0.0 : v[r] * inv;
+    if (Rout && ch == 0 && threadIdx.x == 0) Rout[roff[blockIdx.y] + c + (int64_t)c * b.ell] = dep ? 0.0 : nrm;
+}
+
 // out (rows x q) = Q (rows x ell) * small (ell x q) for each accepted block
 __global__ void k_small_gemm(const double *Qbase, const SketchBlock *blocks, const int64_t *soff,
                              const double *small, const int32_t *qk, const int64_t *ooff, double *out, int use_z) {
@@ -352,6 +473,32 @@ void launch_cgs2(double *base, const SketchBlock *blocks, int32_t nblocks, int u
     if (nblocks <= 0) return;
     hipLaunchKernelGGL(k_cgs2, dim3(nblocks), dim3(256), 0, s, base, blocks, use_z, Rout, roff);
     RAD_HIP(hipGetLastError());
+}
+
+void launch_cgs2_tall(double *base, const SketchBlock *blocks, int32_t nblocks, int use_z, double *Rout,
+                      const int64_t *roff, int32_t max_rows, int32_t max_ell, double *part, double *normpart,
+                      double *norm0part, hipStream_t s) {
+    (void)norm0part;
+    if (nblocks <= 0) return;
+    const int nch = (max_rows + kCgsRows - 1) / kCgsRows;
+    const int stride = max_ell + 1;
+    dim3 grid(nch, nblocks);
+    if (Rout) {
+        // R = 0 before accumulation: one small kernel per block would also do; reuse the fill
+        hipLaunchKernelGGL(k_zero_r, dim3(nblocks), dim3(256), 0, s, blocks, Rout, roff);
+        RAD_HIP(hipGetLastError());
+    }
+    for (int c = 0; c < max_ell; ++c) {
+        hipLaunchKernelGGL(k_cgs2_dots, grid, dim3(256), 0, s, base, blocks, use_z, c, nch, stride, part, 1);
+        hipLaunchKernelGGL(k_cgs2_update, grid, dim3(256), 0, s, base, blocks, use_z, c, nch, stride,
+                           (const double *)part, Rout, roff, normpart);
+        hipLaunchKernelGGL(k_cgs2_dots, grid, dim3(256), 0, s, base, blocks, use_z, c, nch, stride, part, 0);
+        hipLaunchKernelGGL(k_cgs2_update, grid, dim3(256), 0, s, base, blocks, use_z, c, nch, stride,
+                           (const double *)part, Rout, roff, normpart);
+        hipLaunchKernelGGL(k_cgs2_norm, grid, dim3(256), 0, s, base, blocks, use_z, c, nch, stride,
+                           (const double *)part, (const double *)normpart, Rout, roff);
+        RAD_HIP(hipGetLastError());
+    }
 }
 
 void launch_small_gemm(const double *Qbase, const SketchBlock *blocks, const int64_t *soff, const double *small,

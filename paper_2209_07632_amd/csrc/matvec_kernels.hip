@@ -228,4 +228,44 @@ void solve_update(const rad_hmat *H, const void *E, const void *rho, double rho_
 
 size_t reduction_doubles(int64_t R) { return (size_t)kRedParts * (size_t)R; }
 
+namespace {
+template <class T>
+__global__ void k_elementwise(int32_t op, double a, double b, double c, const T *x, const T *y, T *z, int64_t N,
+                              int64_t R, int64_t ld, int rmajor) {
+    const int64_t tot = N * R;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i, r;
+        if (rmajor) {
+            i = e / R;
+            r = e - i * R;
+        } else {
+            r = e / N;
+            i = e - r * N;
+        }
+        const int64_t k = rmajor ? i * ld + r : i + r * ld;
+        if (op == EW_SCALE) {
+            z[k] = (T)(a * (double)x[k]);
+        } else if (op == EW_ADD) {
+            z[k] = x[k] + y[k];
+        } else {
+            double f = a * (double)x[k] + b * (double)y[k];
+            z[k] = (T)sqrt(sqrt((f > 0.0 ? f : 0.0) / c));
+        }
+    }
+}
+}  // namespace
+
+void launch_elementwise(const rad_hmat *H, int32_t op, double a, double b, double c, const void *x, const void *y,
+                        void *z, int64_t R, int64_t ld, bool rmajor, hipStream_t s) {
+    int64_t tot = H->N * R;
+    unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 16384);
+    if (H->dtype == RAD_F64)
+        hipLaunchKernelGGL(k_elementwise<double>, dim3(blocks), dim3(256), 0, s, op, a, b, c, (const double *)x,
+                           (const double *)y, (double *)z, H->N, R, ld, (int)rmajor);
+    else
+        hipLaunchKernelGGL(k_elementwise<float>, dim3(blocks), dim3(256), 0, s, op, a, b, c, (const float *)x,
+                           (const float *)y, (float *)z, H->N, R, ld, (int)rmajor);
+    RAD_HIP(hipGetLastError());
+}
+
 }  // namespace rad

@@ -224,7 +224,7 @@ struct rad_hmat {
     ~rad_hmat();
 
     // workspace (sized for max_rhs)
-    rad::DevBuf<unsigned char> w_x, w_y, w_t, w_b, w_e, w_rho, w_red, w_part;
+    rad::DevBuf<unsigned char> w_x, w_y, w_t, w_b, w_e, w_rho, w_red, w_part, w_q1, w_q2;
     rad::DevBuf<double> w_norms;
 };
 
@@ -254,6 +254,9 @@ void launch_sketch_apply(const DevGeom &g, const SketchBlock *blocks, int32_t nb
                          const double *in, double *out, int32_t max_rows, int32_t max_ell, hipStream_t s);
 void launch_cgs2(double *Ybase, const SketchBlock *blocks, int32_t nblocks, int use_z, double *Rout,
                  const int64_t *roff, hipStream_t s);
+void launch_cgs2_tall(double *base, const SketchBlock *blocks, int32_t nblocks, int use_z, double *Rout,
+                      const int64_t *roff, int32_t max_rows, int32_t max_ell, double *part, double *normpart,
+                      double *norm0part, hipStream_t s);
 void launch_small_gemm(const double *Qbase, const SketchBlock *blocks, const int64_t *small_off,
                        const double *small, const int32_t *qk, const int64_t *out_off, double *out,
                        int32_t nblocks, int use_z, int32_t max_rows, hipStream_t s);
@@ -279,6 +282,15 @@ void col_norms2(const rad_hmat *H, const void *E, int64_t ld, int64_t R, double 
 void solve_update(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *FB,
                   const void *Bold, void *Bnew, int64_t ld, int64_t R, double *norms, hipStream_t s);
 size_t reduction_doubles(int64_t R);
+
+// elementwise operations on N x R blocks (column-major or R-major, leading dimension ld)
+enum EwOp : int32_t {
+    EW_SCALE = 0,   // z = a x
+    EW_ADD = 1,     // z = x + y
+    EW_TEMP = 2     // z = (max(0, a x + b y) / c)^(1/4)
+};
+void launch_elementwise(const rad_hmat *H, int32_t op, double a, double b, double c, const void *x, const void *y,
+                        void *z, int64_t R, int64_t ld, bool rmajor, hipStream_t s);
 
 // multi-RHS path (matmat_kernels.hip), R-major tree-ordered buffers
 constexpr int64_t kMfmaMinRhs = 16;

@@ -33,7 +33,8 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("leaf_size", ctypes.c_int32), ("max_depth", ctypes.c_int32),
                 ("nearfield", ctypes.c_int32), ("visibility", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("oversample", ctypes.c_int32), ("power_iters", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("seed", ctypes.c_uint64), ("verbose", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("seed", ctypes.c_uint64), ("verbose", ctypes.c_int32),
+                ("max_rank", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -60,7 +61,7 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_matvec", "rad_solve_opts_default", "rad_solve",
-           "rad_insolation", "rad_hmat_time_phases", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free",
+           "rad_insolation", "rad_equilibrium", "rad_hmat_time_phases", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free",
            "rad_last_error"]
 
 _lib = None
@@ -91,6 +92,10 @@ def load(path: str = LIB_PATH):
     L.rad_insolation.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_double, ctypes.c_int32, vp, ctypes.c_int64,
                                  ctypes.c_int32, vp]
     L.rad_insolation.restype = ctypes.c_int
+    L.rad_equilibrium.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int64, ctypes.c_double,
+                                  ctypes.c_double, vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo),
+                                  ctypes.POINTER(SolveInfo), vp]
+    L.rad_equilibrium.restype = ctypes.c_int
     L.rad_hmat_time_phases.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
     L.rad_hmat_time_phases.restype = ctypes.c_int
     L.rad_hmat_info.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -152,7 +157,7 @@ class HMatrix:
 
     def __init__(self, verts, faces, tol=1e-3, leaf_size=64, max_depth=0, nearfield="auto",
                  visibility="backface", storage="f64", oversample=8, power_iters=1, max_rhs=1, device=0,
-                 seed=0x5EED, verbose=False):
+                 seed=0x5EED, verbose=False, max_rank=0):
         L = load()
         o = BuildOpts()
         L.rad_build_opts_default(ctypes.byref(o))
@@ -168,6 +173,7 @@ class HMatrix:
         o.device = int(device)
         o.seed = int(seed)
         o.verbose = int(bool(verbose))
+        o.max_rank = int(max_rank)
         v = np.ascontiguousarray(verts, dtype=np.float64)
         f = np.ascontiguousarray(faces, dtype=np.int32)
         h = ctypes.c_void_p()
@@ -287,6 +293,32 @@ class HMatrix:
         if Qc.data_ptr() != out.data_ptr():
             out.copy_(Qc)
         return out
+
+    def equilibrium(self, Qdir, albedo=0.3, emissivity=0.99, rtol=1e-8, max_iter=200, order="original", R=None,
+                    use_graph=True):
+        """Two-band equilibrium temperature; returns (T, Q_vis, Q_IR, info)."""
+        torch = _torch()
+        L = load()
+        if order == "tree_rmajor":
+            R = int(R if R is not None else Qdir.shape[1])
+            Qc, ld = _rmajor(Qdir, self.N, R)
+            mk = lambda: torch.zeros_like(Qc)
+        else:
+            Q2 = Qdir.reshape(self.N, -1)
+            Qc = Q2.t().contiguous().t()
+            R, ld = Qc.shape[1], self.N
+            mk = lambda: torch.empty((R, self.N), dtype=Qc.dtype, device=Qc.device).t()
+        T, Qv, Qi = mk(), mk(), mk()
+        o = SolveOpts()
+        L.rad_solve_opts_default(ctypes.byref(o))
+        o.rtol, o.max_iter, o.order, o.use_graph = float(rtol), int(max_iter), ORDER[order], int(bool(use_graph))
+        its = [np.zeros(R, dtype=np.int32) for _ in range(2)]
+        infos = [SolveInfo(x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None, 0) for x in its]
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        _check(L.rad_equilibrium(self._h, R, self.rad_dtype, p(Qc), ld, float(albedo), float(emissivity), p(T),
+                                 p(Qv), p(Qi), ctypes.byref(o), ctypes.byref(infos[0]), ctypes.byref(infos[1]),
+                                 _stream_handle()))
+        return T, Qv, Qi, {"iters_sw": its[0], "iters_ir": its[1]}
 
     def time_phases(self, R, nrep=20):
         """Average ms per launch of (projections, split-K sum, expansion + Jacobi update)."""

@@ -287,3 +287,47 @@ def test_graph_replays_match_eager(cap, R):
             # eager work on the same stream between replays
             H.matvec(E[:, 0].contiguous())
             torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------ two-band equilibrium
+@pytest.mark.parametrize("R,order", [(1, "original"), (20, "original"), (20, "tree_rmajor")])
+def test_equilibrium_temperature(cap, R, order):
+    """GPU two-band T equals the FP64 reference chain (section 5.1) and the
+    closed form of section 7.1 on shadowed facets."""
+    from paper_2209_07632_amd.rad import ldr_of
+    verts, faces, fac, F = cap
+    e = 15.0
+    suns = np.tile([np.cos(np.deg2rad(e)), 0.0, np.sin(np.deg2rad(e))], (R, 1))
+    Q = ref.insolation(fac, suns, S=1365.0)
+    out0 = ref.equilibrium_temperature(lambda X: F @ X, Q, 0.3, 0.99)
+    H = _hm(verts, faces, tol=1e-6, storage="f64", max_rhs=R)
+    if order == "tree_rmajor":
+        perm = H.perm()
+        Qr = np.zeros((fac.N, ldr_of(R)))
+        Qr[:, :R] = Q[perm]
+        T, Qv, Qi, info = H.equilibrium(torch.from_numpy(Qr).to(DEV), order=order, R=R)
+        Tn = np.empty((fac.N, R))
+        Tn[perm] = T.cpu().numpy()[:, :R]
+        Qvn = np.empty((fac.N, R))
+        Qvn[perm] = Qv.cpu().numpy()[:, :R]
+    else:
+        T, Qv, Qi, info = H.equilibrium(torch.from_numpy(Q).to(DEV))
+        Tn, Qvn = T.cpu().numpy().reshape(fac.N, R), Qv.cpu().numpy().reshape(fac.N, R)
+    assert np.max(np.abs(Tn - out0["T"]) / out0["T"]) < 1e-5
+    assert _rel(Qvn, out0["Q_vis"]) < 1e-5
+    shadow = Q[:, 0] == 0.0
+    Tc = ref.crater_shadow_temperature(1365.0, e, 0.3, 0.99, ref.crater_f(5.0))
+    assert abs(Tn[shadow, 0].mean() - Tc) / Tc < 5e-3
+    assert np.all(info["iters_sw"] > 0) and np.all(info["iters_ir"] > 0)
+
+
+def test_tall_block_orthogonalisation_path(cap, monkeypatch):
+    """The many-workgroup CGS2 (used for blocks of thousands of rows) gives the
+    same compression quality as the single-workgroup one, forced on small blocks."""
+    verts, faces, fac, F = cap
+    X = np.random.default_rng(40).random((fac.N, 2))
+    monkeypatch.setenv("RAD_CGS2_TALL_ROWS", "100")
+    for tol in (1e-4, 1e-8):
+        H = _hm(verts, faces, tol=tol, storage="f64", max_rhs=2)
+        Y = H.matvec(torch.from_numpy(X).to(DEV)).cpu().numpy()
+        assert _rel(Y, F @ X) <= tol + 1e-6
