@@ -83,6 +83,8 @@ typedef struct {
     uint64_t seed;        /* seed of the sketch's random signs                        */
     int32_t verbose;      /* 1: print build progress and statistics to stderr         */
     int32_t max_rank;     /* 0: no limit; else Algorithm 3 gives up above this rank   */
+    int32_t lowp;         /* 0: none; RAD_F16 or RAD_BF16: also keep a 16-bit copy of the
+                             operator (needs storage RAD_F32) for refined solves       */
 } rad_build_opts;
 
 /* Fills *opts with the defaults listed above (tol 1e-3). */
@@ -107,6 +109,9 @@ rad_status rad_hmat_build(const double *verts, int64_t nv, const int32_t *faces,
  * arrays of the matrix's compute dtype (rad_hmat_dtype) in the layout named
  * by order (rad_order; leading dimensions ldx, ldy as that layout requires).
  * X and Y must not overlap.  1 <= R <= max_rhs.
+ * dtype equal to the matrix's lowp (RAD_F16 or RAD_BF16) applies the 16-bit
+ * copy of the operator instead, with FP32 X and Y and FP32 accumulation
+ * (R >= 16 only).
  * Errors: RAD_EINVAL (null, R out of range, ld < N, dtype mismatch), RAD_EDEVICE.
  */
 rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const void *X, int64_t ldx,
@@ -118,6 +123,9 @@ typedef struct {
     int32_t order;    /* rad_order of E and B                                            */
     int32_t check_every; /* read residuals back every this many iterations (default 1) */
     int32_t use_graph;   /* 1: replay each iteration as a cached HIP graph (default 1) */
+    int32_t refine;      /* 0: Jacobi on F-hat; 1: iterative refinement: FP64 residual with the
+                            FP32 operator, inner Jacobi with the 16-bit copy (needs lowp, R >= 16) */
+    int32_t inner_iters; /* inner Jacobi iterations per refinement step (default 3)  */
 } rad_solve_opts;
 
 void rad_solve_opts_default(rad_solve_opts *opts);
@@ -125,13 +133,18 @@ void rad_solve_opts_default(rad_solve_opts *opts);
 typedef struct {
     int32_t *iters;      /* host, length R (or NULL): iterations at which column met rtol (-1: never) */
     double *rel_change;  /* host, length R (or NULL): last ||B^{k+1}-B^k|| / ||E||                   */
-    int32_t total_iters; /* iterations run                                                          */
+    int32_t total_iters; /* iterations run (refinement steps when refine = 1)                      */
+    int32_t inner_iters; /* inner iterations run in total (refine = 1)                              */
 } rad_solve_info;
 
 /*
  * Solves (I - diag(rho) F-hat) B = E, the radiosity system eq.
  * radiosity-system, for R right-hand sides by Jacobi relaxation
  * B^{k+1} = E + rho (F-hat B^k), B^0 = E (sections 3 and 5.1).
+ * With opts->refine = 1 (mixed precision): B (FP64 accumulator) starts at 0;
+ * each step forms r = E - B + rho (F-hat B) in FP64 from the FP32 operator,
+ * stops columns with ||r|| <= rtol ||E||, runs inner_iters Jacobi iterations of
+ * (I - rho F16) d = r with the 16-bit operator (FP32 accumulation) and adds d.
  * rho: device array of N reflectances (original order for RAD_ORDER_ORIGINAL,
  * tree order otherwise), or NULL to use rho_scalar for every facet.  E and B
  * are device arrays of the compute dtype in the layout opts->order names; they

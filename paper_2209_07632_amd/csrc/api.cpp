@@ -31,6 +31,7 @@ static void alloc_workspace(rad_hmat *H) {
         H->w_part.alloc((size_t)H->n_parts * mm_part_rows() * ldr * s);
     H->w_q1.alloc(nr * s);
     H->w_q2.alloc(nr * s);
+    if (H->lowp) H->w_b64.alloc(nr);
     RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * (size_t)H->max_rhs, hipHostMallocDefault));
     RAD_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
 }
@@ -39,6 +40,7 @@ static void alloc_workspace(rad_hmat *H) {
 // the squared column changes in w_norms[max_rhs...], copied to pinned memory.
 struct IterArgs {
     bool mm;
+    bool lowp;
     int64_t R, ld;
     const void *E, *rho, *Bold;
     void *Bnew;
@@ -47,7 +49,9 @@ struct IterArgs {
 
 static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t s) {
     double *dn = H->w_norms.p + H->max_rhs;
-    if (a.mm) {
+    if (a.lowp) {
+        lowp_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s);
+    } else if (a.mm) {
         mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s);
     } else {
         mv_apply(H, a.Bold, a.ld, H->w_y.p, a.ld, a.R, s);
@@ -60,7 +64,7 @@ static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t 
 // launched on the caller's); the cache is keyed by every captured argument.
 static hipGraphExec_t iteration_graph(rad_hmat *H, const IterArgs &a) {
     for (auto &g : H->graphs)
-        if (g.path == (int)a.mm && g.R == a.R && g.Bold == a.Bold && g.Bnew == a.Bnew && g.E == a.E &&
+        if (g.path == (int)a.mm + 2 * (int)a.lowp && g.R == a.R && g.Bold == a.Bold && g.Bnew == a.Bnew && g.E == a.E &&
             g.rho == a.rho && g.rho_s == a.rho_s)
             return g.ex;
     if (H->graphs.size() >= 24) {
@@ -71,7 +75,7 @@ static hipGraphExec_t iteration_graph(rad_hmat *H, const IterArgs &a) {
         H->graphs.clear();
     }
     rad_hmat::GraphEntry e{};
-    e.path = (int)a.mm;
+    e.path = (int)a.mm + 2 * (int)a.lowp;
     e.R = a.R;
     e.Bold = a.Bold;
     e.Bnew = a.Bnew;
@@ -152,6 +156,8 @@ void rad_solve_opts_default(rad_solve_opts *o) {
     o->order = RAD_ORDER_ORIGINAL;
     o->check_every = 1;
     o->use_graph = 1;
+    o->refine = 0;
+    o->inner_iters = 3;
 }
 
 const char *rad_last_error(void) { return g_last_error.c_str(); }
@@ -217,8 +223,10 @@ rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const vo
     return guard([&] {
         check_hmat(H);
         RAD_REQUIRE(X && Y, "null X or Y");
-        RAD_REQUIRE(dtype == H->dtype, "dtype does not match the matrix");
+        const bool lowp = H->lowp != 0 && dtype == H->lowp;
+        RAD_REQUIRE(dtype == H->dtype || lowp, "dtype does not match the matrix");
         RAD_REQUIRE(R >= 1 && R <= H->max_rhs, "R must be in [1, max_rhs]");
+        RAD_REQUIRE(!lowp || R >= kMfmaMinRhs, "the 16-bit operator needs R >= 16");
         check_layout(H, order, R, ldx, "X");
         check_layout(H, order, R, ldy, "Y");
         RAD_HIP(hipSetDevice(H->device));
@@ -226,12 +234,18 @@ rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const vo
         const int64_t N = H->N;
         if (R >= kMfmaMinRhs) {
             int64_t ldr = mm_ldr(R);
+            auto apply = [&](const void *x, void *y) {
+                if (lowp)
+                    lowp_step(H, nullptr, nullptr, 0.0, x, y, ldr, R, nullptr, s);
+                else
+                    mm_apply(H, x, y, ldr, R, s);
+            };
             if (order == RAD_ORDER_TREE_RMAJOR) {
-                mm_apply(H, X, Y, ldr, R, s);
+                apply(X, Y);
             } else {
                 bool perm = order == RAD_ORDER_ORIGINAL;
                 mm_to_rmajor(H, X, ldx, perm, H->w_x.p, ldr, R, s);
-                mm_apply(H, H->w_x.p, H->w_y.p, ldr, R, s);
+                apply(H->w_x.p, H->w_y.p);
                 mm_from_rmajor(H, H->w_y.p, ldr, perm, Y, ldy, R, s);
             }
         } else if (order == RAD_ORDER_TREE) {
@@ -317,9 +331,72 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         std::vector<double> rel(R, 0.0);
         int k = 0;
         bool done = false;
+        if (o.refine) {
+            // iterative refinement: FP64 accumulator, FP64 residual with the FP32
+            // operator, inner Jacobi with the 16-bit copy
+            RAD_REQUIRE(H->lowp != 0, "refine needs a matrix built with lowp");
+            RAD_REQUIRE(mm, "refine needs R >= 16");
+            RAD_REQUIRE(o.inner_iters >= 1, "inner_iters must be >= 1");
+            double *B64 = H->w_b64.p;
+            float *B32 = (float *)H->w_x.p, *FB = (float *)H->w_y.p, *r = (float *)H->w_q1.p;
+            float *D[2] = {(float *)H->w_q2.p, (float *)H->w_b.p};
+            RAD_HIP(hipMemsetAsync(B64, 0, (size_t)N * ld * sizeof(double), s));
+            RAD_HIP(hipMemsetAsync(B32, 0, (size_t)N * ld * sizeof(float), s));
+            double *dn_d = H->w_norms.p + H->max_rhs;
+            int inner_total = 0;
+            while (true) {
+                const float *rp = (const float *)Ein;
+                if (k > 0) {
+                    mm_apply(H, B32, FB, ld, R, s);
+                    ir_residual(H, (const float *)Ein, B64, FB, (const float *)rho_t, rho_scalar, r, ld, R, dn_d, s);
+                    RAD_HIP(hipMemcpyAsync(dn.data(), dn_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
+                    RAD_HIP(hipStreamSynchronize(s));
+                    rp = r;
+                    done = true;
+                    for (int64_t c = 0; c < R; ++c) {
+                        double d = std::sqrt(dn[c]);
+                        rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
+                        RAD_REQUIRE(std::isfinite(rel[c]), "solve produced non-finite values");
+                        if (iters[c] < 0 && rel[c] <= o.rtol) iters[c] = k;
+                        if (iters[c] < 0) done = false;
+                    }
+                    if (done || k >= o.max_iter) break;
+                }
+                // inner: d^0 = r, d^{i} = r + rho F16 d^{i-1}
+                const void *prev = rp;
+                for (int it = 1; it <= o.inner_iters; ++it) {
+                    IterArgs a{true, true, R, ld, rp, rho_t, prev, D[(it - 1) % 2], rho_scalar};
+                    if (o.use_graph)
+                        RAD_HIP(hipGraphLaunch(iteration_graph(Hm, a), s));
+                    else
+                        enqueue_iteration(H, a, s);
+                    prev = D[(it - 1) % 2];
+                }
+                inner_total += o.inner_iters;
+                ir_update(H, B64, (const float *)prev, B32, ld, R, s);
+                ++k;
+            }
+            void *Bk = B32;
+            if (rmaj)
+                RAD_HIP(hipMemcpyAsync(B, Bk, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
+            else
+                mm_from_rmajor(H, Bk, ld, o.order == RAD_ORDER_ORIGINAL, B, ldb, R, s);
+            RAD_HIP(hipStreamSynchronize(s));
+            if (info) {
+                if (info->iters) std::copy(iters.begin(), iters.end(), info->iters);
+                if (info->rel_change) std::copy(rel.begin(), rel.end(), info->rel_change);
+                info->total_iters = k;
+                info->inner_iters = inner_total;
+            }
+            if (!done) {
+                conv = RAD_ENOCONV;
+                set_error("refinement reached max_iter before rtol");
+            }
+            return;
+        }
         while (k < o.max_iter && !done) {
             ++k;
-            IterArgs a{mm, R, ld, Ein, rho_t, k == 1 ? Ein : P[k % 2], P[(k - 1) % 2], rho_scalar};
+            IterArgs a{mm, false, R, ld, Ein, rho_t, k == 1 ? Ein : P[k % 2], P[(k - 1) % 2], rho_scalar};
             if (o.use_graph)
                 RAD_HIP(hipGraphLaunch(iteration_graph(Hm, a), s));
             else
@@ -354,6 +431,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             if (info->iters) std::copy(iters.begin(), iters.end(), info->iters);
             if (info->rel_change) std::copy(rel.begin(), rel.end(), info->rel_change);
             info->total_iters = k;
+            info->inner_iters = 0;
         }
         if (!done) {
             conv = RAD_ENOCONV;

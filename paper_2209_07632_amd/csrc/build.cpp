@@ -634,7 +634,8 @@ struct Builder {
             ProjGroup g{};
             g.j0 = cn.start;
             g.n = cn.size;
-            g.ld = round4(cn.size);
+            g.ld = (cn.size + 7) / 8 * 8;  // 16-byte rows for the 16-bit copy too
+            vfill = (vfill + 7) / 8 * 8;
             g.t_off = t_fill;
             int32_t ktot = 0;
             for (int64_t p : by_col[J]) ktot += bp[p].rank;
@@ -894,6 +895,17 @@ struct Builder {
                                (int64_t)H->d_brow.bytes() + (int64_t)H->d_groups.bytes() +
                                (int64_t)H->d_tile_tasks.bytes() + (int64_t)H->d_perm.bytes();
         H->stats.flops_per_rhs = 2.0 * ((double)H->stats.lowrank_elems + (double)H->stats.nnz_near);
+        if (o.lowp) {
+            H->lowp = o.lowp;
+            H->d_vals16.alloc((size_t)std::max<int64_t>(vfill, 1));
+            RAD_HIP(hipMemsetAsync(H->d_vals16.p, 0, (size_t)std::max<int64_t>(vfill, 1) * 2, st));
+            H->d_pscale.alloc((size_t)std::max<int64_t>(csr_val_start / 64 + 1, 1));
+            H->d_tscale.alloc((size_t)std::max<int32_t>(t_fill, 1));
+            lowp_convert(H, st);
+            RAD_HIP(hipStreamSynchronize(st));
+            H->stats.bytes_total += (int64_t)H->d_vals16.bytes() + (int64_t)H->d_pscale.bytes() +
+                                    (int64_t)H->d_tscale.bytes();
+        }
     }
 };
 
@@ -913,6 +925,8 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
     RAD_REQUIRE(o.oversample >= 2 && o.oversample <= 64, "oversample must be in [2, 64]");
     RAD_REQUIRE(o.power_iters >= 0 && o.power_iters <= 4, "power_iters must be in [0, 4]");
     RAD_REQUIRE(o.max_rhs >= 1, "max_rhs must be >= 1");
+    RAD_REQUIRE(o.lowp == 0 || ((o.lowp == RAD_F16 || o.lowp == RAD_BF16) && o.storage == RAD_F32),
+                "lowp must be 0, RAD_F16 or RAD_BF16, with storage RAD_F32");
 
     Builder B;
     B.log.on = o.verbose != 0;

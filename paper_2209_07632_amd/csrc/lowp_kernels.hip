@@ -1,0 +1,443 @@
+// 16-bit (FP16 or BF16) copy of the compressed operator for the inner solves
+// of iterative refinement: matrix-core products with FP32 accumulation.
+//
+// Scaling: every panel column k (a column of U' or of a dense block restricted
+// to one 64-row tile) is stored as A[:, k] * c_k with c_k a power of two that
+// brings max |A[:, k]| into [0.5, 1); the operand row it multiplies is staged
+// as B[k, :] / c_k, so the product is unchanged.  Every stacked V column kk is
+// stored as V[:, kk] * d_kk and the projection is divided by d_kk when the
+// split-K partials are summed.  Powers of two make the scaling exact.
+//
+// 16-bit panels are stored per 32-column chunk as 64 rows x 32 values with the
+// reduction index contiguous (the operand layout of v_mfma_f32_16x16x32_*:
+// lane l holds A[l % 16][8 (l / 16) .. 8 (l / 16) + 7]), at the same element
+// offsets as the FP32 panels.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <algorithm>
+
+#include "mm_epilogue.h"
+#include "rad_internal.h"
+
+namespace rad {
+
+namespace {
+
+constexpr int TM = 64, TN = 128, KC = 32, LDK = KC + 8;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <class H>
+struct M16;
+template <>
+struct M16<_Float16> {
+    typedef f16x8 vec;
+    static __device__ __forceinline__ f32x4 run(vec a, vec b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct M16<__bf16> {
+    typedef bf16x8 vec;
+    static __device__ __forceinline__ f32x4 run(vec a, vec b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+// power of two p with max_abs * p in [0.5, 1) (1 for an all-zero column)
+__device__ __forceinline__ float pow2_scale(float max_abs) {
+    if (!(max_abs > 0.0f)) return 1.0f;
+    int e;
+    frexpf(max_abs, &e);  // max_abs = m 2^e, m in [0.5, 1)
+    return ldexpf(1.0f, -e);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// conversion (build time)
+// ---------------------------------------------------------------------------
+template <class H>
+__global__ void __launch_bounds__(256) k_lowp_panels(const float *vals, const TileInfo *tiles, H *out, float *pscale) {
+    const TileInfo ti = tiles[blockIdx.x];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = w; k < ti.kpad; k += 4) {
+        const float v = vals[ti.panel_off + (int64_t)k * TM + lane];
+        const float c = pow2_scale(wave_max(fabsf(v)));
+        out[ti.panel_off + (int64_t)(k / KC) * TM * KC + lane * KC + (k % KC)] = (H)(v * c);
+        if (lane == 0) pscale[ti.panel_off / TM + k] = c;
+    }
+}
+
+template <class H>
+__global__ void __launch_bounds__(256) k_lowp_v(const float *vals, const ProjGroup *groups, H *out, float *tscale) {
+    const ProjGroup g = groups[blockIdx.x];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int kk = blockIdx.y * 4 + w; kk < g.ktot; kk += gridDim.y * 4) {
+        const float *v = vals + g.v_off + (int64_t)kk * g.ld;
+        float m = 0.0f;
+        for (int j = lane; j < g.n; j += 64) m = fmaxf(m, fabsf(v[j]));
+        const float d = pow2_scale(wave_max(m));
+        H *o = out + g.v_off + (int64_t)kk * g.ld;
+        for (int j = lane; j < g.ld; j += 64) o[j] = (H)(j < g.n ? v[j] * d : 0.0f);
+        if (lane == 0) tscale[g.t_off + kk] = d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// products
+// ---------------------------------------------------------------------------
+template <class H>
+struct Acc16 {
+    f32x4 acc[4][2];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    }
+    __device__ __forceinline__ void mma(const H (*sA)[LDK], const H (*sB)[LDK], int lane, int w) {
+        typedef typename M16<H>::vec vec;
+        const int lr = lane & 15, k0 = 8 * (lane >> 4);
+        vec a[4], b[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = *(const vec *)&sA[i * 16 + lr][k0];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *(const vec *)&sB[w * 32 + j * 16 + lr][k0];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = M16<H>::run(a[i], b[j], acc[i][j]);
+    }
+};
+
+// B chunk: 32 operand rows (FP32, R-major) times 128 columns, each row divided
+// by its scale, converted and stored with the reduction index contiguous
+template <class H>
+struct StageB16 {
+    float v[16];
+    __device__ __forceinline__ void fetch(const float *const *rowp, const float *inv, int r0, int R, int t) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int e = t + q * 256;
+            int k = e >> 5, c = (e & 31) * 4;
+            const float *p = rowp[k];
+            float s = inv[k];
+            float4 x = make_float4(0, 0, 0, 0);
+            if (p) {
+                if (r0 + c + 3 < R) {
+                    x = *(const float4 *)(p + r0 + c);
+                } else {
+                    if (r0 + c < R) x.x = p[r0 + c];
+                    if (r0 + c + 1 < R) x.y = p[r0 + c + 1];
+                    if (r0 + c + 2 < R) x.z = p[r0 + c + 2];
+                }
+            }
+            v[4 * q] = x.x * s;
+            v[4 * q + 1] = x.y * s;
+            v[4 * q + 2] = x.z * s;
+            v[4 * q + 3] = x.w * s;
+        }
+    }
+    __device__ __forceinline__ void commit(H (*sB)[LDK], int t) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int e = t + q * 256;
+            int k = e >> 5, c = (e & 31) * 4;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sB[c + u][k] = (H)v[4 * q + u];
+        }
+    }
+};
+
+template <class H>
+__global__ void __launch_bounds__(256) k_proj_mm16(const ProjGroup *groups, const P1Work *work, const H *vals16,
+                                                    const float *X, int64_t ldr, int R, float *part) {
+    const P1Work wk = work[blockIdx.x];
+    const ProjGroup g = groups[wk.group];
+    const int r0 = blockIdx.y * TN;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    __shared__ __align__(16) H sA[2][TM][LDK];
+    __shared__ __align__(16) H sB[2][TN][LDK];
+    __shared__ const float *rowp[2][KC];
+    __shared__ float one[KC];
+    if (t < KC) one[t] = 1.0f;
+    Acc16<H> acc;
+    acc.zero();
+    const int rows = min(TM, g.ktot - wk.krow0);
+    const H *V = vals16 + g.v_off + (int64_t)wk.krow0 * g.ld;
+    StageB16<H> sb;
+    // A: row r (a V column) x 32 consecutive facets: four 16-byte pieces per row
+    auto fetchA = [&](int kb, typename M16<H>::vec &va) {
+        int r = t >> 2, k8 = (t & 3) * 8;
+        typename M16<H>::vec z{};
+        va = z;
+        if (r < rows) {
+            const H *p = V + (int64_t)r * g.ld + kb + k8;
+            if (kb + k8 + 7 < wk.je) {
+                va = *(const typename M16<H>::vec *)p;
+            } else {
+                for (int u = 0; u < 8; ++u)
+                    if (kb + k8 + u < wk.je) va[u] = p[u];
+            }
+        }
+    };
+    auto setrows = [&](int kb, int buf) {
+        if (t < KC) rowp[buf][t] = (kb + t < wk.je) ? X + ((int64_t)g.j0 + kb + t) * ldr : nullptr;
+    };
+    typename M16<H>::vec va;
+    int buf = 0;
+    setrows(wk.jb, 0);
+    __syncthreads();
+    fetchA(wk.jb, va);
+    sb.fetch(rowp[0], one, r0, R, t);
+    for (int kb = wk.jb; kb < wk.je; kb += KC) {
+        *(typename M16<H>::vec *)&sA[buf][t >> 2][(t & 3) * 8] = va;
+        sb.commit(sB[buf], t);
+        if (kb + KC < wk.je) setrows(kb + KC, buf ^ 1);
+        __syncthreads();
+        if (kb + KC < wk.je) {
+            fetchA(kb + KC, va);
+            sb.fetch(rowp[buf ^ 1], one, r0, R, t);
+        }
+        acc.mma(sA[buf], sB[buf], lane, w);
+        buf ^= 1;
+    }
+    float *out = part + (int64_t)wk.part * TM * ldr;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int row = i * 16 + 4 * lk + v;
+                int col = r0 + w * 32 + j * 16 + lr;
+                if (col < R) out[(int64_t)row * ldr + col] = acc.acc[i][j][v];
+            }
+}
+
+// T rows = (sum of the split partials) / d_row
+__global__ void __launch_bounds__(256) k_proj_reduce16(const P1Red *red, const float *part, const float *tscale,
+                                                        int64_t ldr, int R, float *Tb) {
+    const P1Red rd = red[blockIdx.x / TM];
+    const int row = blockIdx.x % TM;
+    const int c = blockIdx.y * 256 + threadIdx.x;
+    if (c >= R || row >= rd.nrows) return;
+    float s = 0.0f;
+    for (int p = 0; p < rd.part_count; ++p) s += part[((int64_t)(rd.part_begin + p) * TM + row) * ldr + c];
+    Tb[(int64_t)(rd.t_row0 + row) * ldr + c] = s / tscale[rd.t_row0 + row];
+}
+
+template <class H, bool kFused>
+__global__ void __launch_bounds__(256) k_tile_mm16(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
+                                                    const H *vals16, const float *pscale, const float *vals32,
+                                                    const int32_t *csr_ptr, const int32_t *csr_idx,
+                                                    int64_t csr_val_start, const float *X, const float *Tb,
+                                                    int64_t ldr, int R, int64_t N, float *Y, const float *E,
+                                                    const float *rho, float rho_s, double *partial) {
+    const int tile = blockIdx.x;
+    const TileInfo ti = tiles[tile];
+    const int64_t tile0 = (int64_t)tile * TM;
+    const int r0 = blockIdx.y * TN;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    constexpr int kPipe = (2 * TM * LDK + 2 * TN * LDK) * 2;
+    constexpr int kOut = TM * (TN + 4) * 4;
+    __shared__ __align__(16) unsigned char smem[kPipe > kOut ? kPipe : kOut];
+    H (*sA)[TM][LDK] = (H (*)[TM][LDK])smem;
+    H (*sB)[TN][LDK] = (H (*)[TN][LDK])(smem + 2 * TM * LDK * sizeof(H));
+    __shared__ const float *rowp[2][KC];
+    __shared__ float inv[2][KC];
+    Acc16<H> acc;
+    acc.zero();
+    StageB16<H> sb;
+    // CSR tasks (FP32 values, unit scale), expanded to dense chunks in LDS
+    for (int c = ti.csr_begin; c < ti.csr_end; ++c) {
+        const TileTask tk = ctasks[c];
+        const float *v = vals32 + tk.a_off;
+        const int32_t *ci = csr_idx + (tk.a_off - csr_val_start);
+        int cur = 0, end = 0;
+        if (t >= tk.r_lo && t < tk.r_hi) {
+            cur = csr_ptr[tk.aux_off + tk.row_off + t];
+            end = csr_ptr[tk.aux_off + tk.row_off + t + 1];
+        }
+        for (int kb = 0; kb < tk.ncol; kb += KC) {
+            for (int e = t; e < TM * KC; e += 256) sA[0][e / KC][e % KC] = (H)0.0f;
+            if (t < KC) {
+                rowp[0][t] = (kb + t < tk.ncol) ? X + ((int64_t)tk.col0 + kb + t) * ldr : nullptr;
+                inv[0][t] = 1.0f;
+            }
+            __syncthreads();
+            while (cur < end && ci[cur] < kb + KC) {
+                sA[0][t][ci[cur] - kb] = (H)v[cur];
+                ++cur;
+            }
+            sb.fetch(rowp[0], inv[0], r0, R, t);
+            sb.commit(sB[0], t);
+            __syncthreads();
+            acc.mma(sA[0], sB[0], lane, w);
+            __syncthreads();
+        }
+    }
+    // packed panel
+    if (ti.kpad > 0) {
+        const H *pan = vals16 + ti.panel_off;
+        const float *ps = pscale + ti.panel_off / TM;
+        const int32_t *br = brow + ti.brow_off;
+        auto setrows = [&](int kb, int b) {
+            if (t < KC) {
+                int32_t v = br[kb + t];
+                rowp[b][t] = v >= 0 ? X + (int64_t)v * ldr : Tb + (int64_t)(-1 - v) * ldr;
+                inv[b][t] = 1.0f / ps[kb + t];
+            }
+        };
+        typedef typename M16<H>::vec vec;
+        vec va;
+        int buf = 0;
+        setrows(0, 0);
+        __syncthreads();
+        va = *(const vec *)(pan + t * 8);
+        sb.fetch(rowp[0], inv[0], r0, R, t);
+        for (int kb = 0; kb < ti.kpad; kb += KC) {
+            *(vec *)&sA[buf][t >> 2][(t & 3) * 8] = va;
+            sb.commit(sB[buf], t);
+            if (kb + KC < ti.kpad) setrows(kb + KC, buf ^ 1);
+            __syncthreads();
+            if (kb + KC < ti.kpad) {
+                va = *(const vec *)(pan + (int64_t)(kb + KC) * TM + t * 8);
+                sb.fetch(rowp[buf ^ 1], inv[buf ^ 1], r0, R, t);
+            }
+            acc.mma(sA[buf], sB[buf], lane, w);
+            buf ^= 1;
+        }
+    }
+    __syncthreads();
+    float (*sC)[TN + 4] = (float (*)[TN + 4])smem;
+    {
+        const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sC[i * 16 + 4 * lk + v][w * 32 + j * 16 + lr] = acc.acc[i][j][v];
+    }
+    __syncthreads();
+    tile_epilogue<float, kFused, TM, TN, TN + 4>(sC, smem, tile, tile0, r0, ldr, R, N, Y, E, X, rho, rho_s, partial);
+}
+
+template <class H>
+void convert_t(rad_hmat *H_, hipStream_t s) {
+    H *out = (H *)H_->d_vals16.p;
+    const float *vals = (const float *)H_->d_vals.p;
+    if (H_->n_tiles > 0)
+        hipLaunchKernelGGL(k_lowp_panels<H>, dim3(H_->n_tiles), dim3(256), 0, s, vals, H_->d_tiles.p, out,
+                           H_->d_pscale.p);
+    if (H_->n_groups > 0)
+        hipLaunchKernelGGL(k_lowp_v<H>, dim3(H_->n_groups, 16), dim3(256), 0, s, vals, H_->d_groups.p, out,
+                           H_->d_tscale.p);
+    RAD_HIP(hipGetLastError());
+}
+
+template <class H>
+void step16_t(const rad_hmat *Hm, const float *E, const float *rho, float rho_s, const float *Bold, float *Bnew,
+              int64_t ldr, int R, double *norms, hipStream_t s) {
+    unsigned rtiles = (unsigned)((R + TN - 1) / TN);
+    const H *v16 = (const H *)Hm->d_vals16.p;
+    if (Hm->n_p1work > 0) {
+        hipLaunchKernelGGL(k_proj_mm16<H>, dim3(Hm->n_p1work, rtiles), dim3(256), 0, s, Hm->d_groups.p,
+                           Hm->d_p1work.p, v16, Bold, ldr, R, (float *)Hm->w_part.p);
+        hipLaunchKernelGGL(k_proj_reduce16, dim3(Hm->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s, Hm->d_p1red.p,
+                           (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)Hm->w_t.p);
+        RAD_HIP(hipGetLastError());
+    }
+    double *part = (double *)Hm->w_red.p;
+    if (E)
+        hipLaunchKernelGGL((k_tile_mm16<H, true>), dim3(Hm->n_tiles, rtiles), dim3(256), 0, s, Hm->d_tiles.p,
+                           Hm->d_brow.p, Hm->d_tile_tasks.p, v16, Hm->d_pscale.p, (const float *)Hm->d_vals.p,
+                           Hm->d_csr_ptr.p, Hm->d_csr_idx.p, Hm->csr_val_start, Bold, (const float *)Hm->w_t.p, ldr,
+                           R, Hm->N, Bnew, E, rho, rho_s, part);
+    else
+        hipLaunchKernelGGL((k_tile_mm16<H, false>), dim3(Hm->n_tiles, rtiles), dim3(256), 0, s, Hm->d_tiles.p,
+                           Hm->d_brow.p, Hm->d_tile_tasks.p, v16, Hm->d_pscale.p, (const float *)Hm->d_vals.p,
+                           Hm->d_csr_ptr.p, Hm->d_csr_idx.p, Hm->csr_val_start, Bold, (const float *)Hm->w_t.p, ldr,
+                           R, Hm->N, Bnew, E, rho, rho_s, part);
+    RAD_HIP(hipGetLastError());
+    if (E) mm_reduce_cols(Hm, part, Hm->n_tiles, R, norms, s);
+}
+
+// r = E - B + rho (F B) in FP64 (stored FP32); partial[tile * R + c] = sum of r^2
+__global__ void __launch_bounds__(256) k_ir_resid(const float *E, const double *B64, const float *FB, const float *rho,
+                                                   double rho_s, float *r, int64_t N, int64_t ldr, int R,
+                                                   double *partial) {
+    const int c = blockIdx.y * 256 + threadIdx.x;
+    if (c >= R) return;
+    const int64_t t0 = (int64_t)blockIdx.x * TM, t1 = min(N, t0 + TM);
+    double s = 0.0;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t e = t * ldr + c;
+        const double rh = rho ? (double)rho[t] : rho_s;
+        const double v = (double)E[e] - B64[e] + rh * (double)FB[e];
+        r[e] = (float)v;
+        s += v * v;
+    }
+    partial[(int64_t)blockIdx.x * R + c] = s;
+}
+
+// B64 += d; B32 = (float) B64
+__global__ void __launch_bounds__(256) k_ir_update(double *B64, const float *d, float *B32, int64_t N, int64_t ldr,
+                                                    int R) {
+    const int c = blockIdx.y * 256 + threadIdx.x;
+    if (c >= R) return;
+    const int64_t t0 = (int64_t)blockIdx.x * TM, t1 = min(N, t0 + TM);
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t e = t * ldr + c;
+        const double b = B64[e] + (double)d[e];
+        B64[e] = b;
+        B32[e] = (float)b;
+    }
+}
+
+}  // namespace
+
+void ir_residual(const rad_hmat *H, const float *E, const double *B64, const float *FB, const float *rho, double rho_s,
+                 float *r, int64_t ldr, int64_t R, double *norms, hipStream_t s) {
+    double *part = (double *)H->w_red.p;
+    dim3 grid((unsigned)H->n_tiles, (unsigned)((R + 255) / 256));
+    hipLaunchKernelGGL(k_ir_resid, grid, dim3(256), 0, s, E, B64, FB, rho, rho_s, r, H->N, ldr, (int)R, part);
+    RAD_HIP(hipGetLastError());
+    mm_reduce_cols(H, part, H->n_tiles, R, norms, s);
+}
+
+void ir_update(const rad_hmat *H, double *B64, const float *d, float *B32, int64_t ldr, int64_t R, hipStream_t s) {
+    dim3 grid((unsigned)H->n_tiles, (unsigned)((R + 255) / 256));
+    hipLaunchKernelGGL(k_ir_update, grid, dim3(256), 0, s, B64, d, B32, H->N, ldr, (int)R);
+    RAD_HIP(hipGetLastError());
+}
+
+void lowp_convert(rad_hmat *H, hipStream_t s) {
+    if (H->lowp == RAD_F16)
+        convert_t<_Float16>(H, s);
+    else
+        convert_t<__bf16>(H, s);
+}
+
+// One product (E == nullptr: Bnew = F16 Bold) or fused Jacobi step with the 16-bit operator.
+void lowp_step(const rad_hmat *H, const void *E, const void *rho, double rho_s, const void *Bold, void *Bnew,
+               int64_t ldr, int64_t R, double *norms, hipStream_t s) {
+    if (H->lowp == RAD_F16)
+        step16_t<_Float16>(H, (const float *)E, (const float *)rho, (float)rho_s, (const float *)Bold, (float *)Bnew,
+                           ldr, (int)R, norms, s);
+    else
+        step16_t<__bf16>(H, (const float *)E, (const float *)rho, (float)rho_s, (const float *)Bold, (float *)Bnew,
+                         ldr, (int)R, norms, s);
+}
+
+}  // namespace rad

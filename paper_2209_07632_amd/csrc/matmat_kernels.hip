@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "rad_internal.h"
+#include "mm_epilogue.h"
 
 namespace rad {
 
@@ -398,86 +399,7 @@ __global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const in
                 for (int v = 0; v < 4; ++v) sC[i * 16 + Mfma<T>::row(lk, v)][w * 32 + j * 16 + lr] = acc.acc[i][j][v];
     }
     __syncthreads();
-    const int rows = (int)min((int64_t)TM, N - tile0);
-    const int c4 = (t & 31) * 4;          // this thread's four columns
-    const int rsub = t >> 5;              // rows rsub, rsub + 8, ...
-    const int col = r0 + c4;
-    double d2[4] = {0.0, 0.0, 0.0, 0.0};
-    const bool full = col + 3 < R;
-    // rows rsub + 8q in two halves of four: all loads of a half first, then
-    // the arithmetic and the stores
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        T ev[4][4], bo[4][4];
-        if constexpr (kFused) {
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                const int row = rsub + 8 * (4 * half + qq);
-                const int64_t e = (tile0 + row) * ldr + col;
-                if (row < rows && full) {
-                    if constexpr (sizeof(T) == 4) {
-                        float4 a = *(const float4 *)(E + e), o = *(const float4 *)(X + e);
-                        ev[qq][0] = a.x; ev[qq][1] = a.y; ev[qq][2] = a.z; ev[qq][3] = a.w;
-                        bo[qq][0] = o.x; bo[qq][1] = o.y; bo[qq][2] = o.z; bo[qq][3] = o.w;
-                    } else {
-                        double2 a0 = *(const double2 *)(E + e), a1 = *(const double2 *)(E + e + 2);
-                        double2 o0 = *(const double2 *)(X + e), o1 = *(const double2 *)(X + e + 2);
-                        ev[qq][0] = a0.x; ev[qq][1] = a0.y; ev[qq][2] = a1.x; ev[qq][3] = a1.y;
-                        bo[qq][0] = o0.x; bo[qq][1] = o0.y; bo[qq][2] = o1.x; bo[qq][3] = o1.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        bool ok = row < rows && col + u < R;
-                        ev[qq][u] = ok ? E[e + u] : (T)0;
-                        bo[qq][u] = ok ? X[e + u] : (T)0;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
-            const int row = rsub + 8 * (4 * half + qq);
-            if (row < rows) {
-                const int64_t e = (tile0 + row) * ldr + col;
-                T y[4] = {sC[row][c4], sC[row][c4 + 1], sC[row][c4 + 2], sC[row][c4 + 3]};
-                if constexpr (kFused) {
-                    T rh = rho ? rho[tile0 + row] : rho_s;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        T bn = ev[qq][u] + rh * y[u];
-                        double d = (double)bn - (double)bo[qq][u];
-                        if (col + u < R) d2[u] += d * d;
-                        y[u] = bn;
-                    }
-                }
-                if (full) {
-                    if constexpr (sizeof(T) == 4) {
-                        *(float4 *)(Y + e) = make_float4(y[0], y[1], y[2], y[3]);
-                    } else {
-                        *(double2 *)(Y + e) = make_double2(y[0], y[1]);
-                        *(double2 *)(Y + e + 2) = make_double2(y[2], y[3]);
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (col + u < R) Y[e + u] = y[u];
-                }
-            }
-        }
-    }
-    if constexpr (kFused) {
-        __syncthreads();
-        double *red = (double *)smem;   // 8 x 128 partial sums (fits in the LDS tile)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) red[rsub * TN + c4 + u] = d2[u];
-        __syncthreads();
-        if (t < TN) {
-            double sum = 0.0;
-            for (int q = 0; q < 8; ++q) sum += red[q * TN + t];
-            if (r0 + t < R) partial[(int64_t)tile * R + r0 + t] = sum;
-        }
-    }
+    tile_epilogue<T, kFused, TM, TN, TN + PADB>(sC, smem, tile, tile0, r0, ldr, R, N, Y, E, X, rho, rho_s, partial);
 }
 
 // col-major (original or tree order) <-> R-major tree order, 64 x 64 tiles
@@ -691,6 +613,12 @@ void mm_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, doubl
         time_phases_t<double>(H, (int)R, nrep, s, ms);
     else
         time_phases_t<float>(H, (int)R, nrep, s, ms);
+}
+
+void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s) {
+    (void)H;
+    hipLaunchKernelGGL(k_reduce_rm, dim3((unsigned)((R + 15) / 16)), dim3(256), 0, s, partial, nparts, (int)R, out);
+    RAD_HIP(hipGetLastError());
 }
 
 size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R) {

@@ -225,6 +225,12 @@ struct rad_hmat {
 
     // workspace (sized for max_rhs)
     rad::DevBuf<unsigned char> w_x, w_y, w_t, w_b, w_e, w_rho, w_red, w_part, w_q1, w_q2;
+    rad::DevBuf<double> w_b64;            // FP64 accumulator of refined solves
+
+    // 16-bit copy of the operator (panels and stacked V, power-of-two scales)
+    int32_t lowp = 0;
+    rad::DevBuf<uint16_t> d_vals16;
+    rad::DevBuf<float> d_pscale, d_tscale;
     rad::DevBuf<double> w_norms;
 };
 
@@ -305,6 +311,15 @@ void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, dou
 void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
                     int64_t ldr, int64_t R, double *norms, hipStream_t s);
 size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R);
+void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s);
+
+// 16-bit operator (lowp_kernels.hip)
+void lowp_convert(rad_hmat *H, hipStream_t s);
+void lowp_step(const rad_hmat *H, const void *E, const void *rho, double rho_s, const void *Bold, void *Bnew,
+               int64_t ldr, int64_t R, double *norms, hipStream_t s);
+void ir_residual(const rad_hmat *H, const float *E, const double *B64, const float *FB, const float *rho, double rho_s,
+                 float *r, int64_t ldr, int64_t R, double *norms, hipStream_t s);
+void ir_update(const rad_hmat *H, double *B64, const float *d, float *B32, int64_t ldr, int64_t R, hipStream_t s);
 void mm_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, double *ms);
 
 }  // namespace rad

@@ -34,17 +34,18 @@ class BuildOpts(ctypes.Structure):
                 ("nearfield", ctypes.c_int32), ("visibility", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("oversample", ctypes.c_int32), ("power_iters", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("seed", ctypes.c_uint64), ("verbose", ctypes.c_int32),
-                ("max_rank", ctypes.c_int32)]
+                ("max_rank", ctypes.c_int32), ("lowp", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.POINTER(ctypes.c_int32)), ("rel_change", ctypes.POINTER(ctypes.c_double)),
-                ("total_iters", ctypes.c_int32)]
+                ("total_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -157,7 +158,7 @@ class HMatrix:
 
     def __init__(self, verts, faces, tol=1e-3, leaf_size=64, max_depth=0, nearfield="auto",
                  visibility="backface", storage="f64", oversample=8, power_iters=1, max_rhs=1, device=0,
-                 seed=0x5EED, verbose=False, max_rank=0):
+                 seed=0x5EED, verbose=False, max_rank=0, lowp=None):
         L = load()
         o = BuildOpts()
         L.rad_build_opts_default(ctypes.byref(o))
@@ -174,6 +175,7 @@ class HMatrix:
         o.seed = int(seed)
         o.verbose = int(bool(verbose))
         o.max_rank = int(max_rank)
+        o.lowp = {None: 0, "f16": RAD_F16, "bf16": RAD_BF16}[lowp]
         v = np.ascontiguousarray(verts, dtype=np.float64)
         f = np.ascontiguousarray(faces, dtype=np.int32)
         h = ctypes.c_void_p()
@@ -182,6 +184,7 @@ class HMatrix:
         self._h = h
         self.N = int(L.rad_hmat_n(h))
         self.rad_dtype = int(L.rad_hmat_dtype(h))
+        self.lowp = int(o.lowp)
         self.max_rhs = int(max_rhs)
         self.device = int(device)
 
@@ -200,17 +203,19 @@ class HMatrix:
         _check(load().rad_hmat_perm(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return p
 
-    def matvec(self, X, out=None, order="original", R=None):
+    def matvec(self, X, out=None, order="original", R=None, lowp=False):
         """Y = F-hat X.  Column-major orders take X of shape (N,) or (N, R);
-        order="tree_rmajor" takes the internal layout, shape (N, ldr_of(R))."""
+        order="tree_rmajor" takes the internal layout, shape (N, ldr_of(R)).
+        lowp=True applies the 16-bit copy of the operator (FP32 X and Y)."""
         torch = _torch()
+        dt = self.lowp if lowp else self.rad_dtype
         if order == "tree_rmajor":
             R = int(R if R is not None else X.shape[1])
             Xc, ldx = _rmajor(X, self.N, R)
             if out is None:
                 out = torch.zeros_like(X)
             Yc, ldy = _rmajor(out, self.N, R)
-            _check(load().rad_hmat_matvec(self._h, R, self.rad_dtype, ctypes.c_void_p(Xc.data_ptr()), ldx,
+            _check(load().rad_hmat_matvec(self._h, R, dt, ctypes.c_void_p(Xc.data_ptr()), ldx,
                                           ctypes.c_void_p(Yc.data_ptr()), ldy, ORDER[order], _stream_handle()))
             return out
         squeeze = X.dim() == 1
@@ -219,14 +224,14 @@ class HMatrix:
         if out is None:
             out = torch.empty((R, self.N), dtype=X.dtype, device=X.device).t()
         Yc, ldy = _colmajor(out, self.N)
-        _check(load().rad_hmat_matvec(self._h, R, self.rad_dtype, ctypes.c_void_p(Xc.data_ptr()), ldx,
+        _check(load().rad_hmat_matvec(self._h, R, dt, ctypes.c_void_p(Xc.data_ptr()), ldx,
                                       ctypes.c_void_p(Yc.data_ptr()), ldy, ORDER[order], _stream_handle()))
         if Yc.data_ptr() != out.data_ptr():
             out.copy_(Yc)
         return out.reshape(-1) if squeeze else out
 
     def solve(self, E, rho=0.3, rtol=1e-3, max_iter=100, order="original", check_every=1, out=None,
-              raise_on_noconv=True, use_graph=True, R=None):
+              raise_on_noconv=True, use_graph=True, R=None, refine=False, inner_iters=3):
         """Jacobi solve of (I - diag(rho) F-hat) B = E; returns (B, info dict)."""
         torch = _torch()
         L = load()
@@ -258,10 +263,12 @@ class HMatrix:
         o.order = ORDER[order]
         o.check_every = int(check_every)
         o.use_graph = int(bool(use_graph))
+        o.refine = int(bool(refine))
+        o.inner_iters = int(inner_iters)
         iters = np.zeros(R, dtype=np.int32)
         rel = np.zeros(R, dtype=np.float64)
         info = SolveInfo(iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                         rel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0)
+                         rel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0, 0)
         st = L.rad_solve(self._h, rho_ptr, rho_s, R, self.rad_dtype, ctypes.c_void_p(Ec.data_ptr()), lde,
                          ctypes.c_void_p(Bc.data_ptr()), ldb, ctypes.byref(o), ctypes.byref(info),
                          _stream_handle())
@@ -270,7 +277,7 @@ class HMatrix:
         if Bc.data_ptr() != out.data_ptr():
             out.copy_(Bc)
         res = {"iters": iters, "rel_change": rel, "total_iters": int(info.total_iters),
-               "converged": st == RAD_OK}
+               "inner_iters": int(info.inner_iters), "converged": st == RAD_OK}
         return (out.reshape(-1) if squeeze else out), res
 
     def insolation(self, suns, flux=1365.0, order="original", out=None):
@@ -313,7 +320,7 @@ class HMatrix:
         L.rad_solve_opts_default(ctypes.byref(o))
         o.rtol, o.max_iter, o.order, o.use_graph = float(rtol), int(max_iter), ORDER[order], int(bool(use_graph))
         its = [np.zeros(R, dtype=np.int32) for _ in range(2)]
-        infos = [SolveInfo(x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None, 0) for x in its]
+        infos = [SolveInfo(x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None, 0, 0) for x in its]
         p = lambda t: ctypes.c_void_p(t.data_ptr())
         _check(L.rad_equilibrium(self._h, R, self.rad_dtype, p(Qc), ld, float(albedo), float(emissivity), p(T),
                                  p(Qv), p(Qi), ctypes.byref(o), ctypes.byref(infos[0]), ctypes.byref(infos[1]),

@@ -331,3 +331,82 @@ def test_tall_block_orthogonalisation_path(cap, monkeypatch):
         H = _hm(verts, faces, tol=tol, storage="f64", max_rhs=2)
         Y = H.matvec(torch.from_numpy(X).to(DEV)).cpu().numpy()
         assert _rel(Y, F @ X) <= tol + 1e-6
+
+
+# ------------------------------------------------------------ 16-bit operator + refinement
+# unit roundoff of the 16-bit formats (round to nearest)
+U16 = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+@pytest.mark.parametrize("lowp", ["f16", "bf16"])
+@pytest.mark.parametrize("R", [16, 130])
+def test_lowp_matvec(cap, lowp, R):
+    """The 16-bit copy of F-hat (power-of-two column scaling, FP32 accumulation)
+    stays within tol + 2u of the exact product: each term of a dot product
+    carries at most the rounding of its two operands."""
+    verts, faces, fac, F = cap
+    tol = 1e-4
+    H = _hm(verts, faces, tol=tol, storage="f32", max_rhs=R, lowp=lowp)
+    X = np.random.default_rng(50 + R).random((fac.N, R))
+    Xd = torch.from_numpy(X).to(DEV, torch.float32)
+    Y16 = H.matvec(Xd, lowp=True).double().cpu().numpy()
+    Y32 = H.matvec(Xd).double().cpu().numpy()
+    Y = F @ X
+    err16, err32 = _rel(Y16, Y), _rel(Y32, Y)
+    print(f"{lowp} R={R} err16={err16:.3e} err32={err32:.3e}")
+    assert err32 <= tol + 1e-6
+    assert err16 <= tol + 2 * U16[lowp]
+    for c in (0, R - 1):
+        assert _rel(Y16[:, c], Y[:, c]) <= tol + 2 * U16[lowp]
+    assert _rel(Y16, Y32) > 1e-7            # the 16-bit operator really was applied
+
+
+@pytest.mark.parametrize("lowp", ["f16", "bf16"])
+def test_refined_solve_beats_16bit_roundoff(cap, lowp):
+    """Iterative refinement with the 16-bit operator in the inner Jacobi sweeps
+    and an FP32-operator residual accumulated in FP64 reaches 1e-6 relative
+    residual, far below the 16-bit unit roundoff."""
+    verts, faces, fac, F = cap
+    R = 40
+    suns = sun_directions(R, seed=5)
+    E = 0.3 * ref.insolation(fac, suns)
+    B0 = ref.solve_direct(F, 0.3, E)
+    H = _hm(verts, faces, tol=1e-7, storage="f32", max_rhs=R, lowp=lowp)
+    Ed = torch.from_numpy(E).to(DEV, torch.float32)
+    for use_graph in (False, True):
+        B, info = H.solve(Ed, rho=0.3, rtol=1e-6, refine=True, inner_iters=3, use_graph=use_graph)
+        Bn = B.double().cpu().numpy()
+        errs = [_rel(Bn[:, c], B0[:, c]) for c in range(R)]
+        print(f"{lowp} graph={use_graph} outer={info['total_iters']} inner={info['inner_iters']} "
+              f"max err={max(errs):.3e} res={info['rel_change'].max():.3e}")
+        assert info["converged"] and info["total_iters"] <= 8
+        assert info["inner_iters"] == 3 * info["total_iters"]
+        assert np.all(info["rel_change"] <= 1e-6)
+        assert max(errs) <= 5e-6
+    # the same system by plain FP32 Jacobi agrees
+    Bj, _ = H.solve(Ed, rho=0.3, rtol=1e-7)
+    assert _rel(Bn, Bj.double().cpu().numpy()) <= 5e-6
+
+
+@pytest.mark.parametrize("lowp", ["f16", "bf16"])
+def test_refined_solve_ir_band_rho_vector(cap, lowp):
+    """Refinement for the long-wave band (rho = 1) and for a per-facet rho, in
+    the internal layout."""
+    from paper_2209_07632_amd.rad import ldr_of
+    verts, faces, fac, F = cap
+    R = 20
+    rng = np.random.default_rng(60)
+    E = rng.uniform(0.0, 100.0, (fac.N, R))
+    H = _hm(verts, faces, tol=1e-7, storage="f32", max_rhs=R, lowp=lowp)
+    perm = H.perm()
+    B, info = H.solve(torch.from_numpy(E).to(DEV, torch.float32), rho=1.0, rtol=1e-6, max_iter=60, refine=True)
+    assert _rel(B.double().cpu().numpy(), ref.solve_direct(F, 1.0, E)) <= 1e-5
+    rho = rng.uniform(0.1, 0.6, fac.N)
+    Er = np.zeros((fac.N, ldr_of(R)))
+    Er[:, :R] = E[perm]
+    Br, info = H.solve(torch.from_numpy(Er).to(DEV, torch.float32), rho=torch.from_numpy(rho[perm]).to(DEV, torch.float32),
+                       rtol=1e-6, order="tree_rmajor", R=R, refine=True)
+    Bo = np.empty((fac.N, R))
+    Bo[perm] = Br.double().cpu().numpy()[:, :R]
+    assert _rel(Bo, ref.solve_direct(F, rho, E)) <= 5e-6
+    assert np.all(info["iters"] > 0)
