@@ -217,9 +217,11 @@ rad_status rad_hmat_info(const rad_hmat *H, rad_hmat_stats *stats);
  *   ms[0] = projections T = V^T X (split-K GEMM),
  *   ms[1] = sum of the split-K partial tiles,
  *   ms[2] = expansion and near field with the fused Jacobi update.
- * Averages per launch in milliseconds.  Requires 16 <= R <= max_rhs.
+ * Averages per launch in milliseconds.  Requires 16 <= R <= max_rhs.  dtype
+ * is the matrix's dtype, or its lowp to time the 16-bit kernels.
  */
-rad_status rad_hmat_time_phases(const rad_hmat *H, int64_t R, int32_t nrep, void *hip_stream, double *ms);
+rad_status rad_hmat_time_phases(const rad_hmat *H, int64_t R, int32_t dtype, int32_t nrep, void *hip_stream,
+                                double *ms);
 
 /* Number of facets N and compute dtype of H (-1 when H is NULL). */
 int64_t rad_hmat_n(const rad_hmat *H);

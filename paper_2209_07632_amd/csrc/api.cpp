@@ -518,10 +518,13 @@ rad_status rad_insolation(const rad_hmat *H, int64_t R, const double *suns, doub
     });
 }
 
-rad_status rad_hmat_time_phases(const rad_hmat *H, int64_t R, int32_t nrep, void *hip_stream, double *ms) {
+rad_status rad_hmat_time_phases(const rad_hmat *H, int64_t R, int32_t dtype, int32_t nrep, void *hip_stream,
+                                double *ms) {
     return guard([&] {
         check_hmat(H);
         RAD_REQUIRE(ms != nullptr, "null ms pointer");
+        const bool lowp = H->lowp != 0 && dtype == H->lowp;
+        RAD_REQUIRE(dtype == H->dtype || lowp, "dtype does not match the matrix");
         RAD_REQUIRE(R >= kMfmaMinRhs && R <= H->max_rhs, "R must be in [16, max_rhs]");
         RAD_REQUIRE(nrep >= 1, "nrep must be >= 1");
         RAD_HIP(hipSetDevice(H->device));
@@ -530,7 +533,10 @@ rad_status rad_hmat_time_phases(const rad_hmat *H, int64_t R, int32_t nrep, void
         size_t n = (size_t)H->N * (size_t)mm_ldr(R) * es;
         RAD_HIP(hipMemsetAsync(H->w_x.p, 0, n, s));
         RAD_HIP(hipMemsetAsync(H->w_e.p, 0, n, s));
-        mm_time_phases(H, R, nrep, s, ms);
+        if (lowp)
+            lowp_time_phases(H, R, nrep, s, ms);
+        else
+            mm_time_phases(H, R, nrep, s, ms);
     });
 }
 

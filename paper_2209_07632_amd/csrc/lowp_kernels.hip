@@ -405,7 +405,57 @@ __global__ void __launch_bounds__(256) k_ir_update(double *B64, const float *d, 
     }
 }
 
+template <class H>
+void time16_t(const rad_hmat *Hm, int R, int nrep, hipStream_t s, double *ms) {
+    const int64_t ldr = (R + 3) & ~3;
+    const float *X = (const float *)Hm->w_x.p;
+    const float *E = (const float *)Hm->w_e.p;
+    float *Y = (float *)Hm->w_b.p;
+    const H *v16 = (const H *)Hm->d_vals16.p;
+    double *part = (double *)Hm->w_red.p;
+    unsigned rtiles = (unsigned)((R + TN - 1) / TN);
+    hipEvent_t e0, e1;
+    RAD_HIP(hipEventCreate(&e0));
+    RAD_HIP(hipEventCreate(&e1));
+    float t = 0;
+    ms[0] = ms[1] = ms[2] = 0.0;
+    auto timed = [&](auto &&launch) {
+        RAD_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < nrep; ++i) launch();
+        RAD_HIP(hipEventRecord(e1, s));
+        RAD_HIP(hipEventSynchronize(e1));
+        RAD_HIP(hipEventElapsedTime(&t, e0, e1));
+        return (double)t / nrep;
+    };
+    if (Hm->n_p1work > 0) {
+        ms[0] = timed([&] {
+            hipLaunchKernelGGL(k_proj_mm16<H>, dim3(Hm->n_p1work, rtiles), dim3(256), 0, s, Hm->d_groups.p,
+                               Hm->d_p1work.p, v16, X, ldr, R, (float *)Hm->w_part.p);
+        });
+        ms[1] = timed([&] {
+            hipLaunchKernelGGL(k_proj_reduce16, dim3(Hm->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s,
+                               Hm->d_p1red.p, (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)Hm->w_t.p);
+        });
+    }
+    ms[2] = timed([&] {
+        hipLaunchKernelGGL((k_tile_mm16<H, true>), dim3(Hm->n_tiles, rtiles), dim3(256), 0, s, Hm->d_tiles.p,
+                           Hm->d_brow.p, Hm->d_tile_tasks.p, v16, Hm->d_pscale.p, (const float *)Hm->d_vals.p,
+                           Hm->d_csr_ptr.p, Hm->d_csr_idx.p, Hm->csr_val_start, X, (const float *)Hm->w_t.p, ldr, R,
+                           Hm->N, Y, E, (const float *)nullptr, 0.3f, part);
+    });
+    RAD_HIP(hipGetLastError());
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
 }  // namespace
+
+void lowp_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, double *ms) {
+    if (H->lowp == RAD_F16)
+        time16_t<_Float16>(H, (int)R, nrep, s, ms);
+    else
+        time16_t<__bf16>(H, (int)R, nrep, s, ms);
+}
 
 void ir_residual(const rad_hmat *H, const float *E, const double *B64, const float *FB, const float *rho, double rho_s,
                  float *r, int64_t ldr, int64_t R, double *norms, hipStream_t s) {

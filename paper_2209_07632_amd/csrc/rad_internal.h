@@ -314,6 +314,7 @@ size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R);
 void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s);
 
 // 16-bit operator (lowp_kernels.hip)
+void lowp_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, double *ms);
 void lowp_convert(rad_hmat *H, hipStream_t s);
 void lowp_step(const rad_hmat *H, const void *E, const void *rho, double rho_s, const void *Bold, void *Bnew,
                int64_t ldr, int64_t R, double *norms, hipStream_t s);

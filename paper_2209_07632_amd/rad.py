@@ -97,7 +97,8 @@ def load(path: str = LIB_PATH):
                                   ctypes.c_double, vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo),
                                   ctypes.POINTER(SolveInfo), vp]
     L.rad_equilibrium.restype = ctypes.c_int
-    L.rad_hmat_time_phases.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
+    L.rad_hmat_time_phases.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp,
+                                       ctypes.POINTER(ctypes.c_double)]
     L.rad_hmat_time_phases.restype = ctypes.c_int
     L.rad_hmat_info.argtypes = [vp, ctypes.POINTER(Stats)]
     L.rad_hmat_info.restype = ctypes.c_int
@@ -327,10 +328,12 @@ class HMatrix:
                                  _stream_handle()))
         return T, Qv, Qi, {"iters_sw": its[0], "iters_ir": its[1]}
 
-    def time_phases(self, R, nrep=20):
-        """Average ms per launch of (projections, split-K sum, expansion + Jacobi update)."""
+    def time_phases(self, R, nrep=20, lowp=False):
+        """Average ms per launch of (projections, split-K sum, expansion + Jacobi update);
+        lowp=True times the 16-bit kernels."""
         ms = (ctypes.c_double * 3)()
-        _check(load().rad_hmat_time_phases(self._h, int(R), int(nrep), _stream_handle(), ms))
+        dt = self.lowp if lowp else self.rad_dtype
+        _check(load().rad_hmat_time_phases(self._h, int(R), dt, int(nrep), _stream_handle(), ms))
         return list(ms)
 
     def close(self):
