@@ -191,3 +191,16 @@ def sun_grid_azimuth(elev_deg: float, count: int, step_deg: float):
     phi = np.deg2rad(np.arange(count) * step_deg)
     return np.column_stack([np.cos(e) * np.cos(phi), np.cos(e) * np.sin(phi),
                             np.full(count, np.sin(e))])
+
+
+def mlp_init(sizes, seed: int = 0) -> np.ndarray:
+    """Packed initial parameters of a perceptron with layer widths ``sizes``:
+    per layer W (out x in, row-major) drawn U(-1/sqrt(in), 1/sqrt(in)), then a
+    zero bias.  FP32 values."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        a = 1.0 / np.sqrt(fi)
+        parts.append(rng.uniform(-a, a, size=fo * fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
