@@ -126,6 +126,9 @@ typedef struct {
     int32_t refine;      /* 0: Jacobi on F-hat; 1: iterative refinement: FP64 residual with the
                             FP32 operator, inner Jacobi with the 16-bit copy (needs lowp, R >= 16) */
     int32_t inner_iters; /* inner Jacobi iterations per refinement step (default 3)  */
+    int32_t warm;        /* 1: B holds a starting guess on entry (same layout as the output);
+                            each column keeps it only if its first residual is no larger
+                            than the cold start's (default 0)                          */
 } rad_solve_opts;
 
 void rad_solve_opts_default(rad_solve_opts *opts);
@@ -135,6 +138,7 @@ typedef struct {
     double *rel_change;  /* host, length R (or NULL): last ||B^{k+1}-B^k|| / ||E||                   */
     int32_t total_iters; /* iterations run (refinement steps when refine = 1)                      */
     int32_t inner_iters; /* inner iterations run in total (refine = 1)                              */
+    int32_t warm_columns; /* columns that kept the starting guess (warm = 1)                        */
 } rad_solve_info;
 
 /*
@@ -145,6 +149,13 @@ typedef struct {
  * each step forms r = E - B + rho (F-hat B) in FP64 from the FP32 operator,
  * stops columns with ||r|| <= rtol ||E||, runs inner_iters Jacobi iterations of
  * (I - rho F16) d = r with the 16-bit operator (FP32 accumulation) and adds d.
+ * Warm start (opts->warm = 1; the solve accepts any B^0): per column, the
+ * guess G in B is judged against the cold start by their first residuals.
+ * Jacobi: ||E + rho F G - G|| against ||rho F E||, both from one iteration;
+ * the smaller one's iterate continues (one extra product).  Refinement:
+ * ||E - G + rho F32 G|| against ||rho F16 E||; a rejected column restarts
+ * from B = 0.  info->iters then counts from the chosen start (0 when the
+ * guess already meets rtol under refinement).
  * rho: device array of N reflectances (original order for RAD_ORDER_ORIGINAL,
  * tree order otherwise), or NULL to use rho_scalar for every facet.  E and B
  * are device arrays of the compute dtype in the layout opts->order names; they
@@ -183,7 +194,8 @@ rad_status rad_insolation(const rad_hmat *H, int64_t R, const double *suns, doub
  * dtype in the layout opts->order names, all with leading dimension ld (N for
  * the column-major layouts, R rounded up to 4 for RAD_ORDER_TREE_RMAJOR); Qvis
  * and Qir may be NULL.  albedo in [0, 1), emissivity in (0, 1].  The two
- * solves use opts (rtol, max_iter, graphs); info_sw / info_ir may be NULL.
+ * solves use opts (rtol, max_iter, graphs; refine and warm are ignored: both
+ * bands run plain Jacobi from B^0 = E); info_sw / info_ir may be NULL.
  * Errors: as rad_solve, plus RAD_EINVAL for albedo/emissivity out of range.
  */
 rad_status rad_equilibrium(const rad_hmat *H, int64_t R, int32_t dtype, const void *Qdir, int64_t ld, double albedo,

@@ -27,6 +27,7 @@ static void alloc_workspace(rad_hmat *H) {
     H->w_rho.alloc((size_t)H->N * s);
     H->w_red.alloc(std::max(reduction_doubles(H->max_rhs), mm_reduction_doubles_for(H, H->max_rhs)) * sizeof(double));
     H->w_norms.alloc((size_t)3 * H->max_rhs);
+    H->w_flags.alloc((size_t)H->max_rhs);
     if (H->max_rhs >= kMfmaMinRhs && H->n_parts > 0)
         H->w_part.alloc((size_t)H->n_parts * mm_part_rows() * ldr * s);
     H->w_q1.alloc(nr * s);
@@ -97,22 +98,6 @@ static hipGraphExec_t iteration_graph(rad_hmat *H, const IterArgs &a) {
     return e.ex;
 }
 
-template <class F>
-static rad_status guard(F &&f) {
-    try {
-        f();
-        return RAD_OK;
-    } catch (const Error &e) {
-        set_error(e.what());
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        set_error("host allocation failed");
-        return RAD_ENOMEM;
-    } catch (const std::exception &e) {
-        set_error(e.what());
-        return RAD_EDEVICE;
-    }
-}
 
 static void check_hmat(const rad_hmat *H) { RAD_REQUIRE(H != nullptr, "null matrix handle"); }
 
@@ -158,6 +143,7 @@ void rad_solve_opts_default(rad_solve_opts *o) {
     o->use_graph = 1;
     o->refine = 0;
     o->inner_iters = 3;
+    o->warm = 0;
 }
 
 const char *rad_last_error(void) { return g_last_error.c_str(); }
@@ -340,12 +326,45 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             double *B64 = H->w_b64.p;
             float *B32 = (float *)H->w_x.p, *FB = (float *)H->w_y.p, *r = (float *)H->w_q1.p;
             float *D[2] = {(float *)H->w_q2.p, (float *)H->w_b.p};
-            RAD_HIP(hipMemsetAsync(B64, 0, (size_t)N * ld * sizeof(double), s));
-            RAD_HIP(hipMemsetAsync(B32, 0, (size_t)N * ld * sizeof(float), s));
             double *dn_d = H->w_norms.p + H->max_rhs;
             int inner_total = 0;
-            while (true) {
-                const float *rp = (const float *)Ein;
+            int warm_cols = 0;
+            if (o.warm) {
+                // guess G into the working layout (w_q2), residual with the FP32
+                // operator, judged against ||rho F16 E|| (one 16-bit Jacobi step from E)
+                float *G = (float *)H->w_q2.p;
+                if (rmaj)
+                    RAD_HIP(hipMemcpyAsync(G, B, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
+                else
+                    mm_to_rmajor(H, B, ldb, o.order == RAD_ORDER_ORIGINAL, G, ld, R, s);
+                ir_load(H, B64, B32, G, ld, R, s);
+                mm_apply(H, B32, FB, ld, R, s);
+                ir_residual(H, (const float *)Ein, B64, FB, (const float *)rho_t, rho_scalar, r, ld, R, dn_d, s);
+                std::vector<double> nw(R), nc(R);
+                RAD_HIP(hipMemcpyAsync(nw.data(), dn_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
+                lowp_step(H, Ein, rho_t, rho_scalar, Ein, D[1], ld, R, dn_d, s);
+                RAD_HIP(hipMemcpyAsync(nc.data(), dn_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
+                RAD_HIP(hipStreamSynchronize(s));
+                std::vector<int32_t> flag(R);
+                done = true;
+                for (int64_t c = 0; c < R; ++c) {
+                    RAD_REQUIRE(std::isfinite(nw[c]), "starting guess gives a non-finite residual");
+                    flag[c] = nw[c] <= nc[c];
+                    warm_cols += flag[c];
+                    double d = std::sqrt(flag[c] ? nw[c] : enorm[c] * enorm[c]);
+                    rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
+                    if (rel[c] <= o.rtol) iters[c] = 0;
+                    if (iters[c] < 0) done = false;
+                }
+                RAD_HIP(hipMemcpyAsync(H->w_flags.p, flag.data(), R * sizeof(int32_t), hipMemcpyHostToDevice, s));
+                ir_select(H, B64, B32, r, (const float *)Ein, H->w_flags.p, ld, R, s);
+                RAD_HIP(hipStreamSynchronize(s));
+            } else {
+                RAD_HIP(hipMemsetAsync(B64, 0, (size_t)N * ld * sizeof(double), s));
+                RAD_HIP(hipMemsetAsync(B32, 0, (size_t)N * ld * sizeof(float), s));
+            }
+            while (!done) {
+                const float *rp = o.warm ? r : (const float *)Ein;
                 if (k > 0) {
                     mm_apply(H, B32, FB, ld, R, s);
                     ir_residual(H, (const float *)Ein, B64, FB, (const float *)rho_t, rho_scalar, r, ld, R, dn_d, s);
@@ -387,12 +406,54 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 if (info->rel_change) std::copy(rel.begin(), rel.end(), info->rel_change);
                 info->total_iters = k;
                 info->inner_iters = inner_total;
+                info->warm_columns = warm_cols;
             }
             if (!done) {
                 conv = RAD_ENOCONV;
                 set_error("refinement reached max_iter before rtol");
             }
             return;
+        }
+        int warm_cols = 0;
+        if (o.warm) {
+            // guess G into the working layout (w_q2); one iteration from G into
+            // P[1] and one from E into w_q1; per column the smaller change wins
+            // and its iterate becomes B^1 in P[0]
+            void *G = H->w_q2.p, *C1 = H->w_q1.p;
+            if (mm && rmaj)
+                RAD_HIP(hipMemcpyAsync(G, B, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
+            else if (mm)
+                mm_to_rmajor(H, B, ldb, o.order == RAD_ORDER_ORIGINAL, G, ld, R, s);
+            else if (rmaj)
+                mm_from_rmajor(H, B, ldb, false, G, N, R, s);
+            else if (o.order == RAD_ORDER_TREE)
+                RAD_HIP(hipMemcpy2DAsync(G, N * es, B, ldb * es, N * es, R, hipMemcpyDeviceToDevice, s));
+            else
+                mv_gather(H, B, ldb, G, N, R, s);
+            std::vector<double> nw(R), nc(R);
+            IterArgs aw{mm, false, R, ld, Ein, rho_t, G, P[1], rho_scalar};
+            enqueue_iteration(H, aw, s);
+            RAD_HIP(hipStreamSynchronize(s));
+            std::copy(H->h_norms, H->h_norms + R, nw.begin());
+            IterArgs ac{mm, false, R, ld, Ein, rho_t, Ein, C1, rho_scalar};
+            enqueue_iteration(H, ac, s);
+            RAD_HIP(hipStreamSynchronize(s));
+            std::copy(H->h_norms, H->h_norms + R, nc.begin());
+            std::vector<int32_t> flag(R);
+            k = 1;
+            done = true;
+            for (int64_t c = 0; c < R; ++c) {
+                RAD_REQUIRE(std::isfinite(nw[c]), "starting guess gives a non-finite residual");
+                flag[c] = nw[c] <= nc[c];
+                warm_cols += flag[c];
+                double d = std::sqrt(flag[c] ? nw[c] : nc[c]);
+                rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
+                RAD_REQUIRE(std::isfinite(rel[c]), "solve produced non-finite values");
+                if (rel[c] <= o.rtol) iters[c] = 1;
+                if (iters[c] < 0) done = false;
+            }
+            RAD_HIP(hipMemcpyAsync(H->w_flags.p, flag.data(), R * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            select_columns(H, P[1], C1, H->w_flags.p, P[0], ld, R, mm, s);
         }
         while (k < o.max_iter && !done) {
             ++k;
@@ -432,6 +493,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             if (info->rel_change) std::copy(rel.begin(), rel.end(), info->rel_change);
             info->total_iters = k;
             info->inner_iters = 0;
+            info->warm_columns = warm_cols;
         }
         if (!done) {
             conv = RAD_ENOCONV;
@@ -457,6 +519,8 @@ rad_status rad_equilibrium(const rad_hmat *H, int64_t R, int32_t dtype, const vo
             o = *opts;
         else
             rad_solve_opts_default(&o);
+        o.refine = 0;  // the bands run plain Jacobi from B^0 = E (their inputs live in the refinement workspace)
+        o.warm = 0;
         check_layout(H, o.order, R, ld, "Qdir");
         const bool rmaj = o.order == RAD_ORDER_TREE_RMAJOR;
         RAD_REQUIRE(rmaj || ld == H->N, "column-major layouts need ld == N here");

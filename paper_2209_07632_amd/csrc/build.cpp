@@ -131,6 +131,8 @@ struct QuadBuilder {
     }
 };
 
+}  // namespace
+
 // One-sided Jacobi SVD (Hestenes) of the l x l matrix A (column-major), in
 // place: on return the columns of A are U*Sigma (sorted by decreasing norm)
 // and V holds the right singular vectors.  sv gets the column norms.
@@ -189,6 +191,8 @@ void jacobi_svd(int l, std::vector<double> &A, std::vector<double> &V, std::vect
     V.swap(V2);
     sv.swap(s2);
 }
+
+namespace {
 
 // verbose progress: one flushed line per stage with the elapsed time
 struct StageLog {

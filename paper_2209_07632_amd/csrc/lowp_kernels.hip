@@ -448,7 +448,47 @@ void time16_t(const rad_hmat *Hm, int R, int nrep, hipStream_t s, double *ms) {
     (void)hipEventDestroy(e1);
 }
 
+// columns with flag 0 restart from B = 0, r = E
+__global__ void __launch_bounds__(256) k_ir_select(double *B64, float *B32, float *r, const float *E,
+                                                    const int32_t *flag, int64_t N, int64_t ldr, int R) {
+    const int c = blockIdx.y * 256 + threadIdx.x;
+    if (c >= R || flag[c]) return;
+    const int64_t t0 = (int64_t)blockIdx.x * TM, t1 = min(N, t0 + TM);
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t e = t * ldr + c;
+        B64[e] = 0.0;
+        B32[e] = 0.0f;
+        r[e] = E[e];
+    }
+}
+
+// B64 = B32 = B0
+__global__ void __launch_bounds__(256) k_ir_load(double *B64, float *B32, const float *B0, int64_t N, int64_t ldr,
+                                                  int R) {
+    const int c = blockIdx.y * 256 + threadIdx.x;
+    if (c >= R) return;
+    const int64_t t0 = (int64_t)blockIdx.x * TM, t1 = min(N, t0 + TM);
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t e = t * ldr + c;
+        B64[e] = (double)B0[e];
+        B32[e] = B0[e];
+    }
+}
+
 }  // namespace
+
+void ir_select(const rad_hmat *H, double *B64, float *B32, float *r, const float *E, const int32_t *flag, int64_t ldr,
+               int64_t R, hipStream_t s) {
+    dim3 grid((unsigned)H->n_tiles, (unsigned)((R + 255) / 256));
+    hipLaunchKernelGGL(k_ir_select, grid, dim3(256), 0, s, B64, B32, r, E, flag, H->N, ldr, (int)R);
+    RAD_HIP(hipGetLastError());
+}
+
+void ir_load(const rad_hmat *H, double *B64, float *B32, const float *B0, int64_t ldr, int64_t R, hipStream_t s) {
+    dim3 grid((unsigned)H->n_tiles, (unsigned)((R + 255) / 256));
+    hipLaunchKernelGGL(k_ir_load, grid, dim3(256), 0, s, B64, B32, B0, H->N, ldr, (int)R);
+    RAD_HIP(hipGetLastError());
+}
 
 void lowp_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, double *ms) {
     if (H->lowp == RAD_F16)

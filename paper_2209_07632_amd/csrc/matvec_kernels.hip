@@ -268,4 +268,31 @@ void launch_elementwise(const rad_hmat *H, int32_t op, double a, double b, doubl
     RAD_HIP(hipGetLastError());
 }
 
+namespace {
+// out[:, c] = flag[c] ? a[:, c] : b[:, c] (R-major: element (t, c) at t ld + c; else c ld + t)
+template <class T>
+__global__ void k_select_cols(const T *a, const T *b, const int32_t *flag, T *out, int64_t N, int64_t R, int64_t ld,
+                              int rmajor) {
+    const int64_t tot = N * R;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = rmajor ? e / R : e % N, c = rmajor ? e % R : e / N;
+        const int64_t k = rmajor ? i * ld + c : i + c * ld;
+        out[k] = flag[c] ? a[k] : b[k];
+    }
+}
+}  // namespace
+
+void select_columns(const rad_hmat *H, const void *a, const void *b, const int32_t *flag, void *out, int64_t ld,
+                    int64_t R, bool rmajor, hipStream_t s) {
+    const int64_t tot = H->N * R;
+    const unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
+    if (H->dtype == RAD_F64)
+        hipLaunchKernelGGL(k_select_cols<double>, dim3(blocks), dim3(256), 0, s, (const double *)a, (const double *)b,
+                           flag, (double *)out, H->N, R, ld, (int)rmajor);
+    else
+        hipLaunchKernelGGL(k_select_cols<float>, dim3(blocks), dim3(256), 0, s, (const float *)a, (const float *)b,
+                           flag, (float *)out, H->N, R, ld, (int)rmajor);
+    RAD_HIP(hipGetLastError());
+}
+
 }  // namespace rad

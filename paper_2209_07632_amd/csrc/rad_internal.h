@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <new>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -232,12 +233,36 @@ struct rad_hmat {
     rad::DevBuf<uint16_t> d_vals16;
     rad::DevBuf<float> d_pscale, d_tscale;
     rad::DevBuf<double> w_norms;
+    rad::DevBuf<int32_t> w_flags;         // per-column choices of warm-started solves
 };
 
 namespace rad {
 
 // thread-local error text
 void set_error(const std::string &msg);
+
+// Runs f, translating exceptions into a status code and the thread's last error.
+template <class F>
+rad_status guard(F &&f) {
+    try {
+        f();
+        return RAD_OK;
+    } catch (const Error &e) {
+        set_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return RAD_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return RAD_EDEVICE;
+    }
+}
+
+// One-sided Jacobi SVD of the l x l column-major matrix A (host, FP64), in
+// place: columns of A become U Sigma sorted by decreasing norm, V the right
+// singular vectors, sv the singular values.
+void jacobi_svd(int l, std::vector<double> &A, std::vector<double> &V, std::vector<double> &sv);
 
 // builder entry (build.cpp)
 void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
@@ -314,6 +339,11 @@ size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R);
 void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s);
 
 // 16-bit operator (lowp_kernels.hip)
+void ir_select(const rad_hmat *H, double *B64, float *B32, float *r, const float *E, const int32_t *flag, int64_t ldr,
+               int64_t R, hipStream_t s);
+void ir_load(const rad_hmat *H, double *B64, float *B32, const float *B0, int64_t ldr, int64_t R, hipStream_t s);
+void select_columns(const rad_hmat *H, const void *a, const void *b, const int32_t *flag, void *out, int64_t ld,
+                    int64_t R, bool rmajor, hipStream_t s);
 void lowp_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, double *ms);
 void lowp_convert(rad_hmat *H, hipStream_t s);
 void lowp_step(const rad_hmat *H, const void *E, const void *rho, double rho_s, const void *Bold, void *Bnew,

@@ -40,12 +40,13 @@ class BuildOpts(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("inner_iters", ctypes.c_int32)]
+                ("inner_iters", ctypes.c_int32), ("warm", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.POINTER(ctypes.c_int32)), ("rel_change", ctypes.POINTER(ctypes.c_double)),
-                ("total_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32)]
+                ("total_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+                ("warm_columns", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -63,7 +64,9 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_matvec", "rad_solve_opts_default", "rad_solve",
            "rad_insolation", "rad_equilibrium", "rad_hmat_time_phases", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free",
-           "rad_last_error"]
+           "rad_last_error", "rad_pod_build", "rad_pod_project", "rad_pod_expand", "rad_mlp_create",
+           "rad_mlp_param_count", "rad_mlp_get_params", "rad_mlp_set_params", "rad_mlp_forward", "rad_mlp_loss_grad",
+           "rad_mlp_adam_step", "rad_mlp_train", "rad_mlp_free"]
 
 _lib = None
 
@@ -112,6 +115,26 @@ def load(path: str = LIB_PATH):
     L.rad_hmat_free.restype = None
     L.rad_last_error.argtypes = []
     L.rad_last_error.restype = ctypes.c_char_p
+    i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    sigs = {
+        "rad_pod_build": [vp, i64, i64, i64, i32, vp, i64, vp, i32, vp],
+        "rad_pod_project": [vp, i64, i32, i64, vp, vp, i64, i64, vp, vp, vp],
+        "rad_pod_expand": [vp, i64, i32, i64, vp, vp, vp, i64, i64, vp, vp],
+        "rad_mlp_create": [vp, i32, vp, i32, i32, i32, ctypes.POINTER(vp)],
+        "rad_mlp_get_params": [vp, vp],
+        "rad_mlp_set_params": [vp, vp],
+        "rad_mlp_forward": [vp, vp, i64, vp, vp],
+        "rad_mlp_loss_grad": [vp, vp, vp, vp, i64, vp, vp, vp],
+        "rad_mlp_adam_step": [vp, dbl, dbl, dbl, dbl, vp],
+        "rad_mlp_train": [vp, vp, vp, vp, i64, i32, dbl, dbl, dbl, dbl, vp, vp],
+    }
+    for name, args in sigs.items():
+        getattr(L, name).argtypes = args
+        getattr(L, name).restype = ctypes.c_int
+    L.rad_mlp_param_count.argtypes = [vp]
+    L.rad_mlp_param_count.restype = i64
+    L.rad_mlp_free.argtypes = [vp]
+    L.rad_mlp_free.restype = None
     _lib = L
     return L
 
@@ -232,8 +255,10 @@ class HMatrix:
         return out.reshape(-1) if squeeze else out
 
     def solve(self, E, rho=0.3, rtol=1e-3, max_iter=100, order="original", check_every=1, out=None,
-              raise_on_noconv=True, use_graph=True, R=None, refine=False, inner_iters=3):
-        """Jacobi solve of (I - diag(rho) F-hat) B = E; returns (B, info dict)."""
+              raise_on_noconv=True, use_graph=True, R=None, refine=False, inner_iters=3, warm=None):
+        """Jacobi solve of (I - diag(rho) F-hat) B = E; returns (B, info dict).
+        warm: optional starting guess in the layout of B (judged per column
+        against the cold start)."""
         torch = _torch()
         L = load()
         squeeze = False
@@ -250,6 +275,10 @@ class HMatrix:
             if out is None:
                 out = torch.empty((R, self.N), dtype=E.dtype, device=E.device).t()
             Bc, ldb = _colmajor(out, self.N)
+        if warm is not None:
+            if warm.shape[0] != self.N or warm.dtype != Bc.dtype:
+                raise ValueError("warm must match B in shape and dtype")
+            Bc.copy_(warm if order == "tree_rmajor" else warm.reshape(Bc.shape))
         rho_ptr = ctypes.c_void_p(0)
         rho_s = 0.0
         if isinstance(rho, (float, int)):
@@ -266,10 +295,11 @@ class HMatrix:
         o.use_graph = int(bool(use_graph))
         o.refine = int(bool(refine))
         o.inner_iters = int(inner_iters)
+        o.warm = int(warm is not None)
         iters = np.zeros(R, dtype=np.int32)
         rel = np.zeros(R, dtype=np.float64)
         info = SolveInfo(iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                         rel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0, 0)
+                         rel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0, 0, 0)
         st = L.rad_solve(self._h, rho_ptr, rho_s, R, self.rad_dtype, ctypes.c_void_p(Ec.data_ptr()), lde,
                          ctypes.c_void_p(Bc.data_ptr()), ldb, ctypes.byref(o), ctypes.byref(info),
                          _stream_handle())
@@ -278,7 +308,8 @@ class HMatrix:
         if Bc.data_ptr() != out.data_ptr():
             out.copy_(Bc)
         res = {"iters": iters, "rel_change": rel, "total_iters": int(info.total_iters),
-               "inner_iters": int(info.inner_iters), "converged": st == RAD_OK}
+               "inner_iters": int(info.inner_iters), "warm_columns": int(info.warm_columns),
+               "converged": st == RAD_OK}
         return (out.reshape(-1) if squeeze else out), res
 
     def insolation(self, suns, flux=1365.0, order="original", out=None):
@@ -321,7 +352,7 @@ class HMatrix:
         L.rad_solve_opts_default(ctypes.byref(o))
         o.rtol, o.max_iter, o.order, o.use_graph = float(rtol), int(max_iter), ORDER[order], int(bool(use_graph))
         its = [np.zeros(R, dtype=np.int32) for _ in range(2)]
-        infos = [SolveInfo(x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None, 0, 0) for x in its]
+        infos = [SolveInfo(x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None, 0, 0, 0) for x in its]
         p = lambda t: ctypes.c_void_p(t.data_ptr())
         _check(L.rad_equilibrium(self._h, R, self.rad_dtype, p(Qc), ld, float(albedo), float(emissivity), p(T),
                                  p(Qv), p(Qi), ctypes.byref(o), ctypes.byref(infos[0]), ctypes.byref(infos[1]),

@@ -1,5 +1,5 @@
 """CPU-side checks of the C-ABI library: it loads, exports every symbol that
-include/rad.h declares, and rejects bad arguments before touching a GPU."""
+include/*.h declares, and rejects bad arguments before touching a GPU."""
 import ctypes
 import os
 import re
@@ -11,7 +11,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_symbols():
-    text = open(os.path.join(ROOT, "include", "rad.h")).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     return sorted(set(re.findall(r"\b(rad_[a-z_0-9]+)\s*\(", text)))
 
 
