@@ -134,8 +134,9 @@ typedef struct {
 void rad_solve_opts_default(rad_solve_opts *opts);
 
 typedef struct {
-    int32_t *iters;      /* host, length R (or NULL): iterations at which column met rtol (-1: never) */
-    double *rel_change;  /* host, length R (or NULL): last ||B^{k+1}-B^k|| / ||E||                   */
+    int32_t *iters;      /* host, length R (R x instances for a group, instance-major; or NULL):
+                            iterations at which column met rtol (-1: never)                      */
+    double *rel_change;  /* host, same length (or NULL): last ||B^{k+1}-B^k|| / ||E||            */
     int32_t total_iters; /* iterations run (refinement steps when refine = 1)                      */
     int32_t inner_iters; /* inner iterations run in total (refine = 1)                              */
     int32_t warm_columns; /* columns that kept the starting guess (warm = 1)                        */
@@ -235,7 +236,34 @@ rad_status rad_hmat_info(const rad_hmat *H, rad_hmat_stats *stats);
 rad_status rad_hmat_time_phases(const rad_hmat *H, int64_t R, int32_t dtype, int32_t nrep, void *hip_stream,
                                 double *ms);
 
-/* Number of facets N and compute dtype of H (-1 when H is NULL). */
+/*
+ * Groups of independent matrices (many craters, each with its own suns) as
+ * one block-diagonal operator, so that every product and Jacobi iteration of
+ * all instances runs in one launch per kernel over all of their blocks.
+ * parts: count built matrices on one device with equal dtype and lowp (not
+ * groups).  The group copies their device data (parts may be freed after).
+ * Layout: instance k's facets, in its tree order, are rows
+ * [offsets[k], offsets[k] + sizes[k]) of an RAD_ORDER_TREE_RMAJOR block of
+ * rad_hmat_n(group) rows; offsets are multiples of 64 and the rows between
+ * instances are padding that must be zero in E (solves keep them zero).
+ * Column c of instance k is right-hand side c of that instance; solves track
+ * convergence per (instance, column).  A group supports rad_hmat_matvec and
+ * rad_solve with RAD_ORDER_TREE_RMAJOR and 16 <= R <= max_rhs (no warm
+ * start); rad_insolation and rad_equilibrium return RAD_EUNSUP (run them on
+ * the parts and write into the group layout at the offsets).
+ * Errors: RAD_EINVAL, RAD_ENOMEM, RAD_EDEVICE.  *out is NULL on error.
+ */
+rad_status rad_hmat_group(const rad_hmat *const *parts, int32_t count, int32_t max_rhs, rad_hmat **out);
+
+/* Instances in H (1 for a matrix built by rad_hmat_build; -1 for NULL). */
+int32_t rad_hmat_instances(const rad_hmat *H);
+
+/* Row offset and facet count of every instance (host arrays of
+ * rad_hmat_instances(H) entries; either may be NULL). */
+rad_status rad_hmat_group_layout(const rad_hmat *H, int64_t *offsets, int64_t *sizes);
+
+/* Number of facets N and compute dtype of H (-1 when H is NULL).  For a group,
+ * N counts the rows of its layout, padding included. */
 int64_t rad_hmat_n(const rad_hmat *H);
 int32_t rad_hmat_dtype(const rad_hmat *H);
 

@@ -15,7 +15,7 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 
 static int dsize(int32_t dt) { return dt == RAD_F64 ? 8 : dt == RAD_F32 ? 4 : 2; }
 
-static void alloc_workspace(rad_hmat *H) {
+void alloc_workspace(rad_hmat *H) {
     size_t s = (size_t)dsize(H->dtype);
     size_t ldr = (size_t)mm_ldr(H->max_rhs);
     size_t nr = (size_t)H->N * ldr;
@@ -26,14 +26,15 @@ static void alloc_workspace(rad_hmat *H) {
     H->w_t.alloc((size_t)std::max(H->t_ld, 4) * ldr * s);
     H->w_rho.alloc((size_t)H->N * s);
     H->w_red.alloc(std::max(reduction_doubles(H->max_rhs), mm_reduction_doubles_for(H, H->max_rhs)) * sizeof(double));
-    H->w_norms.alloc((size_t)3 * H->max_rhs);
-    H->w_flags.alloc((size_t)H->max_rhs);
+    const size_t nc = (size_t)H->max_rhs * (size_t)H->n_inst;  // per-column norms (per instance in a group)
+    H->w_norms.alloc(3 * nc);
+    H->w_flags.alloc(nc);
     if (H->max_rhs >= kMfmaMinRhs && H->n_parts > 0)
         H->w_part.alloc((size_t)H->n_parts * mm_part_rows() * ldr * s);
     H->w_q1.alloc(nr * s);
     H->w_q2.alloc(nr * s);
     if (H->lowp) H->w_b64.alloc(nr);
-    RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * (size_t)H->max_rhs, hipHostMallocDefault));
+    RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * nc, hipHostMallocDefault));
     RAD_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
 }
 
@@ -49,7 +50,7 @@ struct IterArgs {
 };
 
 static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t s) {
-    double *dn = H->w_norms.p + H->max_rhs;
+    double *dn = H->w_norms.p + (int64_t)H->max_rhs * H->n_inst;
     if (a.lowp) {
         lowp_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s);
     } else if (a.mm) {
@@ -58,7 +59,7 @@ static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t 
         mv_apply(H, a.Bold, a.ld, H->w_y.p, a.ld, a.R, s);
         solve_update(H, a.E, a.rho, a.rho_s, H->w_y.p, a.Bold, a.Bnew, a.ld, a.R, dn, s);
     }
-    RAD_HIP(hipMemcpyAsync(H->h_norms, dn, sizeof(double) * a.R, hipMemcpyDeviceToHost, s));
+    RAD_HIP(hipMemcpyAsync(H->h_norms, dn, sizeof(double) * a.R * H->n_inst, hipMemcpyDeviceToHost, s));
 }
 
 // Cached graph of one iteration (captured on the library's own stream,
@@ -213,6 +214,8 @@ rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const vo
         RAD_REQUIRE(dtype == H->dtype || lowp, "dtype does not match the matrix");
         RAD_REQUIRE(R >= 1 && R <= H->max_rhs, "R must be in [1, max_rhs]");
         RAD_REQUIRE(!lowp || R >= kMfmaMinRhs, "the 16-bit operator needs R >= 16");
+        RAD_REQUIRE(H->n_inst == 1 || (order == RAD_ORDER_TREE_RMAJOR && R >= kMfmaMinRhs),
+                    "a group multiplies in RAD_ORDER_TREE_RMAJOR with R >= 16");
         check_layout(H, order, R, ldx, "X");
         check_layout(H, order, R, ldy, "Y");
         RAD_HIP(hipSetDevice(H->device));
@@ -264,6 +267,9 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         else
             rad_solve_opts_default(&o);
         RAD_REQUIRE(o.rtol > 0 && o.max_iter >= 1 && o.check_every >= 1, "bad solve options");
+        RAD_REQUIRE(H->n_inst == 1 || (o.order == RAD_ORDER_TREE_RMAJOR && R >= kMfmaMinRhs && !o.warm),
+                    "a group solves in RAD_ORDER_TREE_RMAJOR with R >= 16 and without a warm start");
+        const int64_t NC = R * H->n_inst;  // convergence is tracked per (instance, column)
         check_layout(H, o.order, R, lde, "E");
         check_layout(H, o.order, R, ldb, "B");
         RAD_HIP(hipSetDevice(H->device));
@@ -306,15 +312,15 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             mm_col_norms2(H, Ein, ld, R, enorm_d, s);
         else
             col_norms2(H, Ein, N, R, enorm_d, s);
-        std::vector<double> enorm(R), dn(R);
-        RAD_HIP(hipMemcpyAsync(enorm.data(), enorm_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
+        std::vector<double> enorm(NC), dn(NC);
+        RAD_HIP(hipMemcpyAsync(enorm.data(), enorm_d, NC * sizeof(double), hipMemcpyDeviceToHost, s));
         RAD_HIP(hipStreamSynchronize(s));
         for (auto &v : enorm) {
             RAD_REQUIRE(std::isfinite(v), "E contains non-finite values");
             v = std::sqrt(v);
         }
-        std::vector<int32_t> iters(R, -1);
-        std::vector<double> rel(R, 0.0);
+        std::vector<int32_t> iters(NC, -1);
+        std::vector<double> rel(NC, 0.0);
         int k = 0;
         bool done = false;
         if (o.refine) {
@@ -326,7 +332,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             double *B64 = H->w_b64.p;
             float *B32 = (float *)H->w_x.p, *FB = (float *)H->w_y.p, *r = (float *)H->w_q1.p;
             float *D[2] = {(float *)H->w_q2.p, (float *)H->w_b.p};
-            double *dn_d = H->w_norms.p + H->max_rhs;
+            double *dn_d = H->w_norms.p + (int64_t)H->max_rhs * H->n_inst;
             int inner_total = 0;
             int warm_cols = 0;
             if (o.warm) {
@@ -368,11 +374,11 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 if (k > 0) {
                     mm_apply(H, B32, FB, ld, R, s);
                     ir_residual(H, (const float *)Ein, B64, FB, (const float *)rho_t, rho_scalar, r, ld, R, dn_d, s);
-                    RAD_HIP(hipMemcpyAsync(dn.data(), dn_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
+                    RAD_HIP(hipMemcpyAsync(dn.data(), dn_d, NC * sizeof(double), hipMemcpyDeviceToHost, s));
                     RAD_HIP(hipStreamSynchronize(s));
                     rp = r;
                     done = true;
-                    for (int64_t c = 0; c < R; ++c) {
+                    for (int64_t c = 0; c < NC; ++c) {
                         double d = std::sqrt(dn[c]);
                         rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
                         RAD_REQUIRE(std::isfinite(rel[c]), "solve produced non-finite values");
@@ -464,9 +470,9 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 enqueue_iteration(H, a, s);
             if (k % o.check_every == 0 || k == o.max_iter) {
                 RAD_HIP(hipStreamSynchronize(s));
-                std::copy(H->h_norms, H->h_norms + R, dn.begin());
+                std::copy(H->h_norms, H->h_norms + NC, dn.begin());
                 done = true;
-                for (int64_t c = 0; c < R; ++c) {
+                for (int64_t c = 0; c < NC; ++c) {
                     double d = std::sqrt(dn[c]);
                     rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
                     RAD_REQUIRE(std::isfinite(rel[c]), "solve produced non-finite values");
@@ -510,6 +516,7 @@ rad_status rad_equilibrium(const rad_hmat *H, int64_t R, int32_t dtype, const vo
     rad_status st = guard([&] {
         check_hmat(H);
         RAD_REQUIRE(Qdir && T, "null Qdir or T");
+        if (H->n_inst > 1) throw Error(RAD_EUNSUP, "equilibrium runs per instance, not on a group");
         RAD_REQUIRE(dtype == H->dtype, "dtype does not match the matrix");
         RAD_REQUIRE(R >= 1 && R <= H->max_rhs, "R must be in [1, max_rhs]");
         RAD_REQUIRE(albedo >= 0.0 && albedo < 1.0, "albedo must be in [0, 1)");
@@ -565,6 +572,7 @@ rad_status rad_insolation(const rad_hmat *H, int64_t R, const double *suns, doub
     return guard([&] {
         check_hmat(H);
         RAD_REQUIRE(suns && Q, "null suns or Q");
+        if (H->n_inst > 1) throw Error(RAD_EUNSUP, "insolation runs per instance, not on a group");
         RAD_REQUIRE(R >= 1, "R must be >= 1");
         RAD_REQUIRE(dtype == H->dtype, "dtype does not match the matrix");
         RAD_REQUIRE(std::isfinite(flux), "flux must be finite");

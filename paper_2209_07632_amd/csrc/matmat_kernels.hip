@@ -465,6 +465,26 @@ __global__ void __launch_bounds__(256) k_reduce_rm(const double *partial, int np
     }
 }
 
+// Groups: out[k * R + r] = sum over the tiles of instance k, fixed order
+__global__ void __launch_bounds__(256) k_reduce_inst(const double *partial, const int32_t *inst_tile, int R,
+                                                      double *out) {
+    const int k = blockIdx.y;
+    const int cl = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int r = blockIdx.x * 16 + cl;
+    const int t0 = inst_tile[k], t1 = inst_tile[k + 1];
+    double s = 0.0;
+    if (r < R)
+        for (int i = t0 + g; i < t1; i += 16) s += partial[(int64_t)i * R + r];
+    __shared__ double red[16][17];
+    red[g][cl] = s;
+    __syncthreads();
+    if (g == 0 && r < R) {
+        double tot = 0.0;
+        for (int q = 0; q < 16; ++q) tot += red[q][cl];
+        out[(int64_t)k * R + r] = tot;
+    }
+}
+
 // partial[tile * R + r] = sum over the tile's 64 facets of E^2 (R-major)
 template <class T>
 __global__ void __launch_bounds__(256) k_colnorm_tiles(const T *E, int64_t N, int64_t ldr, int R, double *partial) {
@@ -558,7 +578,7 @@ void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rh
     else
         apply_mm_t<float>(H, (const float *)Bold, (float *)Bnew, ldr, (int)R, (const float *)E, (const float *)rho,
                           (float)rho_scalar, part, s);
-    hipLaunchKernelGGL(k_reduce_rm, dim3((unsigned)((R + 15) / 16)), dim3(256), 0, s, part, H->n_tiles, (int)R, norms);
+    mm_reduce_cols(H, part, H->n_tiles, R, norms, s);
     RAD_HIP(hipGetLastError());
 }
 
@@ -616,8 +636,12 @@ void mm_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, doubl
 }
 
 void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s) {
-    (void)H;
-    hipLaunchKernelGGL(k_reduce_rm, dim3((unsigned)((R + 15) / 16)), dim3(256), 0, s, partial, nparts, (int)R, out);
+    if (H->n_inst > 1)
+        hipLaunchKernelGGL(k_reduce_inst, dim3((unsigned)((R + 15) / 16), (unsigned)H->n_inst), dim3(256), 0, s,
+                           partial, (const int32_t *)H->d_inst_tile.p, (int)R, out);
+    else
+        hipLaunchKernelGGL(k_reduce_rm, dim3((unsigned)((R + 15) / 16)), dim3(256), 0, s, partial, nparts, (int)R,
+                           out);
     RAD_HIP(hipGetLastError());
 }
 
@@ -632,7 +656,7 @@ void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, dou
         hipLaunchKernelGGL(k_colnorm_tiles<double>, grid, dim3(256), 0, s, (const double *)E, H->N, ldr, (int)R, part);
     else
         hipLaunchKernelGGL(k_colnorm_tiles<float>, grid, dim3(256), 0, s, (const float *)E, H->N, ldr, (int)R, part);
-    hipLaunchKernelGGL(k_reduce_rm, dim3((unsigned)((R + 15) / 16)), dim3(256), 0, s, part, H->n_tiles, (int)R, out);
+    mm_reduce_cols(H, part, H->n_tiles, R, out, s);
     RAD_HIP(hipGetLastError());
 }
 

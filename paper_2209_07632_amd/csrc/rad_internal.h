@@ -234,12 +234,22 @@ struct rad_hmat {
     rad::DevBuf<float> d_pscale, d_tscale;
     rad::DevBuf<double> w_norms;
     rad::DevBuf<int32_t> w_flags;         // per-column choices of warm-started solves
+
+    // group of independent matrices (block diagonal): instance k owns rows
+    // [inst_off[k], inst_off[k] + inst_n[k]) and tiles [inst_tile[k], inst_tile[k+1])
+    int32_t n_inst = 1;
+    std::vector<int64_t> inst_off, inst_n;
+    std::vector<int32_t> inst_tile;
+    rad::DevBuf<int32_t> d_inst_tile;
 };
 
 namespace rad {
 
 // thread-local error text
 void set_error(const std::string &msg);
+
+// Allocates the solve/matvec workspace of H for max_rhs right-hand sides.
+void alloc_workspace(rad_hmat *H);
 
 // Runs f, translating exceptions into a status code and the thread's last error.
 template <class F>

@@ -66,7 +66,8 @@ EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_matvec", "rad_s
            "rad_insolation", "rad_equilibrium", "rad_hmat_time_phases", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free",
            "rad_last_error", "rad_pod_build", "rad_pod_project", "rad_pod_expand", "rad_mlp_create",
            "rad_mlp_param_count", "rad_mlp_get_params", "rad_mlp_set_params", "rad_mlp_forward", "rad_mlp_loss_grad",
-           "rad_mlp_adam_step", "rad_mlp_train", "rad_mlp_free"]
+           "rad_mlp_adam_step", "rad_mlp_train", "rad_mlp_free", "rad_hmat_group", "rad_hmat_instances",
+           "rad_hmat_group_layout"]
 
 _lib = None
 
@@ -131,6 +132,12 @@ def load(path: str = LIB_PATH):
     for name, args in sigs.items():
         getattr(L, name).argtypes = args
         getattr(L, name).restype = ctypes.c_int
+    L.rad_hmat_group.argtypes = [vp, i32, i32, ctypes.POINTER(vp)]
+    L.rad_hmat_group.restype = ctypes.c_int
+    L.rad_hmat_instances.argtypes = [vp]
+    L.rad_hmat_instances.restype = i32
+    L.rad_hmat_group_layout.argtypes = [vp, vp, vp]
+    L.rad_hmat_group_layout.restype = ctypes.c_int
     L.rad_mlp_param_count.argtypes = [vp]
     L.rad_mlp_param_count.restype = i64
     L.rad_mlp_free.argtypes = [vp]
@@ -211,6 +218,29 @@ class HMatrix:
         self.lowp = int(o.lowp)
         self.max_rhs = int(max_rhs)
         self.device = int(device)
+        self.n_inst = 1
+
+    @classmethod
+    def group(cls, parts, max_rhs):
+        """Block-diagonal group of built matrices (one launch per kernel for all
+        instances).  Its layout is tree_rmajor with instance k at rows
+        offsets[k] .. offsets[k] + sizes[k]; padding rows between instances stay zero."""
+        L = load()
+        arr = (ctypes.c_void_p * len(parts))(*[p._h.value for p in parts])
+        h = ctypes.c_void_p()
+        _check(L.rad_hmat_group(arr, len(parts), int(max_rhs), ctypes.byref(h)))
+        self = object.__new__(cls)
+        self._h = h
+        self.N = int(L.rad_hmat_n(h))
+        self.rad_dtype = int(L.rad_hmat_dtype(h))
+        self.lowp = parts[0].lowp
+        self.max_rhs = int(max_rhs)
+        self.device = parts[0].device
+        self.n_inst = int(L.rad_hmat_instances(h))
+        self.offsets = np.zeros(self.n_inst, dtype=np.int64)
+        self.sizes = np.zeros(self.n_inst, dtype=np.int64)
+        _check(L.rad_hmat_group_layout(h, self.offsets.ctypes.data, self.sizes.ctypes.data))
+        return self
 
     @property
     def torch_dtype(self):
@@ -296,8 +326,8 @@ class HMatrix:
         o.refine = int(bool(refine))
         o.inner_iters = int(inner_iters)
         o.warm = int(warm is not None)
-        iters = np.zeros(R, dtype=np.int32)
-        rel = np.zeros(R, dtype=np.float64)
+        iters = np.zeros(R * self.n_inst, dtype=np.int32)
+        rel = np.zeros(R * self.n_inst, dtype=np.float64)
         info = SolveInfo(iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                          rel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0, 0, 0)
         st = L.rad_solve(self._h, rho_ptr, rho_s, R, self.rad_dtype, ctypes.c_void_p(Ec.data_ptr()), lde,
