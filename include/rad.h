@@ -255,6 +255,31 @@ rad_status rad_hmat_time_phases(const rad_hmat *H, int64_t R, int32_t dtype, int
  */
 rad_status rad_hmat_group(const rad_hmat *const *parts, int32_t count, int32_t max_rhs, rad_hmat **out);
 
+/*
+ * Autotuner of the multi-RHS kernels for R right-hand sides (R >= 16).  The
+ * candidates are 64- or 128-column workgroup tiles, each as a flat grid (one
+ * workgroup per 64-row tile and column tile) or as a persistent grid of 1, 2
+ * or 4 workgroups per compute unit pulling tiles, in decreasing order of
+ * their reduction length, from a work counter.  Each candidate runs nrep
+ * Jacobi iterations on the matrix's own blocks (timed with HIP events on
+ * hip_stream); the fastest is used by every later product and solve with
+ * this R.  cache_path (may be NULL) names a JSON file of earlier results
+ * keyed by the matrix signature (dtype, tile count, hash of the tile-cost
+ * histogram, compute units) and R: a hit is used without timing (ms = 0);
+ * a miss is timed and added.  config (host int32[3], may be NULL) receives
+ * (tn, persistent, blocks_per_cu); ms (may be NULL) the chosen time per
+ * iteration.  All candidates give identical products.  Synchronises.
+ * Errors: RAD_EINVAL (R out of range, bad cache file path), RAD_EDEVICE.
+ */
+rad_status rad_hmat_autotune(rad_hmat *H, int64_t R, int32_t nrep, const char *cache_path, int32_t *config,
+                             double *ms, void *hip_stream);
+
+/* Forces the configuration (tn 64|128, persistent 0|1, blocks_per_cu 1..64)
+ * for R right-hand sides, or reads the one in use (default: tn 64 for
+ * R <= 64 else 128, flat grid). */
+rad_status rad_hmat_set_config(rad_hmat *H, int64_t R, const int32_t *config);
+rad_status rad_hmat_get_config(const rad_hmat *H, int64_t R, int32_t *config);
+
 /* Instances in H (1 for a matrix built by rad_hmat_build; -1 for NULL). */
 int32_t rad_hmat_instances(const rad_hmat *H);
 

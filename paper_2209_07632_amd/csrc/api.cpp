@@ -36,6 +36,7 @@ void alloc_workspace(rad_hmat *H) {
     if (H->lowp) H->w_b64.alloc(nr);
     RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * nc, hipHostMallocDefault));
     RAD_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
+    if (H->n_tiles > 0) mm_prepare_schedule(H);
 }
 
 // One Jacobi iteration, enqueued on stream s: B_new = E + rho (F-hat B_old),

@@ -13,6 +13,10 @@
 //       CSR slices are expanded to dense chunks in LDS.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
 #include "rad_internal.h"
 #include "mm_epilogue.h"
 
@@ -20,8 +24,7 @@ namespace rad {
 
 namespace {
 
-constexpr int TM = 64;    // output rows per workgroup
-constexpr int TN = 128;   // output columns (right-hand sides) per workgroup
+constexpr int TM = 64;    // output rows per workgroup; TN (64 or 128) columns is a template parameter
 constexpr int KC = 16;    // reduction chunk
 constexpr int PADA = 4, PADB = 4;
 
@@ -50,15 +53,16 @@ struct Mfma<double> {
     static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
 };
 
-// acc[i][j]: row tile i (16 rows), column tile j (16 columns of this wave's 32)
-template <class T>
+// acc[i][j]: row tile i (16 rows), column tile j (16 columns of this wave's TN / 4)
+template <class T, int TN>
 struct Tile {
-    typename Mfma<T>::acc_t acc[4][2];
+    static constexpr int NJ = TN / 64;
+    typename Mfma<T>::acc_t acc[4][NJ];
     __device__ __forceinline__ void zero() {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < NJ; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
     }
@@ -68,15 +72,15 @@ struct Tile {
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
             const int k = s * 4 + lk;
-            T a[4], b[2];
+            T a[4], b[NJ];
 #pragma unroll
             for (int i = 0; i < 4; ++i) a[i] = sA[k][i * 16 + lr];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = sB[k][w * 32 + j * 16 + lr];
+            for (int j = 0; j < NJ; ++j) b[j] = sB[k][w * (TN / 4) + j * 16 + lr];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
         }
     }
 };
@@ -84,7 +88,7 @@ struct Tile {
 // B chunk: rows [brow, brow + kcount) of an R-major matrix, columns [r0, r0+TN).
 // ldr and r0 are multiples of 4, so groups of four columns are loaded as one
 // 16-byte (FP32) or two 16-byte (FP64) vectors.
-template <class T>
+template <class T, int TN>
 __device__ __forceinline__ void load_b_rmajor(T (*sB)[TN + PADB], const T *src, int64_t brow, int kcount,
                                               int64_t ldr, int r0, int R, int t) {
     for (int e = t; e < KC * TN / 4; e += 256) {
@@ -129,7 +133,7 @@ __device__ __forceinline__ void load_a_colmajor(T (*sA)[TM + PADA], const T *src
 // loads of chunk c+1 are in flight while chunk c runs on the matrix cores.
 // A[r][k]: kind 0 = column-major block rows (row_off + r, r in [r_lo, r_hi)),
 //          kind 1 = transposed V (A[r][k] = V[k + r * ld], r < r_hi).
-template <class T>
+template <class T, int TN>
 struct Stage {
     T a[KC * TM / 256];
     T b[KC * TN / 256];
@@ -201,7 +205,7 @@ struct Stage {
 
 // Chunk of a packed panel (64 x KC contiguous, ld 64) and of the operand rows
 // it multiplies (gathered through brow: X row if >= 0, T row -1-v if < 0).
-template <class T>
+template <class T, int TN>
 struct PanelStage {
     T a[KC * TM / 256];
     T b[KC * TN / 256];
@@ -269,7 +273,7 @@ struct PanelStage {
 // ---------------------------------------------------------------------------
 // phase 1: partial projections
 // ---------------------------------------------------------------------------
-template <class T>
+template <class T, int TN>
 __global__ void __launch_bounds__(256) k_proj_mm(const ProjGroup *groups, const P1Work *work, const T *vals,
                                                   const T *X, int64_t ldr, int R, T *part) {
     const P1Work wk = work[blockIdx.x];
@@ -278,11 +282,11 @@ __global__ void __launch_bounds__(256) k_proj_mm(const ProjGroup *groups, const 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     __shared__ T sA[2][KC][TM + PADA];
     __shared__ T sB[2][KC][TN + PADB];
-    Tile<T> tile;
+    Tile<T, TN> tile;
     tile.zero();
     const int rows = min(TM, g.ktot - wk.krow0);
     const T *V = vals + g.v_off + (int64_t)wk.krow0 * g.ld;
-    Stage<T> st;
+    Stage<T, TN> st;
     int buf = 0;
     st.fetch(1, V, g.ld, 0, 0, rows, wk.jb, min(KC, wk.je - wk.jb), X, (int64_t)g.j0 + wk.jb, ldr, r0, R, t);
     for (int kb = wk.jb; kb < wk.je; kb += KC) {
@@ -298,11 +302,11 @@ __global__ void __launch_bounds__(256) k_proj_mm(const ProjGroup *groups, const 
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TN / 64; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 int row = i * 16 + Mfma<T>::row(lk, v);
-                int col = r0 + w * 32 + j * 16 + lr;
+                int col = r0 + w * (TN / 4) + j * 16 + lr;
                 if (col < R) out[(int64_t)row * ldr + col] = tile.acc[i][j][v];
             }
 }
@@ -325,25 +329,28 @@ __global__ void __launch_bounds__(256) k_proj_reduce(const P1Red *red, const T *
 // the epilogue performs the Jacobi update B_new = E + rho * (F B_old) and
 // writes the per-column partial sums of (B_new - B_old)^2 for this tile.
 // ---------------------------------------------------------------------------
-template <class T, bool kFused>
-__global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
-                                                  const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
-                                                  int64_t csr_val_start, const T *X, const T *Tb, int64_t ldr, int R,
-                                                  int64_t N, T *Y, const T *E, const T *rho, T rho_s,
-                                                  double *partial) {
-    const int tile = blockIdx.x;
+template <class T, int TN>
+struct TileSmem {
+    static constexpr int kPipe = 2 * KC * (TM + PADA) + 2 * KC * (TN + PADB);
+    static constexpr int kOut = TM * (TN + PADB);
+    static constexpr int kSize = kPipe > kOut ? kPipe : kOut;
+    static_assert(1024 * sizeof(double) <= sizeof(T) * kSize, "partial sums fit");
+};
+
+template <class T, bool kFused, int TN>
+__device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileInfo *tiles, const int32_t *brow,
+                                          const TileTask *ctasks, const T *vals, const int32_t *csr_ptr,
+                                          const int32_t *csr_idx, int64_t csr_val_start, const T *X, const T *Tb,
+                                          int64_t ldr, int R, int64_t N, T *Y, const T *E, const T *rho, T rho_s,
+                                          double *partial) {
     const TileInfo ti = tiles[tile];
     const int64_t tile0 = (int64_t)tile * TM;
-    const int r0 = blockIdx.y * TN;
+    const int r0 = rt * TN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    // pipeline buffers during the reduction, the 64 x 128 result tile after it
-    constexpr int kPipe = 2 * KC * (TM + PADA) + 2 * KC * (TN + PADB);
-    constexpr int kOut = TM * (TN + PADB);
-    __shared__ T smem[kPipe > kOut ? kPipe : kOut];
-    static_assert(8 * TN * sizeof(double) <= sizeof(T) * (kPipe > kOut ? kPipe : kOut), "partial sums fit");
+    // pipeline buffers during the reduction, the 64 x TN result tile after it
     T (*sA)[KC][TM + PADA] = (T (*)[KC][TM + PADA])smem;
     T (*sB)[KC][TN + PADB] = (T (*)[KC][TN + PADB])(smem + 2 * KC * (TM + PADA));
-    Tile<T> acc;
+    Tile<T, TN> acc;
     acc.zero();
     // CSR tasks: rows expanded into dense chunks in LDS
     for (int c = ti.csr_begin; c < ti.csr_end; ++c) {
@@ -363,7 +370,7 @@ __global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const in
                 sA[0][ci[cur] - kb][t] = v[cur];
                 ++cur;
             }
-            load_b_rmajor(sB[0], X, (int64_t)tk.col0 + kb, kcount, ldr, r0, R, t);
+            load_b_rmajor<T, TN>(sB[0], X, (int64_t)tk.col0 + kb, kcount, ldr, r0, R, t);
             __syncthreads();
             acc.mma(sA[0], sB[0], lane, w);
             __syncthreads();
@@ -373,7 +380,7 @@ __global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const in
     if (ti.kpad > 0) {
         const T *pan = vals + ti.panel_off;
         const int32_t *br = brow + ti.brow_off;
-        PanelStage<T> st;
+        PanelStage<T, TN> st;
         st.fetch(pan, br, X, Tb, ldr, r0, R, t);
         int buf = 0;
         for (int kb = 0; kb < ti.kpad; kb += KC) {
@@ -384,9 +391,9 @@ __global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const in
             buf ^= 1;
         }
     }
-    // epilogue through LDS: the 64 x 128 result tile is written to LDS, then
-    // every thread streams 16-byte groups of whole rows (coalesced E, B_old,
-    // B_new accesses).  Per-column partial sums are reduced in a fixed order.
+    // epilogue through LDS: the result tile is written to LDS, then every
+    // thread streams 16-byte groups of whole rows (coalesced E, B_old, B_new
+    // accesses).  Per-column partial sums are reduced in a fixed order.
     __syncthreads();
     T (*sC)[TN + PADB] = (T (*)[TN + PADB])smem;
     {
@@ -394,12 +401,58 @@ __global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const in
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < TN / 64; ++j)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) sC[i * 16 + Mfma<T>::row(lk, v)][w * 32 + j * 16 + lr] = acc.acc[i][j][v];
+                for (int v = 0; v < 4; ++v)
+                    sC[i * 16 + Mfma<T>::row(lk, v)][w * (TN / 4) + j * 16 + lr] = acc.acc[i][j][v];
     }
     __syncthreads();
     tile_epilogue<T, kFused, TM, TN, TN + PADB>(sC, smem, tile, tile0, r0, ldr, R, N, Y, E, X, rho, rho_s, partial);
+}
+
+// one workgroup per (64-row tile, TN-column tile)
+template <class T, bool kFused, int TN>
+__global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
+                                                  const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
+                                                  int64_t csr_val_start, const T *X, const T *Tb, int64_t ldr, int R,
+                                                  int64_t N, T *Y, const T *E, const T *rho, T rho_s,
+                                                  double *partial) {
+    __shared__ T smem[TileSmem<T, TN>::kSize];
+    tile_body<T, kFused, TN>(smem, blockIdx.x, blockIdx.y, tiles, brow, ctasks, vals, csr_ptr, csr_idx, csr_val_start,
+                             X, Tb, ldr, R, N, Y, E, rho, rho_s, partial);
+}
+
+// Persistent form: a fixed grid pulls work items (tiles in decreasing cost
+// order, all column tiles of a tile in a row) from a counter.  Every
+// workgroup leaves when the counter passes nwork; the last one to leave
+// resets both counters for the next launch (no memset in captured graphs).
+template <class T, bool kFused, int TN>
+__global__ void __launch_bounds__(256) k_tile_mm_q(const TileInfo *tiles, const int32_t *brow,
+                                                    const TileTask *ctasks, const T *vals, const int32_t *csr_ptr,
+                                                    const int32_t *csr_idx, int64_t csr_val_start, const T *X,
+                                                    const T *Tb, int64_t ldr, int R, int64_t N, T *Y, const T *E,
+                                                    const T *rho, T rho_s, double *partial, const int32_t *order,
+                                                    int nwork, int rtiles, int *queue) {
+    __shared__ T smem[TileSmem<T, TN>::kSize];
+    __shared__ int item;
+    while (true) {
+        if (threadIdx.x == 0) item = atomicAdd(&queue[0], 1);
+        __syncthreads();
+        const int wi = item;
+        __syncthreads();
+        if (wi >= nwork) break;
+        tile_body<T, kFused, TN>(smem, order[wi / rtiles], wi % rtiles, tiles, brow, ctasks, vals, csr_ptr, csr_idx,
+                                 csr_val_start, X, Tb, ldr, R, N, Y, E, rho, rho_s, partial);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {
+            queue[0] = 0;
+            queue[1] = 0;
+            __threadfence();
+        }
+    }
 }
 
 // col-major (original or tree order) <-> R-major tree order, 64 x 64 tiles
@@ -501,12 +554,12 @@ __global__ void __launch_bounds__(256) k_colnorm_tiles(const T *E, int64_t N, in
 
 constexpr int kRmParts = 64;
 
-template <class T>
-void proj_mm_t(const rad_hmat *H, const T *X, int64_t ldr, int R, hipStream_t s) {
+template <class T, int TN>
+void proj_mm_tn(const rad_hmat *H, const T *X, int64_t ldr, int R, hipStream_t s) {
     unsigned rtiles = (unsigned)((R + TN - 1) / TN);
     if (H->n_p1work > 0) {
-        hipLaunchKernelGGL(k_proj_mm<T>, dim3(H->n_p1work, rtiles), dim3(256), 0, s, H->d_groups.p, H->d_p1work.p,
-                           (const T *)H->d_vals.p, X, ldr, R, (T *)H->w_part.p);
+        hipLaunchKernelGGL((k_proj_mm<T, TN>), dim3(H->n_p1work, rtiles), dim3(256), 0, s, H->d_groups.p,
+                           H->d_p1work.p, (const T *)H->d_vals.p, X, ldr, R, (T *)H->w_part.p);
         RAD_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_proj_reduce<T>, dim3(H->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s, H->d_p1red.p,
                            (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p);
@@ -514,20 +567,48 @@ void proj_mm_t(const rad_hmat *H, const T *X, int64_t ldr, int R, hipStream_t s)
     }
 }
 
+template <class T, bool kFused, int TN>
+void tile_mm_launch(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int64_t ldr, int R, const T *E,
+                    const T *rho, T rho_s, double *partial, hipStream_t s) {
+    const int rtiles = (R + TN - 1) / TN;
+    if (c.persistent) {
+        const int nwork = H->n_tiles * rtiles;
+        const int grid = std::max(1, std::min(nwork, H->n_cu * std::max(1, (int)c.blocks_per_cu)));
+        hipLaunchKernelGGL((k_tile_mm_q<T, kFused, TN>), dim3(grid), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
+                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
+                           H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial,
+                           (const int32_t *)H->d_tile_order.p, nwork, rtiles, H->d_queue.p);
+    } else {
+        hipLaunchKernelGGL((k_tile_mm<T, kFused, TN>), dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p,
+                           H->d_brow.p, H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
+                           H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial);
+    }
+    RAD_HIP(hipGetLastError());
+}
+
+template <class T, int TN>
+void apply_mm_tn(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int64_t ldr, int R, const T *E, const T *rho,
+                 T rho_s, double *partial, hipStream_t s) {
+    proj_mm_tn<T, TN>(H, X, ldr, R, s);
+    if (E)
+        tile_mm_launch<T, true, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
+    else
+        tile_mm_launch<T, false, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
+}
+
+template <class T>
+void apply_mm_cfg(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int64_t ldr, int R, const T *E,
+                  const T *rho, T rho_s, double *partial, hipStream_t s) {
+    if (c.tn == 64)
+        apply_mm_tn<T, 64>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
+    else
+        apply_mm_tn<T, 128>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
+}
+
 template <class T>
 void apply_mm_t(const rad_hmat *H, const T *X, T *Y, int64_t ldr, int R, const T *E, const T *rho, T rho_s,
                 double *partial, hipStream_t s) {
-    proj_mm_t<T>(H, X, ldr, R, s);
-    unsigned rtiles = (unsigned)((R + TN - 1) / TN);
-    if (E)
-        hipLaunchKernelGGL((k_tile_mm<T, true>), dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
-                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
-                           H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial);
-    else
-        hipLaunchKernelGGL((k_tile_mm<T, false>), dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p,
-                           H->d_brow.p, H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
-                           H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial);
-    RAD_HIP(hipGetLastError());
+    apply_mm_cfg<T>(H, mm_config(H, R), X, Y, ldr, R, E, rho, rho_s, partial, s);
 }
 
 }  // namespace
@@ -589,43 +670,76 @@ void time_phases_t(const rad_hmat *H, int R, int nrep, hipStream_t s, double *ms
     T *Y = (T *)H->w_b.p;
     const T *E = (const T *)H->w_e.p;
     double *part = (double *)H->w_red.p;
-    unsigned rtiles = (unsigned)((R + TN - 1) / TN);
+    const MmConfig c = mm_config(H, R);
     hipEvent_t e0, e1;
     RAD_HIP(hipEventCreate(&e0));
     RAD_HIP(hipEventCreate(&e1));
     float t = 0;
+    auto timed = [&](auto &&launch) {
+        RAD_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < nrep; ++i) launch();
+        RAD_HIP(hipEventRecord(e1, s));
+        RAD_HIP(hipEventSynchronize(e1));
+        RAD_HIP(hipEventElapsedTime(&t, e0, e1));
+        return (double)t / nrep;
+    };
     ms[0] = ms[1] = ms[2] = 0.0;
     if (H->n_p1work > 0) {
-        RAD_HIP(hipEventRecord(e0, s));
-        for (int i = 0; i < nrep; ++i)
-            hipLaunchKernelGGL(k_proj_mm<T>, dim3(H->n_p1work, rtiles), dim3(256), 0, s, H->d_groups.p,
-                               H->d_p1work.p, (const T *)H->d_vals.p, X, ldr, R, (T *)H->w_part.p);
-        RAD_HIP(hipEventRecord(e1, s));
-        RAD_HIP(hipEventSynchronize(e1));
-        RAD_HIP(hipEventElapsedTime(&t, e0, e1));
-        ms[0] = t / nrep;
-        RAD_HIP(hipEventRecord(e0, s));
-        for (int i = 0; i < nrep; ++i)
+        const unsigned rtiles = (unsigned)((R + c.tn - 1) / c.tn);
+        ms[0] = timed([&] {
+            if (c.tn == 64)
+                hipLaunchKernelGGL((k_proj_mm<T, 64>), dim3(H->n_p1work, rtiles), dim3(256), 0, s, H->d_groups.p,
+                                   H->d_p1work.p, (const T *)H->d_vals.p, X, ldr, R, (T *)H->w_part.p);
+            else
+                hipLaunchKernelGGL((k_proj_mm<T, 128>), dim3(H->n_p1work, rtiles), dim3(256), 0, s, H->d_groups.p,
+                                   H->d_p1work.p, (const T *)H->d_vals.p, X, ldr, R, (T *)H->w_part.p);
+        });
+        ms[1] = timed([&] {
             hipLaunchKernelGGL(k_proj_reduce<T>, dim3(H->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s,
                                H->d_p1red.p, (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p);
-        RAD_HIP(hipEventRecord(e1, s));
-        RAD_HIP(hipEventSynchronize(e1));
-        RAD_HIP(hipEventElapsedTime(&t, e0, e1));
-        ms[1] = t / nrep;
+        });
     }
-    RAD_HIP(hipEventRecord(e0, s));
-    for (int i = 0; i < nrep; ++i)
-        hipLaunchKernelGGL((k_tile_mm<T, true>), dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
-                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
-                           H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, (const T *)nullptr, (T)0.3,
-                           part);
-    RAD_HIP(hipEventRecord(e1, s));
-    RAD_HIP(hipEventSynchronize(e1));
-    RAD_HIP(hipEventElapsedTime(&t, e0, e1));
-    ms[2] = t / nrep;
+    ms[2] = timed([&] {
+        if (c.tn == 64)
+            tile_mm_launch<T, true, 64>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3, part, s);
+        else
+            tile_mm_launch<T, true, 128>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3, part, s);
+    });
     RAD_HIP(hipGetLastError());
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+}
+
+template <class T>
+std::vector<std::pair<MmConfig, double>> autotune_t(rad_hmat *H, int R, int nrep, hipStream_t s) {
+    const int64_t ldr = mm_ldr(R);
+    const T *X = (const T *)H->w_x.p;
+    T *Y = (T *)H->w_b.p;
+    const T *E = (const T *)H->w_e.p;
+    double *part = (double *)H->w_red.p;
+    std::vector<MmConfig> cands;
+    for (int tn : {64, 128}) {
+        cands.push_back(MmConfig{tn, 0, 0});
+        for (int bpc : {1, 2, 4}) cands.push_back(MmConfig{tn, 1, bpc});
+    }
+    hipEvent_t e0, e1;
+    RAD_HIP(hipEventCreate(&e0));
+    RAD_HIP(hipEventCreate(&e1));
+    std::vector<std::pair<MmConfig, double>> out;
+    for (const MmConfig &c : cands) {
+        // one Jacobi iteration's kernels: projections, their sum, fused expansion
+        apply_mm_cfg<T>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3, part, s);
+        float t = 0;
+        RAD_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < nrep; ++i) apply_mm_cfg<T>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3, part, s);
+        RAD_HIP(hipEventRecord(e1, s));
+        RAD_HIP(hipEventSynchronize(e1));
+        RAD_HIP(hipEventElapsedTime(&t, e0, e1));
+        out.push_back({c, (double)t / nrep});
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return out;
 }
 
 void mm_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, double *ms) {
@@ -633,6 +747,71 @@ void mm_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, doubl
         time_phases_t<double>(H, (int)R, nrep, s, ms);
     else
         time_phases_t<float>(H, (int)R, nrep, s, ms);
+}
+
+MmConfig mm_config(const rad_hmat *H, int64_t R) {
+    for (const auto &e : H->tuned)
+        if (e.first == R) return e.second;
+    MmConfig c;
+    c.tn = R <= 64 ? 64 : 128;
+    return c;
+}
+
+// tile order for the persistent kernels: decreasing reduction length
+// (panel columns plus CSR columns), ties by tile index; and the zeroed counter
+void mm_prepare_schedule(rad_hmat *H) {
+    const int32_t n = H->n_tiles;
+    std::vector<TileInfo> ti = H->d_tiles.download((size_t)n);
+    std::vector<TileTask> tk = H->d_tile_tasks.download(H->d_tile_tasks.n);
+    std::vector<int64_t> cost(n, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        cost[i] = ti[i].kpad;
+        for (int32_t c = ti[i].csr_begin; c < ti[i].csr_end; ++c) cost[i] += tk[c].ncol;
+    }
+    std::vector<int32_t> order(n);
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    H->d_tile_order.upload(order);
+    std::vector<int32_t> zero(2, 0);
+    H->d_queue.upload(zero);
+    int ncu = 0;
+    RAD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, H->device));
+    H->n_cu = std::max(1, ncu);
+    // signature: FNV-1a over the log2 histogram of tile costs and the shape counts
+    std::vector<int64_t> hist(40, 0);
+    for (int64_t c : cost) {
+        int b = 0;
+        while (b < 39 && ((int64_t)1 << b) <= c) ++b;
+        hist[b]++;
+    }
+    hist.push_back(H->n_p1work);
+    hist.push_back(H->n_p1red);
+    hist.push_back(H->n_inst);
+    uint64_t h = 1469598103934665603ull;
+    for (int64_t v : hist)
+        for (int byte = 0; byte < 8; ++byte) {
+            h ^= (uint64_t)((v >> (8 * byte)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "dt%d_tiles%d_cu%d_h%016llx", (int)H->dtype, (int)n, H->n_cu,
+                  (unsigned long long)h);
+    H->sched_sig = buf;
+}
+
+std::vector<std::pair<MmConfig, double>> mm_autotune(rad_hmat *H, int64_t R, int nrep, hipStream_t s) {
+    auto res = H->dtype == RAD_F64 ? autotune_t<double>(H, (int)R, nrep, s) : autotune_t<float>(H, (int)R, nrep, s);
+    size_t best = 0;
+    for (size_t i = 1; i < res.size(); ++i)
+        if (res[i].second < res[best].second) best = i;
+    bool found = false;
+    for (auto &e : H->tuned)
+        if (e.first == R) {
+            e.second = res[best].first;
+            found = true;
+        }
+    if (!found) H->tuned.push_back({R, res[best].first});
+    return res;
 }
 
 void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s) {

@@ -1,6 +1,6 @@
 // Shared epilogue of the multi-RHS expansion kernels (included by the
-// FP32/FP64 and the 16-bit kernels).  The 64 x 128 FP32/FP64 result tile sits
-// in LDS (sC); every thread streams 16-byte groups of whole rows: Y = tile, or
+// FP32/FP64 and the 16-bit kernels).  The 64 x TN (TN = 64 or 128) result tile
+// sits in LDS (sC); every thread streams 16-byte groups of whole rows: Y = tile, or
 // with the fused Jacobi update B_new = E + rho * tile, writing the per-column
 // partial sums of (B_new - B_old)^2 of this tile.  Reductions use a fixed order.
 #pragma once
@@ -13,22 +13,26 @@ template <class T, bool kFused, int TM, int TN, int LDC>
 __device__ __forceinline__ void tile_epilogue(const T (*sC)[LDC], void *smem, int tile, int64_t tile0, int r0,
                                               int64_t ldr, int R, int64_t N, T *Y, const T *E, const T *X,
                                               const T *rho, T rho_s, double *partial) {
+    constexpr int CT = TN / 4;            // threads per row, four columns each
+    constexpr int RS = 256 / CT;          // row groups
+    constexpr int NQ = TM / RS;           // rows per thread
+    static_assert(NQ % 4 == 0 && RS * CT == 256, "tile shape");
     const int t = threadIdx.x;
     const int rows = (int)min((int64_t)TM, N - tile0);
-    const int c4 = (t & 31) * 4;          // this thread's four columns
-    const int rsub = t >> 5;              // rows rsub, rsub + 8, ...
+    const int c4 = (t % CT) * 4;          // this thread's four columns
+    const int rsub = t / CT;              // rows rsub, rsub + RS, ...
     const int col = r0 + c4;
     double d2[4] = {0.0, 0.0, 0.0, 0.0};
     const bool full = col + 3 < R;
-    // rows rsub + 8q in two halves of four: all loads of a half first, then
+    // rows rsub + RS q in groups of four: all loads of a group first, then
     // the arithmetic and the stores
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
+    for (int half = 0; half < NQ / 4; ++half) {
         T ev[4][4], bo[4][4];
         if constexpr (kFused) {
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) {
-                const int row = rsub + 8 * (4 * half + qq);
+                const int row = rsub + RS * (4 * half + qq);
                 const int64_t e = (tile0 + row) * ldr + col;
                 if (row < rows && full) {
                     if constexpr (sizeof(T) == 4) {
@@ -53,7 +57,7 @@ __device__ __forceinline__ void tile_epilogue(const T (*sC)[LDC], void *smem, in
         }
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
-            const int row = rsub + 8 * (4 * half + qq);
+            const int row = rsub + RS * (4 * half + qq);
             if (row < rows) {
                 const int64_t e = (tile0 + row) * ldr + col;
                 T y[4] = {sC[row][c4], sC[row][c4 + 1], sC[row][c4 + 2], sC[row][c4 + 3]};
@@ -84,13 +88,13 @@ __device__ __forceinline__ void tile_epilogue(const T (*sC)[LDC], void *smem, in
     }
     if constexpr (kFused) {
         __syncthreads();
-        double *red = (double *)smem;   // 8 x 128 partial sums (fits in the LDS tile)
+        double *red = (double *)smem;   // RS x TN partial sums (1024 doubles; fit in the LDS tile)
 #pragma unroll
         for (int u = 0; u < 4; ++u) red[rsub * TN + c4 + u] = d2[u];
         __syncthreads();
         if (t < TN) {
             double sum = 0.0;
-            for (int q = 0; q < 8; ++q) sum += red[q * TN + t];
+            for (int q = 0; q < RS; ++q) sum += red[q * TN + t];
             if (r0 + t < R) partial[(int64_t)tile * R + r0 + t] = sum;
         }
     }

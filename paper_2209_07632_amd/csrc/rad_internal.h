@@ -161,6 +161,13 @@ struct ProjGroup {
     int32_t pad_;
 };
 
+// Launch configuration of the multi-RHS kernels for one R (rad_hmat_autotune).
+struct MmConfig {
+    int32_t tn = 128;          // right-hand-side columns per workgroup: 64 or 128
+    int32_t persistent = 0;    // 1: fixed grid pulling work items from a counter
+    int32_t blocks_per_cu = 2; // grid of the persistent form, per compute unit
+};
+
 // Phase-1 split-K work item of the multi-RHS path: rows [krow0, krow0+64) of
 // stacked V_J^T times facets [jb, je) of the column node, into partial tile `part`.
 struct P1Work {
@@ -238,6 +245,13 @@ struct rad_hmat {
     // group of independent matrices (block diagonal): instance k owns rows
     // [inst_off[k], inst_off[k] + inst_n[k]) and tiles [inst_tile[k], inst_tile[k+1])
     int32_t n_inst = 1;
+
+    // multi-RHS launch configurations (autotuned per R), tile order by
+    // decreasing cost and the work counter of the persistent kernels
+    std::vector<std::pair<int64_t, rad::MmConfig>> tuned;
+    rad::DevBuf<int32_t> d_tile_order, d_queue;
+    int32_t n_cu = 256;
+    std::string sched_sig;           // dtype, tile count and tile-cost histogram hash (autotuner cache key)
     std::vector<int64_t> inst_off, inst_n;
     std::vector<int32_t> inst_tile;
     rad::DevBuf<int32_t> d_inst_tile;
@@ -346,6 +360,11 @@ void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, dou
 void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
                     int64_t ldr, int64_t R, double *norms, hipStream_t s);
 size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R);
+rad::MmConfig mm_config(const rad_hmat *H, int64_t R);
+void mm_prepare_schedule(rad_hmat *H);
+// times every candidate configuration of one Jacobi iteration for R columns
+// and records the fastest in H->tuned; returns (config, ms) of every candidate
+std::vector<std::pair<rad::MmConfig, double>> mm_autotune(rad_hmat *H, int64_t R, int nrep, hipStream_t s);
 void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s);
 
 // 16-bit operator (lowp_kernels.hip)

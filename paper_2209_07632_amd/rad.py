@@ -67,7 +67,7 @@ EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_matvec", "rad_s
            "rad_last_error", "rad_pod_build", "rad_pod_project", "rad_pod_expand", "rad_mlp_create",
            "rad_mlp_param_count", "rad_mlp_get_params", "rad_mlp_set_params", "rad_mlp_forward", "rad_mlp_loss_grad",
            "rad_mlp_adam_step", "rad_mlp_train", "rad_mlp_free", "rad_hmat_group", "rad_hmat_instances",
-           "rad_hmat_group_layout"]
+           "rad_hmat_group_layout", "rad_hmat_autotune", "rad_hmat_set_config", "rad_hmat_get_config"]
 
 _lib = None
 
@@ -138,6 +138,12 @@ def load(path: str = LIB_PATH):
     L.rad_hmat_instances.restype = i32
     L.rad_hmat_group_layout.argtypes = [vp, vp, vp]
     L.rad_hmat_group_layout.restype = ctypes.c_int
+    L.rad_hmat_autotune.argtypes = [vp, i64, i32, ctypes.c_char_p, vp, vp, vp]
+    L.rad_hmat_autotune.restype = ctypes.c_int
+    L.rad_hmat_set_config.argtypes = [vp, i64, vp]
+    L.rad_hmat_set_config.restype = ctypes.c_int
+    L.rad_hmat_get_config.argtypes = [vp, i64, vp]
+    L.rad_hmat_get_config.restype = ctypes.c_int
     L.rad_mlp_param_count.argtypes = [vp]
     L.rad_mlp_param_count.restype = i64
     L.rad_mlp_free.argtypes = [vp]
@@ -246,6 +252,25 @@ class HMatrix:
     def torch_dtype(self):
         torch = _torch()
         return torch.float64 if self.rad_dtype == RAD_F64 else torch.float32
+
+    def autotune(self, R, nrep=5, cache=None):
+        """Pick the fastest multi-RHS launch configuration for R columns
+        (timed on this matrix, or read from the JSON cache file)."""
+        cfg = np.zeros(3, dtype=np.int32)
+        ms = ctypes.c_double()
+        path = None if cache is None else str(cache).encode()
+        _check(load().rad_hmat_autotune(self._h, int(R), int(nrep), path, cfg.ctypes.data, ctypes.byref(ms),
+                                        _stream_handle()))
+        return {"tn": int(cfg[0]), "persistent": int(cfg[1]), "blocks_per_cu": int(cfg[2]), "ms": ms.value}
+
+    def set_config(self, R, tn, persistent=0, blocks_per_cu=2):
+        cfg = np.array([tn, persistent, blocks_per_cu], dtype=np.int32)
+        _check(load().rad_hmat_set_config(self._h, int(R), cfg.ctypes.data))
+
+    def get_config(self, R):
+        cfg = np.zeros(3, dtype=np.int32)
+        _check(load().rad_hmat_get_config(self._h, int(R), cfg.ctypes.data))
+        return {"tn": int(cfg[0]), "persistent": int(cfg[1]), "blocks_per_cu": int(cfg[2])}
 
     def stats(self) -> dict:
         s = Stats()
