@@ -818,7 +818,16 @@ struct Builder {
         }
         const int64_t csr_val_start = vfill;
         vfill += csr_nnz_total;
-        for (TileTask &t : ttasks) t.a_off += csr_val_start;
+        for (TileTask &t : ttasks) {
+            t.a_off += csr_val_start;
+            // rows that hold every column of the block: their values form a
+            // row-major dense slab the expansion kernel stages without indices
+            t.full = 1;
+            for (int32_t r = t.r_lo; r < t.r_hi && t.full; ++r) {
+                const int64_t q = t.aux_off + t.row_off + r;
+                if (h_ptr[q + 1] - h_ptr[q] != t.ncol) t.full = 0;
+            }
+        }
 
         // allocate the value pool and fill it
         H->d_vals.alloc((size_t)std::max<int64_t>(vfill, 1) * s);
@@ -885,6 +894,13 @@ struct Builder {
                     red.push_back(rd);
                 }
             }
+            // launch order: the row tiles of one facet chunk next to each other,
+            // so that workgroups sharing an X chunk run together (same L2)
+            std::stable_sort(work.begin(), work.end(), [](const P1Work &a, const P1Work &b) {
+                if (a.group != b.group) return a.group < b.group;
+                if (a.jb != b.jb) return a.jb < b.jb;
+                return a.krow0 < b.krow0;
+            });
             H->d_p1work.upload(work);
             H->d_p1red.upload(red);
             H->n_p1work = (int32_t)work.size();

@@ -54,31 +54,32 @@ struct Mfma<double> {
 };
 
 // acc[i][j]: row tile i (16 rows), column tile j (16 columns of this wave's TN / 4)
-template <class T, int TN>
+// MI row tiles of 16 (64 rows for the expansion, 128 for paired projections)
+template <class T, int TN, int MI = 4>
 struct Tile {
     static constexpr int NJ = TN / 64;
-    typename Mfma<T>::acc_t acc[4][NJ];
+    typename Mfma<T>::acc_t acc[MI][NJ];
     __device__ __forceinline__ void zero() {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
             for (int j = 0; j < NJ; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
     }
     // one chunk of KC from LDS: sA[k][row], sB[k][col]
-    __device__ __forceinline__ void mma(const T (*sA)[TM + PADA], const T (*sB)[TN + PADB], int lane, int w) {
+    __device__ __forceinline__ void mma(const T (*sA)[MI * 16 + PADA], const T (*sB)[TN + PADB], int lane, int w) {
         const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
             const int k = s * 4 + lk;
-            T a[4], b[NJ];
+            T a[MI], b[NJ];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = sA[k][i * 16 + lr];
+            for (int i = 0; i < MI; ++i) a[i] = sA[k][i * 16 + lr];
 #pragma unroll
             for (int j = 0; j < NJ; ++j) b[j] = sB[k][w * (TN / 4) + j * 16 + lr];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < MI; ++i)
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
         }
@@ -132,13 +133,15 @@ __device__ __forceinline__ void load_a_colmajor(T (*sA)[TM + PADA], const T *src
 // One reduction chunk of a GEMM, staged through registers so that the global
 // loads of chunk c+1 are in flight while chunk c runs on the matrix cores.
 // A[r][k]: kind 0 = column-major block rows (row_off + r, r in [r_lo, r_hi)),
-//          kind 1 = transposed V (A[r][k] = V[k + r * ld], r < r_hi).
+//          kind 1 = transposed V (A[r][k] = V[k + r * ld], r < r_hi),
+//          kind 2 = complete CSR rows (A[r][k] = A[rb[r] + k], r in [r_lo, r_hi)).
 template <class T, int TN>
 struct Stage {
     T a[KC * TM / 256];
     T b[KC * TN / 256];
     __device__ __forceinline__ void fetch(int kind, const T *A, int64_t ld, int row_off, int r_lo, int r_hi, int kb,
-                                          int kcount, const T *B, int64_t brow, int64_t ldr, int r0, int R, int t) {
+                                          int kcount, const T *B, int64_t brow, int64_t ldr, int r0, int R, int t,
+                                          const int32_t *rb = nullptr) {
 #pragma unroll
         for (int q = 0; q < KC * TM / 256; ++q) {
             int e = t + q * 256;
@@ -146,6 +149,9 @@ struct Stage {
             if (kind == 0) {
                 int k = e / TM, r = e - k * TM;
                 if (k < kcount && r >= r_lo && r < r_hi) v = A[(int64_t)(row_off + r) + (int64_t)(kb + k) * ld];
+            } else if (kind == 2) {
+                int r = e / KC, k = e - r * KC;
+                if (k < kcount && r >= r_lo && r < r_hi) v = A[(int64_t)rb[r] + kb + k];
             } else {
                 int r = e / KC, k = e - r * KC;
                 if (k < kcount && r < r_hi) v = A[(int64_t)(kb + k) + (int64_t)r * ld];
@@ -270,44 +276,119 @@ struct PanelStage {
     }
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin by linear index; this
+// maps dispatch index L to a work index so that each XCD receives one
+// contiguous run of work items (neighbouring tiles, which gather the same
+// operand rows, then share that XCD's L2).  A bijection on [0, total).
+__device__ __forceinline__ int xcd_remap(int L, int total) {
+    constexpr int kXcd = 8;
+    const int q = total / kXcd, rem = total % kXcd;
+    const int x = L % kXcd, slot = L / kXcd;
+    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + slot;
+}
+
 // ---------------------------------------------------------------------------
 // phase 1: partial projections
 // ---------------------------------------------------------------------------
+// Stage of the projections: 128 rows of V_J^T (A[r][k] = V[k + r ld], r < rows)
+// and KC rows of X.
 template <class T, int TN>
-__global__ void __launch_bounds__(256) k_proj_mm(const ProjGroup *groups, const P1Work *work, const T *vals,
-                                                  const T *X, int64_t ldr, int R, T *part) {
-    const P1Work wk = work[blockIdx.x];
+struct P1Stage {
+    static constexpr int RA = 128;
+    T a[KC * RA / 256];
+    T b[KC * TN / 256];
+    __device__ __forceinline__ void fetch(const T *V, int64_t ld, int rows, int kb, int kcount, const T *X,
+                                          int64_t xrow, int64_t ldr, int r0, int R, int t) {
+#pragma unroll
+        for (int q = 0; q < KC * RA / 256; ++q) {
+            const int e = t + q * 256, r = e / KC, k = e - r * KC;
+            a[q] = (k < kcount && r < rows) ? V[(int64_t)(kb + k) + (int64_t)r * ld] : (T)0;
+        }
+#pragma unroll
+        for (int q = 0; q < KC * TN / 1024; ++q) {
+            const int e = t + q * 256, k = e / (TN / 4), c = (e - k * (TN / 4)) * 4;
+            T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+            if (k < kcount) {
+                const T *p = X + (xrow + k) * ldr + r0 + c;
+                if (r0 + c + 3 < R) {
+                    if constexpr (sizeof(T) == 4) {
+                        float4 qv = *(const float4 *)p;
+                        v0 = qv.x; v1 = qv.y; v2 = qv.z; v3 = qv.w;
+                    } else {
+                        double2 q0 = *(const double2 *)p, q1 = *(const double2 *)(p + 2);
+                        v0 = q0.x; v1 = q0.y; v2 = q1.x; v3 = q1.y;
+                    }
+                } else {
+                    if (r0 + c < R) v0 = p[0];
+                    if (r0 + c + 1 < R) v1 = p[1];
+                    if (r0 + c + 2 < R) v2 = p[2];
+                }
+            }
+            b[4 * q] = v0;
+            b[4 * q + 1] = v1;
+            b[4 * q + 2] = v2;
+            b[4 * q + 3] = v3;
+        }
+    }
+    __device__ __forceinline__ void commit(T (*sA)[RA + PADA], T (*sB)[TN + PADB], int t) {
+#pragma unroll
+        for (int q = 0; q < KC * RA / 256; ++q) {
+            const int e = t + q * 256, r = e / KC, k = e - r * KC;
+            sA[k][r] = a[q];
+        }
+#pragma unroll
+        for (int q = 0; q < KC * TN / 1024; ++q) {
+            const int e = t + q * 256, k = e / (TN / 4), c = (e - k * (TN / 4)) * 4;
+            sB[k][c] = b[4 * q];
+            sB[k][c + 1] = b[4 * q + 1];
+            sB[k][c + 2] = b[4 * q + 2];
+            sB[k][c + 3] = b[4 * q + 3];
+        }
+    }
+};
+
+// Partial projections of up to two work items that share a facet chunk
+// (consecutive 64-row slabs of V_J^T): the X chunk is staged once for 128 rows.
+template <class T, int TN>
+__global__ void __launch_bounds__(256) k_proj_mm(const ProjGroup *groups, const P1Work *work, const int32_t *pairs,
+                                                  const T *vals, const T *X, int64_t ldr, int R, T *part,
+                                                  int rtiles) {
+    const int wi = xcd_remap(blockIdx.x, gridDim.x);
+    const int p0 = pairs[2 * (wi / rtiles)], p1 = pairs[2 * (wi / rtiles) + 1];
+    const P1Work wk = work[p0];
     const ProjGroup g = groups[wk.group];
-    const int r0 = blockIdx.y * TN;
+    const int r0 = (wi % rtiles) * TN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    __shared__ T sA[2][KC][TM + PADA];
+    __shared__ T sA[2][KC][128 + PADA];
     __shared__ T sB[2][KC][TN + PADB];
-    Tile<T, TN> tile;
+    Tile<T, TN, 8> tile;
     tile.zero();
-    const int rows = min(TM, g.ktot - wk.krow0);
+    const int rows = min(p1 >= 0 ? 128 : TM, g.ktot - wk.krow0);
     const T *V = vals + g.v_off + (int64_t)wk.krow0 * g.ld;
-    Stage<T, TN> st;
+    P1Stage<T, TN> st;
     int buf = 0;
-    st.fetch(1, V, g.ld, 0, 0, rows, wk.jb, min(KC, wk.je - wk.jb), X, (int64_t)g.j0 + wk.jb, ldr, r0, R, t);
+    st.fetch(V, g.ld, rows, wk.jb, min(KC, wk.je - wk.jb), X, (int64_t)g.j0 + wk.jb, ldr, r0, R, t);
     for (int kb = wk.jb; kb < wk.je; kb += KC) {
-        st.commit(1, sA[buf], sB[buf], t);
+        st.commit(sA[buf], sB[buf], t);
         __syncthreads();
         const int nk = kb + KC;
-        if (nk < wk.je) st.fetch(1, V, g.ld, 0, 0, rows, nk, min(KC, wk.je - nk), X, (int64_t)g.j0 + nk, ldr, r0, R, t);
+        if (nk < wk.je) st.fetch(V, g.ld, rows, nk, min(KC, wk.je - nk), X, (int64_t)g.j0 + nk, ldr, r0, R, t);
         tile.mma(sA[buf], sB[buf], lane, w);
         buf ^= 1;
     }
-    T *out = part + (int64_t)wk.part * TM * ldr;
+    T *out0 = part + (int64_t)wk.part * TM * ldr;
+    T *out1 = p1 >= 0 ? part + (int64_t)work[p1].part * TM * ldr : nullptr;
     const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int j = 0; j < TN / 64; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int row = i * 16 + Mfma<T>::row(lk, v);
-                int col = r0 + w * (TN / 4) + j * 16 + lr;
-                if (col < R) out[(int64_t)row * ldr + col] = tile.acc[i][j][v];
+                const int row = i * 16 + Mfma<T>::row(lk, v);
+                const int col = r0 + w * (TN / 4) + j * 16 + lr;
+                T *out = row < TM ? out0 : out1;
+                if (out && col < R) out[(int64_t)(row & (TM - 1)) * ldr + col] = tile.acc[i][j][v];
             }
 }
 
@@ -376,19 +457,27 @@ __device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileI
             __syncthreads();
         }
     }
-    // packed panel: software-pipelined chunks
+    // packed panel: software pipeline with two register stages in flight
+    // (chunk c + 2 loads while chunk c runs on the matrix cores)
     if (ti.kpad > 0) {
         const T *pan = vals + ti.panel_off;
         const int32_t *br = brow + ti.brow_off;
-        PanelStage<T, TN> st;
-        st.fetch(pan, br, X, Tb, ldr, r0, R, t);
-        int buf = 0;
-        for (int kb = 0; kb < ti.kpad; kb += KC) {
-            st.commit(sA[buf], sB[buf], t);
+        PanelStage<T, TN> st0, st1;
+        auto fetch = [&](PanelStage<T, TN> &st, int kb) {
+            st.fetch(pan + (int64_t)kb * TM, br + kb, X, Tb, ldr, r0, R, t);
+        };
+        fetch(st0, 0);
+        if (KC < ti.kpad) fetch(st1, KC);
+        for (int kb = 0; kb < ti.kpad; kb += 2 * KC) {
+            st0.commit(sA[0], sB[0], t);
             __syncthreads();
-            if (kb + KC < ti.kpad) st.fetch(pan + (int64_t)(kb + KC) * TM, br + kb + KC, X, Tb, ldr, r0, R, t);
-            acc.mma(sA[buf], sB[buf], lane, w);
-            buf ^= 1;
+            if (kb + 2 * KC < ti.kpad) fetch(st0, kb + 2 * KC);
+            acc.mma(sA[0], sB[0], lane, w);
+            if (kb + KC >= ti.kpad) break;
+            st1.commit(sA[1], sB[1], t);
+            __syncthreads();
+            if (kb + 3 * KC < ti.kpad) fetch(st1, kb + 3 * KC);
+            acc.mma(sA[1], sB[1], lane, w);
         }
     }
     // epilogue through LDS: the result tile is written to LDS, then every
@@ -410,16 +499,17 @@ __device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileI
     tile_epilogue<T, kFused, TM, TN, TN + PADB>(sC, smem, tile, tile0, r0, ldr, R, N, Y, E, X, rho, rho_s, partial);
 }
 
-// one workgroup per (64-row tile, TN-column tile)
+// one workgroup per (64-row tile, TN-column tile); 1-D grid, XCD-aware order
 template <class T, bool kFused, int TN>
 __global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
                                                   const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
                                                   int64_t csr_val_start, const T *X, const T *Tb, int64_t ldr, int R,
                                                   int64_t N, T *Y, const T *E, const T *rho, T rho_s,
-                                                  double *partial) {
+                                                  double *partial, int rtiles) {
     __shared__ T smem[TileSmem<T, TN>::kSize];
-    tile_body<T, kFused, TN>(smem, blockIdx.x, blockIdx.y, tiles, brow, ctasks, vals, csr_ptr, csr_idx, csr_val_start,
-                             X, Tb, ldr, R, N, Y, E, rho, rho_s, partial);
+    const int wi = xcd_remap(blockIdx.x, gridDim.x);
+    tile_body<T, kFused, TN>(smem, wi / rtiles, wi % rtiles, tiles, brow, ctasks, vals, csr_ptr, csr_idx,
+                             csr_val_start, X, Tb, ldr, R, N, Y, E, rho, rho_s, partial);
 }
 
 // Persistent form: a fixed grid pulls work items (tiles in decreasing cost
@@ -558,8 +648,9 @@ template <class T, int TN>
 void proj_mm_tn(const rad_hmat *H, const T *X, int64_t ldr, int R, hipStream_t s) {
     unsigned rtiles = (unsigned)((R + TN - 1) / TN);
     if (H->n_p1work > 0) {
-        hipLaunchKernelGGL((k_proj_mm<T, TN>), dim3(H->n_p1work, rtiles), dim3(256), 0, s, H->d_groups.p,
-                           H->d_p1work.p, (const T *)H->d_vals.p, X, ldr, R, (T *)H->w_part.p);
+        hipLaunchKernelGGL((k_proj_mm<T, TN>), dim3(H->n_p1pairs * rtiles), dim3(256), 0, s, H->d_groups.p,
+                           H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const T *)H->d_vals.p, X, ldr, R,
+                           (T *)H->w_part.p, (int)rtiles);
         RAD_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_proj_reduce<T>, dim3(H->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s, H->d_p1red.p,
                            (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p);
@@ -579,9 +670,10 @@ void tile_mm_launch(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int6
                            H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial,
                            (const int32_t *)H->d_tile_order.p, nwork, rtiles, H->d_queue.p);
     } else {
-        hipLaunchKernelGGL((k_tile_mm<T, kFused, TN>), dim3(H->n_tiles, rtiles), dim3(256), 0, s, H->d_tiles.p,
-                           H->d_brow.p, H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
-                           H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial);
+        hipLaunchKernelGGL((k_tile_mm<T, kFused, TN>), dim3((unsigned)(H->n_tiles * rtiles)), dim3(256), 0, s,
+                           H->d_tiles.p, H->d_brow.p, H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p,
+                           H->d_csr_idx.p, H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s,
+                           partial, rtiles);
     }
     RAD_HIP(hipGetLastError());
 }
@@ -688,11 +780,13 @@ void time_phases_t(const rad_hmat *H, int R, int nrep, hipStream_t s, double *ms
         const unsigned rtiles = (unsigned)((R + c.tn - 1) / c.tn);
         ms[0] = timed([&] {
             if (c.tn == 64)
-                hipLaunchKernelGGL((k_proj_mm<T, 64>), dim3(H->n_p1work, rtiles), dim3(256), 0, s, H->d_groups.p,
-                                   H->d_p1work.p, (const T *)H->d_vals.p, X, ldr, R, (T *)H->w_part.p);
+                hipLaunchKernelGGL((k_proj_mm<T, 64>), dim3(H->n_p1pairs * rtiles), dim3(256), 0, s, H->d_groups.p,
+                                   H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const T *)H->d_vals.p, X, ldr,
+                                   R, (T *)H->w_part.p, (int)rtiles);
             else
-                hipLaunchKernelGGL((k_proj_mm<T, 128>), dim3(H->n_p1work, rtiles), dim3(256), 0, s, H->d_groups.p,
-                                   H->d_p1work.p, (const T *)H->d_vals.p, X, ldr, R, (T *)H->w_part.p);
+                hipLaunchKernelGGL((k_proj_mm<T, 128>), dim3(H->n_p1pairs * rtiles), dim3(256), 0, s, H->d_groups.p,
+                                   H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const T *)H->d_vals.p, X, ldr,
+                                   R, (T *)H->w_part.p, (int)rtiles);
         });
         ms[1] = timed([&] {
             hipLaunchKernelGGL(k_proj_reduce<T>, dim3(H->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s,
@@ -774,6 +868,19 @@ void mm_prepare_schedule(rad_hmat *H) {
     H->d_tile_order.upload(order);
     std::vector<int32_t> zero(2, 0);
     H->d_queue.upload(zero);
+    // phase-1 pairs: consecutive work items of one group and facet chunk whose
+    // V slabs follow each other (the list is ordered by group, chunk, slab)
+    std::vector<P1Work> wl = H->d_p1work.download((size_t)H->n_p1work);
+    std::vector<int32_t> pairs;
+    for (int32_t i = 0; i < H->n_p1work;) {
+        const bool pair = i + 1 < H->n_p1work && wl[i + 1].group == wl[i].group && wl[i + 1].jb == wl[i].jb &&
+                          wl[i + 1].krow0 == wl[i].krow0 + TM;
+        pairs.push_back(i);
+        pairs.push_back(pair ? i + 1 : -1);
+        i += pair ? 2 : 1;
+    }
+    H->n_p1pairs = (int32_t)(pairs.size() / 2);
+    H->d_p1pairs.upload(pairs);
     int ncu = 0;
     RAD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, H->device));
     H->n_cu = std::max(1, ncu);

@@ -9,6 +9,53 @@
 
 namespace rad {
 
+// E and B_old values of one group of four rows of this thread's epilogue
+// share (rows rsub + RS (4 g + q), columns col .. col + 3)
+template <class T, int TM, int TN>
+struct EpiRegs {
+    static constexpr int CT = TN / 4, RS = 256 / CT;
+    T ev[4][4], bo[4][4];
+    __device__ __forceinline__ void load(int grp, int64_t tile0, int r0, int64_t ldr, int R, int64_t N, const T *E,
+                                         const T *X) {
+        const int t = threadIdx.x;
+        const int rows = (int)min((int64_t)TM, N - tile0);
+        const int rsub = t / CT, col = r0 + (t % CT) * 4;
+        const bool full = col + 3 < R;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int row = rsub + RS * (4 * grp + qq);
+            const int64_t e = (tile0 + row) * ldr + col;
+            // values first, then unconditional register writes (keeps the
+            // arrays in registers)
+            T a[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+            if (row < rows && full) {
+                if constexpr (sizeof(T) == 4) {
+                    float4 av = *(const float4 *)(E + e), ov = *(const float4 *)(X + e);
+                    a[0] = av.x; a[1] = av.y; a[2] = av.z; a[3] = av.w;
+                    o[0] = ov.x; o[1] = ov.y; o[2] = ov.z; o[3] = ov.w;
+                } else {
+                    double2 a0 = *(const double2 *)(E + e), a1 = *(const double2 *)(E + e + 2);
+                    double2 o0 = *(const double2 *)(X + e), o1 = *(const double2 *)(X + e + 2);
+                    a[0] = a0.x; a[1] = a0.y; a[2] = a1.x; a[3] = a1.y;
+                    o[0] = o0.x; o[1] = o0.y; o[2] = o1.x; o[3] = o1.y;
+                }
+            } else if (row < rows) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (col + u < R) {
+                        a[u] = E[e + u];
+                        o[u] = X[e + u];
+                    }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ev[qq][u] = a[u];
+                bo[qq][u] = o[u];
+            }
+        }
+    }
+};
+
 template <class T, bool kFused, int TM, int TN, int LDC>
 __device__ __forceinline__ void tile_epilogue(const T (*sC)[LDC], void *smem, int tile, int64_t tile0, int r0,
                                               int64_t ldr, int R, int64_t N, T *Y, const T *E, const T *X,
@@ -28,33 +75,8 @@ __device__ __forceinline__ void tile_epilogue(const T (*sC)[LDC], void *smem, in
     // the arithmetic and the stores
 #pragma unroll
     for (int half = 0; half < NQ / 4; ++half) {
-        T ev[4][4], bo[4][4];
-        if constexpr (kFused) {
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                const int row = rsub + RS * (4 * half + qq);
-                const int64_t e = (tile0 + row) * ldr + col;
-                if (row < rows && full) {
-                    if constexpr (sizeof(T) == 4) {
-                        float4 a = *(const float4 *)(E + e), o = *(const float4 *)(X + e);
-                        ev[qq][0] = a.x; ev[qq][1] = a.y; ev[qq][2] = a.z; ev[qq][3] = a.w;
-                        bo[qq][0] = o.x; bo[qq][1] = o.y; bo[qq][2] = o.z; bo[qq][3] = o.w;
-                    } else {
-                        double2 a0 = *(const double2 *)(E + e), a1 = *(const double2 *)(E + e + 2);
-                        double2 o0 = *(const double2 *)(X + e), o1 = *(const double2 *)(X + e + 2);
-                        ev[qq][0] = a0.x; ev[qq][1] = a0.y; ev[qq][2] = a1.x; ev[qq][3] = a1.y;
-                        bo[qq][0] = o0.x; bo[qq][1] = o0.y; bo[qq][2] = o1.x; bo[qq][3] = o1.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        bool ok = row < rows && col + u < R;
-                        ev[qq][u] = ok ? E[e + u] : (T)0;
-                        bo[qq][u] = ok ? X[e + u] : (T)0;
-                    }
-                }
-            }
-        }
+        EpiRegs<T, TM, TN> cur;
+        if constexpr (kFused) cur.load(half, tile0, r0, ldr, R, N, E, X);
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
             const int row = rsub + RS * (4 * half + qq);
@@ -65,8 +87,8 @@ __device__ __forceinline__ void tile_epilogue(const T (*sC)[LDC], void *smem, in
                     T rh = rho ? rho[tile0 + row] : rho_s;
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        T bn = ev[qq][u] + rh * y[u];
-                        double d = (double)bn - (double)bo[qq][u];
+                        T bn = cur.ev[qq][u] + rh * y[u];
+                        double d = (double)bn - (double)cur.bo[qq][u];
                         if (col + u < R) d2[u] += d * d;
                         y[u] = bn;
                     }

@@ -148,7 +148,7 @@ struct TileTask {
     int64_t aux_off;
     int32_t row_off;
     int32_t r_lo, r_hi;
-    int32_t pad_;
+    int32_t full;          // 1: every row in [r_lo, r_hi) holds all ncol columns (values row-major, ld ncol)
 };
 
 // Phase-1 group: all low-rank blocks sharing column node J.
@@ -250,6 +250,8 @@ struct rad_hmat {
     // decreasing cost and the work counter of the persistent kernels
     std::vector<std::pair<int64_t, rad::MmConfig>> tuned;
     rad::DevBuf<int32_t> d_tile_order, d_queue;
+    rad::DevBuf<int32_t> d_p1pairs;  // phase-1 work items taken two at a time (second -1 if single)
+    int32_t n_p1pairs = 0;
     int32_t n_cu = 256;
     std::string sched_sig;           // dtype, tile count and tile-cost histogram hash (autotuner cache key)
     std::vector<int64_t> inst_off, inst_n;

@@ -79,6 +79,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_2209_07632_amd.build_lib.build()")
+    # torch's HIP runtime must be loaded before librad's dependency on it is
+    # resolved, or torch later finds no device
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     L.rad_build_opts_default.argtypes = [ctypes.POINTER(BuildOpts)]
