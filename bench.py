@@ -475,6 +475,24 @@ def main():
         "projections_tflops": p1_tf,
         "autotune": tune,
     }
+    # the plain form the batched solve replaces: FP64 operator, one sun at a
+    # time (single-RHS products), same tolerance and stopping rule
+    del X, Y
+    H64 = HMatrix(verts, faces, tol=args.tol, storage="f64", nearfield=args.nearfield, max_rhs=1)
+    cols64 = [E[:, c].double().contiguous() for c in range(16)]
+    Bt = torch.zeros(N, dtype=torch.float64, device=dev)
+    for e in cols64[:2]:
+        H64.solve(e, rho=albedo, rtol=args.rtol, out=Bt, order="tree")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in cols64:
+        H64.solve(e, rho=albedo, rtol=args.rtol, out=Bt, order="tree")
+    torch.cuda.synchronize()
+    single64 = len(cols64) / (time.perf_counter() - t0)
+    del H64
+    log(f"plain FP64 single-RHS solves: {single64:.1f} solves/s ({len(cols64)} suns one at a time)")
+    result["fp64_single_rhs_solves_per_s"] = single64
+    result["speedup_vs_fp64_single_rhs"] = solves_per_s / single64
     if not args.no_cpu_baseline:
         cols = list(range(args.cpu_cols))
         Bt = B.double().cpu().numpy()[:, :R]

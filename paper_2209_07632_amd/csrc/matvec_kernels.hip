@@ -8,6 +8,8 @@
 //            Y_L = sum_dense A_LJ X_J + sum_csr A_LJ X_J + sum_lowrank U'_L T_b.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "rad_internal.h"
 
 namespace rad {
@@ -55,38 +57,65 @@ __global__ void __launch_bounds__(256) k_proj(const ProjGroup *groups, const T *
     }
 }
 
-// phase 2: one workgroup per (64-row tile, right-hand side).  Lane = row of
-// the tile; wave w takes panel columns w, w+4, ... (each a contiguous 64-row
-// column of the packed panel) and CSR tasks w, w+4, ...; the four partial
-// results meet in LDS.
+// phase 2: one workgroup per (64-row tile, right-hand side).  The packed panel
+// (64 x K, column-major) is streamed with 16-byte loads: a wave reads VW
+// consecutive columns per step, lane l holding rows VW (l % (64/VW)) .. + VW-1
+// of column VW g + l / (64/VW); wave w takes column groups w, w+4, ... and
+// keeps four groups in flight.  CSR tasks are split over the waves by task.
+// Partial row sums meet in LDS in a fixed order.
 template <class T>
 __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
                                                     const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
                                                     int64_t csr_val_start, const T *X, int64_t ldx, const T *Tb,
                                                     int32_t t_ld, int64_t N, T *Y, int64_t ldy) {
+    constexpr int VW = 16 / sizeof(T);      // values per 16-byte load
+    constexpr int LPC = 64 / VW;            // lanes per panel column
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type vec_t;
     const int tile = blockIdx.x;
     const TileInfo ti = tiles[tile];
     const int64_t r = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int sub = lane / LPC, r0 = VW * (lane % LPC);
     const T *x = X + r * ldx;
     const T *tb = Tb + r * t_ld;
-    const T *panel = vals + ti.panel_off + lane;
+    const T *panel = vals + ti.panel_off + r0;
     const int32_t *br = brow + ti.brow_off;
-    T acc = 0;
-    int k = w;
-    for (; k + 12 < ti.kpad; k += 16) {
-        T a0 = panel[(int64_t)k * 64], a1 = panel[(int64_t)(k + 4) * 64];
-        T a2 = panel[(int64_t)(k + 8) * 64], a3 = panel[(int64_t)(k + 12) * 64];
-        int32_t b0 = br[k], b1 = br[k + 4], b2 = br[k + 8], b3 = br[k + 12];
-        acc += a0 * (b0 >= 0 ? x[b0] : tb[-1 - b0]);
-        acc += a1 * (b1 >= 0 ? x[b1] : tb[-1 - b1]);
-        acc += a2 * (b2 >= 0 ? x[b2] : tb[-1 - b2]);
-        acc += a3 * (b3 >= 0 ? x[b3] : tb[-1 - b3]);
+    T acc[VW];
+#pragma unroll
+    for (int u = 0; u < VW; ++u) acc[u] = 0;
+    auto operand = [&](int k) -> T {
+        const int32_t b = br[k];
+        return b >= 0 ? x[b] : tb[-1 - b];
+    };
+    auto fma_col = [&](const vec_t &a, T xv) {
+        const T *av = (const T *)&a;
+#pragma unroll
+        for (int u = 0; u < VW; ++u) acc[u] += av[u] * xv;
+    };
+    const int ngroups = ti.kpad / VW;       // kpad is a multiple of 32
+    int g = w;
+    for (; g + 12 < ngroups; g += 16) {
+        const int k0 = VW * g + sub, k1 = k0 + 4 * VW, k2 = k0 + 8 * VW, k3 = k0 + 12 * VW;
+        const vec_t a0 = *(const vec_t *)(panel + (int64_t)k0 * 64);
+        const vec_t a1 = *(const vec_t *)(panel + (int64_t)k1 * 64);
+        const vec_t a2 = *(const vec_t *)(panel + (int64_t)k2 * 64);
+        const vec_t a3 = *(const vec_t *)(panel + (int64_t)k3 * 64);
+        const T x0 = operand(k0), x1 = operand(k1), x2 = operand(k2), x3 = operand(k3);
+        fma_col(a0, x0);
+        fma_col(a1, x1);
+        fma_col(a2, x2);
+        fma_col(a3, x3);
     }
-    for (; k < ti.kpad; k += 4) {
-        int32_t b0 = br[k];
-        acc += panel[(int64_t)k * 64] * (b0 >= 0 ? x[b0] : tb[-1 - b0]);
+    for (; g < ngroups; g += 4) {
+        const int k0 = VW * g + sub;
+        const vec_t a0 = *(const vec_t *)(panel + (int64_t)k0 * 64);
+        fma_col(a0, operand(k0));
     }
+    __shared__ T red[4][VW][64];
+#pragma unroll
+    for (int u = 0; u < VW; ++u) red[w][sub][r0 + u] = acc[u];
+    // CSR tasks: lane = row, wave w takes tasks w, w+4, ...
+    T cacc = 0;
     for (int c = ti.csr_begin + w; c < ti.csr_end; c += 4) {
         const TileTask tk = ctasks[c];
         if (lane >= tk.r_lo && lane < tk.r_hi) {
@@ -94,14 +123,21 @@ __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const 
             const T *v = vals + tk.a_off;
             const int32_t *ci = csr_idx + (tk.a_off - csr_val_start);
             const T *xc = x + tk.col0;
-            for (int e = ptr[0]; e < ptr[1]; ++e) acc += v[e] * xc[ci[e]];
+            for (int e = ptr[0]; e < ptr[1]; ++e) cacc += v[e] * xc[ci[e]];
         }
     }
-    __shared__ T red[4][64];
-    red[w][lane] = acc;
+    __shared__ T cred[4][64];
+    cred[w][lane] = cacc;
     __syncthreads();
     const int64_t row = (int64_t)tile * 64 + lane;
-    if (w == 0 && row < N) Y[row + r * ldy] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    if (w == 0 && row < N) {
+        T s = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int u = 0; u < VW; ++u) s += red[q][u][lane];
+        Y[row + r * ldy] = s + ((cred[0][lane] + cred[1][lane]) + (cred[2][lane] + cred[3][lane]));
+    }
 }
 
 // B_new = E + rho * FB; partial[col][block] = sum (B_new - B_old)^2
