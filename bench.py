@@ -114,6 +114,8 @@ def run_dem(args):
             tot_inner += info["inner_iters"]
         return tot_outer, tot_inner
 
+    tune = H.autotune(Rb, nrep=3)
+    log(f"autotuned FP32 launch configuration for R={Rb}: {tune}")
     results = {}
     for name, refine in (("refined_16bit", True), ("fp32_jacobi", False)):
         E, B, R = batches[0]
@@ -225,7 +227,8 @@ def run_batch(args):
     for k, n in enumerate(sizes):
         v, f = dem_mesh(dem_instance(k, int(n)))
         tb = time.perf_counter()
-        H = HMatrix(v, f, tol=args.tol, storage="f32", visibility="raycast", max_rhs=R, max_rank=256)
+        H = HMatrix(v, f, tol=args.tol, storage="f32", visibility="raycast", nearfield=args.nearfield,
+                    max_rhs=R, max_rank=256)
         suns = sun_directions(R, (5.0, 30.0), seed=1000 + k)
         Es.append(albedo * H.insolation(suns, order="tree_rmajor"))
         parts.append(H)
@@ -291,7 +294,8 @@ def run_batch(args):
         "data": "synthetic",
         "config": {"workload": f"{len(parts)} uneven terrains (fBm H=0.8 RMS 30 m + 1.5 km bowl, seeds 0-"
                                f"{len(parts) - 1}), {int(G.sizes.min())}-{int(G.sizes.max())} facets, {R} suns each, "
-                               f"one grouped operator, tol {args.tol}, Jacobi rtol {args.rtol}",
+                               f"one grouped operator, tol {args.tol}, near field {args.nearfield}, "
+                               f"Jacobi rtol {args.rtol}",
                    "instances": len(parts), "facets": int(G.sizes.sum()), "rhs_per_instance": R, "tol": args.tol},
         "iterations": info["total_iters"], "build_seconds": build_s, "hmat_bytes": st["bytes_total"],
         "separate_solves_per_s": nrhs / dt_sep, "autotune": tune,
@@ -345,6 +349,8 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it"}))
         sys.exit(2)
     if args.workload == "batch64":
+        if args.nearfield == "csr":
+            args.nearfield = "dense"   # terrain near field: dense panels run far faster than CSR slices
         return run_batch(args)
     if args.workload == "dem131k":
         if args.rtol == 1e-3:

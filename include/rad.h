@@ -257,7 +257,8 @@ rad_status rad_hmat_group(const rad_hmat *const *parts, int32_t count, int32_t m
 
 /*
  * Autotuner of the multi-RHS kernels for R right-hand sides (R >= 16).  The
- * candidates are 64- or 128-column workgroup tiles, each as a flat grid (one
+ * candidates are 64-, 128- or (FP32, R > 128) 256-column workgroup tiles of the
+ * expansion, each as a flat grid (one
  * workgroup per 64-row tile and column tile) or as a persistent grid of 1, 2
  * or 4 workgroups per compute unit pulling tiles, in decreasing order of
  * their reduction length, from a work counter.  Each candidate runs nrep
@@ -274,7 +275,7 @@ rad_status rad_hmat_group(const rad_hmat *const *parts, int32_t count, int32_t m
 rad_status rad_hmat_autotune(rad_hmat *H, int64_t R, int32_t nrep, const char *cache_path, int32_t *config,
                              double *ms, void *hip_stream);
 
-/* Forces the configuration (tn 64|128, persistent 0|1, blocks_per_cu 1..64)
+/* Forces the configuration (tn 64|128|256 (FP32), persistent 0|1, blocks_per_cu 1..64)
  * for R right-hand sides, or reads the one in use (default: tn 64 for
  * R <= 64 else 128, flat grid). */
 rad_status rad_hmat_set_config(rad_hmat *H, int64_t R, const int32_t *config);

@@ -34,6 +34,11 @@ void alloc_workspace(rad_hmat *H) {
     H->w_q1.alloc(nr * s);
     H->w_q2.alloc(nr * s);
     if (H->lowp) H->w_b64.alloc(nr);
+    if (H->lowp == RAD_BF16 && H->max_rhs >= kMfmaMinRhs) {
+        const size_t ld16 = (size_t)((H->max_rhs + 7) & ~7);
+        H->w_x16.alloc((size_t)H->N * ld16);
+        H->w_t16.alloc((size_t)std::max(H->t_ld, 4) * ld16);
+    }
     RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * nc, hipHostMallocDefault));
     RAD_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
     if (H->n_tiles > 0) mm_prepare_schedule(H);

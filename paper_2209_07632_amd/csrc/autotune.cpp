@@ -28,7 +28,7 @@ std::map<std::string, CacheEntry> read_cache(const std::string &path) {
         double ms = 0;
         if (std::sscanf(line.c_str() + q1 + 1, ": {\"tn\": %d, \"persistent\": %d, \"blocks_per_cu\": %d, \"ms\": %lf",
                         &tn, &pe, &bpc, &ms) == 4 &&
-            (tn == 64 || tn == 128) && (pe == 0 || pe == 1) && bpc >= 0 && bpc <= 64) {
+            (tn == 64 || tn == 128 || tn == 256) && (pe == 0 || pe == 1) && bpc >= 0 && bpc <= 64) {
             e.c = MmConfig{tn, pe, bpc};
             e.ms = ms;
             out[line.substr(q0 + 1, q1 - q0 - 1)] = e;
@@ -127,7 +127,8 @@ rad_status rad_hmat_set_config(rad_hmat *H, int64_t R, const int32_t *config) {
     return guard([&] {
         RAD_REQUIRE(H != nullptr && config != nullptr, "null matrix handle or config");
         RAD_REQUIRE(R >= kMfmaMinRhs && R <= H->max_rhs, "R must be in [16, max_rhs]");
-        RAD_REQUIRE(config[0] == 64 || config[0] == 128, "tn must be 64 or 128");
+        RAD_REQUIRE(config[0] == 64 || config[0] == 128 || (config[0] == 256 && H->dtype == RAD_F32),
+                    "tn must be 64 or 128 (or 256 for FP32)");
         RAD_REQUIRE(config[1] == 0 || config[1] == 1, "persistent must be 0 or 1");
         RAD_REQUIRE(config[2] >= 1 && config[2] <= 64, "blocks_per_cu must be in [1, 64]");
         set_tuned(H, R, MmConfig{config[0], config[1], config[2]});

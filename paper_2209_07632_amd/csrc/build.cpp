@@ -364,8 +364,10 @@ struct Builder {
                 process_chunk(level, sb, chunk.size(), yfill, zfill, max_rows, max_ell,
                               [&](size_t c, bool resolved) {
                                   if (!resolved) {
+                                      // doubling, capped at the first width that
+                                      // decides every rank up to the limit
                                       State nx = chunk[c];
-                                      nx.k *= 2;
+                                      nx.k = std::min(2 * nx.k, nx.qlim + 1);
                                       next.push_back(nx);
                                   }
                               },

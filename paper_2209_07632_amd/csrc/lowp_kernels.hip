@@ -1,12 +1,15 @@
 // 16-bit (FP16 or BF16) copy of the compressed operator for the inner solves
 // of iterative refinement: matrix-core products with FP32 accumulation.
 //
-// Scaling: every panel column k (a column of U' or of a dense block restricted
-// to one 64-row tile) is stored as A[:, k] * c_k with c_k a power of two that
-// brings max |A[:, k]| into [0.5, 1); the operand row it multiplies is staged
-// as B[k, :] / c_k, so the product is unchanged.  Every stacked V column kk is
-// stored as V[:, kk] * d_kk and the projection is divided by d_kk when the
-// split-K partials are summed.  Powers of two make the scaling exact.
+// Scaling (FP16): every panel column k (a column of U' or of a dense block
+// restricted to one 64-row tile) is stored as A[:, k] * c_k with c_k a power
+// of two that brings max |A[:, k]| into [0.5, 1); the operand row it
+// multiplies is staged as B[k, :] / c_k, so the product is unchanged.  Every
+// stacked V column kk is stored as V[:, kk] * d_kk and the projection is
+// divided by d_kk when the split-K partials are summed.  Powers of two make
+// the scaling exact.  BF16 has the FP32 exponent range and uses unit scales,
+// which lets its operand rows be converted once per product (X16, T16) and
+// staged without arithmetic by the wide expansion kernel below.
 //
 // 16-bit panels are stored per 32-column chunk as 64 rows x 32 values with the
 // reduction index contiguous (the operand layout of v_mfma_f32_16x16x32_*:
@@ -56,6 +59,11 @@ __device__ __forceinline__ float pow2_scale(float max_abs) {
     return ldexpf(1.0f, -e);
 }
 
+template <class H>
+constexpr bool kUnitScale = false;
+template <>
+constexpr bool kUnitScale<__bf16> = true;
+
 __device__ __forceinline__ float wave_max(float v) {
     for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
     return v;
@@ -70,7 +78,8 @@ __global__ void __launch_bounds__(256) k_lowp_panels(const float *vals, const Ti
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int k = w; k < ti.kpad; k += 4) {
         const float v = vals[ti.panel_off + (int64_t)k * TM + lane];
-        const float c = pow2_scale(wave_max(fabsf(v)));
+        // BF16 keeps the FP32 exponent range: unit scales (operands convert directly)
+        const float c = kUnitScale<H> ? 1.0f : pow2_scale(wave_max(fabsf(v)));
         out[ti.panel_off + (int64_t)(k / KC) * TM * KC + lane * KC + (k % KC)] = (H)(v * c);
         if (lane == 0) pscale[ti.panel_off / TM + k] = c;
     }
@@ -84,7 +93,7 @@ __global__ void __launch_bounds__(256) k_lowp_v(const float *vals, const ProjGro
         const float *v = vals + g.v_off + (int64_t)kk * g.ld;
         float m = 0.0f;
         for (int j = lane; j < g.n; j += 64) m = fmaxf(m, fabsf(v[j]));
-        const float d = pow2_scale(wave_max(m));
+        const float d = kUnitScale<H> ? 1.0f : pow2_scale(wave_max(m));
         H *o = out + g.v_off + (int64_t)kk * g.ld;
         for (int j = lane; j < g.ld; j += 64) o[j] = (H)(j < g.n ? v[j] * d : 0.0f);
         if (lane == 0) tscale[g.t_off + kk] = d;
@@ -226,14 +235,136 @@ __global__ void __launch_bounds__(256) k_proj_mm16(const ProjGroup *groups, cons
 
 // T rows = (sum of the split partials) / d_row
 __global__ void __launch_bounds__(256) k_proj_reduce16(const P1Red *red, const float *part, const float *tscale,
-                                                        int64_t ldr, int R, float *Tb) {
+                                                        int64_t ldr, int R, float *Tb, __bf16 *T16, int64_t ld16) {
     const P1Red rd = red[blockIdx.x / TM];
     const int row = blockIdx.x % TM;
     const int c = blockIdx.y * 256 + threadIdx.x;
     if (c >= R || row >= rd.nrows) return;
     float s = 0.0f;
     for (int p = 0; p < rd.part_count; ++p) s += part[((int64_t)(rd.part_begin + p) * TM + row) * ldr + c];
-    Tb[(int64_t)(rd.t_row0 + row) * ldr + c] = s / tscale[rd.t_row0 + row];
+    const float v = s / tscale[rd.t_row0 + row];
+    Tb[(int64_t)(rd.t_row0 + row) * ldr + c] = v;
+    if (T16) T16[(int64_t)(rd.t_row0 + row) * ld16 + c] = (__bf16)v;
+}
+
+// X16 = bf16(X) for the R columns, zero padding up to ld16
+__global__ void __launch_bounds__(256) k_to_bf16(const float *X, int64_t N, int64_t ldr, int R, __bf16 *X16,
+                                                  int64_t ld16) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= N * ld16) return;
+    const int64_t t = e / ld16;
+    const int c = (int)(e % ld16);
+    X16[e] = (__bf16)(c < R ? X[t * ldr + c] : 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// BF16 wide expansion: one workgroup per 64-row tile and all R <= 256
+// columns (wave w owns columns 64 w .. 64 w + 63), reduction chunks of 32
+// with two register stages in flight.  Operand rows come pre-converted
+// (X16, T16: facet-major, ld16 a multiple of 8); each thread loads four
+// operand rows x eight columns and writes them transposed into LDS as
+// 8-byte groups of four consecutive k, the operand layout of the matrix
+// cores.  No CSR tasks (matrices with CSR near field use k_tile_mm16).
+// ---------------------------------------------------------------------------
+constexpr int WN = 256, WKC = 32, WLDK = WKC + 8;
+
+struct WideStage {
+    bf16x8 a;          // panel: row t >> 2, k (t & 3) * 8 .. + 7
+    bf16x8 b[4];       // operand rows 4 (t >> 5) + i, columns 8 (t & 31) .. + 7
+    __device__ __forceinline__ void fetch(const __bf16 *pan, const int32_t *brc, const __bf16 *X16,
+                                          const __bf16 *T16, int64_t ld16, int t) {
+        a = *(const bf16x8 *)(pan + t * 8);
+        const int kq = t >> 5, c8 = (t & 31) * 8;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int32_t v = brc[4 * kq + i];
+            const __bf16 *p = (v >= 0 ? X16 + (int64_t)v * ld16 : T16 + (int64_t)(-1 - v) * ld16) + c8;
+            b[i] = c8 < ld16 ? *(const bf16x8 *)p : bf16x8{};
+        }
+    }
+    __device__ __forceinline__ void commit(__bf16 (*sA)[WLDK], __bf16 (*sB)[WLDK], int t) {
+        *(bf16x8 *)&sA[t >> 2][(t & 3) * 8] = a;
+        const int kq = t >> 5, c8 = (t & 31) * 8;
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            bf16x4 q = {b[0][j], b[1][j], b[2][j], b[3][j]};
+            *(bf16x4 *)&sB[c8 + j][4 * kq] = q;
+        }
+    }
+};
+
+template <bool kFused>
+__global__ void __launch_bounds__(256) k_tile_mm16w(const TileInfo *tiles, const int32_t *brow, const __bf16 *vals16,
+                                                     const __bf16 *X16, const __bf16 *T16, int64_t ld16,
+                                                     const float *X, int64_t ldr, int R, int64_t N, float *Y,
+                                                     const float *E, const float *rho, float rho_s,
+                                                     double *partial) {
+    const int tile = blockIdx.x;
+    const TileInfo ti = tiles[tile];
+    const int64_t tile0 = (int64_t)tile * TM;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    constexpr int kPipe = (2 * TM * WLDK + 2 * WN * WLDK) * 2;
+    constexpr int kOut = TM * (128 + 4) * 4;
+    __shared__ __align__(16) unsigned char smem[kPipe > kOut ? kPipe : kOut];
+    __bf16 (*sA)[TM][WLDK] = (__bf16 (*)[TM][WLDK])smem;
+    __bf16 (*sB)[WN][WLDK] = (__bf16 (*)[WN][WLDK])(smem + 2 * TM * WLDK * sizeof(__bf16));
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    const int lr = lane & 15, k0 = 8 * (lane >> 4);
+    auto mma = [&](const __bf16 (*A)[WLDK], const __bf16 (*B)[WLDK]) {
+        bf16x8 av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = *(const bf16x8 *)&A[i * 16 + lr][k0];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = *(const bf16x8 *)&B[w * 64 + j * 16 + lr][k0];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    };
+    if (ti.kpad > 0) {
+        const __bf16 *pan = vals16 + ti.panel_off;
+        const int32_t *br = brow + ti.brow_off;
+        WideStage s0, s1;
+        s0.fetch(pan, br, X16, T16, ld16, t);
+        if (WKC < ti.kpad) s1.fetch(pan + (int64_t)WKC * TM, br + WKC, X16, T16, ld16, t);
+        for (int kb = 0; kb < ti.kpad; kb += 2 * WKC) {
+            s0.commit(sA[0], sB[0], t);
+            __syncthreads();
+            if (kb + 2 * WKC < ti.kpad)
+                s0.fetch(pan + (int64_t)(kb + 2 * WKC) * TM, br + kb + 2 * WKC, X16, T16, ld16, t);
+            mma(sA[0], sB[0]);
+            if (kb + WKC >= ti.kpad) break;
+            s1.commit(sA[1], sB[1], t);
+            __syncthreads();
+            if (kb + 3 * WKC < ti.kpad)
+                s1.fetch(pan + (int64_t)(kb + 3 * WKC) * TM, br + kb + 3 * WKC, X16, T16, ld16, t);
+            mma(sA[1], sB[1]);
+        }
+    }
+    // epilogue in two halves of 128 columns (waves 2h, 2h + 1 hold half h)
+    float (*sC)[128 + 4] = (float (*)[128 + 4])smem;
+    const int lk = lane >> 4;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        __syncthreads();
+        if ((w >> 1) == h) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) sC[i * 16 + 4 * lk + v][(w & 1) * 64 + j * 16 + lr] = acc[i][j][v];
+        }
+        __syncthreads();
+        if (128 * h < R)
+            tile_epilogue<float, kFused, TM, 128, 128 + 4>(sC, smem, tile, tile0, 128 * h, ldr, R, N, Y, E, X, rho,
+                                                           rho_s, partial);
+    }
 }
 
 template <class H, bool kFused>
@@ -346,19 +477,53 @@ void convert_t(rad_hmat *H_, hipStream_t s) {
     RAD_HIP(hipGetLastError());
 }
 
+// the wide BF16 kernel serves matrices without CSR tasks and R <= 256
+bool wide_ok(const rad_hmat *Hm, int R) {
+    return Hm->lowp == RAD_BF16 && Hm->d_tile_tasks.n == 0 && R <= WN && Hm->w_x16.p != nullptr;
+}
+
+int64_t ld16_of(int64_t R) { return (R + 7) & ~(int64_t)7; }
+
+template <bool kFused>
+void launch_wide(const rad_hmat *Hm, const float *E, const float *rho, float rho_s, const float *Bold, float *Bnew,
+                 int64_t ldr, int R, double *part, hipStream_t s) {
+    const int64_t ld16 = ld16_of(R);
+    hipLaunchKernelGGL((k_tile_mm16w<kFused>), dim3(Hm->n_tiles), dim3(256), 0, s, Hm->d_tiles.p, Hm->d_brow.p,
+                       (const __bf16 *)Hm->d_vals16.p, (const __bf16 *)Hm->w_x16.p, (const __bf16 *)Hm->w_t16.p, ld16,
+                       Bold, ldr, R, Hm->N, Bnew, E, rho, rho_s, part);
+    RAD_HIP(hipGetLastError());
+}
+
 template <class H>
 void step16_t(const rad_hmat *Hm, const float *E, const float *rho, float rho_s, const float *Bold, float *Bnew,
               int64_t ldr, int R, double *norms, hipStream_t s) {
     unsigned rtiles = (unsigned)((R + TN - 1) / TN);
     const H *v16 = (const H *)Hm->d_vals16.p;
+    const bool wide = wide_ok(Hm, R);
+    const int64_t ld16 = ld16_of(R);
+    if (wide) {
+        const int64_t n = Hm->N * ld16;
+        hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Bold, Hm->N, ldr, R,
+                           (__bf16 *)Hm->w_x16.p, ld16);
+        RAD_HIP(hipGetLastError());
+    }
     if (Hm->n_p1work > 0) {
         hipLaunchKernelGGL(k_proj_mm16<H>, dim3(Hm->n_p1work, rtiles), dim3(256), 0, s, Hm->d_groups.p,
                            Hm->d_p1work.p, v16, Bold, ldr, R, (float *)Hm->w_part.p);
         hipLaunchKernelGGL(k_proj_reduce16, dim3(Hm->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s, Hm->d_p1red.p,
-                           (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)Hm->w_t.p);
+                           (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)Hm->w_t.p,
+                           wide ? (__bf16 *)Hm->w_t16.p : (__bf16 *)nullptr, ld16);
         RAD_HIP(hipGetLastError());
     }
     double *part = (double *)Hm->w_red.p;
+    if (wide) {
+        if (E)
+            launch_wide<true>(Hm, E, rho, rho_s, Bold, Bnew, ldr, R, part, s);
+        else
+            launch_wide<false>(Hm, E, rho, rho_s, Bold, Bnew, ldr, R, part, s);
+        if (E) mm_reduce_cols(Hm, part, Hm->n_tiles, R, norms, s);
+        return;
+    }
     if (E)
         hipLaunchKernelGGL((k_tile_mm16<H, true>), dim3(Hm->n_tiles, rtiles), dim3(256), 0, s, Hm->d_tiles.p,
                            Hm->d_brow.p, Hm->d_tile_tasks.p, v16, Hm->d_pscale.p, (const float *)Hm->d_vals.p,
@@ -434,8 +599,20 @@ void time16_t(const rad_hmat *Hm, int R, int nrep, hipStream_t s, double *ms) {
         });
         ms[1] = timed([&] {
             hipLaunchKernelGGL(k_proj_reduce16, dim3(Hm->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s,
-                               Hm->d_p1red.p, (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)Hm->w_t.p);
+                               Hm->d_p1red.p, (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)Hm->w_t.p,
+                               (__bf16 *)nullptr, (int64_t)0);
         });
+    }
+    if (wide_ok(Hm, R)) {
+        // operand rows need finite values: convert the (zeroed) workspace once
+        const int64_t ld16 = ld16_of(R), n = Hm->N * ld16;
+        hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, Hm->N, ldr, R,
+                           (__bf16 *)Hm->w_x16.p, ld16);
+        RAD_HIP(hipMemsetAsync(Hm->w_t16.p, 0, Hm->w_t16.bytes(), s));
+        ms[2] = timed([&] { launch_wide<true>(Hm, E, nullptr, 0.3f, X, Y, ldr, R, part, s); });
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return;
     }
     ms[2] = timed([&] {
         hipLaunchKernelGGL((k_tile_mm16<H, true>), dim3(Hm->n_tiles, rtiles), dim3(256), 0, s, Hm->d_tiles.p,

@@ -678,10 +678,11 @@ void tile_mm_launch(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int6
     RAD_HIP(hipGetLastError());
 }
 
+// projections with at most 128-column tiles (their accumulators hold 128 rows)
 template <class T, int TN>
 void apply_mm_tn(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int64_t ldr, int R, const T *E, const T *rho,
                  T rho_s, double *partial, hipStream_t s) {
-    proj_mm_tn<T, TN>(H, X, ldr, R, s);
+    proj_mm_tn<T, (TN > 128 ? 128 : TN)>(H, X, ldr, R, s);
     if (E)
         tile_mm_launch<T, true, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
     else
@@ -693,6 +694,8 @@ void apply_mm_cfg(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int64_
                   const T *rho, T rho_s, double *partial, hipStream_t s) {
     if (c.tn == 64)
         apply_mm_tn<T, 64>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
+    else if (c.tn == 256 && sizeof(T) == 4)
+        apply_mm_tn<T, (sizeof(T) == 4 ? 256 : 128)>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
     else
         apply_mm_tn<T, 128>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
 }
@@ -777,9 +780,10 @@ void time_phases_t(const rad_hmat *H, int R, int nrep, hipStream_t s, double *ms
     };
     ms[0] = ms[1] = ms[2] = 0.0;
     if (H->n_p1work > 0) {
-        const unsigned rtiles = (unsigned)((R + c.tn - 1) / c.tn);
+        const int tn1 = c.tn == 64 ? 64 : 128;
+        const unsigned rtiles = (unsigned)((R + tn1 - 1) / tn1);
         ms[0] = timed([&] {
-            if (c.tn == 64)
+            if (tn1 == 64)
                 hipLaunchKernelGGL((k_proj_mm<T, 64>), dim3(H->n_p1pairs * rtiles), dim3(256), 0, s, H->d_groups.p,
                                    H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const T *)H->d_vals.p, X, ldr,
                                    R, (T *)H->w_part.p, (int)rtiles);
@@ -796,6 +800,9 @@ void time_phases_t(const rad_hmat *H, int R, int nrep, hipStream_t s, double *ms
     ms[2] = timed([&] {
         if (c.tn == 64)
             tile_mm_launch<T, true, 64>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3, part, s);
+        else if (c.tn == 256 && sizeof(T) == 4)
+            tile_mm_launch<T, true, (sizeof(T) == 4 ? 256 : 128)>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3,
+                                                                 part, s);
         else
             tile_mm_launch<T, true, 128>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3, part, s);
     });
@@ -812,7 +819,8 @@ std::vector<std::pair<MmConfig, double>> autotune_t(rad_hmat *H, int R, int nrep
     const T *E = (const T *)H->w_e.p;
     double *part = (double *)H->w_red.p;
     std::vector<MmConfig> cands;
-    for (int tn : {64, 128}) {
+    for (int tn : {64, 128, 256}) {
+        if (tn == 256 && (sizeof(T) != 4 || R <= 128)) continue;
         cands.push_back(MmConfig{tn, 0, 0});
         for (int bpc : {1, 2, 4}) cands.push_back(MmConfig{tn, 1, bpc});
     }

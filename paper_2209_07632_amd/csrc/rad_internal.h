@@ -234,6 +234,7 @@ struct rad_hmat {
     // workspace (sized for max_rhs)
     rad::DevBuf<unsigned char> w_x, w_y, w_t, w_b, w_e, w_rho, w_red, w_part, w_q1, w_q2;
     rad::DevBuf<double> w_b64;            // FP64 accumulator of refined solves
+    rad::DevBuf<uint16_t> w_x16, w_t16;   // BF16 operand rows (X and T) of the wide 16-bit kernel
 
     // 16-bit copy of the operator (panels and stacked V, power-of-two scales)
     int32_t lowp = 0;

@@ -339,7 +339,7 @@ U16 = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
 
 
 @pytest.mark.parametrize("lowp", ["f16", "bf16"])
-@pytest.mark.parametrize("R", [16, 130])
+@pytest.mark.parametrize("R", [16, 130, 200, 256])
 def test_lowp_matvec(cap, lowp, R):
     """The 16-bit copy of F-hat (power-of-two column scaling, FP32 accumulation)
     stays within tol + 2u of the exact product: each term of a dot product
