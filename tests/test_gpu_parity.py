@@ -410,3 +410,35 @@ def test_refined_solve_ir_band_rho_vector(cap, lowp):
     Bo[perm] = Br.double().cpu().numpy()[:, :R]
     assert _rel(Bo, ref.solve_direct(F, rho, E)) <= 5e-6
     assert np.all(info["iters"] > 0)
+
+
+# ------------------------------------------------------------ the benchmark's own configuration
+def test_full_size_cap_sampled_columns():
+    """The 40k-facet cap with 1,024 suns, near field CSR, tol 1e-3, FP32, solved
+    in the autotuned launch configuration the benchmark times: two sampled
+    columns against the FP64 matrix-free reference (insolation and Jacobi),
+    and shadows bit for bit on those columns."""
+    from paper_2209_07632_amd import HMatrix
+    from paper_2209_07632_amd.rad import ldr_of
+    from synth import CAP_LARGE
+    verts, faces = cap_mesh(CAP_LARGE)
+    R = 1024
+    suns = sun_directions(R, (5.0, 30.0), seed=1)
+    print("[full] cap40k R=1024", flush=True)
+    H = HMatrix(verts, faces, tol=1e-3, storage="f32", nearfield="csr", max_rhs=R)
+    H.autotune(R, nrep=2)
+    Q = H.insolation(suns, flux=1365.0, order="tree_rmajor")
+    B, info = H.solve(0.3 * Q, rho=0.3, rtol=1e-3, order="tree_rmajor", R=R)
+    assert info["converged"]
+    perm = H.perm()
+    cols = [0, 777]
+    fac = ref.Facets(verts, faces)
+    Q0 = ref.insolation(fac, suns[cols], S=1365.0)
+    Qg = np.empty((fac.N, len(cols)))
+    Qg[perm] = Q.double().cpu().numpy()[:, cols]
+    np.testing.assert_array_equal(Qg == 0.0, Q0 == 0.0)
+    B0, _ = ref.jacobi(lambda X: ref.matvec_free(fac, X), 0.3, 0.3 * Q0, tol=1e-10)
+    Bg = np.empty((fac.N, len(cols)))
+    Bg[perm] = B.double().cpu().numpy()[:, cols]
+    for c in range(len(cols)):
+        assert _rel(Bg[:, c], B0[:, c]) < 1e-3
