@@ -783,6 +783,7 @@ struct Builder {
             TileInfo ti{};
             ti.panel_off = vfill;
             ti.kpad = (int32_t)kpad;
+            ti.k16 = (int32_t)((K + 15) / 16 * 16);
             ti.brow_off = (int64_t)brow.size();
             int64_t col = 0;
             for (const PT &pt : v) {

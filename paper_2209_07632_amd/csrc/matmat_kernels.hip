@@ -67,8 +67,10 @@ struct Tile {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
     }
-    // one chunk of KC from LDS: sA[k][row], sB[k][col]
-    __device__ __forceinline__ void mma(const T (*sA)[MI * 16 + PADA], const T (*sB)[TN + PADB], int lane, int w) {
+    // one chunk of KC from LDS: sA[k][row], sB[k][col]; row tiles from mi_on on
+    // hold only zero rows and are skipped (a uniform branch per wave)
+    __device__ __forceinline__ void mma(const T (*sA)[MI * 16 + PADA], const T (*sB)[TN + PADB], int lane, int w,
+                                        int mi_on = MI) {
         const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
@@ -80,8 +82,9 @@ struct Tile {
             for (int j = 0; j < NJ; ++j) b[j] = sB[k][w * (TN / 4) + j * 16 + lr];
 #pragma unroll
             for (int i = 0; i < MI; ++i)
+                if (i < mi_on)
 #pragma unroll
-                for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
+                    for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
         }
     }
 };
@@ -295,14 +298,29 @@ __device__ __forceinline__ int xcd_remap(int L, int total) {
 template <class T, int TN>
 struct P1Stage {
     static constexpr int RA = 128;
+    static constexpr int VW = 16 / sizeof(T);   // V values per 16-byte load
     T a[KC * RA / 256];
     T b[KC * TN / 256];
+    // A: each thread loads VW consecutive k of one V column with one 16-byte
+    // load (V columns start on 8-value boundaries, kb on KC boundaries)
     __device__ __forceinline__ void fetch(const T *V, int64_t ld, int rows, int kb, int kcount, const T *X,
                                           int64_t xrow, int64_t ldr, int r0, int R, int t) {
 #pragma unroll
-        for (int q = 0; q < KC * RA / 256; ++q) {
-            const int e = t + q * 256, r = e / KC, k = e - r * KC;
-            a[q] = (k < kcount && r < rows) ? V[(int64_t)(kb + k) + (int64_t)r * ld] : (T)0;
+        for (int q = 0; q < KC * RA / 256 / VW; ++q) {
+            const int e = t + q * 256, r = e / (KC / VW), k = (e % (KC / VW)) * VW;
+            const T *p = V + (int64_t)(kb + k) + (int64_t)r * ld;
+            if (r < rows && k + VW <= kcount) {
+                if constexpr (sizeof(T) == 4) {
+                    const float4 v = *(const float4 *)p;
+                    a[VW * q] = v.x; a[VW * q + 1] = v.y; a[VW * q + 2] = v.z; a[VW * q + 3] = v.w;
+                } else {
+                    const double2 v = *(const double2 *)p;
+                    a[VW * q] = v.x; a[VW * q + 1] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < VW; ++u) a[VW * q + u] = (r < rows && k + u < kcount) ? p[u] : (T)0;
+            }
         }
 #pragma unroll
         for (int q = 0; q < KC * TN / 1024; ++q) {
@@ -332,9 +350,10 @@ struct P1Stage {
     }
     __device__ __forceinline__ void commit(T (*sA)[RA + PADA], T (*sB)[TN + PADB], int t) {
 #pragma unroll
-        for (int q = 0; q < KC * RA / 256; ++q) {
-            const int e = t + q * 256, r = e / KC, k = e - r * KC;
-            sA[k][r] = a[q];
+        for (int q = 0; q < KC * RA / 256 / VW; ++q) {
+            const int e = t + q * 256, r = e / (KC / VW), k = (e % (KC / VW)) * VW;
+#pragma unroll
+            for (int u = 0; u < VW; ++u) sA[k + u][r] = a[VW * q + u];
         }
 #pragma unroll
         for (int q = 0; q < KC * TN / 1024; ++q) {
@@ -373,7 +392,7 @@ __global__ void __launch_bounds__(256) k_proj_mm(const ProjGroup *groups, const 
         __syncthreads();
         const int nk = kb + KC;
         if (nk < wk.je) st.fetch(V, g.ld, rows, nk, min(KC, wk.je - nk), X, (int64_t)g.j0 + nk, ldr, r0, R, t);
-        tile.mma(sA[buf], sB[buf], lane, w);
+        tile.mma(sA[buf], sB[buf], lane, w, (rows + 15) / 16);
         buf ^= 1;
     }
     T *out0 = part + (int64_t)wk.part * TM * ldr;
@@ -459,7 +478,9 @@ __device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileI
     }
     // packed panel: software pipeline with two register stages in flight
     // (chunk c + 2 loads while chunk c runs on the matrix cores)
-    if (ti.kpad > 0) {
+    // (columns past k16 are zero padding of the 16-bit chunk width: skipped)
+    const int kend = ti.k16;
+    if (kend > 0) {
         const T *pan = vals + ti.panel_off;
         const int32_t *br = brow + ti.brow_off;
         PanelStage<T, TN> st0, st1;
@@ -467,16 +488,16 @@ __device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileI
             st.fetch(pan + (int64_t)kb * TM, br + kb, X, Tb, ldr, r0, R, t);
         };
         fetch(st0, 0);
-        if (KC < ti.kpad) fetch(st1, KC);
-        for (int kb = 0; kb < ti.kpad; kb += 2 * KC) {
+        if (KC < kend) fetch(st1, KC);
+        for (int kb = 0; kb < kend; kb += 2 * KC) {
             st0.commit(sA[0], sB[0], t);
             __syncthreads();
-            if (kb + 2 * KC < ti.kpad) fetch(st0, kb + 2 * KC);
+            if (kb + 2 * KC < kend) fetch(st0, kb + 2 * KC);
             acc.mma(sA[0], sB[0], lane, w);
-            if (kb + KC >= ti.kpad) break;
+            if (kb + KC >= kend) break;
             st1.commit(sA[1], sB[1], t);
             __syncthreads();
-            if (kb + 3 * KC < ti.kpad) fetch(st1, kb + 3 * KC);
+            if (kb + 3 * KC < kend) fetch(st1, kb + 3 * KC);
             acc.mma(sA[1], sB[1], lane, w);
         }
     }
@@ -867,7 +888,7 @@ void mm_prepare_schedule(rad_hmat *H) {
     std::vector<TileTask> tk = H->d_tile_tasks.download(H->d_tile_tasks.n);
     std::vector<int64_t> cost(n, 0);
     for (int32_t i = 0; i < n; ++i) {
-        cost[i] = ti[i].kpad;
+        cost[i] = ti[i].k16;
         for (int32_t c = ti[i].csr_begin; c < ti[i].csr_end; ++c) cost[i] += tk[c].ncol;
     }
     std::vector<int32_t> order(n);

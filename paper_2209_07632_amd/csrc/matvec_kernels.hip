@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const 
 #pragma unroll
         for (int u = 0; u < VW; ++u) acc[u] += av[u] * xv;
     };
-    const int ngroups = ti.kpad / VW;       // kpad is a multiple of 32
+    const int ngroups = ti.k16 / VW;        // columns that hold values (a multiple of 16)
     int g = w;
     for (; g + 12 < ngroups; g += 16) {
         const int k0 = VW * g + sub, k1 = k0 + 4 * VW, k2 = k0 + 8 * VW, k3 = k0 + 12 * VW;

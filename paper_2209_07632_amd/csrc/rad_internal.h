@@ -123,9 +123,9 @@ enum TaskType : int32_t { TASK_DENSE = 0, TASK_CSR = 1, TASK_LOWRANK = 2 };
 struct TileInfo {
     int64_t panel_off;
     int64_t brow_off;
-    int32_t kpad;
+    int32_t kpad;          // panel columns, a multiple of 32 (the 16-bit chunk width)
     int32_t csr_begin, csr_end;
-    int32_t pad_;
+    int32_t k16;           // panel columns that hold values, rounded up to 16 (the FP32/FP64 chunk)
 };
 
 // Batched copy-with-cast of a column-major FP64 block into the value pool.
