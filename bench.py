@@ -330,6 +330,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="cap40k", choices=["cap40k", "dem131k", "batch64"])
     ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--tn", type=int, default=0, help="force the column-tile width (flat grid) instead of autotuning")
     ap.add_argument("--lowp", default="bf16", choices=["f16", "bf16"])
     ap.add_argument("--inner", type=int, default=3)
     ap.add_argument("--cpu-rows", type=int, default=6)
@@ -383,8 +384,13 @@ def main():
     E = albedo * Q
     B = torch.zeros_like(E)
     perm = H.perm()
-    tune = H.autotune(R, nrep=5)
-    log(f"autotuned launch configuration for R={R}: {tune}")
+    if args.tn:
+        H.set_config(R, args.tn, 0, 1)
+        tune = dict(H.get_config(R), ms=0.0)
+        log(f"forced launch configuration for R={R}: {tune}")
+    else:
+        tune = H.autotune(R, nrep=5)
+        log(f"autotuned launch configuration for R={R}: {tune}")
 
     def step():
         _, info = H.solve(E, rho=albedo, rtol=args.rtol, out=B, order="tree_rmajor", R=R)

@@ -649,18 +649,50 @@ __global__ void __launch_bounds__(256) k_reduce_inst(const double *partial, cons
     }
 }
 
-// partial[tile * R + r] = sum over the tile's 64 facets of E^2 (R-major)
+// partial[tile * R + r] = sum over the tile's 64 facets of E^2 (R-major).
+// A workgroup covers one tile and 256 columns: each thread four columns
+// (16-byte loads) over 16 of the 64 rows, the
+// four row quarters meeting in LDS in a fixed order.
 template <class T>
 __global__ void __launch_bounds__(256) k_colnorm_tiles(const T *E, int64_t N, int64_t ldr, int R, double *partial) {
-    const int r = blockIdx.y * 256 + threadIdx.x;
-    if (r >= R) return;
-    const int64_t t0 = (int64_t)blockIdx.x * 64, t1 = min(N, t0 + 64);
-    double s = 0.0;
-    for (int64_t t = t0; t < t1; ++t) {
-        double v = (double)E[t * ldr + r];
-        s += v * v;
+    const int c4 = blockIdx.y * 256 + (threadIdx.x & 63) * 4;
+    const int quarter = threadIdx.x >> 6;
+    const int64_t t0 = (int64_t)blockIdx.x * 64 + quarter * 16;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        const int64_t t = t0 + i;
+        if (t < N) {
+            const T *p = E + t * ldr + c4;
+            if (c4 + 3 < R) {
+                T v[4];
+                if constexpr (sizeof(T) == 4) {
+                    const float4 q = *(const float4 *)p;
+                    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+                } else {
+                    const double2 q0 = *(const double2 *)p, q1 = *(const double2 *)(p + 2);
+                    v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) s[u] += (double)v[u] * (double)v[u];
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (c4 + u < R) {
+                        const double v = (double)p[u];
+                        s[u] += v * v;
+                    }
+            }
+        }
     }
-    partial[(int64_t)blockIdx.x * R + r] = s;
+    __shared__ double red[4][256];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) red[quarter][(threadIdx.x & 63) * 4 + u] = s[u];
+    __syncthreads();
+    const int c = blockIdx.y * 256 + threadIdx.x;
+    if (c < R)
+        partial[(int64_t)blockIdx.x * R + c] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
 constexpr int kRmParts = 64;
