@@ -54,6 +54,12 @@ struct Mfma<double> {
 };
 
 // acc[i][j]: row tile i (16 rows), column tile j (16 columns of this wave's TN / 4)
+// Minimum waves per SIMD asked of the compiler: the FP32 64-column kernels
+// fit six (no spills), which hides more of their memory latency; the others
+// keep the compiler's choice.
+template <class T, int TN>
+constexpr int kWavesPerEu = (sizeof(T) == 4 && TN == 64) ? 6 : 1;
+
 // MI row tiles of 16 (64 rows for the expansion, 128 for paired projections)
 template <class T, int TN, int MI = 4>
 struct Tile {
@@ -369,7 +375,8 @@ struct P1Stage {
 // Partial projections of up to two work items that share a facet chunk
 // (consecutive 64-row slabs of V_J^T): the X chunk is staged once for 128 rows.
 template <class T, int TN>
-__global__ void __launch_bounds__(256) k_proj_mm(const ProjGroup *groups, const P1Work *work, const int32_t *pairs,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<T, TN>, 8)))
+k_proj_mm(const ProjGroup *groups, const P1Work *work, const int32_t *pairs,
                                                   const T *vals, const T *X, int64_t ldr, int R, T *part,
                                                   int rtiles) {
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
@@ -522,7 +529,8 @@ __device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileI
 
 // one workgroup per (64-row tile, TN-column tile); 1-D grid, XCD-aware order
 template <class T, bool kFused, int TN>
-__global__ void __launch_bounds__(256) k_tile_mm(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<T, TN>, 8)))
+k_tile_mm(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
                                                   const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
                                                   int64_t csr_val_start, const T *X, const T *Tb, int64_t ldr, int R,
                                                   int64_t N, T *Y, const T *E, const T *rho, T rho_s,
