@@ -155,8 +155,10 @@ typedef struct {
  * Jacobi: ||E + rho F G - G|| against ||rho F E||, both from one iteration;
  * the smaller one's iterate continues (one extra product).  Refinement:
  * ||E - G + rho F32 G|| against ||rho F16 E||; a rejected column restarts
- * from B = 0.  info->iters then counts from the chosen start (0 when the
- * guess already meets rtol under refinement).
+ * from B = 0.  A column whose guess already meets rtol is kept, and when
+ * every column's does, the cold-start product is skipped.  info->iters then
+ * counts from the chosen start (0 when the guess already meets rtol under
+ * refinement).  An R-major B is read in place (the guess may be B itself).
  * rho: device array of N reflectances (original order for RAD_ORDER_ORIGINAL,
  * tree order otherwise), or NULL to use rho_scalar for every facet.  E and B
  * are device arrays of the compute dtype in the layout opts->order names; they

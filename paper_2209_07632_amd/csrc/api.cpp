@@ -344,24 +344,32 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             if (o.warm) {
                 // guess G into the working layout (w_q2), residual with the FP32
                 // operator, judged against ||rho F16 E|| (one 16-bit Jacobi step from E)
-                float *G = (float *)H->w_q2.p;
-                if (rmaj)
-                    RAD_HIP(hipMemcpyAsync(G, B, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
-                else
-                    mm_to_rmajor(H, B, ldb, o.order == RAD_ORDER_ORIGINAL, G, ld, R, s);
+                // (an R-major B is read in place: it is only written at the end)
+                const float *G = rmaj ? (const float *)B : (const float *)H->w_q2.p;
+                if (!rmaj) mm_to_rmajor(H, B, ldb, o.order == RAD_ORDER_ORIGINAL, H->w_q2.p, ld, R, s);
                 ir_load(H, B64, B32, G, ld, R, s);
                 mm_apply(H, B32, FB, ld, R, s);
                 ir_residual(H, (const float *)Ein, B64, FB, (const float *)rho_t, rho_scalar, r, ld, R, dn_d, s);
-                std::vector<double> nw(R), nc(R);
+                std::vector<double> nw(R), nc(R, 0.0);
                 RAD_HIP(hipMemcpyAsync(nw.data(), dn_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
-                lowp_step(H, Ein, rho_t, rho_scalar, Ein, D[1], ld, R, dn_d, s);
-                RAD_HIP(hipMemcpyAsync(nc.data(), dn_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
                 RAD_HIP(hipStreamSynchronize(s));
+                // a guess that already meets rtol is kept without the comparison
+                std::vector<char> met(R);
+                bool all_met = true;
+                for (int64_t c = 0; c < R; ++c) {
+                    RAD_REQUIRE(std::isfinite(nw[c]), "starting guess gives a non-finite residual");
+                    met[c] = (enorm[c] > 0 ? std::sqrt(nw[c]) / enorm[c] : std::sqrt(nw[c])) <= o.rtol;
+                    all_met = all_met && met[c];
+                }
+                if (!all_met) {
+                    lowp_step(H, Ein, rho_t, rho_scalar, Ein, D[1], ld, R, dn_d, s);
+                    RAD_HIP(hipMemcpyAsync(nc.data(), dn_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
+                    RAD_HIP(hipStreamSynchronize(s));
+                }
                 std::vector<int32_t> flag(R);
                 done = true;
                 for (int64_t c = 0; c < R; ++c) {
-                    RAD_REQUIRE(std::isfinite(nw[c]), "starting guess gives a non-finite residual");
-                    flag[c] = nw[c] <= nc[c];
+                    flag[c] = met[c] || nw[c] <= nc[c];
                     warm_cols += flag[c];
                     double d = std::sqrt(flag[c] ? nw[c] : enorm[c] * enorm[c]);
                     rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
@@ -431,9 +439,10 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             // guess G into the working layout (w_q2); one iteration from G into
             // P[1] and one from E into w_q1; per column the smaller change wins
             // and its iterate becomes B^1 in P[0]
-            void *G = H->w_q2.p, *C1 = H->w_q1.p;
+            // (an R-major B on the multi-RHS path is read in place)
+            void *G = (mm && rmaj) ? B : H->w_q2.p, *C1 = H->w_q1.p;
             if (mm && rmaj)
-                RAD_HIP(hipMemcpyAsync(G, B, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
+                ;
             else if (mm)
                 mm_to_rmajor(H, B, ldb, o.order == RAD_ORDER_ORIGINAL, G, ld, R, s);
             else if (rmaj)
@@ -442,21 +451,31 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 RAD_HIP(hipMemcpy2DAsync(G, N * es, B, ldb * es, N * es, R, hipMemcpyDeviceToDevice, s));
             else
                 mv_gather(H, B, ldb, G, N, R, s);
-            std::vector<double> nw(R), nc(R);
+            std::vector<double> nw(R), nc(R, 0.0);
             IterArgs aw{mm, false, R, ld, Ein, rho_t, G, P[1], rho_scalar};
             enqueue_iteration(H, aw, s);
             RAD_HIP(hipStreamSynchronize(s));
             std::copy(H->h_norms, H->h_norms + R, nw.begin());
-            IterArgs ac{mm, false, R, ld, Ein, rho_t, Ein, C1, rho_scalar};
-            enqueue_iteration(H, ac, s);
-            RAD_HIP(hipStreamSynchronize(s));
-            std::copy(H->h_norms, H->h_norms + R, nc.begin());
+            // a guess whose first change already meets rtol is kept without the
+            // comparison; otherwise one iteration from E decides
+            std::vector<char> met(R);
+            bool all_met = true;
+            for (int64_t c = 0; c < R; ++c) {
+                RAD_REQUIRE(std::isfinite(nw[c]), "starting guess gives a non-finite residual");
+                met[c] = (enorm[c] > 0 ? std::sqrt(nw[c]) / enorm[c] : std::sqrt(nw[c])) <= o.rtol;
+                all_met = all_met && met[c];
+            }
+            if (!all_met) {
+                IterArgs ac{mm, false, R, ld, Ein, rho_t, Ein, C1, rho_scalar};
+                enqueue_iteration(H, ac, s);
+                RAD_HIP(hipStreamSynchronize(s));
+                std::copy(H->h_norms, H->h_norms + R, nc.begin());
+            }
             std::vector<int32_t> flag(R);
             k = 1;
             done = true;
             for (int64_t c = 0; c < R; ++c) {
-                RAD_REQUIRE(std::isfinite(nw[c]), "starting guess gives a non-finite residual");
-                flag[c] = nw[c] <= nc[c];
+                flag[c] = met[c] || nw[c] <= nc[c];
                 warm_cols += flag[c];
                 double d = std::sqrt(flag[c] ? nw[c] : nc[c]);
                 rel[c] = enorm[c] > 0 ? d / enorm[c] : d;

@@ -316,7 +316,7 @@ class HMatrix:
               raise_on_noconv=True, use_graph=True, R=None, refine=False, inner_iters=3, warm=None):
         """Jacobi solve of (I - diag(rho) F-hat) B = E; returns (B, info dict).
         warm: optional starting guess in the layout of B (judged per column
-        against the cold start)."""
+        against the cold start); it may be `out` itself."""
         torch = _torch()
         L = load()
         squeeze = False
@@ -336,7 +336,8 @@ class HMatrix:
         if warm is not None:
             if warm.shape[0] != self.N or warm.dtype != Bc.dtype:
                 raise ValueError("warm must match B in shape and dtype")
-            Bc.copy_(warm if order == "tree_rmajor" else warm.reshape(Bc.shape))
+            if warm.data_ptr() != Bc.data_ptr():
+                Bc.copy_(warm if order == "tree_rmajor" else warm.reshape(Bc.shape))
         rho_ptr = ctypes.c_void_p(0)
         rho_s = 0.0
         if isinstance(rho, (float, int)):
