@@ -29,6 +29,8 @@ void alloc_workspace(rad_hmat *H) {
     const size_t nc = (size_t)H->max_rhs * (size_t)H->n_inst;  // per-column norms (per instance in a group)
     H->w_norms.alloc(3 * nc);
     H->w_flags.alloc(nc);
+    H->w_thr.alloc(nc);
+    H->w_conv.alloc(nc + 1);
     if (H->max_rhs >= kMfmaMinRhs && H->n_parts > 0)
         H->w_part.alloc((size_t)H->n_parts * mm_part_rows() * ldr * s);
     H->w_q1.alloc(nr * s);
@@ -39,13 +41,17 @@ void alloc_workspace(rad_hmat *H) {
         H->w_x16.alloc((size_t)H->N * ld16);
         H->w_t16.alloc((size_t)std::max(H->t_ld, 4) * ld16);
     }
-    RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * nc, hipHostMallocDefault));
+    RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * 3 * nc, hipHostMallocDefault));
+    for (auto &e : H->ev) RAD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     RAD_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
     if (H->n_tiles > 0) mm_prepare_schedule(H);
 }
 
 // One Jacobi iteration, enqueued on stream s: B_new = E + rho (F-hat B_old),
-// the squared column changes in w_norms[max_rhs...], copied to pinned memory.
+// the squared column changes in w_norms[max_rhs...], copied to pinned memory
+// (hn, else the first slot).  With stop set (multi-RHS path only) every kernel
+// returns at once while the device flag is set, and the iteration ends with
+// the device-side stopping test.
 struct IterArgs {
     bool mm;
     bool lowp;
@@ -53,6 +59,8 @@ struct IterArgs {
     const void *E, *rho, *Bold;
     void *Bnew;
     double rho_s;
+    double *hn = nullptr;
+    const int32_t *stop = nullptr;
 };
 
 static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t s) {
@@ -60,12 +68,15 @@ static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t 
     if (a.lowp) {
         lowp_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s);
     } else if (a.mm) {
-        mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s);
+        mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s, a.stop);
+        if (a.stop)
+            conv_check(dn, H->w_thr.p, a.R * H->n_inst, H->w_conv.p, H->w_conv.p + H->max_rhs * H->n_inst, s);
     } else {
         mv_apply(H, a.Bold, a.ld, H->w_y.p, a.ld, a.R, s);
         solve_update(H, a.E, a.rho, a.rho_s, H->w_y.p, a.Bold, a.Bnew, a.ld, a.R, dn, s);
     }
-    RAD_HIP(hipMemcpyAsync(H->h_norms, dn, sizeof(double) * a.R * H->n_inst, hipMemcpyDeviceToHost, s));
+    RAD_HIP(hipMemcpyAsync(a.hn ? a.hn : H->h_norms, dn, sizeof(double) * a.R * H->n_inst, hipMemcpyDeviceToHost,
+                           s));
 }
 
 // Cached graph of one iteration (captured on the library's own stream,
@@ -73,7 +84,7 @@ static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t 
 static hipGraphExec_t iteration_graph(rad_hmat *H, const IterArgs &a) {
     for (auto &g : H->graphs)
         if (g.path == (int)a.mm + 2 * (int)a.lowp && g.R == a.R && g.Bold == a.Bold && g.Bnew == a.Bnew && g.E == a.E &&
-            g.rho == a.rho && g.rho_s == a.rho_s)
+            g.rho == a.rho && g.rho_s == a.rho_s && g.hn == a.hn && g.stop == a.stop)
             return g.ex;
     if (H->graphs.size() >= 24) {
         for (auto &g : H->graphs) {
@@ -90,6 +101,8 @@ static hipGraphExec_t iteration_graph(rad_hmat *H, const IterArgs &a) {
     e.E = a.E;
     e.rho = a.rho;
     e.rho_s = a.rho_s;
+    e.hn = a.hn;
+    e.stop = a.stop;
     RAD_HIP(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
     try {
         enqueue_iteration(H, a, H->cap_stream);
@@ -116,6 +129,8 @@ rad_hmat::~rad_hmat() {
         (void)hipGraphDestroy(g.g);
     }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
     if (h_norms) (void)hipHostFree(h_norms);
 }
 
@@ -318,12 +333,35 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             mm_col_norms2(H, Ein, ld, R, enorm_d, s);
         else
             col_norms2(H, Ein, N, R, enorm_d, s);
-        std::vector<double> enorm(NC), dn(NC);
-        RAD_HIP(hipMemcpyAsync(enorm.data(), enorm_d, NC * sizeof(double), hipMemcpyDeviceToHost, s));
-        RAD_HIP(hipStreamSynchronize(s));
-        for (auto &v : enorm) {
-            RAD_REQUIRE(std::isfinite(v), "E contains non-finite values");
-            v = std::sqrt(v);
+        // Multi-RHS Jacobi tested every iteration runs one iteration ahead of
+        // the host; the device skips that iteration once every column has met
+        // rtol (the same test in the same arithmetic as the host's below).
+        const bool ahead = mm && !o.refine && o.check_every == 1;
+        const int64_t nc_all = (int64_t)H->max_rhs * H->n_inst;
+        double *h_en = H->h_norms + 2 * nc_all;
+        int32_t *conv_d = H->w_conv.p, *stop_d = H->w_conv.p + nc_all;
+        const double rtol2 = o.rtol * o.rtol;
+        if (ahead) conv_init(enorm_d, rtol2, NC, H->w_thr.p, conv_d, stop_d, s);
+        RAD_HIP(hipMemcpyAsync(h_en, enorm_d, NC * sizeof(double), hipMemcpyDeviceToHost, s));
+        // column c has met rtol when its squared change (or residual) is <= thr[c]
+        std::vector<double> enorm(NC), thr(NC), dn(NC);
+        bool have_en = false;
+        auto take_enorm = [&] {   // after a synchronisation
+            if (have_en) return;
+            for (int64_t c = 0; c < NC; ++c) {
+                const double e2 = h_en[c];
+                if (!std::isfinite(e2)) {
+                    (void)hipStreamSynchronize(s);
+                    RAD_REQUIRE(false, "E contains non-finite values");
+                }
+                enorm[c] = std::sqrt(e2);
+                thr[c] = e2 > 0 ? rtol2 * e2 : rtol2;
+            }
+            have_en = true;
+        };
+        if (!ahead || o.warm) {
+            RAD_HIP(hipStreamSynchronize(s));
+            take_enorm();
         }
         std::vector<int32_t> iters(NC, -1);
         std::vector<double> rel(NC, 0.0);
@@ -358,7 +396,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 bool all_met = true;
                 for (int64_t c = 0; c < R; ++c) {
                     RAD_REQUIRE(std::isfinite(nw[c]), "starting guess gives a non-finite residual");
-                    met[c] = (enorm[c] > 0 ? std::sqrt(nw[c]) / enorm[c] : std::sqrt(nw[c])) <= o.rtol;
+                    met[c] = nw[c] <= thr[c];
                     all_met = all_met && met[c];
                 }
                 if (!all_met) {
@@ -371,9 +409,9 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 for (int64_t c = 0; c < R; ++c) {
                     flag[c] = met[c] || nw[c] <= nc[c];
                     warm_cols += flag[c];
-                    double d = std::sqrt(flag[c] ? nw[c] : enorm[c] * enorm[c]);
-                    rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
-                    if (rel[c] <= o.rtol) iters[c] = 0;
+                    const double d2 = flag[c] ? nw[c] : h_en[c];
+                    rel[c] = enorm[c] > 0 ? std::sqrt(d2) / enorm[c] : std::sqrt(d2);
+                    if (d2 <= thr[c]) iters[c] = 0;
                     if (iters[c] < 0) done = false;
                 }
                 RAD_HIP(hipMemcpyAsync(H->w_flags.p, flag.data(), R * sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -396,7 +434,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                         double d = std::sqrt(dn[c]);
                         rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
                         RAD_REQUIRE(std::isfinite(rel[c]), "solve produced non-finite values");
-                        if (iters[c] < 0 && rel[c] <= o.rtol) iters[c] = k;
+                        if (iters[c] < 0 && dn[c] <= thr[c]) iters[c] = k;
                         if (iters[c] < 0) done = false;
                     }
                     if (done || k >= o.max_iter) break;
@@ -462,7 +500,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             bool all_met = true;
             for (int64_t c = 0; c < R; ++c) {
                 RAD_REQUIRE(std::isfinite(nw[c]), "starting guess gives a non-finite residual");
-                met[c] = (enorm[c] > 0 ? std::sqrt(nw[c]) / enorm[c] : std::sqrt(nw[c])) <= o.rtol;
+                met[c] = nw[c] <= thr[c];
                 all_met = all_met && met[c];
             }
             if (!all_met) {
@@ -477,16 +515,54 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             for (int64_t c = 0; c < R; ++c) {
                 flag[c] = met[c] || nw[c] <= nc[c];
                 warm_cols += flag[c];
-                double d = std::sqrt(flag[c] ? nw[c] : nc[c]);
-                rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
+                const double d2 = flag[c] ? nw[c] : nc[c];
+                rel[c] = enorm[c] > 0 ? std::sqrt(d2) / enorm[c] : std::sqrt(d2);
                 RAD_REQUIRE(std::isfinite(rel[c]), "solve produced non-finite values");
-                if (rel[c] <= o.rtol) iters[c] = 1;
+                if (d2 <= thr[c]) iters[c] = 1;
                 if (iters[c] < 0) done = false;
             }
             RAD_HIP(hipMemcpyAsync(H->w_flags.p, flag.data(), R * sizeof(int32_t), hipMemcpyHostToDevice, s));
             select_columns(H, P[1], C1, H->w_flags.p, P[0], ld, R, mm, s);
         }
-        while (k < o.max_iter && !done) {
+        if (ahead) {
+            if (o.warm) {   // columns already met by the warm start
+                std::vector<int32_t> cv(NC);
+                for (int64_t c = 0; c < NC; ++c) cv[c] = iters[c] >= 0;
+                RAD_HIP(hipMemcpyAsync(conv_d, cv.data(), NC * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            }
+            double *slot[2] = {H->h_norms, H->h_norms + nc_all};
+            auto enqueue = [&](int kk) {
+                IterArgs a{mm, false, R, ld, Ein, rho_t, kk == 1 ? Ein : P[kk % 2], P[(kk - 1) % 2], rho_scalar,
+                           slot[kk % 2], stop_d};
+                if (o.use_graph)
+                    RAD_HIP(hipGraphLaunch(iteration_graph(Hm, a), s));
+                else
+                    enqueue_iteration(H, a, s);
+                RAD_HIP(hipEventRecord(H->ev[kk % 2], s));
+            };
+            int queued = k;
+            if (!done && k < o.max_iter) enqueue(++queued);
+            while (!done && k < o.max_iter) {
+                // iteration k + 1 is in flight; queue k + 2 behind it, then test k + 1
+                if (queued < o.max_iter) enqueue(++queued);
+                RAD_HIP(hipEventSynchronize(H->ev[(k + 1) % 2]));
+                ++k;
+                take_enorm();
+                const double *d2 = slot[k % 2];
+                done = true;
+                for (int64_t c = 0; c < NC; ++c) {
+                    const double d = std::sqrt(d2[c]);
+                    rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
+                    if (!std::isfinite(rel[c])) {
+                        (void)hipStreamSynchronize(s);
+                        RAD_REQUIRE(false, "solve produced non-finite values");
+                    }
+                    if (iters[c] < 0 && d2[c] <= thr[c]) iters[c] = k;
+                    if (iters[c] < 0) done = false;
+                }
+            }
+        }
+        while (!ahead && k < o.max_iter && !done) {
             ++k;
             IterArgs a{mm, false, R, ld, Ein, rho_t, k == 1 ? Ein : P[k % 2], P[(k - 1) % 2], rho_scalar};
             if (o.use_graph)
@@ -501,7 +577,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                     double d = std::sqrt(dn[c]);
                     rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
                     RAD_REQUIRE(std::isfinite(rel[c]), "solve produced non-finite values");
-                    if (iters[c] < 0 && rel[c] <= o.rtol) iters[c] = k;
+                    if (iters[c] < 0 && dn[c] <= thr[c]) iters[c] = k;
                     if (iters[c] < 0) done = false;
                 }
             }

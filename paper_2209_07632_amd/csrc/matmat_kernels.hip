@@ -378,7 +378,8 @@ template <class T, int TN>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<T, TN>, 8)))
 k_proj_mm(const ProjGroup *groups, const P1Work *work, const int32_t *pairs,
                                                   const T *vals, const T *X, int64_t ldr, int R, T *part,
-                                                  int rtiles) {
+                                                  int rtiles, const int32_t *stop) {
+    if (stop && *stop) return;
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
     const int p0 = pairs[2 * (wi / rtiles)], p1 = pairs[2 * (wi / rtiles) + 1];
     const P1Work wk = work[p0];
@@ -421,7 +422,9 @@ k_proj_mm(const ProjGroup *groups, const P1Work *work, const int32_t *pairs,
 // T rows = sum of the partial tiles of every split (fixed order); one thread
 // per (row of T, column)
 template <class T>
-__global__ void __launch_bounds__(256) k_proj_reduce(const P1Red *red, const T *part, int64_t ldr, int R, T *Tb) {
+__global__ void __launch_bounds__(256) k_proj_reduce(const P1Red *red, const T *part, int64_t ldr, int R, T *Tb,
+                                                     const int32_t *stop) {
+    if (stop && *stop) return;
     const P1Red rd = red[blockIdx.x / TM];
     const int row = blockIdx.x % TM;
     const int c = blockIdx.y * 256 + threadIdx.x;
@@ -534,7 +537,8 @@ k_tile_mm(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
                                                   const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
                                                   int64_t csr_val_start, const T *X, const T *Tb, int64_t ldr, int R,
                                                   int64_t N, T *Y, const T *E, const T *rho, T rho_s,
-                                                  double *partial, int rtiles) {
+                                                  double *partial, int rtiles, const int32_t *stop) {
+    if (stop && *stop) return;
     __shared__ T smem[TileSmem<T, TN>::kSize];
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
     tile_body<T, kFused, TN>(smem, wi / rtiles, wi % rtiles, tiles, brow, ctasks, vals, csr_ptr, csr_idx,
@@ -551,7 +555,8 @@ __global__ void __launch_bounds__(256) k_tile_mm_q(const TileInfo *tiles, const 
                                                     const int32_t *csr_idx, int64_t csr_val_start, const T *X,
                                                     const T *Tb, int64_t ldr, int R, int64_t N, T *Y, const T *E,
                                                     const T *rho, T rho_s, double *partial, const int32_t *order,
-                                                    int nwork, int rtiles, int *queue) {
+                                                    int nwork, int rtiles, int *queue, const int32_t *stop) {
+    if (stop && *stop) return;   // (before the counters: they stay at zero)
     __shared__ T smem[TileSmem<T, TN>::kSize];
     __shared__ int item;
     while (true) {
@@ -619,34 +624,31 @@ __global__ void __launch_bounds__(256) k_from_rmajor(const int32_t *perm, const 
     }
 }
 
-// out[r] = sum_i partial[i * R + r]: 16 columns x 16 part groups per
-// workgroup, fixed summation order (deterministic)
-__global__ void __launch_bounds__(256) k_reduce_rm(const double *partial, int nparts, int R, double *out) {
-    const int cl = threadIdx.x & 15, g = threadIdx.x >> 4;
-    const int r = blockIdx.x * 16 + cl;
-    double s = 0.0;
-    if (r < R)
-        for (int i = g; i < nparts; i += 16) s += partial[(int64_t)i * R + r];
-    __shared__ double red[16][17];
-    red[g][cl] = s;
-    __syncthreads();
-    if (g == 0 && r < R) {
-        double tot = 0.0;
-        for (int k = 0; k < 16; ++k) tot += red[k][cl];
-        out[r] = tot;
-    }
-}
-
-// Groups: out[k * R + r] = sum over the tiles of instance k, fixed order
-__global__ void __launch_bounds__(256) k_reduce_inst(const double *partial, const int32_t *inst_tile, int R,
-                                                      double *out) {
+// out[k * R + r] = sum over parts [t0, t1) of column r, where [t0, t1) is
+// [inst_tile[k], inst_tile[k + 1]) for instance k of a group, else [0, nparts).
+// Sixteen part classes (i mod 16) summed in order, then the classes in order:
+// the same fixed order for a matrix and for each instance of a group.  The loads
+// of a class are independent of its additions, so eight are kept in flight.
+__global__ void __launch_bounds__(256) k_reduce_parts(const double *partial, const int32_t *inst_tile, int nparts,
+                                                      int R, double *out, const int32_t *stop) {
+    if (stop && *stop) return;
     const int k = blockIdx.y;
     const int cl = threadIdx.x & 15, g = threadIdx.x >> 4;
     const int r = blockIdx.x * 16 + cl;
-    const int t0 = inst_tile[k], t1 = inst_tile[k + 1];
+    const int t0 = inst_tile ? inst_tile[k] : 0, t1 = inst_tile ? inst_tile[k + 1] : nparts;
     double s = 0.0;
-    if (r < R)
-        for (int i = t0 + g; i < t1; i += 16) s += partial[(int64_t)i * R + r];
+    if (r < R) {
+        const double *p = partial + r;
+        int i = t0 + g;
+        for (; i + 7 * 16 < t1; i += 8 * 16) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(i + 16 * u) * R];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; i < t1; i += 16) s += p[(int64_t)i * R];
+    }
     __shared__ double red[16][17];
     red[g][cl] = s;
     __syncthreads();
@@ -655,6 +657,31 @@ __global__ void __launch_bounds__(256) k_reduce_inst(const double *partial, cons
         for (int q = 0; q < 16; ++q) tot += red[q][cl];
         out[(int64_t)k * R + r] = tot;
     }
+}
+
+__global__ void __launch_bounds__(256) k_conv_init(const double *enorm2, double rtol2, int nc, double *thr,
+                                                   int32_t *conv, int32_t *stop) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < nc) {
+        const double e = enorm2[c];
+        thr[c] = e > 0 ? rtol2 * e : rtol2;
+        conv[c] = 0;
+    }
+    if (c == 0) *stop = 0;
+}
+
+// one workgroup; the branch on *stop is uniform
+__global__ void __launch_bounds__(1024) k_conv_check(const double *dn, const double *thr, int nc, int32_t *conv,
+                                                     int32_t *stop) {
+    if (*stop) return;
+    int all = 1;
+    for (int c = threadIdx.x; c < nc; c += 1024) {
+        const int v = conv[c] | (dn[c] <= thr[c] ? 1 : 0);
+        conv[c] = v;
+        all &= v;
+    }
+    all = __syncthreads_and(all);
+    if (threadIdx.x == 0) *stop = all;
 }
 
 // partial[tile * R + r] = sum over the tile's 64 facets of E^2 (R-major).
@@ -706,22 +733,22 @@ __global__ void __launch_bounds__(256) k_colnorm_tiles(const T *E, int64_t N, in
 constexpr int kRmParts = 64;
 
 template <class T, int TN>
-void proj_mm_tn(const rad_hmat *H, const T *X, int64_t ldr, int R, hipStream_t s) {
+void proj_mm_tn(const rad_hmat *H, const T *X, int64_t ldr, int R, hipStream_t s, const int32_t *stop = nullptr) {
     unsigned rtiles = (unsigned)((R + TN - 1) / TN);
     if (H->n_p1work > 0) {
         hipLaunchKernelGGL((k_proj_mm<T, TN>), dim3(H->n_p1pairs * rtiles), dim3(256), 0, s, H->d_groups.p,
                            H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const T *)H->d_vals.p, X, ldr, R,
-                           (T *)H->w_part.p, (int)rtiles);
+                           (T *)H->w_part.p, (int)rtiles, stop);
         RAD_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_proj_reduce<T>, dim3(H->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s, H->d_p1red.p,
-                           (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p);
+                           (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p, stop);
         RAD_HIP(hipGetLastError());
     }
 }
 
 template <class T, bool kFused, int TN>
 void tile_mm_launch(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int64_t ldr, int R, const T *E,
-                    const T *rho, T rho_s, double *partial, hipStream_t s) {
+                    const T *rho, T rho_s, double *partial, hipStream_t s, const int32_t *stop = nullptr) {
     const int rtiles = (R + TN - 1) / TN;
     if (c.persistent) {
         const int nwork = H->n_tiles * rtiles;
@@ -729,12 +756,12 @@ void tile_mm_launch(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int6
         hipLaunchKernelGGL((k_tile_mm_q<T, kFused, TN>), dim3(grid), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
                            H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
                            H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial,
-                           (const int32_t *)H->d_tile_order.p, nwork, rtiles, H->d_queue.p);
+                           (const int32_t *)H->d_tile_order.p, nwork, rtiles, H->d_queue.p, stop);
     } else {
         hipLaunchKernelGGL((k_tile_mm<T, kFused, TN>), dim3((unsigned)(H->n_tiles * rtiles)), dim3(256), 0, s,
                            H->d_tiles.p, H->d_brow.p, H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p,
                            H->d_csr_idx.p, H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s,
-                           partial, rtiles);
+                           partial, rtiles, stop);
     }
     RAD_HIP(hipGetLastError());
 }
@@ -742,29 +769,29 @@ void tile_mm_launch(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int6
 // projections with at most 128-column tiles (their accumulators hold 128 rows)
 template <class T, int TN>
 void apply_mm_tn(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int64_t ldr, int R, const T *E, const T *rho,
-                 T rho_s, double *partial, hipStream_t s) {
-    proj_mm_tn<T, (TN > 128 ? 128 : TN)>(H, X, ldr, R, s);
+                 T rho_s, double *partial, hipStream_t s, const int32_t *stop = nullptr) {
+    proj_mm_tn<T, (TN > 128 ? 128 : TN)>(H, X, ldr, R, s, stop);
     if (E)
-        tile_mm_launch<T, true, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
+        tile_mm_launch<T, true, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
     else
-        tile_mm_launch<T, false, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
+        tile_mm_launch<T, false, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
 }
 
 template <class T>
 void apply_mm_cfg(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int64_t ldr, int R, const T *E,
-                  const T *rho, T rho_s, double *partial, hipStream_t s) {
+                  const T *rho, T rho_s, double *partial, hipStream_t s, const int32_t *stop = nullptr) {
     if (c.tn == 64)
-        apply_mm_tn<T, 64>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
+        apply_mm_tn<T, 64>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
     else if (c.tn == 256 && sizeof(T) == 4)
-        apply_mm_tn<T, (sizeof(T) == 4 ? 256 : 128)>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
+        apply_mm_tn<T, (sizeof(T) == 4 ? 256 : 128)>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
     else
-        apply_mm_tn<T, 128>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s);
+        apply_mm_tn<T, 128>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
 }
 
 template <class T>
 void apply_mm_t(const rad_hmat *H, const T *X, T *Y, int64_t ldr, int R, const T *E, const T *rho, T rho_s,
-                double *partial, hipStream_t s) {
-    apply_mm_cfg<T>(H, mm_config(H, R), X, Y, ldr, R, E, rho, rho_s, partial, s);
+                double *partial, hipStream_t s, const int32_t *stop = nullptr) {
+    apply_mm_cfg<T>(H, mm_config(H, R), X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
 }
 
 }  // namespace
@@ -805,17 +832,18 @@ void mm_apply(const rad_hmat *H, const void *X, void *Y, int64_t ldr, int64_t R,
         apply_mm_t<float>(H, (const float *)X, (float *)Y, ldr, (int)R, nullptr, nullptr, 0.0f, nullptr, s);
 }
 
-// one Jacobi iteration: B_new = E + rho * (F-hat B_old), norms[r] = ||B_new - B_old||^2
+// one Jacobi iteration: B_new = E + rho * (F-hat B_old), norms[r] = ||B_new - B_old||^2;
+// with stop given, every kernel returns at once while *stop is set
 void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
-                    int64_t ldr, int64_t R, double *norms, hipStream_t s) {
+                    int64_t ldr, int64_t R, double *norms, hipStream_t s, const int32_t *stop) {
     double *part = (double *)H->w_red.p;
     if (H->dtype == RAD_F64)
         apply_mm_t<double>(H, (const double *)Bold, (double *)Bnew, ldr, (int)R, (const double *)E,
-                           (const double *)rho, rho_scalar, part, s);
+                           (const double *)rho, rho_scalar, part, s, stop);
     else
         apply_mm_t<float>(H, (const float *)Bold, (float *)Bnew, ldr, (int)R, (const float *)E, (const float *)rho,
-                          (float)rho_scalar, part, s);
-    mm_reduce_cols(H, part, H->n_tiles, R, norms, s);
+                          (float)rho_scalar, part, s, stop);
+    mm_reduce_cols(H, part, H->n_tiles, R, norms, s, stop);
     RAD_HIP(hipGetLastError());
 }
 
@@ -847,15 +875,15 @@ void time_phases_t(const rad_hmat *H, int R, int nrep, hipStream_t s, double *ms
             if (tn1 == 64)
                 hipLaunchKernelGGL((k_proj_mm<T, 64>), dim3(H->n_p1pairs * rtiles), dim3(256), 0, s, H->d_groups.p,
                                    H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const T *)H->d_vals.p, X, ldr,
-                                   R, (T *)H->w_part.p, (int)rtiles);
+                                   R, (T *)H->w_part.p, (int)rtiles, nullptr);
             else
                 hipLaunchKernelGGL((k_proj_mm<T, 128>), dim3(H->n_p1pairs * rtiles), dim3(256), 0, s, H->d_groups.p,
                                    H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const T *)H->d_vals.p, X, ldr,
-                                   R, (T *)H->w_part.p, (int)rtiles);
+                                   R, (T *)H->w_part.p, (int)rtiles, nullptr);
         });
         ms[1] = timed([&] {
             hipLaunchKernelGGL(k_proj_reduce<T>, dim3(H->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s,
-                               H->d_p1red.p, (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p);
+                               H->d_p1red.p, (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p, nullptr);
         });
     }
     ms[2] = timed([&] {
@@ -990,13 +1018,23 @@ std::vector<std::pair<MmConfig, double>> mm_autotune(rad_hmat *H, int64_t R, int
     return res;
 }
 
-void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s) {
-    if (H->n_inst > 1)
-        hipLaunchKernelGGL(k_reduce_inst, dim3((unsigned)((R + 15) / 16), (unsigned)H->n_inst), dim3(256), 0, s,
-                           partial, (const int32_t *)H->d_inst_tile.p, (int)R, out);
-    else
-        hipLaunchKernelGGL(k_reduce_rm, dim3((unsigned)((R + 15) / 16)), dim3(256), 0, s, partial, nparts, (int)R,
-                           out);
+void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s,
+                    const int32_t *stop) {
+    const bool grp = H->n_inst > 1;
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((R + 15) / 16), (unsigned)H->n_inst), dim3(256), 0, s,
+                       partial, grp ? (const int32_t *)H->d_inst_tile.p : nullptr, nparts, (int)R, out, stop);
+    RAD_HIP(hipGetLastError());
+}
+
+void conv_init(const double *enorm2, double rtol2, int64_t nc, double *thr, int32_t *conv, int32_t *stop,
+               hipStream_t s) {
+    hipLaunchKernelGGL(k_conv_init, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, enorm2, rtol2, (int)nc, thr,
+                       conv, stop);
+    RAD_HIP(hipGetLastError());
+}
+
+void conv_check(const double *dn, const double *thr, int64_t nc, int32_t *conv, int32_t *stop, hipStream_t s) {
+    hipLaunchKernelGGL(k_conv_check, dim3(1), dim3(1024), 0, s, dn, thr, (int)nc, conv, stop);
     RAD_HIP(hipGetLastError());
 }
 

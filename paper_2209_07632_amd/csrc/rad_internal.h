@@ -223,12 +223,15 @@ struct rad_hmat {
         const void *Bold, *E, *rho;
         void *Bnew;
         double rho_s;
+        double *hn;
+        const int32_t *stop;
         hipGraph_t g;
         hipGraphExec_t ex;
     };
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
-    double *h_norms = nullptr;   // pinned host copy of the per-column norms
+    double *h_norms = nullptr;   // pinned: two slots of per-column changes, then ||E||^2
+    hipEvent_t ev[2] = {nullptr, nullptr};   // ends of the iterations in flight
     ~rad_hmat();
 
     // workspace (sized for max_rhs)
@@ -242,6 +245,8 @@ struct rad_hmat {
     rad::DevBuf<float> d_pscale, d_tscale;
     rad::DevBuf<double> w_norms;
     rad::DevBuf<int32_t> w_flags;         // per-column choices of warm-started solves
+    rad::DevBuf<double> w_thr;            // per-column stopping thresholds of a solve
+    rad::DevBuf<int32_t> w_conv;          // per-column "met rtol", then the stop flag
 
     // group of independent matrices (block diagonal): instance k owns rows
     // [inst_off[k], inst_off[k] + inst_n[k]) and tiles [inst_tile[k], inst_tile[k+1])
@@ -361,14 +366,21 @@ void mm_from_rmajor(const rad_hmat *H, const void *src, int64_t ldr, bool permut
 void mm_apply(const rad_hmat *H, const void *X, void *Y, int64_t ldr, int64_t R, hipStream_t s);
 void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, double *out, hipStream_t s);
 void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
-                    int64_t ldr, int64_t R, double *norms, hipStream_t s);
+                    int64_t ldr, int64_t R, double *norms, hipStream_t s, const int32_t *stop = nullptr);
 size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R);
 rad::MmConfig mm_config(const rad_hmat *H, int64_t R);
 void mm_prepare_schedule(rad_hmat *H);
 // times every candidate configuration of one Jacobi iteration for R columns
 // and records the fastest in H->tuned; returns (config, ms) of every candidate
 std::vector<std::pair<rad::MmConfig, double>> mm_autotune(rad_hmat *H, int64_t R, int nrep, hipStream_t s);
-void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s);
+void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s,
+                    const int32_t *stop = nullptr);
+// device-side stopping test of a Jacobi solve: thr[c] = rtol2 enorm2[c] (rtol2
+// when enorm2[c] = 0), conv and stop cleared; then per iteration conv[c] |=
+// dn[c] <= thr[c] and stop = all(conv), skipped once stop is set
+void conv_init(const double *enorm2, double rtol2, int64_t nc, double *thr, int32_t *conv, int32_t *stop,
+               hipStream_t s);
+void conv_check(const double *dn, const double *thr, int64_t nc, int32_t *conv, int32_t *stop, hipStream_t s);
 
 // 16-bit operator (lowp_kernels.hip)
 void ir_select(const rad_hmat *H, double *B64, float *B32, float *r, const float *E, const int32_t *flag, int64_t ldr,
