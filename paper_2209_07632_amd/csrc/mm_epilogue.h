@@ -3,11 +3,17 @@
 // sits in LDS (sC); every thread streams 16-byte groups of whole rows: Y = tile, or
 // with the fused Jacobi update B_new = E + rho * tile, writing the per-column
 // partial sums of (B_new - B_old)^2 of this tile.  Reductions use a fixed order.
+// E, B_old and the output are streamed once per launch: their accesses are
+// non-temporal, which leaves the caches to the operator panels and T rows that
+// every column tile of a row tile re-reads.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace rad {
+
+typedef float epi_f4 __attribute__((ext_vector_type(4)));
+typedef double epi_d2 __attribute__((ext_vector_type(2)));
 
 // E and B_old values of one group of four rows of this thread's epilogue
 // share (rows rsub + RS (4 g + q), columns col .. col + 3)
@@ -30,12 +36,15 @@ struct EpiRegs {
             T a[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
             if (row < rows && full) {
                 if constexpr (sizeof(T) == 4) {
-                    float4 av = *(const float4 *)(E + e), ov = *(const float4 *)(X + e);
+                    const epi_f4 av = __builtin_nontemporal_load((const epi_f4 *)(E + e));
+                    const epi_f4 ov = __builtin_nontemporal_load((const epi_f4 *)(X + e));
                     a[0] = av.x; a[1] = av.y; a[2] = av.z; a[3] = av.w;
                     o[0] = ov.x; o[1] = ov.y; o[2] = ov.z; o[3] = ov.w;
                 } else {
-                    double2 a0 = *(const double2 *)(E + e), a1 = *(const double2 *)(E + e + 2);
-                    double2 o0 = *(const double2 *)(X + e), o1 = *(const double2 *)(X + e + 2);
+                    const epi_d2 a0 = __builtin_nontemporal_load((const epi_d2 *)(E + e));
+                    const epi_d2 a1 = __builtin_nontemporal_load((const epi_d2 *)(E + e + 2));
+                    const epi_d2 o0 = __builtin_nontemporal_load((const epi_d2 *)(X + e));
+                    const epi_d2 o1 = __builtin_nontemporal_load((const epi_d2 *)(X + e + 2));
                     a[0] = a0.x; a[1] = a0.y; a[2] = a1.x; a[3] = a1.y;
                     o[0] = o0.x; o[1] = o0.y; o[2] = o1.x; o[3] = o1.y;
                 }
@@ -95,10 +104,12 @@ __device__ __forceinline__ void tile_epilogue(const T (*sC)[LDC], void *smem, in
                 }
                 if (full) {
                     if constexpr (sizeof(T) == 4) {
-                        *(float4 *)(Y + e) = make_float4(y[0], y[1], y[2], y[3]);
+                        const epi_f4 yv = {y[0], y[1], y[2], y[3]};
+                        __builtin_nontemporal_store(yv, (epi_f4 *)(Y + e));
                     } else {
-                        *(double2 *)(Y + e) = make_double2(y[0], y[1]);
-                        *(double2 *)(Y + e + 2) = make_double2(y[2], y[3]);
+                        const epi_d2 y0 = {y[0], y[1]}, y1 = {y[2], y[3]};
+                        __builtin_nontemporal_store(y0, (epi_d2 *)(Y + e));
+                        __builtin_nontemporal_store(y1, (epi_d2 *)(Y + e + 2));
                     }
                 } else {
 #pragma unroll
