@@ -13,6 +13,8 @@
 //       CSR slices are expanded to dense chunks in LDS.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cstdio>
 #include <vector>
@@ -73,24 +75,25 @@ struct Tile {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
     }
-    // one chunk of KC from LDS: sA[k][row], sB[k][col]; row tiles from mi_on on
-    // hold only zero rows and are skipped (a uniform branch per wave)
-    __device__ __forceinline__ void mma(const T (*sA)[MI * 16 + PADA], const T (*sB)[TN + PADB], int lane, int w,
-                                        int mi_on = MI) {
+    // one chunk of KC from LDS: sA[k][row], sB[k][col]; only the first MION row
+    // tiles are computed (the others hold zero rows).  Instruction s takes
+    // k = (KC / 4) lk + s in lane group lk: with row strides of 4 (mod 16)
+    // values the four groups read disjoint LDS banks.
+    template <int MION = MI>
+    __device__ __forceinline__ void mma(const T (*sA)[MI * 16 + PADA], const T (*sB)[TN + PADB], int lane, int w) {
         const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
-            const int k = s * 4 + lk;
-            T a[MI], b[NJ];
+            const int k = lk * (KC / 4) + s;
+            T a[MION], b[NJ];
 #pragma unroll
-            for (int i = 0; i < MI; ++i) a[i] = sA[k][i * 16 + lr];
+            for (int i = 0; i < MION; ++i) a[i] = sA[k][i * 16 + lr];
 #pragma unroll
             for (int j = 0; j < NJ; ++j) b[j] = sB[k][w * (TN / 4) + j * 16 + lr];
 #pragma unroll
-            for (int i = 0; i < MI; ++i)
-                if (i < mi_on)
+            for (int i = 0; i < MION; ++i)
 #pragma unroll
-                    for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
         }
     }
 };
@@ -392,16 +395,31 @@ k_proj_mm(const ProjGroup *groups, const P1Work *work, const int32_t *pairs,
     tile.zero();
     const int rows = min(p1 >= 0 ? 128 : TM, g.ktot - wk.krow0);
     const T *V = vals + g.v_off + (int64_t)wk.krow0 * g.ld;
-    P1Stage<T, TN> st;
-    int buf = 0;
-    st.fetch(V, g.ld, rows, wk.jb, min(KC, wk.je - wk.jb), X, (int64_t)g.j0 + wk.jb, ldr, r0, R, t);
-    for (int kb = wk.jb; kb < wk.je; kb += KC) {
-        st.commit(sA[buf], sB[buf], t);
-        __syncthreads();
-        const int nk = kb + KC;
-        if (nk < wk.je) st.fetch(V, g.ld, rows, nk, min(KC, wk.je - nk), X, (int64_t)g.j0 + nk, ldr, r0, R, t);
-        tile.mma(sA[buf], sB[buf], lane, w, (rows + 15) / 16);
-        buf ^= 1;
+    // the reduction loop for MION active row tiles (all-zero row tiles of the
+    // slab are skipped): one straight-line instance per count
+    auto reduce = [&](auto mion) {
+        constexpr int MION = decltype(mion)::value;
+        P1Stage<T, TN> st;
+        int buf = 0;
+        st.fetch(V, g.ld, rows, wk.jb, min(KC, wk.je - wk.jb), X, (int64_t)g.j0 + wk.jb, ldr, r0, R, t);
+        for (int kb = wk.jb; kb < wk.je; kb += KC) {
+            st.commit(sA[buf], sB[buf], t);
+            __syncthreads();
+            const int nk = kb + KC;
+            if (nk < wk.je) st.fetch(V, g.ld, rows, nk, min(KC, wk.je - nk), X, (int64_t)g.j0 + nk, ldr, r0, R, t);
+            tile.template mma<MION>(sA[buf], sB[buf], lane, w);
+            buf ^= 1;
+        }
+    };
+    switch ((rows + 15) / 16) {
+        case 1: reduce(std::integral_constant<int, 1>{}); break;
+        case 2: reduce(std::integral_constant<int, 2>{}); break;
+        case 3: reduce(std::integral_constant<int, 3>{}); break;
+        case 4: reduce(std::integral_constant<int, 4>{}); break;
+        case 5: reduce(std::integral_constant<int, 5>{}); break;
+        case 6: reduce(std::integral_constant<int, 6>{}); break;
+        case 7: reduce(std::integral_constant<int, 7>{}); break;
+        default: reduce(std::integral_constant<int, 8>{}); break;
     }
     T *out0 = part + (int64_t)wk.part * TM * ldr;
     T *out1 = p1 >= 0 ? part + (int64_t)work[p1].part * TM * ldr : nullptr;
