@@ -475,14 +475,31 @@ def main():
         tune = H.autotune(R, nrep=5)
         log(f"autotuned launch configuration for R={R}: {tune}")
 
+    # iteration launches: replayed graphs or direct launches (the solve keeps one
+    # iteration queued ahead of the host either way); the faster one is kept
+    use_graph = True
+
     def step():
-        _, info = H.solve(E, rho=albedo, rtol=args.rtol, out=B, order="tree_rmajor", R=R)
+        _, info = H.solve(E, rho=albedo, rtol=args.rtol, out=B, order="tree_rmajor", R=R, use_graph=use_graph)
         return info
 
+    mode_ms = {}
+    for g in (True, False):
+        use_graph = g
+        for _ in range(max(1, args.warmup)):
+            info = step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            step()
+        torch.cuda.synchronize()
+        mode_ms[g] = 1e3 * (time.perf_counter() - t0) / 5
+    use_graph = min(mode_ms, key=mode_ms.get)
     for _ in range(args.warmup):
         info = step()
     torch.cuda.synchronize()
-    log(f"warmup done, iters {int(info['total_iters'])}")
+    log(f"warmup done, iters {int(info['total_iters'])}; ms/step with graphs {mode_ms[True]:.3f}, "
+        f"direct launches {mode_ms[False]:.3f}: use_graph={use_graph}")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         info = step()
@@ -569,6 +586,7 @@ def main():
         "phase_ms": {"projections": ph[0], "split_k_sum": ph[1], "expansion_jacobi": ph[2]},
         "projections_tflops": p1_tf,
         "autotune": tune,
+        "use_graph": use_graph,
     }
     # the plain form the batched solve replaces: FP64 operator, one sun at a
     # time (single-RHS products), same tolerance and stopping rule

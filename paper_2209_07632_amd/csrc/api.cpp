@@ -31,6 +31,7 @@ void alloc_workspace(rad_hmat *H) {
     H->w_flags.alloc(nc);
     H->w_thr.alloc(nc);
     H->w_conv.alloc(nc + 1);
+    if (H->max_rhs >= kMfmaMinRhs && H->n_tiles > 0) H->w_ered.alloc((size_t)H->n_tiles * (size_t)H->max_rhs);
     if (H->max_rhs >= kMfmaMinRhs && H->n_parts > 0)
         H->w_part.alloc((size_t)H->n_parts * mm_part_rows() * ldr * s);
     H->w_q1.alloc(nr * s);
@@ -51,7 +52,9 @@ void alloc_workspace(rad_hmat *H) {
 // the squared column changes in w_norms[max_rhs...], copied to pinned memory
 // (hn, else the first slot).  With stop set (multi-RHS path only) every kernel
 // returns at once while the device flag is set, and the iteration ends with
-// the device-side stopping test.
+// the device-side stopping test.  first (multi-RHS, B_old = E): the same pass
+// also sums ||E||^2 per column (to w_norms and the pinned slot after the two
+// change slots), and the test starts from thresholds rtol2 ||E||^2.
 struct IterArgs {
     bool mm;
     bool lowp;
@@ -61,6 +64,8 @@ struct IterArgs {
     double rho_s;
     double *hn = nullptr;
     const int32_t *stop = nullptr;
+    bool first = false;
+    double rtol2 = 0.0;
 };
 
 static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t s) {
@@ -68,9 +73,15 @@ static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t 
     if (a.lowp) {
         lowp_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s);
     } else if (a.mm) {
-        mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s, a.stop);
-        if (a.stop)
-            conv_check(dn, H->w_thr.p, a.R * H->n_inst, H->w_conv.p, H->w_conv.p + H->max_rhs * H->n_inst, s);
+        const int64_t nc = a.R * H->n_inst, nc_all = (int64_t)H->max_rhs * H->n_inst;
+        double *en = a.first ? H->w_norms.p : nullptr;
+        mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s, a.stop, en);
+        if (a.first) {
+            conv_first(en, a.rtol2, dn, nc, H->w_thr.p, H->w_conv.p, H->w_conv.p + nc_all, s);
+            RAD_HIP(hipMemcpyAsync(H->h_norms + 2 * nc_all, en, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+        } else if (a.stop) {
+            conv_check(dn, H->w_thr.p, nc, H->w_conv.p, H->w_conv.p + nc_all, s);
+        }
     } else {
         mv_apply(H, a.Bold, a.ld, H->w_y.p, a.ld, a.R, s);
         solve_update(H, a.E, a.rho, a.rho_s, H->w_y.p, a.Bold, a.Bnew, a.ld, a.R, dn, s);
@@ -84,7 +95,8 @@ static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t 
 static hipGraphExec_t iteration_graph(rad_hmat *H, const IterArgs &a) {
     for (auto &g : H->graphs)
         if (g.path == (int)a.mm + 2 * (int)a.lowp && g.R == a.R && g.Bold == a.Bold && g.Bnew == a.Bnew && g.E == a.E &&
-            g.rho == a.rho && g.rho_s == a.rho_s && g.hn == a.hn && g.stop == a.stop)
+            g.rho == a.rho && g.rho_s == a.rho_s && g.hn == a.hn && g.stop == a.stop && g.first == a.first &&
+            g.rtol2 == a.rtol2)
             return g.ex;
     if (H->graphs.size() >= 24) {
         for (auto &g : H->graphs) {
@@ -103,6 +115,8 @@ static hipGraphExec_t iteration_graph(rad_hmat *H, const IterArgs &a) {
     e.rho_s = a.rho_s;
     e.hn = a.hn;
     e.stop = a.stop;
+    e.first = a.first;
+    e.rtol2 = a.rtol2;
     RAD_HIP(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
     try {
         enqueue_iteration(H, a, H->cap_stream);
@@ -329,20 +343,24 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             rho_t = H->w_rho.p;
         }
         double *enorm_d = H->w_norms.p;
-        if (mm)
-            mm_col_norms2(H, Ein, ld, R, enorm_d, s);
-        else
-            col_norms2(H, Ein, N, R, enorm_d, s);
         // Multi-RHS Jacobi tested every iteration runs one iteration ahead of
         // the host; the device skips that iteration once every column has met
         // rtol (the same test in the same arithmetic as the host's below).
+        // From a cold start the first iteration also sums ||E||^2.
         const bool ahead = mm && !o.refine && o.check_every == 1;
+        const bool fused_en = ahead && !o.warm;
+        if (fused_en)
+            ;
+        else if (mm)
+            mm_col_norms2(H, Ein, ld, R, enorm_d, s);
+        else
+            col_norms2(H, Ein, N, R, enorm_d, s);
         const int64_t nc_all = (int64_t)H->max_rhs * H->n_inst;
         double *h_en = H->h_norms + 2 * nc_all;
         int32_t *conv_d = H->w_conv.p, *stop_d = H->w_conv.p + nc_all;
         const double rtol2 = o.rtol * o.rtol;
-        if (ahead) conv_init(enorm_d, rtol2, NC, H->w_thr.p, conv_d, stop_d, s);
-        RAD_HIP(hipMemcpyAsync(h_en, enorm_d, NC * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (ahead && !fused_en) conv_init(enorm_d, rtol2, NC, H->w_thr.p, conv_d, stop_d, s);
+        if (!fused_en) RAD_HIP(hipMemcpyAsync(h_en, enorm_d, NC * sizeof(double), hipMemcpyDeviceToHost, s));
         // column c has met rtol when its squared change (or residual) is <= thr[c]
         std::vector<double> enorm(NC), thr(NC), dn(NC);
         bool have_en = false;
@@ -532,8 +550,10 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             }
             double *slot[2] = {H->h_norms, H->h_norms + nc_all};
             auto enqueue = [&](int kk) {
+                // (the first iteration of a cold start is never skipped)
+                const bool first = kk == 1 && fused_en;
                 IterArgs a{mm, false, R, ld, Ein, rho_t, kk == 1 ? Ein : P[kk % 2], P[(kk - 1) % 2], rho_scalar,
-                           slot[kk % 2], stop_d};
+                           slot[kk % 2], first ? nullptr : stop_d, first, rtol2};
                 if (o.use_graph)
                     RAD_HIP(hipGraphLaunch(iteration_graph(Hm, a), s));
                 else

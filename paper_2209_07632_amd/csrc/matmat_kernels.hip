@@ -465,12 +465,13 @@ struct TileSmem {
     static_assert(1024 * sizeof(double) <= sizeof(T) * kSize, "partial sums fit");
 };
 
-template <class T, bool kFused, int TN>
+// kMode: 0 = Y = F X; 1 = fused Jacobi update; 2 = fused, plus ||E||^2 partials
+template <class T, int kMode, int TN>
 __device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileInfo *tiles, const int32_t *brow,
                                           const TileTask *ctasks, const T *vals, const int32_t *csr_ptr,
                                           const int32_t *csr_idx, int64_t csr_val_start, const T *X, const T *Tb,
                                           int64_t ldr, int R, int64_t N, T *Y, const T *E, const T *rho, T rho_s,
-                                          double *partial) {
+                                          double *partial, double *epartial) {
     const TileInfo ti = tiles[tile];
     const int64_t tile0 = (int64_t)tile * TM;
     const int r0 = rt * TN;
@@ -545,34 +546,36 @@ __device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileI
                     sC[i * 16 + Mfma<T>::row(lk, v)][w * (TN / 4) + j * 16 + lr] = acc.acc[i][j][v];
     }
     __syncthreads();
-    tile_epilogue<T, kFused, TM, TN, TN + PADB>(sC, smem, tile, tile0, r0, ldr, R, N, Y, E, X, rho, rho_s, partial);
+    tile_epilogue<T, kMode != 0, TM, TN, TN + PADB, kMode == 2>(sC, smem, tile, tile0, r0, ldr, R, N, Y, E, X, rho,
+                                                                rho_s, partial, epartial);
 }
 
 // one workgroup per (64-row tile, TN-column tile); 1-D grid, XCD-aware order
-template <class T, bool kFused, int TN>
+template <class T, int kMode, int TN>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<T, TN>, 8)))
 k_tile_mm(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
                                                   const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
                                                   int64_t csr_val_start, const T *X, const T *Tb, int64_t ldr, int R,
                                                   int64_t N, T *Y, const T *E, const T *rho, T rho_s,
-                                                  double *partial, int rtiles, const int32_t *stop) {
+                                                  double *partial, double *epartial, int rtiles, const int32_t *stop) {
     if (stop && *stop) return;
     __shared__ T smem[TileSmem<T, TN>::kSize];
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
-    tile_body<T, kFused, TN>(smem, wi / rtiles, wi % rtiles, tiles, brow, ctasks, vals, csr_ptr, csr_idx,
-                             csr_val_start, X, Tb, ldr, R, N, Y, E, rho, rho_s, partial);
+    tile_body<T, kMode, TN>(smem, wi / rtiles, wi % rtiles, tiles, brow, ctasks, vals, csr_ptr, csr_idx,
+                            csr_val_start, X, Tb, ldr, R, N, Y, E, rho, rho_s, partial, epartial);
 }
 
 // Persistent form: a fixed grid pulls work items (tiles in decreasing cost
 // order, all column tiles of a tile in a row) from a counter.  Every
 // workgroup leaves when the counter passes nwork; the last one to leave
 // resets both counters for the next launch (no memset in captured graphs).
-template <class T, bool kFused, int TN>
+template <class T, int kMode, int TN>
 __global__ void __launch_bounds__(256) k_tile_mm_q(const TileInfo *tiles, const int32_t *brow,
                                                     const TileTask *ctasks, const T *vals, const int32_t *csr_ptr,
                                                     const int32_t *csr_idx, int64_t csr_val_start, const T *X,
                                                     const T *Tb, int64_t ldr, int R, int64_t N, T *Y, const T *E,
-                                                    const T *rho, T rho_s, double *partial, const int32_t *order,
+                                                    const T *rho, T rho_s, double *partial, double *epartial,
+                                                    const int32_t *order,
                                                     int nwork, int rtiles, int *queue, const int32_t *stop) {
     if (stop && *stop) return;   // (before the counters: they stay at zero)
     __shared__ T smem[TileSmem<T, TN>::kSize];
@@ -583,8 +586,8 @@ __global__ void __launch_bounds__(256) k_tile_mm_q(const TileInfo *tiles, const 
         const int wi = item;
         __syncthreads();
         if (wi >= nwork) break;
-        tile_body<T, kFused, TN>(smem, order[wi / rtiles], wi % rtiles, tiles, brow, ctasks, vals, csr_ptr, csr_idx,
-                                 csr_val_start, X, Tb, ldr, R, N, Y, E, rho, rho_s, partial);
+        tile_body<T, kMode, TN>(smem, order[wi / rtiles], wi % rtiles, tiles, brow, ctasks, vals, csr_ptr, csr_idx,
+                                csr_val_start, X, Tb, ldr, R, N, Y, E, rho, rho_s, partial, epartial);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -702,6 +705,22 @@ __global__ void __launch_bounds__(1024) k_conv_check(const double *dn, const dou
     if (threadIdx.x == 0) *stop = all;
 }
 
+// one workgroup: thresholds as k_conv_init, then the test as k_conv_check
+__global__ void __launch_bounds__(1024) k_conv_first(const double *enorm2, double rtol2, const double *dn, int nc,
+                                                     double *thr, int32_t *conv, int32_t *stop) {
+    int all = 1;
+    for (int c = threadIdx.x; c < nc; c += 1024) {
+        const double e = enorm2[c];
+        const double th = e > 0 ? rtol2 * e : rtol2;
+        thr[c] = th;
+        const int v = dn[c] <= th ? 1 : 0;
+        conv[c] = v;
+        all &= v;
+    }
+    all = __syncthreads_and(all);
+    if (threadIdx.x == 0) *stop = all;
+}
+
 // partial[tile * R + r] = sum over the tile's 64 facets of E^2 (R-major).
 // A workgroup covers one tile and 256 columns: each thread four columns
 // (16-byte loads) over 16 of the 64 rows, the
@@ -764,22 +783,23 @@ void proj_mm_tn(const rad_hmat *H, const T *X, int64_t ldr, int R, hipStream_t s
     }
 }
 
-template <class T, bool kFused, int TN>
+template <class T, int kMode, int TN>
 void tile_mm_launch(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int64_t ldr, int R, const T *E,
-                    const T *rho, T rho_s, double *partial, hipStream_t s, const int32_t *stop = nullptr) {
+                    const T *rho, T rho_s, double *partial, hipStream_t s, const int32_t *stop = nullptr,
+                    double *epartial = nullptr) {
     const int rtiles = (R + TN - 1) / TN;
     if (c.persistent) {
         const int nwork = H->n_tiles * rtiles;
         const int grid = std::max(1, std::min(nwork, H->n_cu * std::max(1, (int)c.blocks_per_cu)));
-        hipLaunchKernelGGL((k_tile_mm_q<T, kFused, TN>), dim3(grid), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
+        hipLaunchKernelGGL((k_tile_mm_q<T, kMode, TN>), dim3(grid), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
                            H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
                            H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial,
-                           (const int32_t *)H->d_tile_order.p, nwork, rtiles, H->d_queue.p, stop);
+                           epartial, (const int32_t *)H->d_tile_order.p, nwork, rtiles, H->d_queue.p, stop);
     } else {
-        hipLaunchKernelGGL((k_tile_mm<T, kFused, TN>), dim3((unsigned)(H->n_tiles * rtiles)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_tile_mm<T, kMode, TN>), dim3((unsigned)(H->n_tiles * rtiles)), dim3(256), 0, s,
                            H->d_tiles.p, H->d_brow.p, H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p,
                            H->d_csr_idx.p, H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s,
-                           partial, rtiles, stop);
+                           partial, epartial, rtiles, stop);
     }
     RAD_HIP(hipGetLastError());
 }
@@ -787,29 +807,32 @@ void tile_mm_launch(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int6
 // projections with at most 128-column tiles (their accumulators hold 128 rows)
 template <class T, int TN>
 void apply_mm_tn(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int64_t ldr, int R, const T *E, const T *rho,
-                 T rho_s, double *partial, hipStream_t s, const int32_t *stop = nullptr) {
+                 T rho_s, double *partial, hipStream_t s, const int32_t *stop = nullptr, double *epartial = nullptr) {
     proj_mm_tn<T, (TN > 128 ? 128 : TN)>(H, X, ldr, R, s, stop);
-    if (E)
-        tile_mm_launch<T, true, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
+    if (E && epartial)
+        tile_mm_launch<T, 2, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop, epartial);
+    else if (E)
+        tile_mm_launch<T, 1, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
     else
-        tile_mm_launch<T, false, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
+        tile_mm_launch<T, 0, TN>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
 }
 
 template <class T>
 void apply_mm_cfg(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int64_t ldr, int R, const T *E,
-                  const T *rho, T rho_s, double *partial, hipStream_t s, const int32_t *stop = nullptr) {
+                  const T *rho, T rho_s, double *partial, hipStream_t s, const int32_t *stop = nullptr,
+                  double *epartial = nullptr) {
     if (c.tn == 64)
-        apply_mm_tn<T, 64>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
+        apply_mm_tn<T, 64>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop, epartial);
     else if (c.tn == 256 && sizeof(T) == 4)
-        apply_mm_tn<T, (sizeof(T) == 4 ? 256 : 128)>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
+        apply_mm_tn<T, (sizeof(T) == 4 ? 256 : 128)>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop, epartial);
     else
-        apply_mm_tn<T, 128>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
+        apply_mm_tn<T, 128>(H, c, X, Y, ldr, R, E, rho, rho_s, partial, s, stop, epartial);
 }
 
 template <class T>
 void apply_mm_t(const rad_hmat *H, const T *X, T *Y, int64_t ldr, int R, const T *E, const T *rho, T rho_s,
-                double *partial, hipStream_t s, const int32_t *stop = nullptr) {
-    apply_mm_cfg<T>(H, mm_config(H, R), X, Y, ldr, R, E, rho, rho_s, partial, s, stop);
+                double *partial, hipStream_t s, const int32_t *stop = nullptr, double *epartial = nullptr) {
+    apply_mm_cfg<T>(H, mm_config(H, R), X, Y, ldr, R, E, rho, rho_s, partial, s, stop, epartial);
 }
 
 }  // namespace
@@ -851,17 +874,20 @@ void mm_apply(const rad_hmat *H, const void *X, void *Y, int64_t ldr, int64_t R,
 }
 
 // one Jacobi iteration: B_new = E + rho * (F-hat B_old), norms[r] = ||B_new - B_old||^2;
-// with stop given, every kernel returns at once while *stop is set
+// with stop given, every kernel returns at once while *stop is set; with
+// enorms given, also enorms[r] = ||E_r||^2 (from the same pass over E)
 void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
-                    int64_t ldr, int64_t R, double *norms, hipStream_t s, const int32_t *stop) {
+                    int64_t ldr, int64_t R, double *norms, hipStream_t s, const int32_t *stop, double *enorms) {
     double *part = (double *)H->w_red.p;
+    double *epart = enorms ? H->w_ered.p : nullptr;
     if (H->dtype == RAD_F64)
         apply_mm_t<double>(H, (const double *)Bold, (double *)Bnew, ldr, (int)R, (const double *)E,
-                           (const double *)rho, rho_scalar, part, s, stop);
+                           (const double *)rho, rho_scalar, part, s, stop, epart);
     else
         apply_mm_t<float>(H, (const float *)Bold, (float *)Bnew, ldr, (int)R, (const float *)E, (const float *)rho,
-                          (float)rho_scalar, part, s, stop);
+                          (float)rho_scalar, part, s, stop, epart);
     mm_reduce_cols(H, part, H->n_tiles, R, norms, s, stop);
+    if (enorms) mm_reduce_cols(H, epart, H->n_tiles, R, enorms, s, stop);
     RAD_HIP(hipGetLastError());
 }
 
@@ -907,12 +933,12 @@ void time_phases_t(const rad_hmat *H, int R, int nrep, hipStream_t s, double *ms
     }
     ms[2] = timed([&] {
         if (c.tn == 64)
-            tile_mm_launch<T, true, 64>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3, part, s);
+            tile_mm_launch<T, 1, 64>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3, part, s);
         else if (c.tn == 256 && sizeof(T) == 4)
-            tile_mm_launch<T, true, (sizeof(T) == 4 ? 256 : 128)>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3,
+            tile_mm_launch<T, 1, (sizeof(T) == 4 ? 256 : 128)>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3,
                                                                  part, s);
         else
-            tile_mm_launch<T, true, 128>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3, part, s);
+            tile_mm_launch<T, 1, 128>(H, c, X, Y, ldr, R, E, (const T *)nullptr, (T)0.3, part, s);
     });
     RAD_HIP(hipGetLastError());
     (void)hipEventDestroy(e0);
@@ -1054,6 +1080,12 @@ void conv_init(const double *enorm2, double rtol2, int64_t nc, double *thr, int3
 
 void conv_check(const double *dn, const double *thr, int64_t nc, int32_t *conv, int32_t *stop, hipStream_t s) {
     hipLaunchKernelGGL(k_conv_check, dim3(1), dim3(1024), 0, s, dn, thr, (int)nc, conv, stop);
+    RAD_HIP(hipGetLastError());
+}
+
+void conv_first(const double *enorm2, double rtol2, const double *dn, int64_t nc, double *thr, int32_t *conv,
+                int32_t *stop, hipStream_t s) {
+    hipLaunchKernelGGL(k_conv_first, dim3(1), dim3(1024), 0, s, enorm2, rtol2, dn, (int)nc, thr, conv, stop);
     RAD_HIP(hipGetLastError());
 }
 

@@ -65,10 +65,11 @@ struct EpiRegs {
     }
 };
 
-template <class T, bool kFused, int TM, int TN, int LDC>
+// kNormE (with kFused): also the per-column partial sums of E^2 into epartial
+template <class T, bool kFused, int TM, int TN, int LDC, bool kNormE = false>
 __device__ __forceinline__ void tile_epilogue(const T (*sC)[LDC], void *smem, int tile, int64_t tile0, int r0,
                                               int64_t ldr, int R, int64_t N, T *Y, const T *E, const T *X,
-                                              const T *rho, T rho_s, double *partial) {
+                                              const T *rho, T rho_s, double *partial, double *epartial = nullptr) {
     constexpr int CT = TN / 4;            // threads per row, four columns each
     constexpr int RS = 256 / CT;          // row groups
     constexpr int NQ = TM / RS;           // rows per thread
@@ -79,6 +80,7 @@ __device__ __forceinline__ void tile_epilogue(const T (*sC)[LDC], void *smem, in
     const int rsub = t / CT;              // rows rsub, rsub + RS, ...
     const int col = r0 + c4;
     double d2[4] = {0.0, 0.0, 0.0, 0.0};
+    double e2[4] = {0.0, 0.0, 0.0, 0.0};
     const bool full = col + 3 < R;
     // rows rsub + RS q in groups of four: all loads of a group first, then
     // the arithmetic and the stores
@@ -99,6 +101,7 @@ __device__ __forceinline__ void tile_epilogue(const T (*sC)[LDC], void *smem, in
                         T bn = cur.ev[qq][u] + rh * y[u];
                         double d = (double)bn - (double)cur.bo[qq][u];
                         if (col + u < R) d2[u] += d * d;
+                        if constexpr (kNormE) e2[u] += (double)cur.ev[qq][u] * (double)cur.ev[qq][u];
                         y[u] = bn;
                     }
                 }
@@ -129,6 +132,17 @@ __device__ __forceinline__ void tile_epilogue(const T (*sC)[LDC], void *smem, in
             double sum = 0.0;
             for (int q = 0; q < RS; ++q) sum += red[q * TN + t];
             if (r0 + t < R) partial[(int64_t)tile * R + r0 + t] = sum;
+        }
+        if constexpr (kNormE) {
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 4; ++u) red[rsub * TN + c4 + u] = e2[u];
+            __syncthreads();
+            if (t < TN) {
+                double sum = 0.0;
+                for (int q = 0; q < RS; ++q) sum += red[q * TN + t];
+                if (r0 + t < R) epartial[(int64_t)tile * R + r0 + t] = sum;
+            }
         }
     }
 }

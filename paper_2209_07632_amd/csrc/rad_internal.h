@@ -225,6 +225,8 @@ struct rad_hmat {
         double rho_s;
         double *hn;
         const int32_t *stop;
+        bool first;
+        double rtol2;
         hipGraph_t g;
         hipGraphExec_t ex;
     };
@@ -246,6 +248,7 @@ struct rad_hmat {
     rad::DevBuf<double> w_norms;
     rad::DevBuf<int32_t> w_flags;         // per-column choices of warm-started solves
     rad::DevBuf<double> w_thr;            // per-column stopping thresholds of a solve
+    rad::DevBuf<double> w_ered;           // per-tile partial sums of E^2 (first iteration)
     rad::DevBuf<int32_t> w_conv;          // per-column "met rtol", then the stop flag
 
     // group of independent matrices (block diagonal): instance k owns rows
@@ -366,7 +369,8 @@ void mm_from_rmajor(const rad_hmat *H, const void *src, int64_t ldr, bool permut
 void mm_apply(const rad_hmat *H, const void *X, void *Y, int64_t ldr, int64_t R, hipStream_t s);
 void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, double *out, hipStream_t s);
 void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
-                    int64_t ldr, int64_t R, double *norms, hipStream_t s, const int32_t *stop = nullptr);
+                    int64_t ldr, int64_t R, double *norms, hipStream_t s, const int32_t *stop = nullptr,
+                    double *enorms = nullptr);
 size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R);
 rad::MmConfig mm_config(const rad_hmat *H, int64_t R);
 void mm_prepare_schedule(rad_hmat *H);
@@ -381,6 +385,9 @@ void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_
 void conv_init(const double *enorm2, double rtol2, int64_t nc, double *thr, int32_t *conv, int32_t *stop,
                hipStream_t s);
 void conv_check(const double *dn, const double *thr, int64_t nc, int32_t *conv, int32_t *stop, hipStream_t s);
+// first iteration: thresholds from enorm2 (as conv_init), then the test (as conv_check)
+void conv_first(const double *enorm2, double rtol2, const double *dn, int64_t nc, double *thr, int32_t *conv,
+                int32_t *stop, hipStream_t s);
 
 // 16-bit operator (lowp_kernels.hip)
 void ir_select(const rad_hmat *H, double *B64, float *B32, float *r, const float *E, const int32_t *flag, int64_t ldr,
