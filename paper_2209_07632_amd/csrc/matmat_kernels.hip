@@ -651,7 +651,7 @@ __global__ void __launch_bounds__(256) k_from_rmajor(const int32_t *perm, const 
 // the same fixed order for a matrix and for each instance of a group.  The loads
 // of a class are independent of its additions, so eight are kept in flight.
 __global__ void __launch_bounds__(256) k_reduce_parts(const double *partial, const int32_t *inst_tile, int nparts,
-                                                      int R, double *out, const int32_t *stop) {
+                                                      int R, double *out, const int32_t *stop, ConvTest test) {
     if (stop && *stop) return;
     const int k = blockIdx.y;
     const int cl = threadIdx.x & 15, g = threadIdx.x >> 4;
@@ -678,47 +678,50 @@ __global__ void __launch_bounds__(256) k_reduce_parts(const double *partial, con
         for (int q = 0; q < 16; ++q) tot += red[q][cl];
         out[(int64_t)k * R + r] = tot;
     }
+    if (test.mode == 0) return;
+    // the last workgroup to finish runs the stopping test over all columns
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(test.counter, 1) == (int)(gridDim.x * gridDim.y) - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    int all = 1;
+    for (int c = threadIdx.x; c < test.nc; c += 256) {
+        int v;
+        if (test.mode == 1) {
+            v = test.conv[c] | (out[c] <= test.thr[c] ? 1 : 0);
+        } else {
+            const double e = out[c];
+            const double th = e > 0 ? test.rtol2 * e : test.rtol2;
+            test.thr[c] = th;
+            v = test.dn[c] <= th ? 1 : 0;
+        }
+        test.conv[c] = v;
+        all &= v;
+    }
+    all = __syncthreads_and(all);
+    if (threadIdx.x == 0) {
+        *test.stop = all;
+        *test.counter = 0;
+    }
 }
 
+// thr[c] = rtol2 enorm2[c] (rtol2 when 0); conv[c], the stop flag and the
+// stopping test's counter cleared
 __global__ void __launch_bounds__(256) k_conv_init(const double *enorm2, double rtol2, int nc, double *thr,
-                                                   int32_t *conv, int32_t *stop) {
+                                                   int32_t *conv, int32_t *stop, int32_t *counter) {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c < nc) {
         const double e = enorm2[c];
         thr[c] = e > 0 ? rtol2 * e : rtol2;
         conv[c] = 0;
     }
-    if (c == 0) *stop = 0;
-}
-
-// one workgroup; the branch on *stop is uniform
-__global__ void __launch_bounds__(1024) k_conv_check(const double *dn, const double *thr, int nc, int32_t *conv,
-                                                     int32_t *stop) {
-    if (*stop) return;
-    int all = 1;
-    for (int c = threadIdx.x; c < nc; c += 1024) {
-        const int v = conv[c] | (dn[c] <= thr[c] ? 1 : 0);
-        conv[c] = v;
-        all &= v;
+    if (c == 0) {
+        *stop = 0;
+        *counter = 0;
     }
-    all = __syncthreads_and(all);
-    if (threadIdx.x == 0) *stop = all;
-}
-
-// one workgroup: thresholds as k_conv_init, then the test as k_conv_check
-__global__ void __launch_bounds__(1024) k_conv_first(const double *enorm2, double rtol2, const double *dn, int nc,
-                                                     double *thr, int32_t *conv, int32_t *stop) {
-    int all = 1;
-    for (int c = threadIdx.x; c < nc; c += 1024) {
-        const double e = enorm2[c];
-        const double th = e > 0 ? rtol2 * e : rtol2;
-        thr[c] = th;
-        const int v = dn[c] <= th ? 1 : 0;
-        conv[c] = v;
-        all &= v;
-    }
-    all = __syncthreads_and(all);
-    if (threadIdx.x == 0) *stop = all;
 }
 
 // partial[tile * R + r] = sum over the tile's 64 facets of E^2 (R-major).
@@ -875,9 +878,11 @@ void mm_apply(const rad_hmat *H, const void *X, void *Y, int64_t ldr, int64_t R,
 
 // one Jacobi iteration: B_new = E + rho * (F-hat B_old), norms[r] = ||B_new - B_old||^2;
 // with stop given, every kernel returns at once while *stop is set; with
-// enorms given, also enorms[r] = ||E_r||^2 (from the same pass over E)
+// enorms given, also enorms[r] = ||E_r||^2 (from the same pass over E); with
+// test given, the last reduction ends with the device-side stopping test
 void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
-                    int64_t ldr, int64_t R, double *norms, hipStream_t s, const int32_t *stop, double *enorms) {
+                    int64_t ldr, int64_t R, double *norms, hipStream_t s, const int32_t *stop, double *enorms,
+                    const ConvTest *test) {
     double *part = (double *)H->w_red.p;
     double *epart = enorms ? H->w_ered.p : nullptr;
     if (H->dtype == RAD_F64)
@@ -886,8 +891,9 @@ void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rh
     else
         apply_mm_t<float>(H, (const float *)Bold, (float *)Bnew, ldr, (int)R, (const float *)E, (const float *)rho,
                           (float)rho_scalar, part, s, stop, epart);
-    mm_reduce_cols(H, part, H->n_tiles, R, norms, s, stop);
-    if (enorms) mm_reduce_cols(H, epart, H->n_tiles, R, enorms, s, stop);
+    // the stopping test rides on the last reduction of the iteration
+    mm_reduce_cols(H, part, H->n_tiles, R, norms, s, stop, enorms ? nullptr : test);
+    if (enorms) mm_reduce_cols(H, epart, H->n_tiles, R, enorms, s, stop, test);
     RAD_HIP(hipGetLastError());
 }
 
@@ -1064,28 +1070,19 @@ std::vector<std::pair<MmConfig, double>> mm_autotune(rad_hmat *H, int64_t R, int
 }
 
 void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s,
-                    const int32_t *stop) {
+                    const int32_t *stop, const ConvTest *test) {
     const bool grp = H->n_inst > 1;
+    ConvTest none{};
     hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((R + 15) / 16), (unsigned)H->n_inst), dim3(256), 0, s,
-                       partial, grp ? (const int32_t *)H->d_inst_tile.p : nullptr, nparts, (int)R, out, stop);
+                       partial, grp ? (const int32_t *)H->d_inst_tile.p : nullptr, nparts, (int)R, out, stop,
+                       test ? *test : none);
     RAD_HIP(hipGetLastError());
 }
 
 void conv_init(const double *enorm2, double rtol2, int64_t nc, double *thr, int32_t *conv, int32_t *stop,
-               hipStream_t s) {
+               int32_t *counter, hipStream_t s) {
     hipLaunchKernelGGL(k_conv_init, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, enorm2, rtol2, (int)nc, thr,
-                       conv, stop);
-    RAD_HIP(hipGetLastError());
-}
-
-void conv_check(const double *dn, const double *thr, int64_t nc, int32_t *conv, int32_t *stop, hipStream_t s) {
-    hipLaunchKernelGGL(k_conv_check, dim3(1), dim3(1024), 0, s, dn, thr, (int)nc, conv, stop);
-    RAD_HIP(hipGetLastError());
-}
-
-void conv_first(const double *enorm2, double rtol2, const double *dn, int64_t nc, double *thr, int32_t *conv,
-                int32_t *stop, hipStream_t s) {
-    hipLaunchKernelGGL(k_conv_first, dim3(1), dim3(1024), 0, s, enorm2, rtol2, dn, (int)nc, thr, conv, stop);
+                       conv, stop, counter);
     RAD_HIP(hipGetLastError());
 }
 
