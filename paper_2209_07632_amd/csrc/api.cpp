@@ -560,16 +560,22 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                     enqueue_iteration(H, a, s);
                 RAD_HIP(hipEventRecord(H->ev[kk % 2], s));
             };
+            // Iteration k + 1 is normally queued behind the one in flight.  When
+            // every open column's ratio q = |dB|^2 / thr, extrapolated
+            // geometrically from its last two iterations, is predicted to fall
+            // below 1/4 in the iteration in flight, nothing is queued behind it
+            // (a wrong guess costs one host round trip, never a result).
             int queued = k;
-            if (!done && k < o.max_iter) enqueue(++queued);
+            bool predicted = false;
+            std::vector<double> q_prev(NC, 0.0);
             while (!done && k < o.max_iter) {
-                // iteration k + 1 is in flight; queue k + 2 behind it, then test k + 1
-                if (queued < o.max_iter) enqueue(++queued);
+                while (queued < std::min(k + 2, o.max_iter) && !(queued == k + 1 && predicted)) enqueue(++queued);
                 RAD_HIP(hipEventSynchronize(H->ev[(k + 1) % 2]));
                 ++k;
                 take_enorm();
                 const double *d2 = slot[k % 2];
                 done = true;
+                predicted = k >= 2;
                 for (int64_t c = 0; c < NC; ++c) {
                     const double d = std::sqrt(d2[c]);
                     rel[c] = enorm[c] > 0 ? d / enorm[c] : d;
@@ -578,7 +584,12 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                         RAD_REQUIRE(false, "solve produced non-finite values");
                     }
                     if (iters[c] < 0 && d2[c] <= thr[c]) iters[c] = k;
-                    if (iters[c] < 0) done = false;
+                    if (iters[c] < 0) {
+                        done = false;
+                        const double q = d2[c] / thr[c];
+                        if (!(q_prev[c] > 0 && q * q <= 0.25 * q_prev[c])) predicted = false;
+                    }
+                    q_prev[c] = d2[c] / thr[c];
                 }
             }
         }
