@@ -294,8 +294,9 @@ struct WideStage {
     }
 };
 
+// (three workgroups per CU fit its LDS; the register budget is held to match)
 template <bool kFused>
-__global__ void __launch_bounds__(256) k_tile_mm16w(const TileInfo *tiles, const int32_t *brow, const __bf16 *vals16,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_tile_mm16w(const TileInfo *tiles, const int32_t *brow, const __bf16 *vals16,
                                                      const __bf16 *X16, const __bf16 *T16, int64_t ld16,
                                                      const float *X, int64_t ldr, int R, int64_t N, float *Y,
                                                      const float *E, const float *rho, float rho_s,
