@@ -283,7 +283,7 @@ def run_batch(args):
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
     else:
         roof = {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak}
-    roof.update({"traffic": None, "kernel": f"k_tile_mm<float, true, {tune['tn']}> over all instances "
+    roof.update({"traffic": None, "kernel": f"k_tile_mm<float, 1, {tune['tn']}> over all instances "
                                             f"({'persistent' if tune['persistent'] else 'flat'} grid)",
                  "ms_per_launch": ph[2], "flops_per_launch": flops, "bytes_per_launch": bytes_,
                  "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge, "tflops": tf, "gbs": gbs})
@@ -553,7 +553,7 @@ def main():
     else:
         roof = {"bound": "mfma", "achieved": p2_tf, "peak": peak, "unit": "TFLOP/s", "frac": p2_tf / peak}
     roof.update({"traffic": measured_traffic(args.dtype, R, tune["tn"]),
-                 "kernel": f"k_tile_mm<{'double' if args.dtype == 'f64' else 'float'}, true, {tune['tn']}> "
+                 "kernel": f"k_tile_mm<{'double' if args.dtype == 'f64' else 'float'}, 1, {tune['tn']}> "
                            f"(expansion + near field + fused Jacobi update, "
                            f"{'persistent' if tune['persistent'] else 'flat'} grid)",
                  "ms_per_launch": ph[2], "flops_per_launch": p2_flops, "bytes_per_launch": p2_bytes,

@@ -346,9 +346,9 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         // Multi-RHS Jacobi tested every iteration runs one iteration ahead of
         // the host; the device skips that iteration once every column has met
         // rtol (the same test in the same arithmetic as the host's below).
-        // From a cold start the first iteration also sums ||E||^2.
+        // The first iteration (from E, or from the warm guess) also sums ||E||^2.
         const bool ahead = mm && !o.refine && o.check_every == 1;
-        const bool fused_en = ahead && !o.warm;
+        const bool fused_en = ahead;
         if (fused_en)
             ;
         else if (mm)
@@ -377,7 +377,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             }
             have_en = true;
         };
-        if (!ahead || o.warm) {
+        if (!fused_en) {
             RAD_HIP(hipStreamSynchronize(s));
             take_enorm();
         }
@@ -508,9 +508,10 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             else
                 mv_gather(H, B, ldb, G, N, R, s);
             std::vector<double> nw(R), nc(R, 0.0);
-            IterArgs aw{mm, false, R, ld, Ein, rho_t, G, P[1], rho_scalar};
+            IterArgs aw{mm, false, R, ld, Ein, rho_t, G, P[1], rho_scalar, nullptr, nullptr, fused_en, rtol2};
             enqueue_iteration(H, aw, s);
             RAD_HIP(hipStreamSynchronize(s));
+            take_enorm();
             std::copy(H->h_norms, H->h_norms + R, nw.begin());
             // a guess whose first change already meets rtol is kept without the
             // comparison; otherwise one iteration from E decides
