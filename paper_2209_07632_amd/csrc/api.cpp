@@ -30,8 +30,8 @@ void alloc_workspace(rad_hmat *H) {
     H->w_norms.alloc(3 * nc);
     H->w_flags.alloc(nc);
     H->w_thr.alloc(nc);
-    H->w_conv.alloc(nc + 2);   // flags, stop, the stopping test's counter (kept at zero between tests)
-    RAD_HIP(hipMemset(H->w_conv.p, 0, (nc + 2) * sizeof(int32_t)));
+    H->w_conv.alloc(nc + 1);   // per-column flags, then the stop flag
+    RAD_HIP(hipMemset(H->w_conv.p, 0, (nc + 1) * sizeof(int32_t)));
     if (H->max_rhs >= kMfmaMinRhs && H->n_tiles > 0) H->w_ered.alloc((size_t)H->n_tiles * (size_t)H->max_rhs);
     if (H->max_rhs >= kMfmaMinRhs && H->n_parts > 0)
         H->w_part.alloc((size_t)H->n_parts * mm_part_rows() * ldr * s);
@@ -77,7 +77,7 @@ static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t 
         const int64_t nc = a.R * H->n_inst, nc_all = (int64_t)H->max_rhs * H->n_inst;
         double *en = a.first ? H->w_norms.p : nullptr;
         int32_t *conv = H->w_conv.p;
-        const ConvTest test{a.first ? 2 : 1, (int)nc, dn, H->w_thr.p, a.rtol2, conv, conv + nc_all, conv + nc_all + 1};
+        const ConvTest test{a.first ? 2 : 1, (int)nc, dn, H->w_thr.p, a.rtol2, conv, conv + nc_all};
         mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s, a.stop, en,
                        (a.first || a.stop) ? &test : nullptr);
         if (a.first)
@@ -134,6 +134,16 @@ static hipGraphExec_t iteration_graph(rad_hmat *H, const IterArgs &a) {
 
 
 static void check_hmat(const rad_hmat *H) { RAD_REQUIRE(H != nullptr, "null matrix handle"); }
+
+// Waits for e by polling: the solve waits for every iteration's norms, and a
+// poll returns as soon as they have landed (no wake-up of a blocked thread).
+static void wait_event(hipEvent_t e) {
+    for (;;) {
+        const hipError_t r = hipEventQuery(e);
+        if (r == hipSuccess) return;
+        if (r != hipErrorNotReady) RAD_HIP(r);
+    }
+}
 
 }  // namespace rad
 
@@ -359,7 +369,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         double *h_en = H->h_norms + 2 * nc_all;
         int32_t *conv_d = H->w_conv.p, *stop_d = H->w_conv.p + nc_all;
         const double rtol2 = o.rtol * o.rtol;
-        if (ahead && !fused_en) conv_init(enorm_d, rtol2, NC, H->w_thr.p, conv_d, stop_d, stop_d + 1, s);
+        if (ahead && !fused_en) conv_init(enorm_d, rtol2, NC, H->w_thr.p, conv_d, stop_d, s);
         if (!fused_en) RAD_HIP(hipMemcpyAsync(h_en, enorm_d, NC * sizeof(double), hipMemcpyDeviceToHost, s));
         // column c has met rtol when its squared change (or residual) is <= thr[c]
         std::vector<double> enorm(NC), thr(NC), dn(NC);
@@ -571,7 +581,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             std::vector<double> q_prev(NC, 0.0);
             while (!done && k < o.max_iter) {
                 while (queued < std::min(k + 2, o.max_iter) && !(queued == k + 1 && predicted)) enqueue(++queued);
-                RAD_HIP(hipEventSynchronize(H->ev[(k + 1) % 2]));
+                wait_event(H->ev[(k + 1) % 2]);
                 ++k;
                 take_enorm();
                 const double *d2 = slot[k % 2];

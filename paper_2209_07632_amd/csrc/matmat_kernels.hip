@@ -651,7 +651,7 @@ __global__ void __launch_bounds__(256) k_from_rmajor(const int32_t *perm, const 
 // the same fixed order for a matrix and for each instance of a group.  The loads
 // of a class are independent of its additions, so eight are kept in flight.
 __global__ void __launch_bounds__(256) k_reduce_parts(const double *partial, const int32_t *inst_tile, int nparts,
-                                                      int R, double *out, const int32_t *stop, ConvTest test) {
+                                                      int R, double *out, const int32_t *stop) {
     if (stop && *stop) return;
     const int k = blockIdx.y;
     const int cl = threadIdx.x & 15, g = threadIdx.x >> 4;
@@ -678,17 +678,14 @@ __global__ void __launch_bounds__(256) k_reduce_parts(const double *partial, con
         for (int q = 0; q < 16; ++q) tot += red[q][cl];
         out[(int64_t)k * R + r] = tot;
     }
-    if (test.mode == 0) return;
-    // the last workgroup to finish runs the stopping test over all columns
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(test.counter, 1) == (int)(gridDim.x * gridDim.y) - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+// The stopping test on the sums of the reduction before it (one workgroup;
+// returns at once while *stop is set, as the kernels of a skipped iteration do)
+__global__ void __launch_bounds__(1024) k_conv_test(const double *out, ConvTest test) {
+    if (test.mode == 1 && *test.stop) return;
     int all = 1;
-    for (int c = threadIdx.x; c < test.nc; c += 256) {
+    for (int c = threadIdx.x; c < test.nc; c += 1024) {
         int v;
         if (test.mode == 1) {
             v = test.conv[c] | (out[c] <= test.thr[c] ? 1 : 0);
@@ -702,26 +699,19 @@ __global__ void __launch_bounds__(256) k_reduce_parts(const double *partial, con
         all &= v;
     }
     all = __syncthreads_and(all);
-    if (threadIdx.x == 0) {
-        *test.stop = all;
-        *test.counter = 0;
-    }
+    if (threadIdx.x == 0) *test.stop = all;
 }
 
-// thr[c] = rtol2 enorm2[c] (rtol2 when 0); conv[c], the stop flag and the
-// stopping test's counter cleared
+// thr[c] = rtol2 enorm2[c] (rtol2 when 0); conv[c] and the stop flag cleared
 __global__ void __launch_bounds__(256) k_conv_init(const double *enorm2, double rtol2, int nc, double *thr,
-                                                   int32_t *conv, int32_t *stop, int32_t *counter) {
+                                                   int32_t *conv, int32_t *stop) {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c < nc) {
         const double e = enorm2[c];
         thr[c] = e > 0 ? rtol2 * e : rtol2;
         conv[c] = 0;
     }
-    if (c == 0) {
-        *stop = 0;
-        *counter = 0;
-    }
+    if (c == 0) *stop = 0;
 }
 
 // partial[tile * R + r] = sum over the tile's 64 facets of E^2 (R-major).
@@ -1072,17 +1062,19 @@ std::vector<std::pair<MmConfig, double>> mm_autotune(rad_hmat *H, int64_t R, int
 void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s,
                     const int32_t *stop, const ConvTest *test) {
     const bool grp = H->n_inst > 1;
-    ConvTest none{};
     hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((R + 15) / 16), (unsigned)H->n_inst), dim3(256), 0, s,
-                       partial, grp ? (const int32_t *)H->d_inst_tile.p : nullptr, nparts, (int)R, out, stop,
-                       test ? *test : none);
+                       partial, grp ? (const int32_t *)H->d_inst_tile.p : nullptr, nparts, (int)R, out, stop);
+    if (test) {
+        RAD_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_conv_test, dim3(1), dim3(1024), 0, s, (const double *)out, *test);
+    }
     RAD_HIP(hipGetLastError());
 }
 
 void conv_init(const double *enorm2, double rtol2, int64_t nc, double *thr, int32_t *conv, int32_t *stop,
-               int32_t *counter, hipStream_t s) {
+               hipStream_t s) {
     hipLaunchKernelGGL(k_conv_init, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, enorm2, rtol2, (int)nc, thr,
-                       conv, stop, counter);
+                       conv, stop);
     RAD_HIP(hipGetLastError());
 }
 

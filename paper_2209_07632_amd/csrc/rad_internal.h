@@ -368,9 +368,10 @@ void mm_from_rmajor(const rad_hmat *H, const void *src, int64_t ldr, bool permut
                     hipStream_t s);
 void mm_apply(const rad_hmat *H, const void *X, void *Y, int64_t ldr, int64_t R, hipStream_t s);
 void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, double *out, hipStream_t s);
-// Device-side stopping test of a Jacobi solve, run by the last workgroup of a
-// column reduction to finish (counter: a device int that the test resets):
-// mode 1 (out = squared changes): conv[c] |= out[c] <= thr[c];
+// Device-side stopping test of a Jacobi solve, run on the sums of a column
+// reduction (out) right after it:
+// mode 1 (out = squared changes): conv[c] |= out[c] <= thr[c] (skipped while
+//        *stop is set);
 // mode 2 (out = ||E||^2, dn given): thr[c] = rtol2 out[c] (rtol2 when 0),
 //        conv[c] = dn[c] <= thr[c];
 // then stop = all(conv[0..nc)).
@@ -380,7 +381,7 @@ struct ConvTest {
     const double *dn;
     double *thr;
     double rtol2;
-    int32_t *conv, *stop, *counter;
+    int32_t *conv, *stop;
 };
 
 void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
@@ -394,9 +395,9 @@ void mm_prepare_schedule(rad_hmat *H);
 std::vector<std::pair<rad::MmConfig, double>> mm_autotune(rad_hmat *H, int64_t R, int nrep, hipStream_t s);
 void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_t R, double *out, hipStream_t s,
                     const int32_t *stop = nullptr, const ConvTest *test = nullptr);
-// thr[c] = rtol2 enorm2[c] (rtol2 when 0); clears conv[0..nc), stop and counter
+// thr[c] = rtol2 enorm2[c] (rtol2 when 0); clears conv[0..nc) and stop
 void conv_init(const double *enorm2, double rtol2, int64_t nc, double *thr, int32_t *conv, int32_t *stop,
-               int32_t *counter, hipStream_t s);
+               hipStream_t s);
 
 // 16-bit operator (lowp_kernels.hip)
 void ir_select(const rad_hmat *H, double *B64, float *B32, float *r, const float *E, const int32_t *flag, int64_t ldr,
