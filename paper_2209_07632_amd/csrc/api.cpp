@@ -43,7 +43,8 @@ void alloc_workspace(rad_hmat *H) {
         H->w_x16.alloc((size_t)H->N * ld16);
         H->w_t16.alloc((size_t)std::max(H->t_ld, 4) * ld16);
     }
-    RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * 3 * nc, hipHostMallocDefault));
+    RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * 3 * nc, hipHostMallocMapped));
+    RAD_HIP(hipHostGetDevicePointer((void **)&H->d_hnorms, H->h_norms, 0));
     for (auto &e : H->ev) RAD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     RAD_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
     if (H->n_tiles > 0) mm_prepare_schedule(H);
@@ -53,9 +54,10 @@ void alloc_workspace(rad_hmat *H) {
 // the squared column changes in w_norms[max_rhs...], copied to pinned memory
 // (hn, else the first slot).  With stop set (multi-RHS path only) every kernel
 // returns at once while the device flag is set, and the iteration ends with
-// the device-side stopping test.  first (multi-RHS, B_old = E): the same pass
-// also sums ||E||^2 per column (to w_norms and the pinned slot after the two
-// change slots), and the test starts from thresholds rtol2 ||E||^2.
+// the device-side stopping test, which itself writes the changes to the
+// pinned slot.  first (multi-RHS, B_old = E): the same pass also sums
+// ||E||^2 per column (to w_norms and the pinned slot after the two change
+// slots), and the test starts from thresholds rtol2 ||E||^2.
 struct IterArgs {
     bool mm;
     bool lowp;
@@ -77,11 +79,16 @@ static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t 
         const int64_t nc = a.R * H->n_inst, nc_all = (int64_t)H->max_rhs * H->n_inst;
         double *en = a.first ? H->w_norms.p : nullptr;
         int32_t *conv = H->w_conv.p;
-        const ConvTest test{a.first ? 2 : 1, (int)nc, dn, H->w_thr.p, a.rtol2, conv, conv + nc_all};
-        mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s, a.stop, en,
-                       (a.first || a.stop) ? &test : nullptr);
-        if (a.first)
-            RAD_HIP(hipMemcpyAsync(H->h_norms + 2 * nc_all, en, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+        if (a.first || a.stop) {
+            // the stopping test also hands the norms to the host (mapped pinned memory)
+            double *hn = a.hn ? a.hn : H->h_norms;
+            ConvTest test{a.first ? 2 : 1, (int)nc, dn, H->w_thr.p, a.rtol2, conv, conv + nc_all};
+            test.hdn = H->d_hnorms + (hn - H->h_norms);
+            if (a.first) test.hen = H->d_hnorms + 2 * nc_all;
+            mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s, a.stop, en, &test);
+            return;
+        }
+        mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s, nullptr, en, nullptr);
     } else {
         mv_apply(H, a.Bold, a.ld, H->w_y.p, a.ld, a.R, s);
         solve_update(H, a.E, a.rho, a.rho_s, H->w_y.p, a.Bold, a.Bnew, a.ld, a.R, dn, s);

@@ -688,12 +688,16 @@ __global__ void __launch_bounds__(1024) k_conv_test(const double *out, ConvTest 
     for (int c = threadIdx.x; c < test.nc; c += 1024) {
         int v;
         if (test.mode == 1) {
-            v = test.conv[c] | (out[c] <= test.thr[c] ? 1 : 0);
+            const double d = out[c];
+            v = test.conv[c] | (d <= test.thr[c] ? 1 : 0);
+            if (test.hdn) test.hdn[c] = d;
         } else {
-            const double e = out[c];
+            const double e = out[c], d = test.dn[c];
             const double th = e > 0 ? test.rtol2 * e : test.rtol2;
             test.thr[c] = th;
-            v = test.dn[c] <= th ? 1 : 0;
+            v = d <= th ? 1 : 0;
+            if (test.hdn) test.hdn[c] = d;
+            if (test.hen) test.hen[c] = e;
         }
         test.conv[c] = v;
         all &= v;

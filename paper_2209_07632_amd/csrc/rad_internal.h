@@ -233,6 +233,7 @@ struct rad_hmat {
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
     double *h_norms = nullptr;   // pinned: two slots of per-column changes, then ||E||^2
+    double *d_hnorms = nullptr;  // the same memory as the device addresses it
     hipEvent_t ev[2] = {nullptr, nullptr};   // ends of the iterations in flight
     ~rad_hmat();
 
@@ -374,7 +375,8 @@ void mm_col_norms2(const rad_hmat *H, const void *E, int64_t ldr, int64_t R, dou
 //        *stop is set);
 // mode 2 (out = ||E||^2, dn given): thr[c] = rtol2 out[c] (rtol2 when 0),
 //        conv[c] = dn[c] <= thr[c];
-// then stop = all(conv[0..nc)).
+// then stop = all(conv[0..nc)).  hdn (and hen, mode 2), when given: pinned
+// host memory that receives the squared changes (and ||E||^2) directly.
 struct ConvTest {
     int mode;
     int nc;
@@ -382,6 +384,7 @@ struct ConvTest {
     double *thr;
     double rtol2;
     int32_t *conv, *stop;
+    double *hdn = nullptr, *hen = nullptr;
 };
 
 void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
