@@ -14,6 +14,7 @@ Prints one JSON line.  See the design doc for the roofline accounting.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -505,11 +506,15 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup done, iters {int(info['total_iters'])}; ms/step with graphs {mode_ms[True]:.3f}, "
         f"direct launches {mode_ms[False]:.3f}: use_graph={use_graph}")
+    # (Python's collector is paused over the timed steps, as timeit does)
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         info = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    gc.enable()
     ms_per_step = 1e3 * dt / args.steps
     solves_per_s = R * args.steps / dt
     iters = int(info["total_iters"])
