@@ -366,12 +366,12 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         // The first iteration (from E, or from the warm guess) also sums ||E||^2.
         const bool ahead = mm && !o.refine && o.check_every == 1;
         const bool fused_en = ahead;
-        if (fused_en)
-            ;
-        else if (mm)
-            mm_col_norms2(H, Ein, ld, R, enorm_d, s);
-        else
-            col_norms2(H, Ein, N, R, enorm_d, s);
+        if (!fused_en) {
+            if (mm)
+                mm_col_norms2(H, Ein, ld, R, enorm_d, s);
+            else
+                col_norms2(H, Ein, N, R, enorm_d, s);
+        }
         const int64_t nc_all = (int64_t)H->max_rhs * H->n_inst;
         double *h_en = H->h_norms + 2 * nc_all;
         int32_t *conv_d = H->w_conv.p, *stop_d = H->w_conv.p + nc_all;
@@ -514,9 +514,9 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
             // and its iterate becomes B^1 in P[0]
             // (an R-major B on the multi-RHS path is read in place)
             void *G = (mm && rmaj) ? B : H->w_q2.p, *C1 = H->w_q1.p;
-            if (mm && rmaj)
-                ;
-            else if (mm)
+            if (mm && rmaj) {
+                // read in place
+            } else if (mm)
                 mm_to_rmajor(H, B, ldb, o.order == RAD_ORDER_ORIGINAL, G, ld, R, s);
             else if (rmaj)
                 mm_from_rmajor(H, B, ldb, false, G, N, R, s);
