@@ -271,13 +271,23 @@ constexpr int WN = 256, WKC = 32, WLDK = WKC + 8;
 struct WideStage {
     bf16x8 a;          // panel: row t >> 2, k (t & 3) * 8 .. + 7
     bf16x8 b[4];       // operand rows 4 (t >> 5) + i, columns 8 (t & 31) .. + 7
-    __device__ __forceinline__ void fetch(const __bf16 *pan, const int32_t *brc, const __bf16 *X16,
-                                          const __bf16 *T16, int64_t ld16, int t) {
+    // the operand-row indices of this thread's four rows of a chunk (loaded a
+    // chunk ahead of their use, so that the dependent row loads do not wait)
+    struct Rows {
+        int32_t v[4];
+        __device__ __forceinline__ void load(const int32_t *brc, int t) {
+            const int kq = t >> 5;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = brc[4 * kq + i];
+        }
+    };
+    __device__ __forceinline__ void fetch(const __bf16 *pan, const Rows &rw, const __bf16 *X16, const __bf16 *T16,
+                                          int64_t ld16, int t) {
         a = *(const bf16x8 *)(pan + t * 8);
-        const int kq = t >> 5, c8 = (t & 31) * 8;
+        const int c8 = (t & 31) * 8;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int32_t v = brc[4 * kq + i];
+            const int32_t v = rw.v[i];
             const __bf16 *p = (v >= 0 ? X16 + (int64_t)v * ld16 : T16 + (int64_t)(-1 - v) * ld16) + c8;
             b[i] = c8 < ld16 ? *(const bf16x8 *)p : bf16x8{};
         }
@@ -331,19 +341,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
         const __bf16 *pan = vals16 + ti.panel_off;
         const int32_t *br = brow + ti.brow_off;
         WideStage s0, s1;
-        s0.fetch(pan, br, X16, T16, ld16, t);
-        if (WKC < ti.kpad) s1.fetch(pan + (int64_t)WKC * TM, br + WKC, X16, T16, ld16, t);
-        for (int kb = 0; kb < ti.kpad; kb += 2 * WKC) {
+        WideStage::Rows rw0, rw1;   // row indices of the chunks s0 / s1 fetch next
+        const int kp = ti.kpad;
+        rw0.load(br, t);
+        if (WKC < kp) rw1.load(br + WKC, t);
+        s0.fetch(pan, rw0, X16, T16, ld16, t);
+        if (2 * WKC < kp) rw0.load(br + 2 * WKC, t);
+        if (WKC < kp) {
+            s1.fetch(pan + (int64_t)WKC * TM, rw1, X16, T16, ld16, t);
+            if (3 * WKC < kp) rw1.load(br + 3 * WKC, t);
+        }
+        for (int kb = 0; kb < kp; kb += 2 * WKC) {
             s0.commit(sA[0], sB[0], t);
             __syncthreads();
-            if (kb + 2 * WKC < ti.kpad)
-                s0.fetch(pan + (int64_t)(kb + 2 * WKC) * TM, br + kb + 2 * WKC, X16, T16, ld16, t);
+            if (kb + 2 * WKC < kp) {
+                s0.fetch(pan + (int64_t)(kb + 2 * WKC) * TM, rw0, X16, T16, ld16, t);
+                if (kb + 4 * WKC < kp) rw0.load(br + kb + 4 * WKC, t);
+            }
             mma(sA[0], sB[0]);
-            if (kb + WKC >= ti.kpad) break;
+            if (kb + WKC >= kp) break;
             s1.commit(sA[1], sB[1], t);
             __syncthreads();
-            if (kb + 3 * WKC < ti.kpad)
-                s1.fetch(pan + (int64_t)(kb + 3 * WKC) * TM, br + kb + 3 * WKC, X16, T16, ld16, t);
+            if (kb + 3 * WKC < kp) {
+                s1.fetch(pan + (int64_t)(kb + 3 * WKC) * TM, rw1, X16, T16, ld16, t);
+                if (kb + 5 * WKC < kp) rw1.load(br + kb + 5 * WKC, t);
+            }
             mma(sA[1], sB[1]);
         }
     }
