@@ -227,7 +227,16 @@ template <class T, int TN>
 struct PanelStage {
     T a[KC * TM / 256];
     T b[KC * TN / 256];
-    __device__ __forceinline__ void fetch(const T *pan, const int32_t *brc, const T *X, const T *Tb, int64_t ldr, int r0,
+    // the operand-row indices this thread gathers for a chunk (loaded a chunk
+    // ahead of their use, so that the dependent row loads do not wait)
+    struct Rows {
+        int32_t v[KC * TN / 1024];
+        __device__ __forceinline__ void load(const int32_t *brc, int t) {
+#pragma unroll
+            for (int q = 0; q < KC * TN / 1024; ++q) v[q] = brc[(t + q * 256) / (TN / 4)];
+        }
+    };
+    __device__ __forceinline__ void fetch(const T *pan, const Rows &rw, const T *X, const T *Tb, int64_t ldr, int r0,
                                           int R, int t) {
 #pragma unroll
         for (int q = 0; q < KC * TM / 1024; ++q) {
@@ -244,7 +253,7 @@ struct PanelStage {
         for (int q = 0; q < KC * TN / 1024; ++q) {
             int e = t + q * 256;
             int k = e / (TN / 4), c = (e - k * (TN / 4)) * 4;
-            int32_t v = brc[k];
+            int32_t v = rw.v[q];
             const T *p = (v >= 0 ? X + (int64_t)v * ldr : Tb + (int64_t)(-1 - v) * ldr) + r0 + c;
             T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
             if (r0 + c + 3 < R) {
@@ -513,20 +522,25 @@ __device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileI
         const T *pan = vals + ti.panel_off;
         const int32_t *br = brow + ti.brow_off;
         PanelStage<T, TN> st0, st1;
-        auto fetch = [&](PanelStage<T, TN> &st, int kb) {
-            st.fetch(pan + (int64_t)kb * TM, br + kb, X, Tb, ldr, r0, R, t);
+        // row indices of the chunks st0 / st1 fetch next
+        typename PanelStage<T, TN>::Rows rw0, rw1;
+        auto fetch = [&](PanelStage<T, TN> &st, typename PanelStage<T, TN>::Rows &rw, int kb) {
+            st.fetch(pan + (int64_t)kb * TM, rw, X, Tb, ldr, r0, R, t);
+            if (kb + 2 * KC < kend) rw.load(br + kb + 2 * KC, t);
         };
-        fetch(st0, 0);
-        if (KC < kend) fetch(st1, KC);
+        rw0.load(br, t);
+        if (KC < kend) rw1.load(br + KC, t);
+        fetch(st0, rw0, 0);
+        if (KC < kend) fetch(st1, rw1, KC);
         for (int kb = 0; kb < kend; kb += 2 * KC) {
             st0.commit(sA[0], sB[0], t);
             __syncthreads();
-            if (kb + 2 * KC < kend) fetch(st0, kb + 2 * KC);
+            if (kb + 2 * KC < kend) fetch(st0, rw0, kb + 2 * KC);
             acc.mma(sA[0], sB[0], lane, w);
             if (kb + KC >= kend) break;
             st1.commit(sA[1], sB[1], t);
             __syncthreads();
-            if (kb + 3 * KC < kend) fetch(st1, kb + 3 * KC);
+            if (kb + 3 * KC < kend) fetch(st1, rw1, kb + 3 * KC);
             acc.mma(sA[1], sB[1], lane, w);
         }
     }
