@@ -92,15 +92,25 @@ __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const 
 #pragma unroll
         for (int u = 0; u < VW; ++u) acc[u] += av[u] * xv;
     };
+    auto value = [&](int32_t b) -> T { return b >= 0 ? x[b] : tb[-1 - b]; };
     const int ngroups = ti.k16 / VW;        // columns that hold values (a multiple of 16)
     int g = w;
+    // the operand-row indices of an iteration are loaded one iteration ahead
+    // of the gathers that use them
+    int32_t bi[4] = {0, 0, 0, 0};
+    if (g + 12 < ngroups)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bi[q] = br[VW * g + sub + 4 * VW * q];
     for (; g + 12 < ngroups; g += 16) {
         const int k0 = VW * g + sub, k1 = k0 + 4 * VW, k2 = k0 + 8 * VW, k3 = k0 + 12 * VW;
         const vec_t a0 = *(const vec_t *)(panel + (int64_t)k0 * 64);
         const vec_t a1 = *(const vec_t *)(panel + (int64_t)k1 * 64);
         const vec_t a2 = *(const vec_t *)(panel + (int64_t)k2 * 64);
         const vec_t a3 = *(const vec_t *)(panel + (int64_t)k3 * 64);
-        const T x0 = operand(k0), x1 = operand(k1), x2 = operand(k2), x3 = operand(k3);
+        const T x0 = value(bi[0]), x1 = value(bi[1]), x2 = value(bi[2]), x3 = value(bi[3]);
+        if (g + 28 < ngroups)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bi[q] = br[k0 + 16 * VW + 4 * VW * q];
         fma_col(a0, x0);
         fma_col(a1, x1);
         fma_col(a2, x2);
