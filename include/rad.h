@@ -145,7 +145,13 @@ typedef struct {
 /*
  * Solves (I - diag(rho) F-hat) B = E, the radiosity system eq.
  * radiosity-system, for R right-hand sides by Jacobi relaxation
- * B^{k+1} = E + rho (F-hat B^k), B^0 = E (sections 3 and 5.1).
+ * B^{k+1} = E + rho (F-hat B^k), B^0 = E (sections 3 and 5.1).  Column c has
+ * converged at the first k with ||B^k - B^{k-1}||^2 <= rtol^2 ||E_c||^2 (rtol^2
+ * when E_c = 0); the solve returns when every column has converged (per
+ * instance and column for a group) and B holds that iterate.  With R >= 16
+ * and check_every = 1 the test also runs on the device and one iteration is
+ * queued ahead of it (skipped on the device once every column has converged);
+ * the returned iterate and info are those of the host's test.
  * With opts->refine = 1 (mixed precision): B (FP64 accumulator) starts at 0;
  * each step forms r = E - B + rho (F-hat B) in FP64 from the FP32 operator,
  * stops columns with ||r|| <= rtol ||E||, runs inner_iters Jacobi iterations of
