@@ -9,7 +9,10 @@ GPU, outside the timed region).  One step = the Jacobi solve of
 (I - 0.3 F-hat) B = E for all 1,024 right-hand sides to a per-column
 relative change of 1e-3.
 
-Prints one JSON line.  See the design doc for the roofline accounting.
+Prints one JSON line.  Its roofline object covers the dominant kernel (the
+fused phase-2 tile product): algorithmic bytes per launch (E and B_old read,
+B_new written; the U' rows, near-field values and projected rows T read once)
+over the launch time measured with HIP events on the kernel's own stream.
 """
 from __future__ import annotations
 

@@ -51,7 +51,7 @@ typedef enum {
     RAD_VIS_RAYCAST = 1   /* back-face test, then the centroid segment must miss every other triangle */
 } rad_visibility;
 
-/* Storage of leaf blocks next to the diagonal (Algorithm 4, step 2). */
+/* Storage of leaf blocks next to the diagonal (Algorithm 4, the leaf case). */
 typedef enum {
     RAD_NEAR_AUTO = 0,  /* fewer bytes of dense or CSR, as the paper states */
     RAD_NEAR_DENSE = 1, /* always dense                                      */

@@ -6,7 +6,7 @@
 //   block pairs from the first level below the root ..... Algorithm 4 (closing remark)
 //   non-zero counts of leaf blocks (Algorithm 1 entries) . GPU kernel
 //   numerical rank with a doubling sketch width ......... Algorithm 3
-//   bottom-up choice of the fewest-bytes form ........... Algorithm 4, steps 2-6
+//   bottom-up choice of the fewest-bytes form ........... Algorithm 4
 //   device layout for the product ....................... Algorithm 5
 //
 // The rank search replaces ARPACK's truncated SVD by a randomized range
@@ -562,7 +562,7 @@ struct Builder {
             if (cd.bytes < best.bytes || (cd.bytes == best.bytes && cd.kind < best.kind)) best = cd;
         b.kind = best.kind;
         b.best_bytes = best.bytes;
-        if (b.kind == BK_HIER) {  // Algorithm 4, step 6: coalesce uniform children
+        if (b.kind == BK_HIER) {  // Algorithm 4, coalescing: merge uniform children
             bool all_dense = true, all_sparse = true, any_csr = false;
             for (int k = 0; k < b.nchild; ++k) {
                 int8_t ck = bp[b.first_child + k].kind;
