@@ -14,7 +14,7 @@ OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librad.so")
 
 SOURCES = ["api.cpp", "build.cpp", "build_kernels.hip", "matvec_kernels.hip", "matmat_kernels.hip", "raycast.hip",
-           "lowp_kernels.hip", "warmstart.hip",
+           "lowp_kernels.hip", "warmstart.hip", "timestep.hip",
            "group.cpp", "autotune.cpp"]
 
 # geometry, entries and ray tests are evaluated without contraction so that

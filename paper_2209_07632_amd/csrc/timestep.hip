@@ -1,0 +1,371 @@
+// Time stepping with subsurface heat storage (section 5.2, Algorithm 6):
+// C-ABI of include/rad_timestep.h and its kernels.
+//
+// State layout (tree order, scenario fastest): element (t, r) of a per-facet
+// field at t R + r, node j of the columns at (j N + t) R + r, so that the
+// threads of a wave (consecutive (t, r)) touch consecutive addresses.  The
+// 2R-column operand X and product Y of the terrain multiply hold band 1
+// (reflected sunlight) in columns [0, R) and band 2 (infrared) in [R, 2R):
+// R-major with ld = 2R rounded to 4 when 2R >= 16 (the matrix-core path),
+// else column-major with ld = N.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "rad_internal.h"
+#include "rad_timestep.h"
+
+namespace {
+
+constexpr int kMaxLayers = 127;
+constexpr int kColThreads = 64;          // threads per workgroup of the column kernel
+constexpr double kSigmaSB = 5.670374419e-8;  // Stefan-Boltzmann constant, W m^-2 K^-4
+
+// Offset of element (t, r) of a caller block in the given rad_order.
+__device__ inline int64_t user_index(int order, int64_t t, int64_t r, int64_t ld, const int32_t *perm) {
+    if (order == RAD_ORDER_TREE_RMAJOR) return t * ld + r;
+    if (order == RAD_ORDER_TREE) return r * ld + t;
+    return r * ld + (int64_t)perm[t];
+}
+
+// Position of (t, column c) in X / Y.
+__device__ inline int64_t op_index(bool rmajor, int64_t t, int64_t c, int64_t ldx, int64_t N) {
+    return rmajor ? t * ldx + c : c * N + t;
+}
+
+template <class T>
+__global__ void k_ts_init(int M, int64_t N, int64_t R, const double *T0, int64_t ldt, int64_t blk, const T *qd0,
+                          int64_t ldq, int order, const int32_t *perm, double h0, double albedo, double *Ts,
+                          double *qabs, double *qrad, T *Y, int64_t ldx, int rmajor) {
+    const int64_t NR = N * R;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NR; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = i / R, r = i - t * R;
+        const int64_t u = user_index(order, t, r, ldt, perm);
+        for (int j = 0; j <= M; ++j) Ts[(int64_t)j * NR + i] = T0[(int64_t)j * blk + u];
+        const double qa = (1.0 - albedo) * (double)qd0[user_index(order, t, r, ldq, perm)] + h0;
+        qabs[i] = qa;
+        qrad[i] = qa;
+        Y[op_index(rmajor, t, r, ldx, N)] = T(0);
+        Y[op_index(rmajor, t, R + r, ldx, N)] = T(0);
+    }
+}
+
+// Operand of the next multiply from the state: band 1 albedo (Q_dir' + Q_refl),
+// band 2 Q_rad + (1 - emiss) Q_IR (Q_refl, Q_IR: the last product).
+template <class T>
+__global__ void k_ts_operand(int64_t N, int64_t R, const double *qrad, const T *Y, T *X, int64_t ldx, int rmajor,
+                             const T *qd, int64_t ldq, int order, const int32_t *perm, double albedo, double emiss) {
+    const int64_t NR = N * R;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NR; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = i / R, r = i - t * R;
+        const int64_t y1 = op_index(rmajor, t, r, ldx, N), y2 = op_index(rmajor, t, R + r, ldx, N);
+        const double qrefl = (double)Y[y1], qir = (double)Y[y2];
+        const double q = (double)qd[user_index(order, t, r, ldq, perm)];
+        X[y1] = (T)(albedo * (q + qrefl));
+        X[y2] = (T)(qrad[i] + (1.0 - emiss) * qir);
+    }
+}
+
+// One step of every column.  coef holds, per node j, cap_j = rho c V_j / dt,
+// g_j = k / (z_j - z_{j-1}), ib_j = 1 / beta_j and e_j = l_j / beta_j of the
+// bottom-up elimination (T_j = d_j - e_j T_{j-1}), four runs of M + 1 values.
+// The d_j of a thread wait in LDS for the downward substitution.
+template <class T>
+__global__ void __launch_bounds__(kColThreads) k_ts_column(int M, int64_t N, int64_t R, const double *coef,
+                                                           const double *Tin, double *Tout, double *qabs,
+                                                           double *qrad, const T *Y, T *X, int64_t ldx, int rmajor,
+                                                           const T *qd, const T *qd_next, int64_t ldq, int order,
+                                                           const int32_t *perm, double albedo, double emiss,
+                                                           double hb) {
+    extern __shared__ double d_lds[];   // M x kColThreads
+    const double *cap = coef, *g = coef + (M + 1), *ib = coef + 2 * (M + 1), *e = coef + 3 * (M + 1);
+    double *dl = d_lds + threadIdx.x;
+    const int64_t NR = N * R;
+    const double es = emiss * kSigmaSB;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NR; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = i / R, r = i - t * R;
+        const int64_t y1 = op_index(rmajor, t, r, ldx, N), y2 = op_index(rmajor, t, R + r, ldx, N);
+        const double qrefl = (double)Y[y1], qir = (double)Y[y2];
+        const double qdir = (double)qd[user_index(order, t, r, ldq, perm)];
+        const double qa_new = (1.0 - albedo) * (qdir + qrefl) + emiss * qir;
+        const double qa_old = qabs[i];
+        // bottom-up: r_j (explicit half of the step), d_j = (r_j - u_j d_{j+1}) / beta_j
+        double t_below = 0.0, t_here = Tin[(int64_t)M * NR + i], d = 0.0;
+        for (int j = M; j >= 1; --j) {
+            const double t_above = Tin[(int64_t)(j - 1) * NR + i];
+            double rj = cap[j] * t_here + 0.5 * g[j] * (t_above - t_here);
+            if (j < M)
+                rj += 0.5 * g[j + 1] * (t_below - t_here) + 0.5 * g[j + 1] * d;
+            else
+                rj += hb;
+            d = rj * ib[j];
+            dl[(j - 1) * kColThreads] = d;
+            t_below = t_here;
+            t_here = t_above;
+        }
+        // surface row: conduction, the averaged absorbed flux and the emission
+        // linearised about the old surface temperature
+        const double t0 = t_here, t1 = t_below, g1 = g[1];
+        const double t03 = t0 * t0 * t0;
+        const double drad = 2.0 * es * t03;
+        const double r0 = cap[0] * t0 + 0.5 * g1 * (t1 - t0) + 0.5 * (qa_old + qa_new) - es * t03 * t0 + drad * t0;
+        double tn = (r0 + 0.5 * g1 * d) / (cap[0] + 0.5 * g1 + drad + 0.5 * g1 * e[1]);
+        Tout[i] = tn;
+        const double ts = tn;
+        for (int j = 1; j <= M; ++j) {
+            tn = dl[(j - 1) * kColThreads] - e[j] * tn;
+            Tout[(int64_t)j * NR + i] = tn;
+        }
+        qabs[i] = qa_new;
+        const double qr = es * ts * ts * ts * ts;
+        qrad[i] = qr;
+        if (qd_next) {
+            const double q2 = (double)qd_next[user_index(order, t, r, ldq, perm)];
+            X[y1] = (T)(albedo * (q2 + qrefl));
+            X[y2] = (T)(qr + (1.0 - emiss) * qir);
+        }
+    }
+}
+
+template <class T>
+__global__ void k_ts_read(int field, int M, int64_t N, int64_t R, const double *Ts, const double *qabs,
+                          const double *qrad, const T *Y, int64_t ldx, int rmajor, double *out, int64_t ld,
+                          int64_t blk, int order, const int32_t *perm) {
+    const int64_t NR = N * R;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NR; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = i / R, r = i - t * R;
+        const int64_t u = user_index(order, t, r, ld, perm);
+        switch (field) {
+            case RAD_TS_T:
+                for (int j = 0; j <= M; ++j) out[(int64_t)j * blk + u] = Ts[(int64_t)j * NR + i];
+                break;
+            case RAD_TS_QABS: out[u] = qabs[i]; break;
+            case RAD_TS_QRAD: out[u] = qrad[i]; break;
+            case RAD_TS_QREFL: out[u] = (double)Y[op_index(rmajor, t, r, ldx, N)]; break;
+            default: out[u] = (double)Y[op_index(rmajor, t, R + r, ldx, N)]; break;
+        }
+    }
+}
+
+unsigned grid_for(int64_t n, int threads) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + threads - 1) / threads, 1 << 20));
+}
+
+}  // namespace
+
+struct rad_ts {
+    const rad_hmat *H = nullptr;
+    int64_t N = 0, R = 0;
+    int32_t M = 0;
+    double albedo = 0, emiss = 1, hb = 0;
+    bool rmajor = false;   // X / Y on the matrix-core path (2R >= 16)
+    int64_t ldx = 0;
+    int64_t level = -1;
+    int cur = 0;           // T[cur] holds the current level
+    rad::DevBuf<double> coef, T[2], qabs, qrad;
+    rad::DevBuf<unsigned char> X, Y;
+};
+
+using namespace rad;
+
+namespace {
+
+void check_order(const rad_ts *S, int32_t order, int64_t ld, const char *name) {
+    RAD_REQUIRE(order == RAD_ORDER_ORIGINAL || order == RAD_ORDER_TREE || order == RAD_ORDER_TREE_RMAJOR, "bad order");
+    if (order == RAD_ORDER_TREE_RMAJOR)
+        RAD_REQUIRE(ld == mm_ldr(S->R), std::string(name) + ": R-major leading dimension must be R rounded up to 4");
+    else
+        RAD_REQUIRE(ld >= S->N, std::string(name) + ": leading dimension smaller than N");
+}
+
+int64_t block_extent(const rad_ts *S, int32_t order, int64_t ld) {
+    return order == RAD_ORDER_TREE_RMAJOR ? S->N * ld : S->R * ld;
+}
+
+// Per-node constants of the column scheme and of its bottom-up elimination.
+std::vector<double> column_coefficients(const rad_ts_params &p) {
+    const int M = p.n_layers;
+    std::vector<double> c(4 * (size_t)(M + 1), 0.0);
+    double *cap = c.data(), *g = cap + (M + 1), *ib = cap + 2 * (M + 1), *e = cap + 3 * (M + 1);
+    const double *z = p.z;
+    for (int j = 1; j <= M; ++j) g[j] = p.conductivity / (z[j] - z[j - 1]);
+    for (int j = 0; j <= M; ++j) {
+        const double lo = j > 0 ? z[j] - z[j - 1] : 0.0, hi = j < M ? z[j + 1] - z[j] : 0.0;
+        cap[j] = p.heat_capacity * 0.5 * (lo + hi) / p.dt;
+    }
+    // row j: -g_j/2 T_{j-1} + b_j T_j - g_{j+1}/2 T_{j+1}; beta_M = b_M,
+    // beta_j = b_j + g_{j+1}/2 e_{j+1}, e_j = -g_j/2 / beta_j
+    for (int j = M; j >= 1; --j) {
+        double beta = cap[j] + 0.5 * g[j];
+        if (j < M) beta += 0.5 * g[j + 1] + 0.5 * g[j + 1] * e[j + 1];
+        ib[j] = 1.0 / beta;
+        e[j] = -0.5 * g[j] / beta;
+    }
+    return c;
+}
+
+template <class T>
+void enqueue_steps(rad_ts *S, int64_t n_steps, const void *Qdir, int64_t ldq, int64_t stride, int32_t order,
+                   hipStream_t s) {
+    const rad_hmat *H = S->H;
+    const int64_t NR = S->N * S->R;
+    const T *qd0 = (const T *)Qdir;
+    const int32_t *perm = H->d_perm.p;
+    const int rm = S->rmajor ? 1 : 0;
+    hipLaunchKernelGGL(k_ts_operand<T>, dim3(grid_for(NR, 256)), dim3(256), 0, s, S->N, S->R, S->qrad.p,
+                       (const T *)S->Y.p, (T *)S->X.p, S->ldx, rm, qd0, ldq, (int)order, perm, S->albedo, S->emiss);
+    RAD_HIP(hipGetLastError());
+    const size_t lds = sizeof(double) * (size_t)S->M * kColThreads;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        if (S->rmajor)
+            mm_apply(H, S->X.p, S->Y.p, S->ldx, 2 * S->R, s);
+        else
+            mv_apply(H, S->X.p, S->N, S->Y.p, S->N, 2 * S->R, s);
+        const T *qd = qd0 + k * stride;
+        const T *qn = k + 1 < n_steps ? qd0 + (k + 1) * stride : nullptr;
+        hipLaunchKernelGGL(k_ts_column<T>, dim3(grid_for(NR, kColThreads)), dim3(kColThreads), lds, s, S->M, S->N,
+                           S->R, S->coef.p, S->T[S->cur].p, S->T[S->cur ^ 1].p, S->qabs.p, S->qrad.p,
+                           (const T *)S->Y.p, (T *)S->X.p, S->ldx, rm, qd, qn, ldq, (int)order, perm, S->albedo,
+                           S->emiss, S->hb);
+        RAD_HIP(hipGetLastError());
+        S->cur ^= 1;
+        ++S->level;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+rad_status rad_ts_create(const rad_hmat *H, const rad_ts_params *p, int64_t R, rad_ts **out) {
+    if (out) *out = nullptr;
+    rad_ts *S = nullptr;
+    rad_status st = guard([&] {
+        RAD_REQUIRE(out != nullptr && H != nullptr && p != nullptr, "null argument");
+        if (H->n_inst > 1) throw Error(RAD_EUNSUP, "the time stepper runs per instance, not on a group");
+        RAD_REQUIRE(H->dtype == RAD_F64 || H->dtype == RAD_F32, "the matrix must be stored in FP64 or FP32");
+        RAD_REQUIRE(R >= 1 && 2 * R <= H->max_rhs, "need 1 <= R and 2 R <= max_rhs of the matrix");
+        const int M = p->n_layers;
+        RAD_REQUIRE(M >= 1 && M <= kMaxLayers, "n_layers must be in [1, 127]");
+        RAD_REQUIRE(p->z != nullptr, "null z");
+        RAD_REQUIRE(p->z[0] == 0.0, "z[0] must be 0 (the surface)");
+        for (int j = 1; j <= M; ++j)
+            RAD_REQUIRE(std::isfinite(p->z[j]) && p->z[j] > p->z[j - 1], "z must be finite and strictly increasing");
+        RAD_REQUIRE(std::isfinite(p->conductivity) && p->conductivity > 0, "conductivity must be > 0");
+        RAD_REQUIRE(std::isfinite(p->heat_capacity) && p->heat_capacity > 0, "heat_capacity must be > 0");
+        RAD_REQUIRE(std::isfinite(p->dt) && p->dt > 0, "dt must be > 0");
+        RAD_REQUIRE(p->albedo >= 0.0 && p->albedo < 1.0, "albedo must be in [0, 1)");
+        RAD_REQUIRE(p->emissivity > 0.0 && p->emissivity <= 1.0, "emissivity must be in (0, 1]");
+        RAD_REQUIRE(std::isfinite(p->bottom_flux), "bottom_flux must be finite");
+        RAD_HIP(hipSetDevice(H->device));
+        S = new rad_ts();
+        S->H = H;
+        S->N = H->N;
+        S->R = R;
+        S->M = M;
+        S->albedo = p->albedo;
+        S->emiss = p->emissivity;
+        S->hb = p->bottom_flux;
+        S->rmajor = 2 * R >= kMfmaMinRhs;
+        S->ldx = S->rmajor ? mm_ldr(2 * R) : S->N;
+        const size_t es = H->dtype == RAD_F64 ? 8 : 4;
+        const size_t nr = (size_t)S->N * (size_t)R;
+        S->coef.upload(column_coefficients(*p));
+        S->T[0].alloc((size_t)(M + 1) * nr);
+        S->T[1].alloc((size_t)(M + 1) * nr);
+        S->qabs.alloc(nr);
+        S->qrad.alloc(nr);
+        const size_t opbytes = (size_t)S->N * (size_t)(S->rmajor ? S->ldx : 2 * R) * es;
+        S->X.alloc(opbytes);
+        S->Y.alloc(opbytes);
+        // padding columns of the R-major operand are multiplied too: keep them zero
+        RAD_HIP(hipMemset(S->X.p, 0, opbytes));
+        RAD_HIP(hipMemset(S->Y.p, 0, opbytes));
+    });
+    if (st != RAD_OK) {
+        delete S;
+        return st;
+    }
+    *out = S;
+    return RAD_OK;
+}
+
+rad_status rad_ts_init(rad_ts *S, const double *T0, int64_t ldt, const void *Qdir0, int64_t ldq, double H0,
+                       int32_t order, void *hip_stream) {
+    return guard([&] {
+        RAD_REQUIRE(S != nullptr, "null stepper");
+        RAD_REQUIRE(T0 && Qdir0, "null T0 or Qdir0");
+        RAD_REQUIRE(std::isfinite(H0), "H0 must be finite");
+        check_order(S, order, ldt, "T0");
+        check_order(S, order, ldq, "Qdir0");
+        RAD_HIP(hipSetDevice(S->H->device));
+        hipStream_t s = (hipStream_t)hip_stream;
+        const int64_t NR = S->N * S->R;
+        const int rm = S->rmajor ? 1 : 0;
+        const int64_t blk = block_extent(S, order, ldt);
+        if (S->H->dtype == RAD_F64)
+            hipLaunchKernelGGL(k_ts_init<double>, dim3(grid_for(NR, 256)), dim3(256), 0, s, S->M, S->N, S->R, T0, ldt,
+                               blk, (const double *)Qdir0, ldq, (int)order, S->H->d_perm.p, H0, S->albedo,
+                               S->T[0].p, S->qabs.p, S->qrad.p, (double *)S->Y.p, S->ldx, rm);
+        else
+            hipLaunchKernelGGL(k_ts_init<float>, dim3(grid_for(NR, 256)), dim3(256), 0, s, S->M, S->N, S->R, T0, ldt,
+                               blk, (const float *)Qdir0, ldq, (int)order, S->H->d_perm.p, H0, S->albedo,
+                               S->T[0].p, S->qabs.p, S->qrad.p, (float *)S->Y.p, S->ldx, rm);
+        RAD_HIP(hipGetLastError());
+        S->cur = 0;
+        S->level = 0;
+    });
+}
+
+rad_status rad_ts_step(rad_ts *S, int64_t n_steps, const void *Qdir, int64_t ldq, int64_t level_stride,
+                       int32_t order, void *hip_stream) {
+    return guard([&] {
+        RAD_REQUIRE(S != nullptr, "null stepper");
+        RAD_REQUIRE(S->level >= 0, "rad_ts_init has not been called");
+        RAD_REQUIRE(Qdir != nullptr, "null Qdir");
+        RAD_REQUIRE(n_steps >= 1, "n_steps must be >= 1");
+        check_order(S, order, ldq, "Qdir");
+        RAD_REQUIRE(n_steps == 1 || level_stride >= block_extent(S, order, ldq),
+                    "level_stride smaller than one level's block");
+        RAD_HIP(hipSetDevice(S->H->device));
+        hipStream_t s = (hipStream_t)hip_stream;
+        if (S->H->dtype == RAD_F64)
+            enqueue_steps<double>(S, n_steps, Qdir, ldq, level_stride, order, s);
+        else
+            enqueue_steps<float>(S, n_steps, Qdir, ldq, level_stride, order, s);
+    });
+}
+
+rad_status rad_ts_read(const rad_ts *S, int32_t field, double *out, int64_t ld, int32_t order, void *hip_stream) {
+    return guard([&] {
+        RAD_REQUIRE(S != nullptr, "null stepper");
+        RAD_REQUIRE(S->level >= 0, "rad_ts_init has not been called");
+        RAD_REQUIRE(out != nullptr, "null out");
+        RAD_REQUIRE(field >= RAD_TS_T && field <= RAD_TS_QRAD, "bad field");
+        check_order(S, order, ld, "out");
+        RAD_HIP(hipSetDevice(S->H->device));
+        hipStream_t s = (hipStream_t)hip_stream;
+        const int64_t NR = S->N * S->R;
+        const int rm = S->rmajor ? 1 : 0;
+        const int64_t blk = block_extent(S, order, ld);
+        if (S->H->dtype == RAD_F64)
+            hipLaunchKernelGGL(k_ts_read<double>, dim3(grid_for(NR, 256)), dim3(256), 0, s, (int)field, S->M, S->N,
+                               S->R, S->T[S->cur].p, S->qabs.p, S->qrad.p, (const double *)S->Y.p, S->ldx, rm, out,
+                               ld, blk, (int)order, S->H->d_perm.p);
+        else
+            hipLaunchKernelGGL(k_ts_read<float>, dim3(grid_for(NR, 256)), dim3(256), 0, s, (int)field, S->M, S->N,
+                               S->R, S->T[S->cur].p, S->qabs.p, S->qrad.p, (const float *)S->Y.p, S->ldx, rm, out,
+                               ld, blk, (int)order, S->H->d_perm.p);
+        RAD_HIP(hipGetLastError());
+    });
+}
+
+int64_t rad_ts_level(const rad_ts *S) { return S ? S->level : -1; }
+
+void rad_ts_free(rad_ts *S) {
+    if (!S) return;
+    (void)hipSetDevice(S->H->device);
+    delete S;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+"""ctypes binding of librad's time stepper (the C-ABI in include/rad_timestep.h).
+
+Argument marshalling only: the flux products, the absorbed-flux update and
+the Crank-Nicolson column steps of Algorithm 6 run in librad's HIP kernels.
+Tensors use the caller's facet order: a block of R scenarios is an (R, N)
+contiguous tensor (column-major N x R with ld = N), the column temperatures
+(M + 1, R, N), a run of direct-insolation levels (n_steps, R, N).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from .rad import _check, _stream_handle, _torch, load
+
+RAD_TS_T, RAD_TS_QABS, RAD_TS_QREFL, RAD_TS_QIR, RAD_TS_QRAD = range(5)
+_FIELDS = {"T": RAD_TS_T, "Q_abs": RAD_TS_QABS, "Q_refl": RAD_TS_QREFL, "Q_ir": RAD_TS_QIR, "Q_rad": RAD_TS_QRAD}
+
+
+class TsParams(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("z", ctypes.c_void_p), ("conductivity", ctypes.c_double),
+                ("heat_capacity", ctypes.c_double), ("dt", ctypes.c_double), ("albedo", ctypes.c_double),
+                ("emissivity", ctypes.c_double), ("bottom_flux", ctypes.c_double)]
+
+
+_bound = False
+
+
+def _lib():
+    global _bound
+    L = load()
+    if not _bound:
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.rad_ts_create.argtypes = [vp, ctypes.POINTER(TsParams), i64, ctypes.POINTER(vp)]
+        L.rad_ts_init.argtypes = [vp, vp, i64, vp, i64, dbl, i32, vp]
+        L.rad_ts_step.argtypes = [vp, i64, vp, i64, i64, i32, vp]
+        L.rad_ts_read.argtypes = [vp, i32, vp, i64, i32, vp]
+        for name in ("rad_ts_create", "rad_ts_init", "rad_ts_step", "rad_ts_read"):
+            getattr(L, name).restype = ctypes.c_int
+        L.rad_ts_level.argtypes = [vp]
+        L.rad_ts_level.restype = i64
+        L.rad_ts_free.argtypes = [vp]
+        L.rad_ts_free.restype = None
+        _bound = True
+    return L
+
+
+def _block(t, shape, dtype, name):
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor of shape {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class TimeStepper:
+    """R scenarios of Algorithm 6 on the facets of an HMatrix (needs max_rhs >= 2 R)."""
+
+    def __init__(self, H, z, conductivity, heat_capacity, dt, albedo, emissivity, bottom_flux=0.0, R=1):
+        self.H = H
+        self._z = np.ascontiguousarray(z, dtype=np.float64)
+        self.M = len(self._z) - 1
+        self.R = int(R)
+        self.N = H.N
+        p = TsParams(self.M, self._z.ctypes.data, float(conductivity), float(heat_capacity), float(dt),
+                     float(albedo), float(emissivity), float(bottom_flux))
+        h = ctypes.c_void_p()
+        _check(_lib().rad_ts_create(H._h, ctypes.byref(p), self.R, ctypes.byref(h)))
+        self._h = h
+
+    def _flux_dtype(self):
+        return self.H.torch_dtype
+
+    def init(self, T0, Qdir0, H0=0.0):
+        torch = _torch()
+        pt = _block(T0, (self.M + 1, self.R, self.N), torch.float64, "T0")
+        pq = _block(Qdir0, (self.R, self.N), self._flux_dtype(), "Qdir0")
+        _check(_lib().rad_ts_init(self._h, pt, self.N, pq, self.N, float(H0), 0, _stream_handle()))
+
+    def step(self, Qdir):
+        """Advance len(Qdir) levels; Qdir is (n_steps, R, N) in the matrix precision."""
+        n = int(Qdir.shape[0])
+        pq = _block(Qdir, (n, self.R, self.N), self._flux_dtype(), "Qdir")
+        _check(_lib().rad_ts_step(self._h, n, pq, self.N, self.R * self.N, 0, _stream_handle()))
+
+    def read(self, field):
+        """FP64 copy of one field: (M + 1, R, N) for "T", else (R, N)."""
+        torch = _torch()
+        shape = (self.M + 1, self.R, self.N) if field == "T" else (self.R, self.N)
+        out = torch.empty(shape, dtype=torch.float64, device=f"cuda:{self.H.device}")
+        _check(_lib().rad_ts_read(self._h, _FIELDS[field], ctypes.c_void_p(out.data_ptr()), self.N, 0,
+                                  _stream_handle()))
+        return out
+
+    @property
+    def level(self):
+        return int(_lib().rad_ts_level(self._h))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib().rad_ts_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

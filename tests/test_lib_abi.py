@@ -69,3 +69,18 @@ def test_calls_on_null_handle_fail_cleanly():
     assert L.rad_hmat_info(None, ctypes.byref(s)) == rad.RAD_EINVAL
     assert L.rad_hmat_n(None) == -1
     L.rad_hmat_free(None)
+
+
+def test_time_stepper_rejects_null_arguments():
+    from paper_2209_07632_amd import rad
+    from paper_2209_07632_amd.timestep import TsParams, _lib
+    L = _lib()
+    h = ctypes.c_void_p()
+    z = np.array([0.0, 0.1])
+    p = TsParams(1, z.ctypes.data, 0.01, 1e6, 100.0, 0.1, 0.9, 0.0)
+    assert L.rad_ts_create(None, ctypes.byref(p), 1, ctypes.byref(h)) == rad.RAD_EINVAL and not h.value
+    assert L.rad_ts_step(None, 1, None, 1, 1, 0, None) == rad.RAD_EINVAL
+    assert L.rad_ts_init(None, None, 1, None, 1, 0.0, 0, None) == rad.RAD_EINVAL
+    assert L.rad_ts_read(None, 0, None, 1, 0, None) == rad.RAD_EINVAL
+    assert L.rad_ts_level(None) == -1
+    L.rad_ts_free(None)
