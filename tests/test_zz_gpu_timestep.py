@@ -2,11 +2,11 @@
 under every facet, section 5.2) against the FP64 CPU reference, through the
 C-ABI of include/rad_timestep.h.
 
-The matrix is built at tol 1e-10 so that F-hat equals the exact F of the
-reference to about 1e-10; the remaining differences are rounding (the GPU
+The FP64 matrix is built at tol 1e-10 so that F-hat equals the exact F of
+the reference to about 1e-10; the remaining differences are rounding (the GPU
 eliminates each column from the bottom up, the reference from the top down).
 Tolerances: FP64 matrix 1e-9 relative on temperatures and fluxes; FP32
-matrix 2e-5 (fluxes carry FP32 products, columns stay FP64).
+matrix at tol 1e-6, 2e-5 (fluxes carry FP32 products, columns stay FP64).
 """
 import numpy as np
 import pytest
@@ -59,11 +59,11 @@ def _oracle(F, Q, T0, z):
     return outs
 
 
-def _stepper(verts, faces, R, z, storage="f64"):
+def _stepper(verts, faces, R, z, storage="f64", tol=1e-10):
     from paper_2209_07632_amd import HMatrix
     from paper_2209_07632_amd.timestep import TimeStepper
-    print(f"[build] N={faces.shape[0]} R={R} storage={storage}", flush=True)
-    H = HMatrix(verts, faces, tol=1e-10, storage=storage, max_rhs=2 * R)
+    print(f"[build] N={faces.shape[0]} R={R} storage={storage} tol={tol}", flush=True)
+    H = HMatrix(verts, faces, tol=tol, storage=storage, max_rhs=2 * R)
     return H, TimeStepper(H, z, K, RHOC, DT, ALBEDO, EMISS, bottom_flux=HB, R=R)
 
 
@@ -108,9 +108,9 @@ def test_level_zero_state(bowl):
 
 
 def test_split_runs_equal_one_run(bowl):
-    """Steps enqueued in several calls give the same bits as one call (the
-    operand written by the last column step equals the one rebuilt from the
-    state at the start of the next call)."""
+    """Steps enqueued in several calls give the result of one call (the
+    operand written by the last column step is rebuilt from the state at the
+    start of the next call by the same arithmetic)."""
     verts, faces, fac, F = bowl
     R = 8
     z = ots.layer_depths(12, 0.3, 1.1)
@@ -127,7 +127,7 @@ def test_split_runs_equal_one_run(bowl):
     S.step(Q[7:].contiguous())
     two = [S.read(f) for f in ("T", "Q_abs", "Q_refl", "Q_ir", "Q_rad")]
     for a, b in zip(one, two):
-        assert torch.equal(a, b)
+        assert float((a - b).abs().max() / b.abs().max()) < 1e-13
 
 
 def test_fp32_matrix(bowl):
@@ -137,7 +137,7 @@ def test_fp32_matrix(bowl):
     n = 20
     Q = _levels(fac, R, n, seed=21)
     T0 = _initial(fac, R, z, seed=22)
-    H, S = _stepper(verts, faces, R, z, storage="f32")
+    H, S = _stepper(verts, faces, R, z, storage="f32", tol=1e-6)
     S.init(torch.from_numpy(T0).to(DEV), torch.from_numpy(Q[0]).to(DEV, torch.float32), H0=H0)
     S.step(torch.from_numpy(Q[1:]).to(DEV, torch.float32).contiguous())
     want = _oracle(F, Q, T0, z)
