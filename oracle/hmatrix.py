@@ -5,6 +5,7 @@ order, used to check what compression at tolerance eps does to F before the
 GPU library is compared against it:
 
   * quadtree on facet centroids ................... Algorithm 2 (section 4.1)
+  * octree, its 3-D analogue for closed bodies ...... section 4.1, section 8
   * numerical rank by truncated SVD with doubling . Algorithm 3 (section 4.2)
   * hierarchical min-bytes assembly ............... Algorithm 4 (section 4.3)
   * product with the compressed matrix ............ Algorithm 5 (section 4.4)
@@ -17,6 +18,8 @@ Readings of passages that are silent or garbled (listed in the design notes):
   * the quadtree split uses the node's own bounding-box midpoints
     (the printed sets compare with x_min / y_min, which would be empty);
     ``<`` goes to the low side; children ordered I1..I4 as printed;
+  * the octree splits at the three midpoints into at most eight sets, ordered
+    like I1..I4 with x the most significant side, then y, then z;
   * recursion stops at ``leaf_size`` points, at ``max_depth``, or when all
     centroids of a node coincide;
   * a block pair is a leaf block when both index sets are tree leaves or
@@ -54,28 +57,41 @@ class Node:
         return int(self.idx.size)
 
 
-def quadtree(xy: np.ndarray, leaf_size: int = 64, max_depth: int | None = None) -> Node:
-    """Root holds every centroid; split at the node's bounding-box midpoint."""
+def spatial_tree(pts: np.ndarray, leaf_size: int = 64, max_depth: int | None = None) -> Node:
+    """Algorithm 2 on the columns of pts: a quadtree for (x, y), an octree for
+    (x, y, z).  Root holds every centroid; a node splits at its bounding-box
+    midpoint along every axis, into at most 2^d non-empty children."""
+    d = pts.shape[1]
 
     def build(idx: np.ndarray, depth: int) -> Node:
         node = Node(idx=idx, depth=depth)
         if idx.size <= leaf_size or (max_depth is not None and depth >= max_depth):
             return node
-        p = xy[idx]
-        xmin, ymin = p.min(axis=0)
-        xmax, ymax = p.max(axis=0)
-        if xmin == xmax and ymin == ymax:
+        p = pts[idx]
+        lo, hi = p.min(axis=0), p.max(axis=0)
+        if np.all(lo == hi):
             return node
-        xmid = 0.5 * (xmin + xmax)
-        ymid = 0.5 * (ymin + ymax)
-        lx = p[:, 0] < xmid
-        ly = p[:, 1] < ymid
-        for m in (lx & ly, lx & ~ly, ~lx & ly, ~lx & ~ly):
+        low = p < 0.5 * (lo + hi)
+        for code in range(1 << d):
+            m = np.ones(idx.size, dtype=bool)
+            for a in range(d):
+                high_side = (code >> (d - 1 - a)) & 1
+                m &= ~low[:, a] if high_side else low[:, a]
             if m.any():
                 node.children.append(build(idx[m], depth + 1))
         return node
 
-    return build(np.arange(xy.shape[0]), 0)
+    return build(np.arange(pts.shape[0]), 0)
+
+
+def quadtree(xy: np.ndarray, leaf_size: int = 64, max_depth: int | None = None) -> Node:
+    """Algorithm 2 on the (x, y) centroids."""
+    return spatial_tree(np.asarray(xy)[:, :2], leaf_size, max_depth)
+
+
+def octree(xyz: np.ndarray, leaf_size: int = 64, max_depth: int | None = None) -> Node:
+    """The octree of section 4.1 on the (x, y, z) centroids."""
+    return spatial_tree(np.asarray(xyz)[:, :3], leaf_size, max_depth)
 
 
 def leaves(node: Node):
@@ -205,10 +221,11 @@ class HMatrix:
         return sum(b.nbytes for b in self.blocks)
 
 
-def assemble(F: np.ndarray, xy: np.ndarray, eps: float, s: int = 8, leaf_size: int = 64,
+def assemble(F: np.ndarray, pts: np.ndarray, eps: float, s: int = 8, leaf_size: int = 64,
              max_depth: int | None = None) -> HMatrix:
-    """Compress F starting from the pairs of the root's children (at most 16)."""
-    root = quadtree(xy, leaf_size=leaf_size, max_depth=max_depth)
+    """Compress F starting from the pairs of the root's children: at most 16
+    for a quadtree (pts = x, y centroids), 64 for an octree (x, y, z)."""
+    root = spatial_tree(pts, leaf_size=leaf_size, max_depth=max_depth)
     if root.is_leaf:
         return HMatrix(F.shape[0], root, [_leaf_choice(F, root.idx, root.idx, s)])
     blocks = [assemble_block(F, ci, cj, eps, s, leaf_size)

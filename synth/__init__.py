@@ -8,4 +8,5 @@ consume what it produces.
 from .meshes import (  # noqa: F401
     CapSpec, DemSpec, cap_mesh, dem_mesh, sun_directions, sun_grid_azimuth,
     CAP_SMALL, CAP_LARGE, DEM_256, DEM_512, instance_sizes, dem_instance, mlp_init,
+    BodySpec, body_mesh,
 )

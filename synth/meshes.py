@@ -23,6 +23,14 @@ Synthetic polar terrain (stand-in for a lunar DEM):
   * two triangles per pixel with the fixed diagonal (i,j)-(i+1,j+1), normals
     up.
 
+Closed bilobed body (stand-in for a comet shape model):
+  * an icosahedron subdivided ``level`` times (each triangle into four, new
+    vertices projected onto the unit sphere), faces wound so that normals
+    point outward;
+  * every vertex ``u`` moved to radius ``radius (1 + neck cos 2 theta)`` with
+    ``cos theta = u_z``: two lobes joined by a concave waist at the equator
+    (``neck`` = 0 gives the sphere).
+
 Sun directions: unit vectors ``(cos e cos phi, cos e sin phi, sin e)`` with
 ``phi`` counter-clockwise from +x and ``e`` the elevation above the
 horizontal plane.
@@ -204,3 +212,50 @@ def mlp_init(sizes, seed: int = 0) -> np.ndarray:
         parts.append(rng.uniform(-a, a, size=fo * fi))
         parts.append(np.zeros(fo))
     return np.concatenate(parts).astype(np.float32)
+
+
+@dataclass(frozen=True)
+class BodySpec:
+    level: int = 3            # subdivisions of the icosahedron: 20 * 4^level faces
+    radius: float = 1000.0    # mean radius (m)
+    neck: float = 0.5         # waist depth, r = radius (1 + neck cos 2 theta)
+
+
+def _icosphere(level: int):
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    verts = [np.array(p, dtype=np.float64) / np.linalg.norm(p) for p in v]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+             (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5),
+             (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    V = np.array(verts)
+    Fc = np.array(faces, dtype=np.int32)
+    # wind every face outward: normal . centroid > 0 on the unit sphere
+    n = np.cross(V[Fc[:, 1]] - V[Fc[:, 0]], V[Fc[:, 2]] - V[Fc[:, 0]])
+    flip = np.einsum("ij,ij->i", n, V[Fc].mean(axis=1)) < 0
+    Fc[flip] = Fc[flip][:, [0, 2, 1]]
+    return V, Fc
+
+
+def body_mesh(spec: BodySpec = BodySpec()):
+    """Closed bilobed body: (verts (nv, 3) FP64, faces (nf, 3) int32), normals outward."""
+    V, Fc = _icosphere(spec.level)
+    r = spec.radius * (1.0 + spec.neck * (2.0 * V[:, 2] ** 2 - 1.0))
+    return V * r[:, None], Fc

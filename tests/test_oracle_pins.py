@@ -298,3 +298,94 @@ def test_hmatrix_tiles_matrix_and_error_tracks_eps():
         prev = H.nbytes()
     H = hm.assemble(F, xy, eps=1e-15)
     np.testing.assert_allclose(hm.multiply(H, X), Y0, rtol=1e-10)
+
+
+# ---------------------------------------------------------------- octree, sections 4.1 and 8
+def test_octree_partition():
+    """Every child of an octree node lies on one side of each of the node's three
+    mid-planes; leaves hold 1..leaf_size facets and partition the body."""
+    from synth import BodySpec, body_mesh
+    v, f = body_mesh(BodySpec(level=3))
+    fac = ref.Facets(v, f)
+    root = hm.octree(fac.x, leaf_size=32)
+    perm = hm.tree_permutation(root)
+    assert np.array_equal(np.sort(perm), np.arange(fac.N))
+    assert all(1 <= lf.size <= 32 for lf in hm.leaves(root))
+    assert max(len(n.children) for n in _nodes(root)) == 8
+
+    def check(node):
+        if node.is_leaf:
+            return
+        p = fac.x[node.idx]
+        mid = 0.5 * (p.min(axis=0) + p.max(axis=0))
+        for c in node.children:
+            q = fac.x[c.idx]
+            for a in range(3):
+                assert np.all(q[:, a] < mid[a]) or np.all(q[:, a] >= mid[a])
+            check(c)
+    check(root)
+
+
+def _nodes(node):
+    yield node
+    for c in node.children:
+        yield from _nodes(c)
+
+
+def test_octree_of_flat_points_is_the_quadtree():
+    """With every centroid at one height the z split never separates anything,
+    and the octree has the quadtree's leaves in the quadtree's order."""
+    v, f = cap_mesh(CAP_SMALL)
+    fac = ref.Facets(v, f)
+    flat = np.column_stack([fac.x[:, :2], np.full(fac.N, 7.0)])
+    a = [lf.idx for lf in hm.leaves(hm.octree(flat, leaf_size=40))]
+    b = [lf.idx for lf in hm.leaves(hm.quadtree(fac.x[:, :2], leaf_size=40))]
+    assert len(a) == len(b) and all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_octree_sphere_blocks_rank_one():
+    """Inside a sphere the kernel is A_j / (4 pi r^2): with the octree on the
+    3-D centroids every off-diagonal low-rank block has rank one."""
+    fac = sphere_facets(700, seed=6)
+    F = ref.view_factor_matrix(fac)
+    H = hm.assemble(F, fac.x, eps=1e-8, leaf_size=32)
+    svd = [b for b in hm.leaf_blocks(H) if b.kind == "svd" and not np.intersect1d(b.rows, b.cols).size]
+    assert svd and all(b.data[0].shape[1] == 1 for b in svd)
+    X = np.random.default_rng(3).random((fac.N, 2))
+    assert np.linalg.norm(hm.multiply(H, X) - F @ X) / np.linalg.norm(F @ X) < 1e-7
+
+
+def test_convex_body_seen_from_outside_has_no_exchange():
+    """Outward normals on a convex closed body: no facet faces another, so F = 0
+    and the compressed matrix is all zero blocks of no bytes."""
+    from synth import BodySpec, body_mesh
+    v, f = body_mesh(BodySpec(level=2, neck=0.0))
+    fac = ref.Facets(v, f)
+    F = ref.view_factor_matrix(fac)
+    assert not F.any()
+    H = hm.assemble(F, fac.x, eps=1e-3, leaf_size=16)
+    assert H.nbytes() == 0 and {b.kind for b in hm.leaf_blocks(H)} == {"zero"}
+
+
+def test_bilobed_body_is_zero_block_heavy_and_error_tracks_eps():
+    """The closed two-lobed body (ray-cast visibility) compressed on an octree:
+    blocks tile F once, the product error stays below eps, zero blocks cover
+    over a quarter of the matrix (about a third here; on the all-visible
+    crater none) and the bytes are a small fraction of dense storage."""
+    from synth import BodySpec, body_mesh
+    v, f = body_mesh(BodySpec(level=3))
+    fac = ref.Facets(v, f)
+    F = ref.view_factor_matrix(fac, ref.pair_visibility(fac, "raycast"))
+    assert 0.01 < np.count_nonzero(F) / F.size < 0.1
+    X = np.random.default_rng(4).random((fac.N, 3))
+    Y0 = F @ X
+    for eps in (1e-2, 1e-3, 1e-4):
+        H = hm.assemble(F, fac.x, eps=eps, leaf_size=32)
+        blocks = hm.leaf_blocks(H)
+        cover = np.zeros(F.shape, dtype=np.int32)
+        for b in blocks:
+            cover[np.ix_(b.rows, b.cols)] += 1
+        assert np.all(cover == 1)
+        assert np.linalg.norm(hm.multiply(H, X) - Y0) / np.linalg.norm(Y0) <= eps
+        assert sum(b.rows.size * b.cols.size for b in blocks if b.kind == "zero") > 0.25 * F.size
+        assert H.nbytes() < 0.1 * F.size * 8
