@@ -11,6 +11,7 @@ Paper passages followed (Potter et al., arXiv 2209.07632):
   * insolation, eq. insolation ....................... section 2 / 5.1
   * radiosity system B = E + diag(rho) F B ........... eq. radiosity-system
   * Jacobi relaxation ................................ section 3 / 5.1
+  * Chebyshev acceleration (not in the paper) ........ Saad, section 12.1
   * two-band equilibrium, eqs. Qvis, QIR, 3d-equilbr . sections 2 and 5.1
   * closed-form bowl-crater temperature .............. section 7.1
 """
@@ -181,6 +182,53 @@ def jacobi(matvec, rho, E, tol: float = 1e-13, max_iter: int = 500):
         if np.all(iters >= 0):
             return B.reshape(E.shape), iters
     raise RuntimeError("Jacobi did not converge")
+
+
+def chebyshev(matvec, rho: float, E, lam_lo: float, lam_hi: float, tol: float = 1e-13, max_iter: int = 500,
+              strict: bool = True):
+    """Chebyshev acceleration of B = E + rho F B (not in the paper: a faster
+    iteration for systems whose F has a spectral radius near one).
+
+    Reciprocity (A_i F_ij = A_j F_ji, eq. FF-def with symmetric visibility)
+    makes F self-adjoint in the area-weighted inner product, so its spectrum
+    is real.  Given [lam_lo, lam_hi] containing it, M = I - rho F has its
+    spectrum in [1 - rho lam_hi, 1 - rho lam_lo] (rho > 0), and the
+    three-term Chebyshev iteration for M B = E (Saad, Iterative Methods for
+    Sparse Linear Systems, 2nd ed., section 12.1) is run from B^0 = E with one
+    product per iteration: its error in the area-weighted norm is at most
+    the initial error over T_k(theta / delta), theta and delta the centre and
+    half-width of that interval.  Stops when every column's recurrence
+    residual is <= tol ||E||.  Returns (B, iters); after max_iter iterations
+    it raises, or with strict=False returns that iterate.
+    """
+    E2 = E.reshape(E.shape[0], -1)
+    lo, hi = 1.0 - rho * lam_hi, 1.0 - rho * lam_lo
+    if not 0.0 < lo <= hi:
+        raise ValueError("need 0 < 1 - rho lam_hi <= 1 - rho lam_lo")
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    enorm = np.linalg.norm(E2, axis=0)
+    thr = tol * np.where(enorm > 0, enorm, 1.0)
+    B = E2.copy()
+    r = E2 - (B - rho * matvec(B))
+    iters = np.full(E2.shape[1], -1, dtype=np.int64)
+    iters[np.linalg.norm(r, axis=0) <= thr] = 0
+    if delta == 0.0:      # a single point: one scaled step is exact
+        return (B + r / theta).reshape(E.shape), np.maximum(iters, 1)
+    sigma = theta / delta
+    rk = 1.0 / sigma
+    d = r / theta
+    for k in range(1, max_iter + 1):
+        B = B + d
+        r = r - (d - rho * matvec(d))
+        iters[(iters < 0) & (np.linalg.norm(r, axis=0) <= thr)] = k
+        if np.all(iters >= 0):
+            return B.reshape(E.shape), iters
+        rk1 = 1.0 / (2.0 * sigma - rk)
+        d = rk1 * rk * d + (2.0 * rk1 / delta) * r
+        rk = rk1
+    if strict:
+        raise RuntimeError("Chebyshev iteration did not converge")
+    return B.reshape(E.shape), iters
 
 
 def solve_direct(F: np.ndarray, rho, E: np.ndarray) -> np.ndarray:

@@ -389,3 +389,57 @@ def test_bilobed_body_is_zero_block_heavy_and_error_tracks_eps():
         assert np.linalg.norm(hm.multiply(H, X) - Y0) / np.linalg.norm(Y0) <= eps
         assert sum(b.rows.size * b.cols.size for b in blocks if b.kind == "zero") > 0.25 * F.size
         assert H.nbytes() < 0.1 * F.size * 8
+
+
+# ---------------------------------------------------------------- Chebyshev acceleration
+@pytest.fixture(scope="module")
+def hemisphere_bowl():
+    """Bowl with depth / diameter 0.5 (f = 1/2): Jacobi converges only as 2^-k."""
+    v, f = cap_mesh(CapSpec(h=90.0, depth_ratio=0.5, seed=2))
+    fac = ref.Facets(v, f)
+    return fac, ref.view_factor_matrix(fac)
+
+
+def test_view_factor_spectrum_is_real(hemisphere_bowl):
+    """Reciprocity makes diag(A) F symmetric, so F is self-adjoint in the
+    area-weighted inner product and its eigenvalues are real, with the Perron
+    root below the largest row sum."""
+    fac, F = hemisphere_bowl
+    AF = fac.A[:, None] * F
+    assert np.max(np.abs(AF - AF.T)) <= 1e-14 * np.max(AF)
+    ev = np.linalg.eigvals(F)
+    assert np.max(np.abs(ev.imag)) <= 1e-12
+    assert 0.45 < ev.real.max() <= F.sum(axis=1).max()
+
+
+def test_chebyshev_matches_lapack_and_beats_jacobi(hemisphere_bowl):
+    fac, F = hemisphere_bowl
+    ev = np.linalg.eigvals(F).real
+    E = np.random.default_rng(7).random((fac.N, 3))
+    Bd = ref.solve_direct(F, 1.0, E)
+    B, it = ref.chebyshev(lambda X: F @ X, 1.0, E, ev.min(), ev.max(), tol=1e-13)
+    assert np.max(np.abs(B - Bd)) <= 1e-12 * np.max(np.abs(Bd))
+    _, itj = ref.jacobi(lambda X: F @ X, 1.0, E, tol=1e-13)
+    assert np.all(it < 0.5 * itj)
+
+
+def test_chebyshev_error_bound(hemisphere_bowl):
+    """In the area-weighted norm the error after k iterations is at most the
+    initial error over T_k(theta / delta), for the exact spectral interval and
+    for the row-sum bound [-r, r]."""
+    fac, F = hemisphere_bowl
+    ev = np.linalg.eigvals(F).real
+    r = F.sum(axis=1).max()
+    E = np.random.default_rng(8).random((fac.N, 2))
+    Bd = ref.solve_direct(F, 1.0, E)
+
+    def anorm(x):
+        return np.sqrt((fac.A[:, None] * x * x).sum(axis=0))
+
+    e0 = anorm(E - Bd)
+    for lo, hi in ((ev.min(), ev.max()), (-r, r)):
+        theta, delta = 1.0 - 0.5 * (lo + hi), 0.5 * (hi - lo)
+        for k in range(1, 16):
+            Bk, _ = ref.chebyshev(lambda X: F @ X, 1.0, E, lo, hi, tol=0.0, max_iter=k, strict=False)
+            bound = 1.0 / np.cosh(k * np.arccosh(theta / delta))
+            assert np.all(anorm(Bk - Bd) / e0 <= bound * (1 + 1e-6) + 1e-12), (lo, hi, k)
