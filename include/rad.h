@@ -105,6 +105,19 @@ rad_status rad_hmat_build(const double *verts, int64_t nv, const int32_t *faces,
                           const rad_build_opts *opts, rad_hmat **out);
 
 /*
+ * rad_hmat_build with a choice of tree (Algorithm 2; section 4.1 names the
+ * octree as its 3-D analogue for overhangs and small bodies):
+ * tree_dims = 2 splits the centroids on (x, y), a quadtree, as rad_hmat_build;
+ * tree_dims = 3 splits them on (x, y, z), an octree of at most eight children
+ * per node (x the most significant side, then y, then z), for closed bodies.
+ * Everything after the tree (block pairs from the root's children, rank
+ * search, layout, products) is the same.  Errors as rad_hmat_build, and
+ * RAD_EINVAL for another tree_dims.
+ */
+rad_status rad_hmat_build_tree(const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
+                               const rad_build_opts *opts, int32_t tree_dims, rad_hmat **out);
+
+/*
  * Y = F-hat X (Algorithm 5) for R right-hand sides.  X and Y are device
  * arrays of the matrix's compute dtype (rad_hmat_dtype) in the layout named
  * by order (rad_order; leading dimensions ldx, ldy as that layout requires).

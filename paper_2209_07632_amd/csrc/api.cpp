@@ -201,8 +201,8 @@ void rad_solve_opts_default(rad_solve_opts *o) {
 
 const char *rad_last_error(void) { return g_last_error.c_str(); }
 
-rad_status rad_hmat_build(const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
-                          const rad_build_opts *opts, rad_hmat **out) {
+rad_status rad_hmat_build_tree(const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
+                               const rad_build_opts *opts, int32_t tree_dims, rad_hmat **out) {
     if (out) *out = nullptr;
     rad_hmat *H = nullptr;
     rad_status st = guard([&] {
@@ -213,7 +213,7 @@ rad_status rad_hmat_build(const double *verts, int64_t nv, const int32_t *faces,
         else
             rad_build_opts_default(&o);
         H = new rad_hmat();
-        build_hmat(H, verts, nv, faces, nf, o);
+        build_hmat(H, verts, nv, faces, nf, o, tree_dims);
         alloc_workspace(H);
     });
     if (st != RAD_OK) {
@@ -222,6 +222,11 @@ rad_status rad_hmat_build(const double *verts, int64_t nv, const int32_t *faces,
     }
     *out = H;
     return RAD_OK;
+}
+
+rad_status rad_hmat_build(const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
+                          const rad_build_opts *opts, rad_hmat **out) {
+    return rad_hmat_build_tree(verts, nv, faces, nf, opts, 2, out);
 }
 
 void rad_hmat_free(rad_hmat *H) {

@@ -72,10 +72,14 @@ void facet_geometry(const double *V, int64_t nv, const int32_t *Fc, int64_t nf, 
 // box; children in the printed order (x<,y<), (x<,y>=), (x>=,y<), (x>=,y>=);
 // stop at leaf_size points, at max_depth, or when all centroids coincide.
 // Leaves in depth-first order define the tree permutation.
+// With dims = 3 the same split runs on (x, y, z): the octree of section 4.1
+// for closed bodies, each of the four children above split again at the z
+// midpoint (z< first), so x is the most significant side, then y, then z.
 // ---------------------------------------------------------------------------
 struct QuadBuilder {
     const double *x;
     int leaf_size, max_depth;
+    int dims = 2;
     std::vector<TreeNode> nodes;
     std::vector<int32_t> perm;
     int32_t nleaves = 0;
@@ -86,14 +90,19 @@ struct QuadBuilder {
         nodes[node].depth = depth;
         bool leaf = (int)idx.size() <= leaf_size || (max_depth > 0 && depth >= max_depth);
         double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+        double zmin = INFINITY, zmax = -INFINITY;
         if (!leaf) {
             for (int32_t i : idx) {
                 xmin = std::min(xmin, x[3 * i]);
                 xmax = std::max(xmax, x[3 * i]);
                 ymin = std::min(ymin, x[3 * i + 1]);
                 ymax = std::max(ymax, x[3 * i + 1]);
+                if (dims == 3) {
+                    zmin = std::min(zmin, x[3 * i + 2]);
+                    zmax = std::max(zmax, x[3 * i + 2]);
+                }
             }
-            if (xmin == xmax && ymin == ymax) leaf = true;
+            if (xmin == xmax && ymin == ymax && (dims == 2 || zmin == zmax)) leaf = true;
         }
         if (leaf) {
             nodes[node].first_child = -1;
@@ -105,11 +114,12 @@ struct QuadBuilder {
             perm.insert(perm.end(), idx.begin(), idx.end());
             return;
         }
-        double xmid = 0.5 * (xmin + xmax), ymid = 0.5 * (ymin + ymax);
-        std::vector<int32_t> part[4];
+        double xmid = 0.5 * (xmin + xmax), ymid = 0.5 * (ymin + ymax), zmid = 0.5 * (zmin + zmax);
+        std::vector<int32_t> part[8];   // quadtree: parts 0..3 only
         for (int32_t i : idx) {
             bool lx = x[3 * i] < xmid, ly = x[3 * i + 1] < ymid;
             int q = lx ? (ly ? 0 : 1) : (ly ? 2 : 3);
+            if (dims == 3) q = 2 * q + (x[3 * i + 2] < zmid ? 0 : 1);
             part[q].push_back(i);
         }
         idx.clear();
@@ -935,9 +945,10 @@ struct Builder {
 }  // namespace
 
 void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
-                const rad_build_opts &o) {
+                const rad_build_opts &o, int tree_dims) {
     auto t0 = std::chrono::steady_clock::now();
     RAD_REQUIRE(verts && faces, "null mesh pointer");
+    RAD_REQUIRE(tree_dims == 2 || tree_dims == 3, "tree_dims must be 2 (quadtree) or 3 (octree)");
     RAD_REQUIRE(nv >= 3 && nf >= 1, "mesh needs nv >= 3 and nf >= 1");
     RAD_REQUIRE(nf < (int64_t)1 << 31, "too many faces");
     RAD_REQUIRE(o.tol > 0.0 && std::isfinite(o.tol), "tol must be positive");
@@ -971,11 +982,12 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
     qb.x = x.data();
     qb.leaf_size = o.leaf_size;
     qb.max_depth = o.max_depth;
+    qb.dims = tree_dims;
     qb.nodes.resize(1);
     std::vector<int32_t> all(nf);
     std::iota(all.begin(), all.end(), 0);
     qb.split(0, std::move(all), 0);
-    B.log("quadtree", "leaves=" + std::to_string(qb.nleaves));
+    B.log(tree_dims == 3 ? "octree" : "quadtree", "leaves=" + std::to_string(qb.nleaves));
     H->nodes = std::move(qb.nodes);
     H->perm = std::move(qb.perm);
     H->n_leaves = qb.nleaves;

@@ -301,8 +301,9 @@ rad_status guard(F &&f) {
 void jacobi_svd(int l, std::vector<double> &A, std::vector<double> &V, std::vector<double> &sv);
 
 // builder entry (build.cpp)
+// tree_dims: 2 = quadtree on (x, y), 3 = octree on (x, y, z)
 void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
-                const rad_build_opts &o);
+                const rad_build_opts &o, int tree_dims = 2);
 
 // device geometry used by the build kernels (tree order, FP64)
 struct DevGeom {

@@ -62,7 +62,7 @@ class Stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
-EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_matvec", "rad_solve_opts_default", "rad_solve",
+EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_build_tree", "rad_hmat_matvec", "rad_solve_opts_default", "rad_solve",
            "rad_insolation", "rad_equilibrium", "rad_hmat_time_phases", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free",
            "rad_last_error", "rad_pod_build", "rad_pod_project", "rad_pod_expand", "rad_mlp_create",
            "rad_mlp_param_count", "rad_mlp_get_params", "rad_mlp_set_params", "rad_mlp_forward", "rad_mlp_loss_grad",
@@ -91,6 +91,9 @@ def load(path: str = LIB_PATH):
     L.rad_hmat_build.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, ctypes.POINTER(BuildOpts),
                                  ctypes.POINTER(vp)]
     L.rad_hmat_build.restype = ctypes.c_int
+    L.rad_hmat_build_tree.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, ctypes.POINTER(BuildOpts),
+                                      ctypes.c_int32, ctypes.POINTER(vp)]
+    L.rad_hmat_build_tree.restype = ctypes.c_int
     L.rad_hmat_matvec.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int64, vp, ctypes.c_int64,
                                   ctypes.c_int32, vp]
     L.rad_hmat_matvec.restype = ctypes.c_int
@@ -198,7 +201,7 @@ class HMatrix:
 
     def __init__(self, verts, faces, tol=1e-3, leaf_size=64, max_depth=0, nearfield="auto",
                  visibility="backface", storage="f64", oversample=8, power_iters=1, max_rhs=1, device=0,
-                 seed=0x5EED, verbose=False, max_rank=0, lowp=None):
+                 seed=0x5EED, verbose=False, max_rank=0, lowp=None, tree="quad"):
         L = load()
         o = BuildOpts()
         L.rad_build_opts_default(ctypes.byref(o))
@@ -219,8 +222,14 @@ class HMatrix:
         v = np.ascontiguousarray(verts, dtype=np.float64)
         f = np.ascontiguousarray(faces, dtype=np.int32)
         h = ctypes.c_void_p()
-        _check(L.rad_hmat_build(v.ctypes.data, v.shape[0], f.ctypes.data, f.shape[0], ctypes.byref(o),
-                                ctypes.byref(h)))
+        if tree not in ("quad", "oct"):
+            raise ValueError("tree must be 'quad' (on x, y) or 'oct' (on x, y, z)")
+        if tree == "quad":
+            _check(L.rad_hmat_build(v.ctypes.data, v.shape[0], f.ctypes.data, f.shape[0], ctypes.byref(o),
+                                    ctypes.byref(h)))
+        else:
+            _check(L.rad_hmat_build_tree(v.ctypes.data, v.shape[0], f.ctypes.data, f.shape[0], ctypes.byref(o), 3,
+                                         ctypes.byref(h)))
         self._h = h
         self.N = int(L.rad_hmat_n(h))
         self.rad_dtype = int(L.rad_hmat_dtype(h))

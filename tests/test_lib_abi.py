@@ -84,3 +84,15 @@ def test_time_stepper_rejects_null_arguments():
     assert L.rad_ts_read(None, 0, None, 1, 0, None) == rad.RAD_EINVAL
     assert L.rad_ts_level(None) == -1
     L.rad_ts_free(None)
+
+
+def test_build_tree_rejects_bad_tree_dims():
+    from paper_2209_07632_amd import rad
+    L = rad.load()
+    o = rad.BuildOpts()
+    L.rad_build_opts_default(ctypes.byref(o))
+    h = ctypes.c_void_p()
+    verts = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], dtype=np.float64)
+    faces = np.array([[0, 1, 2]], dtype=np.int32)
+    st = L.rad_hmat_build_tree(verts.ctypes.data, 3, faces.ctypes.data, 1, ctypes.byref(o), 4, ctypes.byref(h))
+    assert st == rad.RAD_EINVAL and b"tree_dims" in L.rad_last_error() and not h.value
