@@ -12,6 +12,7 @@ Paper passages followed (Potter et al., arXiv 2209.07632):
   * radiosity system B = E + diag(rho) F B ........... eq. radiosity-system
   * Jacobi relaxation ................................ section 3 / 5.1
   * Chebyshev acceleration (not in the paper) ........ Saad, section 12.1
+  * GMRES (a Krylov solve for the same systems) ...... Saad, section 6.5
   * two-band equilibrium, eqs. Qvis, QIR, 3d-equilbr . sections 2 and 5.1
   * closed-form bowl-crater temperature .............. section 7.1
 """
@@ -229,6 +230,76 @@ def chebyshev(matvec, rho: float, E, lam_lo: float, lam_hi: float, tol: float = 
     if strict:
         raise RuntimeError("Chebyshev iteration did not converge")
     return B.reshape(E.shape), iters
+
+
+def gmres(matvec, rho, E, tol: float = 1e-13, restart: int = 50, max_iter: int = 500):
+    """GMRES for (I - diag(rho) F) B = E, one column at a time, from B = 0
+    (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed., section 6.5:
+    Arnoldi with modified Gram-Schmidt, Givens rotations on the Hessenberg
+    matrix, restarted every ``restart`` steps).  Stops a column when its
+    residual norm is <= tol ||E_c||.  Returns (B, iters, history) with iters[c]
+    the number of Arnoldi steps (products) taken and history[c] the residual
+    norms after 0, 1, 2, ... steps.
+    """
+    E2 = E.reshape(E.shape[0], -1)
+    n, R = E2.shape
+    rho = np.broadcast_to(np.asarray(rho, dtype=np.float64), (n,))
+
+    def A(v):
+        return v - rho * matvec(v[:, None])[:, 0]
+
+    B = np.zeros_like(E2, dtype=np.float64)
+    iters = np.zeros(R, dtype=np.int64)
+    history = []
+    for c in range(R):
+        b = E2[:, c].astype(np.float64)
+        thr = tol * (np.linalg.norm(b) if np.linalg.norm(b) > 0 else 1.0)
+        x = np.zeros(n)
+        r = b.copy()
+        beta = np.linalg.norm(r)
+        hist = [beta]
+        steps = 0
+        while beta > thr and steps < max_iter:
+            m = min(restart, max_iter - steps)
+            V = np.zeros((m + 1, n))
+            Hm = np.zeros((m + 1, m))
+            cs, sn = np.zeros(m), np.zeros(m)
+            g = np.zeros(m + 1)
+            g[0] = beta
+            V[0] = r / beta
+            j_done = 0
+            for j in range(m):
+                w = A(V[j])
+                for i in range(j + 1):            # modified Gram-Schmidt
+                    Hm[i, j] = w @ V[i]
+                    w = w - Hm[i, j] * V[i]
+                Hm[j + 1, j] = np.linalg.norm(w)
+                if Hm[j + 1, j] > 0:
+                    V[j + 1] = w / Hm[j + 1, j]
+                for i in range(j):                # earlier rotations on the new column
+                    t = cs[i] * Hm[i, j] + sn[i] * Hm[i + 1, j]
+                    Hm[i + 1, j] = -sn[i] * Hm[i, j] + cs[i] * Hm[i + 1, j]
+                    Hm[i, j] = t
+                d = np.hypot(Hm[j, j], Hm[j + 1, j])
+                cs[j], sn[j] = Hm[j, j] / d, Hm[j + 1, j] / d
+                Hm[j, j], Hm[j + 1, j] = d, 0.0
+                g[j + 1] = -sn[j] * g[j]
+                g[j] = cs[j] * g[j]
+                j_done = j + 1
+                steps += 1
+                hist.append(abs(g[j + 1]))
+                if abs(g[j + 1]) <= thr or Hm[j, j] == 0.0:
+                    break
+            y = np.linalg.solve(np.triu(Hm[:j_done, :j_done]), g[:j_done])
+            x = x + V[:j_done].T @ y
+            r = b - A(x)
+            beta = np.linalg.norm(r)
+        if beta > thr:
+            raise RuntimeError("GMRES did not converge")
+        B[:, c] = x
+        iters[c] = steps
+        history.append(np.array(hist))
+    return B.reshape(E.shape), iters, history
 
 
 def solve_direct(F: np.ndarray, rho, E: np.ndarray) -> np.ndarray:

@@ -443,3 +443,72 @@ def test_chebyshev_error_bound(hemisphere_bowl):
             Bk, _ = ref.chebyshev(lambda X: F @ X, 1.0, E, lo, hi, tol=0.0, max_iter=k, strict=False)
             bound = 1.0 / np.cosh(k * np.arccosh(theta / delta))
             assert np.all(anorm(Bk - Bd) / e0 <= bound * (1 + 1e-6) + 1e-12), (lo, hi, k)
+
+
+# ---------------------------------------------------------------- GMRES
+def test_gmres_matches_lapack(hemisphere_bowl):
+    fac, F = hemisphere_bowl
+    E = np.random.default_rng(9).random((fac.N, 3))
+    Bd = ref.solve_direct(F, 1.0, E)
+    for restart in (50, 3):
+        B, it, hist = ref.gmres(lambda X: F @ X, 1.0, E, tol=1e-13, restart=restart)
+        assert np.max(np.abs(B - Bd)) <= 1e-11 * np.max(np.abs(Bd))
+        true_res = np.linalg.norm(E - (B - F @ B), axis=0)
+        assert np.all(true_res <= 1e-12 * np.linalg.norm(E, axis=0))
+
+
+def test_gmres_minimal_residual_beats_jacobi(hemisphere_bowl):
+    """Jacobi's k-th iterate from B^0 = E lies in the Krylov space of k + 1
+    GMRES steps, so GMRES's residual after k + 1 steps is never larger, and
+    its residual history never increases."""
+    fac, F = hemisphere_bowl
+    E = np.random.default_rng(10).random((fac.N, 2))
+    _, _, hist = ref.gmres(lambda X: F @ X, 1.0, E, tol=1e-14, restart=100)
+    Bj = E.copy()
+    for k in range(12):
+        if k:
+            Bj = E + F @ Bj
+        rj = np.linalg.norm(E - (Bj - F @ Bj), axis=0)
+        for c, h in enumerate(hist):
+            if k + 1 < len(h):
+                assert h[k + 1] <= rj[c] * (1 + 1e-10) + 1e-14
+    for h in hist:
+        assert np.all(np.diff(h) <= 1e-12 * h[0])
+
+
+def test_gmres_finite_termination():
+    """Without restarts GMRES solves an n x n system in at most n steps."""
+    rng = np.random.default_rng(11)
+    n = 12
+    F = rng.uniform(0.0, 1.0, (n, n)) / n
+    rho = rng.uniform(0.2, 0.9, n)
+    E = rng.standard_normal((n, 2))
+    B, it, _ = ref.gmres(lambda X: F @ X, rho, E, tol=1e-13, restart=n)
+    assert np.all(it <= n)
+    np.testing.assert_allclose(B, ref.solve_direct(F, rho, E), rtol=1e-10, atol=1e-12)
+
+
+def test_gmres_residuals_equal_krylov_least_squares(hemisphere_bowl):
+    """The k-th GMRES residual is the least-squares minimum of ||E - M x|| over
+    the Krylov space span{E, M E, ..., M^(k-1) E} (M = I - F), computed here by
+    brute force; GMRES stops at the first k where that minimum meets tol."""
+    fac, F = hemisphere_bowl
+    E = np.random.default_rng(12).random((fac.N, 1))
+    M = np.eye(fac.N) - F
+    tol = 1e-6
+    _, it, hist = ref.gmres(lambda X: F @ X, 1.0, E, tol=tol, restart=100)
+    e = E[:, 0]
+    best, k_first = [np.linalg.norm(e)], None
+    K = [e / np.linalg.norm(e)]
+    for k in range(1, 9):
+        Q, _ = np.linalg.qr(np.column_stack(K))
+        y, *_ = np.linalg.lstsq(M @ Q, e, rcond=None)
+        best.append(np.linalg.norm(e - M @ Q @ y))
+        if k_first is None and best[-1] <= tol * np.linalg.norm(e):
+            k_first = k
+        nxt = M @ K[-1]
+        K.append(nxt / np.linalg.norm(nxt))
+    h = hist[0]
+    for k in range(1, min(len(h), 9)):
+        assert abs(h[k] - best[k]) <= 1e-6 * best[k] + 1e-13 * best[0]
+    assert it[0] == k_first
