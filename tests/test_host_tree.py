@@ -1,34 +1,19 @@
 """Host logic on the CPU: librad's tree builder (quadtree and octree) gives
 the same facet permutation and leaves as the reference's Algorithm 2."""
-import os
-import shutil
 import subprocess
 
 import numpy as np
 import pytest
 
+from host_build import compile_harness
 from oracle import hmatrix as hm
 from oracle import reference as ref
 from synth import BodySpec, CapSpec, body_mesh, cap_mesh
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PKG = os.path.join(ROOT, "paper_2209_07632_amd")
-
 
 @pytest.fixture(scope="module")
 def harness(tmp_path_factory):
-    hipcc = next((c for c in ("/opt/rocm/bin/hipcc", shutil.which("hipcc")) if c and os.path.exists(c)), None)
-    if hipcc is None:
-        pytest.skip("hipcc not available")
-    if not os.path.exists(os.path.join(PKG, "librad.so")):
-        pytest.fail("librad.so is missing: build it first")
-    exe = str(tmp_path_factory.mktemp("tree") / "tree_harness")
-    cmd = [hipcc, "-O1", "-std=c++17", "-x", "hip", "--offload-host-only", "-fopenmp",
-           "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(PKG, "csrc"),
-           "-Wno-unused-command-line-argument", os.path.join(ROOT, "tests", "host", "tree_harness.cpp"),
-           "-o", exe, "-L" + PKG, "-lrad", "-Wl,-rpath," + PKG]
-    subprocess.run(cmd, check=True, capture_output=True)
-    return exe
+    return compile_harness("tree_harness", tmp_path_factory.mktemp("tree"))
 
 
 def _tree(exe, x, leaf, dims):
