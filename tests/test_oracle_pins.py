@@ -512,3 +512,20 @@ def test_gmres_residuals_equal_krylov_least_squares(hemisphere_bowl):
     for k in range(1, min(len(h), 9)):
         assert abs(h[k] - best[k]) <= 1e-6 * best[k] + 1e-13 * best[0]
     assert it[0] == k_first
+
+
+@pytest.mark.slow
+def test_octree_compresses_closed_body_better_than_quadtree():
+    """Section 4.1 motivates octrees for small bodies: on the closed 5,120-facet
+    body a quadtree on (x, y) puts facets of the top and bottom into one cell,
+    and its compressed matrix is about twice the octree's at eps = 1e-2."""
+    from synth import BodySpec, body_mesh
+    v, f = body_mesh(BodySpec(level=4))
+    fac = ref.Facets(v, f)
+    F = ref.view_factor_matrix(fac, ref.pair_visibility(fac, "raycast"))
+    quad = hm.assemble(F, fac.x[:, :2], eps=1e-2, leaf_size=32)
+    octo = hm.assemble(F, fac.x, eps=1e-2, leaf_size=32)
+    assert octo.nbytes() < 0.6 * quad.nbytes()
+    X = np.random.default_rng(13).random((fac.N, 2))
+    for H in (quad, octo):
+        assert np.linalg.norm(hm.multiply(H, X) - F @ X) / np.linalg.norm(F @ X) <= 1e-2
