@@ -100,13 +100,60 @@ def cn_step(T: np.ndarray, qabs_old: np.ndarray, qabs_new: np.ndarray, dt: float
     return thomas(lower, diag, upper, rhs)
 
 
+def cn_step_balanced(T: np.ndarray, qabs_old: np.ndarray, qabs_new: np.ndarray, dt: float, z: np.ndarray,
+                     k: float, rhoc: float, emiss, H_bottom, newton: int = 3) -> np.ndarray:
+    """A second reading of the column step: the surface node holds no heat and
+    satisfies the radiation boundary condition of section 2 at the new level,
+
+      Qabs' + k (T_1' - T_0') / z_1 = emiss sigma T_0'^4,
+
+    with the emission linearised about T_0^n and the linearisation repeated
+    ``newton`` more times about the latest T_0' (Newton's method on the one
+    nonlinear row; 0 gives the single linearisation).  Nodes 1..M take the
+    Crank-Nicolson average of conduction (half a layer at the bottom, which
+    receives H_bottom); node 1 exchanges with the surface at both levels, the
+    old surface temperature having met the balance with Qabs at its own level.
+    ``qabs_old`` is not needed by this form (it is carried by T_0^n) and is
+    accepted for a common signature."""
+    N, n = T.shape
+    V = cell_volumes(z)
+    V[0] = 0.0
+    g = k / np.diff(z)
+    cap = rhoc * V / dt
+    emiss = np.broadcast_to(np.asarray(emiss, dtype=np.float64), (N,))
+    Hb = np.broadcast_to(np.asarray(H_bottom, dtype=np.float64), (N,))
+    LT = np.zeros_like(T)
+    LT[:, 1:] += g * (T[:, :-1] - T[:, 1:])
+    LT[:, :-1] += g * (T[:, 1:] - T[:, :-1])
+    lower = np.zeros((N, n))
+    upper = np.zeros((N, n))
+    diag = np.broadcast_to(cap, (N, n)).copy()
+    lower[:, 1:] = -0.5 * g
+    diag[:, 1:] += 0.5 * g
+    diag[:, 1:-1] += 0.5 * g[1:]
+    upper[:, 1:-1] = -0.5 * g[1:]
+    rhs = cap * T
+    rhs[:, 1:] += 0.5 * LT[:, 1:]
+    rhs[:, -1] += Hb
+    es = emiss * SIGMA_SB
+    upper[:, 0] = -g[0]
+    t0 = T[:, 0].copy()
+    for _ in range(newton + 1):
+        # emiss sigma T^4 ~ emiss sigma (t0^4 + 4 t0^3 (T - t0))
+        diag[:, 0] = g[0] + 4.0 * es * t0 ** 3
+        rhs[:, 0] = qabs_new + 3.0 * es * t0 ** 4
+        x = thomas(lower, diag, upper, rhs)
+        t0 = x[:, 0]
+    return x
+
+
 def column_energy(T: np.ndarray, z: np.ndarray, rhoc: float) -> np.ndarray:
     """Heat content per unit area of each column, rhoc sum_j V_j T_j (J m^-2)."""
     return rhoc * (T * cell_volumes(z)).sum(axis=1)
 
 
 def simulate(matvec, qdir_steps: np.ndarray, albedo, emiss, T_init: np.ndarray, z: np.ndarray, k: float,
-             rhoc: float, dt: float, H_bottom=0.0, H0=0.0):
+             rhoc: float, dt: float, H_bottom=0.0, H0=0.0, step=cn_step):
     """Algorithm 6.  qdir_steps: (n_steps + 1, N) direct insolation at the
     time levels 0..n_steps; T_init: (N, M+1) initial column temperatures.
 
@@ -114,7 +161,8 @@ def simulate(matvec, qdir_steps: np.ndarray, albedo, emiss, T_init: np.ndarray, 
     Each step:  Qrefl' = F diag(albedo) (Qdir' + Qrefl)
                 QIR'   = F (Qrad + (1 - emiss) QIR)
                 Qabs'  = (1 - albedo) (Qdir' + Qrefl') + emiss QIR'
-    then every column steps with Qabs and Qabs' (``cn_step``) and
+    then every column steps with Qabs and Qabs' (``step``: ``cn_step``, or
+    ``cn_step_balanced``) and
     Qrad' = emiss sigma T_0'^4.  Returns the final state and the surface
     temperature of every level, shape (n_steps + 1, N)."""
     N = qdir_steps.shape[1]
@@ -131,7 +179,7 @@ def simulate(matvec, qdir_steps: np.ndarray, albedo, emiss, T_init: np.ndarray, 
         qrefl_new = matvec(a * (qdir + qrefl))
         qir_new = matvec(qrad + (1.0 - e) * qir)
         qabs_new = (1.0 - a) * (qdir + qrefl_new) + e * qir_new
-        T = cn_step(T, qabs, qabs_new, dt, z, k, rhoc, e, H_bottom)
+        T = step(T, qabs, qabs_new, dt, z, k, rhoc, e, H_bottom)
         qrad = e * SIGMA_SB * T[:, 0] ** 4
         qrefl, qir, qabs = qrefl_new, qir_new, qabs_new
         surface.append(T[:, 0].copy())

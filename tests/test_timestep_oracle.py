@@ -114,16 +114,16 @@ def test_energy_budget_without_emission():
     assert np.max(np.abs((E1 - E0) - budget) / np.abs(budget)) < 1e-9
 
 
-def _radiating_day(dt, M=12, day=86400.0):
-    """Surface temperature after one day of a sinusoidally varying absorbed flux."""
-    z = ts.layer_depths(M, 0.3, 1.1)
+def _radiating_day(dt, M=12, day=86400.0, growth=1.1, step=ts.cn_step):
+    """Column temperatures after one day of a sinusoidally varying absorbed flux."""
+    z = ts.layer_depths(M, 0.3, growth)
     k, rhoc, emiss = 0.01, 1.2e6, 0.95
     n = int(round(day / dt))
     t = np.arange(n + 1) * dt
     qa = 400.0 * (1.0 + 0.5 * np.sin(2.0 * np.pi * t / day))
     T = np.full((1, M + 1), (qa[0] / (emiss * ref.SIGMA_SB)) ** 0.25)
     for i in range(n):
-        T = ts.cn_step(T, qa[i:i + 1], qa[i + 1:i + 2], dt, z, k, rhoc, emiss, 0.0)
+        T = step(T, qa[i:i + 1], qa[i + 1:i + 2], dt, z, k, rhoc, emiss, 0.0)
     return T[0]
 
 
@@ -188,8 +188,9 @@ def test_no_exchange_gives_independent_columns():
         assert np.array_equal(T[0], out["T"][i])
 
 
+@pytest.mark.parametrize("step", [ts.cn_step, ts.cn_step_balanced])
 @pytest.mark.parametrize("H", [0.0, 0.5])
-def test_constant_sun_reaches_two_band_equilibrium(bowl, H):
+def test_constant_sun_reaches_two_band_equilibrium(bowl, H, step):
     """Held under one sun, the lagged one-multiply-per-step recursions settle on
     the solution of the two equilibrium systems of section 5.1 (eqs. Qvis and
     QIR, solved here by Jacobi to 1e-13), with the surface balance
@@ -202,7 +203,7 @@ def test_constant_sun_reaches_two_band_equilibrium(bowl, H):
     k, rhoc, dt, steps = 0.02, 1.0e5, 1000.0, 900
     qd = np.tile(Q, (steps + 1, 1))
     out = ts.simulate(lambda x: F @ x, qd, albedo, emiss, np.full((N, 9), 250.0), z, k, rhoc, dt,
-                      H_bottom=H)
+                      H_bottom=H, step=step)
     eq = ref.equilibrium_temperature(lambda X: F @ X, Q[:, None], albedo, emiss, H=H)
     Qvis, Qir = eq["Q_vis"][:, 0], eq["Q_ir"][:, 0]
     Ts = (((1.0 - albedo) * Qvis + emiss * Qir + H) / (emiss * ref.SIGMA_SB)) ** 0.25
@@ -212,3 +213,48 @@ def test_constant_sun_reaches_two_band_equilibrium(bowl, H):
     assert np.max(np.abs(out["T"] - (Ts[:, None] + H * z[None, :] / k)) / Ts[:, None]) < 1e-11
     if H == 0.0:
         assert np.max(np.abs(Ts - eq["T"][:, 0]) / Ts) < 1e-12
+
+
+# ------------------------------------------------------------ surface held by its balance
+def test_balanced_steady_profile_is_fixed_point():
+    z = ts.layer_depths(25, 2.5, 1.15)
+    k, rhoc, emiss, H = 0.005, 1.1e6, 0.95, 0.03
+    qabs = np.array([0.0, 2.0, 45.0, 400.0])
+    T = _linear_profile(z, qabs, H, k, emiss)
+    T1 = ts.cn_step_balanced(T, qabs, qabs, 3600.0, z, k, rhoc, emiss, H)
+    assert np.max(np.abs(T1 - T) / T) < 1e-12
+
+
+def test_balanced_surface_meets_radiation_condition():
+    """After the step the surface satisfies Qabs' + k (T_1 - T_0) / z_1 =
+    emiss sigma T_0^4 (the radiation boundary condition of section 2) to
+    Newton's convergence, from any start."""
+    rng = np.random.default_rng(0)
+    z = ts.layer_depths(25, 2.5, 1.15)
+    k, emiss = 0.005, 0.95
+    T = rng.uniform(150.0, 300.0, (4, 26))
+    qn = np.array([0.0, 10.0, 200.0, 600.0])
+    x = ts.cn_step_balanced(T, qn, qn, 3600.0, z, k, 1.1e6, emiss, 0.03, newton=8)
+    emit = emiss * ref.SIGMA_SB * x[:, 0] ** 4
+    res = qn + k / z[1] * (x[:, 1] - x[:, 0]) - emit
+    assert np.max(np.abs(res)) <= 1e-10 * np.max(emit)
+
+
+def test_balanced_second_order_in_time():
+    fine = _radiating_day(86400.0 / 4096, step=ts.cn_step_balanced)
+    errs = [np.max(np.abs(_radiating_day(86400.0 / n, step=ts.cn_step_balanced) - fine)) for n in (64, 128, 256)]
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(3.6 < r < 4.4 for r in ratios), ratios
+
+
+def test_surface_readings_agree_as_the_top_layer_thins():
+    """The half-layer surface volume and the surface without heat capacity
+    discretise the same heat equation with the same boundary condition: their
+    surface temperatures after a day differ by an amount that halves with the
+    layer thickness."""
+    diffs = []
+    for M, growth in ((10, 1.2), (20, 1.095), (40, 1.0465)):
+        a = _radiating_day(86400.0 / 1024, M=M, growth=growth)
+        b = _radiating_day(86400.0 / 1024, M=M, growth=growth, step=ts.cn_step_balanced)
+        diffs.append(abs(a[0] - b[0]))
+    assert all(1.8 < diffs[i] / diffs[i + 1] < 2.4 for i in range(2)), diffs
