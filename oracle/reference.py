@@ -47,6 +47,7 @@ def lib():
         L.orc_F_dense.argtypes = [ctypes.c_int64, d, d, d, u8, d]
         L.orc_F_rows.argtypes = [ctypes.c_int64, d, d, d, ctypes.c_int64, d, ctypes.c_int,
                                  ctypes.c_int64, i64, d]
+        L.orc_directed_visibility.argtypes = [ctypes.c_int64, d, d, ctypes.c_int64, d, u8]
         L.orc_matvec_free.argtypes = [ctypes.c_int64, d, d, d, u8, ctypes.c_int64, d,
                                       ctypes.c_int64, d, ctypes.c_int64]
         L.orc_sun_visibility.argtypes = [ctypes.c_int64, d, ctypes.c_int64, d, ctypes.c_int64,
@@ -105,6 +106,15 @@ def pair_visibility(fac: Facets, mode: str = "raycast") -> np.ndarray:
     vis = np.empty((fac.N, fac.N), dtype=np.uint8)
     lib().orc_pair_visibility(fac.N, _p(fac.x), _p(fac.n), fac.N, _p(fac.tri), m,
                               _p(vis, ctypes.c_uint8))
+    return vis
+
+
+def directed_visibility(fac: Facets) -> np.ndarray:
+    """Segment test cast from the row facet for every ordered facing pair (not
+    symmetrised); test use only: it exposes the pairs whose two directions
+    disagree, which the once-per-pair cast of ``pair_visibility`` settles."""
+    vis = np.empty((fac.N, fac.N), dtype=np.uint8)
+    lib().orc_directed_visibility(fac.N, _p(fac.x), _p(fac.n), fac.N, _p(fac.tri), _p(vis, ctypes.c_uint8))
     return vis
 
 

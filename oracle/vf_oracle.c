@@ -212,8 +212,32 @@ void orc_F_dense(int64_t N, const double *x, const double *n, const double *area
 }
 
 /*
+ * Segment test cast from facet i towards facet j for every ordered facing
+ * pair (not symmetrised): vis[i*N + j] = 1 when the pair faces and the open
+ * segment from x_i to x_j misses every other triangle.  The two directions of
+ * one pair can differ where a segment grazes an edge or a vertex; this is the
+ * asymmetry that casting once per unordered pair removes.  Test use only.
+ */
+void orc_directed_visibility(int64_t N, const double *x, const double *n, int64_t ntri,
+                             const double *tri, uint8_t *vis)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < N; ++i) {
+        for (int64_t j = 0; j < N; ++j) {
+            int v = j != i && facing(x + 3 * i, n + 3 * i, x + 3 * j, n + 3 * j);
+            if (v)
+                v = !segment_blocked(i, j, x, ntri, tri);
+            vis[i * N + j] = (uint8_t)v;
+        }
+    }
+}
+
+/*
  * Selected rows of F with visibility computed on the fly:
- *   mode 0: back-face only; mode 1: brute-force segment test against tri.
+ *   mode 0: back-face only; mode 1: brute-force segment test against tri,
+ *   cast from the facet with the smaller index of the pair, exactly as
+ *   orc_pair_visibility does, so these rows equal rows of the dense F built
+ *   from that symmetric V.
  * out is nrows x N row-major.
  */
 void orc_F_rows(int64_t N, const double *x, const double *n, const double *area,
@@ -227,7 +251,8 @@ void orc_F_rows(int64_t N, const double *x, const double *n, const double *area,
             double v = 0.0;
             if (j != i) {
                 v = kernel_entry(x + 3 * i, n + 3 * i, x + 3 * j, n + 3 * j, area[j]);
-                if (v != 0.0 && mode == 1 && segment_blocked(i, j, x, ntri, tri))
+                if (v != 0.0 && mode == 1 &&
+                    segment_blocked(i < j ? i : j, i < j ? j : i, x, ntri, tri))
                     v = 0.0;
             }
             out[r * N + j] = v;

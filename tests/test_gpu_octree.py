@@ -1,6 +1,7 @@
 """GPU parity of the octree build (rad_hmat_build_tree with tree_dims = 3) on
 a closed bilobed body with ray-cast visibility, against the FP64 reference's
-dense F.  Staged: not collected until it has run on a GPU.
+dense F.  The closed body is the zero-block-heavy regime of section 8's
+comet study: most block pairs see nothing (back faces and occlusion).
 
 Tolerances as for the quadtree: the compressed product within eps + 1e-6
 relative L2 of F X; at eps 1e-10 within 1e-9.

@@ -219,6 +219,215 @@ def test_matvec_free_matches_dense():
     np.testing.assert_array_equal(ref.view_factor_rows(fac, rows), F[rows])
 
 
+
+def grazing_pairs(M=200, seed=0):
+    """M far-apart facet pairs (a, b), each with a third triangle whose edge
+    crosses the midpoint of the segment a-b.  Mathematically the segment
+    touches the edge (a hit: edges count); in FP64 the rounding of the two
+    directions of the ray test can disagree, which is what the test needs."""
+    rng = np.random.default_rng(seed)
+    x, n, A, tri = [], [], [], []
+    for m in range(M):
+        off = np.array([100.0 * m, 0.0, 0.0])
+        a = off + rng.uniform(-0.3, 0.3, 3)
+        b = off + np.array([1.0, 0.0, 0.0]) + rng.uniform(-0.3, 0.3, 3)
+        d = b - a
+        p = a + 0.5 * d
+        e = np.cross(d, rng.standard_normal(3))
+        e /= np.linalg.norm(e)
+        q = np.cross(d, e)
+        q /= np.linalg.norm(q)
+        dn = d / np.linalg.norm(d)
+        na = dn + 0.3 * rng.standard_normal(3)
+        nb = -dn + 0.3 * rng.standard_normal(3)
+        v0, v1, v2 = p + 0.25 * e, p - 0.25 * e, p + rng.uniform(0.2, 0.6) * q
+        kn = np.cross(v1 - v0, v2 - v0)
+        small = np.array([[0, 0.01, 0], [0.01, 0, 0], [0, 0, 0.01]])
+        x += [a, b, (v0 + v1 + v2) / 3]
+        n += [na / np.linalg.norm(na), nb / np.linalg.norm(nb), kn / np.linalg.norm(kn)]
+        A += [1e-2, 1e-2, 1e-2]
+        tri += [(a + small).ravel(), (b + small).ravel(), np.concatenate([v0, v1, v2])]
+    return ref.Facets.from_arrays(np.array(x), np.array(n), np.array(A), np.array(tri))
+
+
+def test_raycast_rows_cast_once_per_pair():
+    """Section 3.2, reading 12: rows evaluated on the fly use the same
+    visibility as the dense F, the segment cast once per unordered pair from
+    the smaller index.  On grazing pairs the two directions of the cast
+    disagree, so a row cast from its own facet would differ from F."""
+    fac = grazing_pairs()
+    D = ref.directed_visibility(fac)
+    asym = np.argwhere(np.triu(D != D.T))
+    assert len(asym) >= 10                       # the fixture has teeth
+    V = ref.pair_visibility(fac, "raycast")
+    assert np.array_equal(V, V.T)
+    F = ref.view_factor_matrix(fac, V)
+    rows = np.unique(asym.ravel())
+    Fr = ref.view_factor_rows(fac, rows, "raycast")
+    np.testing.assert_array_equal(Fr, F[rows])
+    # casting each row from its own facet is the row-directed matrix, not F
+    assert not np.array_equal(ref.view_factor_matrix(fac, D)[rows], F[rows])
+    # the smaller index decides: V equals the directed test read from above the diagonal
+    iu = np.triu_indices(fac.N, 1)
+    assert np.array_equal(V[iu], D[iu])
+
+
+def test_raycast_rows_on_terrain():
+    from synth import DemSpec, dem_mesh
+    v, f = dem_mesh(DemSpec(n=16, seed=3))
+    fac = ref.Facets(v, f)
+    F = ref.view_factor_matrix(fac, ref.pair_visibility(fac, "raycast"))
+    assert np.count_nonzero(F) < np.count_nonzero(ref.view_factor_matrix(fac))   # something is occluded
+    rows = np.arange(0, fac.N, 7)
+    np.testing.assert_array_equal(ref.view_factor_rows(fac, rows, "raycast"), F[rows])
+
+
+def test_matvec_free_with_visibility():
+    """The matrix-free product with a visibility matrix equals the pinned
+    dense F with the same visibility, on occluded terrain and on grazing
+    pairs; an all-zero V gives zero, an all-one V the back-face product."""
+    from synth import DemSpec, dem_mesh
+    v, f = dem_mesh(DemSpec(n=12, seed=1))
+    for fac in (ref.Facets(v, f), grazing_pairs(60, seed=1)):
+        V = ref.pair_visibility(fac, "raycast")
+        F = ref.view_factor_matrix(fac, V)
+        X = np.random.default_rng(4).random((fac.N, 3))
+        np.testing.assert_allclose(ref.matvec_free(fac, X, V), F @ X, rtol=1e-13, atol=0)
+        assert np.all(ref.matvec_free(fac, X, np.zeros_like(V)) == 0.0)
+        np.testing.assert_allclose(ref.matvec_free(fac, X, np.ones_like(V)), ref.matvec_free(fac, X),
+                                   rtol=1e-15, atol=0)
+        # a single blocked pair removes exactly its two terms
+        i, j = np.argwhere(np.triu(V, 1))[0]
+        V2 = V.copy()
+        V2[i, j] = V2[j, i] = 0
+        dY = ref.matvec_free(fac, X, V) - ref.matvec_free(fac, X, V2)
+        expect = np.zeros_like(X)
+        expect[i] = F[i, j] * X[j]
+        expect[j] = F[j, i] * X[i]
+        np.testing.assert_allclose(dY, expect, rtol=1e-12, atol=1e-15 * np.abs(F @ X).max())
+
+
+# ---------------------------------------------------------------- Algorithm 4 by hand
+def _two_level(rows, half):
+    """A node over `rows` with two leaf children of `half` rows each."""
+    return hm.Node(idx=np.asarray(rows), depth=0,
+                   children=[hm.Node(idx=np.asarray(rows[:half]), depth=1),
+                             hm.Node(idx=np.asarray(rows[half:]), depth=1)])
+
+
+def _block_of(Fb):
+    """Place an 8 x 8 block at rows 0..7, columns 8..15 of a 16 x 16 F."""
+    F = np.zeros((16, 16))
+    F[:8, 8:] = Fb
+    return F, _two_level(list(range(8)), 4), _two_level(list(range(8, 16)), 4)
+
+
+def test_assembly_choice_by_hand():
+    """Algorithm 4 with eq. nbytes-comparison (value s = 8 bytes, index 4),
+    each expected form and byte count worked out by hand; leaf_size 2, so the
+    8 x 8 pair is not a leaf pair and its 4 x 4 children are."""
+    s, ls = 8, 2
+    rng = np.random.default_rng(7)
+    # all-zero block: a zero block of no bytes
+    F, I, J = _block_of(np.zeros((8, 8)))
+    b = hm.assemble_block(F, I, J, 1e-3, s, ls)
+    assert b.kind == "zero" and b.nbytes == 0
+    # exactly rank one, no zeros: SVD of (m + n) q s + q s = 136 bytes beats
+    # dense 512, CSR 4*9 + 64*12 = 804 and the four dense children (512)
+    u, v = rng.uniform(0.5, 1.5, 8), rng.uniform(0.5, 1.5, 8)
+    F, I, J = _block_of(np.outer(u, v))
+    b = hm.assemble_block(F, I, J, 1e-3, s, ls)
+    assert b.kind == "svd" and b.nbytes == (8 + 8 + 1) * 8
+    U, sv, V = b.data
+    assert U.shape == (8, 1)
+    np.testing.assert_allclose((U * sv) @ V.T, np.outer(u, v), rtol=1e-13)
+    # random full-rank dense block: dense 512 ties with the four dense
+    # children (4 x 128); the tie goes to the simpler dense form
+    F, I, J = _block_of(rng.uniform(0.5, 1.5, (8, 8)))
+    b = hm.assemble_block(F, I, J, 1e-3, s, ls)
+    assert b.kind == "dense" and b.nbytes == 512
+    # eight scattered non-zeros of full rank: CSR 4*9 + 8*12 = 132; children
+    # are CSR 4*5 + 2*12 = 44 each (176); dense 512; SVD would need q = 8
+    Fb = np.zeros((8, 8))
+    perm = [1, 0, 3, 2, 5, 4, 7, 6]
+    for r in range(8):
+        Fb[r, perm[r]] = 1.0 + r
+    F, I, J = _block_of(Fb)
+    b = hm.assemble_block(F, I, J, 1e-3, s, ls)
+    assert b.kind == "csr" and b.nbytes == 132
+    # non-zeros only inside one child (3 on its diagonal): that child is CSR
+    # 4*5 + 3*12 = 56, the rest zero, so the hierarchical form (56) beats
+    # CSR 4*9 + 3*12 = 72; children all CSR or zero coalesce into one CSR
+    # block over the whole pair, of 72 bytes
+    Fb = np.zeros((8, 8))
+    Fb[5, 4], Fb[6, 6], Fb[7, 5] = 2.0, 3.0, 5.0
+    F, I, J = _block_of(Fb)
+    b = hm.assemble_block(F, I, J, 1e-3, s, ls)
+    assert b.kind == "csr" and b.nbytes == 72
+    assert np.array_equal(b.rows, np.arange(8)) and np.array_equal(b.cols, np.arange(8, 16))
+    # a full child (dense 128) and one non-zero in the opposite child (CSR
+    # 4*5 + 12 = 32): hierarchical 160 beats CSR 4*9 + 17*12 = 240, dense 512
+    # and SVD (rank 5: 16*5*8 + 40 = 680); mixed children are not coalesced
+    Fb = np.zeros((8, 8))
+    Fb[:4, :4] = rng.uniform(0.5, 1.5, (4, 4))
+    Fb[6, 5] = 1.0
+    F, I, J = _block_of(Fb)
+    b = hm.assemble_block(F, I, J, 1e-3, s, ls)
+    assert b.kind == "hier" and b.nbytes == 160
+    assert [c.kind for c in b.data] == ["dense", "zero", "zero", "csr"]
+    assert [c.nbytes for c in b.data] == [128, 0, 0, 32]
+    # one full child and three zero children: hierarchical 128 beats CSR
+    # 4*9 + 16*12 = 228; children dense and zero are not coalesced (a dense
+    # block over the pair would cost 512)
+    Fb = np.zeros((8, 8))
+    Fb[4:, 4:] = rng.uniform(0.5, 1.5, (4, 4))
+    F, I, J = _block_of(Fb)
+    b = hm.assemble_block(F, I, J, 1e-3, s, ls)
+    assert b.kind == "hier" and b.nbytes == 128
+    assert [c.kind for c in b.data] == ["zero", "zero", "zero", "dense"]
+    # CSR ties the hierarchical form: a child with 11 non-zeros (dense 128 <
+    # CSR 20 + 11*12), two children with one non-zero (CSR 32 each), one
+    # zero: hierarchical 192 = CSR 4*9 + 13*12 = 192 (rank >= 2, so SVD >= 272);
+    # the tie goes to the simpler CSR form
+    Fb = np.zeros((8, 8))
+    cells = [(r, c) for r in range(4) for c in range(4)][:11]
+    for k, (r, c) in enumerate(cells):
+        Fb[r, c] = 1.0 + 0.1 * k
+    Fb[1, 6], Fb[6, 2] = 4.0, 5.0
+    F, I, J = _block_of(Fb)
+    b = hm.assemble_block(F, I, J, 1e-3, s, ls)
+    assert b.kind == "csr" and b.nbytes == 192
+    # (children all dense tie the dense form exactly, so the dense coalescing
+    # and the tie rule give the same block there)
+
+
+def test_assembly_splits_the_non_leaf_side():
+    """Reading 5: a leaf row node against an internal column node is not a
+    leaf pair while |I||J| exceeds leaf_size^2; only J splits.  An exactly
+    rank-one 8 x 8 block then becomes an SVD of (8 + 8 + 1) * 8 = 136 bytes,
+    not the leaf choice (dense 512)."""
+    rng = np.random.default_rng(9)
+    F, _, J = _block_of(np.outer(rng.uniform(0.5, 1.5, 8), rng.uniform(0.5, 1.5, 8)))
+    leaf_i = hm.Node(idx=np.arange(8), depth=1)
+    b = hm.assemble_block(F, leaf_i, J, 1e-3, 8, 2)
+    assert b.kind == "svd" and b.nbytes == 136
+    # at leaf_size 8 the same pair is a leaf pair (64 <= 8^2): dense 512
+    b = hm.assemble_block(F, leaf_i, J, 1e-3, 8, 8)
+    assert b.kind == "dense" and b.nbytes == 512
+
+
+def test_leaf_choice_tie_goes_to_dense():
+    """A 1 x 4 leaf block with two non-zeros: dense 4*8 = 32 bytes equals CSR
+    4*2 + 2*12 = 32; the tie goes to the simpler dense form.  One more
+    column (dense 40 vs CSR 32) makes CSR strictly smaller."""
+    leaf_i = hm.Node(idx=np.array([0]), depth=0)
+    F = np.zeros((6, 6))
+    F[0, 1], F[0, 3] = 1.0, 2.0
+    b = hm.assemble_block(F, leaf_i, hm.Node(idx=np.array([1, 2, 3, 4]), depth=0), 1e-3, 8, 64)
+    assert b.kind == "dense" and b.nbytes == 32
+    b = hm.assemble_block(F, leaf_i, hm.Node(idx=np.array([1, 2, 3, 4, 5]), depth=0), 1e-3, 8, 64)
+    assert b.kind == "csr" and b.nbytes == 32
+
 # ---------------------------------------------------------------- H-matrix reference
 def test_quadtree_partition():
     v, f = cap_mesh(CAP_SMALL)
