@@ -130,6 +130,32 @@ rad_status rad_hmat_build_tree(const double *verts, int64_t nv, const int32_t *f
 rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const void *X, int64_t ldx,
                            void *Y, int64_t ldy, int32_t order, void *hip_stream);
 
+/*
+ * Allocation-free variant of rad_hmat_matvec, for callers that cannot
+ * allocate device memory at call time (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same product, same
+ * kernels, same arguments and layouts as rad_hmat_matvec with 1 <= R <= 15
+ * (the single-RHS kernels); R is not limited by the matrix's max_rhs.
+ * Its scratch (the projections T = V^T X, t_ld x R values, and for the
+ * original and R-major orders X and Y in tree order, N x R values each) lives
+ * in a file-scope device array of rad_noalloc_scratch_bytes() bytes (8 MiB)
+ * that every device running the library holds until the process ends; the
+ * call allocates nothing (no hipMalloc, no host-side allocating library
+ * call).  Every value read from the scratch is written earlier in the same
+ * call, so nothing needs clearing.  All calls on one device share that
+ * device's array: calls that overlap in time on one device (different
+ * streams, host threads or matrices) race and must be serialised by the
+ * caller.  The first call on a device looks the array's device address up
+ * with that device current (H's device).
+ * Errors: as rad_hmat_matvec; RAD_EINVAL for R outside [1, 15], for a group,
+ * and when the scratch needed exceeds the array (the message states both).
+ */
+rad_status rad_hmat_matvec_noalloc(const rad_hmat *H, int64_t R, int32_t dtype, const void *X, int64_t ldx,
+                                   void *Y, int64_t ldy, int32_t order, void *hip_stream);
+
+/* Size in bytes of the static scratch array of rad_hmat_matvec_noalloc. */
+size_t rad_noalloc_scratch_bytes(void);
+
 typedef struct {
     double rtol;      /* stop column c when ||B^{k+1}-B^k||_2 <= rtol ||E_c||_2 (default 1e-3) */
     int32_t max_iter; /* default 100                                                     */

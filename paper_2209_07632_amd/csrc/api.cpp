@@ -308,6 +308,47 @@ rad_status rad_hmat_matvec(const rad_hmat *H, int64_t R, int32_t dtype, const vo
     });
 }
 
+size_t rad_noalloc_scratch_bytes(void) { return kStaticScratchBytes; }
+
+rad_status rad_hmat_matvec_noalloc(const rad_hmat *H, int64_t R, int32_t dtype, const void *X, int64_t ldx, void *Y,
+                                   int64_t ldy, int32_t order, void *hip_stream) {
+    return guard([&] {
+        check_hmat(H);
+        RAD_REQUIRE(X && Y, "null X or Y");
+        RAD_REQUIRE(dtype == H->dtype, "dtype does not match the matrix");
+        RAD_REQUIRE(R >= 1 && R < kMfmaMinRhs, "R must be in [1, 15] for the allocation-free product");
+        RAD_REQUIRE(H->n_inst == 1, "the allocation-free product takes a single matrix, not a group");
+        check_layout(H, order, R, ldx, "X");
+        check_layout(H, order, R, ldy, "Y");
+        // scratch: projections T (t_ld x R), then, unless X and Y are already
+        // column-major in tree order, X and Y in that layout (N x R each)
+        const size_t es = (size_t)dsize(H->dtype);
+        auto round256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t t_bytes = round256((size_t)std::max(H->t_ld, 1) * (size_t)R * es);
+        const size_t v_bytes = round256((size_t)H->N * (size_t)R * es);
+        const size_t need = t_bytes + (order == RAD_ORDER_TREE ? 0 : 2 * v_bytes);
+        RAD_REQUIRE(need <= kStaticScratchBytes,
+                    "the allocation-free product needs " + std::to_string(need) + " bytes of scratch, more than its " +
+                        std::to_string(kStaticScratchBytes) + "-byte static array");
+        RAD_HIP(hipSetDevice(H->device));
+        unsigned char *base = (unsigned char *)static_scratch(H->device);
+        void *Tb = base, *Xt = base + t_bytes, *Yt = base + t_bytes + v_bytes;
+        hipStream_t s = (hipStream_t)hip_stream;
+        const int64_t N = H->N;
+        if (order == RAD_ORDER_TREE) {
+            mv_apply_ws(H, X, ldx, Y, ldy, R, Tb, s);
+        } else if (order == RAD_ORDER_TREE_RMAJOR) {
+            mm_from_rmajor(H, X, ldx, false, Xt, N, R, s);
+            mv_apply_ws(H, Xt, N, Yt, N, R, Tb, s);
+            mm_to_rmajor(H, Yt, N, false, Y, ldy, R, s);
+        } else {
+            mv_gather(H, X, ldx, Xt, N, R, s);
+            mv_apply_ws(H, Xt, N, Yt, N, R, Tb, s);
+            mv_scatter(H, Yt, N, Y, ldy, R, s);
+        }
+    });
+}
+
 rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int64_t R, int32_t dtype, const void *E,
                      int64_t lde, void *B, int64_t ldb, const rad_solve_opts *opts, rad_solve_info *info,
                      void *hip_stream) {

@@ -8,6 +8,7 @@
 //            Y_L = sum_dense A_LJ X_J + sum_csr A_LJ X_J + sum_lowrank U'_L T_b.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "rad_internal.h"
@@ -241,10 +242,44 @@ void mv_scatter(const rad_hmat *H, const void *src, int64_t lds, void *dst, int6
 }
 
 void mv_apply(const rad_hmat *H, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R, hipStream_t s) {
+    mv_apply_ws(H, X, ldx, Y, ldy, R, H->w_t.p, s);
+}
+
+void mv_apply_ws(const rad_hmat *H, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R, void *Tb,
+                 hipStream_t s) {
     if (H->dtype == RAD_F64)
-        apply_t<double>(H, (const double *)X, ldx, (double *)Y, ldy, R, (double *)H->w_t.p, s);
+        apply_t<double>(H, (const double *)X, ldx, (double *)Y, ldy, R, (double *)Tb, s);
     else
-        apply_t<float>(H, (const float *)X, ldx, (float *)Y, ldy, R, (float *)H->w_t.p, s);
+        apply_t<float>(H, (const float *)X, ldx, (float *)Y, ldy, R, (float *)Tb, s);
+}
+
+// ----------------------------------------------------------------------------
+// Static scratch of the allocation-free product.  Every device that loads
+// this code object holds its own copy of the array until the process ends.
+// In host code the array's name is only a stand-in for the symbol: its
+// device address comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that address is ever passed to kernels.
+// ----------------------------------------------------------------------------
+namespace {
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+void *static_scratch(int device) {
+    RAD_REQUIRE(device >= 0 && device < kMaxDevices, "device ordinal out of range for the static scratch");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[device]) {
+        int cur = -1;
+        RAD_HIP(hipGetDevice(&cur));
+        RAD_REQUIRE(cur == device, "the static scratch is looked up with its device current");
+        void *ptr = nullptr;
+        RAD_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        RAD_REQUIRE(ptr != nullptr, "hipGetSymbolAddress returned no address for the static scratch");
+        g_scratch_addr[device] = ptr;
+    }
+    return g_scratch_addr[device];
 }
 
 void col_norms2(const rad_hmat *H, const void *E, int64_t ld, int64_t R, double *out, hipStream_t s) {

@@ -346,6 +346,14 @@ void launch_insolation(const rad_hmat *H, const double *suns_dev, int64_t R, dou
 void mv_gather(const rad_hmat *H, const void *src, int64_t lds, void *dst, int64_t ldd, int64_t R, hipStream_t s);
 void mv_scatter(const rad_hmat *H, const void *src, int64_t lds, void *dst, int64_t ldd, int64_t R, hipStream_t s);
 void mv_apply(const rad_hmat *H, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R, hipStream_t s);
+// the same product with the projections T in caller-chosen device memory
+// (t_ld x R values of the matrix's dtype)
+void mv_apply_ws(const rad_hmat *H, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R, void *Tb,
+                 hipStream_t s);
+// Device address of the file-scope scratch array of the allocation-free
+// product on `device` (which must be current); looked up once per device.
+constexpr size_t kStaticScratchBytes = size_t(8) << 20;
+void *static_scratch(int device);
 void col_norms2(const rad_hmat *H, const void *E, int64_t ld, int64_t R, double *out, hipStream_t s);
 void solve_update(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *FB,
                   const void *Bold, void *Bnew, int64_t ld, int64_t R, double *norms, hipStream_t s);

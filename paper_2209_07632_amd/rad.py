@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
-EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_build_tree", "rad_hmat_matvec", "rad_solve_opts_default", "rad_solve",
+EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_build_tree", "rad_hmat_matvec",
+           "rad_hmat_matvec_noalloc", "rad_noalloc_scratch_bytes", "rad_solve_opts_default", "rad_solve",
            "rad_insolation", "rad_equilibrium", "rad_hmat_time_phases", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free",
            "rad_last_error", "rad_pod_build", "rad_pod_project", "rad_pod_expand", "rad_mlp_create",
            "rad_mlp_param_count", "rad_mlp_get_params", "rad_mlp_set_params", "rad_mlp_forward", "rad_mlp_loss_grad",
@@ -97,6 +98,10 @@ def load(path: str = LIB_PATH):
     L.rad_hmat_matvec.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int64, vp, ctypes.c_int64,
                                   ctypes.c_int32, vp]
     L.rad_hmat_matvec.restype = ctypes.c_int
+    L.rad_hmat_matvec_noalloc.argtypes = L.rad_hmat_matvec.argtypes
+    L.rad_hmat_matvec_noalloc.restype = ctypes.c_int
+    L.rad_noalloc_scratch_bytes.argtypes = []
+    L.rad_noalloc_scratch_bytes.restype = ctypes.c_size_t
     L.rad_solve.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int64, vp,
                             ctypes.c_int64, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     L.rad_solve.restype = ctypes.c_int
@@ -320,6 +325,25 @@ class HMatrix:
         if Yc.data_ptr() != out.data_ptr():
             out.copy_(Yc)
         return out.reshape(-1) if squeeze else out
+
+    def matvec_noalloc(self, X, out, order="original", R=None):
+        """Y = F-hat X through rad_hmat_matvec_noalloc (1 <= R <= 15): the
+        library allocates nothing; `out` is the caller's preallocated Y in the
+        layout `order` names (for column-major orders it must already be
+        column-major with leading dimension >= N)."""
+        if order == "tree_rmajor":
+            R = int(R if R is not None else X.shape[1])
+            Xc, ldx = _rmajor(X, self.N, R)
+            Yc, ldy = _rmajor(out, self.N, R)
+        else:
+            Xc, ldx = _colmajor(X, self.N)
+            R = Xc.shape[1]
+            Yc, ldy = _colmajor(out, self.N)
+            if Yc.data_ptr() != out.data_ptr():
+                raise ValueError("out must be column-major with leading dimension >= N")
+        _check(load().rad_hmat_matvec_noalloc(self._h, R, self.rad_dtype, ctypes.c_void_p(Xc.data_ptr()), ldx,
+                                              ctypes.c_void_p(Yc.data_ptr()), ldy, ORDER[order], _stream_handle()))
+        return out
 
     def solve(self, E, rho=0.3, rtol=1e-3, max_iter=100, order="original", check_every=1, out=None,
               raise_on_noconv=True, use_graph=True, R=None, refine=False, inner_iters=3, warm=None):
