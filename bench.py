@@ -31,6 +31,40 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+# the metric's accuracy: relative L2 error per sun column against the FP64 oracle
+ACCURACY_TOL = 1e-3
+
+
+def spread_columns(suns, count):
+    """Indices of `count` sun columns spread evenly over the elevation range,
+    the lowest and the highest sun included."""
+    elev = np.arcsin(np.clip(suns[:, 2], -1.0, 1.0))
+    order = np.argsort(elev, kind="stable")
+    pick = np.round(np.linspace(0, len(order) - 1, count)).astype(int)
+    return sorted(set(int(order[i]) for i in pick))
+
+
+def roofline(flops, bytes_, ms, peak_tflops, kernel):
+    """Roofline record of one kernel launch (or one whole product): the bound
+    is the one its arithmetic intensity selects against the chip's peaks."""
+    tf = flops / (ms * 1e-3) / 1e12
+    gbs = bytes_ / (ms * 1e-3) / 1e9
+    intensity = flops / bytes_
+    ridge = peak_tflops * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if intensity < ridge:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    else:
+        roof = {"bound": "mfma", "achieved": tf, "peak": peak_tflops, "unit": "TFLOP/s", "frac": tf / peak_tflops}
+    roof.update({"traffic": None, "kernel": kernel, "ms_per_launch": ms, "flops_per_launch": flops,
+                 "bytes_per_launch": bytes_, "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+                 "tflops": tf, "gbs": gbs})
+    return roof
+
+
+def block_counts(st):
+    """The compressed operator's structure, so that its shape is visible."""
+    return {k: st[k] for k in ("n_leaves", "depth", "n_dense", "n_csr", "n_lowrank", "n_zero", "sum_rank",
+                               "max_rank", "nnz_near", "bytes_dense", "bytes_csr", "bytes_lowrank", "bytes_total")}
 
 
 def log(msg):
@@ -428,7 +462,7 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-3)
     ap.add_argument("--nearfield", default="csr")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cols", type=int, default=2)
+    ap.add_argument("--cpu-cols", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true", help="add a 1 GiB copy for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -596,6 +630,14 @@ def main():
         "hmat_bytes": st["bytes_total"],
         "hmatvec_ms": mv_ms, "hmatvec_gbs": gbs, "hmatvec_tflops": tflops,
         "roofline": roof,
+        # the whole product Y = F-hat X (both phases, all launches) and the
+        # phase-1 projections, each against the peak its intensity selects
+        "roofline_hmatvec": roofline(alg_flops, alg_bytes, mv_ms, peak,
+                                     f"whole H-matmat, {R} columns (projections, split-K sum, expansion)"),
+        "roofline_projections": roofline(
+            p1_flops, st["lowrank_col_elems"] * s_bytes + N * R * s_bytes + st["sum_rank"] * R * s_bytes, ph[0],
+            peak, f"k_proj_mm<{'double' if args.dtype == 'f64' else 'float'}> (phase-1 split-K projections)"),
+        "hmat_blocks": block_counts(st),
         "phase_ms": {"projections": ph[0], "split_k_sum": ph[1], "expansion_jacobi": ph[2]},
         "projections_tflops": p1_tf,
         "autotune": tune,
@@ -619,18 +661,26 @@ def main():
     log(f"plain FP64 single-RHS solves: {single64:.1f} solves/s ({len(cols64)} suns one at a time)")
     result["fp64_single_rhs_solves_per_s"] = single64
     result["speedup_vs_fp64_single_rhs"] = solves_per_s / single64
+    ok = True
     if not args.no_cpu_baseline:
-        cols = list(range(args.cpu_cols))
+        cols = spread_columns(suns, args.cpu_cols)
         Bt = B.double().cpu().numpy()[:, :R]
         Bo = np.empty_like(Bt)
         Bo[perm] = Bt
         Bc = Bo[:, cols]
-        log("CPU reference on sampled columns ...")
+        log(f"CPU reference on sun columns {cols} ...")
         cb, err, it = cpu_baseline(verts, faces, suns, albedo, Bc, cols, S)
         result["cpu_baseline"] = cb
         result["max_rel_err_vs_fp64"] = err
-        log(f"cpu baseline {cb}; GPU vs FP64 reference max rel err {err:.3e}")
+        result["accuracy_columns"] = cols
+        result["accuracy_tol"] = ACCURACY_TOL
+        ok = err <= ACCURACY_TOL
+        result["accuracy_ok"] = ok
+        log(f"cpu baseline {cb}; GPU vs FP64 reference max rel err {err:.3e} over columns {cols}")
     print(json.dumps(result), flush=True)
+    if not ok:
+        log(f"ACCURACY GATE FAILED: max relative error {result['max_rel_err_vs_fp64']:.3e} > {ACCURACY_TOL}")
+        sys.exit(3)
 
 
 if __name__ == "__main__":

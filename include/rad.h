@@ -69,6 +69,27 @@ typedef enum {
  */
 typedef enum { RAD_ORDER_ORIGINAL = 0, RAD_ORDER_TREE = 1, RAD_ORDER_TREE_RMAJOR = 2 } rad_order;
 
+/*
+ * Device-memory hook.  When rad_build_opts.allocator is non-NULL, every device
+ * allocation of the matrix (operator, geometry, ray-casting grid, solve and
+ * product workspace) and of its build's temporaries goes through alloc, and is
+ * returned through free, instead of hipMalloc/hipFree; for example a caching
+ * allocator of the caller's framework.  alloc returns device memory of at
+ * least `bytes` bytes on `device`, 256-byte aligned, or NULL on failure (the
+ * call then fails with RAD_ENOMEM); free receives the same pointer, byte count
+ * and device.  The library copies the struct at build or load time; ctx and
+ * both functions must stay valid until rad_hmat_free of that matrix (and of
+ * groups built from it).  Both are called from the thread that calls into the
+ * library, only during rad_hmat_build*, rad_hmat_load, rad_hmat_group,
+ * rad_insolation (its sun list) and rad_hmat_free; products and solves never
+ * allocate.
+ */
+typedef struct {
+    void *ctx;
+    void *(*alloc)(void *ctx, size_t bytes, int32_t device);
+    void (*free)(void *ctx, void *ptr, size_t bytes, int32_t device);
+} rad_allocator;
+
 typedef struct {
     double tol;           /* compression tolerance eps of Algorithm 3 (> 0)           */
     int32_t leaf_size;    /* quadtree leaf capacity, Algorithm 2 (default 64, <= 4096) */
@@ -85,6 +106,7 @@ typedef struct {
     int32_t max_rank;     /* 0: no limit; else Algorithm 3 gives up above this rank   */
     int32_t lowp;         /* 0: none; RAD_F16 or RAD_BF16: also keep a 16-bit copy of the
                              operator (needs storage RAD_F32) for refined solves       */
+    const rad_allocator *allocator; /* NULL: hipMalloc/hipFree; else the hook above     */
 } rad_build_opts;
 
 /* Fills *opts with the defaults listed above (tol 1e-3). */
@@ -116,6 +138,61 @@ rad_status rad_hmat_build(const double *verts, int64_t nv, const int32_t *faces,
  */
 rad_status rad_hmat_build_tree(const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
                                const rad_build_opts *opts, int32_t tree_dims, rad_hmat **out);
+
+/*
+ * rad_hmat_build from facet geometry instead of a mesh (section 3 states the
+ * view factors of eq. FF-def through centroids, unit normals and areas alone):
+ * host arrays x (N x 3 centroids), n (N x 3 unit normals, |n| within 1e-6 of 1,
+ * used as given), area (N, > 0), all row-major FP64 in the caller's facet
+ * order.  tri_verts (N x 9: the three vertices of facet i's triangle, row-major)
+ * supplies the occluders of ray-cast visibility (section 3.2) and the shadows
+ * of rad_insolation; it may be NULL only with visibility RAD_VIS_BACKFACE, and
+ * then rad_insolation casts no shadows.  tree_dims as rad_hmat_build_tree.
+ * Errors: RAD_EINVAL for null arrays, N < 1, non-finite values, non-unit
+ * normals, areas <= 0, bad options or RAD_VIS_RAYCAST without triangles;
+ * RAD_ENOMEM; RAD_EDEVICE.  *out is NULL on error.
+ */
+rad_status rad_hmat_build_facets(const double *x, const double *n, const double *area, int64_t N,
+                                 const double *tri_verts, const rad_build_opts *opts, int32_t tree_dims,
+                                 rad_hmat **out);
+
+/*
+ * Writes the blocks of F-hat to a binary file at path, for use outside the
+ * library (for example to form F-hat densely on the host).  The blocks are
+ * the leaves of the partition Algorithm 4 chose: every non-zero block of F-hat
+ * once, rows and columns as ranges of the tree order (rad_hmat_perm maps tree
+ * position t to original facet perm[t]); zero blocks are not listed.  All
+ * integers little-endian, values FP64 (the stored values converted exactly):
+ *   char magic[8] = "RADHBLKS"; uint32 version = 1; int32 storage dtype;
+ *   int64 N; int64 nblocks; int32 perm[N];
+ *   per block: int32 kind (1 dense, 2 CSR, 3 low rank), i0, m, j0, n, rank
+ *              (0 unless low rank); int64 nnz (non-zero entries of the block
+ *              of F; for CSR the stored entries); then
+ *     dense:    double A[m * n], column-major (F-hat[i0 + r, j0 + c] = A[r + c m]);
+ *     CSR:      int32 rowptr[m + 1] (rowptr[0] = 0), int32 col[nnz] (0 .. n-1),
+ *               double val[nnz];
+ *     low rank: double U[m * rank], double V[n * rank], both column-major, with
+ *               F-hat block = U V^T (U = U Sigma of Algorithm 3).
+ * Errors: RAD_EINVAL (null, a group), RAD_EDEVICE (file or HIP failure).
+ */
+rad_status rad_hmat_export(const rad_hmat *H, const char *path);
+
+/*
+ * Saves the complete compressed operator (device layout, geometry, ray-casting
+ * grid, 16-bit copy, launch configurations) to a versioned binary file, so
+ * that it is built once and used elsewhere (section 10 names reuse of the
+ * assembled matrix).  rad_hmat_load reads it back onto `device` with
+ * workspace for max_rhs right-hand sides (0: the saved max_rhs); every
+ * product and solve of the loaded matrix equals that of the saved one bit for
+ * bit.  The file holds raw little-endian structures of this library version:
+ * a file from another version or with other structure sizes is refused.
+ * allocator: as rad_build_opts.allocator (NULL: hipMalloc).
+ * Errors: RAD_EINVAL (null, bad file), RAD_ENOMEM, RAD_EDEVICE (file or HIP
+ * failure).  *out is NULL on error.
+ */
+rad_status rad_hmat_save(const rad_hmat *H, const char *path);
+rad_status rad_hmat_load(const char *path, int32_t device, int32_t max_rhs, const rad_allocator *allocator,
+                         rad_hmat **out);
 
 /*
  * Y = F-hat X (Algorithm 5) for R right-hand sides.  X and Y are device
@@ -168,7 +245,37 @@ typedef struct {
     int32_t warm;        /* 1: B holds a starting guess on entry (same layout as the output);
                             each column keeps it only if its first residual is no larger
                             than the cold start's (default 0)                          */
+    int32_t method;      /* a rad_solve_method; default RAD_SOLVE_JACOBI                 */
+    double lam_lo, lam_hi; /* Chebyshev: an interval containing the (real) spectrum of
+                            F-hat; both 0 (default): [-s, s] with s = 1.01 max_i (F-hat 1)_i */
+    int32_t restart;     /* GMRES: Arnoldi steps per cycle (default 30)                  */
 } rad_solve_opts;
+
+/*
+ * Iterations of rad_solve.  The paper relaxes with Jacobi (section 5.1:
+ * O(1) iterations for its systems).  Chebyshev and GMRES are not in the paper:
+ * they serve systems whose spectral radius rho max|lambda(F)| approaches one
+ * (closed or deep bodies in the infrared band, rho = 1), where Jacobi needs
+ * many products.
+ *  RAD_SOLVE_CHEBYSHEV: the three-term Chebyshev iteration for
+ *    (I - rho F-hat) B = E from B^0 = E (Saad, Iterative Methods for Sparse
+ *    Linear Systems, 2nd ed., section 12.1), one product per iteration.  F is
+ *    self-adjoint in the area-weighted inner product (reciprocity, eq. FF-def),
+ *    so its spectrum is real; [lam_lo, lam_hi] must contain it (F-hat's), and
+ *    1 - rho lam_hi > 0.  Column c stops counting at the first iteration whose
+ *    recurrence residual has ||r_c|| <= rtol ||E_c||; all columns step until
+ *    every one has (one scalar recurrence), and B holds that iterate.  Needs a
+ *    scalar rho (rho == NULL), no refinement, no warm start, no group.
+ *  RAD_SOLVE_GMRES: restarted GMRES (same reference, section 6.5) from B = 0,
+ *    every column its own Krylov space, all columns advancing together (one
+ *    multi-column product per Arnoldi step); Arnoldi with classical
+ *    Gram-Schmidt applied twice, Givens rotations on the host.  A column stops
+ *    when its residual estimate meets rtol ||E_c||; each cycle ends with the
+ *    true residual.  info->iters counts each column's Arnoldi steps (products).
+ *    Allocates its Krylov basis ((restart + 1) N R values) for the call.  Needs
+ *    no refinement, no warm start, no group; rho may be per facet.
+ */
+typedef enum { RAD_SOLVE_JACOBI = 0, RAD_SOLVE_CHEBYSHEV = 1, RAD_SOLVE_GMRES = 2 } rad_solve_method;
 
 void rad_solve_opts_default(rad_solve_opts *opts);
 
@@ -266,6 +373,9 @@ typedef struct {
     double flops_per_rhs;      /* 2 (sum (m+n)k + nnz_near): matvec flops per column   */
     int64_t lowrank_row_elems; /* sum over low-rank blocks of m k (U' factors)        */
     int64_t lowrank_col_elems; /* sum over low-rank blocks of n k (V factors)         */
+    int64_t max_panel_cols;    /* widest 64-row tile panel: dense columns plus ranks of the
+                                  blocks covering the tile (the longest reduction of the
+                                  expansion)                                          */
 } rad_hmat_stats;
 
 rad_status rad_hmat_info(const rad_hmat *H, rad_hmat_stats *stats);
@@ -339,6 +449,11 @@ rad_status rad_hmat_group_layout(const rad_hmat *H, int64_t *offsets, int64_t *s
  * N counts the rows of its layout, padding included. */
 int64_t rad_hmat_n(const rad_hmat *H);
 int32_t rad_hmat_dtype(const rad_hmat *H);
+
+/* The 16-bit copy's dtype (0: none) and the right-hand sides the workspace
+ * holds (max_rhs) of H; -1 when H is NULL. */
+int32_t rad_hmat_lowp(const rad_hmat *H);
+int32_t rad_hmat_max_rhs(const rad_hmat *H);
 
 /* perm (host, length N): perm[t] = original index of the facet in tree position t. */
 rad_status rad_hmat_perm(const rad_hmat *H, int32_t *perm);

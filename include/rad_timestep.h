@@ -16,13 +16,23 @@
  *
  * Column scheme (section 5.2 leaves the discretisation to its reference):
  * nodes z_0 = 0 < z_1 < ... < z_M, a finite volume of half a layer on each
- * side of a node (half a layer at the surface and at the bottom); the
- * surface volume receives Q_abs - emiss sigma T_0^4 (the radiation boundary
- * condition of section 2), the bottom volume the fixed flux H.  Conduction
- * and Q_abs are averaged over the two time levels; the emission is averaged
- * with its new value linearised about the old surface temperature.  The
- * M + 1 unknowns of a column form a tridiagonal system, eliminated from the
- * bottom up.
+ * side of nodes 1..M (half a layer at the bottom, which receives the fixed
+ * flux H); conduction is averaged over the two time levels (Crank-Nicolson).
+ * The surface node has one of two readings (rad_ts_params.surface):
+ *  - RAD_TS_SURFACE_HALF_LAYER: a volume of half a layer that receives
+ *    Q_abs - emiss sigma T_0^4 (the radiation boundary condition of section 2),
+ *    Q_abs averaged over the two levels and the emission averaged with its new
+ *    value linearised about the old surface temperature.  Accurate for steps
+ *    short against the top layer's diffusion time (on centimetre top layers
+ *    about 0.3 K up to dt = 0.03 day, 2.8 K at 0.1 day, 24 K at 0.3 day);
+ *  - RAD_TS_SURFACE_BALANCED: no heat capacity at the surface, which meets
+ *    the radiation boundary condition at the new level,
+ *    Q_abs' + k (T_1' - T_0') / z_1 = emiss sigma T_0'^4, solved by Newton's
+ *    method on that one row (newton repeats after the first linearisation);
+ *    accurate at the long steps of a lunation (0.5 K at 0.3 day on the same
+ *    layers).
+ * The M + 1 unknowns of a column form a tridiagonal system, eliminated from
+ * the bottom up.
  *
  * R independent scenarios (for example R different sun sequences over the
  * same terrain) advance together.  Conventions as in rad.h: status codes,
@@ -55,7 +65,13 @@ typedef struct {
     double albedo;         /* in [0, 1)                                                   */
     double emissivity;     /* in (0, 1]                                                   */
     double bottom_flux;    /* H: heat flux entering every column from below (W m^-2)      */
+    int32_t surface;       /* rad_ts_surface: reading of the surface node (default half layer) */
+    int32_t newton;        /* balanced surface: Newton repeats after the first linearisation,
+                              0 .. 16 (3 is enough for 1e-9 K at 0.3-day steps)          */
 } rad_ts_params;
+
+/* Reading of the surface node of every column (see the scheme above). */
+typedef enum { RAD_TS_SURFACE_HALF_LAYER = 0, RAD_TS_SURFACE_BALANCED = 1 } rad_ts_surface;
 
 /* Fields of the state, for rad_ts_read. */
 typedef enum {

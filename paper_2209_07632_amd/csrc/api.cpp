@@ -32,7 +32,7 @@ void alloc_workspace(rad_hmat *H) {
     H->w_thr.alloc(nc);
     H->w_conv.alloc(nc + 1);   // per-column flags, then the stop flag
     RAD_HIP(hipMemset(H->w_conv.p, 0, (nc + 1) * sizeof(int32_t)));
-    if (H->max_rhs >= kMfmaMinRhs && H->n_tiles > 0) H->w_ered.alloc((size_t)H->n_tiles * (size_t)H->max_rhs);
+    if (H->n_tiles > 0) H->w_ered.alloc((size_t)H->n_tiles * (size_t)H->max_rhs);
     if (H->max_rhs >= kMfmaMinRhs && H->n_parts > 0)
         H->w_part.alloc((size_t)H->n_parts * mm_part_rows() * ldr * s);
     H->w_q1.alloc(nr * s);
@@ -43,7 +43,8 @@ void alloc_workspace(rad_hmat *H) {
         H->w_x16.alloc((size_t)H->N * ld16);
         H->w_t16.alloc((size_t)std::max(H->t_ld, 4) * ld16);
     }
-    RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * 3 * nc, hipHostMallocMapped));
+    RAD_HIP(hipHostMalloc((void **)&H->h_norms, sizeof(double) * (rad_hmat::kNormSlots + 1) * nc,
+                          hipHostMallocMapped));
     RAD_HIP(hipHostGetDevicePointer((void **)&H->d_hnorms, H->h_norms, 0));
     for (auto &e : H->ev) RAD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     RAD_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
@@ -75,7 +76,10 @@ static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t 
     double *dn = H->w_norms.p + (int64_t)H->max_rhs * H->n_inst;
     if (a.lowp) {
         lowp_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s);
-    } else if (a.mm) {
+    } else {
+        // multi-RHS (matrix cores) or single-RHS kernels, Jacobi update fused
+        // into the tile kernel either way
+        auto step = a.mm ? mm_jacobi_step : mv_jacobi_step;
         const int64_t nc = a.R * H->n_inst, nc_all = (int64_t)H->max_rhs * H->n_inst;
         double *en = a.first ? H->w_norms.p : nullptr;
         int32_t *conv = H->w_conv.p;
@@ -84,14 +88,11 @@ static void enqueue_iteration(const rad_hmat *H, const IterArgs &a, hipStream_t 
             double *hn = a.hn ? a.hn : H->h_norms;
             ConvTest test{a.first ? 2 : 1, (int)nc, dn, H->w_thr.p, a.rtol2, conv, conv + nc_all};
             test.hdn = H->d_hnorms + (hn - H->h_norms);
-            if (a.first) test.hen = H->d_hnorms + 2 * nc_all;
-            mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s, a.stop, en, &test);
+            if (a.first) test.hen = H->d_hnorms + rad_hmat::kNormSlots * nc_all;
+            step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s, a.stop, en, &test);
             return;
         }
-        mm_jacobi_step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s, nullptr, en, nullptr);
-    } else {
-        mv_apply(H, a.Bold, a.ld, H->w_y.p, a.ld, a.R, s);
-        solve_update(H, a.E, a.rho, a.rho_s, H->w_y.p, a.Bold, a.Bnew, a.ld, a.R, dn, s);
+        step(H, a.E, a.rho, a.rho_s, a.Bold, a.Bnew, a.ld, a.R, dn, s, nullptr, en, nullptr);
     }
     RAD_HIP(hipMemcpyAsync(a.hn ? a.hn : H->h_norms, dn, sizeof(double) * a.R * H->n_inst, hipMemcpyDeviceToHost,
                            s));
@@ -152,6 +153,253 @@ static void wait_event(hipEvent_t e) {
     }
 }
 
+// Y = F-hat X on the working layout of a solve
+static void product_ws(const rad_hmat *H, bool mm, int64_t ld, int64_t R, const void *X, void *Y, hipStream_t s) {
+    if (mm)
+        mm_apply(H, X, Y, ld, R, s);
+    else
+        mv_apply(H, X, ld, Y, ld, R, s);
+}
+
+// max_i (F-hat 1)_i, the largest row sum: one single-RHS product
+static double max_row_sum(const rad_hmat *H, hipStream_t s) {
+    const int64_t N = H->N;
+    std::vector<double> y(N);
+    if (H->dtype == RAD_F64) {
+        std::vector<double> ones(N, 1.0);
+        RAD_HIP(hipMemcpyAsync(H->w_q2.p, ones.data(), N * 8, hipMemcpyHostToDevice, s));
+        mv_apply(H, H->w_q2.p, N, H->w_q1.p, N, 1, s);
+        RAD_HIP(hipMemcpyAsync(y.data(), H->w_q1.p, N * 8, hipMemcpyDeviceToHost, s));
+        RAD_HIP(hipStreamSynchronize(s));
+    } else {
+        std::vector<float> ones(N, 1.0f), yf(N);
+        RAD_HIP(hipMemcpyAsync(H->w_q2.p, ones.data(), N * 4, hipMemcpyHostToDevice, s));
+        mv_apply(H, H->w_q2.p, N, H->w_q1.p, N, 1, s);
+        RAD_HIP(hipMemcpyAsync(yf.data(), H->w_q1.p, N * 4, hipMemcpyDeviceToHost, s));
+        RAD_HIP(hipStreamSynchronize(s));
+        std::copy(yf.begin(), yf.end(), y.begin());
+    }
+    double m = 0.0;
+    for (double v : y) {
+        RAD_REQUIRE(std::isfinite(v), "the operator gives non-finite row sums");
+        m = std::max(m, v);
+    }
+    return m;
+}
+
+// Chebyshev iteration for (I - rho F-hat) B = E from B^0 = E (three-term
+// recurrence of Saad, section 12.1), in the working layout: E in Ein, B in Bw.
+// Returns whether every column met rtol; iters, rel and k as rad_solve_info.
+bool solve_chebyshev(const rad_hmat *H, const rad_solve_opts &o, bool mm, int64_t ld, int64_t R, double rho,
+                     const void *Ein, void *Bw, std::vector<int32_t> &iters, std::vector<double> &rel, int &k,
+                     hipStream_t s) {
+    const int64_t N = H->N;
+    const size_t es = (size_t)dsize(H->dtype);
+    double lam_lo = o.lam_lo, lam_hi = o.lam_hi;
+    RAD_REQUIRE(std::isfinite(lam_lo) && std::isfinite(lam_hi) && lam_lo <= lam_hi, "bad spectral interval");
+    if (lam_lo == 0.0 && lam_hi == 0.0) {
+        // F-hat is F up to the compression error, and F >= 0 has its spectrum
+        // in [-rho(F), rho(F)] with rho(F) <= the largest row sum
+        const double sm = 1.01 * max_row_sum(H, s);
+        lam_lo = -sm;
+        lam_hi = sm;
+    }
+    const double a1 = 1.0 - rho * lam_hi, a2 = 1.0 - rho * lam_lo;
+    const double lo = std::min(a1, a2), hi = std::max(a1, a2);
+    RAD_REQUIRE(lo > 0.0, "the Chebyshev interval of I - rho F-hat must lie in (0, inf): need rho lam < 1");
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+    void *r = H->w_q1.p, *d = H->w_q2.p, *Y = H->w_y.p;
+    double *part = (double *)H->w_red.p;
+    double *en_d = H->w_norms.p, *dn_d = H->w_norms.p + R;
+    RAD_HIP(hipMemcpyAsync(Bw, Ein, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
+    krylov_dots(H, mm, ld, R, Ein, 0, 1, Ein, part, en_d, s);
+    product_ws(H, mm, ld, R, Ein, Y, s);
+    krylov_cheb_init(H, mm, ld, R, rho, theta, Y, r, d, part, s);
+    mm_reduce_cols(H, part, H->n_tiles, R, dn_d, s);
+    std::vector<double> e2(R), d2(R), thr(R);
+    RAD_HIP(hipMemcpyAsync(e2.data(), en_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
+    RAD_HIP(hipMemcpyAsync(d2.data(), dn_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
+    RAD_HIP(hipStreamSynchronize(s));
+    const double rtol2 = o.rtol * o.rtol;
+    bool done = true;
+    auto take = [&](int kk) {
+        done = true;
+        for (int64_t c = 0; c < R; ++c) {
+            RAD_REQUIRE(std::isfinite(d2[c]), "solve produced non-finite values");
+            rel[c] = e2[c] > 0 ? std::sqrt(d2[c] / e2[c]) : std::sqrt(d2[c]);
+            if (iters[c] < 0 && d2[c] <= thr[c]) iters[c] = kk;
+            if (iters[c] < 0) done = false;
+        }
+    };
+    for (int64_t c = 0; c < R; ++c) {
+        RAD_REQUIRE(std::isfinite(e2[c]), "E contains non-finite values");
+        thr[c] = e2[c] > 0 ? rtol2 * e2[c] : rtol2;
+    }
+    take(0);
+    k = 0;
+    if (delta == 0.0) {
+        // a single point: B = E + r / theta (= E + d) is exact
+        std::vector<double> one(R, 1.0);
+        RAD_HIP(hipMemcpyAsync(en_d, one.data(), R * sizeof(double), hipMemcpyHostToDevice, s));
+        krylov_combine(H, mm, ld, R, d, 0, 1, en_d, 1.0, Bw, s);
+        for (auto &it : iters) it = std::max(it, 1);
+        k = 1;
+        return true;
+    }
+    const double sigma = theta / delta;
+    double rk = 1.0 / sigma;
+    while (!done && k < o.max_iter) {
+        ++k;
+        product_ws(H, mm, ld, R, d, Y, s);
+        const double rk1 = 1.0 / (2.0 * sigma - rk);
+        krylov_cheb_step(H, mm, ld, R, rho, rk1 * rk, 2.0 * rk1 / delta, Y, Bw, r, d, part, s);
+        mm_reduce_cols(H, part, H->n_tiles, R, dn_d, s);
+        RAD_HIP(hipMemcpyAsync(d2.data(), dn_d, R * sizeof(double), hipMemcpyDeviceToHost, s));
+        RAD_HIP(hipStreamSynchronize(s));
+        take(k);
+        rk = rk1;
+    }
+    return done;
+}
+
+// Restarted GMRES, all columns advancing together (see rad_solve_method).
+bool solve_gmres(const rad_hmat *H, const rad_solve_opts &o, bool mm, int64_t ld, int64_t R, double rho,
+                 const void *rhov, const void *Ein, void *x, std::vector<int32_t> &iters, std::vector<double> &rel,
+                 int &k, hipStream_t s) {
+    const int64_t N = H->N;
+    const size_t es = (size_t)dsize(H->dtype);
+    const int m = o.restart;
+    const int64_t vstride = N * ld;   // elements between basis vectors
+    const int n_tiles = (int)((N + 63) / 64);
+    AllocScope scope(H->hook(), H->device);
+    DevBuf<unsigned char> Vb((size_t)(m + 1) * (size_t)vstride * es);
+    DevBuf<double> part((size_t)(m + 1) * n_tiles * R), h1((size_t)(m + 1) * R), h2((size_t)(m + 1) * R), nrm(R),
+        yd((size_t)m * R);
+    unsigned char *V = Vb.p;
+    void *w = H->w_q1.p, *r = H->w_q2.p, *Y = H->w_y.p;
+    auto Vj = [&](int j) { return (void *)(V + (size_t)j * vstride * es); };
+    RAD_HIP(hipMemsetAsync(x, 0, (size_t)N * ld * es, s));
+    std::vector<double> e2(R), thr(R), beta(R);
+    krylov_dots(H, mm, ld, R, Ein, 0, 1, Ein, part.p, nrm.p, s);
+    RAD_HIP(hipMemcpyAsync(e2.data(), nrm.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
+    RAD_HIP(hipStreamSynchronize(s));
+    for (int64_t c = 0; c < R; ++c) {
+        RAD_REQUIRE(std::isfinite(e2[c]), "E contains non-finite values");
+        thr[c] = o.rtol * (e2[c] > 0 ? std::sqrt(e2[c]) : 1.0);
+    }
+    std::vector<int32_t> steps(R, 0);
+    std::vector<char> done(R, 0);
+    // per column: Hessenberg ((m + 1) x m, column-major), rotations, rhs g
+    std::vector<double> Hh((size_t)R * (m + 1) * m), cs((size_t)R * m), sn((size_t)R * m), g((size_t)R * (m + 1));
+    std::vector<double> h1h((size_t)(m + 1) * R), h2h((size_t)(m + 1) * R), n2h(R), yh((size_t)m * R);
+    bool first = true;
+    for (;;) {
+        // true residual r = E - (I - rho F) x (x = 0 at the start: r = E)
+        if (first) {
+            RAD_HIP(hipMemcpyAsync(r, Ein, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
+        } else {
+            product_ws(H, mm, ld, R, x, Y, s);
+            krylov_apply_a(H, mm, ld, R, rho, rhov, Ein, x, Y, r, s);
+        }
+        krylov_dots(H, mm, ld, R, r, 0, 1, r, part.p, nrm.p, s);
+        RAD_HIP(hipMemcpyAsync(n2h.data(), nrm.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
+        RAD_HIP(hipStreamSynchronize(s));
+        bool any = false;
+        for (int64_t c = 0; c < R; ++c) {
+            RAD_REQUIRE(std::isfinite(n2h[c]), "solve produced non-finite values");
+            beta[c] = std::sqrt(n2h[c]);
+            rel[c] = e2[c] > 0 ? beta[c] / std::sqrt(e2[c]) : beta[c];
+            if (!done[c] && beta[c] <= thr[c]) {
+                done[c] = 1;
+                iters[c] = steps[c];
+            }
+            if (!done[c] && steps[c] < o.max_iter) any = true;
+        }
+        if (!any) break;
+        first = false;
+        krylov_scale(H, mm, ld, R, r, nrm.p, Vj(0), s);
+        // one cycle
+        std::vector<char> in(R, 0);
+        std::vector<int> mc(R, 0), jc(R, 0);
+        for (int64_t c = 0; c < R; ++c) {
+            if (done[c] || steps[c] >= o.max_iter) continue;
+            in[c] = 1;
+            mc[c] = std::min(m, o.max_iter - steps[c]);
+            std::fill(g.begin() + c * (m + 1), g.begin() + (c + 1) * (m + 1), 0.0);
+            g[c * (m + 1)] = beta[c];
+        }
+        for (int j = 0; j < m; ++j) {
+            bool open = false;
+            for (int64_t c = 0; c < R; ++c) open = open || in[c];
+            if (!open) break;
+            // w = (I - rho F) V_j, orthogonalised against V_0..V_j twice
+            product_ws(H, mm, ld, R, Vj(j), Y, s);
+            krylov_apply_a(H, mm, ld, R, rho, rhov, nullptr, Vj(j), Y, w, s);
+            krylov_dots(H, mm, ld, R, V, vstride, j + 1, w, part.p, h1.p, s);
+            krylov_combine(H, mm, ld, R, V, vstride, j + 1, h1.p, -1.0, w, s);
+            krylov_dots(H, mm, ld, R, V, vstride, j + 1, w, part.p, h2.p, s);
+            krylov_combine(H, mm, ld, R, V, vstride, j + 1, h2.p, -1.0, w, s);
+            krylov_dots(H, mm, ld, R, w, 0, 1, w, part.p, nrm.p, s);
+            krylov_scale(H, mm, ld, R, w, nrm.p, Vj(j + 1), s);
+            RAD_HIP(hipMemcpyAsync(h1h.data(), h1.p, (size_t)(j + 1) * R * sizeof(double), hipMemcpyDeviceToHost, s));
+            RAD_HIP(hipMemcpyAsync(h2h.data(), h2.p, (size_t)(j + 1) * R * sizeof(double), hipMemcpyDeviceToHost, s));
+            RAD_HIP(hipMemcpyAsync(n2h.data(), nrm.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
+            RAD_HIP(hipStreamSynchronize(s));
+            for (int64_t c = 0; c < R; ++c) {
+                if (!in[c]) continue;
+                double *Hc = Hh.data() + (size_t)c * (m + 1) * m + (size_t)j * (m + 1);  // column j
+                double *csc = cs.data() + c * m, *snc = sn.data() + c * m, *gc = g.data() + c * (m + 1);
+                for (int i = 0; i <= j; ++i) Hc[i] = h1h[(size_t)i * R + c] + h2h[(size_t)i * R + c];
+                Hc[j + 1] = std::sqrt(n2h[c]);
+                for (int i = 0; i < j; ++i) {   // earlier rotations on the new column
+                    const double t = csc[i] * Hc[i] + snc[i] * Hc[i + 1];
+                    Hc[i + 1] = -snc[i] * Hc[i] + csc[i] * Hc[i + 1];
+                    Hc[i] = t;
+                }
+                const double dd = std::hypot(Hc[j], Hc[j + 1]);
+                csc[j] = dd > 0 ? Hc[j] / dd : 1.0;
+                snc[j] = dd > 0 ? Hc[j + 1] / dd : 0.0;
+                Hc[j] = dd;
+                Hc[j + 1] = 0.0;
+                gc[j + 1] = -snc[j] * gc[j];
+                gc[j] = csc[j] * gc[j];
+                ++steps[c];
+                jc[c] = j + 1;
+                RAD_REQUIRE(std::isfinite(gc[j + 1]), "solve produced non-finite values");
+                if (std::fabs(gc[j + 1]) <= thr[c] || Hc[j] == 0.0 || j + 1 >= mc[c]) in[c] = 0;
+            }
+        }
+        // x += V y with H y = g (upper triangular, per column)
+        int jmax = 0;
+        std::fill(yh.begin(), yh.end(), 0.0);
+        for (int64_t c = 0; c < R; ++c) {
+            const int n = jc[c];
+            jmax = std::max(jmax, n);
+            const double *Hc = Hh.data() + (size_t)c * (m + 1) * m, *gc = g.data() + c * (m + 1);
+            for (int i = n - 1; i >= 0; --i) {
+                double t = gc[i];
+                for (int l = i + 1; l < n; ++l) t -= Hc[(size_t)l * (m + 1) + i] * yh[(size_t)l * R + c];
+                const double piv = Hc[(size_t)i * (m + 1) + i];
+                yh[(size_t)i * R + c] = piv != 0.0 ? t / piv : 0.0;
+            }
+        }
+        if (jmax > 0) {
+            RAD_HIP(hipMemcpyAsync(yd.p, yh.data(), (size_t)jmax * R * sizeof(double), hipMemcpyHostToDevice, s));
+            krylov_combine(H, mm, ld, R, V, vstride, jmax, yd.p, 1.0, x, s);
+        }
+    }
+    k = 0;
+    bool all = true;
+    for (int64_t c = 0; c < R; ++c) {
+        k = std::max(k, steps[c]);
+        if (!done[c]) {
+            iters[c] = -1;
+            all = false;
+        }
+    }
+    return all;
+}
+
 }  // namespace rad
 
 rad_hmat::~rad_hmat() {
@@ -184,6 +432,7 @@ void rad_build_opts_default(rad_build_opts *o) {
     o->device = 0;
     o->seed = 0x5eed;
     o->verbose = 0;
+    o->allocator = nullptr;
 }
 
 void rad_solve_opts_default(rad_solve_opts *o) {
@@ -197,6 +446,10 @@ void rad_solve_opts_default(rad_solve_opts *o) {
     o->refine = 0;
     o->inner_iters = 3;
     o->warm = 0;
+    o->method = RAD_SOLVE_JACOBI;
+    o->lam_lo = 0.0;
+    o->lam_hi = 0.0;
+    o->restart = 30;
 }
 
 const char *rad_last_error(void) { return g_last_error.c_str(); }
@@ -213,7 +466,71 @@ rad_status rad_hmat_build_tree(const double *verts, int64_t nv, const int32_t *f
         else
             rad_build_opts_default(&o);
         H = new rad_hmat();
+        if (o.allocator) H->allocator = *o.allocator;
+        AllocScope scope(H->hook(), o.device);
         build_hmat(H, verts, nv, faces, nf, o, tree_dims);
+        alloc_workspace(H);
+    });
+    if (st != RAD_OK) {
+        delete H;
+        return st;
+    }
+    *out = H;
+    return RAD_OK;
+}
+
+rad_status rad_hmat_build_facets(const double *x, const double *n, const double *area, int64_t N,
+                                 const double *tri_verts, const rad_build_opts *opts, int32_t tree_dims,
+                                 rad_hmat **out) {
+    if (out) *out = nullptr;
+    rad_hmat *H = nullptr;
+    rad_status st = guard([&] {
+        RAD_REQUIRE(out != nullptr, "null output pointer");
+        rad_build_opts o;
+        if (opts)
+            o = *opts;
+        else
+            rad_build_opts_default(&o);
+        H = new rad_hmat();
+        if (o.allocator) H->allocator = *o.allocator;
+        AllocScope scope(H->hook(), o.device);
+        build_hmat_facets(H, x, n, area, N, tri_verts, o, tree_dims);
+        alloc_workspace(H);
+    });
+    if (st != RAD_OK) {
+        delete H;
+        return st;
+    }
+    *out = H;
+    return RAD_OK;
+}
+
+rad_status rad_hmat_export(const rad_hmat *H, const char *path) {
+    return guard([&] {
+        check_hmat(H);
+        export_blocks(H, path);
+    });
+}
+
+rad_status rad_hmat_save(const rad_hmat *H, const char *path) {
+    return guard([&] {
+        check_hmat(H);
+        save_hmat(H, path);
+    });
+}
+
+rad_status rad_hmat_load(const char *path, int32_t device, int32_t max_rhs, const rad_allocator *allocator,
+                         rad_hmat **out) {
+    if (out) *out = nullptr;
+    rad_hmat *H = nullptr;
+    rad_status st = guard([&] {
+        RAD_REQUIRE(out != nullptr, "null output pointer");
+        RAD_REQUIRE(device >= 0 && max_rhs >= 0, "bad device or max_rhs");
+        H = new rad_hmat();
+        if (allocator) H->allocator = *allocator;
+        AllocScope scope(H->hook(), device);
+        load_hmat(H, path, device, max_rhs);
+        RAD_REQUIRE(H->n_inst == 1 || H->max_rhs >= kMfmaMinRhs, "a group needs max_rhs >= 16");
         alloc_workspace(H);
     });
     if (st != RAD_OK) {
@@ -237,6 +554,8 @@ void rad_hmat_free(rad_hmat *H) {
 
 int64_t rad_hmat_n(const rad_hmat *H) { return H ? H->N : -1; }
 int32_t rad_hmat_dtype(const rad_hmat *H) { return H ? H->dtype : -1; }
+int32_t rad_hmat_lowp(const rad_hmat *H) { return H ? H->lowp : -1; }
+int32_t rad_hmat_max_rhs(const rad_hmat *H) { return H ? H->max_rhs : -1; }
 
 rad_status rad_hmat_info(const rad_hmat *H, rad_hmat_stats *s) {
     return guard([&] {
@@ -365,6 +684,13 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
         else
             rad_solve_opts_default(&o);
         RAD_REQUIRE(o.rtol > 0 && o.max_iter >= 1 && o.check_every >= 1, "bad solve options");
+        RAD_REQUIRE(o.method == RAD_SOLVE_JACOBI || o.method == RAD_SOLVE_CHEBYSHEV || o.method == RAD_SOLVE_GMRES,
+                    "method must be RAD_SOLVE_JACOBI, RAD_SOLVE_CHEBYSHEV or RAD_SOLVE_GMRES");
+        RAD_REQUIRE(o.method == RAD_SOLVE_JACOBI || (!o.refine && !o.warm && H->n_inst == 1),
+                    "Chebyshev and GMRES solves take no refinement, no warm start and no group");
+        RAD_REQUIRE(o.method != RAD_SOLVE_CHEBYSHEV || rho == nullptr, "the Chebyshev solve needs a scalar rho");
+        RAD_REQUIRE(o.method != RAD_SOLVE_GMRES || (o.restart >= 1 && o.restart <= 500),
+                    "restart must be in [1, 500]");
         RAD_REQUIRE(H->n_inst == 1 || (o.order == RAD_ORDER_TREE_RMAJOR && R >= kMfmaMinRhs && !o.warm),
                     "a group solves in RAD_ORDER_TREE_RMAJOR with R >= 16 and without a warm start");
         const int64_t NC = R * H->n_inst;  // convergence is tracked per (instance, column)
@@ -405,12 +731,49 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 RAD_HIP(hipMemcpyAsync(H->w_rho.p, rho, N * es, hipMemcpyDeviceToDevice, s));
             rho_t = H->w_rho.p;
         }
+        // B (working layout, in the buffer bk) back to the caller's layout
+        auto copy_out = [&](void *Bk) {
+            if (mm && rmaj) {
+                if (Bk != B) RAD_HIP(hipMemcpyAsync(B, Bk, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
+            } else if (mm) {
+                mm_from_rmajor(H, Bk, ld, o.order == RAD_ORDER_ORIGINAL, B, ldb, R, s);
+            } else if (rmaj) {
+                mm_to_rmajor(H, Bk, N, false, B, ldb, R, s);
+            } else if (o.order == RAD_ORDER_TREE) {
+                RAD_HIP(hipMemcpy2DAsync(B, ldb * es, Bk, N * es, N * es, R, hipMemcpyDeviceToDevice, s));
+            } else {
+                mv_scatter(H, Bk, N, B, ldb, R, s);
+            }
+            RAD_HIP(hipStreamSynchronize(s));
+        };
+        if (o.method != RAD_SOLVE_JACOBI) {
+            std::vector<int32_t> iters(R, -1);
+            std::vector<double> rel(R, 0.0);
+            int k = 0;
+            const bool ok = o.method == RAD_SOLVE_CHEBYSHEV
+                                ? solve_chebyshev(H, o, mm, ld, R, rho_scalar, Ein, P[0], iters, rel, k, s)
+                                : solve_gmres(H, o, mm, ld, R, rho_scalar, rho_t, Ein, P[0], iters, rel, k, s);
+            copy_out(P[0]);
+            if (info) {
+                if (info->iters) std::copy(iters.begin(), iters.end(), info->iters);
+                if (info->rel_change) std::copy(rel.begin(), rel.end(), info->rel_change);
+                info->total_iters = k;
+                info->inner_iters = 0;
+                info->warm_columns = 0;
+            }
+            if (!ok) {
+                conv = RAD_ENOCONV;
+                set_error(o.method == RAD_SOLVE_CHEBYSHEV ? "Chebyshev reached max_iter before rtol"
+                                                          : "GMRES reached max_iter before rtol");
+            }
+            return;
+        }
         double *enorm_d = H->w_norms.p;
-        // Multi-RHS Jacobi tested every iteration runs one iteration ahead of
-        // the host; the device skips that iteration once every column has met
-        // rtol (the same test in the same arithmetic as the host's below).
-        // The first iteration (from E, or from the warm guess) also sums ||E||^2.
-        const bool ahead = mm && !o.refine && o.check_every == 1;
+        // Jacobi tested every iteration runs one iteration ahead of the host;
+        // the device skips that iteration once every column has met rtol (the
+        // same test in the same arithmetic as the host's below).  The first
+        // iteration (from E, or from the warm guess) also sums ||E||^2.
+        const bool ahead = !o.refine && o.check_every == 1;
         const bool fused_en = ahead;
         if (!fused_en) {
             if (mm)
@@ -419,7 +782,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 col_norms2(H, Ein, N, R, enorm_d, s);
         }
         const int64_t nc_all = (int64_t)H->max_rhs * H->n_inst;
-        double *h_en = H->h_norms + 2 * nc_all;
+        double *h_en = H->h_norms + rad_hmat::kNormSlots * nc_all;
         int32_t *conv_d = H->w_conv.p, *stop_d = H->w_conv.p + nc_all;
         const double rtol2 = o.rtol * o.rtol;
         if (ahead && !fused_en) conv_init(enorm_d, rtol2, NC, H->w_thr.p, conv_d, stop_d, s);
@@ -612,32 +975,41 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 for (int64_t c = 0; c < NC; ++c) cv[c] = iters[c] >= 0;
                 RAD_HIP(hipMemcpyAsync(conv_d, cv.data(), NC * sizeof(int32_t), hipMemcpyHostToDevice, s));
             }
-            double *slot[2] = {H->h_norms, H->h_norms + nc_all};
+            constexpr int S = rad_hmat::kNormSlots;
+            auto slot = [&](int kk) { return H->h_norms + (int64_t)(kk % S) * nc_all; };
             auto enqueue = [&](int kk) {
                 // (the first iteration of a cold start is never skipped)
                 const bool first = kk == 1 && fused_en;
                 IterArgs a{mm, false, R, ld, Ein, rho_t, kk == 1 ? Ein : P[kk % 2], P[(kk - 1) % 2], rho_scalar,
-                           slot[kk % 2], first ? nullptr : stop_d, first, rtol2};
+                           slot(kk), first ? nullptr : stop_d, first, rtol2};
                 if (o.use_graph)
                     RAD_HIP(hipGraphLaunch(iteration_graph(Hm, a), s));
                 else
                     enqueue_iteration(H, a, s);
-                RAD_HIP(hipEventRecord(H->ev[kk % 2], s));
+                RAD_HIP(hipEventRecord(H->ev[kk % S], s));
             };
-            // Iteration k + 1 is normally queued behind the one in flight.  When
-            // every open column's ratio q = |dB|^2 / thr, extrapolated
-            // geometrically from its last two iterations, is predicted to fall
-            // below 1/4 in the iteration in flight, nothing is queued behind it
-            // (a wrong guess costs one host round trip, never a result).
+            // Up to `depth` iterations are queued behind the one the host waits
+            // for: one on the matrix cores (an iteration there outlasts the
+            // host's test), S - 1 on the single-RHS kernels (whose iterations
+            // are short against a host round trip; those queued past
+            // convergence cost only their launches).  When every open column's
+            // ratio q = |dB|^2 / thr, extrapolated geometrically from its last
+            // two iterations, is predicted to fall below 1/4 in the iteration
+            // in flight, nothing is queued behind it (a wrong guess costs one
+            // host round trip, never a result).  Iteration kk writes its
+            // changes to slot kk mod S, which the host has read before kk is
+            // queued (queued <= k + depth + 1 <= k + S).
+            const int depth = mm ? 1 : S - 1;
             int queued = k;
             bool predicted = false;
             std::vector<double> q_prev(NC, 0.0);
             while (!done && k < o.max_iter) {
-                while (queued < std::min(k + 2, o.max_iter) && !(queued == k + 1 && predicted)) enqueue(++queued);
-                wait_event(H->ev[(k + 1) % 2]);
+                while (queued < std::min(k + depth + 1, o.max_iter) && !(queued >= k + 1 && predicted))
+                    enqueue(++queued);
+                wait_event(H->ev[(k + 1) % S]);
                 ++k;
                 take_enorm();
-                const double *d2 = slot[k % 2];
+                const double *d2 = slot(k);
                 done = true;
                 predicted = k >= 2;
                 for (int64_t c = 0; c < NC; ++c) {
@@ -677,19 +1049,7 @@ rad_status rad_solve(const rad_hmat *H, const void *rho, double rho_scalar, int6
                 }
             }
         }
-        void *Bk = P[(k - 1) % 2];
-        if (mm && rmaj) {
-            if (Bk != B) RAD_HIP(hipMemcpyAsync(B, Bk, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
-        } else if (mm) {
-            mm_from_rmajor(H, Bk, ld, o.order == RAD_ORDER_ORIGINAL, B, ldb, R, s);
-        } else if (rmaj) {
-            mm_to_rmajor(H, Bk, N, false, B, ldb, R, s);
-        } else if (o.order == RAD_ORDER_TREE) {
-            RAD_HIP(hipMemcpy2DAsync(B, ldb * es, Bk, N * es, N * es, R, hipMemcpyDeviceToDevice, s));
-        } else {
-            mv_scatter(H, Bk, N, B, ldb, R, s);
-        }
-        RAD_HIP(hipStreamSynchronize(s));
+        copy_out(P[(k - 1) % 2]);
         if (info) {
             if (info->iters) std::copy(iters.begin(), iters.end(), info->iters);
             if (info->rel_change) std::copy(rel.begin(), rel.end(), info->rel_change);
@@ -779,6 +1139,7 @@ rad_status rad_insolation(const rad_hmat *H, int64_t R, const double *suns, doub
         }
         RAD_HIP(hipSetDevice(H->device));
         hipStream_t s = (hipStream_t)hip_stream;
+        AllocScope scope(H->hook(), H->device);
         DevBuf<double> d_s((size_t)3 * R);
         RAD_HIP(hipMemcpy(d_s.p, suns, sizeof(double) * 3 * R, hipMemcpyHostToDevice));
         launch_insolation(H, d_s.p, R, flux, H->dtype, Q, ldq, order, s);

@@ -626,6 +626,24 @@ struct Builder {
             }
         }
         std::sort(finals.begin(), finals.end());
+        // the block table kept for rad_hmat_export
+        std::vector<int32_t> blk_of(bp.size(), -1);
+        H->blocks.clear();
+        H->pieces.clear();
+        for (size_t b = 0; b < finals.size(); ++b) {
+            const BlockPair &q = bp[finals[b]];
+            blk_of[finals[b]] = (int32_t)b;
+            BlockRec r{};
+            r.kind = q.kind;
+            r.i0 = H->nodes[q.I].start;
+            r.m = H->nodes[q.I].size;
+            r.j0 = H->nodes[q.J].start;
+            r.n = H->nodes[q.J].size;
+            r.rank = q.kind == BK_LOWRANK ? q.rank : 0;
+            r.nnz = q.nnz;
+            r.group = -1;
+            H->blocks.push_back(r);
+        }
 
         struct Copy {
             int64_t src_off;  // candidate pool (doubles)
@@ -661,6 +679,8 @@ struct Builder {
             for (int64_t p : by_col[J]) {
                 const BlockPair &b = bp[p];
                 const TreeNode &rn = H->nodes[b.I];
+                H->blocks[blk_of[p]].group = (int32_t)groups.size();
+                H->blocks[blk_of[p]].vcol = col;
                 copies.push_back(Copy{b.cand_off + (int64_t)rn.size * b.rank, b.cand_level, cn.size, b.rank,
                                       cn.size, vfill + (int64_t)col * g.ld, g.ld});
                 t_rows.push_back({p, t_fill + col});
@@ -699,6 +719,7 @@ struct Builder {
             const BlockPair &b = bp[p];
             const TreeNode &rn = H->nodes[b.I], &cn = H->nodes[b.J];
             int64_t ptr_off = 0;
+            if (b.kind == BK_CSR) H->blocks[blk_of[p]].ptr_off = ptr_fill;
             if (b.kind == BK_DENSE) {
                 H->stats.n_dense++;
                 H->stats.bytes_dense += dense_bytes(rn.size, cn.size);
@@ -773,6 +794,8 @@ struct Builder {
                 csr_val_base[t] = csr_nnz_total;
                 csr_nnz_total += acc;
             }
+            // (csr_ptr_of lists the CSR blocks in the order of csr_tiles)
+            for (int64_t t = 0; t < ntile_csr; ++t) H->blocks[blk_of[csr_ptr_of[t].first]].val_base = csr_val_base[t];
         }
 
         // panels (16-byte vector loads need panel_off aligned to 64 elements)
@@ -789,6 +812,7 @@ struct Builder {
             std::stable_sort(v.begin(), v.end(), [](const PT &a, const PT &b) { return a.type < b.type; });
             int64_t K = 0;
             for (const PT &pt : v) K += pt.ncol;
+            H->stats.max_panel_cols = std::max<int64_t>(H->stats.max_panel_cols, K);
             int64_t kpad = (K + 31) / 32 * 32;
             TileInfo ti{};
             ti.panel_off = vfill;
@@ -799,6 +823,7 @@ struct Builder {
             for (const PT &pt : v) {
                 const BlockPair &b = bp[pt.p];
                 int64_t dst = vfill + col * 64 + pt.r_lo;
+                H->pieces.push_back(BlockPiece{blk_of[pt.p], tl, (int32_t)col, pt.r_lo, pt.r_hi});
                 if (pt.type == TASK_DENSE) {
                     dense_desc.insert(dense_desc.end(), {tl * 64 + pt.r_lo, pt.r_hi - pt.r_lo, pt.src_row0, pt.ncol, 64, 0});
                     dense_offs.push_back(dst);
@@ -944,13 +969,10 @@ struct Builder {
 
 }  // namespace
 
-void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
-                const rad_build_opts &o, int tree_dims) {
-    auto t0 = std::chrono::steady_clock::now();
-    RAD_REQUIRE(verts && faces, "null mesh pointer");
+namespace {
+
+void check_opts(const rad_build_opts &o, int tree_dims) {
     RAD_REQUIRE(tree_dims == 2 || tree_dims == 3, "tree_dims must be 2 (quadtree) or 3 (octree)");
-    RAD_REQUIRE(nv >= 3 && nf >= 1, "mesh needs nv >= 3 and nf >= 1");
-    RAD_REQUIRE(nf < (int64_t)1 << 31, "too many faces");
     RAD_REQUIRE(o.tol > 0.0 && std::isfinite(o.tol), "tol must be positive");
     RAD_REQUIRE(o.leaf_size >= 1 && o.leaf_size <= 4096, "leaf_size must be in [1, 4096]");
     RAD_REQUIRE(o.storage == RAD_F64 || o.storage == RAD_F32, "storage must be RAD_F64 or RAD_F32");
@@ -961,7 +983,14 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
     RAD_REQUIRE(o.max_rhs >= 1, "max_rhs must be >= 1");
     RAD_REQUIRE(o.lowp == 0 || ((o.lowp == RAD_F16 || o.lowp == RAD_BF16) && o.storage == RAD_F32),
                 "lowp must be 0, RAD_F16 or RAD_BF16, with storage RAD_F32");
+}
 
+// Everything after the facet geometry: x, n (nf x 3) and A (nf) in the
+// caller's facet order; tri (nf x 9, the facets' own triangles, same order)
+// for ray casting and shadows, or empty (no occluders).
+void build_from_geometry(rad_hmat *H, std::vector<double> &x, std::vector<double> &n, std::vector<double> &A,
+                         const std::vector<double> &tri_orig, int64_t nf, const rad_build_opts &o, int tree_dims,
+                         std::chrono::steady_clock::time_point t0) {
     Builder B;
     B.log.on = o.verbose != 0;
     B.H = H;
@@ -973,9 +1002,6 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
     H->max_rhs = o.max_rhs;
     H->leaf_size = o.leaf_size;
 
-    // all host-side validation happens before the first HIP call
-    std::vector<double> x, n, A;
-    facet_geometry(verts, nv, faces, nf, x, n, A);
     RAD_HIP(hipSetDevice(o.device));
 
     QuadBuilder qb;
@@ -1018,12 +1044,13 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
     B.geom.a = H->d_a.p;
     B.geom.vis = nullptr;
     {
-        std::vector<double> tri(9 * nf);
-        for (int64_t t = 0; t < nf; ++t) {
-            int32_t f = H->perm[t];
-            for (int v = 0; v < 3; ++v)
-                for (int k = 0; k < 3; ++k) tri[9 * t + 3 * v + k] = verts[3 * (int64_t)faces[3 * f + v] + k];
-        }
+        std::vector<double> tri(tri_orig.size());
+        if (!tri.empty())
+            for (int64_t t = 0; t < nf; ++t) {
+                int32_t f = H->perm[t];
+                std::copy(tri_orig.begin() + 9 * (int64_t)f, tri_orig.begin() + 9 * (int64_t)f + 9,
+                          tri.begin() + 9 * t);
+            }
         build_grid(H, tri);
     }
     B.log("grid");
@@ -1058,6 +1085,49 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
                      (long long)s.bytes_dense, (long long)s.bytes_csr, (long long)s.bytes_lowrank,
                      (long long)s.sum_rank, s.max_rank, s.build_seconds);
     }
+}
+
+}  // namespace
+
+void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
+                const rad_build_opts &o, int tree_dims) {
+    auto t0 = std::chrono::steady_clock::now();
+    RAD_REQUIRE(verts && faces, "null mesh pointer");
+    RAD_REQUIRE(nv >= 3 && nf >= 1, "mesh needs nv >= 3 and nf >= 1");
+    RAD_REQUIRE(nf < (int64_t)1 << 31, "too many faces");
+    check_opts(o, tree_dims);
+    // all host-side validation happens before the first HIP call
+    std::vector<double> x, n, A;
+    facet_geometry(verts, nv, faces, nf, x, n, A);
+    std::vector<double> tri(9 * nf);
+    for (int64_t f = 0; f < nf; ++f)
+        for (int v = 0; v < 3; ++v)
+            for (int k = 0; k < 3; ++k) tri[9 * f + 3 * v + k] = verts[3 * (int64_t)faces[3 * f + v] + k];
+    build_from_geometry(H, x, n, A, tri, nf, o, tree_dims, t0);
+}
+
+void build_hmat_facets(rad_hmat *H, const double *xc, const double *nc, const double *area, int64_t N,
+                       const double *tri_verts, const rad_build_opts &o, int tree_dims) {
+    auto t0 = std::chrono::steady_clock::now();
+    RAD_REQUIRE(xc && nc && area, "null facet array");
+    RAD_REQUIRE(N >= 1 && N < (int64_t)1 << 31, "N must be in [1, 2^31)");
+    check_opts(o, tree_dims);
+    RAD_REQUIRE(tri_verts || o.visibility == RAD_VIS_BACKFACE,
+                "ray-cast visibility needs the facets' triangles (tri_verts)");
+    std::vector<double> x(xc, xc + 3 * N), n(nc, nc + 3 * N), A(area, area + N), tri;
+    for (int64_t i = 0; i < N; ++i) {
+        for (int k = 0; k < 3; ++k)
+            RAD_REQUIRE(std::isfinite(x[3 * i + k]) && std::isfinite(n[3 * i + k]),
+                        "facet " + std::to_string(i) + " has a non-finite centroid or normal");
+        const double len = std::sqrt(n[3 * i] * n[3 * i] + n[3 * i + 1] * n[3 * i + 1] + n[3 * i + 2] * n[3 * i + 2]);
+        RAD_REQUIRE(std::fabs(len - 1.0) <= 1e-6, "facet " + std::to_string(i) + " has a normal that is not unit length");
+        RAD_REQUIRE(std::isfinite(A[i]) && A[i] > 0.0, "facet " + std::to_string(i) + " has a non-positive area");
+    }
+    if (tri_verts) {
+        tri.assign(tri_verts, tri_verts + 9 * N);
+        for (double v : tri) RAD_REQUIRE(std::isfinite(v), "non-finite triangle vertex");
+    }
+    build_from_geometry(H, x, n, A, tri, N, o, tree_dims, t0);
 }
 
 }  // namespace rad

@@ -47,6 +47,8 @@ extern "C" rad_status rad_hmat_group(const rad_hmat *const *parts, int32_t count
         RAD_HIP(hipSetDevice(P0.device));
         const size_t es = (size_t)dsize(P0.dtype);
         G = new rad_hmat();
+        G->allocator = P0.allocator;   // the parts' hook (if any) also serves the group
+        AllocScope scope(G->hook(), P0.device);
         G->device = P0.device;
         G->dtype = P0.dtype;
         G->lowp = P0.lowp;
@@ -214,6 +216,7 @@ extern "C" rad_status rad_hmat_group(const rad_hmat *const *parts, int32_t count
             S.flops_per_rhs += p.flops_per_rhs;
             S.lowrank_row_elems += p.lowrank_row_elems;
             S.lowrank_col_elems += p.lowrank_col_elems;
+            S.max_panel_cols = std::max(S.max_panel_cols, p.max_panel_cols);
         }
         S.bytes_total = (int64_t)(G->d_vals.bytes() + G->d_csr_idx.bytes() + G->d_csr_ptr.bytes() +
                                   G->d_tiles.bytes() + G->d_brow.bytes() + G->d_tile_tasks.bytes() +

@@ -59,6 +59,16 @@ __device__ __forceinline__ float pow2_scale(float max_abs) {
     return ldexpf(1.0f, -e);
 }
 
+// Dispatch index -> work index such that each of the 8 XCDs (which receive
+// workgroups round-robin) gets one contiguous run of work items: neighbouring
+// tiles gather the same operand rows and then share that XCD's L2.
+__device__ __forceinline__ int xcd_remap16(int L, int total) {
+    constexpr int kXcd = 8;
+    const int q = total / kXcd, rem = total % kXcd;
+    const int x = L % kXcd, slot = L / kXcd;
+    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + slot;
+}
+
 template <class H>
 constexpr bool kUnitScale = false;
 template <>
@@ -305,13 +315,14 @@ struct WideStage {
 };
 
 // (three workgroups per CU fit its LDS; the register budget is held to match)
+// (tile_list: the tiles to compute, one per workgroup; nullptr: every tile)
 template <bool kFused>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_tile_mm16w(const TileInfo *tiles, const int32_t *brow, const __bf16 *vals16,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_tile_mm16w(const TileInfo *tiles, const int32_t *tile_list, const int32_t *brow, const __bf16 *vals16,
                                                      const __bf16 *X16, const __bf16 *T16, int64_t ld16,
                                                      const float *X, int64_t ldr, int R, int64_t N, float *Y,
                                                      const float *E, const float *rho, float rho_s,
                                                      double *partial) {
-    const int tile = blockIdx.x;
+    const int tile = tile_list ? tile_list[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tiles[tile];
     const int64_t tile0 = (int64_t)tile * TM;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -387,6 +398,134 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
         if (128 * h < R)
             tile_epilogue<float, kFused, TM, 128, 128 + 4>(sC, smem, tile, tile0, 128 * h, ldr, R, N, Y, E, X, rho,
                                                            rho_s, partial);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 wide expansion of two consecutive 64-row tiles whose panels multiply
+// the same operand rows (identical brow lists: the two halves of a 128-facet
+// leaf): one workgroup computes the 128 x R block, so every gathered operand
+// chunk staged in LDS feeds twice the matrix-core work of the one-tile
+// kernel.  Wave w owns rows 64 (w & 1) .. + 63 and columns 128 (w >> 1) ..
+// + 127.  Otherwise as k_tile_mm16w: chunks of 32 with two register stages in
+// flight, epilogue per 64 x 128 quarter.
+// ---------------------------------------------------------------------------
+struct PairStage {
+    bf16x8 a0, a1;     // panel rows t >> 2 of the first and of the second tile
+    bf16x8 b[4];       // operand rows 4 (t >> 5) + i, columns 8 (t & 31) .. + 7
+    __device__ __forceinline__ void fetch(const __bf16 *pa, const __bf16 *pb, const WideStage::Rows &rw,
+                                          const __bf16 *X16, const __bf16 *T16, int64_t ld16, int t) {
+        a0 = *(const bf16x8 *)(pa + t * 8);
+        a1 = *(const bf16x8 *)(pb + t * 8);
+        const int c8 = (t & 31) * 8;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int32_t v = rw.v[i];
+            const __bf16 *p = (v >= 0 ? X16 + (int64_t)v * ld16 : T16 + (int64_t)(-1 - v) * ld16) + c8;
+            b[i] = c8 < ld16 ? *(const bf16x8 *)p : bf16x8{};
+        }
+    }
+    __device__ __forceinline__ void commit(__bf16 (*sA)[WLDK], __bf16 (*sB)[WLDK], int t) {
+        *(bf16x8 *)&sA[t >> 2][(t & 3) * 8] = a0;
+        *(bf16x8 *)&sA[TM + (t >> 2)][(t & 3) * 8] = a1;
+        const int kq = t >> 5, c8 = (t & 31) * 8;
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            bf16x4 q = {b[0][j], b[1][j], b[2][j], b[3][j]};
+            *(bf16x4 *)&sB[c8 + j][4 * kq] = q;
+        }
+    }
+};
+
+template <bool kFused>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_tile_mm16p(const TileInfo *tiles, const int32_t *first_tiles, const int32_t *brow, const __bf16 *vals16,
+             const __bf16 *X16, const __bf16 *T16, int64_t ld16, const float *X, int64_t ldr, int R, int64_t N,
+             float *Y, const float *E, const float *rho, float rho_s, double *partial) {
+    const int tile = first_tiles[xcd_remap16(blockIdx.x, gridDim.x)];
+    const TileInfo ti = tiles[tile], tj = tiles[tile + 1];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    constexpr int kPipe = (2 * 2 * TM * WLDK + 2 * WN * WLDK) * 2;
+    constexpr int kOut = TM * (128 + 4) * 4;
+    __shared__ __align__(16) unsigned char smem[kPipe > kOut ? kPipe : kOut];
+    __bf16 (*sA)[2 * TM][WLDK] = (__bf16 (*)[2 * TM][WLDK])smem;
+    __bf16 (*sB)[WN][WLDK] = (__bf16 (*)[WN][WLDK])(smem + 2 * 2 * TM * WLDK * sizeof(__bf16));
+    f32x4 acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    const int lr = lane & 15, k0 = 8 * (lane >> 4);
+    const int wr = (w & 1) * TM, wc = (w >> 1) * 128;
+    auto mma = [&](const __bf16 (*A)[WLDK], const __bf16 (*B)[WLDK]) {
+        bf16x8 av[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = *(const bf16x8 *)&A[wr + i * 16 + lr][k0];
+#pragma unroll
+        for (int jh = 0; jh < 2; ++jh) {
+            bf16x8 bv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = *(const bf16x8 *)&B[wc + (4 * jh + j) * 16 + lr][k0];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][4 * jh + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][4 * jh + j], 0, 0, 0);
+        }
+    };
+    if (ti.kpad > 0) {
+        const __bf16 *pa = vals16 + ti.panel_off, *pb = vals16 + tj.panel_off;
+        const int32_t *br = brow + ti.brow_off;
+        PairStage s0, s1;
+        WideStage::Rows rw0, rw1;
+        const int kp = ti.kpad;
+        rw0.load(br, t);
+        if (WKC < kp) rw1.load(br + WKC, t);
+        s0.fetch(pa, pb, rw0, X16, T16, ld16, t);
+        if (2 * WKC < kp) rw0.load(br + 2 * WKC, t);
+        if (WKC < kp) {
+            s1.fetch(pa + (int64_t)WKC * TM, pb + (int64_t)WKC * TM, rw1, X16, T16, ld16, t);
+            if (3 * WKC < kp) rw1.load(br + 3 * WKC, t);
+        }
+        for (int kb = 0; kb < kp; kb += 2 * WKC) {
+            s0.commit(sA[0], sB[0], t);
+            __syncthreads();
+            if (kb + 2 * WKC < kp) {
+                s0.fetch(pa + (int64_t)(kb + 2 * WKC) * TM, pb + (int64_t)(kb + 2 * WKC) * TM, rw0, X16, T16, ld16, t);
+                if (kb + 4 * WKC < kp) rw0.load(br + kb + 4 * WKC, t);
+            }
+            mma(sA[0], sB[0]);
+            if (kb + WKC >= kp) break;
+            s1.commit(sA[1], sB[1], t);
+            __syncthreads();
+            if (kb + 3 * WKC < kp) {
+                s1.fetch(pa + (int64_t)(kb + 3 * WKC) * TM, pb + (int64_t)(kb + 3 * WKC) * TM, rw1, X16, T16, ld16, t);
+                if (kb + 5 * WKC < kp) rw1.load(br + kb + 5 * WKC, t);
+            }
+            mma(sA[1], sB[1]);
+        }
+    }
+    // epilogue per 64 x 128 quarter (q: tile half q & 1, column half q >> 1),
+    // held by wave q
+    float (*sC)[128 + 4] = (float (*)[128 + 4])smem;
+    const int lk = lane >> 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        __syncthreads();
+        if (w == q) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) sC[i * 16 + 4 * lk + v][j * 16 + lr] = acc[i][j][v];
+        }
+        __syncthreads();
+        const int tq = tile + (q & 1), h = q >> 1;
+        if (128 * h < R && (int64_t)tq * TM < N)
+            tile_epilogue<float, kFused, TM, 128, 128 + 4>(sC, smem, tq, (int64_t)tq * TM, 128 * h, ldr, R, N, Y, E,
+                                                           X, rho, rho_s, partial);
     }
 }
 
@@ -511,9 +650,22 @@ template <bool kFused>
 void launch_wide(const rad_hmat *Hm, const float *E, const float *rho, float rho_s, const float *Bold, float *Bnew,
                  int64_t ldr, int R, double *part, hipStream_t s) {
     const int64_t ld16 = ld16_of(R);
-    hipLaunchKernelGGL((k_tile_mm16w<kFused>), dim3(Hm->n_tiles), dim3(256), 0, s, Hm->d_tiles.p, Hm->d_brow.p,
-                       (const __bf16 *)Hm->d_vals16.p, (const __bf16 *)Hm->w_x16.p, (const __bf16 *)Hm->w_t16.p, ld16,
-                       Bold, ldr, R, Hm->N, Bnew, E, rho, rho_s, part);
+    const __bf16 *v16 = (const __bf16 *)Hm->d_vals16.p, *x16 = (const __bf16 *)Hm->w_x16.p,
+                 *t16 = (const __bf16 *)Hm->w_t16.p;
+    if (Hm->n_wpairs > 0) {
+        // pairs of tiles with one operand-row list, then the tiles left alone
+        hipLaunchKernelGGL((k_tile_mm16p<kFused>), dim3(Hm->n_wpairs), dim3(256), 0, s, Hm->d_tiles.p,
+                           Hm->d_wpairs.p, Hm->d_brow.p, v16, x16, t16, ld16, Bold, ldr, R, Hm->N, Bnew, E, rho,
+                           rho_s, part);
+        if (Hm->n_wsingles > 0)
+            hipLaunchKernelGGL((k_tile_mm16w<kFused>), dim3(Hm->n_wsingles), dim3(256), 0, s, Hm->d_tiles.p,
+                               Hm->d_wsingles.p, Hm->d_brow.p, v16, x16, t16, ld16, Bold, ldr, R, Hm->N, Bnew, E, rho,
+                               rho_s, part);
+    } else {
+        hipLaunchKernelGGL((k_tile_mm16w<kFused>), dim3(Hm->n_tiles), dim3(256), 0, s, Hm->d_tiles.p,
+                           (const int32_t *)nullptr, Hm->d_brow.p, v16, x16, t16, ld16, Bold, ldr, R, Hm->N, Bnew, E,
+                           rho, rho_s, part);
+    }
     RAD_HIP(hipGetLastError());
 }
 

@@ -1037,6 +1037,30 @@ void mm_prepare_schedule(rad_hmat *H) {
     }
     H->n_p1pairs = (int32_t)(pairs.size() / 2);
     H->d_p1pairs.upload(pairs);
+    // tile pairs of the wide BF16 expansion: consecutive tiles (the halves of
+    // a 128-facet leaf) whose panels multiply the same operand rows
+    H->n_wpairs = H->n_wsingles = 0;
+    if (H->lowp == RAD_BF16 && H->d_tile_tasks.n == 0 && n > 1) {
+        std::vector<int32_t> br = H->d_brow.download(H->d_brow.n);
+        std::vector<int32_t> wp, ws;
+        for (int32_t i = 0; i < n;) {
+            bool same = i + 1 < n && ti[i].kpad == ti[i + 1].kpad && ti[i].kpad > 0;
+            if (same)
+                same = std::equal(br.begin() + ti[i].brow_off, br.begin() + ti[i].brow_off + ti[i].kpad,
+                                  br.begin() + ti[i + 1].brow_off);
+            if (same) {
+                wp.push_back(i);
+                i += 2;
+            } else {
+                ws.push_back(i);
+                i += 1;
+            }
+        }
+        H->n_wpairs = (int32_t)wp.size();
+        H->n_wsingles = (int32_t)ws.size();
+        H->d_wpairs.upload(wp);
+        H->d_wsingles.upload(ws);
+    }
     int ncu = 0;
     RAD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, H->device));
     H->n_cu = std::max(1, ncu);

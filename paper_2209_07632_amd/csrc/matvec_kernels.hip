@@ -44,7 +44,8 @@ __global__ void k_scatter(const int32_t *perm, const T *src, int64_t lds, T *dst
 // phase 1: one wave per stacked V column, lanes stride the rows of X_J
 template <class T>
 __global__ void __launch_bounds__(256) k_proj(const ProjGroup *groups, const T *vals, const T *X, int64_t ldx,
-                                               T *Tb, int32_t t_ld) {
+                                               T *Tb, int32_t t_ld, const int32_t *stop) {
+    if (stop && *stop) return;
     const ProjGroup g = groups[blockIdx.x];
     const int64_t r = blockIdx.z;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -64,11 +65,19 @@ __global__ void __launch_bounds__(256) k_proj(const ProjGroup *groups, const T *
 // of column VW g + l / (64/VW); wave w takes column groups w, w+4, ... and
 // keeps four groups in flight.  CSR tasks are split over the waves by task.
 // Partial row sums meet in LDS in a fixed order.
-template <class T>
+// kMode 0: Y = F-hat X.  kMode 1: one Jacobi iteration with X = B_old,
+// Y = B_new = E + rho (F-hat B_old), and partial[tile R + r] = the tile's
+// sum of (B_new - B_old)^2 (FP64, rows in order).  kMode 2: also
+// epartial[tile R + r] = the tile's sum of E^2.  With stop given, the kernel
+// returns at once while *stop is set.
+template <class T, int kMode>
 __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
                                                     const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
                                                     int64_t csr_val_start, const T *X, int64_t ldx, const T *Tb,
-                                                    int32_t t_ld, int64_t N, T *Y, int64_t ldy) {
+                                                    int32_t t_ld, int64_t N, T *Y, int64_t ldy, const T *E,
+                                                    const T *rho, T rho_s, double *partial, double *epartial,
+                                                    const int32_t *stop) {
+    if (stop && *stop) return;
     constexpr int VW = 16 / sizeof(T);      // values per 16-byte load
     constexpr int LPC = 64 / VW;            // lanes per panel column
     typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type vec_t;
@@ -141,35 +150,34 @@ __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const 
     cred[w][lane] = cacc;
     __syncthreads();
     const int64_t row = (int64_t)tile * 64 + lane;
-    if (w == 0 && row < N) {
+    if (w != 0) return;
+    double d2 = 0.0, e2 = 0.0;
+    if (row < N) {
         T s = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int u = 0; u < VW; ++u) s += red[q][u][lane];
-        Y[row + r * ldy] = s + ((cred[0][lane] + cred[1][lane]) + (cred[2][lane] + cred[3][lane]));
+        const T y = s + ((cred[0][lane] + cred[1][lane]) + (cred[2][lane] + cred[3][lane]));
+        if (kMode == 0) {
+            Y[row + r * ldy] = y;
+        } else {
+            const T e = E[row + r * ldy];
+            const T b = e + (rho ? rho[row] : rho_s) * y;
+            const double d = (double)b - (double)x[row];
+            d2 = d * d;
+            e2 = (double)e * (double)e;
+            Y[row + r * ldy] = b;
+        }
     }
-}
-
-// B_new = E + rho * FB; partial[col][block] = sum (B_new - B_old)^2
-template <class T>
-__global__ void __launch_bounds__(256) k_jacobi_update(const T *E, const T *rho, T rho_s, const T *FB, const T *Bold,
-                                                        T *Bnew, int64_t N, int64_t ld, double *partial) {
-    const int64_t r = blockIdx.y;
-    double s = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
-        T rh = rho ? rho[t] : rho_s;
-        int64_t e = t + r * ld;
-        T b = E[e] + rh * FB[e];
-        double d = (double)b - (double)Bold[e];
-        s += d * d;
-        Bnew[e] = b;
+    if (kMode != 0) {
+        d2 = wsum(d2);
+        if (kMode == 2) e2 = wsum(e2);
+        if (lane == 0) {
+            partial[(int64_t)tile * gridDim.y + r] = d2;
+            if (kMode == 2) epartial[(int64_t)tile * gridDim.y + r] = e2;
+        }
     }
-    s = wsum(s);
-    __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x + r * gridDim.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 template <class T>
@@ -196,20 +204,37 @@ __global__ void k_reduce_cols(const double *partial, int nparts, int64_t R, doub
     out[r] = s;
 }
 
+// Y = F-hat X (E == nullptr), or one fused Jacobi iteration (X = B_old,
+// Y = B_new, E with leading dimension ldy == ldx; per-tile partial sums of the
+// squared change, and of E^2 when epartial is given)
 template <class T>
-void apply_t(const rad_hmat *H, const T *X, int64_t ldx, T *Y, int64_t ldy, int64_t R, T *Tb, hipStream_t s) {
+void apply_t(const rad_hmat *H, const T *X, int64_t ldx, T *Y, int64_t ldy, int64_t R, T *Tb, hipStream_t s,
+             const T *E = nullptr, const T *rho = nullptr, T rho_s = 0, double *partial = nullptr,
+             double *epartial = nullptr, const int32_t *stop = nullptr) {
     if (H->n_groups > 0) {
         int maxk = 0;
         for (const ProjGroup &g : H->h_groups) maxk = std::max(maxk, g.ktot);
         dim3 grid(H->n_groups, std::max(1, std::min(64, (maxk + 3) / 4)), (unsigned)R);
         hipLaunchKernelGGL(k_proj<T>, grid, dim3(256), 0, s, H->d_groups.p, (const T *)H->d_vals.p, X, ldx, Tb,
-                           H->t_ld);
+                           H->t_ld, stop);
         RAD_HIP(hipGetLastError());
     }
     dim3 grid2(H->n_tiles, (unsigned)R);
-    hipLaunchKernelGGL(k_tile_gemv<T>, grid2, dim3(256), 0, s, H->d_tiles.p, H->d_brow.p, H->d_tile_tasks.p,
-                       (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p, H->csr_val_start, X, ldx,
-                       (const T *)Tb, H->t_ld, H->N, Y, ldy);
+    if (!E)
+        hipLaunchKernelGGL((k_tile_gemv<T, 0>), grid2, dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
+                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
+                           H->csr_val_start, X, ldx, (const T *)Tb, H->t_ld, H->N, Y, ldy, E, rho, rho_s, partial,
+                           epartial, stop);
+    else if (!epartial)
+        hipLaunchKernelGGL((k_tile_gemv<T, 1>), grid2, dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
+                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
+                           H->csr_val_start, X, ldx, (const T *)Tb, H->t_ld, H->N, Y, ldy, E, rho, rho_s, partial,
+                           epartial, stop);
+    else
+        hipLaunchKernelGGL((k_tile_gemv<T, 2>), grid2, dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
+                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
+                           H->csr_val_start, X, ldx, (const T *)Tb, H->t_ld, H->N, Y, ldy, E, rho, rho_s, partial,
+                           epartial, stop);
     RAD_HIP(hipGetLastError());
 }
 
@@ -293,21 +318,23 @@ void col_norms2(const rad_hmat *H, const void *E, int64_t ld, int64_t R, double 
     RAD_HIP(hipGetLastError());
 }
 
-void solve_update(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *FB,
-                  const void *Bold, void *Bnew, int64_t ld, int64_t R, double *norms, hipStream_t s) {
-    dim3 grid(kRedParts, (unsigned)R);
-    double *part = (double *)H->w_red.p;
-    if (H->dtype == RAD_F64)
-        hipLaunchKernelGGL(k_jacobi_update<double>, grid, dim3(256), 0, s, (const double *)E, (const double *)rho,
-                           rho_scalar, (const double *)FB, (const double *)Bold, (double *)Bnew, H->N, ld, part);
-    else
-        hipLaunchKernelGGL(k_jacobi_update<float>, grid, dim3(256), 0, s, (const float *)E, (const float *)rho,
-                           (float)rho_scalar, (const float *)FB, (const float *)Bold, (float *)Bnew, H->N, ld, part);
-    hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, part, kRedParts, R, norms);
-    RAD_HIP(hipGetLastError());
-}
-
 size_t reduction_doubles(int64_t R) { return (size_t)kRedParts * (size_t)R; }
+
+void mv_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
+                    int64_t ld, int64_t R, double *norms, hipStream_t s, const int32_t *stop, double *enorms,
+                    const ConvTest *test) {
+    double *part = (double *)H->w_red.p;
+    double *epart = enorms ? H->w_ered.p : nullptr;
+    if (H->dtype == RAD_F64)
+        apply_t<double>(H, (const double *)Bold, ld, (double *)Bnew, ld, R, (double *)H->w_t.p, s, (const double *)E,
+                        (const double *)rho, rho_scalar, part, epart, stop);
+    else
+        apply_t<float>(H, (const float *)Bold, ld, (float *)Bnew, ld, R, (float *)H->w_t.p, s, (const float *)E,
+                       (const float *)rho, (float)rho_scalar, part, epart, stop);
+    // per-column sums in a fixed order; the stopping test rides on the last one
+    mm_reduce_cols(H, part, H->n_tiles, R, norms, s, stop, enorms ? nullptr : test);
+    if (enorms) mm_reduce_cols(H, epart, H->n_tiles, R, enorms, s, stop, test);
+}
 
 namespace {
 template <class T>

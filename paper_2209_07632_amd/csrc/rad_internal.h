@@ -31,33 +31,73 @@ struct Error : std::runtime_error {
             throw ::rad::Error(RAD_EINVAL, std::string(msg));  \
     } while (0)
 
-// Owning device allocation.
+// Caller-supplied device allocator (rad_allocator) in force on this thread,
+// and the device it allocates on: set by AllocScope for the duration of a
+// build, load, group or insolation call; nullptr means hipMalloc/hipFree.
+struct AllocCtx {
+    const rad_allocator *al = nullptr;
+    int32_t device = 0;
+};
+inline AllocCtx &alloc_ctx() {
+    static thread_local AllocCtx c;
+    return c;
+}
+struct AllocScope {
+    AllocCtx saved;
+    AllocScope(const rad_allocator *al, int32_t device) : saved(alloc_ctx()) {
+        alloc_ctx().al = (al && al->alloc && al->free) ? al : nullptr;
+        alloc_ctx().device = device;
+    }
+    ~AllocScope() { alloc_ctx() = saved; }
+    AllocScope(const AllocScope &) = delete;
+    AllocScope &operator=(const AllocScope &) = delete;
+};
+
+// Owning device allocation (through the allocator in force when it was made).
 template <class T>
 struct DevBuf {
     T *p = nullptr;
     size_t n = 0;
+    const rad_allocator *al = nullptr;
+    int32_t dev = 0;
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), al(o.al), dev(o.dev) { o.p = nullptr; o.n = 0; }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; al = o.al; dev = o.dev;
+            o.p = nullptr; o.n = 0;
+        }
         return *this;
     }
     ~DevBuf() { release(); }
     void alloc(size_t count) {
         release();
         if (count == 0) return;
-        hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
-        if (e != hipSuccess) {
-            p = nullptr;
-            throw Error(RAD_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        al = alloc_ctx().al;
+        dev = alloc_ctx().device;
+        if (al) {
+            p = (T *)al->alloc(al->ctx, count * sizeof(T), dev);
+            if (!p) throw Error(RAD_ENOMEM, "allocator hook returned NULL for " + std::to_string(count * sizeof(T)) + " bytes");
+        } else {
+            hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+            if (e != hipSuccess) {
+                p = nullptr;
+                throw Error(RAD_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+            }
         }
         n = count;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (al)
+                al->free(al->ctx, p, n * sizeof(T), dev);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
     }
@@ -180,10 +220,31 @@ struct P1Red {
     int32_t t_row0, nrows, part_begin, part_count;
 };
 
+// One final block of the partition Algorithm 4 chose (zero blocks are not
+// kept), rows [i0, i0 + m) x columns [j0, j0 + n) of the tree order, and
+// where its values live: dense values and U' rows in the tile panels (see
+// BlockPiece); V columns [vcol, vcol + rank) of the stacked V of projection
+// group `group`; CSR row pointers at ptr_off of the CSR pointer pool and
+// values at csr_val_start + val_base (column indices at val_base).
+struct BlockRec {
+    int32_t kind;          // BlockKind: BK_DENSE, BK_CSR or BK_LOWRANK
+    int32_t i0, m, j0, n, rank;
+    int64_t nnz;
+    int32_t group, vcol;
+    int64_t ptr_off, val_base;
+};
+
+// Rows [r_lo, r_hi) of 64-row tile `tile` of block `block` sit in that tile's
+// panel at columns [col, col + width) (width n for dense, rank for low rank).
+struct BlockPiece {
+    int32_t block, tile, col, r_lo, r_hi;
+};
+
 }  // namespace rad
 
 // Opaque matrix handle (device-resident operator + host metadata).
 struct rad_hmat {
+    rad_allocator allocator{};         // device-memory hook (all null: hipMalloc)
     int device = 0;
     int64_t N = 0;
     int32_t dtype = RAD_F64;   // storage and compute dtype
@@ -232,9 +293,12 @@ struct rad_hmat {
     };
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
-    double *h_norms = nullptr;   // pinned: two slots of per-column changes, then ||E||^2
+    // pinned: kNormSlots slots of per-column changes (one per iteration in
+    // flight), then ||E||^2
+    static constexpr int kNormSlots = 4;
+    double *h_norms = nullptr;
     double *d_hnorms = nullptr;  // the same memory as the device addresses it
-    hipEvent_t ev[2] = {nullptr, nullptr};   // ends of the iterations in flight
+    hipEvent_t ev[kNormSlots] = {};   // ends of the iterations in flight
     ~rad_hmat();
 
     // workspace (sized for max_rhs)
@@ -262,11 +326,22 @@ struct rad_hmat {
     rad::DevBuf<int32_t> d_tile_order, d_queue;
     rad::DevBuf<int32_t> d_p1pairs;  // phase-1 work items taken two at a time (second -1 if single)
     int32_t n_p1pairs = 0;
+    // wide 16-bit expansion: first tiles of consecutive tile pairs with identical
+    // operand-row lists (one 128-row workgroup each), and the remaining tiles
+    rad::DevBuf<int32_t> d_wpairs, d_wsingles;
+    int32_t n_wpairs = 0, n_wsingles = 0;
     int32_t n_cu = 256;
     std::string sched_sig;           // dtype, tile count and tile-cost histogram hash (autotuner cache key)
     std::vector<int64_t> inst_off, inst_n;
     std::vector<int32_t> inst_tile;
     rad::DevBuf<int32_t> d_inst_tile;
+
+    // final blocks and their places in the layout (rad_hmat_export)
+    std::vector<rad::BlockRec> blocks;
+    std::vector<rad::BlockPiece> pieces;
+
+    // allocator hook of this matrix, or nullptr
+    const rad_allocator *hook() const { return allocator.alloc && allocator.free ? &allocator : nullptr; }
 };
 
 namespace rad {
@@ -304,6 +379,13 @@ void jacobi_svd(int l, std::vector<double> &A, std::vector<double> &V, std::vect
 // tree_dims: 2 = quadtree on (x, y), 3 = octree on (x, y, z)
 void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *faces, int64_t nf,
                 const rad_build_opts &o, int tree_dims = 2);
+// block export, save and load (serialize.cpp)
+void export_blocks(const rad_hmat *H, const char *path);
+void save_hmat(const rad_hmat *H, const char *path);
+void load_hmat(rad_hmat *H, const char *path, int32_t device, int32_t max_rhs);
+// the same from centroids, unit normals, areas and optional triangles (N x 9)
+void build_hmat_facets(rad_hmat *H, const double *x, const double *n, const double *area, int64_t N,
+                       const double *tri_verts, const rad_build_opts &o, int tree_dims);
 
 // device geometry used by the build kernels (tree order, FP64)
 struct DevGeom {
@@ -355,8 +437,6 @@ void mv_apply_ws(const rad_hmat *H, const void *X, int64_t ldx, void *Y, int64_t
 constexpr size_t kStaticScratchBytes = size_t(8) << 20;
 void *static_scratch(int device);
 void col_norms2(const rad_hmat *H, const void *E, int64_t ld, int64_t R, double *out, hipStream_t s);
-void solve_update(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *FB,
-                  const void *Bold, void *Bnew, int64_t ld, int64_t R, double *norms, hipStream_t s);
 size_t reduction_doubles(int64_t R);
 
 // elementwise operations on N x R blocks (column-major or R-major, leading dimension ld)
@@ -399,6 +479,12 @@ struct ConvTest {
 void mm_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
                     int64_t ldr, int64_t R, double *norms, hipStream_t s, const int32_t *stop = nullptr,
                     double *enorms = nullptr, const ConvTest *test = nullptr);
+// The same iteration on the single-RHS kernels (column-major tree order,
+// leading dimension ld for E, B_old and B_new): the Jacobi update, the squared
+// changes (and ||E||^2 with enorms) are fused into the tile kernel.
+void mv_jacobi_step(const rad_hmat *H, const void *E, const void *rho, double rho_scalar, const void *Bold, void *Bnew,
+                    int64_t ld, int64_t R, double *norms, hipStream_t s, const int32_t *stop = nullptr,
+                    double *enorms = nullptr, const ConvTest *test = nullptr);
 size_t mm_reduction_doubles_for(const rad_hmat *H, int64_t R);
 rad::MmConfig mm_config(const rad_hmat *H, int64_t R);
 void mm_prepare_schedule(rad_hmat *H);
@@ -410,6 +496,22 @@ void mm_reduce_cols(const rad_hmat *H, const double *partial, int nparts, int64_
 // thr[c] = rtol2 enorm2[c] (rtol2 when 0); clears conv[0..nc) and stop
 void conv_init(const double *enorm2, double rtol2, int64_t nc, double *thr, int32_t *conv, int32_t *stop,
                hipStream_t s);
+
+// blocks of R columns in the solve's working layout (R-major with ld when
+// rmajor, else column-major with ld) for Chebyshev and GMRES (krylov.hip);
+// column sums per 64-row tile in part (tile-major), then in a fixed order
+void krylov_cheb_init(const rad_hmat *H, bool rmajor, int64_t ld, int64_t R, double rho, double theta, const void *Y,
+                      void *r, void *d, double *part, hipStream_t s);
+void krylov_cheb_step(const rad_hmat *H, bool rmajor, int64_t ld, int64_t R, double rho, double a, double b,
+                      const void *Y, void *B, void *r, void *d, double *part, hipStream_t s);
+void krylov_apply_a(const rad_hmat *H, bool rmajor, int64_t ld, int64_t R, double rho, const void *rhov, const void *e,
+                    const void *v, const void *Y, void *w, hipStream_t s);
+void krylov_dots(const rad_hmat *H, bool rmajor, int64_t ld, int64_t R, const void *V, int64_t vstride, int nv,
+                 const void *w, double *part, double *out, hipStream_t s);
+void krylov_combine(const rad_hmat *H, bool rmajor, int64_t ld, int64_t R, const void *V, int64_t vstride, int nv,
+                    const double *h, double sign, void *w, hipStream_t s);
+void krylov_scale(const rad_hmat *H, bool rmajor, int64_t ld, int64_t R, const void *w, const double *nrm2, void *v,
+                  hipStream_t s);
 
 // 16-bit operator (lowp_kernels.hip)
 void ir_select(const rad_hmat *H, double *B64, float *B32, float *r, const float *E, const int32_t *flag, int64_t ldr,

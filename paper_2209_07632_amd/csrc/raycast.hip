@@ -179,10 +179,24 @@ GridView view_of(const rad_hmat *H) {
 
 }  // namespace
 
-// Host: bin triangles (tree order, N x 9) into a uniform xy grid of about
-// two triangles per cell.
+// Host: bin triangles (tree order, 9 values each: one per facet, or none)
+// into a uniform xy grid of about two triangles per cell.
 void build_grid(rad_hmat *H, const std::vector<double> &tri) {
-    const int64_t N = H->N;
+    const int64_t N = (int64_t)(tri.size() / 9);
+    if (N == 0) {
+        // no occluders: one empty cell below every ray
+        H->d_tri.alloc(0);
+        H->d_cell_start.upload(std::vector<int32_t>{0, 0});
+        H->d_cell_tris.alloc(0);
+        H->d_cell_zmax.upload(std::vector<double>{-1e300});
+        H->grid_x0 = 0.0;
+        H->grid_y0 = 0.0;
+        H->grid_h = 1.0;
+        H->grid_gx = 1;
+        H->grid_gy = 1;
+        H->grid_ztop = -1e300;
+        return;
+    }
     double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
     for (int64_t t = 0; t < N; ++t)
         for (int v = 0; v < 3; ++v) {

@@ -69,14 +69,24 @@ __global__ void k_ts_operand(int64_t N, int64_t R, const double *qrad, const T *
 // One step of every column.  coef holds, per node j, cap_j = rho c V_j / dt,
 // g_j = k / (z_j - z_{j-1}), ib_j = 1 / beta_j and e_j = l_j / beta_j of the
 // bottom-up elimination (T_j = d_j - e_j T_{j-1}), four runs of M + 1 values.
-// The d_j of a thread wait in LDS for the downward substitution.
+// The d_j of a thread wait in LDS for the downward substitution.  Rows 1..M
+// are the same in both surface readings; only the surface row differs:
+//   half layer (newton < 0): half a layer of heat capacity at the surface,
+//     Q_abs averaged over the two levels, the emission averaged with its new
+//     value linearised about T_0^n;
+//   balanced (newton >= 0): no heat capacity at the surface, which meets the
+//     radiation boundary condition of section 2 at the new level,
+//     Q_abs' + g_1 (T_1' - T_0') = emiss sigma T_0'^4, with the emission
+//     linearised about T_0^n and then newton more times about the latest T_0'
+//     (Newton's method on the one nonlinear row; T_1' = d_1 - e_1 T_0' from
+//     the elimination below, which does not depend on the surface row).
 template <class T>
 __global__ void __launch_bounds__(kColThreads) k_ts_column(int M, int64_t N, int64_t R, const double *coef,
                                                            const double *Tin, double *Tout, double *qabs,
                                                            double *qrad, const T *Y, T *X, int64_t ldx, int rmajor,
                                                            const T *qd, const T *qd_next, int64_t ldq, int order,
                                                            const int32_t *perm, double albedo, double emiss,
-                                                           double hb) {
+                                                           double hb, int newton) {
     extern __shared__ double d_lds[];   // M x kColThreads
     const double *cap = coef, *g = coef + (M + 1), *ib = coef + 2 * (M + 1), *e = coef + 3 * (M + 1);
     double *dl = d_lds + threadIdx.x;
@@ -103,13 +113,26 @@ __global__ void __launch_bounds__(kColThreads) k_ts_column(int M, int64_t N, int
             t_below = t_here;
             t_here = t_above;
         }
-        // surface row: conduction, the averaged absorbed flux and the emission
-        // linearised about the old surface temperature
         const double t0 = t_here, t1 = t_below, g1 = g[1];
-        const double t03 = t0 * t0 * t0;
-        const double drad = 2.0 * es * t03;
-        const double r0 = cap[0] * t0 + 0.5 * g1 * (t1 - t0) + 0.5 * (qa_old + qa_new) - es * t03 * t0 + drad * t0;
-        double tn = (r0 + 0.5 * g1 * d) / (cap[0] + 0.5 * g1 + drad + 0.5 * g1 * e[1]);
+        double tn;
+        if (newton < 0) {
+            // half layer: conduction, the averaged absorbed flux and the
+            // emission linearised about the old surface temperature
+            const double t03 = t0 * t0 * t0;
+            const double drad = 2.0 * es * t03;
+            const double r0 =
+                cap[0] * t0 + 0.5 * g1 * (t1 - t0) + 0.5 * (qa_old + qa_new) - es * t03 * t0 + drad * t0;
+            tn = (r0 + 0.5 * g1 * d) / (cap[0] + 0.5 * g1 + drad + 0.5 * g1 * e[1]);
+        } else {
+            // balanced: (g_1 + 4 es u^3) T_0' - g_1 T_1' = Q_abs' + 3 es u^4,
+            // u the latest surface temperature
+            double u = t0;
+            for (int it = 0; it <= newton; ++it) {
+                const double u3 = u * u * u;
+                u = (qa_new + 3.0 * es * u3 * u + g1 * d) / (g1 * (1.0 + e[1]) + 4.0 * es * u3);
+            }
+            tn = u;
+        }
         Tout[i] = tn;
         const double ts = tn;
         for (int j = 1; j <= M; ++j) {
@@ -158,6 +181,7 @@ struct rad_ts {
     int64_t N = 0, R = 0;
     int32_t M = 0;
     double albedo = 0, emiss = 1, hb = 0;
+    int32_t newton = -1;   // -1: half-layer surface; >= 0: balanced surface with this many repeats
     bool rmajor = false;   // X / Y on the matrix-core path (2R >= 16)
     int64_t ldx = 0;
     int64_t level = -1;
@@ -226,7 +250,7 @@ void enqueue_steps(rad_ts *S, int64_t n_steps, const void *Qdir, int64_t ldq, in
         hipLaunchKernelGGL(k_ts_column<T>, dim3(grid_for(NR, kColThreads)), dim3(kColThreads), lds, s, S->M, S->N,
                            S->R, S->coef.p, S->T[S->cur].p, S->T[S->cur ^ 1].p, S->qabs.p, S->qrad.p,
                            (const T *)S->Y.p, (T *)S->X.p, S->ldx, rm, qd, qn, ldq, (int)order, perm, S->albedo,
-                           S->emiss, S->hb);
+                           S->emiss, S->hb, S->newton);
         RAD_HIP(hipGetLastError());
         S->cur ^= 1;
         ++S->level;
@@ -257,6 +281,10 @@ rad_status rad_ts_create(const rad_hmat *H, const rad_ts_params *p, int64_t R, r
         RAD_REQUIRE(p->albedo >= 0.0 && p->albedo < 1.0, "albedo must be in [0, 1)");
         RAD_REQUIRE(p->emissivity > 0.0 && p->emissivity <= 1.0, "emissivity must be in (0, 1]");
         RAD_REQUIRE(std::isfinite(p->bottom_flux), "bottom_flux must be finite");
+        RAD_REQUIRE(p->surface == RAD_TS_SURFACE_HALF_LAYER || p->surface == RAD_TS_SURFACE_BALANCED,
+                    "surface must be RAD_TS_SURFACE_HALF_LAYER or RAD_TS_SURFACE_BALANCED");
+        RAD_REQUIRE(p->surface == RAD_TS_SURFACE_HALF_LAYER || (p->newton >= 0 && p->newton <= 16),
+                    "newton must be in [0, 16] for the balanced surface");
         RAD_HIP(hipSetDevice(H->device));
         S = new rad_ts();
         S->H = H;
@@ -266,6 +294,7 @@ rad_status rad_ts_create(const rad_hmat *H, const rad_ts_params *p, int64_t R, r
         S->albedo = p->albedo;
         S->emiss = p->emissivity;
         S->hb = p->bottom_flux;
+        S->newton = p->surface == RAD_TS_SURFACE_BALANCED ? p->newton : -1;
         S->rmajor = 2 * R >= kMfmaMinRhs;
         S->ldx = S->rmajor ? mm_ldr(2 * R) : S->N;
         const size_t es = H->dtype == RAD_F64 ? 8 : 4;

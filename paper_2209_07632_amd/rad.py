@@ -29,18 +29,53 @@ class RadError(RuntimeError):
         self.status = status
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
+
+
 class BuildOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("leaf_size", ctypes.c_int32), ("max_depth", ctypes.c_int32),
                 ("nearfield", ctypes.c_int32), ("visibility", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("oversample", ctypes.c_int32), ("power_iters", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("seed", ctypes.c_uint64), ("verbose", ctypes.c_int32),
-                ("max_rank", ctypes.c_int32), ("lowp", ctypes.c_int32)]
+                ("max_rank", ctypes.c_int32), ("lowp", ctypes.c_int32),
+                ("allocator", ctypes.POINTER(Allocator))]
+
+
+class TorchAllocator:
+    """rad_allocator hook backed by torch's caching allocator, so that torch
+    owns the device memory of the matrices built with it.  The object (and its
+    callbacks) must outlive those matrices; HMatrix keeps a reference."""
+
+    def __init__(self):
+        import torch
+
+        def _alloc(ctx, nbytes, device):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), int(device))
+            except Exception:
+                return None
+
+        def _free(ctx, ptr, nbytes, device):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self._alloc_fn = ALLOC_FN(_alloc)
+        self._free_fn = FREE_FN(_free)
+        self.struct = Allocator(None, self._alloc_fn, self._free_fn)
 
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("inner_iters", ctypes.c_int32), ("warm", ctypes.c_int32)]
+                ("inner_iters", ctypes.c_int32), ("warm", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("lam_lo", ctypes.c_double), ("lam_hi", ctypes.c_double), ("restart", ctypes.c_int32)]
+
+
+METHODS = {"jacobi": 0, "chebyshev": 1, "gmres": 2}
 
 
 class SolveInfo(ctypes.Structure):
@@ -56,15 +91,18 @@ class Stats(ctypes.Structure):
                 ("bytes_csr", ctypes.c_int64), ("bytes_lowrank", ctypes.c_int64), ("bytes_total", ctypes.c_int64),
                 ("nnz_near", ctypes.c_int64), ("sum_rank", ctypes.c_int64), ("lowrank_elems", ctypes.c_int64),
                 ("max_rank", ctypes.c_int32), ("build_seconds", ctypes.c_double), ("flops_per_rhs", ctypes.c_double),
-                ("lowrank_row_elems", ctypes.c_int64), ("lowrank_col_elems", ctypes.c_int64)]
+                ("lowrank_row_elems", ctypes.c_int64), ("lowrank_col_elems", ctypes.c_int64),
+                ("max_panel_cols", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
-EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_build_tree", "rad_hmat_matvec",
+EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_build_tree", "rad_hmat_build_facets",
+           "rad_hmat_export", "rad_hmat_save", "rad_hmat_load", "rad_hmat_matvec",
            "rad_hmat_matvec_noalloc", "rad_noalloc_scratch_bytes", "rad_solve_opts_default", "rad_solve",
-           "rad_insolation", "rad_equilibrium", "rad_hmat_time_phases", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_perm", "rad_hmat_free",
+           "rad_insolation", "rad_equilibrium", "rad_hmat_time_phases", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_lowp",
+           "rad_hmat_max_rhs", "rad_hmat_perm", "rad_hmat_free",
            "rad_last_error", "rad_pod_build", "rad_pod_project", "rad_pod_expand", "rad_mlp_create",
            "rad_mlp_param_count", "rad_mlp_get_params", "rad_mlp_set_params", "rad_mlp_forward", "rad_mlp_loss_grad",
            "rad_mlp_adam_step", "rad_mlp_train", "rad_mlp_free", "rad_hmat_group", "rad_hmat_instances",
@@ -95,6 +133,16 @@ def load(path: str = LIB_PATH):
     L.rad_hmat_build_tree.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, ctypes.POINTER(BuildOpts),
                                       ctypes.c_int32, ctypes.POINTER(vp)]
     L.rad_hmat_build_tree.restype = ctypes.c_int
+    L.rad_hmat_build_facets.argtypes = [vp, vp, vp, ctypes.c_int64, vp, ctypes.POINTER(BuildOpts), ctypes.c_int32,
+                                        ctypes.POINTER(vp)]
+    L.rad_hmat_build_facets.restype = ctypes.c_int
+    L.rad_hmat_export.argtypes = [vp, ctypes.c_char_p]
+    L.rad_hmat_export.restype = ctypes.c_int
+    L.rad_hmat_save.argtypes = [vp, ctypes.c_char_p]
+    L.rad_hmat_save.restype = ctypes.c_int
+    L.rad_hmat_load.argtypes = [ctypes.c_char_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Allocator),
+                                ctypes.POINTER(vp)]
+    L.rad_hmat_load.restype = ctypes.c_int
     L.rad_hmat_matvec.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int64, vp, ctypes.c_int64,
                                   ctypes.c_int32, vp]
     L.rad_hmat_matvec.restype = ctypes.c_int
@@ -121,6 +169,10 @@ def load(path: str = LIB_PATH):
     L.rad_hmat_n.restype = ctypes.c_int64
     L.rad_hmat_dtype.argtypes = [vp]
     L.rad_hmat_dtype.restype = ctypes.c_int32
+    L.rad_hmat_lowp.argtypes = [vp]
+    L.rad_hmat_lowp.restype = ctypes.c_int32
+    L.rad_hmat_max_rhs.argtypes = [vp]
+    L.rad_hmat_max_rhs.restype = ctypes.c_int32
     L.rad_hmat_perm.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.rad_hmat_perm.restype = ctypes.c_int
     L.rad_hmat_free.argtypes = [vp]
@@ -201,29 +253,49 @@ def _colmajor(t, N):
     return t, ld
 
 
+def _build_opts(tol, leaf_size, max_depth, nearfield, visibility, storage, oversample, power_iters, max_rhs, device,
+                seed, verbose, max_rank, lowp, allocator):
+    o = BuildOpts()
+    load().rad_build_opts_default(ctypes.byref(o))
+    o.tol = float(tol)
+    o.leaf_size = int(leaf_size)
+    o.max_depth = int(max_depth)
+    o.nearfield = NEARFIELD[nearfield]
+    o.visibility = VISIBILITY[visibility]
+    o.storage = DTYPES[storage]
+    o.oversample = int(oversample)
+    o.power_iters = int(power_iters)
+    o.max_rhs = int(max_rhs)
+    o.device = int(device)
+    o.seed = int(seed)
+    o.verbose = int(bool(verbose))
+    o.max_rank = int(max_rank)
+    o.lowp = {None: 0, "f16": RAD_F16, "bf16": RAD_BF16}[lowp]
+    if allocator is not None:
+        o.allocator = ctypes.pointer(allocator.struct)
+    return o
+
+
+def _allocator(allocator):
+    if allocator is None or isinstance(allocator, TorchAllocator):
+        return allocator
+    if allocator == "torch":
+        return TorchAllocator()
+    raise ValueError("allocator must be None, 'torch' or a TorchAllocator")
+
+
 class HMatrix:
-    """Compressed view-factor matrix F-hat resident on one GPU."""
+    """Compressed view-factor matrix F-hat resident on one GPU.
+    allocator="torch" places all of its device memory in torch's caching
+    allocator (rad_allocator hook)."""
 
     def __init__(self, verts, faces, tol=1e-3, leaf_size=64, max_depth=0, nearfield="auto",
                  visibility="backface", storage="f64", oversample=8, power_iters=1, max_rhs=1, device=0,
-                 seed=0x5EED, verbose=False, max_rank=0, lowp=None, tree="quad"):
+                 seed=0x5EED, verbose=False, max_rank=0, lowp=None, tree="quad", allocator=None):
         L = load()
-        o = BuildOpts()
-        L.rad_build_opts_default(ctypes.byref(o))
-        o.tol = float(tol)
-        o.leaf_size = int(leaf_size)
-        o.max_depth = int(max_depth)
-        o.nearfield = NEARFIELD[nearfield]
-        o.visibility = VISIBILITY[visibility]
-        o.storage = DTYPES[storage]
-        o.oversample = int(oversample)
-        o.power_iters = int(power_iters)
-        o.max_rhs = int(max_rhs)
-        o.device = int(device)
-        o.seed = int(seed)
-        o.verbose = int(bool(verbose))
-        o.max_rank = int(max_rank)
-        o.lowp = {None: 0, "f16": RAD_F16, "bf16": RAD_BF16}[lowp]
+        alloc = _allocator(allocator)
+        o = _build_opts(tol, leaf_size, max_depth, nearfield, visibility, storage, oversample, power_iters, max_rhs,
+                        device, seed, verbose, max_rank, lowp, alloc)
         v = np.ascontiguousarray(verts, dtype=np.float64)
         f = np.ascontiguousarray(faces, dtype=np.int32)
         h = ctypes.c_void_p()
@@ -235,13 +307,70 @@ class HMatrix:
         else:
             _check(L.rad_hmat_build_tree(v.ctypes.data, v.shape[0], f.ctypes.data, f.shape[0], ctypes.byref(o), 3,
                                          ctypes.byref(h)))
+        self._adopt(h, int(o.lowp), int(max_rhs), int(device), alloc)
+
+    def _adopt(self, h, lowp, max_rhs, device, alloc):
+        L = load()
+        self._alloc = alloc      # keeps the allocator's callbacks alive as long as the matrix
         self._h = h
         self.N = int(L.rad_hmat_n(h))
         self.rad_dtype = int(L.rad_hmat_dtype(h))
-        self.lowp = int(o.lowp)
+        self.lowp = int(lowp)
         self.max_rhs = int(max_rhs)
         self.device = int(device)
-        self.n_inst = 1
+        self.n_inst = int(L.rad_hmat_instances(h))
+
+    @classmethod
+    def from_facets(cls, x, n, area, tri=None, tol=1e-3, leaf_size=64, max_depth=0, nearfield="auto",
+                    visibility="backface", storage="f64", oversample=8, power_iters=1, max_rhs=1, device=0,
+                    seed=0x5EED, verbose=False, max_rank=0, lowp=None, tree="quad", allocator=None):
+        """Build from centroids x (N, 3), unit normals n (N, 3) and areas (N,);
+        tri (N, 3, 3) the facets' triangles for ray casting and shadows, or None."""
+        L = load()
+        alloc = _allocator(allocator)
+        o = _build_opts(tol, leaf_size, max_depth, nearfield, visibility, storage, oversample, power_iters, max_rhs,
+                        device, seed, verbose, max_rank, lowp, alloc)
+        xa = np.ascontiguousarray(x, dtype=np.float64)
+        na = np.ascontiguousarray(n, dtype=np.float64)
+        aa = np.ascontiguousarray(area, dtype=np.float64)
+        N = aa.shape[0]
+        if xa.shape != (N, 3) or na.shape != (N, 3):
+            raise ValueError("x and n must have shape (N, 3)")
+        ta = None if tri is None else np.ascontiguousarray(np.reshape(tri, (N, 9)), dtype=np.float64)
+        if tree not in ("quad", "oct"):
+            raise ValueError("tree must be 'quad' (on x, y) or 'oct' (on x, y, z)")
+        h = ctypes.c_void_p()
+        _check(L.rad_hmat_build_facets(xa.ctypes.data, na.ctypes.data, aa.ctypes.data, N,
+                                       None if ta is None else ta.ctypes.data, ctypes.byref(o),
+                                       2 if tree == "quad" else 3, ctypes.byref(h)))
+        self = object.__new__(cls)
+        self._adopt(h, int(o.lowp), int(max_rhs), int(device), alloc)
+        return self
+
+    @classmethod
+    def load(cls, path, device=0, max_rhs=0, allocator=None):
+        """Read a matrix written by save(); workspace for max_rhs columns
+        (0: the saved matrix's)."""
+        L = load()
+        alloc = _allocator(allocator)
+        h = ctypes.c_void_p()
+        _check(L.rad_hmat_load(str(path).encode(), int(device), int(max_rhs),
+                               None if alloc is None else ctypes.pointer(alloc.struct), ctypes.byref(h)))
+        self = object.__new__(cls)
+        self._adopt(h, int(L.rad_hmat_lowp(h)), int(L.rad_hmat_max_rhs(h)), int(device), alloc)
+        if self.n_inst > 1:
+            self.offsets = np.zeros(self.n_inst, dtype=np.int64)
+            self.sizes = np.zeros(self.n_inst, dtype=np.int64)
+            _check(L.rad_hmat_group_layout(h, self.offsets.ctypes.data, self.sizes.ctypes.data))
+        return self
+
+    def save(self, path):
+        """Write the whole compressed operator to a file (rad_hmat_save)."""
+        _check(load().rad_hmat_save(self._h, str(path).encode()))
+
+    def export(self, path):
+        """Write the blocks of F-hat, FP64, to a file (rad_hmat_export)."""
+        _check(load().rad_hmat_export(self._h, str(path).encode()))
 
     @classmethod
     def group(cls, parts, max_rhs):
@@ -253,6 +382,7 @@ class HMatrix:
         h = ctypes.c_void_p()
         _check(L.rad_hmat_group(arr, len(parts), int(max_rhs), ctypes.byref(h)))
         self = object.__new__(cls)
+        self._alloc = getattr(parts[0], "_alloc", None)   # the group allocates through the parts' hook
         self._h = h
         self.N = int(L.rad_hmat_n(h))
         self.rad_dtype = int(L.rad_hmat_dtype(h))
@@ -346,10 +476,14 @@ class HMatrix:
         return out
 
     def solve(self, E, rho=0.3, rtol=1e-3, max_iter=100, order="original", check_every=1, out=None,
-              raise_on_noconv=True, use_graph=True, R=None, refine=False, inner_iters=3, warm=None):
-        """Jacobi solve of (I - diag(rho) F-hat) B = E; returns (B, info dict).
+              raise_on_noconv=True, use_graph=True, R=None, refine=False, inner_iters=3, warm=None,
+              method="jacobi", lam=None, restart=30):
+        """Solve of (I - diag(rho) F-hat) B = E; returns (B, info dict).
+        method: "jacobi" (the paper's), "chebyshev" (scalar rho; lam = (lo, hi)
+        an interval holding F-hat's spectrum, default from the largest row sum)
+        or "gmres" (restart = Arnoldi steps per cycle).
         warm: optional starting guess in the layout of B (judged per column
-        against the cold start); it may be `out` itself."""
+        against the cold start); it may be `out` itself (Jacobi only)."""
         torch = _torch()
         L = load()
         squeeze = False
@@ -388,6 +522,10 @@ class HMatrix:
         o.refine = int(bool(refine))
         o.inner_iters = int(inner_iters)
         o.warm = int(warm is not None)
+        o.method = METHODS[method]
+        if lam is not None:
+            o.lam_lo, o.lam_hi = float(lam[0]), float(lam[1])
+        o.restart = int(restart)
         iters = np.zeros(R * self.n_inst, dtype=np.int32)
         rel = np.zeros(R * self.n_inst, dtype=np.float64)
         info = SolveInfo(iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),

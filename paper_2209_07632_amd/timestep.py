@@ -21,7 +21,10 @@ _FIELDS = {"T": RAD_TS_T, "Q_abs": RAD_TS_QABS, "Q_refl": RAD_TS_QREFL, "Q_ir": 
 class TsParams(ctypes.Structure):
     _fields_ = [("n_layers", ctypes.c_int32), ("z", ctypes.c_void_p), ("conductivity", ctypes.c_double),
                 ("heat_capacity", ctypes.c_double), ("dt", ctypes.c_double), ("albedo", ctypes.c_double),
-                ("emissivity", ctypes.c_double), ("bottom_flux", ctypes.c_double)]
+                ("emissivity", ctypes.c_double), ("bottom_flux", ctypes.c_double), ("surface", ctypes.c_int32),
+                ("newton", ctypes.c_int32)]
+
+SURFACE = {"half_layer": 0, "balanced": 1}
 
 
 _bound = False
@@ -55,14 +58,15 @@ def _block(t, shape, dtype, name):
 class TimeStepper:
     """R scenarios of Algorithm 6 on the facets of an HMatrix (needs max_rhs >= 2 R)."""
 
-    def __init__(self, H, z, conductivity, heat_capacity, dt, albedo, emissivity, bottom_flux=0.0, R=1):
+    def __init__(self, H, z, conductivity, heat_capacity, dt, albedo, emissivity, bottom_flux=0.0, R=1,
+                 surface="half_layer", newton=3):
         self.H = H
         self._z = np.ascontiguousarray(z, dtype=np.float64)
         self.M = len(self._z) - 1
         self.R = int(R)
         self.N = H.N
         p = TsParams(self.M, self._z.ctypes.data, float(conductivity), float(heat_capacity), float(dt),
-                     float(albedo), float(emissivity), float(bottom_flux))
+                     float(albedo), float(emissivity), float(bottom_flux), SURFACE[surface], int(newton))
         h = ctypes.c_void_p()
         _check(_lib().rad_ts_create(H._h, ctypes.byref(p), self.R, ctypes.byref(h)))
         self._h = h

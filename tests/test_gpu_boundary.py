@@ -1,0 +1,189 @@
+"""GPU tests of the boundary calls beyond build / product / solve:
+
+* rad_hmat_build_facets on the exact-sphere kernel (centroids on a sphere,
+  inward radial normals: F_ij = A_j / (4 pi r^2), eq. FF-def) and the
+  Sherman-Morrison solution of (I - rho F) B = E that follows from it;
+* rad_hmat_export: the exported blocks tile F once, dense and CSR blocks equal
+  the reference's entries of F, low-rank blocks meet Algorithm 3's
+  truncation, uncovered entries of F are zero, and the product of the
+  densified blocks equals the GPU product elementwise (arithmetic parity of
+  Algorithm 5, independent of compression);
+* rad_hmat_save / rad_hmat_load: products and solves of a loaded matrix equal
+  those of the saved one bit for bit;
+* the rad_allocator hook: a matrix built through torch's caching allocator
+  lives in torch's memory and multiplies exactly as one built with hipMalloc.
+"""
+import numpy as np
+import pytest
+
+from oracle import reference as ref
+from synth import CAP_SMALL, DemSpec, cap_mesh, dem_mesh
+from hmat_blocks import densify, read_export
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def sphere(N, r, seed):
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal((N, 3))
+    p /= np.linalg.norm(p, axis=1, keepdims=True)
+    return r * p, -p, rng.uniform(0.5, 1.5, N) * 1e-2
+
+
+@pytest.mark.parametrize("tree", ["quad", "oct"])
+def test_build_facets_exact_sphere(tree):
+    """P1 through the GPU path: y = F-hat x with F_ij = A_j / (4 pi r^2), i != j."""
+    from paper_2209_07632_amd import HMatrix
+    r = 2.0
+    x, n, A = sphere(700, r, seed=4)
+    print(f"[build] sphere N=700 tree={tree}", flush=True)
+    H = HMatrix.from_facets(x, n, A, tol=1e-10, storage="f64", max_rhs=20, tree=tree)
+    X = np.random.default_rng(1).random((700, 20))
+    c = 1.0 / (4 * np.pi * r * r)
+    Yx = c * (A @ X)[None, :] - c * A[:, None] * X
+    for R in (3, 20):     # single-RHS kernels and the matrix cores
+        Y = H.matvec(torch.from_numpy(X[:, :R].copy()).to(DEV)).cpu().numpy()
+        err = np.max(np.abs(Y - Yx[:, :R])) / np.max(np.abs(Yx[:, :R]))
+        print(f"R={R} max rel err {err:.2e}")
+        assert err < 1e-12
+    st = H.stats()
+    assert st["n_dense"] + st["n_csr"] + st["n_lowrank"] > 0 and st["max_rank"] <= 2
+
+
+@pytest.mark.parametrize("rho", [0.3, 1.0])
+def test_build_facets_sherman_morrison(rho):
+    """P2 through the GPU path: the Jacobi solve equals the closed form."""
+    from paper_2209_07632_amd import HMatrix
+    r = 2.0
+    x, n, A = sphere(500, r, seed=1)
+    H = HMatrix.from_facets(x, n, A, tol=1e-10, storage="f64", max_rhs=16, tree="oct")
+    E = np.random.default_rng(2).uniform(0.0, 10.0, (500, 16))
+    c = 1.0 / (4 * np.pi * r * r)
+    D = 1.0 + rho * c * A
+    s = (A @ (E / D[:, None])) / (1.0 - rho * c * np.sum(A / D))
+    Bx = (E + rho * c * s[None, :]) / D[:, None]
+    for R in (2, 16):
+        B, info = H.solve(torch.from_numpy(E[:, :R].copy()).to(DEV), rho=rho, rtol=1e-14, max_iter=400)
+        err = np.max(np.abs(B.cpu().numpy() - Bx[:, :R])) / np.max(np.abs(Bx))
+        print(f"rho={rho} R={R} iters {info['total_iters']} max rel err {err:.2e}")
+        assert err < 1e-12
+
+
+def test_build_facets_without_triangles_casts_no_shadows():
+    """Without triangles there are no occluders: Q = flux max(0, n . s)."""
+    from paper_2209_07632_amd import HMatrix
+    x, n, A = sphere(300, 2.0, seed=7)
+    H = HMatrix.from_facets(x, n, A, tol=1e-6, storage="f64", max_rhs=4)
+    suns = np.array([[0.0, 0.0, 1.0], [0.6, 0.0, 0.8], [0.0, -1.0, 0.0]])
+    Q = H.insolation(suns, flux=1000.0).cpu().numpy()
+    np.testing.assert_allclose(Q, 1000.0 * np.maximum(0.0, n @ suns.T), rtol=1e-15, atol=0.0)
+
+
+def _mesh(kind):
+    if kind == "cap":
+        return cap_mesh(CAP_SMALL), "backface"
+    return dem_mesh(DemSpec(n=20, seed=3)), "raycast"
+
+
+@pytest.mark.parametrize("kind,nearfield,tol", [("cap", "csr", 1e-2), ("cap", "auto", 1e-4),
+                                                ("dem", "auto", 1e-2), ("dem", "dense", 1e-3)])
+def test_export_blocks_against_reference(tmp_path, kind, nearfield, tol):
+    from paper_2209_07632_amd import HMatrix
+    (verts, faces), vis = _mesh(kind)
+    fac = ref.Facets(verts, faces)
+    F = ref.view_factor_matrix(fac, ref.pair_visibility(fac, "raycast") if vis == "raycast" else None)
+    print(f"[build] {kind} N={fac.N} nearfield={nearfield} tol={tol}", flush=True)
+    H = HMatrix(verts, faces, tol=tol, storage="f64", nearfield=nearfield, visibility=vis, max_rhs=24)
+    path = tmp_path / "blocks.bin"
+    H.export(path)
+    ex = read_export(path)
+    perm = ex["perm"]
+    np.testing.assert_array_equal(perm, H.perm())
+    Ft = F[np.ix_(perm, perm)]               # the reference's F in tree order
+    cover = np.zeros(F.shape, dtype=np.int32)
+    kinds = {1: 0, 2: 0, 3: 0}
+    worst = 0.0
+    for b in ex["blocks"]:
+        rows, cols = slice(b["i0"], b["i0"] + b["m"]), slice(b["j0"], b["j0"] + b["n"])
+        cover[rows, cols] += 1
+        kinds[b["kind"]] += 1
+        Fb = Ft[rows, cols]
+        Ab = b["dense"]()
+        if b["kind"] in (1, 2):
+            # dense and CSR blocks hold the entries of eq. FF-def themselves
+            np.testing.assert_allclose(Ab, Fb, rtol=1e-13, atol=1e-15 * np.abs(Ft).max())
+        else:
+            # Algorithm 3: truncated where sigma_{q+1} / sigma_1 < eps
+            s1 = np.linalg.norm(Fb, 2)
+            worst = max(worst, np.linalg.norm(Fb - Ab, 2) / s1)
+    print(f"blocks by kind {kinds}; worst low-rank spectral error / sigma_1 = {worst:.2e}")
+    assert cover.max() == 1                   # no entry in two blocks
+    assert np.all(Ft[cover == 0] == 0.0)      # what no block covers is zero in F
+    assert worst <= 2.0 * tol
+    # arithmetic parity of the product: densified blocks times X against the GPU
+    Fh = densify(ex)
+    X = np.random.default_rng(3).random((fac.N, 24))
+    Yd = Fh @ X
+    for R in (1, 24):
+        Y = H.matvec(torch.from_numpy(X[:, :R].copy()).to(DEV)).cpu().numpy()
+        err = np.max(np.abs(Y - Yd[:, :R])) / np.max(np.abs(Yd[:, :R]))
+        print(f"R={R} elementwise max rel err vs densified blocks {err:.2e}")
+        assert err < 1e-12
+
+
+@pytest.mark.parametrize("storage,lowp", [("f64", None), ("f32", "bf16")])
+def test_save_load_round_trip(tmp_path, storage, lowp):
+    from paper_2209_07632_amd import HMatrix
+    verts, faces = dem_mesh(DemSpec(n=24, seed=5))
+    H = HMatrix(verts, faces, tol=1e-3, storage=storage, visibility="raycast", max_rhs=32, lowp=lowp)
+    path = tmp_path / "h.bin"
+    H.save(path)
+    G = HMatrix.load(path)
+    assert (G.N, G.rad_dtype, G.lowp, G.max_rhs) == (H.N, H.rad_dtype, H.lowp, 32)
+    assert G.stats() == H.stats()
+    np.testing.assert_array_equal(G.perm(), H.perm())
+    dt = torch.float64 if storage == "f64" else torch.float32
+    X = torch.rand((H.N, 32), dtype=dt, device=DEV)
+    for R in (1, 32):
+        assert torch.equal(G.matvec(X[:, :R].contiguous()), H.matvec(X[:, :R].contiguous())), R
+    E = 0.3 * H.insolation(np.array([[0.3, 0.2, 0.93], [0.0, 0.96, 0.28]]))
+    assert torch.equal(G.insolation(np.array([[0.3, 0.2, 0.93], [0.0, 0.96, 0.28]])) * 0.3, E)
+    B1, i1 = H.solve(E, rho=0.3, rtol=1e-8)
+    B2, i2 = G.solve(E, rho=0.3, rtol=1e-8)
+    assert torch.equal(B1, B2)
+    np.testing.assert_array_equal(i1["iters"], i2["iters"])
+    if lowp:
+        Xr = torch.rand((H.N, 32), dtype=torch.float32, device=DEV)
+        assert torch.equal(G.matvec(Xr, lowp=True), H.matvec(Xr, lowp=True))
+    # a larger workspace on load
+    G2 = HMatrix.load(path, max_rhs=48)
+    assert G2.max_rhs == 48
+    X2 = torch.rand((H.N, 48), dtype=dt, device=DEV)
+    H2 = HMatrix(verts, faces, tol=1e-3, storage=storage, visibility="raycast", max_rhs=48, lowp=lowp)
+    assert torch.equal(G2.matvec(X2), H2.matvec(X2))
+
+
+def test_torch_allocator_hook():
+    from paper_2209_07632_amd import HMatrix
+    verts, faces = cap_mesh(CAP_SMALL)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated(0)
+    H = HMatrix(verts, faces, tol=1e-4, storage="f64", nearfield="csr", max_rhs=32, allocator="torch")
+    held = torch.cuda.memory_allocated(0) - before
+    st = H.stats()
+    print(f"torch holds {held} bytes for an operator of {st['bytes_total']} bytes plus workspace")
+    assert held >= st["bytes_total"]
+    H0 = HMatrix(verts, faces, tol=1e-4, storage="f64", nearfield="csr", max_rhs=32)
+    X = torch.rand((H.N, 32), dtype=torch.float64, device=DEV)
+    for R in (1, 32):
+        assert torch.equal(H.matvec(X[:, :R].contiguous()), H0.matvec(X[:, :R].contiguous()))
+    B, _ = H.solve(X, rho=0.3, rtol=1e-10)
+    B0, _ = H0.solve(X, rho=0.3, rtol=1e-10)
+    assert torch.equal(B, B0)
+    del X, B, B0                               # the test's own tensors
+    H.close()                                  # the matrix returns all of its memory to torch
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated(0) - before <= 0

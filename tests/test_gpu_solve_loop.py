@@ -1,7 +1,9 @@
-"""The multi-RHS Jacobi loop (sections 3 and 5.1): per-column stopping against
-the oracle's Jacobi, the max_iter cap, and solves that follow one another on
-one matrix (the device-side stopping flag of a converged solve must not leak
-into the next one)."""
+"""The Jacobi loop (sections 3 and 5.1), on the matrix-core kernels (R >= 16)
+and on the single-RHS kernels (R < 16), both with the device-side stopping
+test and one iteration queued ahead: per-column stopping against the oracle's
+Jacobi, the max_iter cap, and solves that follow one another on one matrix
+(the device-side stopping flag of a converged solve must not leak into the
+next one)."""
 import numpy as np
 import pytest
 
@@ -40,10 +42,10 @@ def _mixed_rhs(fac, R, seed):
     return E
 
 
+@pytest.mark.parametrize("R", [40, 6])
 @pytest.mark.parametrize("rho,rtol", [(0.3, 1e-6), (0.9, 1e-4)])
-def test_per_column_iterations_match_oracle(cap, rho, rtol):
+def test_per_column_iterations_match_oracle(cap, rho, rtol, R):
     verts, faces, fac, F = cap
-    R = 40
     E = _mixed_rhs(fac, R, seed=int(10 * rho))
     H = _hm(verts, faces, tol=1e-10, storage="f64", max_rhs=R)
     B, info = H.solve(torch.from_numpy(E).to(DEV), rho=rho, rtol=rtol, max_iter=300)
@@ -55,9 +57,9 @@ def test_per_column_iterations_match_oracle(cap, rho, rtol):
     np.testing.assert_allclose(B.cpu().numpy(), Bo, rtol=1e-8, atol=1e-8 * np.abs(Bo).max())
 
 
-def test_max_iter_cap_returns_that_iterate(cap):
+@pytest.mark.parametrize("R", [24, 4])
+def test_max_iter_cap_returns_that_iterate(cap, R):
     verts, faces, fac, F = cap
-    R = 24
     E = _mixed_rhs(fac, R, seed=5)
     H = _hm(verts, faces, tol=1e-10, storage="f64", max_rhs=R)
     B, info = H.solve(torch.from_numpy(E).to(DEV), rho=0.5, rtol=1e-14, max_iter=2, raise_on_noconv=False)
@@ -68,12 +70,12 @@ def test_max_iter_cap_returns_that_iterate(cap):
     np.testing.assert_allclose(B.cpu().numpy(), B2, rtol=1e-8, atol=1e-8 * np.abs(B2).max())
 
 
+@pytest.mark.parametrize("R", [32, 5])
 @pytest.mark.parametrize("storage", ["f32", "f64"])
-def test_consecutive_solves_do_not_interfere(cap, storage):
+def test_consecutive_solves_do_not_interfere(cap, storage, R):
     """A quickly converging solve, then a tight one, then the quick one again on
     one matrix: each equals the same solve on a fresh matrix, bit for bit."""
     verts, faces, fac, F = cap
-    R = 32
     dt = torch.float64 if storage == "f64" else torch.float32
     E = torch.from_numpy(_mixed_rhs(fac, R, seed=7)).to(DEV, dt)
     H = _hm(verts, faces, tol=1e-6, storage=storage, max_rhs=R)

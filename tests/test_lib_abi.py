@@ -96,3 +96,68 @@ def test_build_tree_rejects_bad_tree_dims():
     faces = np.array([[0, 1, 2]], dtype=np.int32)
     st = L.rad_hmat_build_tree(verts.ctypes.data, 3, faces.ctypes.data, 1, ctypes.byref(o), 4, ctypes.byref(h))
     assert st == rad.RAD_EINVAL and b"tree_dims" in L.rad_last_error() and not h.value
+
+
+def test_build_facets_rejects_bad_geometry():
+    from paper_2209_07632_amd import rad
+    L = rad.load()
+    o = rad.BuildOpts()
+    L.rad_build_opts_default(ctypes.byref(o))
+    assert not o.allocator
+    h = ctypes.c_void_p()
+    x = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    n = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, 1.0]])
+    a = np.array([1.0, 1.0])
+    st = L.rad_hmat_build_facets(None, n.ctypes.data, a.ctypes.data, 2, None, ctypes.byref(o), 2, ctypes.byref(h))
+    assert st == rad.RAD_EINVAL and not h.value
+    n2 = n.copy()
+    n2[1, 2] = 0.5   # not a unit normal
+    st = L.rad_hmat_build_facets(x.ctypes.data, n2.ctypes.data, a.ctypes.data, 2, None, ctypes.byref(o), 2,
+                                 ctypes.byref(h))
+    assert st == rad.RAD_EINVAL and b"unit" in L.rad_last_error() and not h.value
+    a2 = np.array([1.0, 0.0])
+    st = L.rad_hmat_build_facets(x.ctypes.data, n.ctypes.data, a2.ctypes.data, 2, None, ctypes.byref(o), 2,
+                                 ctypes.byref(h))
+    assert st == rad.RAD_EINVAL and b"area" in L.rad_last_error()
+    o.visibility = 1   # ray casting needs the triangles
+    st = L.rad_hmat_build_facets(x.ctypes.data, n.ctypes.data, a.ctypes.data, 2, None, ctypes.byref(o), 2,
+                                 ctypes.byref(h))
+    assert st == rad.RAD_EINVAL and b"tri_verts" in L.rad_last_error()
+
+
+def test_files_reject_bad_input(tmp_path):
+    from paper_2209_07632_amd import rad
+    L = rad.load()
+    h = ctypes.c_void_p()
+    assert L.rad_hmat_export(None, b"x") == rad.RAD_EINVAL
+    assert L.rad_hmat_save(None, b"x") == rad.RAD_EINVAL
+    missing = str(tmp_path / "missing.bin").encode()
+    assert L.rad_hmat_load(missing, 0, 0, None, ctypes.byref(h)) == rad.RAD_EDEVICE and not h.value
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTAHMAT" + bytes(64))
+    st = L.rad_hmat_load(str(bad).encode(), 0, 0, None, ctypes.byref(h))
+    assert st == rad.RAD_EINVAL and b"not a saved" in L.rad_last_error() and not h.value
+    assert L.rad_hmat_lowp(None) == -1 and L.rad_hmat_max_rhs(None) == -1
+
+
+def test_block_export_reader(tmp_path):
+    """The test-side reader of rad_hmat_export files on a hand-made file: one
+    dense, one CSR and one rank-one block of a 4-facet matrix."""
+    import struct
+    from hmat_blocks import densify, read_export
+    perm = np.array([2, 0, 3, 1], dtype=np.int32)
+    out = [b"RADHBLKS", struct.pack("<Ii", 1, 0), struct.pack("<qq", 4, 3), perm.tobytes()]
+    A = np.array([[0.0, 1.0], [2.0, 0.0]])
+    out += [struct.pack("<6iq", 1, 0, 2, 0, 2, 0, 2), A.T.tobytes()]
+    out += [struct.pack("<6iq", 2, 2, 2, 2, 2, 0, 2), np.array([0, 1, 2], np.int32).tobytes(),
+            np.array([1, 0], np.int32).tobytes(), np.array([5.0, 7.0]).tobytes()]
+    U, V = np.array([[1.0], [2.0]]), np.array([[3.0], [4.0]])
+    out += [struct.pack("<6iq", 3, 0, 2, 2, 2, 1, 4), U.T.tobytes(), V.T.tobytes()]
+    path = tmp_path / "b.bin"
+    path.write_bytes(b"".join(out))
+    ex = read_export(path)
+    Ft = densify(ex, original_order=False)
+    expect = np.array([[0, 1, 3, 4], [2, 0, 6, 8], [0, 0, 0, 5], [0, 0, 7, 0]], dtype=float)
+    np.testing.assert_array_equal(Ft, expect)
+    F = densify(ex)
+    np.testing.assert_array_equal(F[np.ix_(perm, perm)], expect)

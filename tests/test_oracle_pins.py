@@ -486,14 +486,14 @@ def test_hmatrix_exact_sphere_blocks_rank_one():
 
 
 def test_hmatrix_tiles_matrix_and_error_tracks_eps():
-    v, f = cap_mesh(CAP_SMALL)
+    v, f = cap_mesh(CapSpec(h=90.0, seed=11))
     fac = ref.Facets(v, f)
     F = ref.view_factor_matrix(fac)
     xy = fac.x[:, :2]
     X = np.random.default_rng(2).random((fac.N, 4))
     Y0 = F @ X
     prev = None
-    for eps in (1e-2, 1e-3, 1e-4, 1e-6):
+    for eps in (1e-2, 1e-4, 1e-6):
         H = hm.assemble(F, xy, eps=eps)
         blocks = hm.leaf_blocks(H)
         cover = np.zeros((fac.N, fac.N), dtype=np.int32)
@@ -588,7 +588,7 @@ def test_bilobed_body_is_zero_block_heavy_and_error_tracks_eps():
     assert 0.01 < np.count_nonzero(F) / F.size < 0.1
     X = np.random.default_rng(4).random((fac.N, 3))
     Y0 = F @ X
-    for eps in (1e-2, 1e-3, 1e-4):
+    for eps in (1e-2, 1e-4):
         H = hm.assemble(F, fac.x, eps=eps, leaf_size=32)
         blocks = hm.leaf_blocks(H)
         cover = np.zeros(F.shape, dtype=np.int32)

@@ -50,21 +50,21 @@ def _initial(fac, R, z, seed):
     return base[None, :, :] + 20.0 * np.exp(-z / 0.1)[:, None, None] * rng.uniform(-1.0, 1.0, (len(z), R, fac.N))
 
 
-def _oracle(F, Q, T0, z):
+def _oracle(F, Q, T0, z, dt=DT, step=ots.cn_step):
     R = Q.shape[1]
     outs = []
     for r in range(R):
-        outs.append(ots.simulate(lambda x: F @ x, Q[:, r, :], ALBEDO, EMISS, T0[:, r, :].T, z, K, RHOC, DT,
-                                 H_bottom=HB, H0=H0))
+        outs.append(ots.simulate(lambda x: F @ x, Q[:, r, :], ALBEDO, EMISS, T0[:, r, :].T, z, K, RHOC, dt,
+                                 H_bottom=HB, H0=H0, step=step))
     return outs
 
 
-def _stepper(verts, faces, R, z, storage="f64", tol=1e-10):
+def _stepper(verts, faces, R, z, storage="f64", tol=1e-10, dt=DT, **kw):
     from paper_2209_07632_amd import HMatrix
     from paper_2209_07632_amd.timestep import TimeStepper
-    print(f"[build] N={faces.shape[0]} R={R} storage={storage} tol={tol}", flush=True)
+    print(f"[build] N={faces.shape[0]} R={R} storage={storage} tol={tol} dt={dt} {kw}", flush=True)
     H = HMatrix(verts, faces, tol=tol, storage=storage, max_rhs=2 * R)
-    return H, TimeStepper(H, z, K, RHOC, DT, ALBEDO, EMISS, bottom_flux=HB, R=R)
+    return H, TimeStepper(H, z, K, RHOC, dt, ALBEDO, EMISS, bottom_flux=HB, R=R, **kw)
 
 
 def _rel(a, b):
@@ -90,6 +90,31 @@ def test_stepper_matches_reference(bowl, R):
         for name in ("Q_abs", "Q_refl", "Q_ir", "Q_rad"):
             got = S.read(name).cpu().numpy()[r]
             assert _rel(got, want[r][name]) < 1e-9, (r, name)
+
+
+@pytest.mark.parametrize("R", [3, 8])
+@pytest.mark.parametrize("dt_days", [0.1, 0.3])
+def test_balanced_surface_matches_reference(bowl, dt_days, R):
+    """The balanced surface reading (radiation boundary condition at the new
+    level, Newton on the surface row) at the long steps of a lunation, against
+    the reference's second reading of the column step."""
+    import functools
+    verts, faces, fac, F = bowl
+    dt = dt_days * 86400.0
+    z = ots.layer_depths(20, 0.5, 1.12)
+    n = 24
+    Q = _levels(fac, R, n, seed=30 + R)
+    T0 = _initial(fac, R, z, seed=31 + R)
+    H, S = _stepper(verts, faces, R, z, dt=dt, surface="balanced", newton=3)
+    S.init(torch.from_numpy(T0).to(DEV), torch.from_numpy(Q[0]).to(DEV), H0=H0)
+    S.step(torch.from_numpy(Q[1:]).to(DEV).contiguous())
+    want = _oracle(F, Q, T0, z, dt=dt, step=functools.partial(ots.cn_step_balanced, newton=3))
+    T = S.read("T").cpu().numpy()
+    for r in range(R):
+        err = _rel(T[:, r, :].T, want[r]["T"])
+        assert err < 1e-9, (r, err)
+        for name in ("Q_abs", "Q_ir", "Q_rad"):
+            assert _rel(S.read(name).cpu().numpy()[r], want[r][name]) < 1e-9, (r, name)
 
 
 def test_level_zero_state(bowl):
@@ -160,6 +185,8 @@ def test_rejects_bad_arguments(bowl):
         TimeStepper(H, z[::-1] - z[-1], K, RHOC, DT, ALBEDO, EMISS, R=2)
     with pytest.raises(RadError, match="emissivity"):
         TimeStepper(H, z, K, RHOC, DT, ALBEDO, 0.0, R=2)
+    with pytest.raises(RadError, match="newton"):
+        TimeStepper(H, z, K, RHOC, DT, ALBEDO, EMISS, R=2, surface="balanced", newton=-1)
     S = TimeStepper(H, z, K, RHOC, DT, ALBEDO, EMISS, R=2)
     with pytest.raises(RadError, match="rad_ts_init"):
         S.step(torch.zeros((1, 2, fac.N), dtype=torch.float64, device=DEV))
