@@ -97,11 +97,15 @@ def cpu_baseline(verts, faces, suns, albedo, B_gpu_cols, cols, S):
     E = albedo * Q
     B, iters = ref.jacobi(lambda X: ref.matvec_free(fac, X), albedo, E, tol=1e-10)
     dt = time.perf_counter() - t0
-    errs = [float(np.linalg.norm(B_gpu_cols[:, k] - B[:, k]) / np.linalg.norm(B[:, k]))
-            for k in range(len(cols))]
     return {"value": len(cols) / dt, "unit": "solves/s", "cores": ref.num_threads(), "kind": "oracle",
             "sample": f"{len(cols)} sun columns of the full workload (insolation + FP64 matrix-free "
-                      f"Jacobi to 1e-10), {dt:.1f} s"}, max(errs), iters.tolist()
+                      f"Jacobi to 1e-10), {dt:.1f} s"}, col_err(B_gpu_cols, B), B
+
+
+def col_err(B_gpu, B_ref):
+    """Largest relative L2 error over the columns."""
+    return max(float(np.linalg.norm(B_gpu[:, k] - B_ref[:, k]) / np.linalg.norm(B_ref[:, k]))
+               for k in range(B_ref.shape[1]))
 
 
 def sampled_row_residual(verts, faces, B_orig, E_orig, rho, rows):
@@ -114,23 +118,26 @@ def sampled_row_residual(verts, faces, B_orig, E_orig, rho, rows):
     return float(np.linalg.norm(res) / np.linalg.norm(B_orig[rows]))
 
 
-def run_dem(args):
+def terrain_measure(steps, tol=1e-3, lowp="bf16", rtol=1e-4, inner=3, cpu_rows=6, fp64=True):
     """Polar terrain: 256 x 256 DEM (131,072 facets), sun at 1.5 deg elevation
     stepping through 2,880 azimuths (0.125 deg), right-hand sides in batches of
-    256; FP32 operator with a 16-bit copy, refined solves to 1e-4."""
+    256; FP32 operator with a 16-bit copy.  Times the sweep of all suns by
+    refined 16-bit solves to rtol, by plain FP32 Jacobi, and (fp64) by the
+    plain FP64 single-RHS form on the same compressed operator converted to
+    FP64; the single-RHS FP32 product on the multi-GB operator; the kernels of
+    one iteration.  Returns a dict (and the matrix and data for the CPU check)."""
     import torch
     from paper_2209_07632_amd import HMatrix
-    from paper_2209_07632_amd.rad import ldr_of
     from synth import DEM_256, dem_mesh, sun_grid_azimuth
 
     S, albedo, Rb = 1365.0, 0.3, 256
     verts, faces = dem_mesh(DEM_256)
     N = faces.shape[0]
     suns = sun_grid_azimuth(1.5, 2880, 0.125)
-    log(f"DEM N={N}; building F-hat tol={args.tol} f32 + {args.lowp} copy, near field dense, leaf 128")
+    log(f"DEM N={N}; building F-hat tol={tol} f32 + {lowp} copy, near field dense, leaf 128")
     t0 = time.perf_counter()
-    H = HMatrix(verts, faces, tol=args.tol, storage="f32", visibility="raycast", nearfield="dense", leaf_size=128,
-                max_rank=256, max_rhs=Rb, lowp=args.lowp, verbose=True)
+    H = HMatrix(verts, faces, tol=tol, storage="f32", visibility="raycast", nearfield="dense", leaf_size=128,
+                max_rank=256, max_rhs=Rb, lowp=lowp, verbose=True)
     build_s = time.perf_counter() - t0
     st = H.stats()
     log(f"built in {build_s:.1f} s: {st}")
@@ -143,11 +150,11 @@ def run_dem(args):
     torch.cuda.synchronize()
     log(f"insolation of {len(suns)} suns: {time.perf_counter() - t0:.2f} s")
 
-    def sweep(refine, rtol):
+    def sweep(refine, rt):
         tot_outer, tot_inner = 0, 0
         for E, B, R in batches:
-            _, info = H.solve(E, rho=albedo, rtol=rtol, out=B, order="tree_rmajor", R=R, refine=refine,
-                              inner_iters=args.inner, max_iter=200)
+            _, info = H.solve(E, rho=albedo, rtol=rt, out=B, order="tree_rmajor", R=R, refine=refine,
+                              inner_iters=inner, max_iter=200)
             tot_outer += info["total_iters"]
             tot_inner += info["inner_iters"]
         return tot_outer, tot_inner
@@ -157,20 +164,20 @@ def run_dem(args):
     results = {}
     for name, refine in (("refined_16bit", True), ("fp32_jacobi", False)):
         E, B, R = batches[0]
-        H.solve(E, rho=albedo, rtol=args.rtol, out=B, order="tree_rmajor", R=R, refine=refine,
-                inner_iters=args.inner, max_iter=200)
+        H.solve(E, rho=albedo, rtol=rtol, out=B, order="tree_rmajor", R=R, refine=refine, inner_iters=inner,
+                max_iter=200)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            outer, inner = sweep(refine, args.rtol)
+        for _ in range(steps):
+            outer, inner_n = sweep(refine, rtol)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
+        dt = (time.perf_counter() - t0) / steps
         results[name] = {"seconds_per_sweep": dt, "solves_per_s": len(suns) / dt, "outer_iters": outer,
-                         "inner_iters": inner}
+                         "inner_iters": inner_n}
         log(f"{name}: {dt:.3f} s per sweep of {len(suns)} suns, {len(suns) / dt:.1f} solves/s, "
-            f"outer {outer} inner {inner}")
+            f"outer {outer} inner {inner_n}")
     # the refined sweep last, so B holds its result for the accuracy check
-    sweep(True, args.rtol)
+    sweep(True, rtol)
     torch.cuda.synchronize()
 
     # single right-hand side FP32 product (GEMV path): streaming bound on the operator
@@ -187,66 +194,151 @@ def run_dem(args):
     ev1.synchronize()
     mv1_ms = ev0.elapsed_time(ev1) / 10
     op_bytes = st["bytes_dense"] + st["bytes_csr"] + st["bytes_lowrank"]
-    mv1_gbs = (op_bytes + 2 * N * 4) / (mv1_ms * 1e-3) / 1e9
-    log(f"single-RHS FP32 matvec {mv1_ms:.3f} ms, {mv1_gbs:.0f} GB/s on a {op_bytes / 1e9:.2f} GB operator")
+    mv1_flops = st["flops_per_rhs"]
+    roof_mv1 = roofline(mv1_flops, op_bytes + 2 * N * 4, mv1_ms, PEAK_TFLOPS["f32"],
+                        "whole single-RHS FP32 H-matvec (k_proj + k_tile_gemv) on the terrain operator")
+    log(f"single-RHS FP32 matvec {mv1_ms:.3f} ms, {roof_mv1['gbs']:.0f} GB/s on a {op_bytes / 1e9:.2f} GB operator")
 
     ph = H.time_phases(Rb, nrep=10, lowp=True)
     ph32 = H.time_phases(Rb, nrep=5)
     flops = 2.0 * Rb * (st["lowrank_row_elems"] + st["nnz_near"])
     bytes16 = (3.0 * N * Rb * 4 + 2 * st["lowrank_row_elems"] + 2 * st["nnz_near"] + st["sum_rank"] * Rb * 4)
-    tf = flops / (ph[2] * 1e-3) / 1e12
-    gbs = bytes16 / (ph[2] * 1e-3) / 1e9
-    peak = 2500.0
-    intensity = flops / bytes16
-    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if intensity < ridge:
-        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
-    else:
-        roof = {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak}
-    roof.update({"traffic": None, "kernel": f"k_tile_mm16<{args.lowp}, true> (16-bit expansion + dense near field "
-                                            "+ fused Jacobi update)",
-                 "ms_per_launch": ph[2], "flops_per_launch": flops, "bytes_per_launch": bytes16,
-                 "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge, "tflops": tf, "gbs": gbs})
-    log(f"16-bit phases ms {ph}: {tf:.1f} TFLOP/s {gbs:.0f} GB/s; FP32 phases ms {ph32}")
-
-    head = results["refined_16bit"]
-    result = {
-        "metric": "sun-RHS radiosity solves/s + H-matvec HBM GB/s at 1e-3 rel err vs plain FP64",
-        "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
-        "ms_per_step": 1e3 * head["seconds_per_sweep"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": f"{args.lowp}+f32+f64", "data": "synthetic",
-        "config": {"workload": f"polar DEM 256x256 N={N} (fBm H=0.8 RMS 30 m + 1.5 km bowl), sun 1.5 deg x 2880 "
-                               f"azimuths in batches of {Rb}, tol {args.tol}, {args.lowp} operator copy, "
-                               f"refinement to {args.rtol}, albedo {albedo}",
-                   "N": N, "rhs": len(suns), "batch": Rb, "tol": args.tol},
-        "build_seconds": build_s, "hmat_bytes": st["bytes_total"], "sweeps": results,
-        "hmatvec_single_rhs_ms": mv1_ms, "hmatvec_single_rhs_gbs": mv1_gbs,
-        "roofline": roof,
+    roof = roofline(flops, bytes16, ph[2], 2500.0,
+                    f"BF16 wide expansion (k_tile_mm16p on leaf pairs, k_tile_mm16w) + dense near field + fused "
+                    f"Jacobi update")
+    bytes32 = (3.0 * N * Rb * 4 + 4 * st["lowrank_row_elems"] + st["bytes_dense"] + st["sum_rank"] * Rb * 4)
+    roof32 = roofline(flops, bytes32, ph32[2], PEAK_TFLOPS["f32"],
+                      f"k_tile_mm<float, 1, {tune['tn']}> (FP32 expansion + dense near field + fused Jacobi update)")
+    log(f"16-bit phases ms {ph}: {roof['tflops']:.1f} TFLOP/s {roof['gbs']:.0f} GB/s; FP32 phases ms {ph32}")
+    out = {
+        "workload": f"polar DEM 256x256 N={N} (fBm H=0.8 RMS 30 m + 1.5 km bowl), sun 1.5 deg x 2880 azimuths "
+                    f"in batches of {Rb}, tol {tol}, {lowp} operator copy, refinement to {rtol}, albedo {albedo}",
+        "N": N, "suns": len(suns), "batch": Rb, "tol": tol, "build_seconds": build_s,
+        "hmat_bytes": st["bytes_total"], "hmat_blocks": block_counts(st),
+        "max_panel_cols": st["max_panel_cols"], "sweeps": results, "autotune": tune,
+        "hmatvec_single_rhs_ms": mv1_ms, "hmatvec_single_rhs_gbs": roof_mv1["gbs"],
+        "roofline_single_rhs_hmatvec": roof_mv1,
+        "roofline_expansion_16bit": roof, "roofline_expansion_fp32": roof32,
         "phase_ms_16bit": {"projections": ph[0], "split_k_sum": ph[1], "expansion_jacobi": ph[2]},
         "phase_ms_fp32": {"projections": ph32[0], "split_k_sum": ph32[1], "expansion_jacobi": ph32[2]},
     }
-    if not args.no_cpu_baseline:
+    if fp64:
+        # the plain FP64 single-RHS form on the same compressed operator: one
+        # sun at a time, the same tolerance and stopping rule
+        del x, y
+        G = H.convert("f64", max_rhs=1)
+        E0 = batches[0][0]
+        cols = [E0[:, c].double().contiguous() for c in range(16)]
+        Bt = torch.zeros(N, dtype=torch.float64, device="cuda:0")
+        for e in cols[:2]:
+            G.solve(e, rho=albedo, rtol=rtol, out=Bt, order="tree")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = []
+        for e in cols:
+            _, inf = G.solve(e, rho=albedo, rtol=rtol, out=Bt, order="tree")
+            its.append(inf["total_iters"])
+        torch.cuda.synchronize()
+        single64 = len(cols) / (time.perf_counter() - t0)
+        G.close()
+        out["fp64_single_rhs_solves_per_s"] = single64
+        out["fp64_single_rhs_iterations"] = its
+        out["speedup_refined_vs_fp64_single_rhs"] = results["refined_16bit"]["solves_per_s"] / single64
+        out["speedup_fp32_jacobi_vs_fp64_single_rhs"] = results["fp32_jacobi"]["solves_per_s"] / single64
+        log(f"plain FP64 single-RHS solves on the same operator: {single64:.1f} solves/s")
+    if cpu_rows > 0:
         perm = H.perm()
         E, B, R = batches[0]
-        cols = [0, 1]
-        Bt = B.double().cpu().numpy()[:, cols]
-        Et = E.double().cpu().numpy()[:, cols]
+        cc = [0, 1]
+        Bt = B.double().cpu().numpy()[:, cc]
+        Et = E.double().cpu().numpy()[:, cc]
         Bo, Eo = np.empty_like(Bt), np.empty_like(Et)
         Bo[perm], Eo[perm] = Bt, Et
-        rng = np.random.default_rng(3)
-        rows = sorted(rng.choice(N, size=args.cpu_rows, replace=False).tolist())
+        rows = sorted(np.random.default_rng(3).choice(N, size=cpu_rows, replace=False).tolist())
         log(f"CPU reference rows {rows} ...")
         t0 = time.perf_counter()
         res = sampled_row_residual(verts, faces, Bo, Eo, albedo, rows)
         dt = time.perf_counter() - t0
         from oracle import reference as ref
-        result["cpu_baseline"] = {"value": len(rows) / dt, "unit": "exact view-factor rows/s", "cores": ref.num_threads(),
-                                  "kind": "oracle",
-                                  "sample": f"{len(rows)} exact FP64 rows with brute-force ray-cast visibility, "
-                                            f"{dt:.1f} s"}
-        result["sampled_row_residual"] = res
+        out["cpu_baseline"] = {"value": len(rows) / dt, "unit": "exact view-factor rows/s",
+                               "cores": ref.num_threads(), "kind": "oracle",
+                               "sample": f"{len(rows)} exact FP64 rows with brute-force ray-cast visibility, "
+                                         f"{dt:.1f} s"}
+        out["sampled_row_residual"] = res
         log(f"sampled-row relative residual of the refined solution vs exact rows: {res:.3e}")
+    H.close()
+    return out
+
+
+def run_dem(args):
+    """The terrain workload as its own JSON line (value: refined sweep solves/s)."""
+    m = terrain_measure(args.steps, tol=args.tol, lowp=args.lowp, rtol=args.rtol, inner=args.inner,
+                        cpu_rows=0 if args.no_cpu_baseline else args.cpu_rows)
+    head = m["sweeps"]["refined_16bit"]
+    result = {
+        "metric": "sun-RHS radiosity solves/s + H-matvec HBM GB/s at 1e-3 rel err vs plain FP64",
+        "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": 1e3 * head["seconds_per_sweep"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": f"{args.lowp}+f32+f64", "data": "synthetic",
+        "config": {"workload": m["workload"], "N": m["N"], "rhs": m["suns"], "batch": m["batch"], "tol": m["tol"]},
+        "roofline": m["roofline_expansion_16bit"],
+    }
+    result.update({k: v for k, v in m.items() if k not in ("workload", "roofline_expansion_16bit")})
     print(json.dumps(result), flush=True)
+
+
+def cap_leg(verts, faces, suns, albedo, S, R, tol, storage, nearfield, steps, cols, Bref):
+    """One more compressed operator of the cap (another eps or precision): its
+    build, blocks, solve rate over all R suns, product rate, and its error on
+    the oracle's columns."""
+    import torch
+    from paper_2209_07632_amd import HMatrix
+    t0 = time.perf_counter()
+    H = HMatrix(verts, faces, tol=tol, storage=storage, nearfield=nearfield, max_rhs=R)
+    build_s = time.perf_counter() - t0
+    st = H.stats()
+    E = albedo * H.insolation(suns, flux=S, order="tree_rmajor")
+    B = torch.zeros_like(E)
+    H.autotune(R, nrep=3)
+    for _ in range(2):
+        _, info = H.solve(E, rho=albedo, rtol=1e-3, out=B, order="tree_rmajor", R=R)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info = H.solve(E, rho=albedo, rtol=1e-3, out=B, order="tree_rmajor", R=R)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    X = torch.rand(E.shape, dtype=E.dtype, device=E.device)
+    Y = torch.zeros_like(X)
+    for _ in range(3):
+        H.matvec(X, out=Y, order="tree_rmajor", R=R)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    ev0.record(stream)
+    for _ in range(10):
+        H.matvec(X, out=Y, order="tree_rmajor", R=R)
+    ev1.record(stream)
+    ev1.synchronize()
+    mv_ms = ev0.elapsed_time(ev1) / 10
+    sb = 8 if storage == "f64" else 4
+    mv = roofline(st["flops_per_rhs"] * R,
+                  st["bytes_dense"] + st["bytes_csr"] + st["bytes_lowrank"] + 2 * st["n"] * R * sb, mv_ms,
+                  PEAK_TFLOPS[storage], f"whole H-matmat, {R} columns")
+    out = {"tol": tol, "storage": storage, "build_seconds": build_s, "hmat_blocks": block_counts(st),
+           "solves_per_s": R / dt, "ms_per_step": 1e3 * dt, "iterations": info["total_iters"],
+           "hmatvec_ms": mv_ms, "hmatvec_gbs": mv["gbs"], "hmatvec_tflops": mv["tflops"],
+           "roofline_hmatvec": mv}
+    if Bref is not None:
+        perm = H.perm()
+        Bt = B.double().cpu().numpy()[:, :R]
+        Bo = np.empty_like(Bt)
+        Bo[perm] = Bt
+        out["max_rel_err_vs_fp64"] = col_err(Bo[:, cols], Bref)
+    log(f"cap leg tol={tol} {storage}: {out['solves_per_s']:.0f} solves/s, {out['iterations']} iterations, "
+        f"matvec {mv_ms:.3f} ms, build {build_s:.1f} s, blocks {out['hmat_blocks']}, "
+        f"err {out.get('max_rel_err_vs_fp64')}")
+    H.close()
+    return out
 
 
 def run_batch(args):
@@ -464,6 +556,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true", help="add a 1 GiB copy for counter calibration")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="the cap workload alone (no eps sweep, FP64 leg or terrain keys)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it"}))
@@ -669,7 +763,7 @@ def main():
         Bo[perm] = Bt
         Bc = Bo[:, cols]
         log(f"CPU reference on sun columns {cols} ...")
-        cb, err, it = cpu_baseline(verts, faces, suns, albedo, Bc, cols, S)
+        cb, err, Bref = cpu_baseline(verts, faces, suns, albedo, Bc, cols, S)
         result["cpu_baseline"] = cb
         result["max_rel_err_vs_fp64"] = err
         result["accuracy_columns"] = cols
@@ -677,6 +771,21 @@ def main():
         ok = err <= ACCURACY_TOL
         result["accuracy_ok"] = ok
         log(f"cpu baseline {cb}; GPU vs FP64 reference max rel err {err:.3e} over columns {cols}")
+    if not args.no_extras:
+        # the other configurations of the measurement, as extra keys of this
+        # line: the cap at other tolerances and in FP64 (errors on the oracle's
+        # columns above), then the 131k-facet terrain
+        Bref_cols = Bref if not args.no_cpu_baseline else None
+        cols = spread_columns(suns, args.cpu_cols)
+        gc.collect()
+        result["eps_sweep"] = [cap_leg(verts, faces, suns, albedo, S, R, t, args.dtype, args.nearfield, 5, cols,
+                                       Bref_cols) for t in (1e-2, 1e-4, 1e-5)]
+        result["fp64"] = cap_leg(verts, faces, suns, albedo, S, R, args.tol, "f64", args.nearfield, 5, cols,
+                                 Bref_cols)
+        H.close()
+        gc.collect()
+        torch.cuda.empty_cache()
+        result["dem131k"] = terrain_measure(2, cpu_rows=0 if args.no_cpu_baseline else 2)
     print(json.dumps(result), flush=True)
     if not ok:
         log(f"ACCURACY GATE FAILED: max relative error {result['max_rel_err_vs_fp64']:.3e} > {ACCURACY_TOL}")

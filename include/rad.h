@@ -191,6 +191,17 @@ rad_status rad_hmat_export(const rad_hmat *H, const char *path);
  * failure).  *out is NULL on error.
  */
 rad_status rad_hmat_save(const rad_hmat *H, const char *path);
+
+/*
+ * A new matrix with the compressed operator of H (same partition, ranks and
+ * layout) stored in dtype (RAD_F64 or RAD_F32): FP32 values widen exactly,
+ * FP64 values round.  This gives, for example, the FP64 form of an operator
+ * built in FP32 without a second assembly, so both precisions can be compared
+ * on one F-hat.  The 16-bit copy is not carried over; max_rhs as
+ * rad_hmat_load (0: H's); H's allocator hook serves the new matrix too.
+ * Errors: RAD_EINVAL (null, a group, bad dtype), RAD_ENOMEM, RAD_EDEVICE.
+ */
+rad_status rad_hmat_convert(const rad_hmat *H, int32_t dtype, int32_t max_rhs, rad_hmat **out);
 rad_status rad_hmat_load(const char *path, int32_t device, int32_t max_rhs, const rad_allocator *allocator,
                          rad_hmat **out);
 

@@ -49,6 +49,8 @@ void alloc_workspace(rad_hmat *H) {
     for (auto &e : H->ev) RAD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     RAD_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
     if (H->n_tiles > 0) mm_prepare_schedule(H);
+    // partial tiles of the split reductions of the wide 16-bit expansion
+    if (H->n_wsegs > 0 && H->max_rhs >= kMfmaMinRhs) H->w_wpart.alloc((size_t)H->n_wsegs * 128 * 256);
 }
 
 // One Jacobi iteration, enqueued on stream s: B_new = E + rho (F-hat B_old),
@@ -211,7 +213,9 @@ bool solve_chebyshev(const rad_hmat *H, const rad_solve_opts &o, bool mm, int64_
     void *r = H->w_q1.p, *d = H->w_q2.p, *Y = H->w_y.p;
     double *part = (double *)H->w_red.p;
     double *en_d = H->w_norms.p, *dn_d = H->w_norms.p + R;
-    RAD_HIP(hipMemcpyAsync(Bw, Ein, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
+    // (a block of R columns holds N ld values R-major, ld R column-major)
+    const size_t blk = (size_t)(mm ? N * ld : ld * R) * es;
+    RAD_HIP(hipMemcpyAsync(Bw, Ein, blk, hipMemcpyDeviceToDevice, s));
     krylov_dots(H, mm, ld, R, Ein, 0, 1, Ein, part, en_d, s);
     product_ws(H, mm, ld, R, Ein, Y, s);
     krylov_cheb_init(H, mm, ld, R, rho, theta, Y, r, d, part, s);
@@ -269,7 +273,9 @@ bool solve_gmres(const rad_hmat *H, const rad_solve_opts &o, bool mm, int64_t ld
     const int64_t N = H->N;
     const size_t es = (size_t)dsize(H->dtype);
     const int m = o.restart;
-    const int64_t vstride = N * ld;   // elements between basis vectors
+    // elements of one block of R columns (R-major N ld, column-major ld R):
+    // the stride between basis vectors
+    const int64_t vstride = mm ? N * ld : ld * R;
     const int n_tiles = (int)((N + 63) / 64);
     AllocScope scope(H->hook(), H->device);
     DevBuf<unsigned char> Vb((size_t)(m + 1) * (size_t)vstride * es);
@@ -278,7 +284,7 @@ bool solve_gmres(const rad_hmat *H, const rad_solve_opts &o, bool mm, int64_t ld
     unsigned char *V = Vb.p;
     void *w = H->w_q1.p, *r = H->w_q2.p, *Y = H->w_y.p;
     auto Vj = [&](int j) { return (void *)(V + (size_t)j * vstride * es); };
-    RAD_HIP(hipMemsetAsync(x, 0, (size_t)N * ld * es, s));
+    RAD_HIP(hipMemsetAsync(x, 0, (size_t)vstride * es, s));
     std::vector<double> e2(R), thr(R), beta(R);
     krylov_dots(H, mm, ld, R, Ein, 0, 1, Ein, part.p, nrm.p, s);
     RAD_HIP(hipMemcpyAsync(e2.data(), nrm.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -296,7 +302,7 @@ bool solve_gmres(const rad_hmat *H, const rad_solve_opts &o, bool mm, int64_t ld
     for (;;) {
         // true residual r = E - (I - rho F) x (x = 0 at the start: r = E)
         if (first) {
-            RAD_HIP(hipMemcpyAsync(r, Ein, (size_t)N * ld * es, hipMemcpyDeviceToDevice, s));
+            RAD_HIP(hipMemcpyAsync(r, Ein, (size_t)vstride * es, hipMemcpyDeviceToDevice, s));
         } else {
             product_ws(H, mm, ld, R, x, Y, s);
             krylov_apply_a(H, mm, ld, R, rho, rhov, Ein, x, Y, r, s);
@@ -502,6 +508,27 @@ rad_status rad_hmat_build_facets(const double *x, const double *n, const double 
         return st;
     }
     *out = H;
+    return RAD_OK;
+}
+
+rad_status rad_hmat_convert(const rad_hmat *H, int32_t dtype, int32_t max_rhs, rad_hmat **out) {
+    if (out) *out = nullptr;
+    rad_hmat *G = nullptr;
+    rad_status st = guard([&] {
+        RAD_REQUIRE(out != nullptr, "null output pointer");
+        check_hmat(H);
+        RAD_REQUIRE(max_rhs >= 0, "max_rhs must be >= 0");
+        G = new rad_hmat();
+        G->allocator = H->allocator;
+        AllocScope scope(G->hook(), H->device);
+        convert_hmat(G, H, dtype, max_rhs);
+        alloc_workspace(G);
+    });
+    if (st != RAD_OK) {
+        delete G;
+        return st;
+    }
+    *out = G;
     return RAD_OK;
 }
 

@@ -438,17 +438,20 @@ struct PairStage {
     }
 };
 
-template <bool kFused>
+// Segment kernel: work item i multiplies panel columns [k0, k1) of the two
+// tiles of its pair (seg[i]: panel and row-list offsets of that range) and
+// stores the 128 x 256 FP32 partial tile in slot i of wpart.  Items are
+// segments of at most a fixed number of panel columns, launched longest
+// first, so the uneven reductions of terrain tiles spread evenly over the
+// compute units; k_pair_finish sums a pair's segments in order.
+template <bool kUnused = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
-k_tile_mm16p(const TileInfo *tiles, const int32_t *first_tiles, const int32_t *brow, const __bf16 *vals16,
-             const __bf16 *X16, const __bf16 *T16, int64_t ld16, const float *X, int64_t ldr, int R, int64_t N,
-             float *Y, const float *E, const float *rho, float rho_s, double *partial) {
-    const int tile = first_tiles[xcd_remap16(blockIdx.x, gridDim.x)];
-    const TileInfo ti = tiles[tile], tj = tiles[tile + 1];
+k_tile_mm16s(const WideSeg *segs, const int32_t *brow, const __bf16 *vals16, const __bf16 *X16, const __bf16 *T16,
+             int64_t ld16, float *wpart) {
+    const WideSeg sg = segs[blockIdx.x];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     constexpr int kPipe = (2 * 2 * TM * WLDK + 2 * WN * WLDK) * 2;
-    constexpr int kOut = TM * (128 + 4) * 4;
-    __shared__ __align__(16) unsigned char smem[kPipe > kOut ? kPipe : kOut];
+    __shared__ __align__(16) unsigned char smem[kPipe];
     __bf16 (*sA)[2 * TM][WLDK] = (__bf16 (*)[2 * TM][WLDK])smem;
     __bf16 (*sB)[WN][WLDK] = (__bf16 (*)[WN][WLDK])(smem + 2 * 2 * TM * WLDK * sizeof(__bf16));
     f32x4 acc[4][8];
@@ -474,12 +477,12 @@ k_tile_mm16p(const TileInfo *tiles, const int32_t *first_tiles, const int32_t *b
                     acc[i][4 * jh + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][4 * jh + j], 0, 0, 0);
         }
     };
-    if (ti.kpad > 0) {
-        const __bf16 *pa = vals16 + ti.panel_off, *pb = vals16 + tj.panel_off;
-        const int32_t *br = brow + ti.brow_off;
+    if (sg.kp > 0) {
+        const __bf16 *pa = vals16 + sg.pa, *pb = vals16 + sg.pb;
+        const int32_t *br = brow + sg.br;
         PairStage s0, s1;
         WideStage::Rows rw0, rw1;
-        const int kp = ti.kpad;
+        const int kp = sg.kp;
         rw0.load(br, t);
         if (WKC < kp) rw1.load(br + WKC, t);
         s0.fetch(pa, pb, rw0, X16, T16, ld16, t);
@@ -506,26 +509,50 @@ k_tile_mm16p(const TileInfo *tiles, const int32_t *first_tiles, const int32_t *b
             mma(sA[1], sB[1]);
         }
     }
-    // epilogue per 64 x 128 quarter (q: tile half q & 1, column half q >> 1),
-    // held by wave q
-    float (*sC)[128 + 4] = (float (*)[128 + 4])smem;
+    // the partial tile, row-major 128 x 256: each lane's 16 consecutive
+    // columns of a row form 64-byte runs
+    float *out = wpart + (int64_t)sg.slot * (2 * TM * WN);
     const int lk = lane >> 4;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                __builtin_nontemporal_store(acc[i][j][v],
+                                            out + (int64_t)(wr + i * 16 + 4 * lk + v) * WN + wc + j * 16 + lr);
+}
+
+// One workgroup per tile of a pair: the sum of the pair's segments (slots
+// [slot, slot + nseg) of wpart, in order) for this tile's 64 rows, then the
+// epilogue of the expansion (Y, or the fused Jacobi update) per 128 columns.
+template <bool kFused>
+__global__ void __launch_bounds__(256) k_pair_finish(const int32_t *first_tiles, const int32_t *pair_slot,
+                                                      const float *wpart, const float *X, int64_t ldr, int R, int64_t N,
+                                                      float *Y, const float *E, const float *rho, float rho_s,
+                                                      double *partial) {
+    const int pair = blockIdx.x >> 1, half = blockIdx.x & 1;
+    const int tile = first_tiles[pair] + half;
+    const int slot0 = pair_slot[pair], nseg = pair_slot[pair + 1] - slot0;
+    if ((int64_t)tile * TM >= N) return;
+    __shared__ __align__(16) float sC[TM][128 + 4];
+    const int t = threadIdx.x;
+    for (int h = 0; h < 2 && 128 * h < R; ++h) {
         __syncthreads();
-        if (w == q) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) sC[i * 16 + 4 * lk + v][j * 16 + lr] = acc[i][j][v];
+        for (int e = t; e < TM * 128 / 4; e += 256) {
+            const int r = e >> 5, c4 = (e & 31) * 4;
+            const float *p = wpart + (int64_t)slot0 * (2 * TM * WN) + (int64_t)(TM * half + r) * WN + 128 * h + c4;
+            f32x4 sum = {0, 0, 0, 0};
+            for (int sgi = 0; sgi < nseg; ++sgi)
+                sum += __builtin_nontemporal_load((const f32x4 *)(p + (int64_t)sgi * (2 * TM * WN)));
+            sC[r][c4] = sum[0];
+            sC[r][c4 + 1] = sum[1];
+            sC[r][c4 + 2] = sum[2];
+            sC[r][c4 + 3] = sum[3];
         }
         __syncthreads();
-        const int tq = tile + (q & 1), h = q >> 1;
-        if (128 * h < R && (int64_t)tq * TM < N)
-            tile_epilogue<float, kFused, TM, 128, 128 + 4>(sC, smem, tq, (int64_t)tq * TM, 128 * h, ldr, R, N, Y, E,
-                                                           X, rho, rho_s, partial);
+        tile_epilogue<float, kFused, TM, 128, 128 + 4>(sC, sC, tile, (int64_t)tile * TM, 128 * h, ldr, R, N, Y, E, X,
+                                                       rho, rho_s, partial);
     }
 }
 
@@ -653,10 +680,13 @@ void launch_wide(const rad_hmat *Hm, const float *E, const float *rho, float rho
     const __bf16 *v16 = (const __bf16 *)Hm->d_vals16.p, *x16 = (const __bf16 *)Hm->w_x16.p,
                  *t16 = (const __bf16 *)Hm->w_t16.p;
     if (Hm->n_wpairs > 0) {
-        // pairs of tiles with one operand-row list, then the tiles left alone
-        hipLaunchKernelGGL((k_tile_mm16p<kFused>), dim3(Hm->n_wpairs), dim3(256), 0, s, Hm->d_tiles.p,
-                           Hm->d_wpairs.p, Hm->d_brow.p, v16, x16, t16, ld16, Bold, ldr, R, Hm->N, Bnew, E, rho,
-                           rho_s, part);
+        // pairs of tiles with one operand-row list: their segments longest
+        // first, then each pair's sum and epilogue; then the tiles left alone
+        hipLaunchKernelGGL(k_tile_mm16s<>, dim3(Hm->n_wsegs), dim3(256), 0, s, Hm->d_wsegs.p, Hm->d_brow.p, v16,
+                           x16, t16, ld16, Hm->w_wpart.p);
+        hipLaunchKernelGGL((k_pair_finish<kFused>), dim3(2 * Hm->n_wpairs), dim3(256), 0, s, Hm->d_wpairs.p,
+                           Hm->d_wslot.p, (const float *)Hm->w_wpart.p, Bold, ldr, R, Hm->N, Bnew, E, rho, rho_s,
+                           part);
         if (Hm->n_wsingles > 0)
             hipLaunchKernelGGL((k_tile_mm16w<kFused>), dim3(Hm->n_wsingles), dim3(256), 0, s, Hm->d_tiles.p,
                                Hm->d_wsingles.p, Hm->d_brow.p, v16, x16, t16, ld16, Bold, ldr, R, Hm->N, Bnew, E, rho,

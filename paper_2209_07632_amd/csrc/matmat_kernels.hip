@@ -1060,6 +1060,35 @@ void mm_prepare_schedule(rad_hmat *H) {
         H->n_wsingles = (int32_t)ws.size();
         H->d_wpairs.upload(wp);
         H->d_wsingles.upload(ws);
+        // segments: a pair's reduction is cut into near-equal runs of at most
+        // kSeg panel columns (whole 32-column chunks of the 16-bit layout,
+        // 64 x 32 values each); a pair's segments take consecutive partial
+        // slots in order, and are launched longest first
+        constexpr int32_t kSeg = 12288;
+        std::vector<WideSeg> bySlot;
+        std::vector<int32_t> pslot(1, 0);
+        for (int32_t p = 0; p < (int32_t)wp.size(); ++p) {
+            const TileInfo &a = ti[wp[p]], &b = ti[wp[p] + 1];
+            const int32_t chunks = a.kpad / 32;
+            const int32_t nseg = std::max(1, (a.kpad + kSeg - 1) / kSeg);
+            for (int32_t sg = 0; sg < nseg; ++sg) {
+                const int64_t c0 = (int64_t)chunks * sg / nseg, c1 = (int64_t)chunks * (sg + 1) / nseg;
+                WideSeg w{};
+                w.pa = a.panel_off + c0 * 32 * 64;
+                w.pb = b.panel_off + c0 * 32 * 64;
+                w.br = a.brow_off + c0 * 32;
+                w.kp = (int32_t)(32 * (c1 - c0));
+                w.slot = (int32_t)bySlot.size();
+                bySlot.push_back(w);
+            }
+            pslot.push_back((int32_t)bySlot.size());
+        }
+        // launch order: longest first
+        std::vector<WideSeg> segs = bySlot;
+        std::stable_sort(segs.begin(), segs.end(), [](const WideSeg &x, const WideSeg &y) { return x.kp > y.kp; });
+        H->n_wsegs = (int32_t)segs.size();
+        H->d_wsegs.upload(segs);
+        H->d_wslot.upload(pslot);
     }
     int ncu = 0;
     RAD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, H->device));

@@ -191,6 +191,15 @@ struct TileTask {
     int32_t full;          // 1: every row in [r_lo, r_hi) holds all ncol columns (values row-major, ld ncol)
 };
 
+// Segment of the wide 16-bit tile-pair expansion: kp panel columns of the two
+// tiles of a pair, whose 16-bit panels start at element offsets pa and pb
+// of the value pool and whose operand-row list starts at br; its partial
+// tile goes to slot `slot` (a pair's segments hold consecutive slots, in order).
+struct WideSeg {
+    int64_t pa, pb, br;
+    int32_t kp, slot;
+};
+
 // Phase-1 group: all low-rank blocks sharing column node J.
 struct ProjGroup {
     int32_t j0, n;         // X rows
@@ -330,6 +339,10 @@ struct rad_hmat {
     // operand-row lists (one 128-row workgroup each), and the remaining tiles
     rad::DevBuf<int32_t> d_wpairs, d_wsingles;
     int32_t n_wpairs = 0, n_wsingles = 0;
+    rad::DevBuf<rad::WideSeg> d_wsegs;    // the pairs' reduction segments, longest first
+    int32_t n_wsegs = 0;
+    rad::DevBuf<int32_t> d_wslot;         // pair p's segments' partial tiles: slots [wslot[p], wslot[p+1])
+    rad::DevBuf<float> w_wpart;           // partial tiles of the segments (128 x 256 FP32 each)
     int32_t n_cu = 256;
     std::string sched_sig;           // dtype, tile count and tile-cost histogram hash (autotuner cache key)
     std::vector<int64_t> inst_off, inst_n;
@@ -383,6 +396,8 @@ void build_hmat(rad_hmat *H, const double *verts, int64_t nv, const int32_t *fac
 void export_blocks(const rad_hmat *H, const char *path);
 void save_hmat(const rad_hmat *H, const char *path);
 void load_hmat(rad_hmat *H, const char *path, int32_t device, int32_t max_rhs);
+// G = the operator of H with its values in dtype (same structure and layout)
+void convert_hmat(rad_hmat *G, const rad_hmat *H, int32_t dtype, int32_t max_rhs);
 // the same from centroids, unit normals, areas and optional triangles (N x 9)
 void build_hmat_facets(rad_hmat *H, const double *x, const double *n, const double *area, int64_t N,
                        const double *tri_verts, const rad_build_opts &o, int tree_dims);

@@ -1,6 +1,7 @@
 // Files of a compressed operator: the block export (host blocks of the
 // partition of Algorithm 4, FP64) and the save/load of the whole device
 // layout, so that a matrix assembled once is used elsewhere.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -327,6 +328,107 @@ void load_hmat(rad_hmat *H, const char *path, int32_t device, int32_t max_rhs) {
     RAD_REQUIRE((int64_t)H->perm.size() == H->N && H->d_tiles.n == (size_t)H->n_tiles &&
                     H->d_p1work.n == (size_t)H->n_p1work && H->h_groups.size() == (size_t)H->n_groups,
                 "inconsistent table sizes in file");
+}
+
+namespace {
+
+__global__ void k_cast_f32_f64(const float *src, double *dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (double)src[i];
+}
+
+__global__ void k_cast_f64_f32(const double *src, float *dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+template <class T>
+void copy_dev(DevBuf<T> &dst, const DevBuf<T> &src) {
+    dst.alloc(src.n);
+    if (src.n) RAD_HIP(hipMemcpy(dst.p, src.p, src.n * sizeof(T), hipMemcpyDeviceToDevice));
+}
+
+}  // namespace
+
+void convert_hmat(rad_hmat *G, const rad_hmat *H, int32_t dtype, int32_t max_rhs) {
+    RAD_REQUIRE(H->n_inst == 1, "convert takes a single matrix, not a group");
+    RAD_REQUIRE(dtype == RAD_F64 || dtype == RAD_F32, "dtype must be RAD_F64 or RAD_F32");
+    RAD_HIP(hipSetDevice(H->device));
+    G->device = H->device;
+    G->N = H->N;
+    G->dtype = dtype;
+    G->max_rhs = max_rhs > 0 ? max_rhs : H->max_rhs;
+    G->leaf_size = H->leaf_size;
+    G->perm = H->perm;
+    G->nodes = H->nodes;
+    G->stats = H->stats;
+    copy_dev(G->d_perm, H->d_perm);
+    // the value pool, element by element in the new precision (same offsets)
+    const int64_t nvals = (int64_t)(H->d_vals.n / (H->dtype == RAD_F64 ? 8 : 4));
+    G->d_vals.alloc((size_t)nvals * (dtype == RAD_F64 ? 8 : 4));
+    if (dtype == H->dtype) {
+        RAD_HIP(hipMemcpy(G->d_vals.p, H->d_vals.p, H->d_vals.n, hipMemcpyDeviceToDevice));
+    } else {
+        const unsigned blocks = (unsigned)std::min<int64_t>((nvals + 255) / 256, 65536);
+        if (dtype == RAD_F64)
+            hipLaunchKernelGGL(k_cast_f32_f64, dim3(blocks), dim3(256), 0, nullptr, (const float *)H->d_vals.p,
+                               (double *)G->d_vals.p, nvals);
+        else
+            hipLaunchKernelGGL(k_cast_f64_f32, dim3(blocks), dim3(256), 0, nullptr, (const double *)H->d_vals.p,
+                               (float *)G->d_vals.p, nvals);
+        RAD_HIP(hipGetLastError());
+        RAD_HIP(hipDeviceSynchronize());
+    }
+    copy_dev(G->d_csr_idx, H->d_csr_idx);
+    copy_dev(G->d_csr_ptr, H->d_csr_ptr);
+    copy_dev(G->d_groups, H->d_groups);
+    G->n_leaves = H->n_leaves;
+    G->n_groups = H->n_groups;
+    G->t_rows = H->t_rows;
+    G->t_ld = H->t_ld;
+    G->csr_val_start = H->csr_val_start;
+    G->h_groups = H->h_groups;
+    copy_dev(G->d_tile_tasks, H->d_tile_tasks);
+    copy_dev(G->d_tiles, H->d_tiles);
+    copy_dev(G->d_brow, H->d_brow);
+    G->n_tiles = H->n_tiles;
+    copy_dev(G->d_p1work, H->d_p1work);
+    copy_dev(G->d_p1red, H->d_p1red);
+    G->n_p1work = H->n_p1work;
+    G->n_p1red = H->n_p1red;
+    G->n_parts = H->n_parts;
+    copy_dev(G->d_x, H->d_x);
+    copy_dev(G->d_n, H->d_n);
+    copy_dev(G->d_a, H->d_a);
+    copy_dev(G->d_tri, H->d_tri);
+    copy_dev(G->d_cell_zmax, H->d_cell_zmax);
+    copy_dev(G->d_cell_start, H->d_cell_start);
+    copy_dev(G->d_cell_tris, H->d_cell_tris);
+    G->grid_x0 = H->grid_x0;
+    G->grid_y0 = H->grid_y0;
+    G->grid_h = H->grid_h;
+    G->grid_ztop = H->grid_ztop;
+    G->grid_gx = H->grid_gx;
+    G->grid_gy = H->grid_gy;
+    G->lowp = 0;   // the 16-bit copy is not carried over
+    G->blocks = H->blocks;
+    G->pieces = H->pieces;
+    // stored bytes at the new value size (eq. nbytes-comparison, reading 8)
+    const int64_t sz = dtype == RAD_F64 ? 8 : 4;
+    rad_hmat_stats &st = G->stats;
+    st.dtype = dtype;
+    st.bytes_dense = st.bytes_csr = st.bytes_lowrank = 0;
+    for (const BlockRec &b : G->blocks) {
+        if (b.kind == BK_DENSE)
+            st.bytes_dense += (int64_t)b.m * b.n * sz;
+        else if (b.kind == BK_CSR)
+            st.bytes_csr += 4 * ((int64_t)b.m + 1) + b.nnz * (4 + sz);
+        else
+            st.bytes_lowrank += ((int64_t)b.m + b.n) * b.rank * sz + b.rank * sz;
+    }
+    st.bytes_total = (int64_t)G->d_vals.bytes() + (int64_t)G->d_csr_idx.bytes() + (int64_t)G->d_csr_ptr.bytes() +
+                     (int64_t)G->d_tiles.bytes() + (int64_t)G->d_brow.bytes() + (int64_t)G->d_groups.bytes() +
+                     (int64_t)G->d_tile_tasks.bytes() + (int64_t)G->d_perm.bytes();
 }
 
 }  // namespace rad

@@ -99,7 +99,7 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["rad_build_opts_default", "rad_hmat_build", "rad_hmat_build_tree", "rad_hmat_build_facets",
-           "rad_hmat_export", "rad_hmat_save", "rad_hmat_load", "rad_hmat_matvec",
+           "rad_hmat_export", "rad_hmat_save", "rad_hmat_load", "rad_hmat_convert", "rad_hmat_matvec",
            "rad_hmat_matvec_noalloc", "rad_noalloc_scratch_bytes", "rad_solve_opts_default", "rad_solve",
            "rad_insolation", "rad_equilibrium", "rad_hmat_time_phases", "rad_hmat_info", "rad_hmat_n", "rad_hmat_dtype", "rad_hmat_lowp",
            "rad_hmat_max_rhs", "rad_hmat_perm", "rad_hmat_free",
@@ -136,6 +136,8 @@ def load(path: str = LIB_PATH):
     L.rad_hmat_build_facets.argtypes = [vp, vp, vp, ctypes.c_int64, vp, ctypes.POINTER(BuildOpts), ctypes.c_int32,
                                         ctypes.POINTER(vp)]
     L.rad_hmat_build_facets.restype = ctypes.c_int
+    L.rad_hmat_convert.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vp)]
+    L.rad_hmat_convert.restype = ctypes.c_int
     L.rad_hmat_export.argtypes = [vp, ctypes.c_char_p]
     L.rad_hmat_export.restype = ctypes.c_int
     L.rad_hmat_save.argtypes = [vp, ctypes.c_char_p]
@@ -363,6 +365,16 @@ class HMatrix:
             self.sizes = np.zeros(self.n_inst, dtype=np.int64)
             _check(L.rad_hmat_group_layout(h, self.offsets.ctypes.data, self.sizes.ctypes.data))
         return self
+
+    def convert(self, storage, max_rhs=0):
+        """The same compressed operator stored in another precision ("f64" or
+        "f32"), as a new matrix (rad_hmat_convert)."""
+        L = load()
+        h = ctypes.c_void_p()
+        _check(L.rad_hmat_convert(self._h, DTYPES[storage], int(max_rhs), ctypes.byref(h)))
+        G = object.__new__(type(self))
+        G._adopt(h, 0, int(L.rad_hmat_max_rhs(h)), self.device, getattr(self, "_alloc", None))
+        return G
 
     def save(self, path):
         """Write the whole compressed operator to a file (rad_hmat_save)."""

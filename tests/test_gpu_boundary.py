@@ -187,3 +187,27 @@ def test_torch_allocator_hook():
     H.close()                                  # the matrix returns all of its memory to torch
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated(0) - before <= 0
+
+
+def test_convert_keeps_the_operator(tmp_path):
+    """rad_hmat_convert: the FP64 form of an FP32 operator multiplies with the
+    same values (its product equals the FP32 matrix's exported blocks times X
+    in FP64 arithmetic), and converting back gives the FP32 products bit for bit."""
+    from paper_2209_07632_amd import HMatrix
+    verts, faces = dem_mesh(DemSpec(n=20, seed=6))
+    H = HMatrix(verts, faces, tol=1e-3, storage="f32", visibility="raycast", nearfield="auto", max_rhs=24)
+    path = tmp_path / "b32.bin"
+    H.export(path)
+    Fh = densify(read_export(path))
+    G = H.convert("f64")
+    assert G.rad_dtype == 0 and G.max_rhs == 24
+    st, sg = H.stats(), G.stats()
+    assert (sg["n_dense"], sg["n_csr"], sg["n_lowrank"], sg["sum_rank"]) == \
+        (st["n_dense"], st["n_csr"], st["n_lowrank"], st["sum_rank"])
+    X = np.random.default_rng(4).random((H.N, 24))
+    for R in (2, 24):
+        Y = G.matvec(torch.from_numpy(X[:, :R].copy()).to(DEV)).cpu().numpy()
+        assert np.max(np.abs(Y - Fh @ X[:, :R])) <= 1e-12 * np.max(np.abs(Fh @ X[:, :R]))
+    K = G.convert("f32", max_rhs=8)
+    X32 = torch.from_numpy(X[:, :8].copy()).to(DEV, torch.float32)
+    assert torch.equal(K.matvec(X32), H.matvec(X32))

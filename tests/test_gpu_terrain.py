@@ -4,7 +4,7 @@ columns, the regime of the 131k-facet terrain (Algorithm 5 with R = 256).
 
 Checks, at N = 8192 facets:
 * the FP32 matrix-core product and the BF16 wide products (the one-tile
-  kernel for leaves of 64 facets, the tile-pair kernel for leaves of 256)
+  kernel for leaves of 64 facets, the tile-pair kernel for leaves of 512)
   against the exported blocks of F-hat densified in FP64: arithmetic parity of
   the kernels on every row and column (FP32: 1e-5 relative per column; BF16:
   2u = 2^-7 per column);
@@ -52,14 +52,14 @@ def _colwise(Y, Yx):
     return np.max(np.linalg.norm(Y - Yx, axis=0) / np.linalg.norm(Yx, axis=0))
 
 
-@pytest.mark.parametrize("leaf", [256, 64])
+@pytest.mark.parametrize("leaf", [512, 64])
 def test_long_reduction_products(terrain, tmp_path, leaf):
     verts, faces, fac, rows, Fr = terrain
     H, Fh = _build(verts, faces, leaf, tmp_path)
     st = H.stats()
     print(f"stats: dense {st['n_dense']} lowrank {st['n_lowrank']} zero {st['n_zero']} "
           f"widest panel {st['max_panel_cols']}")
-    assert st["n_dense"] > 0 and st["max_panel_cols"] >= (4096 if leaf == 256 else 1024)
+    assert st["n_dense"] > 0 and st["max_panel_cols"] >= (4096 if leaf == 512 else 1024)
     X = np.random.default_rng(leaf).random((fac.N, 256))
     Xd = torch.from_numpy(X).to(DEV, torch.float32)
     Yx = Fh @ X
