@@ -535,9 +535,101 @@ def run_warm(args):
     print(json.dumps(result), flush=True)
 
 
+def run_ts(args):
+    """Time stepping (Algorithm 6) on the 40k-facet cap: 64 scenarios (a sun
+    at its own elevation U[5, 30] deg circling once per synodic month), one
+    lunation of 0.3-day steps, 20-layer columns of lunar regolith to 1 m
+    under every facet, balanced surface with three Newton repeats.  A step of
+    the benchmark is the whole lunation for all scenarios; value in
+    scenario time steps per second."""
+    import torch
+    from paper_2209_07632_amd import HMatrix
+    from paper_2209_07632_amd.timestep import TimeStepper
+    from synth import CAP_LARGE, cap_mesh
+
+    S, albedo, emiss, R, M = 1365.0, 0.12, 0.95, 64, 20
+    dt = 0.3 * 86400.0
+    n_steps = int(round(29.53 / 0.3))
+    k_cond, rhoc = 0.0015, 1.2e6
+    w = 1.12 ** np.arange(M)                        # layer thickness grows 12% per layer
+    z = np.concatenate([[0.0], np.cumsum(1.0 * w / w.sum())])
+    verts, faces = cap_mesh(CAP_LARGE)
+    N = faces.shape[0]
+    H = HMatrix(verts, faces, tol=args.tol, storage=args.dtype, nearfield=args.nearfield, max_rhs=2 * R)
+    st = H.stats()
+    rng = np.random.default_rng(11)
+    el = np.deg2rad(rng.uniform(5.0, 30.0, R))
+    az0 = rng.uniform(0.0, 2.0 * np.pi, R)
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    Q = torch.empty((n_steps + 1, R, N), dtype=dtype, device="cuda:0")
+    t0 = time.perf_counter()
+    for lvl in range(n_steps + 1):
+        az = az0 + 2.0 * np.pi * lvl / n_steps
+        suns = np.column_stack([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)])
+        H.insolation(suns, flux=S, out=Q[lvl].t())
+    torch.cuda.synchronize()
+    log(f"cap N={N}: insolation of {n_steps + 1} levels x {R} scenarios in {time.perf_counter() - t0:.1f} s")
+    TS = TimeStepper(H, z, k_cond, rhoc, dt, albedo, emiss, bottom_flux=0.0, R=R, surface="balanced", newton=3)
+    T0 = torch.full((M + 1, R, N), 250.0, dtype=torch.float64, device="cuda:0")
+
+    def lunation():
+        TS.init(T0, Q[0])
+        TS.step(Q[1:])
+
+    for _ in range(args.warmup):
+        lunation()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lunation()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    Ts = TS.read("T")[0]
+    tmin, tmax = float(Ts.min()), float(Ts.max())
+    # the two parts of a time step on their own: the 2R-column product and the column kernel
+    X = torch.rand((N, 2 * R), dtype=dtype, device="cuda:0")
+    Y = torch.empty_like(X)
+    for _ in range(3):
+        H.matvec(X, out=Y)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(10):
+        H.matvec(X, out=Y)
+    ev1.record(stream)
+    ev1.synchronize()
+    mv_ms = ev0.elapsed_time(ev1) / 10
+    col_ms = TS.time_column(20)
+    s = 8 if args.dtype == "f64" else 4
+    # per column and step: the M + 1 node temperatures read and written (FP64),
+    # Q_abs and Q_rad read and written (FP64), the two product values, Q_dir
+    # and the next operand's two values in the matrix precision
+    col_bytes = float(N * R * (16 * (M + 1) + 32 + 5 * s))
+    roof = roofline(float(N * R * (12 * M + 40)), col_bytes, col_ms, PEAK_TFLOPS["f64"],
+                    f"k_ts_column<{'double' if s == 8 else 'float'}> (balanced surface, M = {M})")
+    roof["bound"] = "hbm"
+    roof["achieved"], roof["peak"], roof["unit"] = roof["gbs"], HBM_PEAK_GBS, "GB/s"
+    roof["frac"] = roof["gbs"] / HBM_PEAK_GBS
+    result = {
+        "metric": "scenario time steps/s (Algorithm 6 with Crank-Nicolson columns)",
+        "value": R * n_steps / wall, "unit": "scenario-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": f"{args.dtype}+f64", "data": "synthetic",
+        "config": {"workload": f"spherical-cap crater N={N}: {R} scenarios x {n_steps} steps of 0.3 day (one "
+                               f"lunation), {M}-layer regolith columns to 1 m, balanced surface, tol {args.tol}",
+                   "N": N, "scenarios": R, "levels": n_steps, "layers": M, "dt_s": dt},
+        "hmat_blocks": block_counts(st), "product_ms_2R_columns": mv_ms, "column_kernel_ms": col_ms,
+        "ms_per_time_step": 1e3 * wall / n_steps, "surface_T_range_K": [tmin, tmax],
+        "roofline": roof,
+    }
+    log(f"lunation {1e3 * wall:.1f} ms ({1e3 * wall / n_steps:.3f} ms per step: product {mv_ms:.3f} ms, "
+        f"column kernel {col_ms:.3f} ms = {roof['gbs']:.0f} GB/s); surface T in [{tmin:.1f}, {tmax:.1f}] K")
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="cap40k", choices=["cap40k", "dem131k", "batch64", "warm40k"])
+    ap.add_argument("--workload", default="cap40k", choices=["cap40k", "dem131k", "batch64", "warm40k", "ts40k"])
     ap.add_argument("--mlp", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--instances", type=int, default=64)
@@ -564,6 +656,8 @@ def main():
         sys.exit(2)
     if args.workload == "warm40k":
         return run_warm(args)
+    if args.workload == "ts40k":
+        return run_ts(args)
     if args.workload == "batch64":
         if args.nearfield == "csr":
             args.nearfield = "dense"   # terrain near field: dense panels run far faster than CSR slices

@@ -123,6 +123,16 @@ rad_status rad_ts_step(rad_ts *S, int64_t n_steps, const void *Qdir, int64_t ldq
  */
 rad_status rad_ts_read(const rad_ts *S, int32_t field, double *out, int64_t ld, int32_t order, void *hip_stream);
 
+/*
+ * Diagnostic timing of the column kernel alone: nrep launches on the current
+ * state (each advances every column from the current level into the spare
+ * buffer, with the last product and operand standing in for the next level's
+ * fluxes; the state's Q_abs and Q_rad are overwritten, so call rad_ts_init
+ * again before using the stepper), timed with HIP events on hip_stream.
+ * ms receives the average milliseconds per launch.
+ */
+rad_status rad_ts_time_column(rad_ts *S, int32_t nrep, void *hip_stream, double *ms);
+
 /* Current level n (0 after rad_ts_init, -1 before); -1 for a null stepper. */
 int64_t rad_ts_level(const rad_ts *S);
 

@@ -49,6 +49,9 @@ void alloc_workspace(rad_hmat *H) {
     for (auto &e : H->ev) RAD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     RAD_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
     if (H->n_tiles > 0) mm_prepare_schedule(H);
+    // partial row sums of the segmented single-RHS product (R < 16)
+    if (H->n_gsegs > 0)
+        H->w_gpart.alloc((size_t)H->n_gsegs * 64 * (size_t)std::min<int64_t>(H->max_rhs, kMfmaMinRhs - 1) * s);
     // partial tiles of the split reductions of the wide 16-bit expansion
     if (H->n_wsegs > 0 && H->max_rhs >= kMfmaMinRhs) H->w_wpart.alloc((size_t)H->n_wsegs * 128 * 256);
 }

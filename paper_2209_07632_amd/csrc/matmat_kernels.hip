@@ -1037,6 +1037,35 @@ void mm_prepare_schedule(rad_hmat *H) {
     }
     H->n_p1pairs = (int32_t)(pairs.size() / 2);
     H->d_p1pairs.upload(pairs);
+    // segments of the single-RHS tile product: panels longer than kGSeg
+    // columns (1 MB of values) are cut into near-equal runs of whole 16-column
+    // chunks, so one long tile no longer holds the product back
+    {
+        const int32_t vw = H->dtype == RAD_F64 ? 2 : 4;            // values per 16-byte load
+        const int32_t kGSeg = H->dtype == RAD_F64 ? 2048 : 4096;
+        int32_t kmax = 0;
+        for (int32_t i = 0; i < n; ++i) kmax = std::max(kmax, ti[i].k16);
+        H->n_gsegs = 0;
+        if (kmax > kGSeg) {
+            std::vector<GemvSeg> segs;
+            std::vector<int32_t> tseg(1, 0);
+            for (int32_t i = 0; i < n; ++i) {
+                const int32_t chunks = ti[i].k16 / 16;
+                const int32_t nseg = std::max(1, (ti[i].k16 + kGSeg - 1) / kGSeg);
+                for (int32_t sg = 0; sg < nseg; ++sg) {
+                    const int64_t c0 = (int64_t)chunks * sg / nseg, c1 = (int64_t)chunks * (sg + 1) / nseg;
+                    segs.push_back(GemvSeg{i, (int32_t)(16 * c0 / vw), (int32_t)(16 * c1 / vw), sg == 0 ? 1 : 0,
+                                           (int32_t)segs.size()});
+                }
+                tseg.push_back((int32_t)segs.size());
+            }
+            std::stable_sort(segs.begin(), segs.end(),
+                             [](const GemvSeg &a, const GemvSeg &b) { return a.g1 - a.g0 > b.g1 - b.g0; });
+            H->n_gsegs = (int32_t)segs.size();
+            H->d_gsegs.upload(segs);
+            H->d_gseg_of_tile.upload(tseg);
+        }
+    }
     // tile pairs of the wide BF16 expansion: consecutive tiles (the halves of
     // a 128-facet leaf) whose panels multiply the same operand rows
     H->n_wpairs = H->n_wsingles = 0;

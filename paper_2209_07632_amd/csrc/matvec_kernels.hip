@@ -70,18 +70,54 @@ __global__ void __launch_bounds__(256) k_proj(const ProjGroup *groups, const T *
 // sum of (B_new - B_old)^2 (FP64, rows in order).  kMode 2: also
 // epartial[tile R + r] = the tile's sum of E^2.  With stop given, the kernel
 // returns at once while *stop is set.
+// The end of a single-RHS product for one 64-row tile and right-hand side r,
+// run by one wave (lane = row): y (this row's value of F-hat X, valid for
+// row < N) is stored, or turned into the Jacobi update with its partial sums
+// (kMode as k_tile_gemv).
+template <class T, int kMode>
+__device__ __forceinline__ void gemv_epilogue(int tile, int64_t r, int lane, T y, int64_t N, const T *x, T *Y,
+                                              int64_t ldy, const T *E, const T *rho, T rho_s, double *partial,
+                                              double *epartial, int R) {
+    const int64_t row = (int64_t)tile * 64 + lane;
+    double d2 = 0.0, e2 = 0.0;
+    if (row < N) {
+        if (kMode == 0) {
+            Y[row + r * ldy] = y;
+        } else {
+            const T e = E[row + r * ldy];
+            const T b = e + (rho ? rho[row] : rho_s) * y;
+            const double d = (double)b - (double)x[row];
+            d2 = d * d;
+            e2 = (double)e * (double)e;
+            Y[row + r * ldy] = b;
+        }
+    }
+    if (kMode != 0) {
+        d2 = wsum(d2);
+        if (kMode == 2) e2 = wsum(e2);
+        if (lane == 0) {
+            partial[(int64_t)tile * R + r] = d2;
+            if (kMode == 2) epartial[(int64_t)tile * R + r] = e2;
+        }
+    }
+}
+
+// With segs given, blockIdx.x is a segment of a tile's panel (column groups
+// [g0, g1), the tile's CSR tasks when csr is set): its 64 row sums go to
+// spart[(slot R + r) 64 + row] and k_gemv_finish completes the tile.
 template <class T, int kMode>
 __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
                                                     const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
                                                     int64_t csr_val_start, const T *X, int64_t ldx, const T *Tb,
                                                     int32_t t_ld, int64_t N, T *Y, int64_t ldy, const T *E,
                                                     const T *rho, T rho_s, double *partial, double *epartial,
-                                                    const int32_t *stop) {
+                                                    const int32_t *stop, const GemvSeg *segs, T *spart) {
     if (stop && *stop) return;
     constexpr int VW = 16 / sizeof(T);      // values per 16-byte load
     constexpr int LPC = 64 / VW;            // lanes per panel column
     typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type vec_t;
-    const int tile = blockIdx.x;
+    const GemvSeg sg = segs ? segs[blockIdx.x] : GemvSeg{(int32_t)blockIdx.x, 0, -1, 1, 0};
+    const int tile = sg.tile;
     const TileInfo ti = tiles[tile];
     const int64_t r = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -103,8 +139,10 @@ __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const 
         for (int u = 0; u < VW; ++u) acc[u] += av[u] * xv;
     };
     auto value = [&](int32_t b) -> T { return b >= 0 ? x[b] : tb[-1 - b]; };
-    const int ngroups = ti.k16 / VW;        // columns that hold values (a multiple of 16)
-    int g = w;
+    // column groups [g, ngroups) of this workgroup (all columns that hold
+    // values, a multiple of 16, or a segment of them)
+    const int ngroups = sg.g1 < 0 ? ti.k16 / VW : sg.g1;
+    int g = sg.g0 + w;
     // the operand-row indices of an iteration are loaded one iteration ahead
     // of the gathers that use them
     int32_t bi[4] = {0, 0, 0, 0};
@@ -136,7 +174,7 @@ __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const 
     for (int u = 0; u < VW; ++u) red[w][sub][r0 + u] = acc[u];
     // CSR tasks: lane = row, wave w takes tasks w, w+4, ...
     T cacc = 0;
-    for (int c = ti.csr_begin + w; c < ti.csr_end; c += 4) {
+    for (int c = ti.csr_begin + w; sg.csr && c < ti.csr_end; c += 4) {
         const TileTask tk = ctasks[c];
         if (lane >= tk.r_lo && lane < tk.r_hi) {
             const int32_t *ptr = csr_ptr + tk.aux_off + tk.row_off + lane;
@@ -149,35 +187,35 @@ __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const 
     __shared__ T cred[4][64];
     cred[w][lane] = cacc;
     __syncthreads();
-    const int64_t row = (int64_t)tile * 64 + lane;
     if (w != 0) return;
-    double d2 = 0.0, e2 = 0.0;
-    if (row < N) {
-        T s = 0;
+    T s = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int u = 0; u < VW; ++u) s += red[q][u][lane];
-        const T y = s + ((cred[0][lane] + cred[1][lane]) + (cred[2][lane] + cred[3][lane]));
-        if (kMode == 0) {
-            Y[row + r * ldy] = y;
-        } else {
-            const T e = E[row + r * ldy];
-            const T b = e + (rho ? rho[row] : rho_s) * y;
-            const double d = (double)b - (double)x[row];
-            d2 = d * d;
-            e2 = (double)e * (double)e;
-            Y[row + r * ldy] = b;
-        }
+        for (int u = 0; u < VW; ++u) s += red[q][u][lane];
+    const T y = s + ((cred[0][lane] + cred[1][lane]) + (cred[2][lane] + cred[3][lane]));
+    if (segs) {
+        spart[((int64_t)sg.slot * gridDim.y + r) * 64 + lane] = y;
+        return;
     }
-    if (kMode != 0) {
-        d2 = wsum(d2);
-        if (kMode == 2) e2 = wsum(e2);
-        if (lane == 0) {
-            partial[(int64_t)tile * gridDim.y + r] = d2;
-            if (kMode == 2) epartial[(int64_t)tile * gridDim.y + r] = e2;
-        }
-    }
+    gemv_epilogue<T, kMode>(tile, r, lane, y, N, x, Y, ldy, E, rho, rho_s, partial, epartial, (int)gridDim.y);
+}
+
+// The tiles of a segmented single-RHS product: one wave per (tile, right-hand
+// side) sums the tile's segments (slots [tseg[tile], tseg[tile + 1]), in
+// order) and runs the epilogue of k_tile_gemv.
+template <class T, int kMode>
+__global__ void __launch_bounds__(64) k_gemv_finish(const int32_t *tseg, const T *spart, int64_t N, const T *X,
+                                                     int64_t ldx, T *Y, int64_t ldy, const T *E, const T *rho, T rho_s,
+                                                     double *partial, double *epartial, const int32_t *stop) {
+    if (stop && *stop) return;
+    const int tile = blockIdx.x;
+    const int64_t r = blockIdx.y;
+    const int lane = threadIdx.x;
+    const int R = (int)gridDim.y;
+    T y = 0;
+    for (int sl = tseg[tile]; sl < tseg[tile + 1]; ++sl) y += spart[((int64_t)sl * R + r) * 64 + lane];
+    gemv_epilogue<T, kMode>(tile, r, lane, y, N, X + r * ldx, Y, ldy, E, rho, rho_s, partial, epartial, R);
 }
 
 template <class T>
@@ -210,7 +248,7 @@ __global__ void k_reduce_cols(const double *partial, int nparts, int64_t R, doub
 template <class T>
 void apply_t(const rad_hmat *H, const T *X, int64_t ldx, T *Y, int64_t ldy, int64_t R, T *Tb, hipStream_t s,
              const T *E = nullptr, const T *rho = nullptr, T rho_s = 0, double *partial = nullptr,
-             double *epartial = nullptr, const int32_t *stop = nullptr) {
+             double *epartial = nullptr, const int32_t *stop = nullptr, bool segmented = true) {
     if (H->n_groups > 0) {
         int maxk = 0;
         for (const ProjGroup &g : H->h_groups) maxk = std::max(maxk, g.ktot);
@@ -219,22 +257,31 @@ void apply_t(const rad_hmat *H, const T *X, int64_t ldx, T *Y, int64_t ldy, int6
                            H->t_ld, stop);
         RAD_HIP(hipGetLastError());
     }
-    dim3 grid2(H->n_tiles, (unsigned)R);
+    // long panels (terrain near field) are cut into segments that run as
+    // separate workgroups, longest first, and are summed per tile in order;
+    // otherwise one workgroup per tile (also the allocation-free product,
+    // which passes its own T buffer and uses no segment workspace)
+    const bool seg = segmented && H->n_gsegs > 0 && (int64_t)H->w_gpart.n >= (int64_t)H->n_gsegs * 64 * R * sizeof(T);
+    T *spart = seg ? (T *)H->w_gpart.p : nullptr;
+    const GemvSeg *segs = seg ? H->d_gsegs.p : nullptr;
+    dim3 grid2(seg ? H->n_gsegs : H->n_tiles, (unsigned)R);
+    auto tile_kernel = [&](auto mode) {
+        constexpr int M = decltype(mode)::value;
+        hipLaunchKernelGGL((k_tile_gemv<T, M>), grid2, dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
+                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
+                           H->csr_val_start, X, ldx, (const T *)Tb, H->t_ld, H->N, Y, ldy, E, rho, rho_s, partial,
+                           epartial, stop, segs, spart);
+        if (seg)
+            hipLaunchKernelGGL((k_gemv_finish<T, M>), dim3(H->n_tiles, (unsigned)R), dim3(64), 0, s,
+                               H->d_gseg_of_tile.p, (const T *)spart, H->N, X, ldx, Y, ldy, E, rho, rho_s, partial,
+                               epartial, stop);
+    };
     if (!E)
-        hipLaunchKernelGGL((k_tile_gemv<T, 0>), grid2, dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
-                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
-                           H->csr_val_start, X, ldx, (const T *)Tb, H->t_ld, H->N, Y, ldy, E, rho, rho_s, partial,
-                           epartial, stop);
+        tile_kernel(std::integral_constant<int, 0>{});
     else if (!epartial)
-        hipLaunchKernelGGL((k_tile_gemv<T, 1>), grid2, dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
-                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
-                           H->csr_val_start, X, ldx, (const T *)Tb, H->t_ld, H->N, Y, ldy, E, rho, rho_s, partial,
-                           epartial, stop);
+        tile_kernel(std::integral_constant<int, 1>{});
     else
-        hipLaunchKernelGGL((k_tile_gemv<T, 2>), grid2, dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
-                           H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
-                           H->csr_val_start, X, ldx, (const T *)Tb, H->t_ld, H->N, Y, ldy, E, rho, rho_s, partial,
-                           epartial, stop);
+        tile_kernel(std::integral_constant<int, 2>{});
     RAD_HIP(hipGetLastError());
 }
 
@@ -267,15 +314,21 @@ void mv_scatter(const rad_hmat *H, const void *src, int64_t lds, void *dst, int6
 }
 
 void mv_apply(const rad_hmat *H, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R, hipStream_t s) {
-    mv_apply_ws(H, X, ldx, Y, ldy, R, H->w_t.p, s);
+    if (H->dtype == RAD_F64)
+        apply_t<double>(H, (const double *)X, ldx, (double *)Y, ldy, R, (double *)H->w_t.p, s);
+    else
+        apply_t<float>(H, (const float *)X, ldx, (float *)Y, ldy, R, (float *)H->w_t.p, s);
 }
 
 void mv_apply_ws(const rad_hmat *H, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R, void *Tb,
                  hipStream_t s) {
+    // (one workgroup per tile: no workspace of the matrix is used)
     if (H->dtype == RAD_F64)
-        apply_t<double>(H, (const double *)X, ldx, (double *)Y, ldy, R, (double *)Tb, s);
+        apply_t<double>(H, (const double *)X, ldx, (double *)Y, ldy, R, (double *)Tb, s, nullptr, nullptr, 0.0,
+                        nullptr, nullptr, nullptr, false);
     else
-        apply_t<float>(H, (const float *)X, ldx, (float *)Y, ldy, R, (float *)Tb, s);
+        apply_t<float>(H, (const float *)X, ldx, (float *)Y, ldy, R, (float *)Tb, s, nullptr, nullptr, 0.0f,
+                       nullptr, nullptr, nullptr, false);
 }
 
 // ----------------------------------------------------------------------------

@@ -191,6 +191,13 @@ struct TileTask {
     int32_t full;          // 1: every row in [r_lo, r_hi) holds all ncol columns (values row-major, ld ncol)
 };
 
+// Segment of a single-RHS tile product: column groups [g0, g1) of the panel
+// of tile `tile` (groups of 16 / sizeof(T) columns; g1 = -1: all), the
+// tile's CSR tasks when csr is set, partial row sums to slot `slot`.
+struct GemvSeg {
+    int32_t tile, g0, g1, csr, slot;
+};
+
 // Segment of the wide 16-bit tile-pair expansion: kp panel columns of the two
 // tiles of a pair, whose 16-bit panels start at element offsets pa and pb
 // of the value pool and whose operand-row list starts at br; its partial
@@ -339,6 +346,12 @@ struct rad_hmat {
     // operand-row lists (one 128-row workgroup each), and the remaining tiles
     rad::DevBuf<int32_t> d_wpairs, d_wsingles;
     int32_t n_wpairs = 0, n_wsingles = 0;
+    // single-RHS products: panel segments (longest first), each tile's slots
+    // [gseg_of_tile[t], gseg_of_tile[t+1]), and the segments' partial row sums
+    rad::DevBuf<rad::GemvSeg> d_gsegs;
+    rad::DevBuf<int32_t> d_gseg_of_tile;
+    int32_t n_gsegs = 0;
+    rad::DevBuf<unsigned char> w_gpart;
     rad::DevBuf<rad::WideSeg> d_wsegs;    // the pairs' reduction segments, longest first
     int32_t n_wsegs = 0;
     rad::DevBuf<int32_t> d_wslot;         // pair p's segments' partial tiles: slots [wslot[p], wslot[p+1])

@@ -41,6 +41,8 @@ def _lib():
         L.rad_ts_read.argtypes = [vp, i32, vp, i64, i32, vp]
         for name in ("rad_ts_create", "rad_ts_init", "rad_ts_step", "rad_ts_read"):
             getattr(L, name).restype = ctypes.c_int
+        L.rad_ts_time_column.argtypes = [vp, i32, vp, ctypes.POINTER(dbl)]
+        L.rad_ts_time_column.restype = ctypes.c_int
         L.rad_ts_level.argtypes = [vp]
         L.rad_ts_level.restype = i64
         L.rad_ts_free.argtypes = [vp]
@@ -94,6 +96,13 @@ class TimeStepper:
         _check(_lib().rad_ts_read(self._h, _FIELDS[field], ctypes.c_void_p(out.data_ptr()), self.N, 0,
                                   _stream_handle()))
         return out
+
+    def time_column(self, nrep=20):
+        """Average ms per launch of the column kernel alone (diagnostic; the
+        state is overwritten: call init again afterwards)."""
+        ms = ctypes.c_double()
+        _check(_lib().rad_ts_time_column(self._h, int(nrep), _stream_handle(), ctypes.byref(ms)))
+        return ms.value
 
     @property
     def level(self):

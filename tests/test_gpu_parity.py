@@ -415,9 +415,10 @@ def test_refined_solve_ir_band_rho_vector(cap, lowp):
 # ------------------------------------------------------------ the benchmark's own configuration
 def test_full_size_cap_sampled_columns():
     """The 40k-facet cap with 1,024 suns, near field CSR, tol 1e-3, FP32, solved
-    in the autotuned launch configuration the benchmark times: two sampled
-    columns against the FP64 matrix-free reference (insolation and Jacobi),
-    and shadows bit for bit on those columns."""
+    in the autotuned launch configuration the benchmark times: 16 columns
+    spread over the sun elevations (the lowest and highest included) against
+    the FP64 matrix-free reference (insolation and Jacobi), and shadows bit for
+    bit on those columns."""
     from paper_2209_07632_amd import HMatrix
     from paper_2209_07632_amd.rad import ldr_of
     from synth import CAP_LARGE
@@ -431,7 +432,9 @@ def test_full_size_cap_sampled_columns():
     B, info = H.solve(0.3 * Q, rho=0.3, rtol=1e-3, order="tree_rmajor", R=R)
     assert info["converged"]
     perm = H.perm()
-    cols = [0, 777]
+    order = np.argsort(np.arcsin(suns[:, 2]), kind="stable")
+    cols = sorted(set(order[np.round(np.linspace(0, R - 1, 16)).astype(int)].tolist()))
+    assert len(cols) == 16
     fac = ref.Facets(verts, faces)
     Q0 = ref.insolation(fac, suns[cols], S=1365.0)
     Qg = np.empty((fac.N, len(cols)))
@@ -442,3 +445,33 @@ def test_full_size_cap_sampled_columns():
     Bg[perm] = B.double().cpu().numpy()[:, cols]
     for c in range(len(cols)):
         assert _rel(Bg[:, c], B0[:, c]) < 1e-3
+
+
+# ------------------------------------------------------------ zero blocks only
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_flat_plane_is_all_zero_blocks(storage):
+    """P9: on a flat plane every n_i . (x_j - x_i) is zero, so F = 0: every
+    block is a zero block, the product is exactly zero and the solve returns
+    B = E after one iteration, on both kernel paths."""
+    from paper_2209_07632_amd import HMatrix
+    g = np.linspace(0.0, 200.0, 21)
+    xx, yy = np.meshgrid(g, g, indexing="ij")
+    verts = np.column_stack([xx.ravel(), yy.ravel(), np.zeros(xx.size)])
+    faces = []
+    for i in range(20):
+        for j in range(20):
+            a, b, c, d = i * 21 + j, (i + 1) * 21 + j, (i + 1) * 21 + j + 1, i * 21 + j + 1
+            faces += [[a, b, c], [a, c, d]]
+    faces = np.array(faces, dtype=np.int32)
+    fac = ref.Facets(verts, faces)
+    assert not ref.view_factor_matrix(fac).any()
+    H = _hm(verts, faces, tol=1e-3, storage=storage, visibility="raycast", max_rhs=20)
+    st = H.stats()
+    assert st["n_zero"] > 0 and st["n_dense"] == st["n_csr"] == st["n_lowrank"] == 0
+    dt = torch.float64 if storage == "f64" else torch.float32
+    for R in (1, 20):
+        E = torch.rand((fac.N, R), dtype=dt, device=DEV) * 100.0
+        assert not H.matvec(E).any()
+        B, info = H.solve(E, rho=0.9, rtol=1e-12)
+        assert torch.equal(B.reshape(E.shape), E)
+        assert info["total_iters"] == 1 and np.all(info["iters"] == 1)
