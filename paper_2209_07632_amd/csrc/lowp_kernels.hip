@@ -276,17 +276,28 @@ __global__ void __launch_bounds__(256) k_to_bf16(const float *X, int64_t N, int6
 // 8-byte groups of four consecutive k, the operand layout of the matrix
 // cores.  No CSR tasks (matrices with CSR near field use k_tile_mm16).
 // ---------------------------------------------------------------------------
-constexpr int WN = 256, WKC = 32, WLDK = WKC + 8;
+constexpr int WN = 256, WKC = 32, WLDK = WKC;
+
+// LDS layout of the wide kernels' chunks: rows of 32 k (64 bytes, no
+// padding); the 16-byte group c of row r sits at group c ^ wsw(r), and the
+// operand row of output column R sits at row wpos(R) = R ^ ((R >> 3) & 3).
+// The transposing 8-byte writes of a wave (eight lanes fill one row) then
+// reach distinct banks, and so do the 16-byte reads of the matrix-core
+// operands (sixteen consecutive rows, one group each).
+__device__ __forceinline__ int wsw(int r) { return (((r >> 1) ^ (r >> 3)) & 1) | ((r >> 1) & 2); }
+__device__ __forceinline__ int wpos(int R) { return R ^ ((R >> 3) & 3); }
+// bf16 offset of (row r, 16-byte group c, 8-byte half q) in a row-swizzled chunk
+__device__ __forceinline__ int wofs(int r, int c, int q) { return r * WLDK + 8 * (c ^ wsw(r)) + 4 * q; }
 
 struct WideStage {
     bf16x8 a;          // panel: row t >> 2, k (t & 3) * 8 .. + 7
-    bf16x8 b[4];       // operand rows 4 (t >> 5) + i, columns 8 (t & 31) .. + 7
+    bf16x8 b[4];       // operand rows 4 (t & 7) + i, columns 8 (t >> 3) .. + 7
     // the operand-row indices of this thread's four rows of a chunk (loaded a
     // chunk ahead of their use, so that the dependent row loads do not wait)
     struct Rows {
         int32_t v[4];
         __device__ __forceinline__ void load(const int32_t *brc, int t) {
-            const int kq = t >> 5;
+            const int kq = t & 7;
 #pragma unroll
             for (int i = 0; i < 4; ++i) v[i] = brc[4 * kq + i];
         }
@@ -294,7 +305,7 @@ struct WideStage {
     __device__ __forceinline__ void fetch(const __bf16 *pan, const Rows &rw, const __bf16 *X16, const __bf16 *T16,
                                           int64_t ld16, int t) {
         a = *(const bf16x8 *)(pan + t * 8);
-        const int c8 = (t & 31) * 8;
+        const int c8 = (t >> 3) * 8;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int32_t v = rw.v[i];
@@ -303,13 +314,16 @@ struct WideStage {
         }
     }
     __device__ __forceinline__ void commit(__bf16 (*sA)[WLDK], __bf16 (*sB)[WLDK], int t) {
-        *(bf16x8 *)&sA[t >> 2][(t & 3) * 8] = a;
-        const int kq = t >> 5, c8 = (t & 31) * 8;
+        *(bf16x8 *)(&sA[0][0] + wofs(t >> 2, t & 3, 0)) = a;
+        commit_b(sB, b, t);
+    }
+    __device__ __forceinline__ static void commit_b(__bf16 (*sB)[WLDK], const bf16x8 *b, int t) {
+        const int kq = t & 7, c8 = (t >> 3) * 8;
         typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             bf16x4 q = {b[0][j], b[1][j], b[2][j], b[3][j]};
-            *(bf16x4 *)&sB[c8 + j][4 * kq] = q;
+            *(bf16x4 *)(&sB[0][0] + wofs(wpos(c8 + j), kq >> 1, kq & 1)) = q;
         }
     }
 };
@@ -336,13 +350,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
-    const int lr = lane & 15, k0 = 8 * (lane >> 4);
+    const int lr = lane & 15, kg = lane >> 4;
     auto mma = [&](const __bf16 (*A)[WLDK], const __bf16 (*B)[WLDK]) {
         bf16x8 av[4], bv[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = *(const bf16x8 *)&A[i * 16 + lr][k0];
+        for (int i = 0; i < 4; ++i) av[i] = *(const bf16x8 *)(&A[0][0] + wofs(i * 16 + lr, kg, 0));
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = *(const bf16x8 *)&B[w * 64 + j * 16 + lr][k0];
+        for (int j = 0; j < 4; ++j) bv[j] = *(const bf16x8 *)(&B[0][0] + wofs(wpos(w * 64 + j * 16 + lr), kg, 0));
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -417,7 +431,7 @@ struct PairStage {
                                           const __bf16 *X16, const __bf16 *T16, int64_t ld16, int t) {
         a0 = *(const bf16x8 *)(pa + t * 8);
         a1 = *(const bf16x8 *)(pb + t * 8);
-        const int c8 = (t & 31) * 8;
+        const int c8 = (t >> 3) * 8;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int32_t v = rw.v[i];
@@ -426,15 +440,9 @@ struct PairStage {
         }
     }
     __device__ __forceinline__ void commit(__bf16 (*sA)[WLDK], __bf16 (*sB)[WLDK], int t) {
-        *(bf16x8 *)&sA[t >> 2][(t & 3) * 8] = a0;
-        *(bf16x8 *)&sA[TM + (t >> 2)][(t & 3) * 8] = a1;
-        const int kq = t >> 5, c8 = (t & 31) * 8;
-        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            bf16x4 q = {b[0][j], b[1][j], b[2][j], b[3][j]};
-            *(bf16x4 *)&sB[c8 + j][4 * kq] = q;
-        }
+        *(bf16x8 *)(&sA[0][0] + wofs(t >> 2, t & 3, 0)) = a0;
+        *(bf16x8 *)(&sA[0][0] + wofs(TM + (t >> 2), t & 3, 0)) = a1;
+        WideStage::commit_b(sB, b, t);
     }
 };
 
@@ -459,17 +467,17 @@ k_tile_mm16s(const WideSeg *segs, const int32_t *brow, const __bf16 *vals16, con
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
-    const int lr = lane & 15, k0 = 8 * (lane >> 4);
+    const int lr = lane & 15, kg = lane >> 4;
     const int wr = (w & 1) * TM, wc = (w >> 1) * 128;
     auto mma = [&](const __bf16 (*A)[WLDK], const __bf16 (*B)[WLDK]) {
         bf16x8 av[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = *(const bf16x8 *)&A[wr + i * 16 + lr][k0];
+        for (int i = 0; i < 4; ++i) av[i] = *(const bf16x8 *)(&A[0][0] + wofs(wr + i * 16 + lr, kg, 0));
 #pragma unroll
         for (int jh = 0; jh < 2; ++jh) {
             bf16x8 bv[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = *(const bf16x8 *)&B[wc + (4 * jh + j) * 16 + lr][k0];
+            for (int j = 0; j < 4; ++j) bv[j] = *(const bf16x8 *)(&B[0][0] + wofs(wpos(wc + (4 * jh + j) * 16 + lr), kg, 0));
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll

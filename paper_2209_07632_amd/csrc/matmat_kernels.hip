@@ -1037,6 +1037,18 @@ void mm_prepare_schedule(rad_hmat *H) {
     }
     H->n_p1pairs = (int32_t)(pairs.size() / 2);
     H->d_p1pairs.upload(pairs);
+    // single-RHS projections of long column nodes: one workgroup per V column
+    {
+        std::vector<int32_t> items;
+        for (int32_t gi = 0; gi < (int32_t)H->h_groups.size(); ++gi)
+            if (H->h_groups[gi].n >= kProjWideN)
+                for (int32_t kk = 0; kk < H->h_groups[gi].ktot; ++kk) {
+                    items.push_back(gi);
+                    items.push_back(kk);
+                }
+        H->n_pwide = (int32_t)(items.size() / 2);
+        H->d_pwide.upload(items);
+    }
     // segments of the single-RHS tile product: panels longer than kGSeg
     // columns (1 MB of values) are cut into near-equal runs of whole 16-column
     // chunks, so one long tile no longer holds the product back

@@ -42,11 +42,13 @@ __global__ void k_scatter(const int32_t *perm, const T *src, int64_t lds, T *dst
 }
 
 // phase 1: one wave per stacked V column, lanes stride the rows of X_J
+// (groups with n >= wide_n are left to k_proj_wide)
 template <class T>
 __global__ void __launch_bounds__(256) k_proj(const ProjGroup *groups, const T *vals, const T *X, int64_t ldx,
-                                               T *Tb, int32_t t_ld, const int32_t *stop) {
+                                               T *Tb, int32_t t_ld, const int32_t *stop, int32_t wide_n) {
     if (stop && *stop) return;
     const ProjGroup g = groups[blockIdx.x];
+    if (g.n >= wide_n) return;
     const int64_t r = blockIdx.z;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const T *x = X + g.j0 + r * ldx;
@@ -70,6 +72,45 @@ __global__ void __launch_bounds__(256) k_proj(const ProjGroup *groups, const T *
 // sum of (B_new - B_old)^2 (FP64, rows in order).  kMode 2: also
 // epartial[tile R + r] = the tile's sum of E^2.  With stop given, the kernel
 // returns at once while *stop is set.
+// phase 1 for column nodes of many facets: one workgroup per stacked V
+// column (item = (group, column)); its 256 threads stride the facets with
+// 16-byte loads of V, four loads in flight, and meet in LDS in a fixed order.
+template <class T>
+__global__ void __launch_bounds__(256) k_proj_wide(const int32_t *items, const ProjGroup *groups, const T *vals,
+                                                    const T *X, int64_t ldx, T *Tb, int32_t t_ld,
+                                                    const int32_t *stop) {
+    if (stop && *stop) return;
+    constexpr int VW = 16 / sizeof(T);
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type vec_t;
+    const ProjGroup g = groups[items[2 * blockIdx.x]];
+    const int kk = items[2 * blockIdx.x + 1];
+    const int64_t r = blockIdx.z;
+    const T *x = X + g.j0 + r * ldx;
+    const T *v = vals + g.v_off + (int64_t)kk * g.ld;   // 16-byte aligned (v_off, ld multiples of 8)
+    const int t = threadIdx.x;
+    T acc = 0;
+    constexpr int STEP = 256 * VW;
+    int j = VW * t;
+    for (; j + 3 * STEP + VW <= g.n; j += 4 * STEP) {
+        vec_t a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = *(const vec_t *)(v + j + q * STEP);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T *av = (const T *)&a[q];
+#pragma unroll
+            for (int u = 0; u < VW; ++u) acc += av[u] * x[j + q * STEP + u];
+        }
+    }
+    for (; j < g.n; j += STEP)
+        for (int u = 0; u < VW && j + u < g.n; ++u) acc += v[j + u] * x[j + u];
+    acc = wsum(acc);
+    __shared__ T red[4];
+    if ((t & 63) == 0) red[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) Tb[g.t_off + kk + r * t_ld] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // The end of a single-RHS product for one 64-row tile and right-hand side r,
 // run by one wave (lane = row): y (this row's value of F-hat X, valid for
 // row < N) is stored, or turned into the Jacobi update with its partial sums
@@ -254,7 +295,10 @@ void apply_t(const rad_hmat *H, const T *X, int64_t ldx, T *Y, int64_t ldy, int6
         for (const ProjGroup &g : H->h_groups) maxk = std::max(maxk, g.ktot);
         dim3 grid(H->n_groups, std::max(1, std::min(64, (maxk + 3) / 4)), (unsigned)R);
         hipLaunchKernelGGL(k_proj<T>, grid, dim3(256), 0, s, H->d_groups.p, (const T *)H->d_vals.p, X, ldx, Tb,
-                           H->t_ld, stop);
+                           H->t_ld, stop, H->n_pwide > 0 ? kProjWideN : INT32_MAX);
+        if (H->n_pwide > 0)
+            hipLaunchKernelGGL(k_proj_wide<T>, dim3(H->n_pwide, 1, (unsigned)R), dim3(256), 0, s, H->d_pwide.p,
+                               H->d_groups.p, (const T *)H->d_vals.p, X, ldx, Tb, H->t_ld, stop);
         RAD_HIP(hipGetLastError());
     }
     // long panels (terrain near field) are cut into segments that run as

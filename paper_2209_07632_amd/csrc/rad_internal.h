@@ -348,6 +348,8 @@ struct rad_hmat {
     int32_t n_wpairs = 0, n_wsingles = 0;
     // single-RHS products: panel segments (longest first), each tile's slots
     // [gseg_of_tile[t], gseg_of_tile[t+1]), and the segments' partial row sums
+    rad::DevBuf<int32_t> d_pwide;        // (group, column) items of k_proj_wide (groups of n >= kProjWideN)
+    int32_t n_pwide = 0;
     rad::DevBuf<rad::GemvSeg> d_gsegs;
     rad::DevBuf<int32_t> d_gseg_of_tile;
     int32_t n_gsegs = 0;
@@ -478,6 +480,8 @@ void launch_elementwise(const rad_hmat *H, int32_t op, double a, double b, doubl
 
 // multi-RHS path (matmat_kernels.hip), R-major tree-ordered buffers
 constexpr int64_t kMfmaMinRhs = 16;
+// column nodes of at least this many facets project with one workgroup per V column
+constexpr int32_t kProjWideN = 4096;
 int64_t mm_ldr(int64_t R);
 int mm_part_rows();
 void mm_to_rmajor(const rad_hmat *H, const void *src, int64_t lds, bool permute, void *dst, int64_t ldr, int64_t R,

@@ -447,6 +447,31 @@ def test_full_size_cap_sampled_columns():
         assert _rel(Bg[:, c], B0[:, c]) < 1e-3
 
 
+def test_full_size_cap_single_rhs_products():
+    """The single-RHS kernels (R < 16) on the 40k-facet cap at tol 1e-3, FP32,
+    near field CSR: column nodes of up to 10k facets (the long-projection path,
+    one workgroup per V column) and segmented tile reductions.  R = 1 and R = 3
+    against the matrix-core product of the same columns (FP32 rounding order
+    only: 1e-5 per column) and R = 1 against the FP64 matrix-free oracle
+    product (within tol + 1e-6)."""
+    from paper_2209_07632_amd import HMatrix
+    from synth import CAP_LARGE
+    verts, faces = cap_mesh(CAP_LARGE)
+    print("[full] cap40k single-RHS products", flush=True)
+    H = HMatrix(verts, faces, tol=1e-3, storage="f32", nearfield="csr", max_rhs=16)
+    X = np.random.default_rng(44).random((H.N, 16))
+    Xd = torch.from_numpy(X).to(DEV, torch.float32)
+    Ymm = H.matvec(Xd).double().cpu().numpy()
+    Y1 = H.matvec(Xd[:, 0].contiguous()).double().cpu().numpy()
+    Y3 = H.matvec(Xd[:, 1:4].contiguous()).double().cpu().numpy()
+    assert _rel(Y1, Ymm[:, 0]) <= 1e-5
+    for c in range(3):
+        assert _rel(Y3[:, c], Ymm[:, 1 + c]) <= 1e-5
+    fac = ref.Facets(verts, faces)
+    Y0 = ref.matvec_free(fac, X[:, :1])[:, 0]
+    assert _rel(Y1, Y0) <= 1e-3 + 1e-6
+
+
 # ------------------------------------------------------------ zero blocks only
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_flat_plane_is_all_zero_blocks(storage):
