@@ -73,14 +73,20 @@ def log(msg):
 
 def measured_traffic(dtype, R, tn):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    runs, or None when the kernel source changed since they were taken."""
+    runs, or None when the kernel's sources (the files holding its device
+    code) changed since they were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, rec["source"])
-    if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != rec["source_sha1"]:
+    h = hashlib.sha1()
+    for rel in rec["sources"]:
+        src = os.path.join(ROOT, rel)
+        if not os.path.exists(src):
+            return None
+        h.update(open(src, "rb").read())
+    if h.hexdigest() != rec["sources_sha1"]:
         return None
     if rec["dtype"] != dtype or rec["rhs"] != R or rec.get("tn") != tn:
         return None

@@ -15,7 +15,7 @@ LIB = os.path.join(PKG, "librad.so")
 
 SOURCES = ["api.cpp", "build.cpp", "build_kernels.hip", "matvec_kernels.hip", "matmat_kernels.hip", "raycast.hip",
            "lowp_kernels.hip", "warmstart.hip", "timestep.hip",
-           "group.cpp", "autotune.cpp", "serialize.cpp", "krylov.hip"]
+           "group.cpp", "autotune.cpp", "serialize.cpp", "krylov.hip", "schedule.cpp"]
 
 # geometry, entries and ray tests are evaluated without contraction so that
 # their zero/non-zero and hit/miss decisions equal plain FP64 arithmetic

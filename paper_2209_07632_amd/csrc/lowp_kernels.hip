@@ -138,17 +138,21 @@ struct Acc16 {
 };
 
 // B chunk: 32 operand rows (FP32, R-major) times 128 columns, each row divided
-// by its scale, converted and stored with the reduction index contiguous
+// by its scale, converted and stored with the reduction index contiguous.
+// Thread t takes rows 4 (t & 7) .. + 3 and columns 4 (t >> 3) .. + 3, and
+// stores each column's four consecutive k as one 8-byte group: eight lanes
+// fill one LDS row, and the row stride of LDK values puts the next eight
+// lanes' row on the other half of the banks (no bank conflicts).
 template <class H>
 struct StageB16 {
-    float v[16];
+    float v[4][4];   // [row 4 (t & 7) + i][column 4 (t >> 3) + u]
     __device__ __forceinline__ void fetch(const float *const *rowp, const float *inv, int r0, int R, int t) {
+        const int kq = t & 7, c = (t >> 3) * 4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int e = t + q * 256;
-            int k = e >> 5, c = (e & 31) * 4;
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * kq + i;
             const float *p = rowp[k];
-            float s = inv[k];
+            const float s = inv[k];
             float4 x = make_float4(0, 0, 0, 0);
             if (p) {
                 if (r0 + c + 3 < R) {
@@ -159,19 +163,19 @@ struct StageB16 {
                     if (r0 + c + 2 < R) x.z = p[r0 + c + 2];
                 }
             }
-            v[4 * q] = x.x * s;
-            v[4 * q + 1] = x.y * s;
-            v[4 * q + 2] = x.z * s;
-            v[4 * q + 3] = x.w * s;
+            v[i][0] = x.x * s;
+            v[i][1] = x.y * s;
+            v[i][2] = x.z * s;
+            v[i][3] = x.w * s;
         }
     }
     __device__ __forceinline__ void commit(H (*sB)[LDK], int t) {
+        const int kq = t & 7, c = (t >> 3) * 4;
+        typedef H h4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int e = t + q * 256;
-            int k = e >> 5, c = (e & 31) * 4;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) sB[c + u][k] = (H)v[4 * q + u];
+        for (int u = 0; u < 4; ++u) {
+            h4 q = {(H)v[0][u], (H)v[1][u], (H)v[2][u], (H)v[3][u]};
+            *(h4 *)&sB[c + u][4 * kq] = q;
         }
     }
 };
@@ -250,10 +254,9 @@ __global__ void __launch_bounds__(256) k_proj_reduce16(const P1Red *red, const f
     const int row = blockIdx.x % TM;
     const int c = blockIdx.y * 256 + threadIdx.x;
     if (c >= R || row >= rd.nrows) return;
-    float s = 0.0f;
-    for (int p = 0; p < rd.part_count; ++p) s += part[((int64_t)(rd.part_begin + p) * TM + row) * ldr + c];
+    const float s = ordered_sum(part + ((int64_t)rd.part_begin * TM + row) * ldr + c, (int64_t)TM * ldr, rd.part_count);
     const float v = s / tscale[rd.t_row0 + row];
-    Tb[(int64_t)(rd.t_row0 + row) * ldr + c] = v;
+    if (Tb) Tb[(int64_t)(rd.t_row0 + row) * ldr + c] = v;
     if (T16) T16[(int64_t)(rd.t_row0 + row) * ld16 + c] = (__bf16)v;
 }
 
@@ -452,11 +455,13 @@ struct PairStage {
 // segments of at most a fixed number of panel columns, launched longest
 // first, so the uneven reductions of terrain tiles spread evenly over the
 // compute units; k_pair_finish sums a pair's segments in order.
-template <bool kUnused = false>
+template <bool kProj = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
-k_tile_mm16s(const WideSeg *segs, const int32_t *brow, const __bf16 *vals16, const __bf16 *X16, const __bf16 *T16,
-             int64_t ld16, float *wpart) {
-    const WideSeg sg = segs[blockIdx.x];
+k_tile_mm16s(const int32_t *order, const WideSeg *segs, const int32_t *brow, const __bf16 *vals16,
+             const __bf16 *X16, const __bf16 *T16, int64_t ld16, float *wpart, int64_t ldr, int R) {
+    const int32_t item = order[blockIdx.x];
+    if (item < 0) return;
+    const WideSeg sg = segs[item];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     constexpr int kPipe = (2 * 2 * TM * WLDK + 2 * WN * WLDK) * 2;
     __shared__ __align__(16) unsigned char smem[kPipe];
@@ -517,18 +522,58 @@ k_tile_mm16s(const WideSeg *segs, const int32_t *brow, const __bf16 *vals16, con
             mma(sA[1], sB[1]);
         }
     }
-    // the partial tile, row-major 128 x 256: each lane's 16 consecutive
-    // columns of a row form 64-byte runs
-    float *out = wpart + (int64_t)sg.slot * (2 * TM * WN);
     const int lk = lane >> 4;
+    if constexpr (kProj) {
+        // projection: rows 0..63 to partial tile `slot`, rows 64..127 to
+        // `slot2` (each 64 x ldr, columns below R)
+        const int32_t p = (w & 1) ? sg.slot2 : sg.slot;
+        if (p < 0) return;
+        float *out = wpart + (int64_t)p * TM * ldr;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+            for (int j = 0; j < 8; ++j) {
+                const int col = wc + j * 16 + lr;
+                if (col < R)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                __builtin_nontemporal_store(acc[i][j][v],
-                                            out + (int64_t)(wr + i * 16 + 4 * lk + v) * WN + wc + j * 16 + lr);
+                    for (int v = 0; v < 4; ++v) out[(int64_t)(i * 16 + 4 * lk + v) * ldr + col] = acc[i][j][v];
+            }
+    } else {
+        // the partial tile, row-major 128 x 256: each lane's 16 consecutive
+        // columns of a row form 64-byte runs
+        float *out = wpart + (int64_t)sg.slot * (2 * TM * WN);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    __builtin_nontemporal_store(acc[i][j][v],
+                                                out + (int64_t)(wr + i * 16 + 4 * lk + v) * WN + wc + j * 16 + lr);
+    }
+}
+
+// Panels of the 16-bit V copy for the wide projection: slab i holds V_J
+// columns krow0 .. krow0 + 63 of its group over the column node's facets,
+// element (r, k) at pan + (k / 32) 2048 + 32 r + k % 32 (the packed-panel
+// layout of the expansion), zero past the stacked rank and the facet count.
+struct VSlab {
+    int64_t pan;
+    int32_t group, krow0, kpad, pad_;
+};
+
+__global__ void __launch_bounds__(256) k_vpanels(const ProjGroup *groups, const VSlab *slabs, const __bf16 *vals16,
+                                                  __bf16 *out) {
+    const VSlab sl = slabs[blockIdx.x];
+    const ProjGroup g = groups[sl.group];
+    const int64_t total = (int64_t)sl.kpad * TM;
+    for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.y * 256) {
+        const int c = (int)(e / (TM * 32)), rem = (int)(e % (TM * 32));
+        const int r = rem / 32, k = c * 32 + rem % 32;
+        __bf16 v = (__bf16)0.0f;
+        if (sl.krow0 + r < g.ktot && k < g.n) v = vals16[g.v_off + (int64_t)(sl.krow0 + r) * g.ld + k];
+        out[sl.pan + e] = v;
+    }
 }
 
 // One workgroup per tile of a pair: the sum of the pair's segments (slots
@@ -690,8 +735,8 @@ void launch_wide(const rad_hmat *Hm, const float *E, const float *rho, float rho
     if (Hm->n_wpairs > 0) {
         // pairs of tiles with one operand-row list: their segments longest
         // first, then each pair's sum and epilogue; then the tiles left alone
-        hipLaunchKernelGGL(k_tile_mm16s<>, dim3(Hm->n_wsegs), dim3(256), 0, s, Hm->d_wsegs.p, Hm->d_brow.p, v16,
-                           x16, t16, ld16, Hm->w_wpart.p);
+        hipLaunchKernelGGL(k_tile_mm16s<false>, dim3(Hm->n_wseg_blocks), dim3(256), 0, s, Hm->d_wseg_order.p,
+                           Hm->d_wsegs.p, Hm->d_brow.p, v16, x16, t16, ld16, Hm->w_wpart.p, (int64_t)0, 0);
         hipLaunchKernelGGL((k_pair_finish<kFused>), dim3(2 * Hm->n_wpairs), dim3(256), 0, s, Hm->d_wpairs.p,
                            Hm->d_wslot.p, (const float *)Hm->w_wpart.p, Bold, ldr, R, Hm->N, Bnew, E, rho, rho_s,
                            part);
@@ -704,6 +749,19 @@ void launch_wide(const rad_hmat *Hm, const float *E, const float *rho, float rho
                            (const int32_t *)nullptr, Hm->d_brow.p, v16, x16, t16, ld16, Bold, ldr, R, Hm->N, Bnew, E,
                            rho, rho_s, part);
     }
+    RAD_HIP(hipGetLastError());
+}
+
+// wide BF16 projection (operands X16 already converted): the tile-pair
+// segment kernel on the V panels, then the sum of each slab's partial tiles
+// into T16 (the wide expansion reads only T16)
+void launch_proj16w(const rad_hmat *Hm, int64_t ldr, int R, __bf16 *T16, hipStream_t s) {
+    const int64_t ld16 = ld16_of(R);
+    hipLaunchKernelGGL(k_tile_mm16s<true>, dim3(Hm->n_pseg_blocks), dim3(256), 0, s, Hm->d_pseg_order.p,
+                       Hm->d_psegs.p, Hm->d_pbrow.p, (const __bf16 *)Hm->d_vpan16.p, (const __bf16 *)Hm->w_x16.p,
+                       (const __bf16 *)nullptr, ld16, (float *)Hm->w_part.p, ldr, R);
+    hipLaunchKernelGGL(k_proj_reduce16, dim3(Hm->n_wpred * TM, (R + 255) / 256), dim3(256), 0, s, Hm->d_wpred.p,
+                       (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)nullptr, T16, ld16);
     RAD_HIP(hipGetLastError());
 }
 
@@ -720,7 +778,9 @@ void step16_t(const rad_hmat *Hm, const float *E, const float *rho, float rho_s,
                            (__bf16 *)Hm->w_x16.p, ld16);
         RAD_HIP(hipGetLastError());
     }
-    if (Hm->n_p1work > 0) {
+    if (wide && Hm->n_psegs > 0) {
+        launch_proj16w(Hm, ldr, R, (__bf16 *)Hm->w_t16.p, s);
+    } else if (Hm->n_p1work > 0) {
         hipLaunchKernelGGL(k_proj_mm16<H>, dim3(Hm->n_p1work, rtiles), dim3(256), 0, s, Hm->d_groups.p,
                            Hm->d_p1work.p, v16, Bold, ldr, R, (float *)Hm->w_part.p);
         hipLaunchKernelGGL(k_proj_reduce16, dim3(Hm->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s, Hm->d_p1red.p,
@@ -806,7 +866,28 @@ void time16_t(const rad_hmat *Hm, int R, int nrep, hipStream_t s, double *ms) {
         RAD_HIP(hipEventElapsedTime(&t, e0, e1));
         return (double)t / nrep;
     };
-    if (Hm->n_p1work > 0) {
+    const bool wide = wide_ok(Hm, R);
+    const int64_t ld16 = ld16_of(R);
+    if (wide) {
+        // operand rows need finite values: convert the (zeroed) workspace once
+        const int64_t n = Hm->N * ld16;
+        hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, Hm->N, ldr, R,
+                           (__bf16 *)Hm->w_x16.p, ld16);
+        RAD_HIP(hipMemsetAsync(Hm->w_t16.p, 0, Hm->w_t16.bytes(), s));
+    }
+    if (wide && Hm->n_psegs > 0) {
+        ms[0] = timed([&] {
+            hipLaunchKernelGGL(k_tile_mm16s<true>, dim3(Hm->n_pseg_blocks), dim3(256), 0, s, Hm->d_pseg_order.p,
+                               Hm->d_psegs.p, Hm->d_pbrow.p, (const __bf16 *)Hm->d_vpan16.p,
+                               (const __bf16 *)Hm->w_x16.p, (const __bf16 *)nullptr, ld16, (float *)Hm->w_part.p,
+                               ldr, R);
+        });
+        ms[1] = timed([&] {
+            hipLaunchKernelGGL(k_proj_reduce16, dim3(Hm->n_wpred * TM, (R + 255) / 256), dim3(256), 0, s,
+                               Hm->d_wpred.p, (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)nullptr,
+                               (__bf16 *)Hm->w_t16.p, ld16);
+        });
+    } else if (Hm->n_p1work > 0) {
         ms[0] = timed([&] {
             hipLaunchKernelGGL(k_proj_mm16<H>, dim3(Hm->n_p1work, rtiles), dim3(256), 0, s, Hm->d_groups.p,
                                Hm->d_p1work.p, v16, X, ldr, R, (float *)Hm->w_part.p);
@@ -817,12 +898,7 @@ void time16_t(const rad_hmat *Hm, int R, int nrep, hipStream_t s, double *ms) {
                                (__bf16 *)nullptr, (int64_t)0);
         });
     }
-    if (wide_ok(Hm, R)) {
-        // operand rows need finite values: convert the (zeroed) workspace once
-        const int64_t ld16 = ld16_of(R), n = Hm->N * ld16;
-        hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, Hm->N, ldr, R,
-                           (__bf16 *)Hm->w_x16.p, ld16);
-        RAD_HIP(hipMemsetAsync(Hm->w_t16.p, 0, Hm->w_t16.bytes(), s));
+    if (wide) {
         ms[2] = timed([&] { launch_wide<true>(Hm, E, nullptr, 0.3f, X, Y, ldr, R, part, s); });
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -901,6 +977,83 @@ void ir_update(const rad_hmat *H, double *B64, const float *d, float *B32, int64
     dim3 grid((unsigned)H->n_tiles, (unsigned)((R + 255) / 256));
     hipLaunchKernelGGL(k_ir_update, grid, dim3(256), 0, s, B64, d, B32, H->N, ldr, (int)R);
     RAD_HIP(hipGetLastError());
+}
+
+// Wide BF16 projection schedule.  Items pair the 64-row slabs of each
+// stacked V_J^T and cut the column node's facets into runs of kw (whole
+// 32-facet chunks; kw a power of two from 512, the largest that still gives at
+// least eight items per compute unit, so that long column nodes leave few
+// partial tiles to sum).  A slab's partial tiles are numbered in facet order
+// (the fixed order of the sum).  The items of one facet run share their
+// operand rows and are launched on one XCD (xcd_launch_order).
+void lowp_prepare_proj(rad_hmat *H) {
+    H->n_psegs = H->n_pseg_blocks = H->n_wpred = 0;
+    if (H->lowp != RAD_BF16 || H->d_tile_tasks.n != 0 || H->h_groups.empty() || H->max_rhs < kMfmaMinRhs) return;
+    const std::vector<ProjGroup> &gs = H->h_groups;
+    auto items_for = [&](int64_t kw) {
+        int64_t c = 0;
+        for (const ProjGroup &g : gs) c += (int64_t)((g.ktot + 127) / 128) * ((g.n + kw - 1) / kw);
+        return c;
+    };
+    int32_t kw = 512;
+    while (kw < (1 << 16) && items_for(2 * kw) >= 8 * (int64_t)H->n_cu) kw *= 2;
+    std::vector<VSlab> slabs;
+    std::vector<int32_t> pbrow;
+    std::vector<WideSeg> segs;
+    std::vector<std::vector<int32_t>> share;   // items of one facet run of one column node
+    std::vector<P1Red> red;
+    int64_t pan = 0;
+    int32_t part = 0;
+    for (int32_t gi = 0; gi < (int32_t)gs.size(); ++gi) {
+        const ProjGroup &g = gs[gi];
+        if (g.n <= 0 || g.ktot <= 0) continue;
+        const int32_t kpad = (g.n + 31) / 32 * 32, nseg = (g.n + kw - 1) / kw;
+        const int64_t br0 = (int64_t)pbrow.size();
+        for (int32_t k = 0; k < kpad; ++k) pbrow.push_back(g.j0 + std::min(k, g.n - 1));
+        const size_t share0 = share.size();
+        share.resize(share0 + nseg);
+        for (int32_t k0 = 0; k0 < g.ktot; k0 += 128) {
+            const bool two = k0 + TM < g.ktot;
+            const int64_t pa = pan, pb = two ? pan + (int64_t)kpad * TM : pan;
+            slabs.push_back(VSlab{pa, gi, k0, kpad, 0});
+            if (two) slabs.push_back(VSlab{pb, gi, k0 + TM, kpad, 0});
+            pan += (two ? 2 : 1) * (int64_t)kpad * TM;
+            const int32_t b0 = part, b1 = two ? part + nseg : -1;
+            red.push_back(P1Red{g.t_off + k0, std::min(TM, g.ktot - k0), b0, nseg});
+            if (two) red.push_back(P1Red{g.t_off + k0 + TM, std::min(TM, g.ktot - k0 - TM), b1, nseg});
+            part += two ? 2 * nseg : nseg;
+            for (int32_t sg = 0; sg < nseg; ++sg) {
+                const int32_t jb = sg * kw, je = std::min(kpad, (sg + 1) * kw);
+                WideSeg w{};
+                w.pa = pa + (int64_t)jb * TM;
+                w.pb = pb + (int64_t)jb * TM;
+                w.br = br0 + jb;
+                w.kp = je - jb;
+                w.slot = b0 + sg;
+                w.slot2 = two ? b1 + sg : -1;
+                share[share0 + sg].push_back((int32_t)segs.size());
+                segs.push_back(w);
+            }
+        }
+    }
+    if (part > H->n_parts) throw Error(RAD_EUNSUP, "wide projection needs more partial tiles than the workspace holds");
+    std::vector<int64_t> cost(segs.size());
+    for (size_t i = 0; i < segs.size(); ++i) cost[i] = segs[i].kp;
+    const std::vector<int32_t> order = xcd_launch_order(share, cost);
+    H->d_vpan16.alloc((size_t)std::max<int64_t>(pan, 1));
+    H->d_pbrow.upload(pbrow);
+    H->d_psegs.upload(segs);
+    H->d_pseg_order.upload(order);
+    H->n_pseg_blocks = (int32_t)order.size();
+    H->d_wpred.upload(red);
+    DevBuf<VSlab> d_slabs;
+    d_slabs.upload(slabs);
+    hipLaunchKernelGGL(k_vpanels, dim3((unsigned)slabs.size(), 16), dim3(256), 0, 0, H->d_groups.p, d_slabs.p,
+                       (const __bf16 *)H->d_vals16.p, (__bf16 *)H->d_vpan16.p);
+    RAD_HIP(hipGetLastError());
+    RAD_HIP(hipStreamSynchronize(0));
+    H->n_psegs = (int32_t)segs.size();
+    H->n_wpred = (int32_t)red.size();
 }
 
 void lowp_convert(rad_hmat *H, hipStream_t s) {

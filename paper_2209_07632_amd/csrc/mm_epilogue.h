@@ -17,6 +17,24 @@ typedef double epi_d2 __attribute__((ext_vector_type(2)));
 
 // E and B_old values of one group of four rows of this thread's epilogue
 // share (rows rsub + RS (4 g + q), columns col .. col + 3)
+// p[0] + p[stride] + ... + p[(n - 1) stride], added in index order from
+// zero, with the loads of eight terms in flight at a time (the split-K sums
+// of partial tiles; the result is that of the plain sequential loop)
+template <class T>
+__device__ __forceinline__ T ordered_sum(const T *p, int64_t stride, int n) {
+    T s = 0;
+    int i = 0;
+    for (; i + 8 <= n; i += 8) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(i + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; i < n; ++i) s += p[(int64_t)i * stride];
+    return s;
+}
+
 template <class T, int TM, int TN>
 struct EpiRegs {
     static constexpr int CT = TN / 4, RS = 256 / CT;

@@ -202,9 +202,14 @@ struct GemvSeg {
 // tiles of a pair, whose 16-bit panels start at element offsets pa and pb
 // of the value pool and whose operand-row list starts at br; its partial
 // tile goes to slot `slot` (a pair's segments hold consecutive slots, in order).
+// The wide BF16 projection runs the same kernel on panels of the 16-bit V
+// copy (two 64-row slabs of V_J^T per item, operand rows the facets of the
+// column node): its rows 0..63 go to partial tile `slot`, rows 64..127 to
+// `slot2` (-1: the item has one slab).
 struct WideSeg {
     int64_t pa, pb, br;
     int32_t kp, slot;
+    int32_t slot2, pad_;
 };
 
 // Phase-1 group: all low-rank blocks sharing column node J.
@@ -354,8 +359,19 @@ struct rad_hmat {
     rad::DevBuf<int32_t> d_gseg_of_tile;
     int32_t n_gsegs = 0;
     rad::DevBuf<unsigned char> w_gpart;
-    rad::DevBuf<rad::WideSeg> d_wsegs;    // the pairs' reduction segments, longest first
+    rad::DevBuf<rad::WideSeg> d_wsegs;    // the pairs' reduction segments (index = partial slot)
     int32_t n_wsegs = 0;
+    rad::DevBuf<int32_t> d_wseg_order;    // their launch table (xcd_launch_order)
+    int32_t n_wseg_blocks = 0;
+    // wide BF16 projection: V panels (64 rows x 32 facets per chunk), the
+    // facet lists of the column nodes, the items (longest first) and the sums
+    // of partial tiles per 64-row slab of T
+    rad::DevBuf<uint16_t> d_vpan16;
+    rad::DevBuf<int32_t> d_pbrow;
+    rad::DevBuf<rad::WideSeg> d_psegs;
+    rad::DevBuf<int32_t> d_pseg_order;
+    rad::DevBuf<rad::P1Red> d_wpred;
+    int32_t n_psegs = 0, n_pseg_blocks = 0, n_wpred = 0;
     rad::DevBuf<int32_t> d_wslot;         // pair p's segments' partial tiles: slots [wslot[p], wslot[p+1])
     rad::DevBuf<float> w_wpart;           // partial tiles of the segments (128 x 256 FP32 each)
     int32_t n_cu = 256;
@@ -553,6 +569,15 @@ void select_columns(const rad_hmat *H, const void *a, const void *b, const int32
                     int64_t R, bool rmajor, hipStream_t s);
 void lowp_time_phases(const rad_hmat *H, int64_t R, int nrep, hipStream_t s, double *ms);
 void lowp_convert(rad_hmat *H, hipStream_t s);
+void lowp_prepare_proj(rad_hmat *H);
+// Launch table for independent work items on the 8 XCDs (workgroup i of a
+// 1-D grid runs on XCD i mod 8).  The items of one group read the same
+// operand rows: they go to one XCD back to back, so that its L2 serves those
+// rows once.  Groups are dealt, longest item first, to the XCD with the least
+// work so far; entry 8 s + x is the s-th item of XCD x (-1: none, the
+// workgroup exits).
+std::vector<int32_t> xcd_launch_order(const std::vector<std::vector<int32_t>> &groups,
+                                      const std::vector<int64_t> &cost);
 void lowp_step(const rad_hmat *H, const void *E, const void *rho, double rho_s, const void *Bold, void *Bnew,
                int64_t ldr, int64_t R, double *norms, hipStream_t s);
 void ir_residual(const rad_hmat *H, const float *E, const double *B64, const float *FB, const float *rho, double rho_s,

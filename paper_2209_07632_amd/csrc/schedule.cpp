@@ -1,0 +1,211 @@
+// Host-side launch schedules of the product kernels, prepared once per
+// matrix (after the build, a load, a precision conversion or a grouping):
+// the tile order of the persistent expansion, the pairs of projection slabs,
+// the single-RHS projection items of long column nodes and the segments of
+// long single-RHS tile reductions, the tile pairs and reduction segments of
+// the wide BF16 expansion, and the launch tables that place work items that
+// read the same operand rows on one XCD.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+#include "rad_internal.h"
+
+namespace rad {
+
+std::vector<int32_t> xcd_launch_order(const std::vector<std::vector<int32_t>> &groups,
+                                      const std::vector<int64_t> &cost) {
+    constexpr int kXcd = 8;
+    std::vector<int64_t> gmax(groups.size(), 0), gsum(groups.size(), 0);
+    for (size_t g = 0; g < groups.size(); ++g)
+        for (int32_t i : groups[g]) {
+            gmax[g] = std::max(gmax[g], cost[i]);
+            gsum[g] += cost[i];
+        }
+    std::vector<int32_t> gi(groups.size());
+    for (size_t g = 0; g < gi.size(); ++g) gi[g] = (int32_t)g;
+    std::stable_sort(gi.begin(), gi.end(), [&](int32_t a, int32_t b) { return gmax[a] > gmax[b]; });
+    std::vector<std::vector<int32_t>> q(kXcd);
+    std::vector<int64_t> load(kXcd, 0);
+    for (int32_t g : gi) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        q[x].insert(q[x].end(), groups[g].begin(), groups[g].end());
+        load[x] += gsum[g];
+    }
+    size_t len = 0;
+    for (const auto &v : q) len = std::max(len, v.size());
+    std::vector<int32_t> order(kXcd * len, -1);
+    for (int x = 0; x < kXcd; ++x)
+        for (size_t sl = 0; sl < q[x].size(); ++sl) order[kXcd * sl + x] = q[x][sl];
+    return order;
+}
+
+void mm_prepare_schedule(rad_hmat *H) {
+    const int32_t n = H->n_tiles;
+    std::vector<TileInfo> ti = H->d_tiles.download((size_t)n);
+    std::vector<TileTask> tk = H->d_tile_tasks.download(H->d_tile_tasks.n);
+    std::vector<int64_t> cost(n, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        cost[i] = ti[i].k16;
+        for (int32_t c = ti[i].csr_begin; c < ti[i].csr_end; ++c) cost[i] += tk[c].ncol;
+    }
+    std::vector<int32_t> order(n);
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    H->d_tile_order.upload(order);
+    std::vector<int32_t> zero(2, 0);
+    H->d_queue.upload(zero);
+    // phase-1 pairs: consecutive work items of one group and facet chunk whose
+    // V slabs follow each other (the list is ordered by group, chunk, slab)
+    std::vector<P1Work> wl = H->d_p1work.download((size_t)H->n_p1work);
+    std::vector<int32_t> pairs;
+    for (int32_t i = 0; i < H->n_p1work;) {
+        const bool pair = i + 1 < H->n_p1work && wl[i + 1].group == wl[i].group && wl[i + 1].jb == wl[i].jb &&
+                          wl[i + 1].krow0 == wl[i].krow0 + mm_part_rows();
+        pairs.push_back(i);
+        pairs.push_back(pair ? i + 1 : -1);
+        i += pair ? 2 : 1;
+    }
+    H->n_p1pairs = (int32_t)(pairs.size() / 2);
+    H->d_p1pairs.upload(pairs);
+    // single-RHS projections of long column nodes: one workgroup per V column
+    {
+        std::vector<int32_t> items;
+        for (int32_t gi = 0; gi < (int32_t)H->h_groups.size(); ++gi)
+            if (H->h_groups[gi].n >= kProjWideN)
+                for (int32_t kk = 0; kk < H->h_groups[gi].ktot; ++kk) {
+                    items.push_back(gi);
+                    items.push_back(kk);
+                }
+        H->n_pwide = (int32_t)(items.size() / 2);
+        H->d_pwide.upload(items);
+    }
+    // segments of the single-RHS tile product: panels longer than kGSeg
+    // columns (1 MB of values) are cut into near-equal runs of whole 16-column
+    // chunks, so one long tile no longer holds the product back
+    {
+        const int32_t vw = H->dtype == RAD_F64 ? 2 : 4;            // values per 16-byte load
+        const int32_t kGSeg = H->dtype == RAD_F64 ? 2048 : 4096;
+        int32_t kmax = 0;
+        for (int32_t i = 0; i < n; ++i) kmax = std::max(kmax, ti[i].k16);
+        H->n_gsegs = 0;
+        if (kmax > kGSeg) {
+            std::vector<GemvSeg> segs;
+            std::vector<int32_t> tseg(1, 0);
+            for (int32_t i = 0; i < n; ++i) {
+                const int32_t chunks = ti[i].k16 / 16;
+                const int32_t nseg = std::max(1, (ti[i].k16 + kGSeg - 1) / kGSeg);
+                for (int32_t sg = 0; sg < nseg; ++sg) {
+                    const int64_t c0 = (int64_t)chunks * sg / nseg, c1 = (int64_t)chunks * (sg + 1) / nseg;
+                    segs.push_back(GemvSeg{i, (int32_t)(16 * c0 / vw), (int32_t)(16 * c1 / vw), sg == 0 ? 1 : 0,
+                                           (int32_t)segs.size()});
+                }
+                tseg.push_back((int32_t)segs.size());
+            }
+            std::stable_sort(segs.begin(), segs.end(),
+                             [](const GemvSeg &a, const GemvSeg &b) { return a.g1 - a.g0 > b.g1 - b.g0; });
+            H->n_gsegs = (int32_t)segs.size();
+            H->d_gsegs.upload(segs);
+            H->d_gseg_of_tile.upload(tseg);
+        }
+    }
+    // tile pairs of the wide BF16 expansion: consecutive tiles (the halves of
+    // a 128-facet leaf) whose panels multiply the same operand rows
+    H->n_wpairs = H->n_wsingles = H->n_wsegs = H->n_wseg_blocks = 0;
+    if (H->lowp == RAD_BF16 && H->d_tile_tasks.n == 0 && n > 1) {
+        std::vector<int32_t> br = H->d_brow.download(H->d_brow.n);
+        std::vector<int32_t> wp, ws;
+        for (int32_t i = 0; i < n;) {
+            bool same = i + 1 < n && ti[i].kpad == ti[i + 1].kpad && ti[i].kpad > 0;
+            if (same)
+                same = std::equal(br.begin() + ti[i].brow_off, br.begin() + ti[i].brow_off + ti[i].kpad,
+                                  br.begin() + ti[i + 1].brow_off);
+            if (same) {
+                wp.push_back(i);
+                i += 2;
+            } else {
+                ws.push_back(i);
+                i += 1;
+            }
+        }
+        H->n_wpairs = (int32_t)wp.size();
+        H->n_wsingles = (int32_t)ws.size();
+        H->d_wpairs.upload(wp);
+        H->d_wsingles.upload(ws);
+        // segments: a pair's reduction is cut into near-equal runs of at most
+        // kSeg panel columns (whole 32-column chunks of the 16-bit layout,
+        // 64 x 32 values each); a pair's segments take consecutive partial
+        // slots in order, and are launched longest first
+        constexpr int32_t kSeg = 12288;
+        std::vector<WideSeg> bySlot;
+        std::vector<int32_t> pslot(1, 0);
+        // share groups: segment sg of consecutive pairs with one operand-row
+        // list (the tiles of one leaf) reads the same operand rows
+        std::vector<std::vector<int32_t>> share;
+        int32_t first_of_run = 0;
+        for (int32_t p = 0; p < (int32_t)wp.size(); ++p) {
+            const TileInfo &a = ti[wp[p]], &b = ti[wp[p] + 1];
+            bool same_rows = false;
+            if (p > 0) {
+                const TileInfo &q = ti[wp[p - 1]];
+                same_rows = q.kpad == a.kpad && std::equal(br.begin() + a.brow_off, br.begin() + a.brow_off + a.kpad,
+                                                           br.begin() + q.brow_off);
+            }
+            const int32_t chunks = a.kpad / 32;
+            const int32_t nseg = std::max(1, (a.kpad + kSeg - 1) / kSeg);
+            if (!same_rows) first_of_run = (int32_t)share.size();
+            for (int32_t sg = 0; sg < nseg; ++sg) {
+                const int64_t c0 = (int64_t)chunks * sg / nseg, c1 = (int64_t)chunks * (sg + 1) / nseg;
+                WideSeg w{};
+                w.pa = a.panel_off + c0 * 32 * 64;
+                w.pb = b.panel_off + c0 * 32 * 64;
+                w.br = a.brow_off + c0 * 32;
+                w.kp = (int32_t)(32 * (c1 - c0));
+                w.slot = (int32_t)bySlot.size();
+                w.slot2 = -1;
+                if (same_rows)
+                    share[first_of_run + sg].push_back(w.slot);
+                else
+                    share.push_back({w.slot});
+                bySlot.push_back(w);
+            }
+            pslot.push_back((int32_t)bySlot.size());
+        }
+        std::vector<int64_t> cost(bySlot.size());
+        for (size_t i = 0; i < bySlot.size(); ++i) cost[i] = bySlot[i].kp;
+        const std::vector<int32_t> order = xcd_launch_order(share, cost);
+        H->n_wsegs = (int32_t)bySlot.size();
+        H->d_wsegs.upload(bySlot);
+        H->n_wseg_blocks = (int32_t)order.size();
+        H->d_wseg_order.upload(order);
+        H->d_wslot.upload(pslot);
+    }
+    int ncu = 0;
+    RAD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, H->device));
+    H->n_cu = std::max(1, ncu);
+    lowp_prepare_proj(H);
+    // signature: FNV-1a over the log2 histogram of tile costs and the shape counts
+    std::vector<int64_t> hist(40, 0);
+    for (int64_t c : cost) {
+        int b = 0;
+        while (b < 39 && ((int64_t)1 << b) <= c) ++b;
+        hist[b]++;
+    }
+    hist.push_back(H->n_p1work);
+    hist.push_back(H->n_p1red);
+    hist.push_back(H->n_inst);
+    uint64_t h = 1469598103934665603ull;
+    for (int64_t v : hist)
+        for (int byte = 0; byte < 8; ++byte) {
+            h ^= (uint64_t)((v >> (8 * byte)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "dt%d_tiles%d_cu%d_h%016llx", (int)H->dtype, (int)n, H->n_cu,
+                  (unsigned long long)h);
+    H->sched_sig = buf;
+}
+
+}  // namespace rad

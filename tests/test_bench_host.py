@@ -16,14 +16,16 @@ def _bench():
 
 
 def test_traffic_record_follows_the_kernel_source():
-    """The recorded bytes are reported while the kernel source has the
-    recorded SHA-1, and null once it has changed."""
+    """The recorded bytes are reported while the kernel's sources have the
+    recorded SHA-1, and null once they have changed."""
     import hashlib
     bench = _bench()
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
     got = bench.measured_traffic(rec["dtype"], rec["rhs"], rec.get("tn"))
-    sha = hashlib.sha1(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()
-    if sha == rec["source_sha1"]:
+    h = hashlib.sha1()
+    for rel in rec["sources"]:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    if h.hexdigest() == rec["sources_sha1"]:
         assert got == rec["traffic_bytes_per_launch"] and got > 0
     else:
         assert got is None
