@@ -462,6 +462,46 @@ def run_batch(args):
     print(json.dumps(result), flush=True)
 
 
+def run_terrain_phases(args):
+    """Kernel phases (projections, split-K sum, expansion with the fused
+    Jacobi update) of the terrain operator at R = 256, 16-bit and FP32: a DEM
+    of --dem-n x --dem-n cells of 10 m (the 131k terrain's generator, leaf
+    128, ray-cast visibility, dense near field, BF16 copy).  With
+    --save-operator the operator is built and written to that file and the
+    run ends; with --load-operator it is read from a file written so, which
+    keeps the build out of a profiled run."""
+    import torch
+    from paper_2209_07632_amd import HMatrix
+    from synth import DemSpec, dem_mesh
+
+    if args.load_operator:
+        H = HMatrix.load(args.load_operator)
+        build_s = None
+    else:
+        verts, faces = dem_mesh(DemSpec(n=args.dem_n, extent=10.0 * args.dem_n, seed=2))
+        t0 = time.perf_counter()
+        H = HMatrix(verts, faces, tol=args.tol, storage="f32", visibility="raycast", nearfield="dense",
+                    leaf_size=128, max_rank=256, max_rhs=256, lowp=args.lowp)
+        build_s = time.perf_counter() - t0
+        if args.save_operator:
+            H.save(args.save_operator)
+            log(f"built N={H.N} in {build_s:.1f} s, saved to {args.save_operator}")
+            return
+    X = torch.rand((H.N, 256), dtype=torch.float32, device="cuda:0")
+    for _ in range(2):
+        H.matvec(X, lowp=True)
+    torch.cuda.synchronize()
+    ph16 = H.time_phases(256, nrep=max(args.steps, 1), lowp=True)
+    ph32 = H.time_phases(256, nrep=max(args.steps // 2, 1))
+    st = H.stats()
+    print(json.dumps({"metric": "terrain product phases (ms per launch, R = 256)", "value": sum(ph16), "unit": "ms",
+                      "higher_is_better": False, "n_gpus": 1, "dtype": "bf16+f32", "data": "synthetic",
+                      "config": {"workload": f"DEM {args.dem_n}x{args.dem_n} cells of 10 m, N={H.N}, leaf 128, "
+                                             f"tol {args.tol}", "N": H.N},
+                      "phases_16bit_ms": ph16, "phases_fp32_ms": ph32, "build_seconds": build_s,
+                      "hmat_blocks": block_counts(st)}), flush=True)
+
+
 def run_warm(args):
     """Learned warm start on the 40k-facet cap: POD (64 modes) of the scattered
     radiosity B - E of 512 training suns, a 3 x 256 tanh perceptron from sun
@@ -635,7 +675,7 @@ def run_ts(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="cap40k", choices=["cap40k", "dem131k", "batch64", "warm40k", "ts40k"])
+    ap.add_argument("--workload", default="cap40k", choices=["cap40k", "dem131k", "batch64", "warm40k", "ts40k", "terrain_phases"])
     ap.add_argument("--mlp", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--instances", type=int, default=64)
@@ -656,6 +696,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true", help="add a 1 GiB copy for counter calibration")
     ap.add_argument("--no-extras", action="store_true",
                     help="the cap workload alone (no eps sweep, FP64 leg or terrain keys)")
+    ap.add_argument("--dem-n", type=int, default=128, help="terrain_phases: DEM cells per side")
+    ap.add_argument("--save-operator", default=None, help="terrain_phases: build, write the operator there, stop")
+    ap.add_argument("--load-operator", default=None, help="terrain_phases: read the operator from this file")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it"}))
@@ -664,6 +707,8 @@ def main():
         return run_warm(args)
     if args.workload == "ts40k":
         return run_ts(args)
+    if args.workload == "terrain_phases":
+        return run_terrain_phases(args)
     if args.workload == "batch64":
         if args.nearfield == "csr":
             args.nearfield = "dense"   # terrain near field: dense panels run far faster than CSR slices
