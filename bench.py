@@ -67,6 +67,46 @@ def block_counts(st):
                                "max_rank", "nnz_near", "bytes_dense", "bytes_csr", "bytes_lowrank", "bytes_total")}
 
 
+def single_rhs_leg(G, cols, albedo, rtol):
+    """The plain FP64 single-RHS form: the given suns solved one at a time
+    (Jacobi, same tolerance and stopping rule), timed; its product kernels
+    (k_proj + k_tile_gemv, one column) timed on their own; and each set
+    against HBM: one iteration must at least read the operator and the
+    column vectors (E, B_old read, B_new written: 3 N 8 bytes)."""
+    import torch
+    N = G.N
+    Bt = torch.zeros(N, dtype=torch.float64, device="cuda:0")
+    for e in cols[:2]:
+        G.solve(e, rho=albedo, rtol=rtol, out=Bt, order="tree")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for e in cols:
+        _, inf = G.solve(e, rho=albedo, rtol=rtol, out=Bt, order="tree")
+        its.append(int(inf["total_iters"]))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    y = torch.empty_like(Bt)
+    for _ in range(3):
+        G.matvec(cols[0], out=y, order="tree")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(20):
+        G.matvec(cols[0], out=y, order="tree")
+    ev1.record()
+    torch.cuda.synchronize()
+    mv_ms = ev0.elapsed_time(ev1) / 20
+    op_bytes = G.stats()["bytes_total"]
+    it_bytes = op_bytes + 3 * N * 8
+    hbm_ms = sum(its) * it_bytes / (HBM_PEAK_GBS * 1e9) * 1e3 / len(cols)
+    solve_ms = 1e3 * dt / len(cols)
+    return {"solves_per_s": len(cols) / dt, "iterations": its, "ms_per_solve": solve_ms,
+            "hbm_ms_per_solve": hbm_ms, "solve_vs_hbm": solve_ms / hbm_ms,
+            "product_ms": mv_ms, "product_gbs": (op_bytes + 2 * N * 8) / (mv_ms * 1e-3) / 1e9,
+            "product_frac_hbm": (op_bytes + 2 * N * 8) / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "operator_bytes": op_bytes}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -235,20 +275,14 @@ def terrain_measure(steps, tol=1e-3, lowp="bf16", rtol=1e-4, inner=3, cpu_rows=6
         G = H.convert("f64", max_rhs=1)
         E0 = batches[0][0]
         cols = [E0[:, c].double().contiguous() for c in range(16)]
-        Bt = torch.zeros(N, dtype=torch.float64, device="cuda:0")
-        for e in cols[:2]:
-            G.solve(e, rho=albedo, rtol=rtol, out=Bt, order="tree")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        its = []
-        for e in cols:
-            _, inf = G.solve(e, rho=albedo, rtol=rtol, out=Bt, order="tree")
-            its.append(inf["total_iters"])
-        torch.cuda.synchronize()
-        single64 = len(cols) / (time.perf_counter() - t0)
+        leg = single_rhs_leg(G, cols, albedo, rtol)
         G.close()
+        single64 = leg["solves_per_s"]
         out["fp64_single_rhs_solves_per_s"] = single64
-        out["fp64_single_rhs_iterations"] = its
+        out["fp64_single_rhs_iterations"] = leg["iterations"]
+        out["fp64_single_rhs"] = leg
+        log(f"plain FP64 single-RHS: {leg['ms_per_solve']:.2f} ms per solve = {leg['solve_vs_hbm']:.2f} x its HBM "
+            f"time; product {leg['product_ms']:.3f} ms ({leg['product_frac_hbm']:.2f} of HBM)")
         out["speedup_refined_vs_fp64_single_rhs"] = results["refined_16bit"]["solves_per_s"] / single64
         out["speedup_fp32_jacobi_vs_fp64_single_rhs"] = results["fp32_jacobi"]["solves_per_s"] / single64
         log(f"plain FP64 single-RHS solves on the same operator: {single64:.1f} solves/s")
@@ -887,18 +921,13 @@ def main():
     del X, Y
     H64 = HMatrix(verts, faces, tol=args.tol, storage="f64", nearfield=args.nearfield, max_rhs=1)
     cols64 = [E[:, c].double().contiguous() for c in range(16)]
-    Bt = torch.zeros(N, dtype=torch.float64, device=dev)
-    for e in cols64[:2]:
-        H64.solve(e, rho=albedo, rtol=args.rtol, out=Bt, order="tree")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e in cols64:
-        H64.solve(e, rho=albedo, rtol=args.rtol, out=Bt, order="tree")
-    torch.cuda.synchronize()
-    single64 = len(cols64) / (time.perf_counter() - t0)
+    leg = single_rhs_leg(H64, cols64, albedo, args.rtol)
     del H64
-    log(f"plain FP64 single-RHS solves: {single64:.1f} solves/s ({len(cols64)} suns one at a time)")
+    single64 = leg["solves_per_s"]
+    log(f"plain FP64 single-RHS solves: {single64:.1f} solves/s ({len(cols64)} suns one at a time; "
+        f"{leg['solve_vs_hbm']:.1f} x the HBM time of its iterations; product {leg['product_ms']:.4f} ms)")
     result["fp64_single_rhs_solves_per_s"] = single64
+    result["fp64_single_rhs"] = leg
     result["speedup_vs_fp64_single_rhs"] = solves_per_s / single64
     ok = True
     if not args.no_cpu_baseline:

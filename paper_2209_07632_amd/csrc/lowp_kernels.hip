@@ -248,17 +248,29 @@ __global__ void __launch_bounds__(256) k_proj_mm16(const ProjGroup *groups, cons
 }
 
 // T rows = (sum of the split partials) / d_row
+// Grid (slabs, 4, column blocks of 256): 16 rows of a slab per workgroup,
+// four consecutive columns per thread (four rows at a time)
 __global__ void __launch_bounds__(256) k_proj_reduce16(const P1Red *red, const float *part, const float *tscale,
                                                         int64_t ldr, int R, float *Tb, __bf16 *T16, int64_t ld16) {
-    const P1Red rd = red[blockIdx.x / TM];
-    const int row = blockIdx.x % TM;
-    const int c = blockIdx.y * 256 + threadIdx.x;
-    if (c >= R || row >= rd.nrows) return;
-    const float s = ordered_sum(part + ((int64_t)rd.part_begin * TM + row) * ldr + c, (int64_t)TM * ldr, rd.part_count);
-    const float v = s / tscale[rd.t_row0 + row];
-    if (Tb) Tb[(int64_t)(rd.t_row0 + row) * ldr + c] = v;
-    if (T16) T16[(int64_t)(rd.t_row0 + row) * ld16 + c] = (__bf16)v;
+    const P1Red rd = red[blockIdx.x];
+    const int c = ((int)blockIdx.z * 64 + (int)(threadIdx.x & 63)) * 4;
+    if (c >= R) return;
+    const int r1 = min(rd.nrows, (int)blockIdx.y * 16 + 16);
+    for (int row = (int)blockIdx.y * 16 + (int)(threadIdx.x >> 6); row < r1; row += 4) {
+        const float4 s = ordered_sum4((const float4 *)(part + ((int64_t)rd.part_begin * TM + row) * ldr + c),
+                                      (int64_t)TM * ldr / 4, rd.part_count);
+        const float d = tscale[rd.t_row0 + row];
+        const float v[4] = {s.x / d, s.y / d, s.z / d, s.w / d};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c + u < R) {
+                if (Tb) Tb[(int64_t)(rd.t_row0 + row) * ldr + c + u] = v[u];
+                if (T16) T16[(int64_t)(rd.t_row0 + row) * ld16 + c + u] = (__bf16)v[u];
+            }
+    }
 }
+
+dim3 reduce_grid(int32_t nred, int R) { return dim3((unsigned)nred, 4, (unsigned)((R + 255) / 256)); }
 
 // X16 = bf16(X) for the R columns, zero padding up to ld16
 __global__ void __launch_bounds__(256) k_to_bf16(const float *X, int64_t N, int64_t ldr, int R, __bf16 *X16,
@@ -760,7 +772,7 @@ void launch_proj16w(const rad_hmat *Hm, int64_t ldr, int R, __bf16 *T16, hipStre
     hipLaunchKernelGGL(k_tile_mm16s<true>, dim3(Hm->n_pseg_blocks), dim3(256), 0, s, Hm->d_pseg_order.p,
                        Hm->d_psegs.p, Hm->d_pbrow.p, (const __bf16 *)Hm->d_vpan16.p, (const __bf16 *)Hm->w_x16.p,
                        (const __bf16 *)nullptr, ld16, (float *)Hm->w_part.p, ldr, R);
-    hipLaunchKernelGGL(k_proj_reduce16, dim3(Hm->n_wpred * TM, (R + 255) / 256), dim3(256), 0, s, Hm->d_wpred.p,
+    hipLaunchKernelGGL(k_proj_reduce16, reduce_grid(Hm->n_wpred, R), dim3(256), 0, s, Hm->d_wpred.p,
                        (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)nullptr, T16, ld16);
     RAD_HIP(hipGetLastError());
 }
@@ -783,7 +795,7 @@ void step16_t(const rad_hmat *Hm, const float *E, const float *rho, float rho_s,
     } else if (Hm->n_p1work > 0) {
         hipLaunchKernelGGL(k_proj_mm16<H>, dim3(Hm->n_p1work, rtiles), dim3(256), 0, s, Hm->d_groups.p,
                            Hm->d_p1work.p, v16, Bold, ldr, R, (float *)Hm->w_part.p);
-        hipLaunchKernelGGL(k_proj_reduce16, dim3(Hm->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s, Hm->d_p1red.p,
+        hipLaunchKernelGGL(k_proj_reduce16, reduce_grid(Hm->n_p1red, R), dim3(256), 0, s, Hm->d_p1red.p,
                            (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)Hm->w_t.p,
                            wide ? (__bf16 *)Hm->w_t16.p : (__bf16 *)nullptr, ld16);
         RAD_HIP(hipGetLastError());
@@ -883,7 +895,7 @@ void time16_t(const rad_hmat *Hm, int R, int nrep, hipStream_t s, double *ms) {
                                ldr, R);
         });
         ms[1] = timed([&] {
-            hipLaunchKernelGGL(k_proj_reduce16, dim3(Hm->n_wpred * TM, (R + 255) / 256), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_proj_reduce16, reduce_grid(Hm->n_wpred, R), dim3(256), 0, s,
                                Hm->d_wpred.p, (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)nullptr,
                                (__bf16 *)Hm->w_t16.p, ld16);
         });
@@ -893,7 +905,7 @@ void time16_t(const rad_hmat *Hm, int R, int nrep, hipStream_t s, double *ms) {
                                Hm->d_p1work.p, v16, X, ldr, R, (float *)Hm->w_part.p);
         });
         ms[1] = timed([&] {
-            hipLaunchKernelGGL(k_proj_reduce16, dim3(Hm->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_proj_reduce16, reduce_grid(Hm->n_p1red, R), dim3(256), 0, s,
                                Hm->d_p1red.p, (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)Hm->w_t.p,
                                (__bf16 *)nullptr, (int64_t)0);
         });

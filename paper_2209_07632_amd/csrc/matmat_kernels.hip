@@ -446,18 +446,29 @@ k_proj_mm(const ProjGroup *groups, const P1Work *work, const int32_t *pairs,
             }
 }
 
-// T rows = sum of the partial tiles of every split (fixed order); one thread
-// per (row of T, column)
+dim3 reduce_grid(int32_t nred, int64_t R) { return dim3((unsigned)nred, 4, (unsigned)((R + 255) / 256)); }
+
+// T rows = sum of the partial tiles of every split (fixed order).  Grid
+// (slabs, 4, column blocks of 256): 16 rows of a slab per workgroup, four
+// consecutive columns per thread (four rows at a time)
 template <class T>
 __global__ void __launch_bounds__(256) k_proj_reduce(const P1Red *red, const T *part, int64_t ldr, int R, T *Tb,
                                                      const int32_t *stop) {
     if (stop && *stop) return;
-    const P1Red rd = red[blockIdx.x / TM];
-    const int row = blockIdx.x % TM;
-    const int c = blockIdx.y * 256 + threadIdx.x;
-    if (c >= R || row >= rd.nrows) return;
-    Tb[(int64_t)(rd.t_row0 + row) * ldr + c] =
-        ordered_sum(part + ((int64_t)rd.part_begin * TM + row) * ldr + c, (int64_t)TM * ldr, rd.part_count);
+    typedef typename std::conditional<sizeof(T) == 4, float4, double4>::type V;
+    const P1Red rd = red[blockIdx.x];
+    const int c = ((int)blockIdx.z * 64 + (int)(threadIdx.x & 63)) * 4;
+    if (c >= R) return;
+    const int r1 = min(rd.nrows, (int)blockIdx.y * 16 + 16);
+    for (int row = (int)blockIdx.y * 16 + (int)(threadIdx.x >> 6); row < r1; row += 4) {
+        const V sv = ordered_sum4((const V *)(part + ((int64_t)rd.part_begin * TM + row) * ldr + c),
+                                  (int64_t)TM * ldr / 4, rd.part_count);
+        const T v[4] = {sv.x, sv.y, sv.z, sv.w};
+        T *out = Tb + (int64_t)(rd.t_row0 + row) * ldr + c;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c + u < R) out[u] = v[u];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -787,7 +798,7 @@ void proj_mm_tn(const rad_hmat *H, const T *X, int64_t ldr, int R, hipStream_t s
                            H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const T *)H->d_vals.p, X, ldr, R,
                            (T *)H->w_part.p, (int)rtiles, stop);
         RAD_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_proj_reduce<T>, dim3(H->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s, H->d_p1red.p,
+        hipLaunchKernelGGL(k_proj_reduce<T>, reduce_grid(H->n_p1red, R), dim3(256), 0, s, H->d_p1red.p,
                            (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p, stop);
         RAD_HIP(hipGetLastError());
     }
@@ -940,7 +951,7 @@ void time_phases_t(const rad_hmat *H, int R, int nrep, hipStream_t s, double *ms
                                    R, (T *)H->w_part.p, (int)rtiles, nullptr);
         });
         ms[1] = timed([&] {
-            hipLaunchKernelGGL(k_proj_reduce<T>, dim3(H->n_p1red * TM, (R + 255) / 256), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_proj_reduce<T>, reduce_grid(H->n_p1red, R), dim3(256), 0, s,
                                H->d_p1red.p, (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p, nullptr);
         });
     }

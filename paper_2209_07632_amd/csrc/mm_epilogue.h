@@ -35,6 +35,35 @@ __device__ __forceinline__ T ordered_sum(const T *p, int64_t stride, int n) {
     return s;
 }
 
+// the same for four consecutive columns at once (V: float4 or double4),
+// component by component in index order
+template <class V>
+__device__ __forceinline__ V ordered_sum4(const V *p, int64_t stride, int n) {
+    V s;
+    s.x = s.y = s.z = s.w = 0;
+    int i = 0;
+    for (; i + 8 <= n; i += 8) {
+        V v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(i + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            s.x += v[u].x;
+            s.y += v[u].y;
+            s.z += v[u].z;
+            s.w += v[u].w;
+        }
+    }
+    for (; i < n; ++i) {
+        const V v = p[(int64_t)i * stride];
+        s.x += v.x;
+        s.y += v.y;
+        s.z += v.z;
+        s.w += v.w;
+    }
+    return s;
+}
+
 template <class T, int TM, int TN>
 struct EpiRegs {
     static constexpr int CT = TN / 4, RS = 256 / CT;

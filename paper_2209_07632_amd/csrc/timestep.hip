@@ -150,6 +150,84 @@ __global__ void __launch_bounds__(kColThreads) k_ts_column(int M, int64_t N, int
     }
 }
 
+// The same step with the column in registers, for columns of at most kMax
+// layers: the thread issues the loads of all M + 1 levels of its column at
+// once (the elimination above waits on them one by one) and keeps the
+// pivoted right-hand sides d_j in registers.  Same arithmetic, same order.
+constexpr int kRegLayers = 32;
+constexpr int kRegThreads = 256;
+
+template <class T, int kMax>
+__global__ void __launch_bounds__(kRegThreads) k_ts_column_r(int M, int64_t N, int64_t R, const double *coef,
+                                                             const double *Tin, double *Tout, double *qabs,
+                                                             double *qrad, const T *Y, T *X, int64_t ldx, int rmajor,
+                                                             const T *qd, const T *qd_next, int64_t ldq, int order,
+                                                             const int32_t *perm, double albedo, double emiss,
+                                                             double hb, int newton) {
+    const double *cap = coef, *g = coef + (M + 1), *ib = coef + 2 * (M + 1), *e = coef + 3 * (M + 1);
+    const int64_t NR = N * R;
+    const double es = emiss * kSigmaSB;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NR; i += (int64_t)gridDim.x * blockDim.x) {
+        double tv[kMax + 2], dv[kMax];   // tv[kMax + 1]: never read (pads the j + 1 below)
+#pragma unroll
+        for (int j = 0; j <= kMax; ++j)
+            if (j <= M) tv[j] = Tin[(int64_t)j * NR + i];
+        const int64_t t = i / R, r = i - t * R;
+        const int64_t y1 = op_index(rmajor, t, r, ldx, N), y2 = op_index(rmajor, t, R + r, ldx, N);
+        const double qrefl = (double)Y[y1], qir = (double)Y[y2];
+        const double qdir = (double)qd[user_index(order, t, r, ldq, perm)];
+        const double qa_new = (1.0 - albedo) * (qdir + qrefl) + emiss * qir;
+        const double qa_old = qabs[i];
+        double d = 0.0;
+#pragma unroll
+        for (int j = kMax; j >= 1; --j) {
+            if (j <= M) {
+                const double t_here = tv[j], t_above = tv[j - 1];
+                double rj = cap[j] * t_here + 0.5 * g[j] * (t_above - t_here);
+                if (j < M)
+                    rj += 0.5 * g[j + 1] * (tv[j + 1] - t_here) + 0.5 * g[j + 1] * d;
+                else
+                    rj += hb;
+                d = rj * ib[j];
+                dv[j - 1] = d;
+            }
+        }
+        const double t0 = tv[0], t1 = tv[1], g1 = g[1];
+        double tn;
+        if (newton < 0) {
+            const double t03 = t0 * t0 * t0;
+            const double drad = 2.0 * es * t03;
+            const double r0 =
+                cap[0] * t0 + 0.5 * g1 * (t1 - t0) + 0.5 * (qa_old + qa_new) - es * t03 * t0 + drad * t0;
+            tn = (r0 + 0.5 * g1 * d) / (cap[0] + 0.5 * g1 + drad + 0.5 * g1 * e[1]);
+        } else {
+            double u = t0;
+            for (int it = 0; it <= newton; ++it) {
+                const double u3 = u * u * u;
+                u = (qa_new + 3.0 * es * u3 * u + g1 * d) / (g1 * (1.0 + e[1]) + 4.0 * es * u3);
+            }
+            tn = u;
+        }
+        Tout[i] = tn;
+        const double ts = tn;
+#pragma unroll
+        for (int j = 1; j <= kMax; ++j) {
+            if (j <= M) {
+                tn = dv[j - 1] - e[j] * tn;
+                Tout[(int64_t)j * NR + i] = tn;
+            }
+        }
+        qabs[i] = qa_new;
+        const double qr = es * ts * ts * ts * ts;
+        qrad[i] = qr;
+        if (qd_next) {
+            const double q2 = (double)qd_next[user_index(order, t, r, ldq, perm)];
+            X[y1] = (T)(albedo * (q2 + qrefl));
+            X[y2] = (T)(qr + (1.0 - emiss) * qir);
+        }
+    }
+}
+
 template <class T>
 __global__ void k_ts_read(int field, int M, int64_t N, int64_t R, const double *Ts, const double *qabs,
                           const double *qrad, const T *Y, int64_t ldx, int rmajor, double *out, int64_t ld,
@@ -172,6 +250,32 @@ __global__ void k_ts_read(int field, int M, int64_t N, int64_t R, const double *
 
 unsigned grid_for(int64_t n, int threads) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + threads - 1) / threads, 1 << 20));
+}
+
+// one step of every column: the register form (its smallest instance that
+// holds M layers) for up to kRegLayers layers
+template <class T>
+void launch_column(int M, int64_t N, int64_t R, const double *coef, const double *Tin, double *Tout, double *qabs,
+                   double *qrad, const T *Y, T *X, int64_t ldx, int rmajor, const T *qd, const T *qd_next,
+                   int64_t ldq, int order, const int32_t *perm, double albedo, double emiss, double hb, int newton,
+                   hipStream_t s) {
+    const int64_t NR = N * R;
+    auto reg = [&](auto kmax) {
+        hipLaunchKernelGGL((k_ts_column_r<T, decltype(kmax)::value>), dim3(grid_for(NR, kRegThreads)),
+                           dim3(kRegThreads), 0, s, M, N, R, coef, Tin, Tout, qabs, qrad, Y, X, ldx, rmajor, qd,
+                           qd_next, ldq, order, perm, albedo, emiss, hb, newton);
+    };
+    if (M <= 16)
+        reg(std::integral_constant<int, 16>{});
+    else if (M <= 24)
+        reg(std::integral_constant<int, 24>{});
+    else if (M <= kRegLayers)
+        reg(std::integral_constant<int, kRegLayers>{});
+    else
+        hipLaunchKernelGGL(k_ts_column<T>, dim3(grid_for(NR, kColThreads)), dim3(kColThreads),
+                           sizeof(double) * (size_t)M * kColThreads, s, M, N, R, coef, Tin, Tout, qabs, qrad, Y, X,
+                           ldx, rmajor, qd, qd_next, ldq, order, perm, albedo, emiss, hb, newton);
+    RAD_HIP(hipGetLastError());
 }
 
 }  // namespace
@@ -239,7 +343,6 @@ void enqueue_steps(rad_ts *S, int64_t n_steps, const void *Qdir, int64_t ldq, in
     hipLaunchKernelGGL(k_ts_operand<T>, dim3(grid_for(NR, 256)), dim3(256), 0, s, S->N, S->R, S->qrad.p,
                        (const T *)S->Y.p, (T *)S->X.p, S->ldx, rm, qd0, ldq, (int)order, perm, S->albedo, S->emiss);
     RAD_HIP(hipGetLastError());
-    const size_t lds = sizeof(double) * (size_t)S->M * kColThreads;
     for (int64_t k = 0; k < n_steps; ++k) {
         if (S->rmajor)
             mm_apply(H, S->X.p, S->Y.p, S->ldx, 2 * S->R, s);
@@ -247,11 +350,9 @@ void enqueue_steps(rad_ts *S, int64_t n_steps, const void *Qdir, int64_t ldq, in
             mv_apply(H, S->X.p, S->N, S->Y.p, S->N, 2 * S->R, s);
         const T *qd = qd0 + k * stride;
         const T *qn = k + 1 < n_steps ? qd0 + (k + 1) * stride : nullptr;
-        hipLaunchKernelGGL(k_ts_column<T>, dim3(grid_for(NR, kColThreads)), dim3(kColThreads), lds, s, S->M, S->N,
-                           S->R, S->coef.p, S->T[S->cur].p, S->T[S->cur ^ 1].p, S->qabs.p, S->qrad.p,
-                           (const T *)S->Y.p, (T *)S->X.p, S->ldx, rm, qd, qn, ldq, (int)order, perm, S->albedo,
-                           S->emiss, S->hb, S->newton);
-        RAD_HIP(hipGetLastError());
+        launch_column<T>(S->M, S->N, S->R, S->coef.p, S->T[S->cur].p, S->T[S->cur ^ 1].p, S->qabs.p, S->qrad.p,
+                         (const T *)S->Y.p, (T *)S->X.p, S->ldx, rm, qd, qn, ldq, (int)order, perm, S->albedo,
+                         S->emiss, S->hb, S->newton, s);
         S->cur ^= 1;
         ++S->level;
     }
@@ -396,8 +497,6 @@ rad_status rad_ts_time_column(rad_ts *S, int32_t nrep, void *hip_stream, double 
         RAD_REQUIRE(nrep >= 1, "nrep must be >= 1");
         RAD_HIP(hipSetDevice(S->H->device));
         hipStream_t s = (hipStream_t)hip_stream;
-        const int64_t NR = S->N * S->R;
-        const size_t lds = sizeof(double) * (size_t)S->M * kColThreads;
         const int rm = S->rmajor ? 1 : 0;
         // the operand buffer X stands in for Q_dir: read as an N x R block in
         // X's own layout (R-major with ld ldx, or column-major with ld N)
@@ -411,17 +510,15 @@ rad_status rad_ts_time_column(rad_ts *S, int32_t nrep, void *hip_stream, double 
             // the operand for Q_dir (the state is advanced from level n into
             // the spare column buffer every time: the same work per launch)
             if (S->H->dtype == RAD_F64)
-                hipLaunchKernelGGL(k_ts_column<double>, dim3(grid_for(NR, kColThreads)), dim3(kColThreads), lds, s,
-                                   S->M, S->N, S->R, S->coef.p, S->T[S->cur].p, S->T[S->cur ^ 1].p, S->qabs.p,
-                                   S->qrad.p, (const double *)S->Y.p, (double *)S->X.p, S->ldx, rm,
-                                   (const double *)S->X.p, (const double *)nullptr, ldq, qorder,
-                                   S->H->d_perm.p, S->albedo, S->emiss, S->hb, S->newton);
+                launch_column<double>(S->M, S->N, S->R, S->coef.p, S->T[S->cur].p, S->T[S->cur ^ 1].p, S->qabs.p,
+                                      S->qrad.p, (const double *)S->Y.p, (double *)S->X.p, S->ldx, rm,
+                                      (const double *)S->X.p, (const double *)nullptr, ldq, qorder, S->H->d_perm.p,
+                                      S->albedo, S->emiss, S->hb, S->newton, s);
             else
-                hipLaunchKernelGGL(k_ts_column<float>, dim3(grid_for(NR, kColThreads)), dim3(kColThreads), lds, s,
-                                   S->M, S->N, S->R, S->coef.p, S->T[S->cur].p, S->T[S->cur ^ 1].p, S->qabs.p,
-                                   S->qrad.p, (const float *)S->Y.p, (float *)S->X.p, S->ldx, rm,
-                                   (const float *)S->X.p, (const float *)nullptr, ldq, qorder,
-                                   S->H->d_perm.p, S->albedo, S->emiss, S->hb, S->newton);
+                launch_column<float>(S->M, S->N, S->R, S->coef.p, S->T[S->cur].p, S->T[S->cur ^ 1].p, S->qabs.p,
+                                     S->qrad.p, (const float *)S->Y.p, (float *)S->X.p, S->ldx, rm,
+                                     (const float *)S->X.p, (const float *)nullptr, ldq, qorder, S->H->d_perm.p,
+                                     S->albedo, S->emiss, S->hb, S->newton, s);
         };
         launch();
         RAD_HIP(hipEventRecord(e0, s));

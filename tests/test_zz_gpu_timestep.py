@@ -71,10 +71,13 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("R", [3, 12])   # 2R = 6: column-major products; 2R = 24: matrix cores
-def test_stepper_matches_reference(bowl, R):
+# 2R = 6: column-major products; 2R = 24: matrix cores.  Up to 32 layers the
+# column kernel keeps the column in registers (instances for 16, 24, 32
+# layers); 40 layers take the LDS form.
+@pytest.mark.parametrize("R,layers", [(3, 20), (12, 20), (3, 12), (4, 32), (5, 40)])
+def test_stepper_matches_reference(bowl, R, layers):
     verts, faces, fac, F = bowl
-    z = ots.layer_depths(20, 0.5, 1.12)
+    z = ots.layer_depths(layers, 0.5, 1.12)
     n = 30
     Q = _levels(fac, R, n, seed=R)
     T0 = _initial(fac, R, z, seed=R + 1)
@@ -92,16 +95,20 @@ def test_stepper_matches_reference(bowl, R):
             assert _rel(got, want[r][name]) < 1e-9, (r, name)
 
 
-@pytest.mark.parametrize("R", [3, 8])
+# 40 layers to 1 m with a ratio of 1.05 (top layer 8 mm): with the 0.5 m,
+# 1.12 grid of the other cases 40 layers make the top layer 0.65 mm, and at
+# 0.3-day steps three Newton repeats from the old surface temperature then
+# diverge in the reference itself
+@pytest.mark.parametrize("R,layers,depth,ratio", [(3, 20, 0.5, 1.12), (8, 20, 0.5, 1.12), (3, 40, 1.0, 1.05)])
 @pytest.mark.parametrize("dt_days", [0.1, 0.3])
-def test_balanced_surface_matches_reference(bowl, dt_days, R):
+def test_balanced_surface_matches_reference(bowl, dt_days, R, layers, depth, ratio):
     """The balanced surface reading (radiation boundary condition at the new
     level, Newton on the surface row) at the long steps of a lunation, against
     the reference's second reading of the column step."""
     import functools
     verts, faces, fac, F = bowl
     dt = dt_days * 86400.0
-    z = ots.layer_depths(20, 0.5, 1.12)
+    z = ots.layer_depths(layers, depth, ratio)
     n = 24
     Q = _levels(fac, R, n, seed=30 + R)
     T0 = _initial(fac, R, z, seed=31 + R)
