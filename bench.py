@@ -641,20 +641,24 @@ def run_ts(args):
     el = np.deg2rad(rng.uniform(5.0, 30.0, R))
     az0 = rng.uniform(0.0, 2.0 * np.pi, R)
     dtype = torch.float64 if args.dtype == "f64" else torch.float32
-    Q = torch.empty((n_steps + 1, R, N), dtype=dtype, device="cuda:0")
+    # every level's direct insolation written by rad_insolation straight into
+    # the stepper's internal layout (tree order, scenarios contiguous)
+    from paper_2209_07632_amd.rad import ldr_of
+    ld = ldr_of(R)
+    Q = torch.zeros((n_steps + 1, N, ld), dtype=dtype, device="cuda:0")
     t0 = time.perf_counter()
     for lvl in range(n_steps + 1):
         az = az0 + 2.0 * np.pi * lvl / n_steps
         suns = np.column_stack([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)])
-        H.insolation(suns, flux=S, out=Q[lvl].t())
+        H.insolation(suns, flux=S, order="tree_rmajor", out=Q[lvl])
     torch.cuda.synchronize()
     log(f"cap N={N}: insolation of {n_steps + 1} levels x {R} scenarios in {time.perf_counter() - t0:.1f} s")
     TS = TimeStepper(H, z, k_cond, rhoc, dt, albedo, emiss, bottom_flux=0.0, R=R, surface="balanced", newton=3)
-    T0 = torch.full((M + 1, R, N), 250.0, dtype=torch.float64, device="cuda:0")
+    T0 = torch.full((M + 1, N, ld), 250.0, dtype=torch.float64, device="cuda:0")
 
     def lunation():
-        TS.init(T0, Q[0])
-        TS.step(Q[1:])
+        TS.init(T0, Q[0], order="tree_rmajor")
+        TS.step(Q[1:], order="tree_rmajor")
 
     for _ in range(args.warmup):
         lunation()
@@ -664,7 +668,7 @@ def run_ts(args):
         lunation()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
-    Ts = TS.read("T")[0]
+    Ts = TS.read("T", order="tree_rmajor")[0][:, :R]
     tmin, tmax = float(Ts.min()), float(Ts.max())
     # the two parts of a time step on their own: the 2R-column product and the column kernel
     X = torch.rand((N, 2 * R), dtype=dtype, device="cuda:0")

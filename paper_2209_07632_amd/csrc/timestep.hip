@@ -2,8 +2,10 @@
 // C-ABI of include/rad_timestep.h and its kernels.
 //
 // State layout (tree order, scenario fastest): element (t, r) of a per-facet
-// field at t R + r, node j of the columns at (j N + t) R + r, so that the
-// threads of a wave (consecutive (t, r)) touch consecutive addresses.  The
+// field at i = t R + r; the column nodes in blocks of 64 columns, node j of
+// column i at ((i / 64) (M + 1) + j) 64 + i % 64, so that the threads of a
+// wave (64 consecutive columns) read and write one contiguous run of
+// (M + 1) x 512 bytes (FP64) per step instead of M + 1 runs far apart.  The
 // 2R-column operand X and product Y of the terrain multiply hold band 1
 // (reflected sunlight) in columns [0, R) and band 2 (infrared) in [R, 2R):
 // R-major with ld = 2R rounded to 4 when 2R >= 16 (the matrix-core path),
@@ -28,6 +30,11 @@ __device__ inline int64_t user_index(int order, int64_t t, int64_t r, int64_t ld
     return r * ld + (int64_t)perm[t];
 }
 
+// Position of node j of column i in the column state (blocks of 64 columns).
+__device__ inline int64_t node_at(int j, int64_t i, int M) {
+    return ((i >> 6) * (M + 1) + j) * 64 + (i & 63);
+}
+
 // Position of (t, column c) in X / Y.
 __device__ inline int64_t op_index(bool rmajor, int64_t t, int64_t c, int64_t ldx, int64_t N) {
     return rmajor ? t * ldx + c : c * N + t;
@@ -41,7 +48,7 @@ __global__ void k_ts_init(int M, int64_t N, int64_t R, const double *T0, int64_t
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NR; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t t = i / R, r = i - t * R;
         const int64_t u = user_index(order, t, r, ldt, perm);
-        for (int j = 0; j <= M; ++j) Ts[(int64_t)j * NR + i] = T0[(int64_t)j * blk + u];
+        for (int j = 0; j <= M; ++j) Ts[node_at(j, i, M)] = T0[(int64_t)j * blk + u];
         const double qa = (1.0 - albedo) * (double)qd0[user_index(order, t, r, ldq, perm)] + h0;
         qabs[i] = qa;
         qrad[i] = qa;
@@ -100,9 +107,9 @@ __global__ void __launch_bounds__(kColThreads) k_ts_column(int M, int64_t N, int
         const double qa_new = (1.0 - albedo) * (qdir + qrefl) + emiss * qir;
         const double qa_old = qabs[i];
         // bottom-up: r_j (explicit half of the step), d_j = (r_j - u_j d_{j+1}) / beta_j
-        double t_below = 0.0, t_here = Tin[(int64_t)M * NR + i], d = 0.0;
+        double t_below = 0.0, t_here = Tin[node_at(M, i, M)], d = 0.0;
         for (int j = M; j >= 1; --j) {
-            const double t_above = Tin[(int64_t)(j - 1) * NR + i];
+            const double t_above = Tin[node_at(j - 1, i, M)];
             double rj = cap[j] * t_here + 0.5 * g[j] * (t_above - t_here);
             if (j < M)
                 rj += 0.5 * g[j + 1] * (t_below - t_here) + 0.5 * g[j + 1] * d;
@@ -133,11 +140,11 @@ __global__ void __launch_bounds__(kColThreads) k_ts_column(int M, int64_t N, int
             }
             tn = u;
         }
-        Tout[i] = tn;
+        Tout[node_at(0, i, M)] = tn;
         const double ts = tn;
         for (int j = 1; j <= M; ++j) {
             tn = dl[(j - 1) * kColThreads] - e[j] * tn;
-            Tout[(int64_t)j * NR + i] = tn;
+            Tout[node_at(j, i, M)] = tn;
         }
         qabs[i] = qa_new;
         const double qr = es * ts * ts * ts * ts;
@@ -171,7 +178,7 @@ __global__ void __launch_bounds__(kRegThreads) k_ts_column_r(int M, int64_t N, i
         double tv[kMax + 2], dv[kMax];   // tv[kMax + 1]: never read (pads the j + 1 below)
 #pragma unroll
         for (int j = 0; j <= kMax; ++j)
-            if (j <= M) tv[j] = Tin[(int64_t)j * NR + i];
+            if (j <= M) tv[j] = Tin[node_at(j, i, M)];
         const int64_t t = i / R, r = i - t * R;
         const int64_t y1 = op_index(rmajor, t, r, ldx, N), y2 = op_index(rmajor, t, R + r, ldx, N);
         const double qrefl = (double)Y[y1], qir = (double)Y[y2];
@@ -208,13 +215,13 @@ __global__ void __launch_bounds__(kRegThreads) k_ts_column_r(int M, int64_t N, i
             }
             tn = u;
         }
-        Tout[i] = tn;
+        Tout[node_at(0, i, M)] = tn;
         const double ts = tn;
 #pragma unroll
         for (int j = 1; j <= kMax; ++j) {
             if (j <= M) {
                 tn = dv[j - 1] - e[j] * tn;
-                Tout[(int64_t)j * NR + i] = tn;
+                Tout[node_at(j, i, M)] = tn;
             }
         }
         qabs[i] = qa_new;
@@ -238,7 +245,7 @@ __global__ void k_ts_read(int field, int M, int64_t N, int64_t R, const double *
         const int64_t u = user_index(order, t, r, ld, perm);
         switch (field) {
             case RAD_TS_T:
-                for (int j = 0; j <= M; ++j) out[(int64_t)j * blk + u] = Ts[(int64_t)j * NR + i];
+                for (int j = 0; j <= M; ++j) out[(int64_t)j * blk + u] = Ts[node_at(j, i, M)];
                 break;
             case RAD_TS_QABS: out[u] = qabs[i]; break;
             case RAD_TS_QRAD: out[u] = qrad[i]; break;
@@ -401,8 +408,9 @@ rad_status rad_ts_create(const rad_hmat *H, const rad_ts_params *p, int64_t R, r
         const size_t es = H->dtype == RAD_F64 ? 8 : 4;
         const size_t nr = (size_t)S->N * (size_t)R;
         S->coef.upload(column_coefficients(*p));
-        S->T[0].alloc((size_t)(M + 1) * nr);
-        S->T[1].alloc((size_t)(M + 1) * nr);
+        const size_t nr64 = (nr + 63) / 64 * 64;   // the column state in whole blocks of 64 columns
+        S->T[0].alloc((size_t)(M + 1) * nr64);
+        S->T[1].alloc((size_t)(M + 1) * nr64);
         S->qabs.alloc(nr);
         S->qrad.alloc(nr);
         const size_t opbytes = (size_t)S->N * (size_t)(S->rmajor ? S->ldx : 2 * R) * es;

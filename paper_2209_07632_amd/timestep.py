@@ -2,9 +2,13 @@
 
 Argument marshalling only: the flux products, the absorbed-flux update and
 the Crank-Nicolson column steps of Algorithm 6 run in librad's HIP kernels.
-Tensors use the caller's facet order: a block of R scenarios is an (R, N)
-contiguous tensor (column-major N x R with ld = N), the column temperatures
-(M + 1, R, N), a run of direct-insolation levels (n_steps, R, N).
+Tensors use the caller's facet order by default: a block of R scenarios is
+an (R, N) contiguous tensor (column-major N x R with ld = N), the column
+temperatures (M + 1, R, N), a run of direct-insolation levels (n_steps, R, N).
+With order="tree_rmajor" they use the library's internal layout instead
+(rows in tree order, scenarios contiguous, ld = ldr_of(R)): blocks (N, ldr),
+temperatures (M + 1, N, ldr), levels (n_steps, N, ldr), as rad_insolation
+writes them with the same order.
 """
 from __future__ import annotations
 
@@ -12,7 +16,9 @@ import ctypes
 
 import numpy as np
 
-from .rad import _check, _stream_handle, _torch, load
+from .rad import _check, _stream_handle, _torch, ldr_of, load
+
+_ORDERS = {"original": 0, "tree_rmajor": 2}
 
 RAD_TS_T, RAD_TS_QABS, RAD_TS_QREFL, RAD_TS_QIR, RAD_TS_QRAD = range(5)
 _FIELDS = {"T": RAD_TS_T, "Q_abs": RAD_TS_QABS, "Q_refl": RAD_TS_QREFL, "Q_ir": RAD_TS_QIR, "Q_rad": RAD_TS_QRAD}
@@ -76,24 +82,36 @@ class TimeStepper:
     def _flux_dtype(self):
         return self.H.torch_dtype
 
-    def init(self, T0, Qdir0, H0=0.0):
-        torch = _torch()
-        pt = _block(T0, (self.M + 1, self.R, self.N), torch.float64, "T0")
-        pq = _block(Qdir0, (self.R, self.N), self._flux_dtype(), "Qdir0")
-        _check(_lib().rad_ts_init(self._h, pt, self.N, pq, self.N, float(H0), 0, _stream_handle()))
+    def _layout(self, order):
+        """(C-ABI order, block shape, leading dimension) of one N x R block."""
+        if order not in _ORDERS:
+            raise ValueError(f"order must be one of {sorted(_ORDERS)}")
+        if order == "tree_rmajor":
+            ld = ldr_of(self.R)
+            return _ORDERS[order], (self.N, ld), ld
+        return _ORDERS[order], (self.R, self.N), self.N
 
-    def step(self, Qdir):
-        """Advance len(Qdir) levels; Qdir is (n_steps, R, N) in the matrix precision."""
+    def init(self, T0, Qdir0, H0=0.0, order="original"):
+        torch = _torch()
+        o, blk, ld = self._layout(order)
+        pt = _block(T0, (self.M + 1,) + blk, torch.float64, "T0")
+        pq = _block(Qdir0, blk, self._flux_dtype(), "Qdir0")
+        _check(_lib().rad_ts_init(self._h, pt, ld, pq, ld, float(H0), o, _stream_handle()))
+
+    def step(self, Qdir, order="original"):
+        """Advance len(Qdir) levels; Qdir is (n_steps,) + one block, in the matrix precision."""
+        o, blk, ld = self._layout(order)
         n = int(Qdir.shape[0])
-        pq = _block(Qdir, (n, self.R, self.N), self._flux_dtype(), "Qdir")
-        _check(_lib().rad_ts_step(self._h, n, pq, self.N, self.R * self.N, 0, _stream_handle()))
+        pq = _block(Qdir, (n,) + blk, self._flux_dtype(), "Qdir")
+        _check(_lib().rad_ts_step(self._h, n, pq, ld, blk[0] * blk[1], o, _stream_handle()))
 
-    def read(self, field):
-        """FP64 copy of one field: (M + 1, R, N) for "T", else (R, N)."""
+    def read(self, field, order="original"):
+        """FP64 copy of one field: M + 1 blocks for "T", else one block."""
         torch = _torch()
-        shape = (self.M + 1, self.R, self.N) if field == "T" else (self.R, self.N)
+        o, blk, ld = self._layout(order)
+        shape = (self.M + 1,) + blk if field == "T" else blk
         out = torch.empty(shape, dtype=torch.float64, device=f"cuda:{self.H.device}")
-        _check(_lib().rad_ts_read(self._h, _FIELDS[field], ctypes.c_void_p(out.data_ptr()), self.N, 0,
+        _check(_lib().rad_ts_read(self._h, _FIELDS[field], ctypes.c_void_p(out.data_ptr()), ld, o,
                                   _stream_handle()))
         return out
 

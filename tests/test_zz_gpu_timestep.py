@@ -124,6 +124,42 @@ def test_balanced_surface_matches_reference(bowl, dt_days, R, layers, depth, rat
             assert _rel(S.read(name).cpu().numpy()[r], want[r][name]) < 1e-9, (r, name)
 
 
+def test_internal_layout_equals_caller_order(bowl):
+    """The same run with every block in the library's internal layout (tree
+    order, scenarios contiguous, as rad_insolation writes them) gives the
+    same state bit for bit as with blocks in the caller's facet order."""
+    from paper_2209_07632_amd.rad import ldr_of
+    verts, faces, fac, F = bowl
+    R, n = 12, 10
+    z = ots.layer_depths(20, 0.5, 1.12)
+    Q = _levels(fac, R, n, seed=77)
+    T0 = _initial(fac, R, z, seed=78)
+    H, S = _stepper(verts, faces, R, z, dt=0.1 * 86400.0, surface="balanced", newton=3)
+    S.init(torch.from_numpy(T0).to(DEV), torch.from_numpy(Q[0]).to(DEV), H0=H0)
+    S.step(torch.from_numpy(Q[1:]).to(DEV).contiguous())
+    want = S.read("T").cpu().numpy()
+    perm = H.perm()
+    ld = ldr_of(R)
+
+    def internal(blocks):                      # (..., R, N) caller order -> (..., N, ld)
+        out = np.zeros(blocks.shape[:-2] + (fac.N, ld))
+        out[..., :R] = np.swapaxes(blocks[..., perm], -1, -2)
+        return torch.from_numpy(out).to(DEV).contiguous()
+
+    from paper_2209_07632_amd.timestep import TimeStepper
+    S2 = TimeStepper(H, z, K, RHOC, 0.1 * 86400.0, ALBEDO, EMISS, bottom_flux=HB, R=R, surface="balanced", newton=3)
+    S2.init(internal(T0), internal(Q[0]), H0=H0, order="tree_rmajor")
+    S2.step(internal(Q[1:]), order="tree_rmajor")
+    got = S2.read("T", order="tree_rmajor").cpu().numpy()[..., :R]
+    back = np.empty_like(want)
+    back[..., perm] = np.swapaxes(got, -1, -2)
+    np.testing.assert_array_equal(back, want)
+    for name in ("Q_abs", "Q_rad"):
+        g = S2.read(name, order="tree_rmajor").cpu().numpy()[:, :R]
+        w = S.read(name).cpu().numpy()
+        np.testing.assert_array_equal(g.T, w[:, perm])
+
+
 def test_level_zero_state(bowl):
     verts, faces, fac, F = bowl
     R = 2
