@@ -722,7 +722,7 @@ def main():
     ap.add_argument("--inner", type=int, default=3)
     ap.add_argument("--cpu-rows", type=int, default=6)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--tol", type=float, default=1e-3)
@@ -820,9 +820,14 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup done, iters {int(info['total_iters'])}; ms/step with graphs {mode_ms[True]:.3f}, "
         f"direct launches {mode_ms[False]:.3f}: use_graph={use_graph}")
-    # (Python's collector is paused over the timed steps, as timeit does)
+    # (Python's collector is paused over the timed steps, as timeit does; two
+    # untimed steps right before the clock starts keep the GPU from idling
+    # between the log line and the timed region)
     gc.collect()
     gc.disable()
+    for _ in range(2):
+        info = step()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         info = step()
