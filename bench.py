@@ -107,6 +107,27 @@ def single_rhs_leg(G, cols, albedo, rtol):
             "operator_bytes": op_bytes}
 
 
+def expansion_bytes(st, N, R, s_bytes):
+    """Algorithmic bytes of one launch of the expansion kernel over R columns:
+    E, B_old read and B_new written (3 N R s), the U' rows and near-field values
+    once, T read once (sum_rank x R)."""
+    return (3.0 * N * R * s_bytes + st["lowrank_row_elems"] * s_bytes + st["bytes_dense"] + st["bytes_csr"]
+            + st["sum_rank"] * R * s_bytes)
+
+
+def calib_copy():
+    """A plain device copy of known size (1 GiB read, 1 GiB written, three
+    times), for scaling hardware byte counters taken in the same run."""
+    import torch
+
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("calibration copy: 3 x 1 GiB read + 1 GiB written")
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -498,7 +519,8 @@ def run_batch(args):
 
 def run_terrain_phases(args):
     """Kernel phases (projections, split-K sum, expansion with the fused
-    Jacobi update) of the terrain operator at R = 256, 16-bit and FP32: a DEM
+    Jacobi update) of the terrain operator at R = 256, 16-bit and FP32, and
+    its single-RHS FP32 product: a DEM
     of --dem-n x --dem-n cells of 10 m (the 131k terrain's generator, leaf
     128, ray-cast visibility, dense near field, BF16 copy).  With
     --save-operator the operator is built and written to that file and the
@@ -521,6 +543,7 @@ def run_terrain_phases(args):
             H.save(args.save_operator)
             log(f"built N={H.N} in {build_s:.1f} s, saved to {args.save_operator}")
             return
+    dem_n = int(round(np.sqrt(H.N / 2)))  # two triangles per cell
     X = torch.rand((H.N, 256), dtype=torch.float32, device="cuda:0")
     for _ in range(2):
         H.matvec(X, lowp=True)
@@ -528,11 +551,100 @@ def run_terrain_phases(args):
     ph16 = H.time_phases(256, nrep=max(args.steps, 1), lowp=True)
     ph32 = H.time_phases(256, nrep=max(args.steps // 2, 1))
     st = H.stats()
+    # the single-RHS FP32 product (k_proj / k_proj_wide + k_tile_gemv)
+    x1 = X[:, 0].contiguous()
+    y1 = torch.empty_like(x1)
+    for _ in range(3):
+        H.matvec(x1, out=y1, order="tree")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(max(args.steps, 1)):
+        H.matvec(x1, out=y1, order="tree")
+    ev1.record()
+    torch.cuda.synchronize()
+    mv1 = ev0.elapsed_time(ev1) / max(args.steps, 1)
+    if args.calib_copy:
+        calib_copy()
     print(json.dumps({"metric": "terrain product phases (ms per launch, R = 256)", "value": sum(ph16), "unit": "ms",
                       "higher_is_better": False, "n_gpus": 1, "dtype": "bf16+f32", "data": "synthetic",
-                      "config": {"workload": f"DEM {args.dem_n}x{args.dem_n} cells of 10 m, N={H.N}, leaf 128, "
+                      "config": {"workload": f"DEM {dem_n}x{dem_n} cells of 10 m, N={H.N}, leaf 128, "
                                              f"tol {args.tol}", "N": H.N},
-                      "phases_16bit_ms": ph16, "phases_fp32_ms": ph32, "build_seconds": build_s,
+                      "phases_16bit_ms": ph16, "phases_fp32_ms": ph32, "single_rhs_fp32_ms": mv1,
+                      "single_rhs_fp32_gbs": (st["bytes_dense"] + st["bytes_csr"] + st["bytes_lowrank"] + 2 * H.N * 4)
+                      / (mv1 * 1e-3) / 1e9,
+                      "build_seconds": build_s,
+                      "hmat_blocks": block_counts(st)}), flush=True)
+
+
+def run_cap_phases(args):
+    """Kernels of one Jacobi iteration on the 40k cap's operator at --tol and
+    --dtype with --rhs columns (projections, split-K sum, expansion with the
+    fused Jacobi update, each timed alone), the whole product and the
+    single-RHS product, on random operands in the solver's layout.  With
+    --save-operator the operator is built, written there and the run ends;
+    with --load-operator it is read back, which keeps the build (many small
+    rank-search launches) out of a profiled run."""
+    import torch
+    from paper_2209_07632_amd import HMatrix
+    from paper_2209_07632_amd.rad import ldr_of
+    from synth import CAP_LARGE, cap_mesh
+
+    R = args.rhs
+    if args.load_operator:
+        H = HMatrix.load(args.load_operator, max_rhs=R)
+        build_s = None
+    else:
+        verts, faces = cap_mesh(CAP_LARGE)
+        t0 = time.perf_counter()
+        H = HMatrix(verts, faces, tol=args.tol, storage=args.dtype, nearfield=args.nearfield, max_rhs=R)
+        build_s = time.perf_counter() - t0
+        if args.save_operator:
+            H.save(args.save_operator)
+            log(f"built N={H.N} in {build_s:.1f} s, saved to {args.save_operator}")
+            return
+    N = H.N
+    st = H.stats()
+    s_bytes = 8 if H.torch_dtype == torch.float64 else 4
+    if args.tn:
+        H.set_config(R, args.tn, 0, 1)
+        tune = dict(H.get_config(R), ms=0.0)
+    else:
+        tune = H.autotune(R, nrep=5)
+    X = torch.rand((N, ldr_of(R)), dtype=H.torch_dtype, device="cuda:0")
+    Y = torch.zeros_like(X)
+    nrep = max(args.steps, 1)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(nrep):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / nrep
+
+    mv_ms = timed(lambda: H.matvec(X, out=Y, order="tree_rmajor", R=R))
+    x1 = X[:, 0].contiguous()
+    y1 = torch.empty_like(x1)
+    mv1_ms = timed(lambda: H.matvec(x1, out=y1, order="tree"))
+    ph = H.time_phases(R, nrep=nrep)
+    op_bytes = st["bytes_dense"] + st["bytes_csr"] + st["bytes_lowrank"]
+    p2_bytes = expansion_bytes(st, N, R, s_bytes)
+    if args.calib_copy:
+        calib_copy()
+    print(json.dumps({"metric": "cap operator kernels (ms per launch)", "value": ph[2], "unit": "ms",
+                      "higher_is_better": False, "n_gpus": 1, "dtype": args.dtype if not args.load_operator
+                      else ("f64" if s_bytes == 8 else "f32"), "data": "synthetic",
+                      "config": {"workload": f"spherical-cap crater N={N}, {R} columns, operator "
+                                             f"{'read from a file' if args.load_operator else f'tol {args.tol}'}",
+                                 "N": N, "rhs": R},
+                      "phase_ms": {"projections": ph[0], "split_k_sum": ph[1], "expansion_jacobi": ph[2]},
+                      "expansion_bytes": p2_bytes, "expansion_gbs": p2_bytes / (ph[2] * 1e-3) / 1e9,
+                      "hmatvec_ms": mv_ms, "hmatvec_gbs": (op_bytes + 2 * N * R * s_bytes) / (mv_ms * 1e-3) / 1e9,
+                      "single_rhs_ms": mv1_ms, "single_rhs_gbs": (op_bytes + 2 * N * s_bytes) / (mv1_ms * 1e-3) / 1e9,
+                      "operator_bytes": op_bytes, "autotune": tune, "build_seconds": build_s,
                       "hmat_blocks": block_counts(st)}), flush=True)
 
 
@@ -713,7 +825,7 @@ def run_ts(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="cap40k", choices=["cap40k", "dem131k", "batch64", "warm40k", "ts40k", "terrain_phases"])
+    ap.add_argument("--workload", default="cap40k", choices=["cap40k", "dem131k", "batch64", "warm40k", "ts40k", "terrain_phases", "cap_phases"])
     ap.add_argument("--mlp", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--instances", type=int, default=64)
@@ -735,8 +847,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="the cap workload alone (no eps sweep, FP64 leg or terrain keys)")
     ap.add_argument("--dem-n", type=int, default=128, help="terrain_phases: DEM cells per side")
-    ap.add_argument("--save-operator", default=None, help="terrain_phases: build, write the operator there, stop")
-    ap.add_argument("--load-operator", default=None, help="terrain_phases: read the operator from this file")
+    ap.add_argument("--save-operator", default=None, help="terrain_phases, cap_phases: build, write the operator there, stop")
+    ap.add_argument("--load-operator", default=None, help="terrain_phases, cap_phases: read the operator from this file")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it"}))
@@ -747,6 +859,8 @@ def main():
         return run_ts(args)
     if args.workload == "terrain_phases":
         return run_terrain_phases(args)
+    if args.workload == "cap_phases":
+        return run_cap_phases(args)
     if args.workload == "batch64":
         if args.nearfield == "csr":
             args.nearfield = "dense"   # terrain near field: dense panels run far faster than CSR slices
@@ -868,8 +982,7 @@ def main():
     # flops 2 R (sum_LR m k + nnz_near); bytes: E, B_old read and B_new written
     # (3 N R s), the U' rows and near-field values once, T read once (sum_rank x R)
     p2_flops = 2.0 * R * (st["lowrank_row_elems"] + st["nnz_near"])
-    p2_bytes = (3.0 * N * R * s_bytes + st["lowrank_row_elems"] * s_bytes + st["bytes_dense"] + st["bytes_csr"]
-                + st["sum_rank"] * R * s_bytes)
+    p2_bytes = expansion_bytes(st, N, R, s_bytes)
     p1_flops = 2.0 * R * st["lowrank_col_elems"]
     p2_tf = p2_flops / (ph[2] * 1e-3) / 1e12
     p2_gbs = p2_bytes / (ph[2] * 1e-3) / 1e9
@@ -891,13 +1004,7 @@ def main():
     log(f"phases ms {ph}: expansion {p2_tf:.2f} TFLOP/s {p2_gbs:.0f} GB/s (I={intensity:.1f}), "
         f"projections {p1_tf:.2f} TFLOP/s")
     if args.calib_copy:
-        # plain copy of known size for scaling hardware byte counters
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("calibration copy: 3 x 1 GiB read + 1 GiB written")
+        calib_copy()
 
     result = {
         "metric": "sun-RHS radiosity solves/s + H-matvec HBM GB/s at 1e-3 rel err vs plain FP64",

@@ -386,14 +386,17 @@ struct P1Stage {
 
 // Partial projections of up to two work items that share a facet chunk
 // (consecutive 64-row slabs of V_J^T): the X chunk is staged once for 128 rows.
+// A pair whose slabs have no other work item (direct[pair] = their first T
+// row) writes its rows of T itself; the others write partial tiles.
 template <class T, int TN>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<T, TN>, 8)))
-k_proj_mm(const ProjGroup *groups, const P1Work *work, const int32_t *pairs,
-                                                  const T *vals, const T *X, int64_t ldr, int R, T *part,
+k_proj_mm(const ProjGroup *groups, const P1Work *work, const int32_t *pairs, const int32_t *direct,
+                                                  const T *vals, const T *X, int64_t ldr, int R, T *part, T *Tb,
                                                   int rtiles, const int32_t *stop) {
     if (stop && *stop) return;
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
     const int p0 = pairs[2 * (wi / rtiles)], p1 = pairs[2 * (wi / rtiles) + 1];
+    const int drow = direct[wi / rtiles];
     const P1Work wk = work[p0];
     const ProjGroup g = groups[wk.group];
     const int r0 = (wi % rtiles) * TN;
@@ -430,9 +433,24 @@ k_proj_mm(const ProjGroup *groups, const P1Work *work, const int32_t *pairs,
         case 7: reduce(std::integral_constant<int, 7>{}); break;
         default: reduce(std::integral_constant<int, 8>{}); break;
     }
+    const int lr = lane & 15, lk = lane >> 4;
+    if (drow >= 0) {
+        // rows [0, rows) are T rows drow.. (the pair's slabs are consecutive)
+        T *out = Tb + (int64_t)drow * ldr;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < TN / 64; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = i * 16 + Mfma<T>::row(lk, v);
+                    const int col = r0 + w * (TN / 4) + j * 16 + lr;
+                    if (row < rows && col < R) out[(int64_t)row * ldr + col] = tile.acc[i][j][v];
+                }
+        return;
+    }
     T *out0 = part + (int64_t)wk.part * TM * ldr;
     T *out1 = p1 >= 0 ? part + (int64_t)work[p1].part * TM * ldr : nullptr;
-    const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
@@ -795,12 +813,14 @@ void proj_mm_tn(const rad_hmat *H, const T *X, int64_t ldr, int R, hipStream_t s
     unsigned rtiles = (unsigned)((R + TN - 1) / TN);
     if (H->n_p1work > 0) {
         hipLaunchKernelGGL((k_proj_mm<T, TN>), dim3(H->n_p1pairs * rtiles), dim3(256), 0, s, H->d_groups.p,
-                           H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const T *)H->d_vals.p, X, ldr, R,
-                           (T *)H->w_part.p, (int)rtiles, stop);
+                           H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const int32_t *)H->d_p1direct.p,
+                           (const T *)H->d_vals.p, X, ldr, R, (T *)H->w_part.p, (T *)H->w_t.p, (int)rtiles, stop);
         RAD_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_proj_reduce<T>, reduce_grid(H->n_p1red, R), dim3(256), 0, s, H->d_p1red.p,
-                           (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p, stop);
-        RAD_HIP(hipGetLastError());
+        if (H->n_p1red_multi > 0) {
+            hipLaunchKernelGGL(k_proj_reduce<T>, reduce_grid(H->n_p1red_multi, R), dim3(256), 0, s,
+                               H->d_p1red_multi.p, (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p, stop);
+            RAD_HIP(hipGetLastError());
+        }
     }
 }
 
@@ -943,17 +963,20 @@ void time_phases_t(const rad_hmat *H, int R, int nrep, hipStream_t s, double *ms
         ms[0] = timed([&] {
             if (tn1 == 64)
                 hipLaunchKernelGGL((k_proj_mm<T, 64>), dim3(H->n_p1pairs * rtiles), dim3(256), 0, s, H->d_groups.p,
-                                   H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const T *)H->d_vals.p, X, ldr,
-                                   R, (T *)H->w_part.p, (int)rtiles, nullptr);
+                                   H->d_p1work.p, (const int32_t *)H->d_p1pairs.p,
+                                   (const int32_t *)H->d_p1direct.p, (const T *)H->d_vals.p, X, ldr, R,
+                                   (T *)H->w_part.p, (T *)H->w_t.p, (int)rtiles, nullptr);
             else
                 hipLaunchKernelGGL((k_proj_mm<T, 128>), dim3(H->n_p1pairs * rtiles), dim3(256), 0, s, H->d_groups.p,
-                                   H->d_p1work.p, (const int32_t *)H->d_p1pairs.p, (const T *)H->d_vals.p, X, ldr,
-                                   R, (T *)H->w_part.p, (int)rtiles, nullptr);
+                                   H->d_p1work.p, (const int32_t *)H->d_p1pairs.p,
+                                   (const int32_t *)H->d_p1direct.p, (const T *)H->d_vals.p, X, ldr, R,
+                                   (T *)H->w_part.p, (T *)H->w_t.p, (int)rtiles, nullptr);
         });
-        ms[1] = timed([&] {
-            hipLaunchKernelGGL(k_proj_reduce<T>, reduce_grid(H->n_p1red, R), dim3(256), 0, s,
-                               H->d_p1red.p, (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p, nullptr);
-        });
+        if (H->n_p1red_multi > 0)
+            ms[1] = timed([&] {
+                hipLaunchKernelGGL(k_proj_reduce<T>, reduce_grid(H->n_p1red_multi, R), dim3(256), 0, s,
+                                   H->d_p1red_multi.p, (const T *)H->w_part.p, ldr, R, (T *)H->w_t.p, nullptr);
+            });
     }
     ms[2] = timed([&] {
         if (c.tn == 64)

@@ -347,6 +347,12 @@ struct rad_hmat {
     rad::DevBuf<int32_t> d_tile_order, d_queue;
     rad::DevBuf<int32_t> d_p1pairs;  // phase-1 work items taken two at a time (second -1 if single)
     int32_t n_p1pairs = 0;
+    // per pair: the T row its slabs start at when each slab is reduced by that
+    // one work item (the kernel then writes T itself), else -1; and the slabs
+    // of several work items, which the split-K sum of the FP32/FP64 path adds
+    rad::DevBuf<int32_t> d_p1direct;
+    rad::DevBuf<rad::P1Red> d_p1red_multi;
+    int32_t n_p1red_multi = 0;
     // wide 16-bit expansion: first tiles of consecutive tile pairs with identical
     // operand-row lists (one 128-row workgroup each), and the remaining tiles
     rad::DevBuf<int32_t> d_wpairs, d_wsingles;

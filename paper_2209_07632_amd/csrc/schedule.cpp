@@ -70,6 +70,31 @@ void mm_prepare_schedule(rad_hmat *H) {
     }
     H->n_p1pairs = (int32_t)(pairs.size() / 2);
     H->d_p1pairs.upload(pairs);
+    // slabs that one work item reduces alone are written straight into T by
+    // it (both slabs of a pair, or neither); the split-K sum takes the rest
+    {
+        std::vector<P1Red> rl = H->d_p1red.download((size_t)H->n_p1red);
+        std::vector<int32_t> lone_row(std::max(H->n_parts, 1), -1);  // T row of a part alone in its slab
+        for (const P1Red &r : rl)
+            if (r.part_count == 1) lone_row[r.part_begin] = r.t_row0;
+        std::vector<char> direct_part(std::max(H->n_parts, 1), 0);
+        std::vector<int32_t> direct(H->n_p1pairs, -1);
+        for (int32_t q = 0; q < H->n_p1pairs; ++q) {
+            const int32_t p0 = pairs[2 * q], p1 = pairs[2 * q + 1];
+            const int32_t d0 = lone_row[wl[p0].part];
+            if (d0 < 0) continue;
+            if (p1 >= 0 && lone_row[wl[p1].part] != d0 + mm_part_rows()) continue;
+            direct[q] = d0;
+            direct_part[wl[p0].part] = 1;
+            if (p1 >= 0) direct_part[wl[p1].part] = 1;
+        }
+        std::vector<P1Red> multi;
+        for (const P1Red &r : rl)
+            if (!(r.part_count == 1 && direct_part[r.part_begin])) multi.push_back(r);
+        H->d_p1direct.upload(direct);
+        H->n_p1red_multi = (int32_t)multi.size();
+        if (!multi.empty()) H->d_p1red_multi.upload(multi);
+    }
     // single-RHS projections of long column nodes: one workgroup per V column
     {
         std::vector<int32_t> items;
