@@ -41,24 +41,50 @@ __global__ void k_scatter(const int32_t *perm, const T *src, int64_t lds, T *dst
     }
 }
 
-// phase 1: one wave per stacked V column, lanes stride the rows of X_J
-// (groups with n >= wide_n are left to k_proj_wide)
+// phase 1 for column nodes below kProjWideN facets: one wave per stacked V
+// column, from a list of (group, column) items, four items per workgroup.
+// Lanes take VW consecutive facets with one 16-byte load of V (columns start
+// on 8-value boundaries), up to four loads in flight; X_J, which starts at
+// any facet, is read value by value (the waves of one node share it in
+// cache).  Lane sums meet by a fixed butterfly.
 template <class T>
-__global__ void __launch_bounds__(256) k_proj(const ProjGroup *groups, const T *vals, const T *X, int64_t ldx,
-                                               T *Tb, int32_t t_ld, const int32_t *stop, int32_t wide_n) {
+__global__ void __launch_bounds__(256) k_proj_cols(const int32_t *items, int32_t n_items, const ProjGroup *groups,
+                                                    const T *vals, const T *X, int64_t ldx, T *Tb, int32_t t_ld,
+                                                    const int32_t *stop) {
     if (stop && *stop) return;
-    const ProjGroup g = groups[blockIdx.x];
-    if (g.n >= wide_n) return;
+    constexpr int VW = 16 / sizeof(T);
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type vec_t;
+    const int it = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (it >= n_items) return;
+    const int lane = threadIdx.x & 63;
+    const ProjGroup g = groups[items[2 * it]];
+    const int kk = items[2 * it + 1];
     const int64_t r = blockIdx.z;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const T *x = X + g.j0 + r * ldx;
-    for (int kk = blockIdx.y * 4 + w; kk < g.ktot; kk += gridDim.y * 4) {
-        const T *v = vals + g.v_off + (int64_t)kk * g.ld;
-        T acc = 0;
-        for (int j = lane; j < g.n; j += 64) acc += v[j] * x[j];
-        acc = wsum(acc);
-        if (lane == 0) Tb[g.t_off + kk + r * t_ld] = acc;
+    const T *v = vals + g.v_off + (int64_t)kk * g.ld;
+    constexpr int STEP = 64 * VW;
+    T acc = 0;
+    int j = VW * lane;
+    for (; j + 3 * STEP + VW <= g.n; j += 4 * STEP) {
+        vec_t a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = *(const vec_t *)(v + j + q * STEP);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T *av = (const T *)&a[q];
+#pragma unroll
+            for (int u = 0; u < VW; ++u) acc += av[u] * x[j + q * STEP + u];
+        }
     }
+    for (; j + VW <= g.n; j += STEP) {
+        const vec_t a = *(const vec_t *)(v + j);
+        const T *av = (const T *)&a;
+#pragma unroll
+        for (int u = 0; u < VW; ++u) acc += av[u] * x[j + u];
+    }
+    for (int u = 0; j + u < g.n && u < VW; ++u) acc += v[j + u] * x[j + u];
+    acc = wsum(acc);
+    if (lane == 0) Tb[g.t_off + kk + r * t_ld] = acc;
 }
 
 // phase 2: one workgroup per (64-row tile, right-hand side).  The packed panel
@@ -291,11 +317,10 @@ void apply_t(const rad_hmat *H, const T *X, int64_t ldx, T *Y, int64_t ldy, int6
              const T *E = nullptr, const T *rho = nullptr, T rho_s = 0, double *partial = nullptr,
              double *epartial = nullptr, const int32_t *stop = nullptr, bool segmented = true) {
     if (H->n_groups > 0) {
-        int maxk = 0;
-        for (const ProjGroup &g : H->h_groups) maxk = std::max(maxk, g.ktot);
-        dim3 grid(H->n_groups, std::max(1, std::min(64, (maxk + 3) / 4)), (unsigned)R);
-        hipLaunchKernelGGL(k_proj<T>, grid, dim3(256), 0, s, H->d_groups.p, (const T *)H->d_vals.p, X, ldx, Tb,
-                           H->t_ld, stop, H->n_pwide > 0 ? kProjWideN : INT32_MAX);
+        if (H->n_pcols > 0)
+            hipLaunchKernelGGL(k_proj_cols<T>, dim3((unsigned)((H->n_pcols + 3) / 4), 1, (unsigned)R), dim3(256), 0,
+                               s, H->d_pcols.p, H->n_pcols, H->d_groups.p, (const T *)H->d_vals.p, X, ldx, Tb,
+                               H->t_ld, stop);
         if (H->n_pwide > 0)
             hipLaunchKernelGGL(k_proj_wide<T>, dim3(H->n_pwide, 1, (unsigned)R), dim3(256), 0, s, H->d_pwide.p,
                                H->d_groups.p, (const T *)H->d_vals.p, X, ldx, Tb, H->t_ld, stop);

@@ -361,13 +361,15 @@ struct rad_hmat {
     // [gseg_of_tile[t], gseg_of_tile[t+1]), and the segments' partial row sums
     rad::DevBuf<int32_t> d_pwide;        // (group, column) items of k_proj_wide (groups of n >= kProjWideN)
     int32_t n_pwide = 0;
+    rad::DevBuf<int32_t> d_pcols;        // (group, column) items of k_proj_cols (the other groups)
+    int32_t n_pcols = 0;
     rad::DevBuf<rad::GemvSeg> d_gsegs;
     rad::DevBuf<int32_t> d_gseg_of_tile;
     int32_t n_gsegs = 0;
     rad::DevBuf<unsigned char> w_gpart;
     rad::DevBuf<rad::WideSeg> d_wsegs;    // the pairs' reduction segments (index = partial slot)
     int32_t n_wsegs = 0;
-    rad::DevBuf<int32_t> d_wseg_order;    // their launch table (xcd_launch_order)
+    rad::DevBuf<int32_t> d_wseg_order;    // their launch table (xcd_region_order)
     int32_t n_wseg_blocks = 0;
     // wide BF16 projection: V panels (64 rows x 32 facets per chunk), the
     // facet lists of the column nodes, the items (longest first) and the sums
@@ -583,6 +585,11 @@ void lowp_prepare_proj(rad_hmat *H);
 // work so far; entry 8 s + x is the s-th item of XCD x (-1: none, the
 // workgroup exits).
 std::vector<int32_t> xcd_launch_order(const std::vector<std::vector<int32_t>> &groups,
+                                      const std::vector<int64_t> &cost);
+// Launch table that keeps the order of the groups: they are cut into 8
+// contiguous runs of near-equal cost, run x going to XCD x in order (layout of
+// the table as for xcd_launch_order).
+std::vector<int32_t> xcd_region_order(const std::vector<std::vector<int32_t>> &groups,
                                       const std::vector<int64_t> &cost);
 void lowp_step(const rad_hmat *H, const void *E, const void *rho, double rho_s, const void *Bold, void *Bnew,
                int64_t ldr, int64_t R, double *norms, hipStream_t s);

@@ -42,6 +42,32 @@ std::vector<int32_t> xcd_launch_order(const std::vector<std::vector<int32_t>> &g
     return order;
 }
 
+std::vector<int32_t> xcd_region_order(const std::vector<std::vector<int32_t>> &groups,
+                                      const std::vector<int64_t> &cost) {
+    constexpr int kXcd = 8;
+    std::vector<int64_t> gsum(groups.size(), 0);
+    int64_t total = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        for (int32_t i : groups[g]) gsum[g] += cost[i];
+        total += gsum[g];
+    }
+    std::vector<std::vector<int32_t>> q(kXcd);
+    int64_t before = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        // the XCD whose share of the total cost holds this group's midpoint
+        const int64_t mid = 2 * before + gsum[g];
+        const int x = total > 0 ? (int)std::min<int64_t>(kXcd - 1, mid * kXcd / (2 * total)) : 0;
+        q[x].insert(q[x].end(), groups[g].begin(), groups[g].end());
+        before += gsum[g];
+    }
+    size_t len = 0;
+    for (const auto &v : q) len = std::max(len, v.size());
+    std::vector<int32_t> order(kXcd * len, -1);
+    for (int x = 0; x < kXcd; ++x)
+        for (size_t sl = 0; sl < q[x].size(); ++sl) order[kXcd * sl + x] = q[x][sl];
+    return order;
+}
+
 void mm_prepare_schedule(rad_hmat *H) {
     const int32_t n = H->n_tiles;
     std::vector<TileInfo> ti = H->d_tiles.download((size_t)n);
@@ -95,17 +121,20 @@ void mm_prepare_schedule(rad_hmat *H) {
         H->n_p1red_multi = (int32_t)multi.size();
         if (!multi.empty()) H->d_p1red_multi.upload(multi);
     }
-    // single-RHS projections of long column nodes: one workgroup per V column
+    // single-RHS projections: one workgroup per V column of long column
+    // nodes, one wave per V column of the others (a node's columns adjacent)
     {
-        std::vector<int32_t> items;
+        std::vector<int32_t> items, cols;
         for (int32_t gi = 0; gi < (int32_t)H->h_groups.size(); ++gi)
-            if (H->h_groups[gi].n >= kProjWideN)
-                for (int32_t kk = 0; kk < H->h_groups[gi].ktot; ++kk) {
-                    items.push_back(gi);
-                    items.push_back(kk);
-                }
+            for (int32_t kk = 0; kk < H->h_groups[gi].ktot; ++kk) {
+                std::vector<int32_t> &dst = H->h_groups[gi].n >= kProjWideN ? items : cols;
+                dst.push_back(gi);
+                dst.push_back(kk);
+            }
         H->n_pwide = (int32_t)(items.size() / 2);
         H->d_pwide.upload(items);
+        H->n_pcols = (int32_t)(cols.size() / 2);
+        H->d_pcols.upload(cols);
     }
     // segments of the single-RHS tile product: panels longer than kGSeg
     // columns (1 MB of values) are cut into near-equal runs of whole 16-column
@@ -162,7 +191,7 @@ void mm_prepare_schedule(rad_hmat *H) {
         // segments: a pair's reduction is cut into near-equal runs of at most
         // kSeg panel columns (whole 32-column chunks of the 16-bit layout,
         // 64 x 32 values each); a pair's segments take consecutive partial
-        // slots in order, and are launched longest first
+        // slots in order
         constexpr int32_t kSeg = 12288;
         std::vector<WideSeg> bySlot;
         std::vector<int32_t> pslot(1, 0);
@@ -198,9 +227,12 @@ void mm_prepare_schedule(rad_hmat *H) {
             }
             pslot.push_back((int32_t)bySlot.size());
         }
+        // neighbouring leaves multiply mostly the same operand rows: the pairs,
+        // in tree order, go to the XCDs as 8 runs of near-equal work, so that
+        // the workgroups an XCD runs at one time share those rows in its L2
         std::vector<int64_t> cost(bySlot.size());
         for (size_t i = 0; i < bySlot.size(); ++i) cost[i] = bySlot[i].kp;
-        const std::vector<int32_t> order = xcd_launch_order(share, cost);
+        const std::vector<int32_t> order = xcd_region_order(share, cost);
         H->n_wsegs = (int32_t)bySlot.size();
         H->d_wsegs.upload(bySlot);
         H->n_wseg_blocks = (int32_t)order.size();
