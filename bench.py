@@ -263,7 +263,8 @@ def terrain_measure(steps, tol=1e-3, lowp="bf16", rtol=1e-4, inner=3, cpu_rows=6
     op_bytes = st["bytes_dense"] + st["bytes_csr"] + st["bytes_lowrank"]
     mv1_flops = st["flops_per_rhs"]
     roof_mv1 = roofline(mv1_flops, op_bytes + 2 * N * 4, mv1_ms, PEAK_TFLOPS["f32"],
-                        "whole single-RHS FP32 H-matvec (k_proj + k_tile_gemv) on the terrain operator")
+                        "whole single-RHS FP32 H-matvec (k_proj_cols, k_proj_wide, k_tile_gemv, k_gemv_finish) "
+                        "on the terrain operator")
     log(f"single-RHS FP32 matvec {mv1_ms:.3f} ms, {roof_mv1['gbs']:.0f} GB/s on a {op_bytes / 1e9:.2f} GB operator")
 
     ph = H.time_phases(Rb, nrep=10, lowp=True)
@@ -271,7 +272,7 @@ def terrain_measure(steps, tol=1e-3, lowp="bf16", rtol=1e-4, inner=3, cpu_rows=6
     flops = 2.0 * Rb * (st["lowrank_row_elems"] + st["nnz_near"])
     bytes16 = (3.0 * N * Rb * 4 + 2 * st["lowrank_row_elems"] + 2 * st["nnz_near"] + st["sum_rank"] * Rb * 4)
     roof = roofline(flops, bytes16, ph[2], 2500.0,
-                    f"BF16 wide expansion (k_tile_mm16p on leaf pairs, k_tile_mm16w) + dense near field + fused "
+                    f"BF16 wide expansion (k_tile_mm16s segments on leaf pairs, k_pair_finish, k_tile_mm16w) + dense near field + fused "
                     f"Jacobi update")
     bytes32 = (3.0 * N * Rb * 4 + 4 * st["lowrank_row_elems"] + st["bytes_dense"] + st["sum_rank"] * Rb * 4)
     roof32 = roofline(flops, bytes32, ph32[2], PEAK_TFLOPS["f32"],

@@ -464,6 +464,15 @@ k_proj_mm(const ProjGroup *groups, const P1Work *work, const int32_t *pairs, con
             }
 }
 
+// out[dst[i]] = vals[i] for entries with dst[i] >= 0
+template <class T>
+__global__ void k_csr_panel_scatter(const T *vals, const int64_t *dst, int64_t n, T *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = dst[i];
+        if (d >= 0) out[d] = vals[i];
+    }
+}
+
 dim3 reduce_grid(int32_t nred, int64_t R) { return dim3((unsigned)nred, 4, (unsigned)((R + 255) / 256)); }
 
 // T rows = sum of the partial tiles of every split (fixed order).  Grid
@@ -506,7 +515,8 @@ struct TileSmem {
 template <class T, int kMode, int TN>
 __device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileInfo *tiles, const int32_t *brow,
                                           const TileTask *ctasks, const T *vals, const int32_t *csr_ptr,
-                                          const int32_t *csr_idx, int64_t csr_val_start, const T *X, const T *Tb,
+                                          const int32_t *csr_idx, int64_t csr_val_start, const CsrPanel *cpan,
+                                          const T *cvals, const int32_t *cbrow, const T *X, const T *Tb,
                                           int64_t ldr, int R, int64_t N, T *Y, const T *E, const T *rho, T rho_s,
                                           double *partial, double *epartial) {
     const TileInfo ti = tiles[tile];
@@ -518,8 +528,9 @@ __device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileI
     T (*sB)[KC][TN + PADB] = (T (*)[KC][TN + PADB])(smem + 2 * KC * (TM + PADA));
     Tile<T, TN> acc;
     acc.zero();
-    // CSR tasks: rows expanded into dense chunks in LDS
-    for (int c = ti.csr_begin; c < ti.csr_end; ++c) {
+    // CSR tasks: rows expanded into dense chunks in LDS (when the schedule
+    // made no compressed panels of them)
+    for (int c = cpan ? ti.csr_end : ti.csr_begin; c < ti.csr_end; ++c) {
         const TileTask tk = ctasks[c];
         const T *v = vals + tk.a_off;
         const int32_t *ci = csr_idx + (tk.a_off - csr_val_start);
@@ -542,13 +553,17 @@ __device__ __forceinline__ void tile_body(T *smem, int tile, int rt, const TileI
             __syncthreads();
         }
     }
-    // packed panel: software pipeline with two register stages in flight
-    // (chunk c + 2 loads while chunk c runs on the matrix cores)
-    // (columns past k16 are zero padding of the 16-bit chunk width: skipped)
-    const int kend = ti.k16;
-    if (kend > 0) {
-        const T *pan = vals + ti.panel_off;
-        const int32_t *br = brow + ti.brow_off;
+    // packed panels: the tile's compressed CSR panel (if any), then its dense
+    // and low-rank panel, each through a software pipeline with two register
+    // stages in flight (chunk c + 2 loads while chunk c runs on the matrix
+    // cores); columns past k16 are zero padding of the 16-bit chunk width
+    const CsrPanel cp = cpan ? cpan[tile] : CsrPanel{0, 0, 0, 0};
+    for (int pass = cp.k16 > 0 ? 0 : 1; pass < 2; ++pass) {
+        const int kend = pass == 0 ? cp.k16 : ti.k16;
+        if (kend == 0) continue;
+        const T *pan = pass == 0 ? cvals + cp.panel_off : vals + ti.panel_off;
+        const int32_t *br = pass == 0 ? cbrow + cp.brow_off : brow + ti.brow_off;
+        if (pass == 1 && cp.k16 > 0) __syncthreads();   // the first panel's last chunk is read
         PanelStage<T, TN> st0, st1;
         // row indices of the chunks st0 / st1 fetch next
         typename PanelStage<T, TN>::Rows rw0, rw1;
@@ -597,14 +612,15 @@ template <class T, int kMode, int TN>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<T, TN>, 8)))
 k_tile_mm(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
                                                   const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
-                                                  int64_t csr_val_start, const T *X, const T *Tb, int64_t ldr, int R,
+                                                  int64_t csr_val_start, const CsrPanel *cpan, const T *cvals,
+                                                  const int32_t *cbrow, const T *X, const T *Tb, int64_t ldr, int R,
                                                   int64_t N, T *Y, const T *E, const T *rho, T rho_s,
                                                   double *partial, double *epartial, int rtiles, const int32_t *stop) {
     if (stop && *stop) return;
     __shared__ T smem[TileSmem<T, TN>::kSize];
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
     tile_body<T, kMode, TN>(smem, wi / rtiles, wi % rtiles, tiles, brow, ctasks, vals, csr_ptr, csr_idx,
-                            csr_val_start, X, Tb, ldr, R, N, Y, E, rho, rho_s, partial, epartial);
+                            csr_val_start, cpan, cvals, cbrow, X, Tb, ldr, R, N, Y, E, rho, rho_s, partial, epartial);
 }
 
 // Persistent form: a fixed grid pulls work items (tiles in decreasing cost
@@ -614,7 +630,9 @@ k_tile_mm(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
 template <class T, int kMode, int TN>
 __global__ void __launch_bounds__(256) k_tile_mm_q(const TileInfo *tiles, const int32_t *brow,
                                                     const TileTask *ctasks, const T *vals, const int32_t *csr_ptr,
-                                                    const int32_t *csr_idx, int64_t csr_val_start, const T *X,
+                                                    const int32_t *csr_idx, int64_t csr_val_start,
+                                                    const CsrPanel *cpan, const T *cvals, const int32_t *cbrow,
+                                                    const T *X,
                                                     const T *Tb, int64_t ldr, int R, int64_t N, T *Y, const T *E,
                                                     const T *rho, T rho_s, double *partial, double *epartial,
                                                     const int32_t *order,
@@ -629,7 +647,8 @@ __global__ void __launch_bounds__(256) k_tile_mm_q(const TileInfo *tiles, const 
         __syncthreads();
         if (wi >= nwork) break;
         tile_body<T, kMode, TN>(smem, order[wi / rtiles], wi % rtiles, tiles, brow, ctasks, vals, csr_ptr, csr_idx,
-                                csr_val_start, X, Tb, ldr, R, N, Y, E, rho, rho_s, partial, epartial);
+                                csr_val_start, cpan, cvals, cbrow, X, Tb, ldr, R, N, Y, E, rho, rho_s, partial,
+                                epartial);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -829,17 +848,20 @@ void tile_mm_launch(const rad_hmat *H, const MmConfig &c, const T *X, T *Y, int6
                     const T *rho, T rho_s, double *partial, hipStream_t s, const int32_t *stop = nullptr,
                     double *epartial = nullptr) {
     const int rtiles = (R + TN - 1) / TN;
+    const CsrPanel *cpan = H->n_cpan > 0 ? H->d_cpan.p : nullptr;
     if (c.persistent) {
         const int nwork = H->n_tiles * rtiles;
         const int grid = std::max(1, std::min(nwork, H->n_cu * std::max(1, (int)c.blocks_per_cu)));
         hipLaunchKernelGGL((k_tile_mm_q<T, kMode, TN>), dim3(grid), dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
                            H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
-                           H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s, partial,
+                           H->csr_val_start, cpan, (const T *)H->d_cvals.p, H->d_cbrow.p, X, (const T *)H->w_t.p,
+                           ldr, R, H->N, Y, E, rho, rho_s, partial,
                            epartial, (const int32_t *)H->d_tile_order.p, nwork, rtiles, H->d_queue.p, stop);
     } else {
         hipLaunchKernelGGL((k_tile_mm<T, kMode, TN>), dim3((unsigned)(H->n_tiles * rtiles)), dim3(256), 0, s,
                            H->d_tiles.p, H->d_brow.p, H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p,
-                           H->d_csr_idx.p, H->csr_val_start, X, (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s,
+                           H->d_csr_idx.p, H->csr_val_start, cpan, (const T *)H->d_cvals.p, H->d_cbrow.p, X,
+                           (const T *)H->w_t.p, ldr, R, H->N, Y, E, rho, rho_s,
                            partial, epartial, rtiles, stop);
     }
     RAD_HIP(hipGetLastError());
@@ -904,6 +926,19 @@ void mm_from_rmajor(const rad_hmat *H, const void *src, int64_t ldr, bool permut
     else
         hipLaunchKernelGGL(k_from_rmajor<float>, grid, dim3(256), 0, s, perm, (const float *)src, ldr, (float *)dst,
                            ldd, H->N, (int)R);
+    RAD_HIP(hipGetLastError());
+}
+
+void launch_csr_panel_scatter(const void *vals, const int64_t *dst, int64_t n, void *out, int32_t dtype,
+                              hipStream_t s) {
+    if (n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    if (dtype == RAD_F64)
+        hipLaunchKernelGGL(k_csr_panel_scatter<double>, dim3(grid), dim3(256), 0, s, (const double *)vals, dst, n,
+                           (double *)out);
+    else
+        hipLaunchKernelGGL(k_csr_panel_scatter<float>, dim3(grid), dim3(256), 0, s, (const float *)vals, dst, n,
+                           (float *)out);
     RAD_HIP(hipGetLastError());
 }
 

@@ -191,6 +191,17 @@ struct TileTask {
     int32_t full;          // 1: every row in [r_lo, r_hi) holds all ncol columns (values row-major, ld ncol)
 };
 
+// A tile's CSR slices as one compressed panel for the multi-RHS kernels:
+// 64 x k16 values (column-major, ld 64) over the union of the columns where
+// any of the tile's rows has an entry (zeros elsewhere, k16 a multiple of 16),
+// and the X row each column multiplies.
+struct CsrPanel {
+    int64_t panel_off;     // into the compressed-panel values
+    int64_t brow_off;      // into their X-row indices
+    int32_t k16;           // 0: no CSR slice in this tile
+    int32_t pad_;
+};
+
 // Segment of a single-RHS tile product: column groups [g0, g1) of the panel
 // of tile `tile` (groups of 16 / sizeof(T) columns; g1 = -1: all), the
 // tile's CSR tasks when csr is set, partial row sums to slot `slot`.
@@ -353,6 +364,13 @@ struct rad_hmat {
     rad::DevBuf<int32_t> d_p1direct;
     rad::DevBuf<rad::P1Red> d_p1red_multi;
     int32_t n_p1red_multi = 0;
+    // the CSR slices of every tile as compressed panels (multi-RHS FP32/FP64
+    // expansion); n_cpan = 0: none, the kernels expand the CSR rows themselves
+    rad::DevBuf<rad::CsrPanel> d_cpan;
+    rad::DevBuf<unsigned char> d_cvals;
+    rad::DevBuf<int32_t> d_cbrow;
+    int32_t n_cpan = 0;
+    int64_t cpan_elems = 0;
     // wide 16-bit expansion: first tiles of consecutive tile pairs with identical
     // operand-row lists (one 128-row workgroup each), and the remaining tiles
     rad::DevBuf<int32_t> d_wpairs, d_wsingles;
@@ -472,6 +490,9 @@ void launch_csr_fill(const DevGeom &g, const int32_t *tiles, int64_t ntiles, con
                      const int64_t *row_offs, const int64_t *val_base, void *vals, int32_t *cols,
                      int32_t dtype, hipStream_t s);
 void launch_copy_batched(const CopyDesc *d, int64_t n, void *vals, int32_t dtype, hipStream_t s);
+// out[dst[i]] = vals[i] for i < n with dst[i] >= 0 (values of the matrix's dtype)
+void launch_csr_panel_scatter(const void *vals, const int64_t *dst, int64_t n, void *out, int32_t dtype,
+                              hipStream_t s);
 // ray casting (raycast.hip)
 void build_grid(rad_hmat *H, const std::vector<double> &tri);
 void launch_vis_grid(const rad_hmat *H, uint32_t *bits, int64_t wpr, hipStream_t s);

@@ -68,14 +68,88 @@ std::vector<int32_t> xcd_region_order(const std::vector<std::vector<int32_t>> &g
     return order;
 }
 
+namespace {
+
+// The CSR slices of each tile as one compressed panel (multi-RHS FP32 / FP64
+// expansion): the panel's columns are the sorted union of the X rows where
+// any of the tile's rows has an entry, so the slices run through the same
+// pipelined panel loop as dense and low-rank columns, with the zeros of that
+// union as the only extra work.  Returns each tile's compressed width.
+std::vector<int32_t> prepare_csr_panels(rad_hmat *H, const std::vector<TileInfo> &ti,
+                                        const std::vector<TileTask> &tk) {
+    const int32_t n = H->n_tiles;
+    std::vector<int32_t> width(n, 0);
+    H->n_cpan = 0;
+    H->cpan_elems = 0;
+    if (tk.empty() || H->max_rhs < kMfmaMinRhs || H->d_csr_idx.n == 0) return width;
+    const std::vector<int32_t> ptr = H->d_csr_ptr.download(H->d_csr_ptr.n);
+    const std::vector<int32_t> idx = H->d_csr_idx.download(H->d_csr_idx.n);
+    std::vector<int64_t> dst(idx.size(), -1);   // per CSR entry: its element of the compressed panels
+    std::vector<CsrPanel> cp(n, CsrPanel{0, 0, 0, 0});
+    std::vector<int32_t> cbrow, cols;
+    int64_t vfill = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (ti[i].csr_begin >= ti[i].csr_end) continue;
+        cols.clear();
+        for (int32_t c = ti[i].csr_begin; c < ti[i].csr_end; ++c) {
+            const TileTask &t = tk[c];
+            const int64_t g0 = t.a_off - H->csr_val_start;
+            for (int32_t r = t.r_lo; r < t.r_hi; ++r)
+                for (int32_t q = ptr[t.aux_off + t.row_off + r]; q < ptr[t.aux_off + t.row_off + r + 1]; ++q)
+                    cols.push_back(t.col0 + idx[g0 + q]);
+        }
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        if (cols.empty()) continue;
+        const int32_t k16 = (int32_t)((cols.size() + 15) / 16 * 16);
+        cp[i] = CsrPanel{vfill, (int64_t)cbrow.size(), k16, 0};
+        cbrow.insert(cbrow.end(), cols.begin(), cols.end());
+        cbrow.insert(cbrow.end(), (size_t)k16 - cols.size(), cols.back());   // padding columns (zero values)
+        for (int32_t c = ti[i].csr_begin; c < ti[i].csr_end; ++c) {
+            const TileTask &t = tk[c];
+            const int64_t g0 = t.a_off - H->csr_val_start;
+            for (int32_t r = t.r_lo; r < t.r_hi; ++r)
+                for (int32_t q = ptr[t.aux_off + t.row_off + r]; q < ptr[t.aux_off + t.row_off + r + 1]; ++q) {
+                    const int32_t col = t.col0 + idx[g0 + q];
+                    const int64_t pos = std::lower_bound(cols.begin(), cols.end(), col) - cols.begin();
+                    dst[g0 + q] = vfill + pos * 64 + r;
+                }
+        }
+        width[i] = k16;
+        vfill += (int64_t)64 * k16;
+    }
+    if (vfill == 0) return width;
+    const size_t s = H->dtype == RAD_F64 ? sizeof(double) : sizeof(float);
+    H->d_cvals.alloc((size_t)vfill * s);
+    RAD_HIP(hipMemset(H->d_cvals.p, 0, (size_t)vfill * s));
+    {
+        DevBuf<int64_t> d_dst;
+        d_dst.upload(dst);
+        launch_csr_panel_scatter((const char *)H->d_vals.p + (size_t)H->csr_val_start * s, d_dst.p,
+                                 (int64_t)dst.size(), H->d_cvals.p, H->dtype, nullptr);
+        RAD_HIP(hipStreamSynchronize(nullptr));
+    }
+    H->d_cpan.upload(cp);
+    H->d_cbrow.upload(cbrow);
+    H->n_cpan = n;
+    H->cpan_elems = vfill;
+    return width;
+}
+
+}  // namespace
+
 void mm_prepare_schedule(rad_hmat *H) {
     const int32_t n = H->n_tiles;
     std::vector<TileInfo> ti = H->d_tiles.download((size_t)n);
     std::vector<TileTask> tk = H->d_tile_tasks.download(H->d_tile_tasks.n);
+    const std::vector<int32_t> cwidth = prepare_csr_panels(H, ti, tk);
     std::vector<int64_t> cost(n, 0);
     for (int32_t i = 0; i < n; ++i) {
         cost[i] = ti[i].k16;
-        for (int32_t c = ti[i].csr_begin; c < ti[i].csr_end; ++c) cost[i] += tk[c].ncol;
+        if (H->n_cpan > 0)
+            cost[i] += cwidth[i];
+        else
+            for (int32_t c = ti[i].csr_begin; c < ti[i].csr_end; ++c) cost[i] += tk[c].ncol;
     }
     std::vector<int32_t> order(n);
     for (int32_t i = 0; i < n; ++i) order[i] = i;

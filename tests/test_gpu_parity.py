@@ -219,6 +219,34 @@ def test_matmat_big_leaves_and_terrain():
         assert _rel(H.matvec(torch.from_numpy(X).to(DEV)).cpu().numpy(), F @ X) < 1e-10
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_csr_near_field_multi_rhs_terrain(storage):
+    """CSR near field of an occluded terrain through the multi-RHS expansion
+    (each tile's CSR slices as one compressed panel over the union of their
+    nonzero columns): 32 x 32 DEM, leaf 32 (several CSR slices per 64-row
+    tile), ray-cast visibility, R = 37 (a ragged last column tile), against
+    the oracle's dense F; the single-RHS product, which reads the CSR rows
+    directly, agrees column by column."""
+    from synth import DemSpec, dem_mesh
+    verts, faces = dem_mesh(DemSpec(n=32, extent=320.0, seed=4))
+    fac = ref.Facets(verts, faces)
+    F = ref.view_factor_matrix(fac, ref.pair_visibility(fac, "raycast"))
+    H = _hm(verts, faces, tol=1e-6, storage=storage, visibility="raycast", leaf_size=32, nearfield="csr",
+            max_rhs=37)
+    st = H.stats()
+    assert st["n_csr"] > 0 and st["n_dense"] == 0
+    X = np.random.default_rng(21).random((fac.N, 37))
+    dt = torch.float64 if storage == "f64" else torch.float32
+    Xd = torch.from_numpy(X).to(DEV, dt)
+    Y = H.matvec(Xd).double().cpu().numpy()
+    tol = 1e-6 + (1e-12 if storage == "f64" else 2e-6)
+    assert _rel(Y, F @ X) <= tol
+    for c in (0, 18, 36):
+        assert _rel(Y[:, c], F @ X[:, c]) <= tol
+        y1 = H.matvec(Xd[:, c].contiguous()).double().cpu().numpy()
+        assert _rel(Y[:, c], y1) <= (1e-13 if storage == "f64" else 3e-6)
+
+
 def test_matmat_agrees_with_single_rhs(cap):
     verts, faces, fac, F = cap
     H = _hm(verts, faces, tol=1e-3, storage="f64", max_rhs=16)
