@@ -387,6 +387,11 @@ typedef struct {
     int64_t max_panel_cols;    /* widest 64-row tile panel: dense columns plus ranks of the
                                   blocks covering the tile (the longest reduction of the
                                   expansion)                                          */
+    int64_t bytes_csr_panels;  /* device copy of the CSR slices as compressed 64-row
+                                  panels (values over the union of each tile's nonzero
+                                  columns, and their X rows), read by the multi-RHS
+                                  expansion; made when max_rhs >= 16, included in
+                                  bytes_total                                         */
 } rad_hmat_stats;
 
 rad_status rad_hmat_info(const rad_hmat *H, rad_hmat_stats *stats);

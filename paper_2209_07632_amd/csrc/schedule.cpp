@@ -143,6 +143,13 @@ void mm_prepare_schedule(rad_hmat *H) {
     std::vector<TileInfo> ti = H->d_tiles.download((size_t)n);
     std::vector<TileTask> tk = H->d_tile_tasks.download(H->d_tile_tasks.n);
     const std::vector<int32_t> cwidth = prepare_csr_panels(H, ti, tk);
+    {
+        const int64_t cb = H->n_cpan > 0 ? (int64_t)(H->d_cvals.n + H->d_cbrow.n * sizeof(int32_t) +
+                                                     H->d_cpan.n * sizeof(CsrPanel))
+                                         : 0;
+        H->stats.bytes_total += cb - H->stats.bytes_csr_panels;
+        H->stats.bytes_csr_panels = cb;
+    }
     std::vector<int64_t> cost(n, 0);
     for (int32_t i = 0; i < n; ++i) {
         cost[i] = ti[i].k16;

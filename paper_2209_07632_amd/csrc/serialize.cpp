@@ -429,6 +429,7 @@ void convert_hmat(rad_hmat *G, const rad_hmat *H, int32_t dtype, int32_t max_rhs
     st.bytes_total = (int64_t)G->d_vals.bytes() + (int64_t)G->d_csr_idx.bytes() + (int64_t)G->d_csr_ptr.bytes() +
                      (int64_t)G->d_tiles.bytes() + (int64_t)G->d_brow.bytes() + (int64_t)G->d_groups.bytes() +
                      (int64_t)G->d_tile_tasks.bytes() + (int64_t)G->d_perm.bytes();
+    st.bytes_csr_panels = 0;   // (the schedule adds the converted matrix's own)
 }
 
 }  // namespace rad

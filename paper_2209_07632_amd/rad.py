@@ -92,7 +92,7 @@ class Stats(ctypes.Structure):
                 ("nnz_near", ctypes.c_int64), ("sum_rank", ctypes.c_int64), ("lowrank_elems", ctypes.c_int64),
                 ("max_rank", ctypes.c_int32), ("build_seconds", ctypes.c_double), ("flops_per_rhs", ctypes.c_double),
                 ("lowrank_row_elems", ctypes.c_int64), ("lowrank_col_elems", ctypes.c_int64),
-                ("max_panel_cols", ctypes.c_int64)]
+                ("max_panel_cols", ctypes.c_int64), ("bytes_csr_panels", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
