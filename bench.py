@@ -185,14 +185,15 @@ def sampled_row_residual(verts, faces, B_orig, E_orig, rho, rows):
     return float(np.linalg.norm(res) / np.linalg.norm(B_orig[rows]))
 
 
-def terrain_measure(steps, tol=1e-3, lowp="bf16", rtol=1e-4, inner=3, cpu_rows=6, fp64=True):
+def terrain_measure(steps, tol=1e-3, lowp="bf16", rtol=1e-4, inner=3, cpu_rows=6, fp64=True, csr=True):
     """Polar terrain: 256 x 256 DEM (131,072 facets), sun at 1.5 deg elevation
     stepping through 2,880 azimuths (0.125 deg), right-hand sides in batches of
     256; FP32 operator with a 16-bit copy.  Times the sweep of all suns by
     refined 16-bit solves to rtol, by plain FP32 Jacobi, and (fp64) by the
     plain FP64 single-RHS form on the same compressed operator converted to
     FP64; the single-RHS FP32 product on the multi-GB operator; the kernels of
-    one iteration.  Returns a dict (and the matrix and data for the CPU check)."""
+    one iteration; and (csr) the same terrain with CSR near field.  Returns a
+    dict."""
     import torch
     from paper_2209_07632_amd import HMatrix
     from synth import DEM_256, dem_mesh, sun_grid_azimuth
@@ -328,8 +329,84 @@ def terrain_measure(steps, tol=1e-3, lowp="bf16", rtol=1e-4, inner=3, cpu_rows=6
                                          f"{dt:.1f} s"}
         out["sampled_row_residual"] = res
         log(f"sampled-row relative residual of the refined solution vs exact rows: {res:.3e}")
-    H.close()
+    if csr:
+        # Algorithm 4's own near-field form (CSR) on the same terrain: same
+        # tree, so the same right-hand sides; FP32 Jacobi sweep, kernels of one
+        # iteration and the single-RHS product
+        perm = H.perm()
+        B_ref = batches[0][1].clone()
+        H.close()
+        out["csr_near_field"] = terrain_csr_leg(verts, faces, perm, batches, B_ref, steps, tol, rtol, albedo, Rb)
+    else:
+        H.close()
     return out
+
+
+def terrain_csr_leg(verts, faces, perm, batches, B_ref, steps, tol, rtol, albedo, Rb):
+    """The terrain operator with CSR near field (the byte rule of Algorithm 4
+    unforced): FP32 Jacobi sweep of the given batches, per-iteration kernels,
+    single-RHS FP32 product, and the first batch's solution against the dense
+    near-field operator's (B_ref, the refined 16-bit sweep)."""
+    import torch
+    from paper_2209_07632_amd import HMatrix
+
+    N = faces.shape[0]
+    log("building the terrain operator with CSR near field (FP32)")
+    t0 = time.perf_counter()
+    H = HMatrix(verts, faces, tol=tol, storage="f32", visibility="raycast", nearfield="csr", leaf_size=128,
+                max_rank=256, max_rhs=Rb)
+    build_s = time.perf_counter() - t0
+    st = H.stats()
+    log(f"built in {build_s:.1f} s: {st}")
+    if not np.array_equal(H.perm(), perm):
+        raise RuntimeError("the CSR near-field operator has another tree order")
+    tune = H.autotune(Rb, nrep=3)
+
+    def sweep():
+        tot = 0
+        for E, B, R in batches:
+            _, info = H.solve(E, rho=albedo, rtol=rtol, out=B, order="tree_rmajor", R=R, max_iter=200)
+            tot += info["total_iters"]
+        return tot
+
+    sweep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        iters = sweep()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    nsuns = sum(R for _, _, R in batches)
+    B0 = batches[0][1][:, :batches[0][2]].double()
+    Br = B_ref[:, :batches[0][2]].double()
+    diff = float((torch.linalg.vector_norm(B0 - Br, dim=0) / torch.linalg.vector_norm(Br, dim=0)).max())
+    x = torch.rand(N, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        H.matvec(x, out=y, order="tree")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        H.matvec(x, out=y, order="tree")
+    ev1.record()
+    torch.cuda.synchronize()
+    mv1_ms = ev0.elapsed_time(ev1) / 10
+    op_bytes = st["bytes_csr"] + st["bytes_lowrank"] + st["bytes_dense"]
+    ph = H.time_phases(Rb, nrep=5)
+    flops = 2.0 * Rb * (st["lowrank_row_elems"] + st["nnz_near"])
+    H.close()
+    log(f"CSR near field: {dt:.3f} s per sweep, {nsuns / dt:.1f} solves/s ({iters} iterations); phases {ph}; "
+        f"single-RHS {mv1_ms:.3f} ms; max column difference from the dense near-field solve {diff:.2e}")
+    return {"build_seconds": build_s, "hmat_blocks": block_counts(st), "bytes_csr_panels": st["bytes_csr_panels"],
+            "autotune": tune,
+            "fp32_jacobi": {"seconds_per_sweep": dt, "solves_per_s": nsuns / dt, "outer_iters": iters},
+            "phase_ms_fp32": {"projections": ph[0], "split_k_sum": ph[1], "expansion_jacobi": ph[2]},
+            "expansion_fp32_tflops": flops / (ph[2] * 1e-3) / 1e12,
+            "hmatvec_single_rhs_ms": mv1_ms,
+            "hmatvec_single_rhs_gbs": (op_bytes + 2 * N * 4) / (mv1_ms * 1e-3) / 1e9,
+            "single_rhs_gbs_with_panel_copy": (st["bytes_csr_panels"] + st["bytes_lowrank"] + 2 * N * 4)
+            / (mv1_ms * 1e-3) / 1e9,
+            "max_col_rel_diff_vs_dense_near_field": diff}
 
 
 def run_dem(args):

@@ -389,9 +389,8 @@ typedef struct {
                                   expansion)                                          */
     int64_t bytes_csr_panels;  /* device copy of the CSR slices as compressed 64-row
                                   panels (values over the union of each tile's nonzero
-                                  columns, and their X rows), read by the multi-RHS
-                                  expansion; made when max_rhs >= 16, included in
-                                  bytes_total                                         */
+                                  columns, and their X rows), read by the FP32/FP64
+                                  products; included in bytes_total                   */
 } rad_hmat_stats;
 
 rad_status rad_hmat_info(const rad_hmat *H, rad_hmat_stats *stats);

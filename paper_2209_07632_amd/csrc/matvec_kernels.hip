@@ -169,13 +169,16 @@ __device__ __forceinline__ void gemv_epilogue(int tile, int64_t r, int lane, T y
     }
 }
 
-// With segs given, blockIdx.x is a segment of a tile's panel (column groups
-// [g0, g1), the tile's CSR tasks when csr is set): its 64 row sums go to
-// spart[(slot R + r) 64 + row] and k_gemv_finish completes the tile.
+// The column groups of a tile are those of its panel followed by those of
+// its compressed CSR panel (when cpan is given; the CSR tasks are then not
+// walked row by row).  With segs given, blockIdx.x is a segment of them
+// (column groups [g0, g1), the tile's CSR tasks when csr is set): its 64 row
+// sums go to spart[(slot R + r) 64 + row] and k_gemv_finish completes the tile.
 template <class T, int kMode>
 __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const int32_t *brow, const TileTask *ctasks,
                                                     const T *vals, const int32_t *csr_ptr, const int32_t *csr_idx,
-                                                    int64_t csr_val_start, const T *X, int64_t ldx, const T *Tb,
+                                                    int64_t csr_val_start, const CsrPanel *cpan, const T *cvals,
+                                                    const int32_t *cbrow, const T *X, int64_t ldx, const T *Tb,
                                                     int32_t t_ld, int64_t N, T *Y, int64_t ldy, const T *E,
                                                     const T *rho, T rho_s, double *partial, double *epartial,
                                                     const int32_t *stop, const GemvSeg *segs, T *spart) {
@@ -191,57 +194,60 @@ __global__ void __launch_bounds__(256) k_tile_gemv(const TileInfo *tiles, const 
     const int sub = lane / LPC, r0 = VW * (lane % LPC);
     const T *x = X + r * ldx;
     const T *tb = Tb + r * t_ld;
-    const T *panel = vals + ti.panel_off + r0;
-    const int32_t *br = brow + ti.brow_off;
     T acc[VW];
 #pragma unroll
     for (int u = 0; u < VW; ++u) acc[u] = 0;
-    auto operand = [&](int k) -> T {
-        const int32_t b = br[k];
-        return b >= 0 ? x[b] : tb[-1 - b];
-    };
     auto fma_col = [&](const vec_t &a, T xv) {
         const T *av = (const T *)&a;
 #pragma unroll
         for (int u = 0; u < VW; ++u) acc[u] += av[u] * xv;
     };
     auto value = [&](int32_t b) -> T { return b >= 0 ? x[b] : tb[-1 - b]; };
-    // column groups [g, ngroups) of this workgroup (all columns that hold
-    // values, a multiple of 16, or a segment of them)
-    const int ngroups = sg.g1 < 0 ? ti.k16 / VW : sg.g1;
-    int g = sg.g0 + w;
-    // the operand-row indices of an iteration are loaded one iteration ahead
-    // of the gathers that use them
-    int32_t bi[4] = {0, 0, 0, 0};
-    if (g + 12 < ngroups)
+    const CsrPanel cp = cpan ? cpan[tile] : CsrPanel{0, 0, 0, 0};
+    const int ngm = ti.k16 / VW, ngc = cp.k16 / VW;
+    // column groups [g0, gend) of this workgroup (all columns that hold
+    // values, a multiple of 16, or a segment of them), the panel's first
+    const int gend = sg.g1 < 0 ? ngm + ngc : sg.g1;
+    for (int part = 0; part < 2; ++part) {
+        const int base = part == 0 ? 0 : ngm;
+        const int ngroups = min(gend, part == 0 ? ngm : ngm + ngc) - base;
+        int g = max(sg.g0, base) - base + w;
+        if (g - w >= ngroups) continue;
+        const T *panel = part == 0 ? vals + ti.panel_off + r0 : cvals + cp.panel_off + r0;
+        const int32_t *br = part == 0 ? brow + ti.brow_off : cbrow + cp.brow_off;
+        // the operand-row indices of an iteration are loaded one iteration
+        // ahead of the gathers that use them
+        int32_t bi[4] = {0, 0, 0, 0};
+        if (g + 12 < ngroups)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bi[q] = br[VW * g + sub + 4 * VW * q];
-    for (; g + 12 < ngroups; g += 16) {
-        const int k0 = VW * g + sub, k1 = k0 + 4 * VW, k2 = k0 + 8 * VW, k3 = k0 + 12 * VW;
-        const vec_t a0 = *(const vec_t *)(panel + (int64_t)k0 * 64);
-        const vec_t a1 = *(const vec_t *)(panel + (int64_t)k1 * 64);
-        const vec_t a2 = *(const vec_t *)(panel + (int64_t)k2 * 64);
-        const vec_t a3 = *(const vec_t *)(panel + (int64_t)k3 * 64);
-        const T x0 = value(bi[0]), x1 = value(bi[1]), x2 = value(bi[2]), x3 = value(bi[3]);
-        if (g + 28 < ngroups)
+            for (int q = 0; q < 4; ++q) bi[q] = br[VW * g + sub + 4 * VW * q];
+        for (; g + 12 < ngroups; g += 16) {
+            const int k0 = VW * g + sub, k1 = k0 + 4 * VW, k2 = k0 + 8 * VW, k3 = k0 + 12 * VW;
+            const vec_t a0 = *(const vec_t *)(panel + (int64_t)k0 * 64);
+            const vec_t a1 = *(const vec_t *)(panel + (int64_t)k1 * 64);
+            const vec_t a2 = *(const vec_t *)(panel + (int64_t)k2 * 64);
+            const vec_t a3 = *(const vec_t *)(panel + (int64_t)k3 * 64);
+            const T x0 = value(bi[0]), x1 = value(bi[1]), x2 = value(bi[2]), x3 = value(bi[3]);
+            if (g + 28 < ngroups)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) bi[q] = br[k0 + 16 * VW + 4 * VW * q];
-        fma_col(a0, x0);
-        fma_col(a1, x1);
-        fma_col(a2, x2);
-        fma_col(a3, x3);
-    }
-    for (; g < ngroups; g += 4) {
-        const int k0 = VW * g + sub;
-        const vec_t a0 = *(const vec_t *)(panel + (int64_t)k0 * 64);
-        fma_col(a0, operand(k0));
+                for (int q = 0; q < 4; ++q) bi[q] = br[k0 + 16 * VW + 4 * VW * q];
+            fma_col(a0, x0);
+            fma_col(a1, x1);
+            fma_col(a2, x2);
+            fma_col(a3, x3);
+        }
+        for (; g < ngroups; g += 4) {
+            const int k0 = VW * g + sub;
+            const vec_t a0 = *(const vec_t *)(panel + (int64_t)k0 * 64);
+            fma_col(a0, value(br[k0]));
+        }
     }
     __shared__ T red[4][VW][64];
 #pragma unroll
     for (int u = 0; u < VW; ++u) red[w][sub][r0 + u] = acc[u];
     // CSR tasks: lane = row, wave w takes tasks w, w+4, ...
     T cacc = 0;
-    for (int c = ti.csr_begin + w; sg.csr && c < ti.csr_end; c += 4) {
+    for (int c = ti.csr_begin + w; sg.csr && !cpan && c < ti.csr_end; c += 4) {
         const TileTask tk = ctasks[c];
         if (lane >= tk.r_lo && lane < tk.r_hi) {
             const int32_t *ptr = csr_ptr + tk.aux_off + tk.row_off + lane;
@@ -338,7 +344,8 @@ void apply_t(const rad_hmat *H, const T *X, int64_t ldx, T *Y, int64_t ldy, int6
         constexpr int M = decltype(mode)::value;
         hipLaunchKernelGGL((k_tile_gemv<T, M>), grid2, dim3(256), 0, s, H->d_tiles.p, H->d_brow.p,
                            H->d_tile_tasks.p, (const T *)H->d_vals.p, H->d_csr_ptr.p, H->d_csr_idx.p,
-                           H->csr_val_start, X, ldx, (const T *)Tb, H->t_ld, H->N, Y, ldy, E, rho, rho_s, partial,
+                           H->csr_val_start, H->n_cpan > 0 ? H->d_cpan.p : nullptr, (const T *)H->d_cvals.p,
+                           H->d_cbrow.p, X, ldx, (const T *)Tb, H->t_ld, H->N, Y, ldy, E, rho, rho_s, partial,
                            epartial, stop, segs, spart);
         if (seg)
             hipLaunchKernelGGL((k_gemv_finish<T, M>), dim3(H->n_tiles, (unsigned)R), dim3(64), 0, s,

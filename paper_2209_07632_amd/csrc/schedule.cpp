@@ -70,18 +70,19 @@ std::vector<int32_t> xcd_region_order(const std::vector<std::vector<int32_t>> &g
 
 namespace {
 
-// The CSR slices of each tile as one compressed panel (multi-RHS FP32 / FP64
-// expansion): the panel's columns are the sorted union of the X rows where
-// any of the tile's rows has an entry, so the slices run through the same
-// pipelined panel loop as dense and low-rank columns, with the zeros of that
-// union as the only extra work.  Returns each tile's compressed width.
+// The CSR slices of each tile as one compressed panel (FP32 / FP64
+// products, single- and multi-RHS): the panel's columns are the sorted union
+// of the X rows where any of the tile's rows has an entry, so the slices run
+// through the same streamed panel loops as dense and low-rank columns, with
+// the zeros of that union as the only extra work.  Returns each tile's
+// compressed width.
 std::vector<int32_t> prepare_csr_panels(rad_hmat *H, const std::vector<TileInfo> &ti,
                                         const std::vector<TileTask> &tk) {
     const int32_t n = H->n_tiles;
     std::vector<int32_t> width(n, 0);
     H->n_cpan = 0;
     H->cpan_elems = 0;
-    if (tk.empty() || H->max_rhs < kMfmaMinRhs || H->d_csr_idx.n == 0) return width;
+    if (tk.empty() || H->d_csr_idx.n == 0) return width;
     const std::vector<int32_t> ptr = H->d_csr_ptr.download(H->d_csr_ptr.n);
     const std::vector<int32_t> idx = H->d_csr_idx.download(H->d_csr_idx.n);
     std::vector<int64_t> dst(idx.size(), -1);   // per CSR entry: its element of the compressed panels
@@ -224,14 +225,14 @@ void mm_prepare_schedule(rad_hmat *H) {
         const int32_t vw = H->dtype == RAD_F64 ? 2 : 4;            // values per 16-byte load
         const int32_t kGSeg = H->dtype == RAD_F64 ? 2048 : 4096;
         int32_t kmax = 0;
-        for (int32_t i = 0; i < n; ++i) kmax = std::max(kmax, ti[i].k16);
+        for (int32_t i = 0; i < n; ++i) kmax = std::max(kmax, ti[i].k16 + cwidth[i]);
         H->n_gsegs = 0;
         if (kmax > kGSeg) {
             std::vector<GemvSeg> segs;
             std::vector<int32_t> tseg(1, 0);
             for (int32_t i = 0; i < n; ++i) {
-                const int32_t chunks = ti[i].k16 / 16;
-                const int32_t nseg = std::max(1, (ti[i].k16 + kGSeg - 1) / kGSeg);
+                const int32_t chunks = (ti[i].k16 + cwidth[i]) / 16;   // the panel, then the CSR panel
+                const int32_t nseg = std::max(1, (ti[i].k16 + cwidth[i] + kGSeg - 1) / kGSeg);
                 for (int32_t sg = 0; sg < nseg; ++sg) {
                     const int64_t c0 = (int64_t)chunks * sg / nseg, c1 = (int64_t)chunks * (sg + 1) / nseg;
                     segs.push_back(GemvSeg{i, (int32_t)(16 * c0 / vw), (int32_t)(16 * c1 / vw), sg == 0 ? 1 : 0,
