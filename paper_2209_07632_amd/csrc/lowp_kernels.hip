@@ -95,6 +95,14 @@ __global__ void __launch_bounds__(256) k_lowp_panels(const float *vals, const Ti
     }
 }
 
+// out[dst[i]] = BF16(vals[i]) for entries with dst[i] >= 0 (compressed CSR pair panels)
+__global__ void k_csr_panel_scatter16(const float *vals, const int64_t *dst, int64_t n, __bf16 *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = dst[i];
+        if (d >= 0) out[d] = (__bf16)vals[i];
+    }
+}
+
 template <class H>
 __global__ void __launch_bounds__(256) k_lowp_v(const float *vals, const ProjGroup *groups, H *out, float *tscale) {
     const ProjGroup g = groups[blockIdx.x];
@@ -470,7 +478,8 @@ struct PairStage {
 template <bool kProj = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_tile_mm16s(const int32_t *order, const WideSeg *segs, const int32_t *brow, const __bf16 *vals16,
-             const __bf16 *X16, const __bf16 *T16, int64_t ld16, float *wpart, int64_t ldr, int R) {
+             const __bf16 *X16, const __bf16 *T16, int64_t ld16, float *wpart, int64_t ldr, int R,
+             const __bf16 *cvals16, const int32_t *cbrow16) {
     const int32_t item = order[blockIdx.x];
     if (item < 0) return;
     const WideSeg sg = segs[item];
@@ -503,8 +512,10 @@ k_tile_mm16s(const int32_t *order, const WideSeg *segs, const int32_t *brow, con
         }
     };
     if (sg.kp > 0) {
-        const __bf16 *pa = vals16 + sg.pa, *pb = vals16 + sg.pb;
-        const int32_t *br = brow + sg.br;
+        // (segments of a pair's compressed CSR panel read the compressed buffers)
+        const __bf16 *vb = sg.pad_ ? cvals16 : vals16;
+        const __bf16 *pa = vb + sg.pa, *pb = vb + sg.pb;
+        const int32_t *br = (sg.pad_ ? cbrow16 : brow) + sg.br;
         PairStage s0, s1;
         WideStage::Rows rw0, rw1;
         const int kp = sg.kp;
@@ -731,9 +742,10 @@ void convert_t(rad_hmat *H_, hipStream_t s) {
     RAD_HIP(hipGetLastError());
 }
 
-// the wide BF16 kernel serves matrices without CSR tasks and R <= 256
+// the wide BF16 kernel serves R <= 256 and matrices whose CSR slices (if
+// any) all have compressed pair panels
 bool wide_ok(const rad_hmat *Hm, int R) {
-    return Hm->lowp == RAD_BF16 && Hm->d_tile_tasks.n == 0 && R <= WN && Hm->w_x16.p != nullptr;
+    return Hm->lowp == RAD_BF16 && (Hm->d_tile_tasks.n == 0 || Hm->wide_csr) && R <= WN && Hm->w_x16.p != nullptr;
 }
 
 int64_t ld16_of(int64_t R) { return (R + 7) & ~(int64_t)7; }
@@ -748,7 +760,8 @@ void launch_wide(const rad_hmat *Hm, const float *E, const float *rho, float rho
         // pairs of tiles with one operand-row list: their segments longest
         // first, then each pair's sum and epilogue; then the tiles left alone
         hipLaunchKernelGGL(k_tile_mm16s<false>, dim3(Hm->n_wseg_blocks), dim3(256), 0, s, Hm->d_wseg_order.p,
-                           Hm->d_wsegs.p, Hm->d_brow.p, v16, x16, t16, ld16, Hm->w_wpart.p, (int64_t)0, 0);
+                           Hm->d_wsegs.p, Hm->d_brow.p, v16, x16, t16, ld16, Hm->w_wpart.p, (int64_t)0, 0,
+                           (const __bf16 *)Hm->d_cvals16.p, Hm->d_cbrow16.p);
         hipLaunchKernelGGL((k_pair_finish<kFused>), dim3(2 * Hm->n_wpairs), dim3(256), 0, s, Hm->d_wpairs.p,
                            Hm->d_wslot.p, (const float *)Hm->w_wpart.p, Bold, ldr, R, Hm->N, Bnew, E, rho, rho_s,
                            part);
@@ -771,7 +784,8 @@ void launch_proj16w(const rad_hmat *Hm, int64_t ldr, int R, __bf16 *T16, hipStre
     const int64_t ld16 = ld16_of(R);
     hipLaunchKernelGGL(k_tile_mm16s<true>, dim3(Hm->n_pseg_blocks), dim3(256), 0, s, Hm->d_pseg_order.p,
                        Hm->d_psegs.p, Hm->d_pbrow.p, (const __bf16 *)Hm->d_vpan16.p, (const __bf16 *)Hm->w_x16.p,
-                       (const __bf16 *)nullptr, ld16, (float *)Hm->w_part.p, ldr, R);
+                       (const __bf16 *)nullptr, ld16, (float *)Hm->w_part.p, ldr, R, (const __bf16 *)nullptr,
+                       (const int32_t *)nullptr);
     hipLaunchKernelGGL(k_proj_reduce16, reduce_grid(Hm->n_wpred, R), dim3(256), 0, s, Hm->d_wpred.p,
                        (const float *)Hm->w_part.p, Hm->d_tscale.p, ldr, R, (float *)nullptr, T16, ld16);
     RAD_HIP(hipGetLastError());
@@ -892,7 +906,7 @@ void time16_t(const rad_hmat *Hm, int R, int nrep, hipStream_t s, double *ms) {
             hipLaunchKernelGGL(k_tile_mm16s<true>, dim3(Hm->n_pseg_blocks), dim3(256), 0, s, Hm->d_pseg_order.p,
                                Hm->d_psegs.p, Hm->d_pbrow.p, (const __bf16 *)Hm->d_vpan16.p,
                                (const __bf16 *)Hm->w_x16.p, (const __bf16 *)nullptr, ld16, (float *)Hm->w_part.p,
-                               ldr, R);
+                               ldr, R, (const __bf16 *)nullptr, (const int32_t *)nullptr);
         });
         ms[1] = timed([&] {
             hipLaunchKernelGGL(k_proj_reduce16, reduce_grid(Hm->n_wpred, R), dim3(256), 0, s,
@@ -1000,7 +1014,9 @@ void ir_update(const rad_hmat *H, double *B64, const float *d, float *B32, int64
 // operand rows and are launched on one XCD (xcd_launch_order).
 void lowp_prepare_proj(rad_hmat *H) {
     H->n_psegs = H->n_pseg_blocks = H->n_wpred = 0;
-    if (H->lowp != RAD_BF16 || H->d_tile_tasks.n != 0 || H->h_groups.empty() || H->max_rhs < kMfmaMinRhs) return;
+    if (H->lowp != RAD_BF16 || (H->d_tile_tasks.n != 0 && !H->wide_csr) || H->h_groups.empty() ||
+        H->max_rhs < kMfmaMinRhs)
+        return;
     const std::vector<ProjGroup> &gs = H->h_groups;
     auto items_for = [&](int64_t kw) {
         int64_t c = 0;
@@ -1066,6 +1082,13 @@ void lowp_prepare_proj(rad_hmat *H) {
     RAD_HIP(hipStreamSynchronize(0));
     H->n_psegs = (int32_t)segs.size();
     H->n_wpred = (int32_t)red.size();
+}
+
+void launch_csr_panel_scatter16(const float *vals, const int64_t *dst, int64_t n, uint16_t *out, hipStream_t s) {
+    if (n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_csr_panel_scatter16, dim3(grid), dim3(256), 0, s, vals, dst, n, (__bf16 *)out);
+    RAD_HIP(hipGetLastError());
 }
 
 void lowp_convert(rad_hmat *H, hipStream_t s) {

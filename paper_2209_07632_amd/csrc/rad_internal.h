@@ -220,7 +220,7 @@ struct GemvSeg {
 struct WideSeg {
     int64_t pa, pb, br;
     int32_t kp, slot;
-    int32_t slot2, pad_;
+    int32_t slot2, pad_;   // pad_ = 1: pa, pb, br index the compressed CSR pair panels
 };
 
 // Phase-1 group: all low-rank blocks sharing column node J.
@@ -371,6 +371,12 @@ struct rad_hmat {
     rad::DevBuf<int32_t> d_cbrow;
     int32_t n_cpan = 0;
     int64_t cpan_elems = 0;
+    // the same for the wide BF16 expansion, one panel per tile pair over the
+    // union of both tiles' columns (16-bit chunk layout; segments with pad_ = 1
+    // read these buffers); wide_csr = 1: every CSR slice lies in a tile pair
+    rad::DevBuf<uint16_t> d_cvals16;
+    rad::DevBuf<int32_t> d_cbrow16;
+    int32_t wide_csr = 0;
     // wide 16-bit expansion: first tiles of consecutive tile pairs with identical
     // operand-row lists (one 128-row workgroup each), and the remaining tiles
     rad::DevBuf<int32_t> d_wpairs, d_wsingles;
@@ -493,6 +499,8 @@ void launch_copy_batched(const CopyDesc *d, int64_t n, void *vals, int32_t dtype
 // out[dst[i]] = vals[i] for i < n with dst[i] >= 0 (values of the matrix's dtype)
 void launch_csr_panel_scatter(const void *vals, const int64_t *dst, int64_t n, void *out, int32_t dtype,
                               hipStream_t s);
+// the same from FP32 values into BF16
+void launch_csr_panel_scatter16(const float *vals, const int64_t *dst, int64_t n, uint16_t *out, hipStream_t s);
 // ray casting (raycast.hip)
 void build_grid(rad_hmat *H, const std::vector<double> &tri);
 void launch_vis_grid(const rad_hmat *H, uint32_t *bits, int64_t wpr, hipStream_t s);

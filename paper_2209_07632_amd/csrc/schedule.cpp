@@ -70,35 +70,45 @@ std::vector<int32_t> xcd_region_order(const std::vector<std::vector<int32_t>> &g
 
 namespace {
 
+// The CSR structure on the host (row pointers and column indices).
+struct CsrHost {
+    std::vector<int32_t> ptr, idx;
+};
+
+// f(row of the tile, X row, entry index) for every CSR entry of tile i
+template <class F>
+void for_each_csr_entry(const rad_hmat *H, const CsrHost &c, const std::vector<TileInfo> &ti,
+                        const std::vector<TileTask> &tk, int32_t i, F &&f) {
+    for (int32_t ct = ti[i].csr_begin; ct < ti[i].csr_end; ++ct) {
+        const TileTask &t = tk[ct];
+        const int64_t g0 = t.a_off - H->csr_val_start;
+        for (int32_t r = t.r_lo; r < t.r_hi; ++r)
+            for (int32_t q = c.ptr[t.aux_off + t.row_off + r]; q < c.ptr[t.aux_off + t.row_off + r + 1]; ++q)
+                f(r, t.col0 + c.idx[g0 + q], g0 + q);
+    }
+}
+
 // The CSR slices of each tile as one compressed panel (FP32 / FP64
 // products, single- and multi-RHS): the panel's columns are the sorted union
 // of the X rows where any of the tile's rows has an entry, so the slices run
 // through the same streamed panel loops as dense and low-rank columns, with
 // the zeros of that union as the only extra work.  Returns each tile's
 // compressed width.
-std::vector<int32_t> prepare_csr_panels(rad_hmat *H, const std::vector<TileInfo> &ti,
+std::vector<int32_t> prepare_csr_panels(rad_hmat *H, const CsrHost &c, const std::vector<TileInfo> &ti,
                                         const std::vector<TileTask> &tk) {
     const int32_t n = H->n_tiles;
     std::vector<int32_t> width(n, 0);
     H->n_cpan = 0;
     H->cpan_elems = 0;
-    if (tk.empty() || H->d_csr_idx.n == 0) return width;
-    const std::vector<int32_t> ptr = H->d_csr_ptr.download(H->d_csr_ptr.n);
-    const std::vector<int32_t> idx = H->d_csr_idx.download(H->d_csr_idx.n);
-    std::vector<int64_t> dst(idx.size(), -1);   // per CSR entry: its element of the compressed panels
+    if (tk.empty() || c.idx.empty()) return width;
+    std::vector<int64_t> dst(c.idx.size(), -1);   // per CSR entry: its element of the compressed panels
     std::vector<CsrPanel> cp(n, CsrPanel{0, 0, 0, 0});
     std::vector<int32_t> cbrow, cols;
     int64_t vfill = 0;
     for (int32_t i = 0; i < n; ++i) {
         if (ti[i].csr_begin >= ti[i].csr_end) continue;
         cols.clear();
-        for (int32_t c = ti[i].csr_begin; c < ti[i].csr_end; ++c) {
-            const TileTask &t = tk[c];
-            const int64_t g0 = t.a_off - H->csr_val_start;
-            for (int32_t r = t.r_lo; r < t.r_hi; ++r)
-                for (int32_t q = ptr[t.aux_off + t.row_off + r]; q < ptr[t.aux_off + t.row_off + r + 1]; ++q)
-                    cols.push_back(t.col0 + idx[g0 + q]);
-        }
+        for_each_csr_entry(H, c, ti, tk, i, [&](int32_t, int32_t col, int64_t) { cols.push_back(col); });
         std::sort(cols.begin(), cols.end());
         cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
         if (cols.empty()) continue;
@@ -106,16 +116,10 @@ std::vector<int32_t> prepare_csr_panels(rad_hmat *H, const std::vector<TileInfo>
         cp[i] = CsrPanel{vfill, (int64_t)cbrow.size(), k16, 0};
         cbrow.insert(cbrow.end(), cols.begin(), cols.end());
         cbrow.insert(cbrow.end(), (size_t)k16 - cols.size(), cols.back());   // padding columns (zero values)
-        for (int32_t c = ti[i].csr_begin; c < ti[i].csr_end; ++c) {
-            const TileTask &t = tk[c];
-            const int64_t g0 = t.a_off - H->csr_val_start;
-            for (int32_t r = t.r_lo; r < t.r_hi; ++r)
-                for (int32_t q = ptr[t.aux_off + t.row_off + r]; q < ptr[t.aux_off + t.row_off + r + 1]; ++q) {
-                    const int32_t col = t.col0 + idx[g0 + q];
-                    const int64_t pos = std::lower_bound(cols.begin(), cols.end(), col) - cols.begin();
-                    dst[g0 + q] = vfill + pos * 64 + r;
-                }
-        }
+        for_each_csr_entry(H, c, ti, tk, i, [&](int32_t r, int32_t col, int64_t g) {
+            const int64_t pos = std::lower_bound(cols.begin(), cols.end(), col) - cols.begin();
+            dst[g] = vfill + pos * 64 + r;
+        });
         width[i] = k16;
         vfill += (int64_t)64 * k16;
     }
@@ -137,20 +141,70 @@ std::vector<int32_t> prepare_csr_panels(rad_hmat *H, const std::vector<TileInfo>
     return width;
 }
 
+// A tile pair's compressed CSR panel for the wide BF16 expansion: offset of
+// its values (the pair's first tile; the second follows 64 x k32 values
+// later) and of its X-row list, and its width k32 (a multiple of 32; 0: none).
+struct PairCsr {
+    int64_t off, br;
+    int32_t k32;
+};
+
+// One compressed panel per tile pair (wp: the pairs' first tiles) over the
+// union of both tiles' nonzero columns, in the 16-bit chunk layout
+// [k / 32][row][32] of each tile, so that the pair's two tiles share one
+// operand-row list as the wide kernel needs.
+std::vector<PairCsr> prepare_pair_csr(rad_hmat *H, const CsrHost &c, const std::vector<TileInfo> &ti,
+                                      const std::vector<TileTask> &tk, const std::vector<int32_t> &wp) {
+    std::vector<PairCsr> out(wp.size(), PairCsr{0, 0, 0});
+    std::vector<int64_t> dst(c.idx.size(), -1);
+    std::vector<int32_t> cb, cols;
+    int64_t fill = 0;
+    for (size_t p = 0; p < wp.size(); ++p) {
+        cols.clear();
+        for (int32_t h = 0; h < 2; ++h)
+            for_each_csr_entry(H, c, ti, tk, wp[p] + h, [&](int32_t, int32_t col, int64_t) { cols.push_back(col); });
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        if (cols.empty()) continue;
+        const int32_t k32 = (int32_t)((cols.size() + 31) / 32 * 32);
+        out[p] = PairCsr{fill, (int64_t)cb.size(), k32};
+        cb.insert(cb.end(), cols.begin(), cols.end());
+        cb.insert(cb.end(), (size_t)k32 - cols.size(), cols.back());   // padding columns (zero values)
+        for (int32_t h = 0; h < 2; ++h)
+            for_each_csr_entry(H, c, ti, tk, wp[p] + h, [&](int32_t r, int32_t col, int64_t g) {
+                const int64_t k = std::lower_bound(cols.begin(), cols.end(), col) - cols.begin();
+                dst[g] = fill + (int64_t)h * 64 * k32 + (k / 32) * 64 * 32 + (int64_t)r * 32 + k % 32;
+            });
+        fill += (int64_t)2 * 64 * k32;
+    }
+    if (fill == 0) return out;
+    H->d_cvals16.alloc((size_t)fill);
+    RAD_HIP(hipMemset(H->d_cvals16.p, 0, (size_t)fill * sizeof(uint16_t)));
+    {
+        DevBuf<int64_t> d_dst;
+        d_dst.upload(dst);
+        launch_csr_panel_scatter16((const float *)H->d_vals.p + H->csr_val_start, d_dst.p, (int64_t)dst.size(),
+                                   H->d_cvals16.p, nullptr);
+        RAD_HIP(hipStreamSynchronize(nullptr));
+    }
+    H->d_cbrow16.upload(cb);
+    return out;
+}
+
 }  // namespace
 
 void mm_prepare_schedule(rad_hmat *H) {
     const int32_t n = H->n_tiles;
     std::vector<TileInfo> ti = H->d_tiles.download((size_t)n);
     std::vector<TileTask> tk = H->d_tile_tasks.download(H->d_tile_tasks.n);
-    const std::vector<int32_t> cwidth = prepare_csr_panels(H, ti, tk);
-    {
-        const int64_t cb = H->n_cpan > 0 ? (int64_t)(H->d_cvals.n + H->d_cbrow.n * sizeof(int32_t) +
-                                                     H->d_cpan.n * sizeof(CsrPanel))
-                                         : 0;
-        H->stats.bytes_total += cb - H->stats.bytes_csr_panels;
-        H->stats.bytes_csr_panels = cb;
+    CsrHost csr;
+    if (!tk.empty()) {
+        csr.ptr = H->d_csr_ptr.download(H->d_csr_ptr.n);
+        csr.idx = H->d_csr_idx.download(H->d_csr_idx.n);
     }
+    H->d_cvals16.release();
+    H->d_cbrow16.release();
+    const std::vector<int32_t> cwidth = prepare_csr_panels(H, csr, ti, tk);
     std::vector<int64_t> cost(n, 0);
     for (int32_t i = 0; i < n; ++i) {
         cost[i] = ti[i].k16;
@@ -250,11 +304,14 @@ void mm_prepare_schedule(rad_hmat *H) {
     // tile pairs of the wide BF16 expansion: consecutive tiles (the halves of
     // a 128-facet leaf) whose panels multiply the same operand rows
     H->n_wpairs = H->n_wsingles = H->n_wsegs = H->n_wseg_blocks = 0;
-    if (H->lowp == RAD_BF16 && H->d_tile_tasks.n == 0 && n > 1) {
+    H->wide_csr = 0;
+    if (H->lowp == RAD_BF16 && n > 1) {
         std::vector<int32_t> br = H->d_brow.download(H->d_brow.n);
         std::vector<int32_t> wp, ws;
         for (int32_t i = 0; i < n;) {
-            bool same = i + 1 < n && ti[i].kpad == ti[i + 1].kpad && ti[i].kpad > 0;
+            // (two tiles with empty panels pair too: their CSR slices, if
+            // any, get one compressed panel over both)
+            bool same = i + 1 < n && ti[i].kpad == ti[i + 1].kpad;
             if (same)
                 same = std::equal(br.begin() + ti[i].brow_off, br.begin() + ti[i].brow_off + ti[i].kpad,
                                   br.begin() + ti[i + 1].brow_off);
@@ -265,6 +322,22 @@ void mm_prepare_schedule(rad_hmat *H) {
                 ws.push_back(i);
                 i += 1;
             }
+        }
+        // CSR slices: one compressed panel per pair, when no lone tile has any
+        // (the wide kernels do not walk CSR rows; otherwise the matrix keeps
+        // the 16-bit tile kernel, which does)
+        std::vector<PairCsr> pc;
+        if (!tk.empty()) {
+            bool lone = false;
+            for (int32_t i : ws) lone = lone || ti[i].csr_begin < ti[i].csr_end;
+            if (!lone && H->max_rhs >= kMfmaMinRhs) {
+                pc = prepare_pair_csr(H, csr, ti, tk, wp);
+                H->wide_csr = 1;
+            }
+        }
+        if (!tk.empty() && !H->wide_csr) {
+            wp.clear();
+            ws.clear();
         }
         H->n_wpairs = (int32_t)wp.size();
         H->n_wsingles = (int32_t)ws.size();
@@ -307,6 +380,22 @@ void mm_prepare_schedule(rad_hmat *H) {
                     share.push_back({w.slot});
                 bySlot.push_back(w);
             }
+            // then the segments of the pair's compressed CSR panel (own share groups)
+            const int32_t ck = pc.empty() ? 0 : pc[p].k32;
+            const int32_t cch = ck / 32, cns = std::max(1, (ck + kSeg - 1) / kSeg);
+            for (int32_t sg = 0; ck > 0 && sg < cns; ++sg) {
+                const int64_t c0 = (int64_t)cch * sg / cns, c1 = (int64_t)cch * (sg + 1) / cns;
+                WideSeg w{};
+                w.pa = pc[p].off + c0 * 32 * 64;
+                w.pb = pc[p].off + (int64_t)64 * ck + c0 * 32 * 64;
+                w.br = pc[p].br + c0 * 32;
+                w.kp = (int32_t)(32 * (c1 - c0));
+                w.slot = (int32_t)bySlot.size();
+                w.slot2 = -1;
+                w.pad_ = 1;
+                share.push_back({w.slot});
+                bySlot.push_back(w);
+            }
             pslot.push_back((int32_t)bySlot.size());
         }
         // neighbouring leaves multiply mostly the same operand rows: the pairs,
@@ -320,6 +409,14 @@ void mm_prepare_schedule(rad_hmat *H) {
         H->n_wseg_blocks = (int32_t)order.size();
         H->d_wseg_order.upload(order);
         H->d_wslot.upload(pslot);
+    }
+    {
+        const int64_t cb = (H->n_cpan > 0 ? (int64_t)(H->d_cvals.n + H->d_cbrow.n * sizeof(int32_t) +
+                                                      H->d_cpan.n * sizeof(CsrPanel))
+                                          : 0) +
+                           (int64_t)(H->d_cvals16.n * sizeof(uint16_t) + H->d_cbrow16.n * sizeof(int32_t));
+        H->stats.bytes_total += cb - H->stats.bytes_csr_panels;
+        H->stats.bytes_csr_panels = cb;
     }
     int ncu = 0;
     RAD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, H->device));

@@ -100,13 +100,16 @@ def test_csr_near_field_products(terrain, tmp_path, leaf):
     CSR slices run as one compressed panel in the FP32 products.  At leaf 512
     the tiles reduce over thousands of columns, so the single-RHS product is
     cut into segments that cross from the dense / low-rank panel into the
-    compressed one.  Both products match the exported blocks of F-hat
-    densified in FP64 column by column, and the sampled exact rows."""
+    compressed one, and the BF16 product takes the wide tile-pair kernels with
+    one compressed panel per pair; at leaf 64 the tiles do not pair and the
+    BF16 product walks the CSR rows.  The products match the exported blocks
+    of F-hat densified in FP64 column by column (FP32: 1e-5, BF16: 2u), and
+    the sampled exact rows; the refined BF16 solve matches the direct solve."""
     from paper_2209_07632_amd import HMatrix
     verts, faces, fac, rows, Fr = terrain
-    print(f"[build] terrain N={faces.shape[0]} leaf={leaf} CSR near field", flush=True)
+    print(f"[build] terrain N={faces.shape[0]} leaf={leaf} CSR near field, bf16 copy", flush=True)
     H = HMatrix(verts, faces, tol=TOL, storage="f32", visibility="raycast", nearfield="csr", leaf_size=leaf,
-                max_rhs=64, max_rank=256)
+                max_rhs=64, max_rank=256, lowp="bf16")
     path = tmp_path / f"terrain_csr{leaf}.bin"
     H.export(path)
     Fh = densify(read_export(path))
@@ -124,3 +127,15 @@ def test_csr_near_field_products(terrain, tmp_path, leaf):
         assert np.linalg.norm(y1 - Yx[:, c]) / np.linalg.norm(Yx[:, c]) <= 1e-5
     Yr = Fr @ X
     assert np.linalg.norm(Y32[rows] - Yr) / np.linalg.norm(Yr) <= 2 * TOL + 1e-6
+    Y16 = H.matvec(Xd, lowp=True).double().cpu().numpy()
+    e16 = _colwise(Y16, Yx)
+    Y16b = H.matvec(Xd[:, :40].contiguous(), lowp=True).double().cpu().numpy()
+    print(f"leaf {leaf} CSR: FP32 {_colwise(Y32, Yx):.2e}, BF16 {e16:.2e}")
+    assert e16 <= 2 * U_BF16 and _colwise(Y16b, Yx[:, :40]) <= 2 * U_BF16
+    suns = sun_grid_azimuth(1.5, 64, 5.0)
+    E = 0.3 * H.insolation(suns, flux=1365.0)
+    Br, ir = H.solve(E, rho=0.3, rtol=1e-4, refine=True, inner_iters=3, max_iter=50)
+    Bd = ref.solve_direct(Fh, 0.3, E.double().cpu().numpy())
+    er = _colwise(Br.double().cpu().numpy(), Bd)
+    print(f"leaf {leaf} CSR: BF16 refined {ir['total_iters']} steps err {er:.2e}")
+    assert er <= 2e-4
