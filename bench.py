@@ -344,17 +344,18 @@ def terrain_measure(steps, tol=1e-3, lowp="bf16", rtol=1e-4, inner=3, cpu_rows=6
 
 def terrain_csr_leg(verts, faces, perm, batches, B_ref, steps, tol, rtol, albedo, Rb):
     """The terrain operator with CSR near field (the byte rule of Algorithm 4
-    unforced): FP32 Jacobi sweep of the given batches, per-iteration kernels,
-    single-RHS FP32 product, and the first batch's solution against the dense
-    near-field operator's (B_ref, the refined 16-bit sweep)."""
+    unforced) and a BF16 copy: refined 16-bit and FP32 Jacobi sweeps of the
+    given batches, per-iteration kernels (16-bit and FP32), single-RHS FP32
+    product, and the first batch's solution against the dense near-field
+    operator's (B_ref, the refined 16-bit sweep)."""
     import torch
     from paper_2209_07632_amd import HMatrix
 
     N = faces.shape[0]
-    log("building the terrain operator with CSR near field (FP32)")
+    log("building the terrain operator with CSR near field (FP32 + BF16 copy)")
     t0 = time.perf_counter()
     H = HMatrix(verts, faces, tol=tol, storage="f32", visibility="raycast", nearfield="csr", leaf_size=128,
-                max_rank=256, max_rhs=Rb)
+                max_rank=256, max_rhs=Rb, lowp="bf16")
     build_s = time.perf_counter() - t0
     st = H.stats()
     log(f"built in {build_s:.1f} s: {st}")
@@ -362,21 +363,26 @@ def terrain_csr_leg(verts, faces, perm, batches, B_ref, steps, tol, rtol, albedo
         raise RuntimeError("the CSR near-field operator has another tree order")
     tune = H.autotune(Rb, nrep=3)
 
-    def sweep():
+    def sweep(refine):
         tot = 0
         for E, B, R in batches:
-            _, info = H.solve(E, rho=albedo, rtol=rtol, out=B, order="tree_rmajor", R=R, max_iter=200)
+            _, info = H.solve(E, rho=albedo, rtol=rtol, out=B, order="tree_rmajor", R=R, refine=refine,
+                              inner_iters=3, max_iter=200)
             tot += info["total_iters"]
         return tot
 
-    sweep()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        iters = sweep()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
     nsuns = sum(R for _, _, R in batches)
+    sweeps = {}
+    for name, refine in (("refined_16bit", True), ("fp32_jacobi", False)):
+        sweep(refine)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            iters = sweep(refine)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        sweeps[name] = {"seconds_per_sweep": dt, "solves_per_s": nsuns / dt, "outer_iters": iters}
+        log(f"CSR near field, {name}: {dt:.3f} s per sweep, {nsuns / dt:.1f} solves/s ({iters} iterations)")
     B0 = batches[0][1][:, :batches[0][2]].double()
     Br = B_ref[:, :batches[0][2]].double()
     diff = float((torch.linalg.vector_norm(B0 - Br, dim=0) / torch.linalg.vector_norm(Br, dim=0)).max())
@@ -393,14 +399,16 @@ def terrain_csr_leg(verts, faces, perm, batches, B_ref, steps, tol, rtol, albedo
     mv1_ms = ev0.elapsed_time(ev1) / 10
     op_bytes = st["bytes_csr"] + st["bytes_lowrank"] + st["bytes_dense"]
     ph = H.time_phases(Rb, nrep=5)
+    ph16 = H.time_phases(Rb, nrep=10, lowp=True)
     flops = 2.0 * Rb * (st["lowrank_row_elems"] + st["nnz_near"])
     H.close()
-    log(f"CSR near field: {dt:.3f} s per sweep, {nsuns / dt:.1f} solves/s ({iters} iterations); phases {ph}; "
-        f"single-RHS {mv1_ms:.3f} ms; max column difference from the dense near-field solve {diff:.2e}")
+    log(f"CSR near field: phases FP32 {ph}, 16-bit {ph16}; single-RHS {mv1_ms:.3f} ms; max column difference "
+        f"from the dense near-field solve {diff:.2e}")
     return {"build_seconds": build_s, "hmat_blocks": block_counts(st), "bytes_csr_panels": st["bytes_csr_panels"],
-            "autotune": tune,
-            "fp32_jacobi": {"seconds_per_sweep": dt, "solves_per_s": nsuns / dt, "outer_iters": iters},
+            "autotune": tune, "sweeps": sweeps,
             "phase_ms_fp32": {"projections": ph[0], "split_k_sum": ph[1], "expansion_jacobi": ph[2]},
+            "phase_ms_16bit": {"projections": ph16[0], "split_k_sum": ph16[1], "expansion_jacobi": ph16[2]},
+            "expansion_16bit_tflops": flops / (ph16[2] * 1e-3) / 1e12,
             "expansion_fp32_tflops": flops / (ph[2] * 1e-3) / 1e12,
             "hmatvec_single_rhs_ms": mv1_ms,
             "hmatvec_single_rhs_gbs": (op_bytes + 2 * N * 4) / (mv1_ms * 1e-3) / 1e9,
