@@ -622,14 +622,17 @@ def run_terrain_phases(args):
     else:
         verts, faces = dem_mesh(DemSpec(n=args.dem_n, extent=10.0 * args.dem_n, seed=2))
         t0 = time.perf_counter()
-        H = HMatrix(verts, faces, tol=args.tol, storage="f32", visibility="raycast", nearfield="dense",
-                    leaf_size=128, max_rank=256, max_rhs=256, lowp=args.lowp)
+        H = HMatrix(verts, faces, tol=args.tol, storage="f32", visibility="raycast",
+                    nearfield=args.terrain_nearfield, leaf_size=128, max_rank=256, max_rhs=256, lowp=args.lowp)
         build_s = time.perf_counter() - t0
         if args.save_operator:
             H.save(args.save_operator)
             log(f"built N={H.N} in {build_s:.1f} s, saved to {args.save_operator}")
             return
     dem_n = int(round(np.sqrt(H.N / 2)))  # two triangles per cell
+    st0 = H.stats()
+    nf = "CSR" if st0["n_csr"] > 0 else "dense"
+
     X = torch.rand((H.N, 256), dtype=torch.float32, device="cuda:0")
     for _ in range(2):
         H.matvec(X, lowp=True)
@@ -654,11 +657,11 @@ def run_terrain_phases(args):
     print(json.dumps({"metric": "terrain product phases (ms per launch, R = 256)", "value": sum(ph16), "unit": "ms",
                       "higher_is_better": False, "n_gpus": 1, "dtype": "bf16+f32", "data": "synthetic",
                       "config": {"workload": f"DEM {dem_n}x{dem_n} cells of 10 m, N={H.N}, leaf 128, "
-                                             f"tol {args.tol}", "N": H.N},
+                                             f"tol {args.tol}, {nf} near field", "N": H.N},
                       "phases_16bit_ms": ph16, "phases_fp32_ms": ph32, "single_rhs_fp32_ms": mv1,
                       "single_rhs_fp32_gbs": (st["bytes_dense"] + st["bytes_csr"] + st["bytes_lowrank"] + 2 * H.N * 4)
                       / (mv1 * 1e-3) / 1e9,
-                      "build_seconds": build_s,
+                      "build_seconds": build_s, "bytes_csr_panels": st["bytes_csr_panels"],
                       "hmat_blocks": block_counts(st)}), flush=True)
 
 
@@ -933,6 +936,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="the cap workload alone (no eps sweep, FP64 leg or terrain keys)")
     ap.add_argument("--dem-n", type=int, default=128, help="terrain_phases: DEM cells per side")
+    ap.add_argument("--terrain-nearfield", default="dense", choices=["dense", "csr"],
+                    help="terrain_phases: near-field form of the built operator")
     ap.add_argument("--save-operator", default=None, help="terrain_phases, cap_phases: build, write the operator there, stop")
     ap.add_argument("--load-operator", default=None, help="terrain_phases, cap_phases: read the operator from this file")
     args = ap.parse_args()
