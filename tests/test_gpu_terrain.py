@@ -139,3 +139,25 @@ def test_csr_near_field_products(terrain, tmp_path, leaf):
     er = _colwise(Br.double().cpu().numpy(), Bd)
     print(f"leaf {leaf} CSR: BF16 refined {ir['total_iters']} steps err {er:.2e}")
     assert er <= 2e-4
+
+
+def test_csr_single_rhs_fp64_segments(terrain, tmp_path):
+    """FP64 terrain with CSR near field at leaf 512, built for single
+    right-hand sides only: the tiles' reductions (low-rank columns, then the
+    compressed CSR panel) run longer than the FP64 segment length of 2,048
+    columns, so the product is cut into segments, some inside the compressed
+    panel; it matches the exported blocks densified in FP64 to 1e-12."""
+    from paper_2209_07632_amd import HMatrix
+    verts, faces, fac, rows, Fr = terrain
+    print(f"[build] terrain N={faces.shape[0]} leaf=512 CSR near field, FP64, max_rhs 1", flush=True)
+    H = HMatrix(verts, faces, tol=TOL, storage="f64", visibility="raycast", nearfield="csr", leaf_size=512,
+                max_rhs=1, max_rank=256)
+    path = tmp_path / "terrain_csr_f64.bin"
+    H.export(path)
+    Fh = densify(read_export(path))
+    st = H.stats()
+    print(f"stats: csr {st['n_csr']} widest panel {st['max_panel_cols']} compressed panels {st['bytes_csr_panels']}")
+    assert st["n_csr"] > 0 and st["bytes_csr_panels"] > 0
+    x = np.random.default_rng(5).random(fac.N)
+    y = H.matvec(torch.from_numpy(x).to(DEV)).cpu().numpy()
+    assert np.linalg.norm(y - Fh @ x) / np.linalg.norm(Fh @ x) <= 1e-12
