@@ -175,10 +175,12 @@ __global__ void __launch_bounds__(kRegThreads) k_ts_column_r(int M, int64_t N, i
     const int64_t NR = N * R;
     const double es = emiss * kSigmaSB;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NR; i += (int64_t)gridDim.x * blockDim.x) {
-        double tv[kMax + 2], dv[kMax];   // tv[kMax + 1]: never read (pads the j + 1 below)
+        // tv[j]: node j; the elimination below stores level j's reduced
+        // right-hand side in tv[j + 1], whose node value it no longer needs
+        double tv[kMax + 2];
 #pragma unroll
         for (int j = 0; j <= kMax; ++j)
-            if (j <= M) tv[j] = Tin[node_at(j, i, M)];
+            if (j <= M) tv[j] = __builtin_nontemporal_load(Tin + node_at(j, i, M));
         const int64_t t = i / R, r = i - t * R;
         const int64_t y1 = op_index(rmajor, t, r, ldx, N), y2 = op_index(rmajor, t, R + r, ldx, N);
         const double qrefl = (double)Y[y1], qir = (double)Y[y2];
@@ -196,7 +198,7 @@ __global__ void __launch_bounds__(kRegThreads) k_ts_column_r(int M, int64_t N, i
                 else
                     rj += hb;
                 d = rj * ib[j];
-                dv[j - 1] = d;
+                tv[j + 1] = d;
             }
         }
         const double t0 = tv[0], t1 = tv[1], g1 = g[1];
@@ -215,13 +217,13 @@ __global__ void __launch_bounds__(kRegThreads) k_ts_column_r(int M, int64_t N, i
             }
             tn = u;
         }
-        Tout[node_at(0, i, M)] = tn;
+        __builtin_nontemporal_store(tn, Tout + node_at(0, i, M));
         const double ts = tn;
 #pragma unroll
         for (int j = 1; j <= kMax; ++j) {
             if (j <= M) {
-                tn = dv[j - 1] - e[j] * tn;
-                Tout[node_at(j, i, M)] = tn;
+                tn = tv[j + 1] - e[j] * tn;
+                __builtin_nontemporal_store(tn, Tout + node_at(j, i, M));
             }
         }
         qabs[i] = qa_new;
