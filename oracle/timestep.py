@@ -105,14 +105,25 @@ def cn_step_balanced(T: np.ndarray, qabs_old: np.ndarray, qabs_new: np.ndarray, 
     """A second reading of the column step: the surface node holds no heat and
     satisfies the radiation boundary condition of section 2 at the new level,
 
-      Qabs' + k (T_1' - T_0') / z_1 = emiss sigma T_0'^4,
+      Qabs' + k (T_1' - T_0') / z_1 = emiss sigma T_0'^4.
 
-    with the emission linearised about T_0^n and the linearisation repeated
-    ``newton`` more times about the latest T_0' (Newton's method on the one
-    nonlinear row; 0 gives the single linearisation).  Nodes 1..M take the
-    Crank-Nicolson average of conduction (half a layer at the bottom, which
-    receives H_bottom); node 1 exchanges with the surface at both levels, the
-    old surface temperature having met the balance with Qabs at its own level.
+    Nodes 1..M take the Crank-Nicolson average of conduction (half a layer at
+    the bottom, which receives H_bottom); node 1 exchanges with the surface at
+    both levels, the old surface temperature having met the balance with Qabs
+    at its own level.  Given the new surface temperature u the rows of nodes
+    1..M are linear, so T_1' = a + s u (a, s from two solves with the surface
+    held at 0 and at 1), and the condition becomes one quartic per column,
+
+      f(u) = emiss sigma u^4 + c u - b = 0,   c = k (1 - s) / z_1,  b = Qabs' + k a / z_1.
+
+    f is increasing and convex for u > 0 (c > 0): a Newton step from any point
+    lands at or above the root, and from above the root Newton's method
+    descends to it without overshoot.  The first step is taken from the old
+    surface temperature T_0^n and capped by the smaller of two bounds above the
+    root, (b / emiss sigma)^(1/4) and b / c (the cap matters after a jump in
+    Qabs, when a step from far below the root would overshoot far above it);
+    ``newton`` more steps follow.  Then the column is solved with the surface
+    at u.
     ``qabs_old`` is not needed by this form (it is carried by T_0^n) and is
     accepted for a common signature."""
     N, n = T.shape
@@ -135,16 +146,26 @@ def cn_step_balanced(T: np.ndarray, qabs_old: np.ndarray, qabs_new: np.ndarray, 
     rhs = cap * T
     rhs[:, 1:] += 0.5 * LT[:, 1:]
     rhs[:, -1] += Hb
+    # the surface row holds T_0' = u
+    diag[:, 0] = 1.0
+    upper[:, 0] = 0.0
+
+    def with_surface(u):
+        r = rhs.copy()
+        r[:, 0] = u
+        return thomas(lower, diag, upper, r)
+
+    a = with_surface(np.zeros(N))[:, 1]
+    s = with_surface(np.ones(N))[:, 1] - a
     es = emiss * SIGMA_SB
-    upper[:, 0] = -g[0]
-    t0 = T[:, 0].copy()
-    for _ in range(newton + 1):
-        # emiss sigma T^4 ~ emiss sigma (t0^4 + 4 t0^3 (T - t0))
-        diag[:, 0] = g[0] + 4.0 * es * t0 ** 3
-        rhs[:, 0] = qabs_new + 3.0 * es * t0 ** 4
-        x = thomas(lower, diag, upper, rhs)
-        t0 = x[:, 0]
-    return x
+    c = g[0] * (1.0 - s)
+    b = qabs_new + g[0] * a
+    bound = np.minimum((np.maximum(b, 0.0) / es) ** 0.25, np.maximum(b, 0.0) / c)
+    t0 = T[:, 0]
+    u = np.minimum(t0 - (es * t0 ** 4 + c * t0 - b) / (4.0 * es * t0 ** 3 + c), bound)
+    for _ in range(newton):
+        u = u - (es * u ** 4 + c * u - b) / (4.0 * es * u ** 3 + c)
+    return with_surface(u)
 
 
 def column_energy(T: np.ndarray, z: np.ndarray, rhoc: float) -> np.ndarray:

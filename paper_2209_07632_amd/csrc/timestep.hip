@@ -36,6 +36,29 @@ __device__ inline int64_t node_at(int j, int64_t i, int M) {
 }
 
 // Position of (t, column c) in X / Y.
+// Surface temperature at the new level from the radiation boundary condition
+// (section 2), the surface holding no heat: with node 1 eliminated as
+// T_1' = d - e_1 T_0', the condition is the quartic
+//   f(u) = es u^4 + c u - b = 0,  c = g_1 (1 + e_1) > 0,  b = Q_abs' + g_1 d,
+// increasing and convex for u > 0.  A Newton step from any point lands at or
+// above the root, and from above Newton descends to it without overshoot.
+// The first step is taken from the old surface temperature and capped by the
+// smaller of two bounds above the root, (b / es)^(1/4) and b / c (after a
+// jump in Q_abs a step from far below would overshoot far above); `newton`
+// more steps follow.
+__device__ inline double balanced_surface(double t0, double qa_new, double g1, double d, double e1, double es,
+                                          int newton) {
+    const double c = g1 * (1.0 + e1), b = qa_new + g1 * d, bp = fmax(b, 0.0);
+    const double bound = fmin(sqrt(sqrt(bp / es)), bp / c);
+    double u = t0;
+    for (int it = 0; it <= newton; ++it) {
+        const double u3 = u * u * u;
+        u = (3.0 * es * u3 * u + b) / (c + 4.0 * es * u3);
+        if (it == 0) u = fmin(u, bound);
+    }
+    return u;
+}
+
 __device__ inline int64_t op_index(bool rmajor, int64_t t, int64_t c, int64_t ldx, int64_t N) {
     return rmajor ? t * ldx + c : c * N + t;
 }
@@ -131,14 +154,7 @@ __global__ void __launch_bounds__(kColThreads) k_ts_column(int M, int64_t N, int
                 cap[0] * t0 + 0.5 * g1 * (t1 - t0) + 0.5 * (qa_old + qa_new) - es * t03 * t0 + drad * t0;
             tn = (r0 + 0.5 * g1 * d) / (cap[0] + 0.5 * g1 + drad + 0.5 * g1 * e[1]);
         } else {
-            // balanced: (g_1 + 4 es u^3) T_0' - g_1 T_1' = Q_abs' + 3 es u^4,
-            // u the latest surface temperature
-            double u = t0;
-            for (int it = 0; it <= newton; ++it) {
-                const double u3 = u * u * u;
-                u = (qa_new + 3.0 * es * u3 * u + g1 * d) / (g1 * (1.0 + e[1]) + 4.0 * es * u3);
-            }
-            tn = u;
+            tn = balanced_surface(t0, qa_new, g1, d, e[1], es, newton);
         }
         Tout[node_at(0, i, M)] = tn;
         const double ts = tn;
@@ -210,12 +226,7 @@ __global__ void __launch_bounds__(kRegThreads) k_ts_column_r(int M, int64_t N, i
                 cap[0] * t0 + 0.5 * g1 * (t1 - t0) + 0.5 * (qa_old + qa_new) - es * t03 * t0 + drad * t0;
             tn = (r0 + 0.5 * g1 * d) / (cap[0] + 0.5 * g1 + drad + 0.5 * g1 * e[1]);
         } else {
-            double u = t0;
-            for (int it = 0; it <= newton; ++it) {
-                const double u3 = u * u * u;
-                u = (qa_new + 3.0 * es * u3 * u + g1 * d) / (g1 * (1.0 + e[1]) + 4.0 * es * u3);
-            }
-            tn = u;
+            tn = balanced_surface(t0, qa_new, g1, d, e[1], es, newton);
         }
         __builtin_nontemporal_store(tn, Tout + node_at(0, i, M));
         const double ts = tn;

@@ -240,6 +240,32 @@ def test_balanced_surface_meets_radiation_condition():
     assert np.max(np.abs(res)) <= 1e-10 * np.max(emit)
 
 
+def test_balanced_surface_after_a_jump_in_sunlight():
+    """Columns at 150 K stepped 0.3 day into shadow and into sunlight of 750
+    and 1,200 W m^-2, with 20 layers to 1 m of low-conductivity regolith:
+    with many repeats the surface meets the radiation condition of section 2
+    to rounding; with the default three it is within 1e-6 (relative) of that
+    solution;
+    and the sunlit surfaces stay below the temperature at which emission alone
+    would carry Qabs away (conduction only takes heat down into the colder
+    column).  Newton's method from the old surface temperature alone
+    overshoots to about 1,000 K here and is still some 150 K high after three
+    repeats."""
+    M = 20
+    w = 1.12 ** np.arange(M)
+    z = np.concatenate([[0.0], np.cumsum(w / w.sum())])
+    k, rhoc, emiss = 0.0015, 1.2e6, 0.95
+    T = np.full((3, M + 1), 150.0)
+    qn = np.array([0.0, 750.0, 1200.0])
+    conv = ts.cn_step_balanced(T, qn, qn, 0.3 * 86400.0, z, k, rhoc, emiss, 0.0, newton=12)
+    emit = emiss * ref.SIGMA_SB * conv[:, 0] ** 4
+    res = qn + k / z[1] * (conv[:, 1] - conv[:, 0]) - emit
+    assert np.max(np.abs(res)) <= 1e-12 * np.max(emit)
+    x = ts.cn_step_balanced(T, qn, qn, 0.3 * 86400.0, z, k, rhoc, emiss, 0.0)
+    assert np.max(np.abs(x[:, 0] - conv[:, 0]) / conv[:, 0]) < 1e-6
+    assert np.all(x[1:, 0] < (qn[1:] / (emiss * ref.SIGMA_SB)) ** 0.25)
+
+
 def test_balanced_second_order_in_time():
     fine = _radiating_day(86400.0 / 4096, step=ts.cn_step_balanced)
     errs = [np.max(np.abs(_radiating_day(86400.0 / n, step=ts.cn_step_balanced) - fine)) for n in (64, 128, 256)]

@@ -233,3 +233,50 @@ def test_rejects_bad_arguments(bowl):
     S = TimeStepper(H, z, K, RHOC, DT, ALBEDO, EMISS, R=2)
     with pytest.raises(RadError, match="rad_ts_init"):
         S.step(torch.zeros((1, 2, fac.N), dtype=torch.float64, device=DEV))
+
+
+def test_lunation_in_internal_layout_r64():
+    """The benchmark's shape on a small cap: 64 scenarios (a 128-column
+    operand), insolation written by the library straight into its internal
+    layout, 20 layers to 1 m, one lunation of 0.3-day steps with the balanced
+    surface, FP32 matrix at tol 1e-6.  Surface temperatures of three
+    scenarios equal the FP64 reference's (fed the same direct insolation),
+    and stay within a few kelvin of radiative equilibrium under a single sun."""
+    from paper_2209_07632_amd import HMatrix
+    from paper_2209_07632_amd.rad import ldr_of
+    from paper_2209_07632_amd.timestep import TimeStepper
+    verts, faces = cap_mesh(CapSpec(h=120.0, seed=3))
+    fac = ref.Facets(verts, faces)
+    F = ref.view_factor_matrix(fac)
+    R, M, n = 64, 20, int(round(29.53 / 0.3))
+    dt, k, albedo, emiss = 0.3 * 86400.0, 0.0015, 0.12, 0.95
+    w = 1.12 ** np.arange(M)
+    z = np.concatenate([[0.0], np.cumsum(w / w.sum())])
+    H = HMatrix(verts, faces, tol=1e-6, storage="f32", max_rhs=2 * R)
+    ld = ldr_of(R)
+    rng = np.random.default_rng(11)
+    el = np.deg2rad(rng.uniform(5.0, 30.0, R))
+    az0 = rng.uniform(0.0, 2.0 * np.pi, R)
+    Q = torch.zeros((n + 1, fac.N, ld), dtype=torch.float32, device=DEV)
+    for lvl in range(n + 1):
+        az = az0 + 2.0 * np.pi * lvl / n
+        suns = np.column_stack([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)])
+        H.insolation(suns, flux=1365.0, order="tree_rmajor", out=Q[lvl])
+    S = TimeStepper(H, z, k, RHOC, dt, albedo, emiss, bottom_flux=0.0, R=R, surface="balanced", newton=3)
+    T0 = torch.full((M + 1, fac.N, ld), 250.0, dtype=torch.float64, device=DEV)
+    S.init(T0, Q[0], order="tree_rmajor")
+    S.step(Q[1:], order="tree_rmajor")
+    Ts = S.read("T", order="tree_rmajor")[0][:, :R].cpu().numpy()      # (N tree order, R)
+    perm = H.perm()
+    Qc = Q[:, :, :R].double().cpu().numpy()                            # (n+1, N tree, R)
+    flat = ((1.0 - albedo) * 1365.0 / (emiss * 5.670374419e-8)) ** 0.25
+    print(f"GPU surface T range {Ts.min():.2f} .. {Ts.max():.2f} K; flat equilibrium {flat:.2f} K", flush=True)
+    assert Ts.max() < flat + 15.0
+    for r in (0, 31, 63):
+        qd = np.empty((n + 1, fac.N))
+        qd[:, perm] = Qc[:, :, r]
+        out = ots.simulate(lambda x: F @ x, qd, albedo, emiss, np.full((fac.N, M + 1), 250.0), z, k, RHOC, dt,
+                           step=lambda T, qo, qn, d, zz, kk, rc, em, hb: ots.cn_step_balanced(
+                               T, qo, qn, d, zz, kk, rc, em, hb, newton=3))
+        want = out["T"][:, 0][perm]
+        assert _rel(Ts[:, r], want) < 2e-5, (r, _rel(Ts[:, r], want))
