@@ -40,13 +40,17 @@ def _place(G, blocks, R):
     return out
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64"])
-def test_group_product_equals_instances(storage):
+@pytest.mark.parametrize("storage,nearfield", [("f32", "auto"), ("f64", "auto"), ("f32", "csr")])
+def test_group_product_equals_instances(storage, nearfield):
+    """(With nearfield="csr" every instance stores its near field as CSR,
+    which the products stream as compressed panels, the group's as well.)"""
     from paper_2209_07632_amd import HMatrix
     from paper_2209_07632_amd.rad import ldr_of
     R = 37
     meshes = _meshes()
-    parts = _build(meshes, R, tol=1e-4, storage=storage, leaf_size=32)
+    parts = _build(meshes, R, tol=1e-4, storage=storage, leaf_size=32, nearfield=nearfield)
+    if nearfield == "csr":
+        assert all(p.stats()["n_csr"] > 0 and p.stats()["bytes_csr_panels"] > 0 for p in parts)
     G = HMatrix.group(parts, R)
     assert G.n_inst == len(parts)
     assert np.all(G.offsets % 64 == 0) and list(G.sizes) == [p.N for p in parts]
