@@ -743,23 +743,57 @@ def run_warm(args):
     direction to POD coefficients trained on the GPU, then 2,048 held-out suns
     in batches of 256, each solved cold (B^0 = E) and warm (B^0 = E + Phi c),
     by FP32 Jacobi and by BF16-refined solves, to rtol 1e-3."""
-    import torch
     from paper_2209_07632_amd import HMatrix
+    from synth import CAP_LARGE, cap_mesh, sun_directions
+
+    verts, faces = cap_mesh(CAP_LARGE)
+    t0 = time.perf_counter()
+    H = HMatrix(verts, faces, tol=args.tol, storage="f32", nearfield=args.nearfield, max_rhs=512, lowp="bf16")
+    build_s = time.perf_counter() - t0
+    warm_measure(H, sun_directions(512, (5.0, 30.0), seed=5), sun_directions(2048, (5.0, 30.0), seed=6),
+                 f"spherical-cap crater N={faces.shape[0]}", build_s, args)
+
+
+def run_warm_dem(args):
+    """The learned warm start on a polar terrain: a DEM of --dem-n x --dem-n
+    cells of 10 m (512: the 524k-facet terrain; fBm + bowl crater recipe of
+    the 131k terrain), ray-cast visibility, CSR near field (Algorithm 4's byte
+    rule) with a BF16 copy, leaf 128; suns at 1-3 deg elevation, azimuth
+    uniform; otherwise as the cap's warm start."""
+    from paper_2209_07632_amd import HMatrix
+    from synth import DemSpec, dem_mesh, sun_directions
+
+    n = args.dem_n
+    verts, faces = dem_mesh(DemSpec(n=n, extent=10.0 * n, seed=7))
+    log(f"DEM {n}x{n}, N={faces.shape[0]}: building F-hat tol={args.tol}, CSR near field, BF16 copy, leaf 128")
+    t0 = time.perf_counter()
+    H = HMatrix(verts, faces, tol=args.tol, storage="f32", visibility="raycast", nearfield="csr", leaf_size=128,
+                max_rank=256, max_rhs=512, lowp="bf16", verbose=True)
+    build_s = time.perf_counter() - t0
+    log(f"built in {build_s:.1f} s: {H.stats()}")
+    warm_measure(H, sun_directions(512, (1.0, 3.0), seed=5), sun_directions(2048, (1.0, 3.0), seed=6),
+                 f"polar DEM {n}x{n} cells of 10 m N={faces.shape[0]}, CSR near field", build_s, args)
+
+
+def warm_measure(H, train, held, label, build_s, args):
+    """POD (64 modes) of B - E of the training suns' solves (FP32 Jacobi to
+    1e-7), a 3 x 256 x 256 x 256 x 64 tanh perceptron trained on the GPU
+    (Adam), then the held-out suns in batches of 256 solved cold and warm by
+    FP32 Jacobi and by BF16 refinement to --rtol; prints the JSON line."""
+    import torch
     from paper_2209_07632_amd.warmstart import MLP, pod_build, pod_expand, pod_project, sun_features
-    from synth import CAP_LARGE, cap_mesh, mlp_init, sun_directions
+    from synth import mlp_init
 
     S, albedo, Rb, m = 1365.0, 0.3, 256, 64
-    verts, faces = cap_mesh(CAP_LARGE)
-    N = faces.shape[0]
-    H = HMatrix(verts, faces, tol=args.tol, storage="f32", nearfield=args.nearfield, max_rhs=512, lowp="bf16")
-    train = sun_directions(512, (5.0, 30.0), seed=5)
-    held = sun_directions(2048, (5.0, 30.0), seed=6)
+    N = H.N
+    st = H.stats()
     t0 = time.perf_counter()
     Et = albedo * H.insolation(train, flux=S, order="tree_rmajor")
-    Bt, _ = H.solve(Et, rho=albedo, rtol=1e-7, order="tree_rmajor", R=512, max_iter=200)
-    Phi, sigma = pod_build((Bt - Et).contiguous(), m, R=512)
+    Bt, _ = H.solve(Et, rho=albedo, rtol=1e-7, order="tree_rmajor", R=len(train), max_iter=200)
+    Phi, sigma = pod_build((Bt - Et).contiguous(), m, R=len(train))
     sig = torch.from_numpy(sigma).to("cuda:0", torch.float32)
-    A = pod_project(Phi, Bt, E=Et, scale=1.0 / sig, R=512)
+    A = pod_project(Phi, Bt, E=Et, scale=1.0 / sig, R=len(train))
+    del Bt, Et
     w = (sig * sig) / (sig * sig).sum()
     sizes = [3, 256, 256, 256, m]
     net = MLP(sizes, mlp_init(sizes, seed=23), compute=args.mlp, max_batch=512)
@@ -807,11 +841,12 @@ def run_warm(args):
         "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
         "ms_per_step": 1e3 * len(held) / head["solves_per_s"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
-        "config": {"workload": f"spherical-cap crater N={N}: POD {m} modes of 512 training solves, perceptron "
-                               f"3x256 ({args.mlp}), 2,048 held-out suns in batches of {Rb}, rtol {args.rtol}",
-                   "N": N, "train": 512, "held_out": len(held), "modes": m},
-        "sweeps": res, "preparation_seconds": prep_s, "final_training_loss": float(hist[-1]),
-        "roofline": None,
+        "config": {"workload": f"{label}: POD {m} modes of {len(train)} training solves, perceptron "
+                               f"3x256 ({args.mlp}), {len(held)} held-out suns in batches of {Rb}, rtol {args.rtol}",
+                   "N": N, "train": len(train), "held_out": len(held), "modes": m},
+        "sweeps": res, "preparation_seconds": prep_s, "build_seconds": build_s,
+        "final_training_loss": float(hist[-1]), "hmat_blocks": block_counts(st),
+        "bytes_csr_panels": st["bytes_csr_panels"], "roofline": None,
     }
     print(json.dumps(result), flush=True)
 
@@ -914,7 +949,8 @@ def run_ts(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="cap40k", choices=["cap40k", "dem131k", "batch64", "warm40k", "ts40k", "terrain_phases", "cap_phases"])
+    ap.add_argument("--workload", default="cap40k", choices=["cap40k", "dem131k", "batch64", "warm40k", "warm_dem", "ts40k", "terrain_phases",
+                             "cap_phases"])
     ap.add_argument("--mlp", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--instances", type=int, default=64)
@@ -946,6 +982,8 @@ def main():
         sys.exit(2)
     if args.workload == "warm40k":
         return run_warm(args)
+    if args.workload == "warm_dem":
+        return run_warm_dem(args)
     if args.workload == "ts40k":
         return run_ts(args)
     if args.workload == "terrain_phases":

@@ -1059,8 +1059,13 @@ void build_from_geometry(rad_hmat *H, std::vector<double> &x, std::vector<double
         B.d_vis.alloc((size_t)wpr * nf);
         B.geom.vis = B.d_vis.p;
         B.geom.vis_words_per_row = wpr;
-        launch_vis_grid(H, B.d_vis.p, wpr, B.st);
-        RAD_HIP(hipStreamSynchronize(B.st));
+        // in row chunks of about 2^31 facet pairs, each reported when done
+        const int64_t chunk = std::max<int64_t>(1, ((int64_t)1 << 26) / wpr);
+        for (int64_t r0 = 0; r0 < nf; r0 += chunk) {
+            launch_vis_grid(H, B.d_vis.p, wpr, r0, std::min<int64_t>(chunk, nf - r0), B.st);
+            RAD_HIP(hipStreamSynchronize(B.st));
+            if (nf > chunk) B.log("  visibility rows", std::to_string(std::min<int64_t>(nf, r0 + chunk)));
+        }
         B.log("visibility bitmap");
     }
 

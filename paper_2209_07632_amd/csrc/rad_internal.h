@@ -503,7 +503,8 @@ void launch_csr_panel_scatter(const void *vals, const int64_t *dst, int64_t n, v
 void launch_csr_panel_scatter16(const float *vals, const int64_t *dst, int64_t n, uint16_t *out, hipStream_t s);
 // ray casting (raycast.hip)
 void build_grid(rad_hmat *H, const std::vector<double> &tri);
-void launch_vis_grid(const rad_hmat *H, uint32_t *bits, int64_t wpr, hipStream_t s);
+// visibility bits of rows [row0, row0 + rows) of the N x N pair matrix
+void launch_vis_grid(const rad_hmat *H, uint32_t *bits, int64_t wpr, int64_t row0, int64_t rows, hipStream_t s);
 void launch_insolation(const rad_hmat *H, const double *suns_dev, int64_t R, double flux, int32_t dtype, void *Q,
                        int64_t ldq, int32_t order, hipStream_t s);
 

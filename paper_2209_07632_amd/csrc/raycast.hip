@@ -140,10 +140,10 @@ __global__ void k_insolation(GridView G, const double *x, const double *n, const
 // V_ij bitmap (row i, 32 columns per word); the segment is cast from the facet
 // with the smaller original index so that V is symmetric.
 __global__ void k_vis_grid(GridView G, const double *x, const double *n, int64_t N, const int32_t *perm,
-                           int64_t wpr, uint32_t *bits) {
+                           int64_t wpr, int64_t row0, int64_t rows, uint32_t *bits) {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= N * wpr) return;
-    int64_t i = id / wpr, w = id - i * wpr;
+    if (id >= rows * wpr) return;
+    int64_t i = row0 + id / wpr, w = id % wpr;
     uint32_t word = 0;
     for (int b = 0; b < 32; ++b) {
         int64_t j = w * 32 + b;
@@ -263,11 +263,11 @@ void build_grid(rad_hmat *H, const std::vector<double> &tri) {
     H->grid_ztop = ztop;
 }
 
-void launch_vis_grid(const rad_hmat *H, uint32_t *bits, int64_t wpr, hipStream_t s) {
-    int64_t tot = H->N * wpr;
+void launch_vis_grid(const rad_hmat *H, uint32_t *bits, int64_t wpr, int64_t row0, int64_t rows, hipStream_t s) {
+    const int64_t tot = rows * wpr;
     if (tot <= 0) return;
     hipLaunchKernelGGL(k_vis_grid, dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, s, view_of(H), H->d_x.p,
-                       H->d_n.p, H->N, H->d_perm.p, wpr, bits);
+                       H->d_n.p, H->N, H->d_perm.p, wpr, row0, rows, bits);
     RAD_HIP(hipGetLastError());
 }
 
